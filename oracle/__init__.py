@@ -1,0 +1,293 @@
+"""CPU oracle for the progressive QMC path tracer -- test infrastructure only.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package. It shares no code with the GPU
+library; both read their inputs from :mod:`scenegen`.
+
+The arithmetic lives in ``qpt_oracle.c`` (plain C, FP64 path tracing, exact
+128-bit radical inverses, FP32 brute-force watertight hits) and, for the
+learned proposal, in :mod:`oracle.guide` (numpy, FP64).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qpt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (no fused multiply-add contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
+            "-fno-fast-math", "-pthread", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        u32, u64, i32 = C.c_uint32, C.c_uint64, C.c_int
+        L.or_dim_base.argtypes = [u32]
+        L.or_dim_base.restype = u32
+        L.or_scramble_mult.argtypes = [u32]
+        L.or_scramble_mult.restype = u32
+        L.or_ri_bits.argtypes = [u64, u32, u32]
+        L.or_ri_bits.restype = u32
+        L.or_enum_params.argtypes = [u32, u32, P, P, P]
+        L.or_pixel_index.argtypes = [u32, u32, u32, u32, u64]
+        L.or_pixel_index.restype = u64
+        L.or_sample_bits.argtypes = [u64, u32, u32, u32, i32]
+        L.or_sample_bits.restype = u32
+        L.or_sample_bits_batch.argtypes = [P, P, u32, u32, u32, i32, P]
+        L.or_trace_f32.argtypes = [P, P, u32, P, u32, i32, P, P, P]
+        L.or_alias_build.argtypes = [u32, P, P, P]
+        L.or_scene_create.argtypes = [u32, P, u32, P, P, u32, P, P, P, P, u32, u32, P, P,
+                                      u32, u32, i32]
+        L.or_scene_create.restype = P
+        L.or_scene_destroy.argtypes = [P]
+        L.or_scene_num_emitters.argtypes = [P]
+        L.or_scene_num_emitters.restype = u32
+        L.or_scene_lights.argtypes = [P, P, P, P, P, P]
+        L.or_scene_env_tables.argtypes = [P, P, P, P]
+        L.or_trace64.argtypes = [P, P, u32, i32, i32, P, P]
+        L.or_render.argtypes = [P, u32, u32, u32, u32, P, u32, u64, u32, P, P, P, u32]
+        L.or_render.restype = u64
+        L.or_camera_ray.argtypes = [P, C.c_double, C.c_double, P, P]
+        L.or_bsdf.argtypes = [P, u32, P, P, P, P, P]
+        L.or_bsdf_sample.argtypes = [P, u32, P, P, C.c_double, C.c_double, C.c_double, P]
+        L.or_bsdf_sample.restype = i32
+        L.or_env_lookup.argtypes = [P, P, P]
+        L.or_env_lookup.restype = C.c_double
+        L.or_bsdf_batch.argtypes = [P, u32, P, P, P, u32, P, P]
+        L.or_bsdf_sample_batch.argtypes = [P, u32, P, P, P, u32, P, P]
+        L.or_ggx_D.argtypes = [C.c_double, C.c_double]
+        L.or_ggx_D.restype = C.c_double
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+# ----------------------------------------------------------------- Halton
+
+def dim_base(d: int) -> int:
+    return lib().or_dim_base(d)
+
+
+def scramble_mult(b: int) -> int:
+    return lib().or_scramble_mult(b)
+
+
+def ri_bits(i: int, b: int, f: int = 1) -> int:
+    """floor(2^32 * scrambled radical inverse of i in base b)."""
+    return lib().or_ri_bits(i, b, f)
+
+
+def enum_params(W: int, H: int):
+    k, l, S = C.c_uint32(), C.c_uint32(), C.c_uint64()
+    lib().or_enum_params(W, H, C.byref(k), C.byref(l), C.byref(S))
+    return k.value, l.value, S.value
+
+
+def pixel_index(W: int, H: int, px: int, py: int, j: int) -> int:
+    return lib().or_pixel_index(W, H, px, py, j)
+
+
+def pixel_indices(W: int, H: int, j: int) -> np.ndarray:
+    out = np.empty(W * H, np.uint64)
+    L = lib()
+    for py in range(H):
+        for px in range(W):
+            out[py * W + px] = L.or_pixel_index(W, H, px, py, j)
+    return out
+
+
+def sample_bits(idx: np.ndarray, dim: np.ndarray, W: int, H: int, scramble: bool = True) -> np.ndarray:
+    idx = np.ascontiguousarray(idx, np.uint64)
+    dim = np.ascontiguousarray(dim, np.uint32)
+    out = np.empty(idx.shape[0], np.uint32)
+    lib().or_sample_bits_batch(_p(idx), _p(dim), idx.shape[0], W, H, int(scramble), _p(out))
+    return out
+
+
+# ------------------------------------------------------------ intersection
+
+def trace_f32(scene, rays: np.ndarray, any_hit: bool = False):
+    """Brute-force FP32 watertight closest hit (or occlusion) for n x 8 float rays."""
+    rays = np.ascontiguousarray(rays, np.float32)
+    n = rays.shape[0]
+    t = np.empty(n, np.float32)
+    tri = np.empty(n, np.uint32)
+    b = np.empty((n, 2), np.float32)
+    pos = np.ascontiguousarray(scene.positions, np.float32)
+    idx = np.ascontiguousarray(scene.indices, np.uint32)
+    lib().or_trace_f32(_p(pos), _p(idx), idx.shape[0], _p(rays), n, int(any_hit), _p(t), _p(tri), _p(b))
+    return t, tri, b
+
+
+def alias_build(w: np.ndarray):
+    w = np.ascontiguousarray(w, np.float64)
+    prob = np.empty_like(w)
+    alias = np.empty(w.shape[0], np.uint32)
+    lib().or_alias_build(w.shape[0], _p(w), _p(prob), _p(alias))
+    return prob, alias
+
+
+# ------------------------------------------------------------- the scene
+
+class Scene:
+    """The oracle's own copy of a scenegen scene (FP64, own BVH and tables)."""
+
+    def __init__(self, sc, build_bvh: bool = True):
+        L = lib()
+        self.sc = sc
+        self._keep = []
+        pos = np.ascontiguousarray(sc.positions, np.float32)
+        idx = np.ascontiguousarray(sc.indices, np.uint32)
+        tm = np.ascontiguousarray(sc.tri_material, np.uint32)
+        alb = np.ascontiguousarray(sc.albedo, np.float32)
+        rough = np.ascontiguousarray(sc.roughness, np.float32)
+        emis = np.ascontiguousarray(sc.emission, np.float32)
+        flags = np.ascontiguousarray(sc.mat_flags, np.uint32)
+        cam = np.array(list(sc.camera.eye) + list(sc.camera.look) + list(sc.camera.up)
+                       + [sc.camera.vfov_deg], np.float64)
+        if sc.env is not None:
+            env = np.ascontiguousarray(sc.env, np.float32)
+            eh, ew = env.shape[:2]
+        else:
+            env, eh, ew = None, 0, 0
+        self._keep = [pos, idx, tm, alb, rough, emis, flags, cam, env]
+        self.h = L.or_scene_create(pos.shape[0], _p(pos), idx.shape[0], _p(idx), _p(tm), alb.shape[0],
+                                   _p(alb), _p(rough), _p(emis), _p(flags), ew, eh, _p(env), _p(cam),
+                                   sc.width, sc.height, int(build_bvh))
+        self.W, self.H = sc.width, sc.height
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().or_scene_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def lights(self):
+        L = lib()
+        ne = L.or_scene_num_emitters(self.h)
+        tri = np.empty(ne, np.uint32)
+        flux = np.empty(ne, np.float64)
+        prob = np.empty(ne, np.float64)
+        alias = np.empty(ne, np.uint32)
+        pmf = np.empty(ne, np.float64)
+        L.or_scene_lights(self.h, _p(tri), _p(flux), _p(prob), _p(alias), _p(pmf))
+        return dict(tri=tri, flux=flux, prob=prob, alias=alias, pmf=pmf)
+
+    def env_tables(self):
+        env = self.sc.env
+        eh, ew = env.shape[:2]
+        rq = np.empty(eh + 1, np.uint64)
+        cq = np.empty(eh * (ew + 1), np.uint64)
+        pdf = np.empty(eh * ew, np.float64)
+        lib().or_scene_env_tables(self.h, _p(rq), _p(cq), _p(pdf))
+        return rq, cq.reshape(eh, ew + 1), pdf.reshape(eh, ew)
+
+    def trace64(self, rays: np.ndarray, any_hit=False, brute=False):
+        rays = np.ascontiguousarray(rays, np.float64)
+        n = rays.shape[0]
+        t = np.empty(n, np.float64)
+        tri = np.empty(n, np.int64)
+        lib().or_trace64(self.h, _p(rays), n, int(any_hit), int(brute), _p(t), _p(tri))
+        return t, tri
+
+    def render(self, pixels=None, pass0=0, npasses=1, max_depth=None, rr=True, mode=0,
+               scramble=True, nthreads=None):
+        """FP64 sums, sums of squares and counts for the listed pixel ids (y*W+x)."""
+        sc = self.sc
+        if max_depth is None:
+            max_depth = sc.max_depth
+        if pixels is None:
+            pix = None
+            npix = sc.width * sc.height
+        else:
+            pix = np.ascontiguousarray(pixels, np.uint32)
+            npix = pix.shape[0]
+        s = np.zeros((npix, 3), np.float64)
+        s2 = np.zeros((npix, 3), np.float64)
+        cnt = np.zeros(npix, np.uint32)
+        nth = nthreads or os.cpu_count() or 1
+        rays = lib().or_render(self.h, max_depth, int(rr), mode, int(scramble), _p(pix), npix, pass0,
+                               npasses, _p(s), _p(s2), _p(cnt), nth)
+        return s, s2, cnt, int(rays)
+
+    def camera_ray(self, fx, fy):
+        o = np.empty(3)
+        d = np.empty(3)
+        lib().or_camera_ray(self.h, fx, fy, _p(o), _p(d))
+        return o, d
+
+    def bsdf(self, m, n, wo, wi):
+        n, wo, wi = (np.ascontiguousarray(v, np.float64) for v in (n, wo, wi))
+        f = np.empty(3)
+        pdf = np.empty(1)
+        lib().or_bsdf(self.h, m, _p(n), _p(wo), _p(wi), _p(f), _p(pdf))
+        return f, float(pdf[0])
+
+    def bsdf_sample(self, m, n, wo, u3, u4, u5):
+        n, wo = (np.ascontiguousarray(v, np.float64) for v in (n, wo))
+        wi = np.empty(3)
+        ok = lib().or_bsdf_sample(self.h, m, _p(n), _p(wo), u3, u4, u5, _p(wi))
+        return bool(ok), wi
+
+    def bsdf_batch(self, m, n, wo, wi):
+        n, wo = (np.ascontiguousarray(v, np.float64) for v in (n, wo))
+        wi = np.ascontiguousarray(wi, np.float64).reshape(-1, 3)
+        f = np.empty_like(wi)
+        pdf = np.empty(wi.shape[0])
+        lib().or_bsdf_batch(self.h, m, _p(n), _p(wo), _p(wi), wi.shape[0], _p(f), _p(pdf))
+        return f, pdf
+
+    def bsdf_sample_batch(self, m, n, wo, u):
+        n, wo = (np.ascontiguousarray(v, np.float64) for v in (n, wo))
+        u = np.ascontiguousarray(u, np.float64).reshape(-1, 3)
+        wi = np.empty_like(u)
+        ok = np.empty(u.shape[0], np.int32)
+        lib().or_bsdf_sample_batch(self.h, m, _p(n), _p(wo), _p(u), u.shape[0], _p(wi), _p(ok))
+        return ok.astype(bool), wi
+
+    def env_lookup(self, w):
+        w = np.ascontiguousarray(w, np.float64)
+        rgb = np.empty(3)
+        pdf = lib().or_env_lookup(self.h, _p(w), _p(rgb))
+        return rgb, pdf
+
+
+def ggx_D(cos_h: float, alpha: float) -> float:
+    return lib().or_ggx_D(cos_h, alpha)
+
+
+def image_parity(gpu_sum, oracle_sum):
+    """Per-pixel error e_p = sum_c |g-o| / (sum_c |o| + eps), eps = 1e-3 mean_p sum_c o.
+
+    Returns (mean e_p, fraction of pixels with e_p > 1e-3, e_p array).
+    """
+    g = np.asarray(gpu_sum, np.float64).reshape(-1, 3)
+    o = np.asarray(oracle_sum, np.float64).reshape(-1, 3)
+    eps = 1e-3 * np.mean(np.sum(o, axis=1))
+    e = np.sum(np.abs(g - o), axis=1) / (np.sum(np.abs(o), axis=1) + eps)
+    return float(np.mean(e)), float(np.mean(e > 1e-3)), e

@@ -1,0 +1,1126 @@
+/*
+ * CPU oracle for the progressive QMC path tracer -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load or run this code. It shares no code with the GPU library: it reads
+ * the same seeded scene arrays and nothing else.
+ *
+ * What it computes, in plain slow C:
+ *   - exact scrambled radical inverses, floor(RI(i) * 2^32), with 128-bit
+ *     integers (Appendix A.2: integer evaluation, indices up to 64 bit);
+ *   - full-screen sample enumeration (Appendix A.2): the unique index in
+ *     [0, 2^k 3^l) whose first base-2 / base-3 digits select a pixel, found
+ *     by brute-force search;
+ *   - FP32 watertight ray/triangle intersection by brute force over every
+ *     triangle (Sec. 2.3: watertight intersection "everywhere"), so that hit
+ *     ids can be compared bit-exactly with a kernel deciding in FP32;
+ *   - an FP64 path tracer: camera rays with box-filtered film samples,
+ *     closest hit, next-event estimation of triangle lights and a lat-long
+ *     environment, multiple importance sampling, Lambert and GGX-over-Lambert
+ *     BSDFs, Russian roulette, FP64 per-pixel sums and sample counts
+ *     (Sec. 2, Sec. 2.1, Sec. 3.2.2, Appendix A.1, A.2, A.4).
+ *
+ * Every discrete decision that a floating-point value drives is taken either
+ * in integers on the exact 32-bit sample value (light and texel selection),
+ * or in FP32 precision on the FP32 rounding of this oracle's FP64 value
+ * (Russian roulette, lobe choice), which is the precision the GPU kernels
+ * decide in.
+ *
+ * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -pthread -lm
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef unsigned __int128 u128;
+
+/* ------------------------------------------------------------------ primes */
+
+#define OR_MAX_PRIMES 1024
+static uint32_t g_primes[OR_MAX_PRIMES];
+static int g_primes_ready = 0;
+
+static void init_primes(void)
+{
+    if (g_primes_ready) return;
+    int n = 0;
+    for (uint32_t c = 2; n < OR_MAX_PRIMES; ++c) {
+        int is_p = 1;
+        for (uint32_t d = 2; d * d <= c; ++d)
+            if (c % d == 0) { is_p = 0; break; }
+        if (is_p) g_primes[n++] = c;
+    }
+    g_primes_ready = 1;
+}
+
+/* base of sample dimension d: the (d+1)-th prime */
+uint32_t or_dim_base(uint32_t d)
+{
+    init_primes();
+    return d < OR_MAX_PRIMES ? g_primes[d] : 0;
+}
+
+/* Linear digit scrambling pi_b(a) = f_b * a mod b (a Faure-Lemieux style
+ * permutation). f_b is round(b * 0.618034) taken in [1, b-1]. pi_b(0) = 0,
+ * so the infinite tail of zero digits stays zero. */
+uint32_t or_scramble_mult(uint32_t b)
+{
+    uint64_t f = ((uint64_t)b * 618034u + 500000u) / 1000000u;
+    if (f < 1) f = 1;
+    if (f > b - 1) f = b - 1;
+    return (uint32_t)f;
+}
+
+/* floor(2^32 * sum_m pi(d_m) b^-(m+1)) for the base-b digits d_m of i */
+uint32_t or_ri_bits(uint64_t i, uint32_t b, uint32_t f)
+{
+    u128 num = 0, den = 1;
+    while (i) {
+        uint64_t d = i % b;
+        i /= b;
+        num = num * b + (u128)((f * d) % b);
+        den *= b;
+    }
+    return (uint32_t)((num << 32) / den);
+}
+
+/* ------------------------------------------------------- enumeration */
+
+void or_enum_params(uint32_t W, uint32_t H, uint32_t *k, uint32_t *l, uint64_t *S)
+{
+    uint32_t kk = 0, ll = 0;
+    uint64_t p2 = 1, p3 = 1;
+    while (p2 < W) { p2 *= 2; ++kk; }
+    while (p3 < H) { p3 *= 3; ++ll; }
+    *k = kk; *l = ll; *S = p2 * p3;
+}
+
+static uint64_t digit_reverse(uint64_t v, uint32_t base, uint32_t ndig)
+{
+    uint64_t r = 0;
+    for (uint32_t m = 0; m < ndig; ++m) { r = r * base + v % base; v /= base; }
+    return r;
+}
+
+/* index of pass j for pixel (px, py): i0 + j*S, i0 found by search */
+uint64_t or_pixel_index(uint32_t W, uint32_t H, uint32_t px, uint32_t py, uint64_t j)
+{
+    uint32_t k, l;
+    uint64_t S;
+    or_enum_params(W, H, &k, &l, &S);
+    uint64_t p2 = 1ull << k, p3 = S >> k;
+    uint64_t a = digit_reverse(px, 2, k);   /* i mod 2^k */
+    uint64_t c = digit_reverse(py, 3, l);   /* i mod 3^l */
+    for (uint64_t t = 0; t < p3; ++t) {
+        uint64_t i = a + p2 * t;
+        if (i % p3 == c) return i + j * S;
+    }
+    return ~0ull; /* unreachable: 2^k and 3^l are coprime */
+}
+
+/* 32-bit sample value of dimension d for index i. Dimensions 0 and 1 are the
+ * film offsets inside the pixel: the digits of i left after the pixel's own
+ * base-2 (resp. base-3) digits, unscrambled. */
+uint32_t or_sample_bits(uint64_t i, uint32_t d, uint32_t W, uint32_t H, int scramble)
+{
+    uint32_t k, l;
+    uint64_t S;
+    or_enum_params(W, H, &k, &l, &S);
+    if (d == 0) return or_ri_bits(i >> k, 2, 1);
+    if (d == 1) return or_ri_bits(i / (S >> k), 3, 1);
+    uint32_t b = or_dim_base(d);
+    return or_ri_bits(i, b, scramble ? or_scramble_mult(b) : 1);
+}
+
+void or_sample_bits_batch(const uint64_t *idx, const uint32_t *dim, uint32_t n, uint32_t W,
+                          uint32_t H, int scramble, uint32_t *out)
+{
+    for (uint32_t q = 0; q < n; ++q) out[q] = or_sample_bits(idx[q], dim[q], W, H, scramble);
+}
+
+static double u24(uint32_t bits) { return (double)(bits >> 8) * (1.0 / 16777216.0); }
+
+/* ------------------------------------------- FP32 watertight, brute force */
+
+/* Watertight ray/triangle test in FP32 (Woop, Benthin, Wald 2013): shear the
+ * triangle into ray space, edge functions with an exact-zero fallback in
+ * FP64, t = T / det. Hit iff 0 < t < tmax. */
+static int tri_hit_f32(const float o[3], const float d[3], float tmax, const float *v0,
+                       const float *v1, const float *v2, float *t_out, float *b1_out,
+                       float *b2_out)
+{
+    int kz = 0;
+    if (fabsf(d[1]) > fabsf(d[kz])) kz = 1;
+    if (fabsf(d[2]) > fabsf(d[kz])) kz = 2;
+    int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+    if (d[kz] < 0.0f) { int s = kx; kx = ky; ky = s; }
+    float Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0f / d[kz];
+
+    float A[3], B[3], C[3];
+    for (int c = 0; c < 3; ++c) { A[c] = v0[c] - o[c]; B[c] = v1[c] - o[c]; C[c] = v2[c] - o[c]; }
+    float Ax = fmaf(-Sx, A[kz], A[kx]), Ay = fmaf(-Sy, A[kz], A[ky]);
+    float Bx = fmaf(-Sx, B[kz], B[kx]), By = fmaf(-Sy, B[kz], B[ky]);
+    float Cx = fmaf(-Sx, C[kz], C[kx]), Cy = fmaf(-Sy, C[kz], C[ky]);
+    /* separately rounded products keep each edge function antisymmetric in its
+     * two vertices, so a shared edge evaluates to exactly opposite values in
+     * the two triangles that own it (no fused multiply-add here) */
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return 0;
+    float det = (U + V) + W;
+    if (det == 0.0f) return 0;
+    float Az = Sz * A[kz], Bz = Sz * B[kz], Cz = Sz * C[kz];
+    float T = fmaf(U, Az, fmaf(V, Bz, W * Cz));
+    float t = T / det;
+    if (!(t > 0.0f && t < tmax)) return 0;
+    *t_out = t;
+    *b1_out = V / det;
+    *b2_out = W / det;
+    return 1;
+}
+
+/* rays: n x 8 floats (ox, oy, oz, tmax, dx, dy, dz, unused).
+ * Closest hit: smallest t, equal t -> smaller triangle id; miss -> id ~0u.
+ * any_hit: out_tri = 0 (visible) or 1 (occluded). */
+void or_trace_f32(const float *pos, const uint32_t *idx, uint32_t nt, const float *rays,
+                  uint32_t n, int any_hit, float *out_t, uint32_t *out_tri, float *out_b)
+{
+    for (uint32_t r = 0; r < n; ++r) {
+        const float *ry = rays + 8 * (size_t)r;
+        float o[3] = {ry[0], ry[1], ry[2]}, d[3] = {ry[4], ry[5], ry[6]};
+        float tmax = ry[3];
+        float bt = INFINITY, bb1 = 0, bb2 = 0;
+        uint32_t bid = 0xffffffffu;
+        for (uint32_t q = 0; q < nt; ++q) {
+            float t, b1, b2;
+            if (!tri_hit_f32(o, d, tmax, pos + 3 * idx[3 * q], pos + 3 * idx[3 * q + 1],
+                             pos + 3 * idx[3 * q + 2], &t, &b1, &b2))
+                continue;
+            if (any_hit) { bid = 1; break; }
+            if (t < bt || (t == bt && q < bid)) { bt = t; bid = q; bb1 = b1; bb2 = b2; }
+        }
+        if (any_hit) {
+            out_tri[r] = bid == 1 ? 1u : 0u;
+            if (out_t) out_t[r] = 0.0f;
+            continue;
+        }
+        out_tri[r] = bid;
+        if (out_t) out_t[r] = bid == 0xffffffffu ? INFINITY : bt;
+        if (out_b) { out_b[2 * r] = bb1; out_b[2 * r + 1] = bb2; }
+    }
+}
+
+/* ------------------------------------------------------------ FP64 math */
+
+typedef struct { double x, y, z; } v3;
+static inline v3 V3(double x, double y, double z) { v3 r = {x, y, z}; return r; }
+static inline v3 add(v3 a, v3 b) { return V3(a.x + b.x, a.y + b.y, a.z + b.z); }
+static inline v3 sub(v3 a, v3 b) { return V3(a.x - b.x, a.y - b.y, a.z - b.z); }
+static inline v3 mul(v3 a, double s) { return V3(a.x * s, a.y * s, a.z * s); }
+static inline v3 vmul(v3 a, v3 b) { return V3(a.x * b.x, a.y * b.y, a.z * b.z); }
+static inline double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static inline v3 cross(v3 a, v3 b)
+{
+    return V3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static inline double len(v3 a) { return sqrt(dot(a, a)); }
+static inline v3 normalize(v3 a) { return mul(a, 1.0 / len(a)); }
+static inline double comp(v3 a, int c) { return c == 0 ? a.x : (c == 1 ? a.y : a.z); }
+static inline double maxc(v3 a) { return fmax(a.x, fmax(a.y, a.z)); }
+static inline double lum(v3 c) { return 0.2126 * c.x + 0.7152 * c.y + 0.0722 * c.z; }
+
+/* ------------------------------------------------------------ the scene */
+
+typedef struct {
+    v3 lo, hi;
+    int32_t left, right; /* inner: child nodes; leaf: left = -1 - first, right = count */
+} bnode;
+
+typedef struct {
+    uint32_t nt;
+    v3 *p0, *p1, *p2;       /* triangle corners, FP32 inputs widened exactly */
+    uint32_t *mat;
+    uint32_t nm;
+    v3 *albedo, *emission;
+    double *rough;
+    uint32_t *flags;
+    /* emitters: triangles with a non-zero emission colour */
+    uint32_t ne;
+    uint32_t *emit_tri;
+    double *emit_flux, *alias_prob;
+    uint32_t *alias_idx;
+    uint64_t *alias_thr;    /* take column c iff sample bits < thr[c] (2^32 scale) */
+    double *emit_pmf;       /* realised selection probability of each emitter */
+    int32_t *tri_emit;      /* triangle -> emitter index or -1 */
+    /* environment */
+    uint32_t ew, eh;
+    v3 *env;
+    uint64_t *row_q;        /* eh + 1 integer CDF (2^32 scale) */
+    uint64_t *col_q;        /* eh * (ew + 1) */
+    double *env_texel_pdf;  /* solid-angle pdf of each texel under the integer CDFs */
+    double p_env;
+    /* camera */
+    v3 eye, fwd, right, up;
+    double tan_half, aspect;
+    uint32_t W, H;
+    /* BVH over triangle ids */
+    bnode *nodes;
+    uint32_t nnodes;
+    uint32_t *order;
+} or_scene;
+
+#define MAT_GGX 1u
+#define MAT_EMIT_TEXTURE 2u
+
+/* emission at a point of a triangle with material m (front face only) */
+static v3 emission_at(const or_scene *s, uint32_t m, v3 x)
+{
+    v3 E = s->emission[m];
+    if (s->flags[m] & MAT_EMIT_TEXTURE) {
+        double k = 0.55 + 0.45 * sin(2.0 * M_PI * 4.0 * (x.x + x.z));
+        E = mul(E, k);
+    }
+    return E;
+}
+
+/* flux of one emitting triangle: pi * area * lum(mean emission), the mean by
+ * the 16-point midpoint rule over the 4x4 split of the triangle */
+static double tri_flux(const or_scene *s, uint32_t t)
+{
+    v3 a = s->p0[t], b = s->p1[t], c = s->p2[t];
+    double area = 0.5 * len(cross(sub(b, a), sub(c, a)));
+    const int n = 4;
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; i + j < n; ++j) {
+            /* upright cell centroid */
+            double u = (i + 1.0 / 3.0) / n, v = (j + 1.0 / 3.0) / n;
+            acc += lum(emission_at(s, s->mat[t], add(a, add(mul(sub(b, a), u), mul(sub(c, a), v)))));
+            if (i + j < n - 1) { /* inverted cell centroid */
+                u = (i + 2.0 / 3.0) / n; v = (j + 2.0 / 3.0) / n;
+                acc += lum(emission_at(s, s->mat[t], add(a, add(mul(sub(b, a), u), mul(sub(c, a), v)))));
+            }
+        }
+    return M_PI * area * acc / (double)(n * n);
+}
+
+/* Vose's alias method, deterministic: q_i = P_i N / sum P; two index-ordered
+ * FIFO lists; the large entry stays at the head until it drops below one. */
+void or_alias_build(uint32_t n, const double *w, double *prob, uint32_t *alias)
+{
+    double sum = 0.0;
+    for (uint32_t i = 0; i < n; ++i) sum += w[i];
+    double *q = (double *)malloc(sizeof(double) * n);
+    uint32_t *small = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint32_t *large = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    uint32_t sh = 0, st = 0, lh = 0, lt = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        q[i] = (w[i] * (double)n) / sum;
+        if (q[i] < 1.0) small[st++] = i; else large[lt++] = i;
+    }
+    while (sh < st && lh < lt) {
+        uint32_t sm = small[sh++], lg = large[lh];
+        prob[sm] = q[sm];
+        alias[sm] = lg;
+        q[lg] = (q[lg] + q[sm]) - 1.0;
+        if (q[lg] < 1.0) { lh++; small[st++] = lg; }
+    }
+    while (sh < st) { uint32_t i = small[sh++]; prob[i] = 1.0; alias[i] = i; }
+    while (lh < lt) { uint32_t i = large[lh++]; prob[i] = 1.0; alias[i] = i; }
+    free(q); free(small); free(large);
+}
+
+/* number of r in [0, R) with floor(r * N / R) == c, R a power of two */
+static uint64_t col_count(uint64_t c, uint64_t N, uint64_t R)
+{
+    /* smallest r with r*N >= c*R is ceil(c*R/N) */
+    u128 hi = ((u128)(c + 1) * R + N - 1) / N, lo = ((u128)c * R + N - 1) / N;
+    return (uint64_t)(hi - lo);
+}
+
+static void build_lights(or_scene *s)
+{
+    s->ne = 0;
+    s->tri_emit = (int32_t *)malloc(sizeof(int32_t) * s->nt);
+    for (uint32_t t = 0; t < s->nt; ++t) {
+        v3 e = s->emission[s->mat[t]];
+        s->tri_emit[t] = -1;
+        if (e.x > 0 || e.y > 0 || e.z > 0) s->ne++;
+    }
+    if (!s->ne) return;
+    s->emit_tri = (uint32_t *)malloc(sizeof(uint32_t) * s->ne);
+    s->emit_flux = (double *)malloc(sizeof(double) * s->ne);
+    s->alias_prob = (double *)malloc(sizeof(double) * s->ne);
+    s->alias_idx = (uint32_t *)malloc(sizeof(uint32_t) * s->ne);
+    s->alias_thr = (uint64_t *)malloc(sizeof(uint64_t) * s->ne);
+    s->emit_pmf = (double *)calloc(s->ne, sizeof(double));
+    uint32_t k = 0;
+    for (uint32_t t = 0; t < s->nt; ++t) {
+        v3 e = s->emission[s->mat[t]];
+        if (e.x > 0 || e.y > 0 || e.z > 0) { s->tri_emit[t] = (int32_t)k; s->emit_tri[k++] = t; }
+    }
+    for (uint32_t e = 0; e < s->ne; ++e) s->emit_flux[e] = tri_flux(s, s->emit_tri[e]);
+    or_alias_build(s->ne, s->emit_flux, s->alias_prob, s->alias_idx);
+    for (uint32_t e = 0; e < s->ne; ++e) {
+        double thr = ceil(s->alias_prob[e] * 4294967296.0);
+        s->alias_thr[e] = (uint64_t)thr;
+    }
+}
+
+/* after p_env is known: realised pmf of the integer selection rule */
+static void build_light_pmf(or_scene *s)
+{
+    if (!s->ne) return;
+    uint64_t R = s->env ? (1ull << 31) : (1ull << 32);
+    double p_tri = 1.0 - s->p_env;
+    for (uint32_t c = 0; c < s->ne; ++c) {
+        double pc = (double)col_count(c, s->ne, R) / (double)R;
+        double take = (double)s->alias_thr[c] / 4294967296.0;
+        s->emit_pmf[c] += p_tri * pc * take;
+        s->emit_pmf[s->alias_idx[c]] += p_tri * pc * (1.0 - take);
+    }
+}
+
+static void build_env(or_scene *s)
+{
+    uint32_t W = s->ew, H = s->eh;
+    s->row_q = (uint64_t *)malloc(sizeof(uint64_t) * (H + 1));
+    s->col_q = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)H * (W + 1));
+    s->env_texel_pdf = (double *)malloc(sizeof(double) * (size_t)W * H);
+    double *rowsum = (double *)malloc(sizeof(double) * H);
+    double *cdf = (double *)malloc(sizeof(double) * (W + 1));
+    for (uint32_t r = 0; r < H; ++r) {
+        double om = (2.0 * M_PI / W) * (cos(M_PI * r / H) - cos(M_PI * (r + 1) / H));
+        cdf[0] = 0.0;
+        for (uint32_t c = 0; c < W; ++c) cdf[c + 1] = cdf[c] + lum(s->env[(size_t)r * W + c]) * om;
+        rowsum[r] = cdf[W];
+        uint64_t *q = s->col_q + (size_t)r * (W + 1);
+        for (uint32_t c = 0; c < W; ++c)
+            q[c] = cdf[W] > 0.0 ? (uint64_t)floor(cdf[c] / cdf[W] * 4294967296.0)
+                                : (uint64_t)(((u128)c << 32) / W);
+        q[W] = 1ull << 32;
+    }
+    double tot = 0.0;
+    cdf = (double *)realloc(cdf, sizeof(double) * (H + 1));
+    cdf[0] = 0.0;
+    for (uint32_t r = 0; r < H; ++r) cdf[r + 1] = cdf[r] + rowsum[r];
+    tot = cdf[H];
+    for (uint32_t r = 0; r < H; ++r) s->row_q[r] = (uint64_t)floor(cdf[r] / tot * 4294967296.0);
+    s->row_q[H] = 1ull << 32;
+    for (uint32_t r = 0; r < H; ++r) {
+        double om = (2.0 * M_PI / W) * (cos(M_PI * r / H) - cos(M_PI * (r + 1) / H));
+        double pr = (double)(s->row_q[r + 1] - s->row_q[r]) / 4294967296.0;
+        const uint64_t *q = s->col_q + (size_t)r * (W + 1);
+        for (uint32_t c = 0; c < W; ++c) {
+            double pc = (double)(q[c + 1] - q[c]) / 4294967296.0;
+            s->env_texel_pdf[(size_t)r * W + c] = pr * pc / om;
+        }
+    }
+    free(rowsum);
+    free(cdf);
+}
+
+/* ----------------------------------------------------------- FP64 BVH */
+
+static void tri_bounds(const or_scene *s, uint32_t t, v3 *lo, v3 *hi)
+{
+    v3 a = s->p0[t], b = s->p1[t], c = s->p2[t];
+    *lo = V3(fmin(a.x, fmin(b.x, c.x)), fmin(a.y, fmin(b.y, c.y)), fmin(a.z, fmin(b.z, c.z)));
+    *hi = V3(fmax(a.x, fmax(b.x, c.x)), fmax(a.y, fmax(b.y, c.y)), fmax(a.z, fmax(b.z, c.z)));
+}
+
+static double *g_sort_key;
+static int cmp_key(const void *a, const void *b)
+{
+    double x = g_sort_key[*(const uint32_t *)a], y = g_sort_key[*(const uint32_t *)b];
+    if (x < y) return -1;
+    if (x > y) return 1;
+    return (*(const uint32_t *)a < *(const uint32_t *)b) ? -1 : 1;
+}
+
+/* median split on the longest centroid axis; leaves of at most 4 triangles */
+static int32_t bvh_build(or_scene *s, uint32_t first, uint32_t count, double *key)
+{
+    int32_t me = (int32_t)s->nnodes++;
+    bnode *nd = &s->nodes[me];
+    v3 lo = V3(INFINITY, INFINITY, INFINITY), hi = V3(-INFINITY, -INFINITY, -INFINITY);
+    v3 clo = lo, chi = hi;
+    for (uint32_t q = first; q < first + count; ++q) {
+        v3 a, b;
+        tri_bounds(s, s->order[q], &a, &b);
+        lo = V3(fmin(lo.x, a.x), fmin(lo.y, a.y), fmin(lo.z, a.z));
+        hi = V3(fmax(hi.x, b.x), fmax(hi.y, b.y), fmax(hi.z, b.z));
+        v3 cc = mul(add(a, b), 0.5);
+        clo = V3(fmin(clo.x, cc.x), fmin(clo.y, cc.y), fmin(clo.z, cc.z));
+        chi = V3(fmax(chi.x, cc.x), fmax(chi.y, cc.y), fmax(chi.z, cc.z));
+    }
+    /* pad so that rounding in the slab test never culls a touching triangle */
+    double pad = 1e-9 * (1.0 + fmax(maxc(V3(fabs(lo.x), fabs(lo.y), fabs(lo.z))),
+                                    maxc(V3(fabs(hi.x), fabs(hi.y), fabs(hi.z)))));
+    s->nodes[me].lo = sub(lo, V3(pad, pad, pad));
+    s->nodes[me].hi = add(hi, V3(pad, pad, pad));
+    if (count <= 4) {
+        nd = &s->nodes[me];
+        nd->left = -1 - (int32_t)first;
+        nd->right = (int32_t)count;
+        return me;
+    }
+    v3 ext = sub(chi, clo);
+    int ax = 0;
+    if (ext.y > comp(ext, ax)) ax = 1;
+    if (ext.z > comp(ext, ax)) ax = 2;
+    for (uint32_t q = first; q < first + count; ++q) {
+        v3 a, b;
+        tri_bounds(s, s->order[q], &a, &b);
+        key[s->order[q]] = comp(add(a, b), ax);
+    }
+    g_sort_key = key;
+    qsort(s->order + first, count, sizeof(uint32_t), cmp_key);
+    uint32_t half = count / 2;
+    int32_t l = bvh_build(s, first, half, key);
+    int32_t r = bvh_build(s, first + half, count - half, key);
+    s->nodes[me].left = l;
+    s->nodes[me].right = r;
+    return me;
+}
+
+/* FP64 watertight test, same structure as the FP32 one */
+static int tri_hit_f64(v3 o, int kx, int ky, int kz, double Sx, double Sy, double Sz,
+                       v3 a, v3 b, v3 c, double tmax, double *t_out, double *b1, double *b2)
+{
+    v3 A = sub(a, o), B = sub(b, o), C = sub(c, o);
+    double Ax = comp(A, kx) - Sx * comp(A, kz), Ay = comp(A, ky) - Sy * comp(A, kz);
+    double Bx = comp(B, kx) - Sx * comp(B, kz), By = comp(B, ky) - Sy * comp(B, kz);
+    double Cx = comp(C, kx) - Sx * comp(C, kz), Cy = comp(C, ky) - Sy * comp(C, kz);
+    double U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
+    if ((U < 0 || V < 0 || W < 0) && (U > 0 || V > 0 || W > 0)) return 0;
+    double det = U + V + W;
+    if (det == 0.0) return 0;
+    double T = U * (Sz * comp(A, kz)) + V * (Sz * comp(B, kz)) + W * (Sz * comp(C, kz));
+    double t = T / det;
+    if (!(t > 0.0 && t < tmax)) return 0;
+    *t_out = t;
+    *b1 = V / det;
+    *b2 = W / det;
+    return 1;
+}
+
+typedef struct { double t, b1, b2; int64_t tri; } hit64;
+
+static int box_hit(const bnode *nd, v3 o, v3 d, double tmax, double *tnear)
+{
+    double t0 = 0.0, t1 = tmax;
+    for (int c = 0; c < 3; ++c) {
+        double oc = comp(o, c), dc = comp(d, c), lo = comp(nd->lo, c), hi = comp(nd->hi, c);
+        if (dc == 0.0) {
+            if (oc < lo || oc > hi) return 0;
+            continue;
+        }
+        double a = (lo - oc) / dc, b = (hi - oc) / dc;
+        if (a > b) { double x = a; a = b; b = x; }
+        if (a > t0) t0 = a;
+        if (b < t1) t1 = b;
+        if (t0 > t1) return 0;
+    }
+    *tnear = t0;
+    return 1;
+}
+
+/* closest hit (any_hit = 0) or occlusion test (any_hit = 1) over [0, tmax) */
+static int trace64(const or_scene *s, v3 o, v3 d, double tmax, int any_hit, int brute, hit64 *h)
+{
+    int kz = 0;
+    if (fabs(d.y) > fabs(comp(d, kz))) kz = 1;
+    if (fabs(d.z) > fabs(comp(d, kz))) kz = 2;
+    int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+    if (comp(d, kz) < 0.0) { int q = kx; kx = ky; ky = q; }
+    double Sx = comp(d, kx) / comp(d, kz), Sy = comp(d, ky) / comp(d, kz), Sz = 1.0 / comp(d, kz);
+    h->t = tmax;
+    h->tri = -1;
+    if (brute || !s->nodes) {
+        for (uint32_t t = 0; t < s->nt; ++t) {
+            double tt, b1, b2;
+            if (!tri_hit_f64(o, kx, ky, kz, Sx, Sy, Sz, s->p0[t], s->p1[t], s->p2[t], tmax,
+                             &tt, &b1, &b2))
+                continue;
+            if (any_hit) return 1;
+            if (h->tri < 0 || tt < h->t || (tt == h->t && (int64_t)t < h->tri)) {
+                h->t = tt; h->b1 = b1; h->b2 = b2; h->tri = t;
+            }
+        }
+        return h->tri >= 0;
+    }
+    int32_t stack[128];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp) {
+        const bnode *nd = &s->nodes[stack[--sp]];
+        double tn;
+        if (!box_hit(nd, o, d, h->tri >= 0 ? h->t : tmax, &tn)) continue;
+        if (nd->left < 0) {
+            uint32_t first = (uint32_t)(-1 - nd->left);
+            for (uint32_t q = first; q < first + (uint32_t)nd->right; ++q) {
+                uint32_t t = s->order[q];
+                double tt, b1, b2;
+                if (!tri_hit_f64(o, kx, ky, kz, Sx, Sy, Sz, s->p0[t], s->p1[t], s->p2[t], tmax,
+                                 &tt, &b1, &b2))
+                    continue;
+                if (any_hit) return 1;
+                if (h->tri < 0 || tt < h->t || (tt == h->t && (int64_t)t < h->tri)) {
+                    h->t = tt; h->b1 = b1; h->b2 = b2; h->tri = t;
+                }
+            }
+        } else {
+            stack[sp++] = nd->right;
+            stack[sp++] = nd->left;
+        }
+    }
+    return h->tri >= 0;
+}
+
+/* ------------------------------------------------------------- creation */
+
+or_scene *or_scene_create(uint32_t nv, const float *pos, uint32_t nt, const uint32_t *idx,
+                          const uint32_t *tri_mat, uint32_t nm, const float *albedo,
+                          const float *rough, const float *emission, const uint32_t *flags,
+                          uint32_t ew, uint32_t eh, const float *env, const double *cam,
+                          uint32_t W, uint32_t H, int build_bvh)
+{
+    (void)nv;
+    or_scene *s = (or_scene *)calloc(1, sizeof(or_scene));
+    s->nt = nt;
+    s->p0 = (v3 *)malloc(sizeof(v3) * nt);
+    s->p1 = (v3 *)malloc(sizeof(v3) * nt);
+    s->p2 = (v3 *)malloc(sizeof(v3) * nt);
+    s->mat = (uint32_t *)malloc(sizeof(uint32_t) * nt);
+    for (uint32_t t = 0; t < nt; ++t) {
+        const float *a = pos + 3 * idx[3 * t], *b = pos + 3 * idx[3 * t + 1],
+                    *c = pos + 3 * idx[3 * t + 2];
+        s->p0[t] = V3(a[0], a[1], a[2]);
+        s->p1[t] = V3(b[0], b[1], b[2]);
+        s->p2[t] = V3(c[0], c[1], c[2]);
+        s->mat[t] = tri_mat[t];
+    }
+    s->nm = nm;
+    s->albedo = (v3 *)malloc(sizeof(v3) * nm);
+    s->emission = (v3 *)malloc(sizeof(v3) * nm);
+    s->rough = (double *)malloc(sizeof(double) * nm);
+    s->flags = (uint32_t *)malloc(sizeof(uint32_t) * nm);
+    for (uint32_t m = 0; m < nm; ++m) {
+        s->albedo[m] = V3(albedo[3 * m], albedo[3 * m + 1], albedo[3 * m + 2]);
+        s->emission[m] = V3(emission[3 * m], emission[3 * m + 1], emission[3 * m + 2]);
+        s->rough[m] = rough[m];
+        s->flags[m] = flags[m];
+    }
+    build_lights(s);
+    if (env && ew && eh) {
+        s->ew = ew; s->eh = eh;
+        s->env = (v3 *)malloc(sizeof(v3) * (size_t)ew * eh);
+        for (size_t q = 0; q < (size_t)ew * eh; ++q)
+            s->env[q] = V3(env[3 * q], env[3 * q + 1], env[3 * q + 2]);
+        build_env(s);
+    }
+    s->p_env = s->env ? (s->ne ? 0.5 : 1.0) : 0.0;
+    build_light_pmf(s);
+    /* camera: cam = eye[3], look[3], up[3], vfov_deg */
+    s->eye = V3(cam[0], cam[1], cam[2]);
+    s->fwd = normalize(sub(V3(cam[3], cam[4], cam[5]), s->eye));
+    s->right = normalize(cross(s->fwd, V3(cam[6], cam[7], cam[8])));
+    s->up = cross(s->right, s->fwd);
+    s->tan_half = tan(0.5 * cam[9] * M_PI / 180.0);
+    s->W = W; s->H = H;
+    s->aspect = (double)W / (double)H;
+    if (build_bvh && nt) {
+        s->nodes = (bnode *)malloc(sizeof(bnode) * 2 * nt);
+        s->order = (uint32_t *)malloc(sizeof(uint32_t) * nt);
+        for (uint32_t t = 0; t < nt; ++t) s->order[t] = t;
+        double *key = (double *)malloc(sizeof(double) * nt);
+        bvh_build(s, 0, nt, key);
+        free(key);
+    }
+    return s;
+}
+
+void or_scene_destroy(or_scene *s)
+{
+    if (!s) return;
+    free(s->p0); free(s->p1); free(s->p2); free(s->mat);
+    free(s->albedo); free(s->emission); free(s->rough); free(s->flags);
+    free(s->emit_tri); free(s->emit_flux); free(s->alias_prob); free(s->alias_idx);
+    free(s->alias_thr); free(s->emit_pmf); free(s->tri_emit);
+    free(s->env); free(s->row_q); free(s->col_q); free(s->env_texel_pdf);
+    free(s->nodes); free(s->order);
+    free(s);
+}
+
+/* table access for host-builder cross-checks */
+uint32_t or_scene_num_emitters(const or_scene *s) { return s->ne; }
+void or_scene_lights(const or_scene *s, uint32_t *emit_tri, double *flux, double *prob,
+                     uint32_t *alias, double *pmf)
+{
+    for (uint32_t e = 0; e < s->ne; ++e) {
+        if (emit_tri) emit_tri[e] = s->emit_tri[e];
+        if (flux) flux[e] = s->emit_flux[e];
+        if (prob) prob[e] = s->alias_prob[e];
+        if (alias) alias[e] = s->alias_idx[e];
+        if (pmf) pmf[e] = s->emit_pmf[e];
+    }
+}
+void or_scene_env_tables(const or_scene *s, uint64_t *row_q, uint64_t *col_q, double *texel_pdf)
+{
+    if (!s->env) return;
+    if (row_q) memcpy(row_q, s->row_q, sizeof(uint64_t) * (s->eh + 1));
+    if (col_q) memcpy(col_q, s->col_q, sizeof(uint64_t) * (size_t)s->eh * (s->ew + 1));
+    if (texel_pdf) memcpy(texel_pdf, s->env_texel_pdf, sizeof(double) * (size_t)s->ew * s->eh);
+}
+
+/* FP64 closest hit / occlusion for a batch of rays (n x 8 doubles) */
+void or_trace64(const or_scene *s, const double *rays, uint32_t n, int any_hit, int brute,
+                double *out_t, int64_t *out_tri)
+{
+    for (uint32_t r = 0; r < n; ++r) {
+        const double *q = rays + 8 * (size_t)r;
+        hit64 h;
+        int hit = trace64(s, V3(q[0], q[1], q[2]), V3(q[4], q[5], q[6]), q[3], any_hit, brute, &h);
+        out_tri[r] = any_hit ? hit : (hit ? h.tri : -1);
+        if (out_t) out_t[r] = hit && !any_hit ? h.t : INFINITY;
+    }
+}
+
+/* ------------------------------------------------------------ sampling */
+
+/* orthonormal basis around unit n (Duff et al. 2017) */
+static void onb(v3 n, v3 *b1, v3 *b2)
+{
+    double sign = copysign(1.0, n.z);
+    double a = -1.0 / (sign + n.z);
+    double b = n.x * n.y * a;
+    *b1 = V3(1.0 + sign * n.x * n.x * a, sign * b, -sign * n.x);
+    *b2 = V3(b, sign + n.y * n.y * a, -n.y);
+}
+
+static double fresnel(double c)
+{
+    double m = 1.0 - c;
+    if (m < 0.0) m = 0.0;
+    double m2 = m * m;
+    return 0.04 + 0.96 * m2 * m2 * m;
+}
+
+static double ggx_D(double cos_h, double a2)
+{
+    double k = cos_h * cos_h * (a2 - 1.0) + 1.0;
+    return a2 / (M_PI * k * k);
+}
+
+static double ggx_lambda(double cos_t, double a2)
+{
+    double c2 = cos_t * cos_t;
+    double tan2 = (1.0 - c2) / c2;
+    return 0.5 * (-1.0 + sqrt(1.0 + a2 * tan2));
+}
+
+/* probability of picking the specular lobe, as realised by u < p on the
+ * 24-bit sample grid: ceil(p * 2^24) / 2^24 with p first rounded to FP32 */
+static double spec_choice(const or_scene *s, uint32_t m, double cos_o)
+{
+    double F = fresnel(cos_o);
+    double p = F / (F + (1.0 - F) * lum(s->albedo[m]));
+    if (p < 0.1) p = 0.1;
+    if (p > 0.9) p = 0.9;
+    float pf = (float)p;
+    return ceil((double)pf * 16777216.0) / 16777216.0;
+}
+
+/* BSDF value f (without the cosine) and sampling pdf (solid angle) for a
+ * reflection on the side of n (n faces wo); wi below the surface -> 0 */
+static void bsdf_eval(const or_scene *s, uint32_t m, v3 n, v3 wo, v3 wi, v3 *f, double *pdf)
+{
+    double co = dot(n, wo), ci = dot(n, wi);
+    *f = V3(0, 0, 0);
+    *pdf = 0.0;
+    if (co <= 0.0 || ci <= 0.0) return;
+    v3 rho = s->albedo[m];
+    if (!(s->flags[m] & MAT_GGX)) {
+        *f = mul(rho, 1.0 / M_PI);
+        *pdf = ci / M_PI;
+        return;
+    }
+    double a = s->rough[m], a2 = a * a;
+    v3 h = normalize(add(wo, wi));
+    double ch = dot(n, h), oh = dot(wo, h);
+    double D = ggx_D(ch, a2);
+    double G2 = 1.0 / (1.0 + ggx_lambda(co, a2) + ggx_lambda(ci, a2));
+    double G1o = 1.0 / (1.0 + ggx_lambda(co, a2));
+    double spec = D * G2 * fresnel(oh) / (4.0 * co * ci);
+    double kd = (1.0 - fresnel(co)) * (1.0 - fresnel(ci)) / M_PI;
+    *f = add(V3(spec, spec, spec), mul(rho, kd));
+    double ps = spec_choice(s, m, co);
+    *pdf = ps * G1o * D / (4.0 * co) + (1.0 - ps) * ci / M_PI;
+}
+
+/* sample wi; returns 0 when the sample leaves the upper hemisphere */
+static int bsdf_sample(const or_scene *s, uint32_t m, v3 n, v3 wo, double u3, double u4,
+                       double u5, v3 *wi)
+{
+    v3 b1, b2;
+    onb(n, &b1, &b2);
+    double co = dot(n, wo);
+    int spec = 0;
+    if (s->flags[m] & MAT_GGX) spec = u3 < spec_choice(s, m, co);
+    if (!spec) {
+        double r = sqrt(u4), ph = 2.0 * M_PI * u5;
+        double z = sqrt(fmax(0.0, 1.0 - u4));
+        *wi = add(add(mul(b1, r * cos(ph)), mul(b2, r * sin(ph))), mul(n, z));
+        return 1;
+    }
+    /* visible-normal sampling (Heitz 2018) in the local frame */
+    double a = s->rough[m];
+    v3 wl = V3(dot(wo, b1), dot(wo, b2), co);
+    v3 vh = normalize(V3(a * wl.x, a * wl.y, wl.z));
+    double l2 = vh.x * vh.x + vh.y * vh.y;
+    v3 T1 = l2 > 0.0 ? mul(V3(-vh.y, vh.x, 0.0), 1.0 / sqrt(l2)) : V3(1.0, 0.0, 0.0);
+    v3 T2 = cross(vh, T1);
+    double r = sqrt(u4), ph = 2.0 * M_PI * u5;
+    double t1 = r * cos(ph), t2 = r * sin(ph);
+    double sh = 0.5 * (1.0 + vh.z);
+    t2 = (1.0 - sh) * sqrt(fmax(0.0, 1.0 - t1 * t1)) + sh * t2;
+    v3 nh = add(add(mul(T1, t1), mul(T2, t2)), mul(vh, sqrt(fmax(0.0, 1.0 - t1 * t1 - t2 * t2))));
+    v3 ne = normalize(V3(a * nh.x, a * nh.y, fmax(0.0, nh.z)));
+    v3 hw = add(add(mul(b1, ne.x), mul(b2, ne.y)), mul(n, ne.z));
+    *wi = sub(mul(hw, 2.0 * dot(wo, hw)), wo);
+    return dot(n, *wi) > 0.0;
+}
+
+/* environment radiance and texel pdf for a direction */
+static v3 env_lookup(const or_scene *s, v3 w, double *pdf)
+{
+    double th = acos(fmax(-1.0, fmin(1.0, w.y)));
+    double ph = atan2(w.x, -w.z);
+    if (ph < 0.0) ph += 2.0 * M_PI;
+    int64_t r = (int64_t)floor(th / M_PI * s->eh), c = (int64_t)floor(ph / (2.0 * M_PI) * s->ew);
+    if (r < 0) r = 0;
+    if (r >= s->eh) r = s->eh - 1;
+    if (c < 0) c = 0;
+    if (c >= s->ew) c = s->ew - 1;
+    size_t q = (size_t)r * s->ew + c;
+    if (pdf) *pdf = s->env_texel_pdf[q];
+    return s->env[q];
+}
+
+/* Wachter-Binder style origin offset, emulated on the FP64 point: move each
+ * coordinate by trunc(256 n_c) units in the last place of its FP32 value,
+ * or by n_c / 65536 within 1/32 of the origin. */
+static double offset1(double p, double n)
+{
+    if (fabs(p) < 1.0 / 32.0) return p + n / 65536.0;
+    int e;
+    frexp(p, &e);                         /* |p| in [2^(e-1), 2^e) */
+    double ulp = ldexp(1.0, e - 1 - 23);
+    int k = (int)(256.0 * n);
+    return p + (double)k * ulp;
+}
+static v3 offset_ray(v3 p, v3 n) { return V3(offset1(p.x, n.x), offset1(p.y, n.y), offset1(p.z, n.z)); }
+
+typedef struct {
+    uint32_t max_depth;
+    uint32_t rr;        /* Russian roulette from vertex 3 */
+    uint32_t mode;      /* 0 MIS, 1 BSDF sampling only, 2 NEE only */
+    uint32_t scramble;
+} or_opts;
+
+static inline double mis2(double a, double b) { return a * a / (a * a + b * b); }
+
+/* radiance estimate of one path for sample index i through film point (fx, fy) */
+static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t px, uint32_t py,
+                     uint32_t *nrays)
+{
+    const uint32_t W = s->W, H = s->H;
+    double u0 = u24(or_sample_bits(i, 0, W, H, 0)), u1 = u24(or_sample_bits(i, 1, W, H, 0));
+    double fx = px + u0, fy = py + u1;
+    double sx = (2.0 * fx / W - 1.0) * s->tan_half * s->aspect;
+    double sy = (1.0 - 2.0 * fy / H) * s->tan_half;
+    v3 d = normalize(add(s->fwd, add(mul(s->right, sx), mul(s->up, sy))));
+    v3 o = s->eye;
+    v3 L = V3(0, 0, 0), T = V3(1, 1, 1);
+    double prev_pdf = 0.0;
+    for (uint32_t v = 1; v <= op->max_depth; ++v) {
+        hit64 h;
+        (*nrays)++;
+        if (!trace64(s, o, d, INFINITY, 0, 0, &h)) {
+            if (s->env && (v == 1 || op->mode != 2)) {
+                double pe;
+                v3 Le = env_lookup(s, d, &pe);
+                double w = 1.0;
+                if (v > 1 && op->mode == 0) w = mis2(prev_pdf, s->p_env * pe);
+                L = add(L, mul(vmul(T, Le), w));
+            }
+            break;
+        }
+        uint32_t t = (uint32_t)h.tri, m = s->mat[t];
+        v3 a = s->p0[t], b = s->p1[t], c = s->p2[t];
+        v3 x = add(a, add(mul(sub(b, a), h.b1), mul(sub(c, a), h.b2)));
+        v3 ng = cross(sub(b, a), sub(c, a));
+        double area2 = len(ng);
+        ng = mul(ng, 1.0 / area2);
+        double dn = dot(d, ng);
+        int front = dn < 0.0;
+        if (front && s->tri_emit[t] >= 0 && !(v > 1 && op->mode == 2)) {
+            v3 Le = emission_at(s, m, x);
+            double w = 1.0;
+            if (v > 1 && op->mode == 0) {
+                double pl = s->emit_pmf[s->tri_emit[t]] / (0.5 * area2) * h.t * h.t / (-dn);
+                w = mis2(prev_pdf, pl);
+            }
+            L = add(L, mul(vmul(T, Le), w));
+        }
+        if (v == op->max_depth) break;
+        if (!(maxc(s->albedo[m]) > 0.0 || (s->flags[m] & MAT_GGX))) break;
+        v3 n = front ? ng : mul(ng, -1.0);
+        v3 wo = mul(d, -1.0);
+        v3 xo = offset_ray(x, n);
+        uint32_t base = 2 + 8 * (v - 1);
+        /* next-event estimation */
+        if (op->mode != 1 && (s->ne || s->env)) {
+            uint32_t s0 = or_sample_bits(i, base + 0, W, H, op->scramble);
+            int use_env = 0;
+            uint64_t r = s0, R = 1ull << 32;
+            if (s->env && s->ne) {
+                use_env = s0 < (1u << 31);
+                r = s0 - (1u << 31);
+                R = 1ull << 31;
+            } else if (s->env) {
+                use_env = 1;
+            }
+            v3 wi, Le;
+            double pl = 0.0, dist = INFINITY;
+            int ok = 0;
+            if (use_env) {
+                uint32_t s1 = or_sample_bits(i, base + 1, W, H, op->scramble);
+                uint32_t s2 = or_sample_bits(i, base + 2, W, H, op->scramble);
+                uint32_t row = 0;
+                while (row + 1 < s->eh && s->row_q[row + 1] <= s1) ++row;
+                const uint64_t *cq = s->col_q + (size_t)row * (s->ew + 1);
+                uint32_t col = 0;
+                while (col + 1 < s->ew && cq[col + 1] <= s2) ++col;
+                double fyr = (double)(s1 - s->row_q[row]) / (double)(s->row_q[row + 1] - s->row_q[row]);
+                double fxc = (double)(s2 - cq[col]) / (double)(cq[col + 1] - cq[col]);
+                double ct = cos(M_PI * row / s->eh), cb = cos(M_PI * (row + 1) / s->eh);
+                double cth = ct + fyr * (cb - ct);
+                double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+                double ph = 2.0 * M_PI * (col + fxc) / s->ew;
+                wi = V3(sth * sin(ph), cth, -sth * cos(ph));
+                size_t q = (size_t)row * s->ew + col;
+                Le = s->env[q];
+                pl = s->p_env * s->env_texel_pdf[q];
+                ok = pl > 0.0;
+            } else {
+                uint32_t col = (uint32_t)(((u128)r * s->ne) / R);
+                uint32_t s7 = or_sample_bits(i, base + 7, W, H, op->scramble);
+                uint32_t e = (uint64_t)s7 < s->alias_thr[col] ? col : s->alias_idx[col];
+                uint32_t lt = s->emit_tri[e];
+                double q1 = u24(or_sample_bits(i, base + 1, W, H, op->scramble));
+                double q2 = u24(or_sample_bits(i, base + 2, W, H, op->scramble));
+                double su = sqrt(q1);
+                double b0 = 1.0 - su, bb1 = q2 * su, bb2 = su * (1.0 - q2);
+                v3 la = s->p0[lt], lb = s->p1[lt], lc = s->p2[lt];
+                v3 y = add(add(mul(la, b0), mul(lb, bb1)), mul(lc, bb2));
+                v3 nl = cross(sub(lb, la), sub(lc, la));
+                double la2 = len(nl);
+                nl = mul(nl, 1.0 / la2);
+                v3 dv = sub(y, xo);
+                double d2 = dot(dv, dv);
+                dist = sqrt(d2);
+                wi = mul(dv, 1.0 / dist);
+                double cl = -dot(nl, wi);
+                if (cl > 0.0) {
+                    Le = emission_at(s, s->mat[lt], y);
+                    pl = s->emit_pmf[e] / (0.5 * la2) * d2 / cl;
+                    ok = 1;
+                }
+            }
+            if (ok) {
+                double ci = dot(n, wi);
+                if (ci > 0.0) {
+                    v3 f;
+                    double pb;
+                    bsdf_eval(s, m, n, wo, wi, &f, &pb);
+                    double w = op->mode == 2 ? 1.0 : mis2(pl, pb);
+                    v3 contrib = mul(vmul(vmul(T, f), Le), ci * w / pl);
+                    if (maxc(contrib) > 0.0) {
+                        hit64 sh;
+                        (*nrays)++;
+                        double tm = isinf(dist) ? INFINITY : dist * (1.0 - 1e-4);
+                        if (!trace64(s, xo, wi, tm, 1, 0, &sh)) L = add(L, contrib);
+                    }
+                }
+            }
+        }
+        /* continue the path by sampling the BSDF */
+        double u3 = u24(or_sample_bits(i, base + 3, W, H, op->scramble));
+        double u4 = u24(or_sample_bits(i, base + 4, W, H, op->scramble));
+        double u5 = u24(or_sample_bits(i, base + 5, W, H, op->scramble));
+        v3 wi;
+        if (!bsdf_sample(s, m, n, wo, u3, u4, u5, &wi)) break;
+        v3 f;
+        double pb;
+        bsdf_eval(s, m, n, wo, wi, &f, &pb);
+        if (!(pb > 0.0)) break;
+        T = vmul(T, mul(f, dot(n, wi) / pb));
+        if (!(maxc(T) > 0.0)) break;
+        prev_pdf = pb;
+        if (op->rr && v >= 3) {
+            double q = fmin(0.95, maxc(T));
+            float qf = (float)q;
+            double qq = ceil((double)qf * 16777216.0) / 16777216.0;
+            double u6 = u24(or_sample_bits(i, base + 6, W, H, op->scramble));
+            if (!(u6 < qq)) break;
+            T = mul(T, 1.0 / qq);
+        }
+        o = xo;
+        d = wi;
+    }
+    return L;
+}
+
+typedef struct {
+    const or_scene *s;
+    const or_opts *op;
+    const uint32_t *pix;
+    uint32_t npix;
+    uint64_t pass0;
+    uint32_t npasses;
+    double *sum, *sumsq;
+    uint32_t *count;
+    uint64_t rays;
+    volatile uint32_t *next;
+    pthread_mutex_t *mu;
+} job;
+
+static void *worker(void *arg)
+{
+    job *jb = (job *)arg;
+    const or_scene *s = jb->s;
+    uint64_t rays = 0;
+    for (;;) {
+        pthread_mutex_lock(jb->mu);
+        uint32_t start = *jb->next;
+        *jb->next = start + 64;
+        pthread_mutex_unlock(jb->mu);
+        if (start >= jb->npix) break;
+        uint32_t end = start + 64 < jb->npix ? start + 64 : jb->npix;
+        for (uint32_t q = start; q < end; ++q) {
+            uint32_t p = jb->pix ? jb->pix[q] : q;
+            uint32_t px = p % s->W, py = p / s->W;
+            for (uint32_t j = 0; j < jb->npasses; ++j) {
+                uint64_t i = or_pixel_index(s->W, s->H, px, py, jb->pass0 + j);
+                uint32_t nr = 0;
+                v3 L = trace_path(s, jb->op, i, px, py, &nr);
+                rays += nr;
+                jb->sum[3 * q] += L.x; jb->sum[3 * q + 1] += L.y; jb->sum[3 * q + 2] += L.z;
+                if (jb->sumsq) {
+                    jb->sumsq[3 * q] += L.x * L.x;
+                    jb->sumsq[3 * q + 1] += L.y * L.y;
+                    jb->sumsq[3 * q + 2] += L.z * L.z;
+                }
+                jb->count[q] += 1;
+            }
+        }
+    }
+    jb->rays = rays;
+    return NULL;
+}
+
+/* Render passes [pass0, pass0 + npasses) for npix pixels (ids p = y*W + x,
+ * or all pixels when pix is NULL). Adds into caller-zeroed sum/sumsq/count,
+ * one entry per listed pixel. Returns the number of rays traced. */
+uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode,
+                   uint32_t scramble, const uint32_t *pix, uint32_t npix, uint64_t pass0,
+                   uint32_t npasses, double *sum, double *sumsq, uint32_t *count,
+                   uint32_t nthreads)
+{
+    or_opts op = {max_depth, rr, mode, scramble};
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t th[256];
+    job jobs[256];
+    volatile uint32_t next = 0;
+    pthread_mutex_t mu;
+    pthread_mutex_init(&mu, NULL);
+    for (uint32_t k = 0; k < nthreads; ++k) {
+        jobs[k] = (job){s, &op, pix, npix, pass0, npasses, sum, sumsq, count, 0, &next, &mu};
+        pthread_create(&th[k], NULL, worker, &jobs[k]);
+    }
+    uint64_t rays = 0;
+    for (uint32_t k = 0; k < nthreads; ++k) {
+        pthread_join(th[k], NULL);
+        rays += jobs[k].rays;
+    }
+    pthread_mutex_destroy(&mu);
+    return rays;
+}
+
+/* ---------------------------------------------- pieces exposed for pins */
+
+void or_camera_ray(const or_scene *s, double fx, double fy, double *o, double *d)
+{
+    double sx = (2.0 * fx / s->W - 1.0) * s->tan_half * s->aspect;
+    double sy = (1.0 - 2.0 * fy / s->H) * s->tan_half;
+    v3 dd = normalize(add(s->fwd, add(mul(s->right, sx), mul(s->up, sy))));
+    o[0] = s->eye.x; o[1] = s->eye.y; o[2] = s->eye.z;
+    d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
+}
+
+/* f (rgb) and pdf of material m for unit n, wo, wi */
+void or_bsdf(const or_scene *s, uint32_t m, const double *n, const double *wo, const double *wi,
+             double *f, double *pdf)
+{
+    v3 ff;
+    bsdf_eval(s, m, V3(n[0], n[1], n[2]), V3(wo[0], wo[1], wo[2]), V3(wi[0], wi[1], wi[2]), &ff, pdf);
+    f[0] = ff.x; f[1] = ff.y; f[2] = ff.z;
+}
+
+int or_bsdf_sample(const or_scene *s, uint32_t m, const double *n, const double *wo, double u3,
+                   double u4, double u5, double *wi)
+{
+    v3 w;
+    int ok = bsdf_sample(s, m, V3(n[0], n[1], n[2]), V3(wo[0], wo[1], wo[2]), u3, u4, u5, &w);
+    wi[0] = w.x; wi[1] = w.y; wi[2] = w.z;
+    return ok;
+}
+
+double or_env_lookup(const or_scene *s, const double *w, double *rgb)
+{
+    double pdf;
+    v3 L = env_lookup(s, V3(w[0], w[1], w[2]), &pdf);
+    rgb[0] = L.x; rgb[1] = L.y; rgb[2] = L.z;
+    return pdf;
+}
+
+double or_ggx_D(double cos_h, double alpha) { return ggx_D(cos_h, alpha * alpha); }
+
+void or_bsdf_batch(const or_scene *s, uint32_t m, const double *n, const double *wo,
+                   const double *wi, uint32_t cnt, double *f, double *pdf)
+{
+    for (uint32_t q = 0; q < cnt; ++q) or_bsdf(s, m, n, wo, wi + 3 * (size_t)q, f + 3 * (size_t)q, pdf + q);
+}
+
+void or_bsdf_sample_batch(const or_scene *s, uint32_t m, const double *n, const double *wo,
+                          const double *u, uint32_t cnt, double *wi, int32_t *ok)
+{
+    for (uint32_t q = 0; q < cnt; ++q)
+        ok[q] = or_bsdf_sample(s, m, n, wo, u[3 * (size_t)q], u[3 * (size_t)q + 1],
+                               u[3 * (size_t)q + 2], wi + 3 * (size_t)q);
+}
