@@ -1,0 +1,208 @@
+/*
+ * qpt -- progressive quasi-Monte Carlo path tracing on MI355X (gfx950).
+ *
+ * C-ABI of the library libqpt.so. Every entry point returns 0 (QPT_OK) on
+ * success or a negative QPT_E_* status; the message of the last failure is
+ * qpt_last_error(). No exception crosses this boundary.
+ *
+ * The calls follow the paper's statement of the problem:
+ *   - rendering is push-button, progressive and consistent (Sec. 1.1);
+ *   - each GPU holds a full copy of the scene (Sec. 5, no out-of-core data);
+ *   - work is handed out as iterations of one sample per pixel, grouped in
+ *     iteration sets (Sec. 3.2.2, batch rendering);
+ *   - each device accumulates into its own framebuffer copy, which is merged
+ *     out (Sec. 3.2.2) -- here: read back;
+ *   - a per-pixel sample count buffer records progress (Appendix A.4);
+ *   - acceleration structures are built per scene (Sec. 2.5, Sec. 3.1).
+ *
+ * Ownership. Host inputs are copied before the call returns. Device memory
+ * comes from the caller only, through qpt_bind_workspace: the library never
+ * allocates or frees device memory, and the caller keeps the workspace alive
+ * (and unmodified) until qpt_destroy or the next qpt_bind_workspace. Output
+ * buffers belong to the caller.
+ *
+ * Streams. All device work is enqueued on the stream given to qpt_create
+ * (a hipStream_t; NULL = the default stream). Calls on one context are not
+ * thread-safe; use one context per stream.
+ *
+ * Call order: create -> build_scene -> build_bvh -> workspace_size ->
+ * bind_workspace -> render_pass* -> readback; violations return QPT_E_STATE.
+ */
+#ifndef QPT_H
+#define QPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QPT_OK = 0,
+    QPT_E_INVALID = -1,      /* bad argument or size */
+    QPT_E_STATE = -2,        /* call out of order */
+    QPT_E_NOMEM = -3,        /* workspace too small */
+    QPT_E_HIP = -4,          /* HIP runtime error (message in qpt_last_error) */
+    QPT_E_UNSUPPORTED = -5,  /* device is not gfx950 */
+    QPT_E_ABORTED = -6
+};
+
+/* material flags */
+#define QPT_MAT_GGX 1u           /* GGX specular layer over the Lambert base */
+#define QPT_MAT_EMIT_TEXTURE 2u  /* emission times 0.55 + 0.45 sin(8 pi (x + z)) */
+
+typedef struct qpt_ctx qpt_ctx;
+
+typedef struct {
+    float albedo[3];     /* Lambert base reflectance, linear RGB */
+    float roughness;     /* GGX alpha (used with QPT_MAT_GGX) */
+    float emission[3];   /* front-face radiance; non-zero makes every triangle of it a light */
+    uint32_t flags;      /* QPT_MAT_* */
+} qpt_material;
+
+typedef struct {
+    float eye[3], look[3], up[3];
+    float vfov_deg;      /* vertical field of view of the pinhole camera */
+} qpt_camera;
+
+/* Scene description: all pointers are HOST memory, copied by qpt_build_scene.
+ * Triangles are counter-clockwise seen from their emitting (front) side. */
+typedef struct {
+    uint32_t num_vertices;
+    const float *positions;        /* 3 * num_vertices */
+    uint32_t num_triangles;
+    const uint32_t *indices;       /* 3 * num_triangles, each < num_vertices */
+    const uint32_t *tri_material;  /* num_triangles, each < num_materials */
+    uint32_t num_materials;
+    const qpt_material *materials; /* num_materials */
+    uint32_t env_width, env_height;/* 0, 0 = no environment */
+    const float *env_rgb;          /* env_height * env_width * 3, lat-long, row 0 at +y */
+    qpt_camera camera;
+    uint32_t width, height;        /* framebuffer size in pixels */
+} qpt_scene_desc;
+
+typedef struct {
+    uint32_t max_leaf_size;  /* triangles per leaf, 1..8 (0 = 4) */
+    uint32_t sah_bins;       /* binned SAH bins, 4..64 (0 = 16) */
+} qpt_bvh_opts;
+
+typedef struct {
+    uint32_t num_nodes;      /* inner nodes */
+    uint32_t num_leaves;
+    uint32_t max_depth;      /* root = depth 0 */
+    uint32_t reserved;
+    double sah_cost;         /* SAH cost with unit traversal and intersection costs */
+    double build_ms;
+} qpt_bvh_stats;
+
+typedef struct {
+    uint32_t max_depth;      /* D: path segments, emission at vertices 1..D, NEE at 1..D-1 */
+    uint32_t rr;             /* 1: Russian roulette from vertex 3 */
+    uint32_t mode;           /* 0: NEE + BSDF sampling with MIS, 1: BSDF sampling only, 2: NEE only */
+    uint32_t scramble;       /* 1: linear digit scrambling of dimensions >= 2 */
+} qpt_render_opts;
+
+typedef struct {
+    uint64_t rays_extension; /* closest-hit rays traced since the last reset */
+    uint64_t rays_shadow;    /* occlusion rays traced */
+    uint64_t paths;          /* paths completed */
+    uint64_t passes;         /* 1-spp iterations completed */
+} qpt_stats;
+
+/* Create a context on HIP device `hip_device` that enqueues on `hip_stream`
+ * (hipStream_t or NULL). QPT_E_UNSUPPORTED if the device is not gfx950.
+ * hip_device = -1 makes a host-only context: the scene and BVH builders and
+ * the host-table hooks work, every device call returns QPT_E_STATE. */
+int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out);
+void qpt_destroy(qpt_ctx *ctx);
+/* message of the last failing call on ctx ("" if none); valid until the next call */
+const char *qpt_last_error(const qpt_ctx *ctx);
+
+/* Copy and validate the scene; build per-triangle flux (16-point rule), the
+ * power-proportional alias table and the environment CDFs on the host in FP64
+ * (Sec. 2.1.1 one flux value per triangle; Sec. 2.1.2 environment importance
+ * sampling). Invalidates a bound workspace. */
+int qpt_build_scene(qpt_ctx *ctx, const qpt_scene_desc *desc);
+
+/* Build the BVH on the host (binned SAH) and lay it out for the GPU
+ * (Sec. 2.3: watertight traversal; Sec. 3.1 replaces the paper's ray casting
+ * library with the library's own traversal). stats may be NULL. */
+int qpt_build_bvh(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
+
+/* Bytes of device workspace needed for `pool_paths` concurrent paths
+ * (0 = 2^21). Scene, BVH, path state, queues and framebuffer all live in it. */
+int qpt_workspace_size(const qpt_ctx *ctx, uint32_t pool_paths, size_t *bytes);
+
+/* Bind caller-owned device memory (256-byte aligned, `bytes` from
+ * qpt_workspace_size) and upload the scene into it; the call returns after
+ * the upload completed. Clears the framebuffer and statistics. */
+int qpt_bind_workspace(qpt_ctx *ctx, void *device_ptr, size_t bytes, uint32_t pool_paths);
+
+/* Enqueue iterations [first_pass, first_pass + num_passes), each one sample
+ * per pixel over the whole frame (Sec. 3.2.2), and accumulate them into the
+ * FP64 framebuffer and the per-pixel counts (Appendix A.4). Asynchronous:
+ * returns after enqueueing. Iteration j of pixel p uses the Halton index
+ * i0(p) + j * 2^k 3^l (Appendix A.2, full-screen enumeration). */
+int qpt_render_pass(qpt_ctx *ctx, uint64_t first_pass, uint32_t num_passes,
+                    const qpt_render_opts *opts);
+
+/* Synchronise the stream and copy the FP64 sums (height*width*3, row-major,
+ * pixel (x, y) at y*width + x) and the uint32 counts (height*width) into
+ * caller buffers; either pointer may be NULL. dst_is_device: 1 if the
+ * buffers are device memory, 0 for host memory. Image = sum / count. */
+int qpt_readback(qpt_ctx *ctx, double *sum_rgb, uint32_t *counts, int dst_is_device);
+
+/* Zero the framebuffer, the counts and the statistics (enqueued on the stream). */
+int qpt_reset_accum(qpt_ctx *ctx);
+
+/* Synchronise and read the ray/path counters. */
+int qpt_get_stats(qpt_ctx *ctx, qpt_stats *out);
+
+/* ---- parity hooks: inputs and outputs are DEVICE pointers, enqueued on the
+ * stream; call qpt_readback or synchronise the stream before reading ---- */
+
+/* out[q] = floor(2^32 * scrambled radical inverse of idx[q] in dimension dim[q])
+ * with the film dimensions 0 and 1 taken as the digits left after the pixel's
+ * own (Appendix A.2). dim[q] < 256. */
+int qpt_debug_sample_bits(qpt_ctx *ctx, const uint64_t *idx, const uint32_t *dim, uint32_t n,
+                          int scramble, uint32_t *out);
+
+/* out[y*width + x] = Halton index of pixel (x, y) in iteration `pass`. */
+int qpt_debug_pixel_index(qpt_ctx *ctx, uint64_t pass, uint64_t *out);
+
+/* Trace n rays (n x 8 floats: ox oy oz tmax dx dy dz unused) through the
+ * BVH (brute_force = 0) or against every triangle (brute_force = 1).
+ * Closest hit: t[n], tri[n] (input triangle id, 0xffffffff on a miss),
+ * b12[2n] barycentrics of vertices 1 and 2. any_hit = 1: tri[q] = 1 if
+ * occluded, else 0 (t and b12 may be NULL). */
+int qpt_debug_trace(qpt_ctx *ctx, const float *rays, uint32_t n, int any_hit, int brute_force,
+                    float *t, uint32_t *tri, float *b12);
+
+/* ---- host-table hooks (host memory, no device needed), for cross-checks of
+ * the builders against an independent implementation ---- */
+
+/* Emitters in ascending input-triangle order: input triangle id, alias
+ * probability (FP64 Vose table), alias index, realised selection pmf of the
+ * integer selection rule. *count receives the number of emitters; array
+ * pointers may be NULL (query the count first). After qpt_build_scene. */
+int qpt_debug_light_tables(const qpt_ctx *ctx, uint32_t *emit_tri, double *prob, uint32_t *alias,
+                           double *pmf, uint32_t *count);
+
+/* Environment tables: row CDF row_q[env_height] (2^32 scale, row_q[0] = 0),
+ * column CDFs col_q[env_height * env_width], texel solid-angle pdfs
+ * texel_pdf[env_height * env_width]. QPT_E_STATE without an environment. */
+int qpt_debug_env_tables(const qpt_ctx *ctx, uint32_t *row_q, uint32_t *col_q, float *texel_pdf);
+
+/* The GPU BVH: nodes16[num_nodes * 16] (each node: child-0 box lo.xyz hi.xyz,
+ * child-1 box lo.xyz hi.xyz, two int32 child references: >= 0 inner node,
+ * < 0 leaf with ~ref = first << 3 | (count - 1)) and tri_order[num_triangles]
+ * (input id of each leaf-order triangle). Pointers may be NULL. After
+ * qpt_build_bvh. */
+int qpt_debug_bvh_nodes(const qpt_ctx *ctx, float *nodes16, uint32_t *tri_order, uint32_t *num_nodes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPT_H */

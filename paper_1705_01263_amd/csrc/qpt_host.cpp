@@ -1,0 +1,1065 @@
+// Host side of libqpt: context, scene ingest, light and environment tables,
+// Halton constant tables, BVH construction, workspace layout and the C-ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <future>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "qpt.h"
+#include "qpt_internal.h"
+
+using namespace qpt;
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+struct Vec3 {
+    double x, y, z;
+};
+inline Vec3 vsub(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline Vec3 vadd(Vec3 a, Vec3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline Vec3 vscale(Vec3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline Vec3 vcross(Vec3 a, Vec3 b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double vlen(Vec3 a) { return std::sqrt(a.x * a.x + a.y * a.y + a.z * a.z); }
+inline double luminance(double r, double g, double b) { return 0.2126 * r + 0.7152 * g + 0.0722 * b; }
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------- Halton
+
+std::vector<uint32_t> first_primes(uint32_t n)
+{
+    std::vector<uint32_t> p;
+    for (uint32_t c = 2; p.size() < n; ++c) {
+        bool prime = true;
+        for (uint32_t q : p) {
+            if (q * q > c) break;
+            if (c % q == 0) { prime = false; break; }
+        }
+        if (prime) p.push_back(c);
+    }
+    return p;
+}
+
+// Granlund-Montgomery round-up multiplier for unsigned division by d of
+// N-bit dividends: q = (t + ((n - t) >> 1)) >> (l - 1), t = mulhi(m, n),
+// l = ceil(log2 d) >= 1, m = floor(2^N (2^l - d) / d) + 1.
+void magic32(uint32_t d, uint32_t *m, uint32_t *sh)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    uint64_t mm = (((uint64_t)1 << 32) * ((1ull << l) - d)) / d + 1;
+    *m = (uint32_t)mm;
+    *sh = l - 1;
+}
+
+void magic64(uint64_t d, uint64_t *m, uint32_t *sh)
+{
+    uint32_t l = 0;
+    while (l < 64 && ((u128)1 << l) < d) ++l;
+    u128 mm = (((u128)1 << 64) * (((u128)1 << l) - d)) / d + 1;
+    *m = (uint64_t)mm;
+    *sh = l - 1;
+}
+
+uint32_t scramble_multiplier(uint32_t b)
+{
+    // round(0.618034 b), kept in [1, b - 1]
+    uint64_t f = ((uint64_t)b * 618034u + 500000u) / 1000000u;
+    if (f < 1) f = 1;
+    if (f > b - 1) f = b - 1;
+    return (uint32_t)f;
+}
+
+std::vector<HaltonBase> make_bases()
+{
+    std::vector<uint32_t> pr = first_primes(kMaxDims);
+    std::vector<HaltonBase> out(kMaxDims);
+    for (uint32_t d = 0; d < kMaxDims; ++d) {
+        HaltonBase h{};
+        h.b = pr[d];
+        h.f = scramble_multiplier(h.b);
+        uint64_t B = h.b;
+        uint32_t e = 1;
+        while (B * h.b < (1ull << 32)) { B *= h.b; ++e; }
+        h.e = e;
+        h.B = B;
+        magic32(h.b, &h.m32, &h.sh32);
+        magic64(B, &h.m64, &h.shB);
+        out[d] = h;
+    }
+    return out;
+}
+
+// ------------------------------------------------------------------- BVH
+
+struct BuildNode {
+    float lo[3], hi[3];
+    int32_t left = -1, right = -1;  // inner: child indices
+    uint32_t first = 0, count = 0;  // leaf: primitive range
+    uint32_t depth = 0;
+};
+
+struct PrimInfo {
+    float lo[3], hi[3];
+    float c[3];
+};
+
+struct Builder {
+    const std::vector<PrimInfo> &prim;
+    std::vector<uint32_t> &order;
+    std::vector<BuildNode> nodes;
+    std::atomic<uint32_t> next{0};
+    uint32_t leaf_size, bins;
+    std::atomic<uint32_t> max_depth{0};
+
+    Builder(const std::vector<PrimInfo> &p, std::vector<uint32_t> &o, uint32_t ls, uint32_t nb)
+        : prim(p), order(o), leaf_size(ls), bins(nb)
+    {
+        nodes.resize(std::max<size_t>(2 * p.size(), 2));
+    }
+
+    static float area(const float lo[3], const float hi[3])
+    {
+        float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+        if (dx < 0 || dy < 0 || dz < 0) return 0.0f;
+        return 2.0f * (dx * dy + dy * dz + dz * dx);
+    }
+
+    uint32_t build(uint32_t first, uint32_t count, uint32_t depth, int spawn_budget)
+    {
+        uint32_t me = next.fetch_add(1);
+        BuildNode &nd = nodes[me];
+        nd.depth = depth;
+        uint32_t md = max_depth.load();
+        while (depth > md && !max_depth.compare_exchange_weak(md, depth)) {
+        }
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        float clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (uint32_t q = first; q < first + count; ++q) {
+            const PrimInfo &p = prim[order[q]];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], p.lo[a]);
+                hi[a] = std::max(hi[a], p.hi[a]);
+                clo[a] = std::min(clo[a], p.c[a]);
+                chi[a] = std::max(chi[a], p.c[a]);
+            }
+        }
+        std::memcpy(nd.lo, lo, sizeof lo);
+        std::memcpy(nd.hi, hi, sizeof hi);
+        if (count <= leaf_size) {
+            nd.first = first;
+            nd.count = count;
+            return me;
+        }
+        // levels a balanced split still needs below this node
+        uint32_t need = 0;
+        while (((uint64_t)leaf_size << need) < count) ++need;
+        bool force_median = depth + need + 1 >= kMaxTreeDepth - 1;
+
+        int best_axis = -1;
+        uint32_t best_split = 0;
+        float best_cost = INFINITY;
+        if (!force_median) {
+            std::vector<uint32_t> cnt(bins);
+            std::vector<float> blo(bins * 3), bhi(bins * 3);
+            std::vector<float> rarea(bins);
+            std::vector<uint32_t> rcnt(bins);
+            for (int a = 0; a < 3; ++a) {
+                float ext = chi[a] - clo[a];
+                if (!(ext > 0.0f)) continue;
+                std::fill(cnt.begin(), cnt.end(), 0u);
+                for (uint32_t b = 0; b < bins; ++b)
+                    for (int k = 0; k < 3; ++k) { blo[b * 3 + k] = INFINITY; bhi[b * 3 + k] = -INFINITY; }
+                float scale = bins / ext;
+                for (uint32_t q = first; q < first + count; ++q) {
+                    const PrimInfo &p = prim[order[q]];
+                    uint32_t b = std::min(bins - 1, (uint32_t)((p.c[a] - clo[a]) * scale));
+                    cnt[b]++;
+                    for (int k = 0; k < 3; ++k) {
+                        blo[b * 3 + k] = std::min(blo[b * 3 + k], p.lo[k]);
+                        bhi[b * 3 + k] = std::max(bhi[b * 3 + k], p.hi[k]);
+                    }
+                }
+                float rl[3] = {INFINITY, INFINITY, INFINITY}, rh[3] = {-INFINITY, -INFINITY, -INFINITY};
+                uint32_t rc = 0;
+                for (uint32_t b = bins - 1; b > 0; --b) {
+                    for (int k = 0; k < 3; ++k) {
+                        rl[k] = std::min(rl[k], blo[b * 3 + k]);
+                        rh[k] = std::max(rh[k], bhi[b * 3 + k]);
+                    }
+                    rc += cnt[b];
+                    rarea[b] = area(rl, rh);
+                    rcnt[b] = rc;
+                }
+                float ll[3] = {INFINITY, INFINITY, INFINITY}, lh[3] = {-INFINITY, -INFINITY, -INFINITY};
+                uint32_t lc = 0;
+                for (uint32_t b = 0; b + 1 < bins; ++b) {
+                    for (int k = 0; k < 3; ++k) {
+                        ll[k] = std::min(ll[k], blo[b * 3 + k]);
+                        lh[k] = std::max(lh[k], bhi[b * 3 + k]);
+                    }
+                    lc += cnt[b];
+                    if (lc == 0 || rcnt[b + 1] == 0) continue;
+                    float cost = area(ll, lh) * lc + rarea[b + 1] * rcnt[b + 1];
+                    if (cost < best_cost) { best_cost = cost; best_axis = a; best_split = b + 1; }
+                }
+            }
+        }
+        uint32_t mid;
+        if (best_axis >= 0) {
+            float ext = chi[best_axis] - clo[best_axis];
+            float scale = bins / ext;
+            int a = best_axis;
+            float c0 = clo[a];
+            uint32_t nb = bins, sp = best_split;
+            auto it = std::partition(order.begin() + first, order.begin() + first + count,
+                                     [&](uint32_t q) {
+                                         uint32_t b = std::min(nb - 1, (uint32_t)((prim[q].c[a] - c0) * scale));
+                                         return b < sp;
+                                     });
+            mid = (uint32_t)(it - order.begin());
+            if (mid == first || mid == first + count) mid = first + count / 2;
+        } else {
+            // object median on the widest centroid axis (or plain index median)
+            int a = 0;
+            for (int k = 1; k < 3; ++k)
+                if (chi[k] - clo[k] > chi[a] - clo[a]) a = k;
+            mid = first + count / 2;
+            std::nth_element(order.begin() + first, order.begin() + mid, order.begin() + first + count,
+                             [&](uint32_t x, uint32_t y) {
+                                 if (prim[x].c[a] != prim[y].c[a]) return prim[x].c[a] < prim[y].c[a];
+                                 return x < y;
+                             });
+        }
+        uint32_t l, r;
+        if (spawn_budget > 0 && count > 100000) {
+            auto fut = std::async(std::launch::async, [&]() {
+                return build(first, mid - first, depth + 1, spawn_budget - 1);
+            });
+            r = build(mid, first + count - mid, depth + 1, spawn_budget - 1);
+            l = fut.get();
+        } else {
+            l = build(first, mid - first, depth + 1, 0);
+            r = build(mid, first + count - mid, depth + 1, 0);
+        }
+        nodes[me].left = (int32_t)l;
+        nodes[me].right = (int32_t)r;
+        return me;
+    }
+};
+
+// ------------------------------------------------------------ the context
+
+struct Layout {
+    size_t nodes, tris, mats, emit_tri, alias_idx, alias_thr, emit_pmf, env_texel, env_row,
+        env_col, env_cos, bases;
+    size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats;
+    size_t fb_sum, fb_count;
+    size_t total;
+};
+
+}  // namespace
+
+struct qpt_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool scene_ok = false, bvh_ok = false, bound = false;
+    // scene (host copies)
+    uint32_t W = 0, H = 0;
+    std::vector<float> pos;
+    std::vector<uint32_t> idx, tri_mat;
+    std::vector<qpt_material> mats;
+    uint32_t ew = 0, eh = 0;
+    std::vector<float> env;
+    qpt_camera cam{};
+    // lights (emitter order: ascending input triangle id)
+    std::vector<uint32_t> emit_input_tri;
+    std::vector<double> emit_flux, alias_prob, emit_pmf;
+    std::vector<uint32_t> alias_idx;
+    std::vector<unsigned long long> alias_thr;
+    std::vector<int32_t> tri_emit;
+    double p_env = 0.0;
+    // environment tables
+    std::vector<uint32_t> env_row, env_col;
+    std::vector<float4> env_texel;
+    std::vector<float> env_cos;
+    // Halton + enumeration
+    std::vector<HaltonBase> bases;
+    Frame frame{};
+    // BVH in GPU layout
+    std::vector<Node> gnodes;
+    std::vector<Tri> gtris;
+    std::vector<Material> gmats;
+    std::vector<uint32_t> emit_tri_bvh;
+    // workspace
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    uint32_t pool_cap = 0;
+    Layout lay{};
+    Pool pool{};
+};
+
+namespace {
+
+int fail(qpt_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+// Make ctx->device current for the duration of a call and restore the caller's.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (dev < 0) return;
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define HIP_TRY(ctx, expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(ctx, QPT_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+Vec3 corner(const qpt_ctx *c, uint32_t t, int k)
+{
+    const float *p = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + k]];
+    return {p[0], p[1], p[2]};
+}
+
+// emission of material m at x (front face)
+Vec3 emission_at(const qpt_material &m, Vec3 x)
+{
+    Vec3 E = {m.emission[0], m.emission[1], m.emission[2]};
+    if (m.flags & QPT_MAT_EMIT_TEXTURE) {
+        double k = 0.55 + 0.45 * std::sin(2.0 * kPi * 4.0 * (x.x + x.z));
+        E = vscale(E, k);
+    }
+    return E;
+}
+
+// pi * area * lum(mean emission); mean over the 16 cell centroids of the
+// 4x4 split, upright cell (i, j) then inverted cell (i, j), i outer, j inner
+double triangle_flux(const qpt_ctx *c, uint32_t t)
+{
+    Vec3 a = corner(c, t, 0), b = corner(c, t, 1), d = corner(c, t, 2);
+    const qpt_material &m = c->mats[c->tri_mat[t]];
+    double area = 0.5 * vlen(vcross(vsub(b, a), vsub(d, a)));
+    const int n = 4;
+    double acc = 0.0;
+    auto point = [&](double u, double v) { return vadd(a, vadd(vscale(vsub(b, a), u), vscale(vsub(d, a), v))); };
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; i + j < n; ++j) {
+            Vec3 E = emission_at(m, point((i + 1.0 / 3.0) / n, (j + 1.0 / 3.0) / n));
+            acc += luminance(E.x, E.y, E.z);
+            if (i + j < n - 1) {
+                E = emission_at(m, point((i + 2.0 / 3.0) / n, (j + 2.0 / 3.0) / n));
+                acc += luminance(E.x, E.y, E.z);
+            }
+        }
+    return kPi * area * acc / (double)(n * n);
+}
+
+// Vose alias table with index-ordered FIFO worklists (FP64)
+void build_alias(const std::vector<double> &w, std::vector<double> &prob, std::vector<uint32_t> &alias)
+{
+    size_t n = w.size();
+    prob.assign(n, 1.0);
+    alias.resize(n);
+    double sum = 0.0;
+    for (double x : w) sum += x;
+    std::vector<double> q(n);
+    std::vector<uint32_t> small, large;
+    small.reserve(n);
+    large.reserve(n);
+    for (size_t i = 0; i < n; ++i) {
+        q[i] = (w[i] * (double)n) / sum;
+        (q[i] < 1.0 ? small : large).push_back((uint32_t)i);
+        alias[i] = (uint32_t)i;
+    }
+    size_t sh = 0, lh = 0;
+    while (sh < small.size() && lh < large.size()) {
+        uint32_t s = small[sh++], l = large[lh];
+        prob[s] = q[s];
+        alias[s] = l;
+        q[l] = (q[l] + q[s]) - 1.0;
+        if (q[l] < 1.0) {
+            ++lh;
+            small.push_back(l);
+        }
+    }
+    // leftovers keep prob 1 and alias = self
+}
+
+void build_lights(qpt_ctx *c)
+{
+    uint32_t nt = (uint32_t)c->tri_mat.size();
+    c->emit_input_tri.clear();
+    c->tri_emit.assign(nt, -1);
+    for (uint32_t t = 0; t < nt; ++t) {
+        const qpt_material &m = c->mats[c->tri_mat[t]];
+        if (m.emission[0] > 0 || m.emission[1] > 0 || m.emission[2] > 0) {
+            c->tri_emit[t] = (int32_t)c->emit_input_tri.size();
+            c->emit_input_tri.push_back(t);
+        }
+    }
+    size_t ne = c->emit_input_tri.size();
+    c->emit_flux.resize(ne);
+    for (size_t e = 0; e < ne; ++e) c->emit_flux[e] = triangle_flux(c, c->emit_input_tri[e]);
+    c->alias_prob.clear();
+    c->alias_idx.clear();
+    c->alias_thr.clear();
+    c->emit_pmf.assign(ne, 0.0);
+    if (!ne) return;
+    build_alias(c->emit_flux, c->alias_prob, c->alias_idx);
+    c->alias_thr.resize(ne);
+    for (size_t e = 0; e < ne; ++e)
+        c->alias_thr[e] = (unsigned long long)std::ceil(c->alias_prob[e] * 4294967296.0);
+}
+
+// probability the integer light-selection rule realises for each emitter
+void build_light_pmf(qpt_ctx *c)
+{
+    size_t ne = c->emit_input_tri.size();
+    if (!ne) return;
+    uint64_t R = c->ew ? (1ull << 31) : (1ull << 32);
+    double ptri = 1.0 - c->p_env;
+    for (size_t col = 0; col < ne; ++col) {
+        // #{r in [0, R) : floor(r ne / R) == col}
+        u128 hi = ((u128)(col + 1) * R + ne - 1) / ne, lo = ((u128)col * R + ne - 1) / ne;
+        double pc = (double)(uint64_t)(hi - lo) / (double)R;
+        double take = (double)c->alias_thr[col] / 4294967296.0;
+        c->emit_pmf[col] += ptri * pc * take;
+        c->emit_pmf[c->alias_idx[col]] += ptri * pc * (1.0 - take);
+    }
+}
+
+void build_env(qpt_ctx *c)
+{
+    uint32_t W = c->ew, H = c->eh;
+    c->env_row.assign(H, 0);
+    c->env_col.assign((size_t)W * H, 0);
+    c->env_texel.resize((size_t)W * H);
+    c->env_cos.resize(H + 1);
+    for (uint32_t r = 0; r <= H; ++r) c->env_cos[r] = (float)std::cos(kPi * r / H);
+    std::vector<double> rowsum(H), cdf(W + 1), omega(H);
+    std::vector<uint64_t> colq((size_t)H * (W + 1));
+    for (uint32_t r = 0; r < H; ++r) {
+        double om = (2.0 * kPi / W) * (std::cos(kPi * r / H) - std::cos(kPi * (r + 1) / H));
+        omega[r] = om;
+        cdf[0] = 0.0;
+        for (uint32_t x = 0; x < W; ++x) {
+            const float *L = &c->env[((size_t)r * W + x) * 3];
+            cdf[x + 1] = cdf[x] + luminance(L[0], L[1], L[2]) * om;
+        }
+        rowsum[r] = cdf[W];
+        uint64_t *q = &colq[(size_t)r * (W + 1)];
+        for (uint32_t x = 0; x < W; ++x)
+            q[x] = cdf[W] > 0.0 ? (uint64_t)std::floor(cdf[x] / cdf[W] * 4294967296.0)
+                                : (uint64_t)(((u128)x << 32) / W);
+        q[W] = 1ull << 32;
+    }
+    std::vector<double> C(H + 1);
+    C[0] = 0.0;
+    for (uint32_t r = 0; r < H; ++r) C[r + 1] = C[r] + rowsum[r];
+    std::vector<uint64_t> rowq(H + 1);
+    for (uint32_t r = 0; r < H; ++r) rowq[r] = (uint64_t)std::floor(C[r] / C[H] * 4294967296.0);
+    rowq[H] = 1ull << 32;
+    for (uint32_t r = 0; r < H; ++r) {
+        c->env_row[r] = (uint32_t)rowq[r];
+        double pr = (double)(rowq[r + 1] - rowq[r]) / 4294967296.0;
+        const uint64_t *q = &colq[(size_t)r * (W + 1)];
+        for (uint32_t x = 0; x < W; ++x) {
+            c->env_col[(size_t)r * W + x] = (uint32_t)q[x];
+            double pc = (double)(q[x + 1] - q[x]) / 4294967296.0;
+            const float *L = &c->env[((size_t)r * W + x) * 3];
+            c->env_texel[(size_t)r * W + x] = make_float4(L[0], L[1], L[2], (float)(pr * pc / omega[r]));
+        }
+    }
+}
+
+void set_frame_constants(qpt_ctx *c)
+{
+    Frame &f = c->frame;
+    f.W = c->W;
+    f.H = c->H;
+    uint32_t k = 0, l = 0;
+    uint64_t p2 = 1, p3 = 1;
+    while (p2 < c->W) { p2 *= 2; ++k; }
+    while (p3 < c->H) { p3 *= 3; ++l; }
+    f.k2 = k;
+    f.l3 = l;
+    f.p3 = p3;
+    f.S = p2 * p3;
+    if (p3 > 1) magic64(p3, &f.m_p3, &f.sh_p3);
+    else { f.m_p3 = 0; f.sh_p3 = 0; }
+    // (2^k)^-1 mod 3^l by search (3^l is small)
+    f.inv2k_mod_p3 = 0;
+    for (uint64_t x = 0; x < p3; ++x)
+        if ((p2 % p3) * x % p3 == 1 % p3) { f.inv2k_mod_p3 = (uint32_t)x; break; }
+    // camera basis in FP64, rounded once
+    Vec3 eye = {c->cam.eye[0], c->cam.eye[1], c->cam.eye[2]};
+    Vec3 look = {c->cam.look[0], c->cam.look[1], c->cam.look[2]};
+    Vec3 up = {c->cam.up[0], c->cam.up[1], c->cam.up[2]};
+    Vec3 fwd = vsub(look, eye);
+    fwd = vscale(fwd, 1.0 / vlen(fwd));
+    Vec3 right = vcross(fwd, up);
+    right = vscale(right, 1.0 / vlen(right));
+    Vec3 u = vcross(right, fwd);
+    float *dst[4] = {f.cam.eye, f.cam.fwd, f.cam.right, f.cam.up};
+    Vec3 src[4] = {eye, fwd, right, u};
+    for (int q = 0; q < 4; ++q) {
+        dst[q][0] = (float)src[q].x;
+        dst[q][1] = (float)src[q].y;
+        dst[q][2] = (float)src[q].z;
+    }
+    f.cam.tan_half = (float)std::tan(0.5 * c->cam.vfov_deg * kPi / 180.0);
+    f.cam.aspect = (float)((double)c->W / (double)c->H);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(const qpt_ctx *c, uint32_t cap)
+{
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.nodes = take(c->gnodes.size() * sizeof(Node));
+    L.tris = take(c->gtris.size() * sizeof(Tri));
+    L.mats = take(c->gmats.size() * sizeof(Material));
+    size_t ne = c->emit_input_tri.size();
+    L.emit_tri = take(ne * 4);
+    L.alias_idx = take(ne * 4);
+    L.alias_thr = take(ne * 8);
+    L.emit_pmf = take(ne * 4);
+    L.env_texel = take(c->env_texel.size() * sizeof(float4));
+    L.env_row = take(c->env_row.size() * 4);
+    L.env_col = take(c->env_col.size() * 4);
+    L.env_cos = take(c->env_cos.size() * 4);
+    L.bases = take(kMaxDims * sizeof(HaltonBase));
+    L.ray_o = take((size_t)cap * 16);
+    L.ray_d = take((size_t)cap * 16);
+    L.hit = take((size_t)cap * 16);
+    L.thr = take((size_t)cap * 16);
+    L.rad = take((size_t)cap * 16);
+    L.idx = take((size_t)cap * 8);
+    L.q0 = take((size_t)cap * 4);
+    L.q1 = take((size_t)cap * 4);
+    L.qsh = take((size_t)cap * 4);
+    L.sh_o = take((size_t)cap * 16);
+    L.sh_d = take((size_t)cap * 16);
+    L.sh_c = take((size_t)cap * 16);
+    L.counters = take(128 * 4);
+    L.stats = take(4 * 8);
+    L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
+    L.fb_count = take((size_t)c->W * c->H * 4);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+// ================================================================== C-ABI
+
+extern "C" {
+
+int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
+{
+    if (!out) return QPT_E_INVALID;
+    *out = nullptr;
+    qpt_ctx *c = new (std::nothrow) qpt_ctx();
+    if (!c) return QPT_E_NOMEM;
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    c->bases = make_bases();
+    if (hip_device >= 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+            delete c;
+            return QPT_E_HIP;
+        }
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+            delete c;
+            return QPT_E_UNSUPPORTED;
+        }
+    }
+    *out = c;
+    return QPT_OK;
+}
+
+void qpt_destroy(qpt_ctx *ctx) { delete ctx; }
+
+const char *qpt_last_error(const qpt_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int qpt_build_scene(qpt_ctx *c, const qpt_scene_desc *d)
+{
+    if (!c || !d) return QPT_E_INVALID;
+    c->scene_ok = c->bvh_ok = c->bound = false;
+    c->err.clear();
+    if (!d->positions || !d->indices || !d->tri_material || !d->materials)
+        return fail(c, QPT_E_INVALID, "null scene array");
+    if (!d->num_vertices || !d->num_triangles || !d->num_materials)
+        return fail(c, QPT_E_INVALID, "empty scene");
+    if (!d->width || !d->height || d->width > 16384 || d->height > 16384)
+        return fail(c, QPT_E_INVALID, "framebuffer %ux%u out of range", d->width, d->height);
+    if (d->num_triangles > (1u << 27)) return fail(c, QPT_E_INVALID, "too many triangles");
+    for (uint64_t q = 0; q < 3ull * d->num_vertices; ++q)
+        if (!std::isfinite(d->positions[q])) return fail(c, QPT_E_INVALID, "non-finite position");
+    for (uint64_t q = 0; q < 3ull * d->num_triangles; ++q)
+        if (d->indices[q] >= d->num_vertices) return fail(c, QPT_E_INVALID, "index out of range");
+    for (uint64_t q = 0; q < d->num_triangles; ++q)
+        if (d->tri_material[q] >= d->num_materials) return fail(c, QPT_E_INVALID, "material out of range");
+    for (uint32_t m = 0; m < d->num_materials; ++m) {
+        const qpt_material &mm = d->materials[m];
+        for (int k = 0; k < 3; ++k)
+            if (!(mm.albedo[k] >= 0 && mm.albedo[k] <= 1) || !(mm.emission[k] >= 0) ||
+                !std::isfinite(mm.emission[k]))
+                return fail(c, QPT_E_INVALID, "material %u out of range", m);
+        if ((mm.flags & QPT_MAT_GGX) && !(mm.roughness > 0 && mm.roughness <= 1))
+            return fail(c, QPT_E_INVALID, "material %u roughness out of (0, 1]", m);
+    }
+    if ((d->env_width || d->env_height) && (!d->env_rgb || !d->env_width || !d->env_height))
+        return fail(c, QPT_E_INVALID, "bad environment");
+    c->W = d->width;
+    c->H = d->height;
+    c->pos.assign(d->positions, d->positions + 3ull * d->num_vertices);
+    c->idx.assign(d->indices, d->indices + 3ull * d->num_triangles);
+    c->tri_mat.assign(d->tri_material, d->tri_material + d->num_triangles);
+    c->mats.assign(d->materials, d->materials + d->num_materials);
+    c->ew = d->env_width;
+    c->eh = d->env_height;
+    c->env.assign(d->env_rgb ? d->env_rgb : nullptr,
+                  d->env_rgb ? d->env_rgb + 3ull * c->ew * c->eh : nullptr);
+    c->cam = d->camera;
+    build_lights(c);
+    c->env_row.clear();
+    c->env_col.clear();
+    c->env_texel.clear();
+    c->env_cos.clear();
+    if (c->ew) build_env(c);
+    c->p_env = c->ew ? (c->emit_input_tri.empty() ? 1.0 : 0.5) : 0.0;
+    build_light_pmf(c);
+    if (c->emit_input_tri.empty() && !c->ew) {
+        // a scene without light renders black; still valid
+    }
+    set_frame_constants(c);
+    c->gmats.resize(c->mats.size());
+    for (size_t m = 0; m < c->mats.size(); ++m) {
+        const qpt_material &mm = c->mats[m];
+        uint32_t fl = mm.flags;
+        float flf;
+        std::memcpy(&flf, &fl, 4);
+        c->gmats[m].albedo_rough = make_float4(mm.albedo[0], mm.albedo[1], mm.albedo[2], mm.roughness);
+        c->gmats[m].emission_flags = make_float4(mm.emission[0], mm.emission[1], mm.emission[2], flf);
+    }
+    c->scene_ok = true;
+    return QPT_OK;
+}
+
+int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->scene_ok) return fail(c, QPT_E_STATE, "build_bvh before build_scene");
+    c->bvh_ok = c->bound = false;
+    auto t0 = std::chrono::steady_clock::now();
+    uint32_t leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 4;
+    uint32_t bins = opts && opts->sah_bins ? opts->sah_bins : 16;
+    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64) return fail(c, QPT_E_INVALID, "bad BVH options");
+    uint32_t nt = (uint32_t)c->tri_mat.size();
+    std::vector<PrimInfo> prim(nt);
+    double maxabs = 0.0;
+    for (uint32_t t = 0; t < nt; ++t) {
+        PrimInfo &p = prim[t];
+        for (int a = 0; a < 3; ++a) {
+            float v0 = c->pos[3 * (size_t)c->idx[3 * (size_t)t] + a];
+            float v1 = c->pos[3 * (size_t)c->idx[3 * (size_t)t + 1] + a];
+            float v2 = c->pos[3 * (size_t)c->idx[3 * (size_t)t + 2] + a];
+            p.lo[a] = std::min(v0, std::min(v1, v2));
+            p.hi[a] = std::max(v0, std::max(v1, v2));
+            p.c[a] = 0.5f * (p.lo[a] + p.hi[a]);
+            maxabs = std::max(maxabs, (double)std::max(std::fabs(p.lo[a]), std::fabs(p.hi[a])));
+        }
+    }
+    std::vector<uint32_t> order(nt);
+    for (uint32_t t = 0; t < nt; ++t) order[t] = t;
+    Builder B(prim, order, leaf, bins);
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int budget = 0;
+    while ((1u << budget) < 2 * hw && budget < 6) ++budget;
+    B.build(0, nt, 0, budget);
+    uint32_t nn = B.next.load();
+    if (B.max_depth.load() >= kMaxTreeDepth) return fail(c, QPT_E_INVALID, "BVH deeper than the traversal stack");
+
+    // boxes padded outward so that rounding in the slab test never culls a
+    // triangle the exact triangle test would report
+    float pad = (float)(std::ldexp(std::max(maxabs, 1e-3), -18));
+    // flatten: inner nodes in depth-first order, leaves become references
+    std::vector<int32_t> remap(nn, -1);
+    std::vector<uint32_t> dfs;
+    dfs.reserve(nn);
+    std::vector<uint32_t> stack = {0};
+    while (!stack.empty()) {
+        uint32_t q = stack.back();
+        stack.pop_back();
+        const BuildNode &bn = B.nodes[q];
+        if (bn.count) continue;
+        remap[q] = (int32_t)dfs.size();
+        dfs.push_back(q);
+        stack.push_back((uint32_t)bn.right);
+        stack.push_back((uint32_t)bn.left);
+    }
+    auto ref_of = [&](uint32_t q) -> int32_t {
+        const BuildNode &bn = B.nodes[q];
+        if (bn.count) return ~(int32_t)((bn.first << 3) | (bn.count - 1));
+        return remap[q];
+    };
+    auto set_box = [&](float *dst, const BuildNode &bn) {
+        for (int a = 0; a < 3; ++a) {
+            dst[a] = bn.lo[a] - pad;
+            dst[3 + a] = bn.hi[a] + pad;
+        }
+    };
+    c->gnodes.clear();
+    uint32_t leaves = 0;
+    double sah = 0.0;
+    const BuildNode &root = B.nodes[0];
+    float root_area = Builder::area(root.lo, root.hi);
+    if (root.count) {
+        // a single leaf: one inner node whose two children are that leaf (the
+        // duplicate test of the same triangles cannot change the closest hit)
+        Node n{};
+        float bx[6];
+        set_box(bx, root);
+        n.a = make_float4(bx[0], bx[1], bx[2], bx[3]);
+        n.b = make_float4(bx[4], bx[5], bx[0], bx[1]);
+        n.c = make_float4(bx[2], bx[3], bx[4], bx[5]);
+        n.d = make_int4(ref_of(0), ref_of(0), 0, 0);
+        c->gnodes.push_back(n);
+        leaves = 1;
+        sah = root.count;
+    } else {
+        c->gnodes.resize(dfs.size());
+        for (size_t k = 0; k < dfs.size(); ++k) {
+            const BuildNode &bn = B.nodes[dfs[k]];
+            const BuildNode &l = B.nodes[bn.left], &r = B.nodes[bn.right];
+            float b0[6], b1[6];
+            set_box(b0, l);
+            set_box(b1, r);
+            Node n;
+            n.a = make_float4(b0[0], b0[1], b0[2], b0[3]);
+            n.b = make_float4(b0[4], b0[5], b1[0], b1[1]);
+            n.c = make_float4(b1[2], b1[3], b1[4], b1[5]);
+            n.d = make_int4(ref_of(bn.left), ref_of(bn.right), 0, 0);
+            c->gnodes[k] = n;
+            float a = Builder::area(bn.lo, bn.hi) / root_area;
+            sah += a;
+            for (const BuildNode *ch : {&l, &r})
+                if (ch->count) {
+                    ++leaves;
+                    sah += Builder::area(ch->lo, ch->hi) / root_area * ch->count;
+                }
+        }
+    }
+    // triangles in leaf order
+    c->gtris.resize(nt);
+    c->emit_tri_bvh.assign(c->emit_input_tri.size(), 0);
+    for (uint32_t k = 0; k < nt; ++k) {
+        uint32_t t = order[k];
+        const float *p0 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t]];
+        const float *p1 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + 1]];
+        const float *p2 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + 2]];
+        uint32_t m = c->tri_mat[t], e = c->tri_emit[t] >= 0 ? (uint32_t)c->tri_emit[t] : kNoHit;
+        float mf, tf, ef;
+        std::memcpy(&mf, &m, 4);
+        std::memcpy(&tf, &t, 4);
+        std::memcpy(&ef, &e, 4);
+        c->gtris[k].v0 = make_float4(p0[0], p0[1], p0[2], mf);
+        c->gtris[k].v1 = make_float4(p1[0], p1[1], p1[2], tf);
+        c->gtris[k].v2 = make_float4(p2[0], p2[1], p2[2], ef);
+        if (e != kNoHit) c->emit_tri_bvh[e] = k;
+    }
+    c->bvh_ok = true;
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        stats->num_nodes = (uint32_t)c->gnodes.size();
+        stats->num_leaves = leaves;
+        stats->max_depth = B.max_depth.load();
+        stats->reserved = 0;
+        stats->sah_cost = sah;
+        stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    return QPT_OK;
+}
+
+int qpt_workspace_size(const qpt_ctx *c, uint32_t pool_paths, size_t *bytes)
+{
+    if (!c || !bytes) return QPT_E_INVALID;
+    if (!c->scene_ok || !c->bvh_ok) return QPT_E_STATE;
+    uint32_t cap = pool_paths ? pool_paths : (1u << 21);
+    *bytes = make_layout(c, cap).total;
+    return QPT_OK;
+}
+
+int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool_paths)
+{
+    if (!c) return QPT_E_INVALID;
+    if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
+    if (!c->scene_ok || !c->bvh_ok) return fail(c, QPT_E_STATE, "bind_workspace before build_scene/build_bvh");
+    if (!device_ptr || ((uintptr_t)device_ptr & 255)) return fail(c, QPT_E_INVALID, "workspace must be 256-byte aligned");
+    uint32_t cap = pool_paths ? pool_paths : (1u << 21);
+    if (cap < 64 || cap > (1u << 28)) return fail(c, QPT_E_INVALID, "pool_paths out of range");
+    Layout L = make_layout(c, cap);
+    if (bytes < L.total) return fail(c, QPT_E_NOMEM, "workspace %zu bytes, need %zu", bytes, L.total);
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
+    c->ws = (uint8_t *)device_ptr;
+    c->ws_bytes = bytes;
+    c->pool_cap = cap;
+    c->lay = L;
+    uint8_t *w = c->ws;
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (!n) return hipSuccess;
+        return hipMemcpyAsync(w + off, src, n, hipMemcpyHostToDevice, c->stream);
+    };
+    std::vector<float> pmf32(c->emit_pmf.size());
+    for (size_t e = 0; e < pmf32.size(); ++e) pmf32[e] = (float)c->emit_pmf[e];
+    HIP_TRY(c, up(L.nodes, c->gnodes.data(), c->gnodes.size() * sizeof(Node)));
+    HIP_TRY(c, up(L.tris, c->gtris.data(), c->gtris.size() * sizeof(Tri)));
+    HIP_TRY(c, up(L.mats, c->gmats.data(), c->gmats.size() * sizeof(Material)));
+    HIP_TRY(c, up(L.emit_tri, c->emit_tri_bvh.data(), c->emit_tri_bvh.size() * 4));
+    HIP_TRY(c, up(L.alias_idx, c->alias_idx.data(), c->alias_idx.size() * 4));
+    HIP_TRY(c, up(L.alias_thr, c->alias_thr.data(), c->alias_thr.size() * 8));
+    HIP_TRY(c, up(L.emit_pmf, pmf32.data(), pmf32.size() * 4));
+    HIP_TRY(c, up(L.env_texel, c->env_texel.data(), c->env_texel.size() * sizeof(float4)));
+    HIP_TRY(c, up(L.env_row, c->env_row.data(), c->env_row.size() * 4));
+    HIP_TRY(c, up(L.env_col, c->env_col.data(), c->env_col.size() * 4));
+    HIP_TRY(c, up(L.env_cos, c->env_cos.data(), c->env_cos.size() * 4));
+    HIP_TRY(c, up(L.bases, c->bases.data(), kMaxDims * sizeof(HaltonBase)));
+    Frame &f = c->frame;
+    f.nodes = (const Node *)(w + L.nodes);
+    f.tris = (const Tri *)(w + L.tris);
+    f.mats = (const Material *)(w + L.mats);
+    f.num_tris = (uint32_t)c->gtris.size();
+    f.num_emit = (uint32_t)c->emit_input_tri.size();
+    f.emit_tri = (const uint32_t *)(w + L.emit_tri);
+    f.alias_idx = (const uint32_t *)(w + L.alias_idx);
+    f.alias_thr = (const unsigned long long *)(w + L.alias_thr);
+    f.emit_pmf = (const float *)(w + L.emit_pmf);
+    f.env_w = c->ew;
+    f.env_h = c->eh;
+    f.env_texel = (const float4 *)(w + L.env_texel);
+    f.env_row = (const uint32_t *)(w + L.env_row);
+    f.env_col = (const uint32_t *)(w + L.env_col);
+    f.env_cos = (const float *)(w + L.env_cos);
+    f.p_env = (float)c->p_env;
+    f.bases = (const HaltonBase *)(w + L.bases);
+    Pool &p = c->pool;
+    p.cap = cap;
+    p.ray_o = (float4 *)(w + L.ray_o);
+    p.ray_d = (float4 *)(w + L.ray_d);
+    p.hit = (float4 *)(w + L.hit);
+    p.thr = (float4 *)(w + L.thr);
+    p.rad = (float4 *)(w + L.rad);
+    p.idx = (unsigned long long *)(w + L.idx);
+    p.q_ext[0] = (uint32_t *)(w + L.q0);
+    p.q_ext[1] = (uint32_t *)(w + L.q1);
+    p.q_sh = (uint32_t *)(w + L.qsh);
+    p.sh_o = (float4 *)(w + L.sh_o);
+    p.sh_d = (float4 *)(w + L.sh_d);
+    p.sh_c = (float4 *)(w + L.sh_c);
+    p.counters = (uint32_t *)(w + L.counters);
+    p.stats = (unsigned long long *)(w + L.stats);
+    p.fb_sum = (double *)(w + L.fb_sum);
+    p.fb_count = (uint32_t *)(w + L.fb_count);
+    c->bound = true;
+    int rc = qpt_reset_accum(c);
+    if (rc) {
+        c->bound = false;
+        return rc;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return QPT_OK;
+}
+
+int qpt_reset_accum(qpt_ctx *c)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    DeviceGuard g(c->device);
+    size_t npix = (size_t)c->W * c->H;
+    HIP_TRY(c, launch_fill_f64(c->pool.fb_sum, npix * 3, c->stream));
+    HIP_TRY(c, launch_fill_u32(c->pool.fb_count, npix, 0, c->stream));
+    HIP_TRY(c, launch_fill_u32((uint32_t *)c->pool.stats, 8, 0, c->stream));
+    return QPT_OK;
+}
+
+int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const qpt_render_opts *o)
+{
+    if (!c || !o) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
+    if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2)
+        return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2)");
+    if (!num_passes) return QPT_OK;
+    // the largest Halton index must fit 64 bits
+    u128 last = (u128)(first_pass + num_passes) * c->frame.S;
+    if (last >> 64) return fail(c, QPT_E_INVALID, "pass range overflows 64-bit sample indices");
+    DeviceGuard g(c->device);
+    Frame f = c->frame;
+    f.max_depth = o->max_depth;
+    f.rr = o->rr;
+    f.mode = o->mode;
+    f.scramble = o->scramble;
+    uint32_t npix = c->W * c->H, cap = c->pool_cap;
+    if (npix <= cap) {
+        uint32_t per = std::max(1u, cap / npix);
+        for (uint32_t done = 0; done < num_passes;) {
+            uint32_t nb = std::min(per, num_passes - done);
+            HIP_TRY(c, launch_render_batch(f, c->pool, 0, npix, first_pass + done, nb, c->stream));
+            done += nb;
+        }
+    } else {
+        for (uint32_t j = 0; j < num_passes; ++j)
+            for (uint32_t p0 = 0; p0 < npix; p0 += cap)
+                HIP_TRY(c, launch_render_batch(f, c->pool, p0, std::min(cap, npix - p0), first_pass + j, 1,
+                                               c->stream));
+    }
+    return QPT_OK;
+}
+
+int qpt_readback(qpt_ctx *c, double *sum_rgb, uint32_t *counts, int dst_is_device)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "readback before bind_workspace");
+    DeviceGuard g(c->device);
+    size_t npix = (size_t)c->W * c->H;
+    hipMemcpyKind k = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (sum_rgb) HIP_TRY(c, hipMemcpyAsync(sum_rgb, c->pool.fb_sum, npix * 3 * 8, k, c->stream));
+    if (counts) HIP_TRY(c, hipMemcpyAsync(counts, c->pool.fb_count, npix * 4, k, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return QPT_OK;
+}
+
+int qpt_get_stats(qpt_ctx *c, qpt_stats *out)
+{
+    if (!c || !out) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    DeviceGuard g(c->device);
+    unsigned long long s[4];
+    HIP_TRY(c, hipMemcpyAsync(s, c->pool.stats, sizeof s, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out->rays_extension = s[0];
+    out->rays_shadow = s[1];
+    out->paths = s[2];
+    out->passes = s[2] / ((uint64_t)c->W * c->H);
+    return QPT_OK;
+}
+
+int qpt_debug_sample_bits(qpt_ctx *c, const uint64_t *idx, const uint32_t *dim, uint32_t n, int scramble,
+                          uint32_t *out)
+{
+    if (!c || (n && (!idx || !dim || !out))) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_debug_sample_bits(c->frame, idx, dim, n, scramble, out, c->stream));
+    return QPT_OK;
+}
+
+int qpt_debug_pixel_index(qpt_ctx *c, uint64_t pass, uint64_t *out)
+{
+    if (!c || !out) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    u128 last = (u128)(pass + 1) * c->frame.S;
+    if (last >> 64) return fail(c, QPT_E_INVALID, "pass overflows 64-bit sample indices");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_debug_pixel_index(c->frame, pass, out, c->stream));
+    return QPT_OK;
+}
+
+int qpt_debug_trace(qpt_ctx *c, const float *rays, uint32_t n, int any_hit, int brute_force, float *t,
+                    uint32_t *tri, float *b12)
+{
+    if (!c || (n && (!rays || !tri))) return QPT_E_INVALID;
+    if (!any_hit && n && (!t || !b12)) return fail(c, QPT_E_INVALID, "closest hit needs t and b12");
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_debug_trace(c->frame, rays, n, any_hit, brute_force, t, tri, b12, c->stream));
+    return QPT_OK;
+}
+
+/* host-side table access (no device needed), for cross-checks of the
+ * builders against an independent implementation */
+int qpt_debug_light_tables(const qpt_ctx *c, uint32_t *emit_tri, double *prob, uint32_t *alias, double *pmf,
+                           uint32_t *count)
+{
+    if (!c || !count) return QPT_E_INVALID;
+    if (!c->scene_ok) return QPT_E_STATE;
+    size_t ne = c->emit_input_tri.size();
+    *count = (uint32_t)ne;
+    for (size_t e = 0; e < ne; ++e) {
+        if (emit_tri) emit_tri[e] = c->emit_input_tri[e];
+        if (prob) prob[e] = c->alias_prob[e];
+        if (alias) alias[e] = c->alias_idx[e];
+        if (pmf) pmf[e] = c->emit_pmf[e];
+    }
+    return QPT_OK;
+}
+
+int qpt_debug_env_tables(const qpt_ctx *c, uint32_t *row_q, uint32_t *col_q, float *texel_pdf)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->scene_ok || !c->ew) return QPT_E_STATE;
+    if (row_q) std::memcpy(row_q, c->env_row.data(), c->env_row.size() * 4);
+    if (col_q) std::memcpy(col_q, c->env_col.data(), c->env_col.size() * 4);
+    if (texel_pdf)
+        for (size_t q = 0; q < c->env_texel.size(); ++q) texel_pdf[q] = c->env_texel[q].w;
+    return QPT_OK;
+}
+
+int qpt_debug_bvh_nodes(const qpt_ctx *c, float *nodes16, uint32_t *tri_order, uint32_t *num_nodes)
+{
+    if (!c || !num_nodes) return QPT_E_INVALID;
+    if (!c->bvh_ok) return QPT_E_STATE;
+    *num_nodes = (uint32_t)c->gnodes.size();
+    if (nodes16) std::memcpy(nodes16, c->gnodes.data(), c->gnodes.size() * sizeof(Node));
+    if (tri_order)
+        for (size_t k = 0; k < c->gtris.size(); ++k) std::memcpy(&tri_order[k], &c->gtris[k].v1.w, 4);
+    return QPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal layout shared by the host side and the HIP kernels of libqpt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qpt {
+
+constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
+constexpr uint32_t kStackSize = 32;      // traversal stack entries per ray (LDS)
+constexpr uint32_t kMaxTreeDepth = 32;   // builder guarantee: stack never overflows
+constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
+constexpr uint32_t kNoHit = 0xffffffffu;
+
+// One base of the Halton sequence with its strength-reduced divisions
+// (Appendix A.2: integer evaluation, division by multiplication).
+// Digits are processed in chunks of e digits, B = b^e < 2^32.
+struct HaltonBase {
+    uint32_t b;        // prime base
+    uint32_t f;        // scrambling multiplier: digit a -> f*a mod b
+    uint32_t e;        // digits per chunk
+    uint32_t m32;      // magic for n/b, n < 2^32
+    uint32_t sh32;     // post-shift for n/b
+    uint32_t shB;      // post-shift for n/B
+    uint64_t B;        // b^e
+    uint64_t m64;      // magic for n/B, n < 2^64
+};
+
+// BVH2 node: both children's boxes plus child references (64 bytes).
+// ref >= 0: inner node index. ref < 0: leaf, ~ref = first << 3 | (count - 1).
+struct alignas(16) Node {
+    float4 a;   // c0.lo.xyz, c0.hi.x
+    float4 b;   // c0.hi.yz,  c1.lo.xy
+    float4 c;   // c1.lo.z,   c1.hi.xyz
+    int4 d;     // ref0, ref1, -, -
+};
+
+// Triangle in BVH order (48 bytes): v0.w = material, v1.w = input id,
+// v2.w = emitter index (or kNoHit).
+struct alignas(16) Tri {
+    float4 v0, v1, v2;
+};
+
+struct alignas(16) Material {
+    float4 albedo_rough;    // rho.rgb, alpha
+    float4 emission_flags;  // Le.rgb, flags (bits)
+};
+
+struct Camera {
+    float eye[3], fwd[3], right[3], up[3];
+    float tan_half, aspect;
+};
+
+// Everything a kernel needs, by value (device pointers into the workspace).
+struct Frame {
+    // scene
+    const Node *nodes;
+    const Tri *tris;
+    const Material *mats;
+    uint32_t num_tris;
+    // lights (emitter order = ascending input triangle id)
+    uint32_t num_emit;
+    const uint32_t *emit_tri;             // BVH-order triangle of emitter e
+    const uint32_t *alias_idx;
+    const unsigned long long *alias_thr;  // take column iff bits < thr (2^32 scale)
+    const float *emit_pmf;                // realised selection probability
+    // environment
+    uint32_t env_w, env_h;
+    const float4 *env_texel;              // rgb, solid-angle pdf
+    const uint32_t *env_row;              // env_h entries, row_q[0] = 0
+    const uint32_t *env_col;              // env_h * env_w
+    const float *env_cos;                 // env_h + 1 row boundary cosines
+    float p_env;                          // probability of choosing the environment
+    // Halton
+    const HaltonBase *bases;              // kMaxDims
+    uint32_t k2, l3;                      // 2^k >= W, 3^l >= H
+    uint64_t S;                           // 2^k 3^l
+    uint64_t p3, m_p3;                    // 3^l and its 64-bit magic
+    uint32_t sh_p3, inv2k_mod_p3;         // (2^k)^-1 mod 3^l
+    // camera and frame
+    Camera cam;
+    uint32_t W, H;
+    // options
+    uint32_t max_depth, rr, mode, scramble;
+};
+
+// Path pool (structure of arrays, Sec. 3.1.1) and queues (Sec. 3.1.2).
+struct Pool {
+    uint32_t cap;
+    float4 *ray_o;      // o.xyz, tmax
+    float4 *ray_d;      // d.xyz, -
+    float4 *hit;        // t, tri (BVH order, bits), b1, b2
+    float4 *thr;        // throughput.rgb, pdf of the last BSDF sample
+    float4 *rad;        // radiance.rgb, -
+    unsigned long long *idx;   // Halton index of the path
+    uint32_t *q_ext[2]; // extension-ray queues (ping-pong)
+    uint32_t *q_sh;     // shadow queue -> slot
+    float4 *sh_o;       // shadow ray o.xyz, tmax
+    float4 *sh_d;       // shadow ray d.xyz, slot (bits)
+    float4 *sh_c;       // pending contribution rgb, -
+    uint32_t *counters; // [0..63] ext counts per depth, [64..127] shadow counts
+    unsigned long long *stats;  // ext rays, shadow rays, paths, passes
+    double *fb_sum;     // W*H*3
+    uint32_t *fb_count; // W*H
+};
+
+// kernel launchers (qpt_kernels.hip)
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s);
+hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
+                               uint64_t pass0, uint32_t npass, hipStream_t s);
+hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
+                                    uint32_t n, int scramble, uint32_t *out, hipStream_t s);
+hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);
+hipError_t launch_debug_trace(const Frame &f, const float *rays, uint32_t n, int any_hit,
+                              int brute, float *t, uint32_t *tri, float *b12, hipStream_t s);
+
+}  // namespace qpt

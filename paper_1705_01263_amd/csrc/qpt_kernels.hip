@@ -1,0 +1,860 @@
+// HIP kernels of libqpt for gfx950 (CDNA4, wave64).
+//
+// One pass = one sample per pixel over the frame (Sec. 3.2.2). A batch of
+// passes (or of pixels) is rendered as a wavefront (Sec. 3.1): a generation
+// kernel fills the path pool, then for every depth v a closest-hit kernel, a
+// shading kernel (emission + MIS, next-event estimation, BSDF sampling,
+// roulette) and an occlusion kernel run over compact queues of path slots;
+// queues are rebuilt just in time by wave-level appends (Sec. 3.1.2); state
+// stays in place as structures of arrays (Sec. 3.1.1). A final kernel adds
+// the batch into the FP64 framebuffer in pass order and bumps the per-pixel
+// sample counts (Appendix A.4).
+#include <hip/hip_runtime.h>
+
+#include "qpt_internal.h"
+
+namespace qpt {
+
+namespace {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+
+// ---------------------------------------------------------------- vectors
+
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 xyz(float4 v) { return {v.x, v.y, v.z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ f3 operator*(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float length(f3 a) { return sqrtf(dot(a, a)); }
+__device__ __forceinline__ f3 normalize(f3 a) { return a * (1.0f / length(a)); }
+__device__ __forceinline__ float maxc(f3 a) { return fmaxf(a.x, fmaxf(a.y, a.z)); }
+__device__ __forceinline__ float lum(f3 c) { return 0.2126f * c.x + 0.7152f * c.y + 0.0722f * c.z; }
+__device__ __forceinline__ float4 f4(f3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
+__device__ __forceinline__ float ubits(uint32_t u) { return __uint_as_float(u); }
+__device__ __forceinline__ uint32_t fbits(float f) { return __float_as_uint(f); }
+
+// ------------------------------------------------------- wave primitives
+
+// Append to a queue from a whole wave with one atomic: ballot the lanes
+// that append, the first of them reserves popcount slots, every lane finds
+// its offset with mbcnt. All 64 lanes must call it.
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred)
+{
+    unsigned long long mask = __ballot(pred);
+    uint32_t base = 0;
+    if (mask) {
+        uint32_t lane = __lane_id();
+        uint32_t leader = __ffsll((long long)mask) - 1;
+        if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+        base = __shfl(base, (int)leader);
+    }
+    uint32_t lo = (uint32_t)mask, hi = (uint32_t)(mask >> 32);
+    return base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+}
+
+// ----------------------------------------------------------------- Halton
+
+__device__ __forceinline__ uint32_t div_b(uint32_t n, uint32_t m, uint32_t sh)
+{
+    uint32_t t = __umulhi(m, n);
+    return (t + ((n - t) >> 1)) >> sh;
+}
+
+__device__ __forceinline__ uint64_t div_B(uint64_t n, uint64_t m, uint32_t sh)
+{
+    uint64_t t = __umul64hi(m, n);
+    return (t + ((n - t) >> 1)) >> sh;
+}
+
+// digits of an e-digit chunk c, scrambled and reversed: sum pi(d_m) b^(e-1-m)
+__device__ __forceinline__ uint32_t chunk_reverse(uint32_t c, const HaltonBase &h, uint32_t f)
+{
+    uint32_t r = 0;
+    for (uint32_t k = 0; k < h.e; ++k) {
+        uint32_t q = div_b(c, h.m32, h.sh32);
+        uint32_t d = c - q * h.b;
+        c = q;
+        uint32_t p = f * d;
+        r = r * h.b + (p - div_b(p, h.m32, h.sh32) * h.b);
+    }
+    return r;
+}
+
+// one Horner step over a chunk in base B = b^e: floor((R 2^32 + Y) / B)
+__device__ __forceinline__ uint32_t horner(uint32_t R, uint32_t Y, const HaltonBase &h)
+{
+    return (uint32_t)div_B(((uint64_t)R << 32) | Y, h.m64, h.shB);
+}
+
+// floor(2^32 * RI^pi_b(i)), exact: i is split into base-B chunks (B < 2^32,
+// at most three for 64-bit indices); each chunk's digits are reversed with
+// 32-bit strength-reduced divisions, the chunks are combined by Horner's
+// rule from the most significant one, each step an exact 64-bit division.
+__device__ uint32_t radical_inverse_bits(uint64_t i, const HaltonBase &h, uint32_t f)
+{
+    uint64_t q1 = div_B(i, h.m64, h.shB);
+    uint32_t c0 = (uint32_t)(i - q1 * h.B);
+    uint32_t Y = 0;
+    if (q1) {
+        uint64_t q2 = div_B(q1, h.m64, h.shB);
+        uint32_t c1 = (uint32_t)(q1 - q2 * h.B);
+        if (q2) Y = horner(chunk_reverse((uint32_t)q2, h, f), 0u, h);
+        Y = horner(chunk_reverse(c1, h, f), Y, h);
+    }
+    return horner(chunk_reverse(c0, h, f), Y, h);
+}
+
+// 32-bit sample of dimension d for Halton index i; dims 0/1 are the film
+// offsets (digits left after the pixel's own base-2 / base-3 digits)
+__device__ __forceinline__ uint32_t sample_bits(const Frame &F, uint64_t i, uint32_t d, uint32_t scramble)
+{
+    if (d == 0) return __brev((uint32_t)(i >> F.k2));
+    if (d == 1) {
+        uint64_t q = F.p3 > 1 ? div_B(i, F.m_p3, F.sh_p3) : i;
+        return radical_inverse_bits(q, F.bases[1], 1u);
+    }
+    const HaltonBase &h = F.bases[d];
+    return radical_inverse_bits(i, h, scramble ? h.f : 1u);
+}
+
+__device__ __forceinline__ float u24(uint32_t bits) { return (float)(bits >> 8) * 0x1p-24f; }
+
+// full-screen enumeration: the index in [0, 2^k 3^l) whose first k binary and
+// l ternary digits reversed are (x, y), plus pass * 2^k 3^l
+__device__ uint64_t pixel_index(const Frame &F, uint32_t px, uint32_t py, uint64_t pass)
+{
+    uint32_t a = F.k2 ? (__brev(px) >> (32 - F.k2)) : 0u;
+    uint32_t c = 0, y = py;
+    for (uint32_t m = 0; m < F.l3; ++m) {
+        c = c * 3u + y % 3u;
+        y /= 3u;
+    }
+    uint32_t p3 = (uint32_t)F.p3;
+    uint32_t diff = (c + p3 - a % p3) % p3;
+    uint32_t t = (uint32_t)(((uint64_t)diff * F.inv2k_mod_p3) % p3);
+    uint64_t i0 = (uint64_t)a + ((uint64_t)t << F.k2);
+    return i0 + pass * F.S;
+}
+
+// ---------------------------------------------------------- intersection
+
+struct RayPre {
+    f3 o;
+    float Sx, Sy, Sz;
+    int kx, ky, kz;
+    f3 inv;  // reciprocal direction for slab tests
+};
+
+__device__ __forceinline__ float comp(f3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+
+__device__ __forceinline__ RayPre prepare(f3 o, f3 d)
+{
+    RayPre r;
+    r.o = o;
+    int kz = 0;
+    if (fabsf(d.y) > fabsf(comp(d, kz))) kz = 1;
+    if (fabsf(d.z) > fabsf(comp(d, kz))) kz = 2;
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    float dz = comp(d, kz);
+    if (dz < 0.0f) {
+        int s = kx;
+        kx = ky;
+        ky = s;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.Sx = comp(d, kx) / dz;
+    r.Sy = comp(d, ky) / dz;
+    r.Sz = 1.0f / dz;
+    auto safe = [](float x) { return fabsf(x) < 1e-20f ? copysignf(1e-20f, x) : x; };
+    r.inv = mk(1.0f / safe(d.x), 1.0f / safe(d.y), 1.0f / safe(d.z));
+    return r;
+}
+
+// Watertight ray/triangle test (Woop, Benthin, Wald 2013) in FP32. The edge
+// functions use separately rounded products so a shared edge evaluates to
+// exactly opposite values in its two triangles; an exact zero is re-evaluated
+// in FP64. Hit iff 0 < t < tmax.
+__device__ __forceinline__ bool tri_test(const RayPre &r, float4 v0, float4 v1, float4 v2, float tmax,
+                                         float &t_out, float &b1, float &b2)
+{
+#pragma clang fp contract(off)
+    f3 A = xyz(v0) - r.o, B = xyz(v1) - r.o, C = xyz(v2) - r.o;
+    float Akz = comp(A, r.kz), Bkz = comp(B, r.kz), Ckz = comp(C, r.kz);
+    float Ax = fmaf(-r.Sx, Akz, comp(A, r.kx)), Ay = fmaf(-r.Sy, Akz, comp(A, r.ky));
+    float Bx = fmaf(-r.Sx, Bkz, comp(B, r.kx)), By = fmaf(-r.Sy, Bkz, comp(B, r.ky));
+    float Cx = fmaf(-r.Sx, Ckz, comp(C, r.kx)), Cy = fmaf(-r.Sy, Ckz, comp(C, r.ky));
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = (U + V) + W;
+    if (det == 0.0f) return false;
+    float Az = r.Sz * Akz, Bz = r.Sz * Bkz, Cz = r.Sz * Ckz;
+    float T = fmaf(U, Az, fmaf(V, Bz, W * Cz));
+    float t = T / det;
+    if (!(t > 0.0f && t < tmax)) return false;
+    t_out = t;
+    b1 = V / det;
+    b2 = W / det;
+    return true;
+}
+
+// slab test of both children of a node against [0, tlim]
+__device__ __forceinline__ void node_test(const Node &n, const RayPre &r, float tlim, bool &h0, bool &h1,
+                                          float &tn0, float &tn1)
+{
+    f3 oi = r.o * r.inv;
+    float lx0 = fmaf(n.a.x, r.inv.x, -oi.x), hx0 = fmaf(n.a.w, r.inv.x, -oi.x);
+    float ly0 = fmaf(n.a.y, r.inv.y, -oi.y), hy0 = fmaf(n.b.x, r.inv.y, -oi.y);
+    float lz0 = fmaf(n.a.z, r.inv.z, -oi.z), hz0 = fmaf(n.b.y, r.inv.z, -oi.z);
+    float lx1 = fmaf(n.b.z, r.inv.x, -oi.x), hx1 = fmaf(n.c.y, r.inv.x, -oi.x);
+    float ly1 = fmaf(n.b.w, r.inv.y, -oi.y), hy1 = fmaf(n.c.z, r.inv.y, -oi.y);
+    float lz1 = fmaf(n.c.x, r.inv.z, -oi.z), hz1 = fmaf(n.c.w, r.inv.z, -oi.z);
+    tn0 = fmaxf(fmaxf(fminf(lx0, hx0), fminf(ly0, hy0)), fmaxf(fminf(lz0, hz0), 0.0f));
+    float tf0 = fminf(fminf(fmaxf(lx0, hx0), fmaxf(ly0, hy0)), fminf(fmaxf(lz0, hz0), tlim));
+    tn1 = fmaxf(fmaxf(fminf(lx1, hx1), fminf(ly1, hy1)), fmaxf(fminf(lz1, hz1), 0.0f));
+    float tf1 = fminf(fminf(fmaxf(lx1, hx1), fmaxf(ly1, hy1)), fminf(fmaxf(lz1, hz1), tlim));
+    // the padded boxes make a relative slack of a few ulps harmless
+    h0 = tn0 <= tf0 * 1.0000005f;
+    h1 = tn1 <= tf1 * 1.0000005f;
+}
+
+struct HitRec {
+    float t, b1, b2;
+    uint32_t tri;   // BVH-order index
+    uint32_t id;    // input id (tie-break)
+};
+
+// Closest hit (ANY = false) or occlusion (ANY = true) through the BVH, with
+// a per-thread stack in LDS laid out [entry][thread] (bank-conflict free).
+template <bool ANY>
+__device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk)
+{
+    h.t = tmax;
+    h.tri = kNoHit;
+    h.id = kNoHit;
+    int sp = 0;
+    int ref = 0;
+    const int step = (int)blockDim.x;
+    while (true) {
+        if (ref >= 0) {
+            const Node n = F.nodes[ref];
+            bool h0, h1;
+            float t0, t1;
+            node_test(n, r, h.t, h0, h1, t0, t1);
+            if (h0 && h1) {
+                bool swap = t1 < t0;
+                int nearr = swap ? n.d.y : n.d.x, farr = swap ? n.d.x : n.d.y;
+                stk[sp * step] = farr;
+                ++sp;
+                ref = nearr;
+                continue;
+            }
+            if (h0 || h1) {
+                ref = h0 ? n.d.x : n.d.y;
+                continue;
+            }
+        } else {
+            uint32_t payload = ~(uint32_t)ref;
+            uint32_t first = payload >> 3, cnt = (payload & 7u) + 1u;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const Tri tr = F.tris[first + k];
+                float t, b1, b2;
+                if (!tri_test(r, tr.v0, tr.v1, tr.v2, tmax, t, b1, b2)) continue;
+                if (ANY) {
+                    h.tri = first + k;
+                    return true;
+                }
+                uint32_t id = fbits(tr.v1.w);
+                if (t < h.t || (t == h.t && id < h.id)) {
+                    h.t = t;
+                    h.b1 = b1;
+                    h.b2 = b2;
+                    h.tri = first + k;
+                    h.id = id;
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        ref = stk[sp * step];
+    }
+    return h.tri != kNoHit;
+}
+
+template <bool ANY>
+__device__ bool brute_force(const Frame &F, const RayPre &r, float tmax, HitRec &h)
+{
+    h.t = tmax;
+    h.tri = kNoHit;
+    h.id = kNoHit;
+    for (uint32_t k = 0; k < F.num_tris; ++k) {
+        const Tri tr = F.tris[k];
+        float t, b1, b2;
+        if (!tri_test(r, tr.v0, tr.v1, tr.v2, tmax, t, b1, b2)) continue;
+        if (ANY) {
+            h.tri = k;
+            return true;
+        }
+        uint32_t id = fbits(tr.v1.w);
+        if (t < h.t || (t == h.t && id < h.id)) {
+            h.t = t;
+            h.b1 = b1;
+            h.b2 = b2;
+            h.tri = k;
+            h.id = id;
+        }
+    }
+    return h.tri != kNoHit;
+}
+
+// -------------------------------------------------------------- shading
+
+__device__ __forceinline__ f3 emission_at(const Material &m, f3 x)
+{
+    f3 E = xyz(m.emission_flags);
+    if (fbits(m.emission_flags.w) & 2u) E = E * (0.55f + 0.45f * sinf(2.0f * kPi * 4.0f * (x.x + x.z)));
+    return E;
+}
+
+__device__ __forceinline__ float fresnel(float c)
+{
+    float m = fmaxf(0.0f, 1.0f - c);
+    float m2 = m * m;
+    return 0.04f + 0.96f * m2 * m2 * m;
+}
+
+__device__ __forceinline__ float ggx_D(float ch, float a2)
+{
+    float k = ch * ch * (a2 - 1.0f) + 1.0f;
+    return a2 / (kPi * k * k);
+}
+
+__device__ __forceinline__ float ggx_lambda(float c, float a2)
+{
+    float c2 = c * c;
+    return 0.5f * (-1.0f + sqrtf(1.0f + a2 * (1.0f - c2) / c2));
+}
+
+// probability of the specular lobe as realised by u < p on the 2^-24 grid
+__device__ __forceinline__ float spec_prob(const Material &m, float co)
+{
+    float F = fresnel(co);
+    float p = F / (F + (1.0f - F) * lum(xyz(m.albedo_rough)));
+    p = fminf(0.9f, fmaxf(0.1f, p));
+    return ceilf(p * 16777216.0f) * 0x1p-24f;
+}
+
+// f (no cosine) and sampling pdf for reflection on the side of n (n . wo > 0)
+__device__ void bsdf_eval(const Material &m, f3 n, f3 wo, f3 wi, f3 &f, float &pdf)
+{
+    float co = dot(n, wo), ci = dot(n, wi);
+    f = mk(0.f, 0.f, 0.f);
+    pdf = 0.0f;
+    if (co <= 0.0f || ci <= 0.0f) return;
+    f3 rho = xyz(m.albedo_rough);
+    if (!(fbits(m.emission_flags.w) & 1u)) {
+        f = rho * kInvPi;
+        pdf = ci * kInvPi;
+        return;
+    }
+    float a = m.albedo_rough.w, a2 = a * a;
+    f3 h = normalize(wo + wi);
+    float D = ggx_D(dot(n, h), a2);
+    float lo = ggx_lambda(co, a2), li = ggx_lambda(ci, a2);
+    float spec = D * fresnel(dot(wo, h)) / ((1.0f + lo + li) * 4.0f * co * ci);
+    float kd = (1.0f - fresnel(co)) * (1.0f - fresnel(ci)) * kInvPi;
+    f = mk(spec, spec, spec) + rho * kd;
+    float ps = spec_prob(m, co);
+    pdf = ps * D / ((1.0f + lo) * 4.0f * co) + (1.0f - ps) * ci * kInvPi;
+}
+
+// orthonormal basis around unit n (Duff et al. 2017)
+__device__ __forceinline__ void onb(f3 n, f3 &b1, f3 &b2)
+{
+    float s = copysignf(1.0f, n.z);
+    float a = -1.0f / (s + n.z);
+    float b = n.x * n.y * a;
+    b1 = mk(1.0f + s * n.x * n.x * a, s * b, -s * n.x);
+    b2 = mk(b, s + n.y * n.y * a, -n.y);
+}
+
+// sample wi: lobe by u3, direction by (u4, u5); false below the surface
+__device__ bool bsdf_sample(const Material &m, f3 n, f3 wo, float u3, float u4, float u5, f3 &wi)
+{
+    f3 b1, b2;
+    onb(n, b1, b2);
+    float co = dot(n, wo);
+    bool spec = (fbits(m.emission_flags.w) & 1u) && u3 < spec_prob(m, co);
+    float r = sqrtf(u4);
+    float s, c;
+    sincosf(2.0f * kPi * u5, &s, &c);
+    if (!spec) {
+        float z = sqrtf(fmaxf(0.0f, 1.0f - u4));
+        wi = b1 * (r * c) + b2 * (r * s) + n * z;
+        return true;
+    }
+    // visible-normal sampling of GGX (Heitz 2018) in the local frame
+    float a = m.albedo_rough.w;
+    f3 vh = normalize(mk(a * dot(wo, b1), a * dot(wo, b2), co));
+    float l2 = vh.x * vh.x + vh.y * vh.y;
+    f3 T1 = l2 > 0.0f ? mk(-vh.y, vh.x, 0.0f) * (1.0f / sqrtf(l2)) : mk(1.0f, 0.0f, 0.0f);
+    f3 T2 = cross(vh, T1);
+    float t1 = r * c, t2 = r * s;
+    float sh = 0.5f * (1.0f + vh.z);
+    t2 = (1.0f - sh) * sqrtf(fmaxf(0.0f, 1.0f - t1 * t1)) + sh * t2;
+    f3 nh = T1 * t1 + T2 * t2 + vh * sqrtf(fmaxf(0.0f, 1.0f - t1 * t1 - t2 * t2));
+    f3 ne = normalize(mk(a * nh.x, a * nh.y, fmaxf(0.0f, nh.z)));
+    f3 hw = b1 * ne.x + b2 * ne.y + n * ne.z;
+    wi = hw * (2.0f * dot(wo, hw)) - wo;
+    return dot(n, wi) > 0.0f;
+}
+
+// origin offset (Waechter and Binder 2019): trunc(256 n) ulps per coordinate,
+// n / 65536 within 1/32 of the origin
+__device__ __forceinline__ float offset1(float p, float n)
+{
+    int k = (int)(256.0f * n);
+    float pi = __int_as_float(__float_as_int(p) + (p < 0.0f ? -k : k));
+    return fabsf(p) < 1.0f / 32.0f ? p + n * (1.0f / 65536.0f) : pi;
+}
+__device__ __forceinline__ f3 offset_ray(f3 p, f3 n) { return mk(offset1(p.x, n.x), offset1(p.y, n.y), offset1(p.z, n.z)); }
+
+__device__ __forceinline__ float mis2(float a, float b)
+{
+    // a^2 / (a^2 + b^2), safe for infinities and zeros
+    if (!(a > 0.0f)) return 0.0f;
+    float q = b / a;
+    return 1.0f / (1.0f + q * q);
+}
+
+__device__ float4 env_lookup(const Frame &F, f3 w)
+{
+    float th = acosf(fminf(1.0f, fmaxf(-1.0f, w.y)));
+    float ph = atan2f(w.x, -w.z);
+    if (ph < 0.0f) ph += 2.0f * kPi;
+    int r = (int)floorf(th / kPi * (float)F.env_h);
+    int c = (int)floorf(ph / (2.0f * kPi) * (float)F.env_w);
+    r = min(max(r, 0), (int)F.env_h - 1);
+    c = min(max(c, 0), (int)F.env_w - 1);
+    return F.env_texel[(size_t)r * F.env_w + c];
+}
+
+// largest k in [0, n) with q[k] <= s (q[0] == 0, non-decreasing)
+__device__ __forceinline__ uint32_t upper_search(const uint32_t *q, uint32_t n, uint32_t s)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (q[mid] <= s) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// camera rays for slots [0, n): slot s -> pixel pix0 + s % npix, pass pass0 + s / npix
+__global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint64_t pass0,
+                                                     uint32_t n)
+{
+    uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s == 0) P.counters[1] = n;
+    if (s >= n) return;
+    uint32_t pl = s % npix, j = s / npix;
+    uint32_t p = pix0 + pl;
+    uint32_t px = p % F.W, py = p / F.W;
+    uint64_t i = pixel_index(F, px, py, pass0 + j);
+    float fx = (float)px + u24(sample_bits(F, i, 0, 0));
+    float fy = (float)py + u24(sample_bits(F, i, 1, 0));
+    float sx = (2.0f * fx / (float)F.W - 1.0f) * F.cam.tan_half * F.cam.aspect;
+    float sy = (1.0f - 2.0f * fy / (float)F.H) * F.cam.tan_half;
+    f3 fwd = mk(F.cam.fwd[0], F.cam.fwd[1], F.cam.fwd[2]);
+    f3 rt = mk(F.cam.right[0], F.cam.right[1], F.cam.right[2]);
+    f3 up = mk(F.cam.up[0], F.cam.up[1], F.cam.up[2]);
+    f3 d = normalize(fwd + (rt * sx + up * sy));
+    P.ray_o[s] = make_float4(F.cam.eye[0], F.cam.eye[1], F.cam.eye[2], INFINITY);
+    P.ray_d[s] = f4(d, 0.0f);
+    P.thr[s] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    P.rad[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    P.idx[s] = i;
+    P.q_ext[1][s] = s;
+}
+
+// closest hit for the extension rays queued at depth v
+__global__ __launch_bounds__(kBlock) void k_trace(Frame F, Pool P, uint32_t v)
+{
+    __shared__ int stk[kStackSize * kBlock];
+    const uint32_t n = P.counters[v];
+    const uint32_t *q = P.q_ext[v & 1];
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        uint32_t i = base + threadIdx.x;
+        if (i >= n) break;
+        uint32_t slot = q[i];
+        float4 o = P.ray_o[slot], d = P.ray_d[slot];
+        RayPre r = prepare(xyz(o), xyz(d));
+        HitRec h;
+        traverse<false>(F, r, o.w, h, stk + threadIdx.x);
+        P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
+    }
+}
+
+// emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
+__global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
+{
+    const uint32_t n = P.counters[v];
+    const uint32_t *q = P.q_ext[v & 1];
+    uint32_t *qn = P.q_ext[(v + 1) & 1];
+    const uint32_t base_dim = 2 + 8 * (v - 1);
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        uint32_t i = base + threadIdx.x;
+        bool active = i < n;
+        bool alive = false, shadow = false;
+        uint32_t slot = 0;
+        float4 sh_o = {}, sh_d = {}, sh_c = {};
+        if (active) {
+            slot = q[i];
+            float4 hv = P.hit[slot];
+            f3 d = xyz(P.ray_d[slot]);
+            float4 T4 = P.thr[slot];
+            f3 T = xyz(T4);
+            float prev_pdf = T4.w;
+            f3 L = xyz(P.rad[slot]);
+            uint32_t tri = fbits(hv.y);
+            if (tri == kNoHit) {
+                if (F.env_w && (v == 1 || F.mode != 2)) {
+                    float4 e = env_lookup(F, d);
+                    float w = (v > 1 && F.mode == 0) ? mis2(prev_pdf, F.p_env * e.w) : 1.0f;
+                    L = L + T * xyz(e) * w;
+                }
+            } else {
+                const Tri tr = F.tris[tri];
+                const Material m = F.mats[fbits(tr.v0.w)];
+                f3 a = xyz(tr.v0), b = xyz(tr.v1), c = xyz(tr.v2);
+                f3 x = a + ((b - a) * hv.z + (c - a) * hv.w);
+                f3 ng = cross(b - a, c - a);
+                float area2 = length(ng);
+                ng = ng * (1.0f / area2);
+                float dn = dot(d, ng);
+                bool front = dn < 0.0f;
+                uint32_t em = fbits(tr.v2.w);
+                if (front && em != kNoHit && !(v > 1 && F.mode == 2)) {
+                    f3 Le = emission_at(m, x);
+                    float w = 1.0f;
+                    if (v > 1 && F.mode == 0) {
+                        float pl = F.emit_pmf[em] / (0.5f * area2) * hv.x * hv.x / (-dn);
+                        w = mis2(prev_pdf, pl);
+                    }
+                    L = L + T * Le * w;
+                }
+                bool scatters = maxc(xyz(m.albedo_rough)) > 0.0f || (fbits(m.emission_flags.w) & 1u);
+                if (v < F.max_depth && scatters) {
+                    f3 nn = front ? ng : ng * -1.0f;
+                    f3 wo = d * -1.0f;
+                    f3 xo = offset_ray(x, nn);
+                    uint64_t idx = P.idx[slot];
+                    // next-event estimation
+                    if (F.mode != 1 && (F.num_emit || F.env_w)) {
+                        uint32_t s0 = sample_bits(F, idx, base_dim + 0, F.scramble);
+                        bool use_env = F.env_w != 0;
+                        uint64_t rr = s0, R = 1ull << 32;
+                        if (F.env_w && F.num_emit) {
+                            use_env = s0 < 0x80000000u;
+                            rr = s0 - 0x80000000u;
+                            R = 1ull << 31;
+                        }
+                        f3 wi, Le;
+                        float pl = 0.0f, tmax = INFINITY;
+                        bool ok = false;
+                        if (use_env) {
+                            uint32_t s1 = sample_bits(F, idx, base_dim + 1, F.scramble);
+                            uint32_t s2 = sample_bits(F, idx, base_dim + 2, F.scramble);
+                            uint32_t row = upper_search(F.env_row, F.env_h, s1);
+                            const uint32_t *cq = F.env_col + (size_t)row * F.env_w;
+                            uint32_t col = upper_search(cq, F.env_w, s2);
+                            uint64_t r0 = F.env_row[row], r1 = row + 1 < F.env_h ? F.env_row[row + 1] : (1ull << 32);
+                            uint64_t c0 = cq[col], c1 = col + 1 < F.env_w ? cq[col + 1] : (1ull << 32);
+                            float fy = (float)(s1 - r0) / (float)(r1 - r0);
+                            float fx = (float)(s2 - c0) / (float)(c1 - c0);
+                            float ct = F.env_cos[row], cb = F.env_cos[row + 1];
+                            float cth = ct + fy * (cb - ct);
+                            float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
+                            float sp, cp;
+                            sincosf(2.0f * kPi * ((float)col + fx) / (float)F.env_w, &sp, &cp);
+                            wi = mk(sth * sp, cth, -sth * cp);
+                            float4 e = F.env_texel[(size_t)row * F.env_w + col];
+                            Le = xyz(e);
+                            pl = F.p_env * e.w;
+                            ok = pl > 0.0f;
+                        } else {
+                            // rr < R <= 2^32 and num_emit < 2^27: the product fits 64 bits
+                            uint32_t col = (uint32_t)((rr * (uint64_t)F.num_emit) >> (R == (1ull << 31) ? 31 : 32));
+                            uint32_t s7 = sample_bits(F, idx, base_dim + 7, F.scramble);
+                            uint32_t e = (unsigned long long)s7 < F.alias_thr[col] ? col : F.alias_idx[col];
+                            const Tri lt = F.tris[F.emit_tri[e]];
+                            float q1 = u24(sample_bits(F, idx, base_dim + 1, F.scramble));
+                            float q2 = u24(sample_bits(F, idx, base_dim + 2, F.scramble));
+                            float su = sqrtf(q1);
+                            float b0 = 1.0f - su, bb1 = q2 * su, bb2 = su * (1.0f - q2);
+                            f3 la = xyz(lt.v0), lb = xyz(lt.v1), lc = xyz(lt.v2);
+                            f3 y = la * b0 + lb * bb1 + lc * bb2;
+                            f3 nl = cross(lb - la, lc - la);
+                            float la2 = length(nl);
+                            nl = nl * (1.0f / la2);
+                            f3 dv = y - xo;
+                            float d2 = dot(dv, dv);
+                            float dist = sqrtf(d2);
+                            wi = dv * (1.0f / dist);
+                            float cl = -dot(nl, wi);
+                            if (cl > 0.0f) {
+                                Le = emission_at(F.mats[fbits(lt.v0.w)], y);
+                                pl = F.emit_pmf[e] / (0.5f * la2) * d2 / cl;
+                                ok = pl > 0.0f;
+                                tmax = dist * (1.0f - 1e-4f);
+                            }
+                        }
+                        if (ok) {
+                            float ci = dot(nn, wi);
+                            if (ci > 0.0f) {
+                                f3 fb;
+                                float pb;
+                                bsdf_eval(m, nn, wo, wi, fb, pb);
+                                float w = F.mode == 2 ? 1.0f : mis2(pl, pb);
+                                f3 contrib = T * fb * Le * (ci * w / pl);
+                                if (maxc(contrib) > 0.0f) {
+                                    shadow = true;
+                                    sh_o = f4(xo, tmax);
+                                    sh_d = f4(wi, ubits(slot));
+                                    sh_c = f4(contrib, 0.0f);
+                                }
+                            }
+                        }
+                    }
+                    // continue by sampling the BSDF
+                    float u3 = u24(sample_bits(F, idx, base_dim + 3, F.scramble));
+                    float u4 = u24(sample_bits(F, idx, base_dim + 4, F.scramble));
+                    float u5 = u24(sample_bits(F, idx, base_dim + 5, F.scramble));
+                    f3 wi;
+                    if (bsdf_sample(m, nn, wo, u3, u4, u5, wi)) {
+                        f3 fb;
+                        float pb;
+                        bsdf_eval(m, nn, wo, wi, fb, pb);
+                        if (pb > 0.0f) {
+                            T = T * fb * (dot(nn, wi) / pb);
+                            if (maxc(T) > 0.0f) {
+                                alive = true;
+                                if (F.rr && v >= 3) {
+                                    float qq = fminf(0.95f, maxc(T));
+                                    qq = ceilf(qq * 16777216.0f) * 0x1p-24f;
+                                    float u6 = u24(sample_bits(F, idx, base_dim + 6, F.scramble));
+                                    if (u6 < qq) T = T * (1.0f / qq);
+                                    else alive = false;
+                                }
+                                if (alive) {
+                                    P.ray_o[slot] = f4(xo, INFINITY);
+                                    P.ray_d[slot] = f4(wi, 0.0f);
+                                    P.thr[slot] = f4(T, pb);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            P.rad[slot] = f4(L, 0.0f);
+        }
+        uint32_t ps = wave_append(&P.counters[64 + v], shadow);
+        if (shadow) {
+            P.q_sh[ps] = slot;
+            P.sh_o[ps] = sh_o;
+            P.sh_d[ps] = sh_d;
+            P.sh_c[ps] = sh_c;
+        }
+        uint32_t pe = wave_append(&P.counters[v + 1], alive);
+        if (alive) qn[pe] = slot;
+    }
+}
+
+// occlusion test of the shadow rays queued at depth v; add unoccluded contributions
+__global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
+{
+    __shared__ int stk[kStackSize * kBlock];
+    const uint32_t n = P.counters[64 + v];
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        uint32_t i = base + threadIdx.x;
+        if (i >= n) break;
+        float4 o = P.sh_o[i], d = P.sh_d[i];
+        RayPre r = prepare(xyz(o), xyz(d));
+        HitRec h;
+        if (!traverse<true>(F, r, o.w, h, stk + threadIdx.x)) {
+            uint32_t slot = fbits(d.w);
+            float4 c = P.sh_c[i];
+            float4 L = P.rad[slot];
+            P.rad[slot] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
+        }
+    }
+}
+
+// FP64 accumulation in pass order and sample counts
+__global__ __launch_bounds__(kBlock) void k_accumulate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint32_t npass)
+{
+    uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q == 0) {
+        unsigned long long ext = 0, sh = 0;
+        for (uint32_t v = 1; v <= F.max_depth; ++v) {
+            ext += P.counters[v];
+            sh += P.counters[64 + v];
+        }
+        P.stats[0] += ext;
+        P.stats[1] += sh;
+        P.stats[2] += (unsigned long long)npix * npass;
+    }
+    if (q >= npix) return;
+    uint32_t p = pix0 + q;
+    double sx = P.fb_sum[3 * (size_t)p], sy = P.fb_sum[3 * (size_t)p + 1], sz = P.fb_sum[3 * (size_t)p + 2];
+    for (uint32_t j = 0; j < npass; ++j) {
+        float4 L = P.rad[(size_t)j * npix + q];
+        sx += (double)L.x;
+        sy += (double)L.y;
+        sz += (double)L.z;
+    }
+    P.fb_sum[3 * (size_t)p] = sx;
+    P.fb_sum[3 * (size_t)p + 1] = sy;
+    P.fb_sum[3 * (size_t)p + 2] = sz;
+    P.fb_count[p] += npass;
+}
+
+__global__ void k_debug_sample_bits(Frame F, const uint64_t *idx, const uint32_t *dim, uint32_t n, int scramble,
+                                    uint32_t *out)
+{
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    uint32_t d = dim[q];
+    out[q] = d < kMaxDims ? sample_bits(F, idx[q], d, (uint32_t)scramble) : 0u;
+}
+
+__global__ void k_debug_pixel_index(Frame F, uint64_t pass, uint64_t *out)
+{
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= F.W * F.H) return;
+    out[q] = pixel_index(F, q % F.W, q / F.W, pass);
+}
+
+template <bool ANY, bool BRUTE>
+__global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, const float *rays, uint32_t n, float *t,
+                                                        uint32_t *tri, float *b12)
+{
+    __shared__ int stk[kStackSize * kBlock];
+    uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const float *ry = rays + 8 * (size_t)q;
+    RayPre r = prepare(mk(ry[0], ry[1], ry[2]), mk(ry[4], ry[5], ry[6]));
+    HitRec h;
+    bool hit = BRUTE ? brute_force<ANY>(F, r, ry[3], h) : traverse<ANY>(F, r, ry[3], h, stk + threadIdx.x);
+    if (ANY) {
+        tri[q] = hit ? 1u : 0u;
+        return;
+    }
+    tri[q] = hit ? h.id : kNoHit;
+    t[q] = hit ? h.t : INFINITY;
+    b12[2 * (size_t)q] = hit ? h.b1 : 0.0f;
+    b12[2 * (size_t)q + 1] = hit ? h.b2 : 0.0f;
+}
+
+inline uint32_t blocks_for(size_t n, uint32_t cap)
+{
+    size_t b = (n + kBlock - 1) / kBlock;
+    return (uint32_t)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 4096)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 4096)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
+                               uint32_t npass, hipStream_t s)
+{
+    uint32_t n = npix * npass;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(128), 0, s, P.counters, (size_t)128, 0u);
+    hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
+    uint32_t g = blocks_for(n, 8192);
+    for (uint32_t v = 1; v <= F.max_depth; ++v) {
+        hipLaunchKernelGGL(k_trace, dim3(g), dim3(kBlock), 0, s, F, P, v);
+        hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v);
+        hipLaunchKernelGGL(k_shadow, dim3(g), dim3(kBlock), 0, s, F, P, v);
+    }
+    hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix,
+                       npass);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_sample_bits(const Frame &F, const uint64_t *idx, const uint32_t *dim, uint32_t n,
+                                    int scramble, uint32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_sample_bits, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, idx, dim, n,
+                       scramble, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_pixel_index(const Frame &F, uint64_t pass, uint64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_pixel_index, dim3(blocks_for((size_t)F.W * F.H, 1u << 30)), dim3(kBlock), 0, s, F,
+                       pass, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_trace(const Frame &F, const float *rays, uint32_t n, int any_hit, int brute, float *t,
+                              uint32_t *tri, float *b12, hipStream_t s)
+{
+    dim3 g(blocks_for(n, 1u << 30)), b(kBlock);
+    if (any_hit) {
+        if (brute) hipLaunchKernelGGL((k_debug_trace<true, true>), g, b, 0, s, F, rays, n, t, tri, b12);
+        else hipLaunchKernelGGL((k_debug_trace<true, false>), g, b, 0, s, F, rays, n, t, tri, b12);
+    } else {
+        if (brute) hipLaunchKernelGGL((k_debug_trace<false, true>), g, b, 0, s, F, rays, n, t, tri, b12);
+        else hipLaunchKernelGGL((k_debug_trace<false, false>), g, b, 0, s, F, rays, n, t, tri, b12);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qpt

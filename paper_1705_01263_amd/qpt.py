@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libqpt (include/qpt.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; PyTorch provides
+the device memory (the workspace) and the stream. If the compiled library is
+missing this module raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpt.so")
+
+QPT_OK = 0
+QPT_E_INVALID, QPT_E_STATE, QPT_E_NOMEM, QPT_E_HIP, QPT_E_UNSUPPORTED, QPT_E_ABORTED = -1, -2, -3, -4, -5, -6
+QPT_MAT_GGX = 1
+QPT_MAT_EMIT_TEXTURE = 2
+
+
+class qpt_material(C.Structure):
+    _fields_ = [("albedo", C.c_float * 3), ("roughness", C.c_float), ("emission", C.c_float * 3),
+                ("flags", C.c_uint32)]
+
+
+class qpt_camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("look", C.c_float * 3), ("up", C.c_float * 3), ("vfov_deg", C.c_float)]
+
+
+class qpt_scene_desc(C.Structure):
+    _fields_ = [("num_vertices", C.c_uint32), ("positions", C.c_void_p), ("num_triangles", C.c_uint32),
+                ("indices", C.c_void_p), ("tri_material", C.c_void_p), ("num_materials", C.c_uint32),
+                ("materials", C.c_void_p), ("env_width", C.c_uint32), ("env_height", C.c_uint32),
+                ("env_rgb", C.c_void_p), ("camera", qpt_camera), ("width", C.c_uint32), ("height", C.c_uint32)]
+
+
+class qpt_bvh_opts(C.Structure):
+    _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32)]
+
+
+class qpt_bvh_stats(C.Structure):
+    _fields_ = [("num_nodes", C.c_uint32), ("num_leaves", C.c_uint32), ("max_depth", C.c_uint32),
+                ("reserved", C.c_uint32), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
+
+
+class qpt_render_opts(C.Structure):
+    _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32)]
+
+
+class qpt_stats(C.Structure):
+    _fields_ = [("rays_extension", C.c_uint64), ("rays_shadow", C.c_uint64), ("paths", C.c_uint64),
+                ("passes", C.c_uint64)]
+
+
+EXPORTS = [
+    "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
+    "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
+    "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
+    "qpt_debug_env_tables", "qpt_debug_bvh_nodes",
+]
+
+_lib = None
+
+
+class QptError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libqpt.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+        sig = {
+            "qpt_create": ([i32, P, C.POINTER(P)], i32),
+            "qpt_destroy": ([P], None),
+            "qpt_last_error": ([P], C.c_char_p),
+            "qpt_build_scene": ([P, C.POINTER(qpt_scene_desc)], i32),
+            "qpt_build_bvh": ([P, C.POINTER(qpt_bvh_opts), C.POINTER(qpt_bvh_stats)], i32),
+            "qpt_workspace_size": ([P, u32, C.POINTER(C.c_size_t)], i32),
+            "qpt_bind_workspace": ([P, P, C.c_size_t, u32], i32),
+            "qpt_render_pass": ([P, u64, u32, C.POINTER(qpt_render_opts)], i32),
+            "qpt_readback": ([P, P, P, i32], i32),
+            "qpt_reset_accum": ([P], i32),
+            "qpt_get_stats": ([P, C.POINTER(qpt_stats)], i32),
+            "qpt_debug_sample_bits": ([P, P, P, u32, i32, P], i32),
+            "qpt_debug_pixel_index": ([P, u64, P], i32),
+            "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P], i32),
+            "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
+            "qpt_debug_env_tables": ([P, P, P, P], i32),
+            "qpt_debug_bvh_nodes": ([P, P, P, P], i32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())  # torch tensor
+
+
+class Context:
+    """One qpt_ctx. device < 0 makes a host-only context (scene and BVH builders only)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.L = lib()
+        self.h = C.c_void_p()
+        s = None if stream is None else C.c_void_p(stream)
+        rc = self.L.qpt_create(device, s, C.byref(self.h))
+        if rc != QPT_OK:
+            raise QptError(f"qpt_create failed ({rc})")
+        self._keep = []
+
+    def close(self):
+        if self.h:
+            self.L.qpt_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int, what: str):
+        if rc != QPT_OK:
+            msg = self.L.qpt_last_error(self.h)
+            raise QptError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    # ---- the boundary calls, same names as the C-ABI
+    def build_scene(self, sc) -> None:
+        pos = np.ascontiguousarray(sc.positions, np.float32)
+        idx = np.ascontiguousarray(sc.indices, np.uint32)
+        tm = np.ascontiguousarray(sc.tri_material, np.uint32)
+        nm = sc.albedo.shape[0]
+        mats = (qpt_material * nm)()
+        for m in range(nm):
+            mats[m].albedo[:] = [float(x) for x in sc.albedo[m]]
+            mats[m].roughness = float(sc.roughness[m])
+            mats[m].emission[:] = [float(x) for x in sc.emission[m]]
+            mats[m].flags = int(sc.mat_flags[m])
+        env = None if sc.env is None else np.ascontiguousarray(sc.env, np.float32)
+        d = qpt_scene_desc()
+        d.num_vertices = pos.shape[0]
+        d.positions = pos.ctypes.data
+        d.num_triangles = idx.shape[0]
+        d.indices = idx.ctypes.data
+        d.tri_material = tm.ctypes.data
+        d.num_materials = nm
+        d.materials = C.cast(mats, C.c_void_p)
+        if env is not None:
+            d.env_height, d.env_width = env.shape[0], env.shape[1]
+            d.env_rgb = env.ctypes.data
+        cam = sc.camera
+        d.camera.eye[:] = list(cam.eye)
+        d.camera.look[:] = list(cam.look)
+        d.camera.up[:] = list(cam.up)
+        d.camera.vfov_deg = cam.vfov_deg
+        d.width, d.height = sc.width, sc.height
+        self.check(self.L.qpt_build_scene(self.h, C.byref(d)), "qpt_build_scene")
+        self.W, self.H = sc.width, sc.height
+
+    def build_bvh(self, max_leaf_size: int = 4, sah_bins: int = 16) -> qpt_bvh_stats:
+        o = qpt_bvh_opts(max_leaf_size, sah_bins)
+        st = qpt_bvh_stats()
+        self.check(self.L.qpt_build_bvh(self.h, C.byref(o), C.byref(st)), "qpt_build_bvh")
+        return st
+
+    def workspace_size(self, pool_paths: int = 0) -> int:
+        n = C.c_size_t()
+        self.check(self.L.qpt_workspace_size(self.h, pool_paths, C.byref(n)), "qpt_workspace_size")
+        return n.value
+
+    def bind_workspace(self, ptr: int, nbytes: int, pool_paths: int = 0) -> None:
+        self.check(self.L.qpt_bind_workspace(self.h, C.c_void_p(ptr), nbytes, pool_paths), "qpt_bind_workspace")
+
+    def render_pass(self, first_pass: int, num_passes: int, max_depth: int, rr: bool = True, mode: int = 0,
+                    scramble: bool = True) -> None:
+        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble))
+        self.check(self.L.qpt_render_pass(self.h, first_pass, num_passes, C.byref(o)), "qpt_render_pass")
+
+    def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> None:
+        self.check(self.L.qpt_readback(self.h, _p(sum_rgb), _p(counts), int(dst_is_device)), "qpt_readback")
+
+    def reset_accum(self) -> None:
+        self.check(self.L.qpt_reset_accum(self.h), "qpt_reset_accum")
+
+    def get_stats(self) -> qpt_stats:
+        s = qpt_stats()
+        self.check(self.L.qpt_get_stats(self.h, C.byref(s)), "qpt_get_stats")
+        return s
+
+    def debug_sample_bits(self, idx, dim, n, scramble, out) -> None:
+        self.check(self.L.qpt_debug_sample_bits(self.h, _p(idx), _p(dim), n, int(scramble), _p(out)),
+                   "qpt_debug_sample_bits")
+
+    def debug_pixel_index(self, pass_: int, out) -> None:
+        self.check(self.L.qpt_debug_pixel_index(self.h, pass_, _p(out)), "qpt_debug_pixel_index")
+
+    def debug_trace(self, rays, n, any_hit, brute_force, t, tri, b12) -> None:
+        self.check(self.L.qpt_debug_trace(self.h, _p(rays), n, int(any_hit), int(brute_force), _p(t), _p(tri),
+                                          _p(b12)), "qpt_debug_trace")
+
+    def debug_light_tables(self):
+        cnt = C.c_uint32()
+        self.check(self.L.qpt_debug_light_tables(self.h, None, None, None, None, C.byref(cnt)),
+                   "qpt_debug_light_tables")
+        n = cnt.value
+        tri = np.empty(n, np.uint32)
+        prob = np.empty(n, np.float64)
+        alias = np.empty(n, np.uint32)
+        pmf = np.empty(n, np.float64)
+        self.check(self.L.qpt_debug_light_tables(self.h, _p(tri), _p(prob), _p(alias), _p(pmf), C.byref(cnt)),
+                   "qpt_debug_light_tables")
+        return dict(tri=tri, prob=prob, alias=alias, pmf=pmf)
+
+    def debug_env_tables(self, eh: int, ew: int):
+        rq = np.empty(eh, np.uint32)
+        cq = np.empty(eh * ew, np.uint32)
+        pdf = np.empty(eh * ew, np.float32)
+        self.check(self.L.qpt_debug_env_tables(self.h, _p(rq), _p(cq), _p(pdf)), "qpt_debug_env_tables")
+        return rq, cq.reshape(eh, ew), pdf.reshape(eh, ew)
+
+    def debug_bvh_nodes(self):
+        nn = C.c_uint32()
+        self.check(self.L.qpt_debug_bvh_nodes(self.h, None, None, C.byref(nn)), "qpt_debug_bvh_nodes")
+        nodes = np.empty((nn.value, 16), np.float32)
+        order = np.empty(self.ntri, np.uint32) if hasattr(self, "ntri") else None
+        self.check(self.L.qpt_debug_bvh_nodes(self.h, _p(nodes), _p(order), C.byref(nn)), "qpt_debug_bvh_nodes")
+        return nodes, order
+
+
+class Renderer:
+    """Scene + BVH + a torch-owned workspace on one GPU; renders 1-spp passes."""
+
+    def __init__(self, sc, device: int = 0, pool_paths: int = 0, stream=None):
+        import torch
+
+        self.torch = torch
+        self.sc = sc
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = Context(device, self.stream.cuda_stream)
+        self.ctx.ntri = sc.num_triangles
+        self.ctx.build_scene(sc)
+        self.bvh_stats = self.ctx.build_bvh()
+        self.pool_paths = pool_paths
+        nbytes = self.ctx.workspace_size(pool_paths)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) & ~255
+        self.ctx.bind_workspace(ptr, nbytes, pool_paths)
+        self.W, self.H = sc.width, sc.height
+
+    def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True):
+        self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble)
+
+    def readback(self):
+        s = np.empty((self.H * self.W, 3), np.float64)
+        c = np.empty(self.H * self.W, np.uint32)
+        self.ctx.readback(s, c)
+        return s, c
+
+    def reset(self):
+        self.ctx.reset_accum()
+
+    def stats(self):
+        return self.ctx.get_stats()

@@ -1,0 +1,114 @@
+"""CPU checks of libqpt: it loads, exports every symbol of include/qpt.h, and its
+host-side builders (alias table, light pmf, environment CDFs, BVH) agree with
+the independent oracle and are structurally valid. No compute call here
+needs a GPU: a context on device -1 only runs the host builders.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def qpt():
+    from paper_1705_01263_amd import qpt as q
+    q.lib()
+    return q
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "qpt.h")).read()
+    return sorted(set(re.findall(r"\b(qpt_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(qpt):
+    L = qpt.lib()
+    names = _declared()
+    assert "qpt_render_pass" in names and "qpt_build_bvh" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(qpt.EXPORTS) == names
+
+
+def test_call_order_and_errors(qpt):
+    c = qpt.Context(-1)
+    with pytest.raises(qpt.QptError):
+        c.build_bvh()  # before build_scene
+    sc = g.make_config(0)
+    sc2 = g.make_config(0)
+    sc2.indices = sc2.indices.copy()
+    sc2.indices[0, 0] = 10_000  # out of range
+    with pytest.raises(qpt.QptError):
+        c.build_scene(sc2)
+    c.build_scene(sc)
+    with pytest.raises(qpt.QptError):
+        c.workspace_size()  # before build_bvh
+    c.build_bvh()
+    assert c.workspace_size(1 << 16) > 0
+    with pytest.raises(qpt.QptError):
+        c.bind_workspace(0x1000, 1 << 30)  # host-only context: no device
+    with pytest.raises(qpt.QptError):
+        c.render_pass(0, 1, 8)
+
+
+@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=2)])
+def test_light_tables_match_oracle(qpt, orc, make):
+    sc = make()
+    c = qpt.Context(-1)
+    c.build_scene(sc)
+    mine = c.debug_light_tables()
+    ref = orc.Scene(sc, build_bvh=False).lights()
+    assert np.array_equal(mine["tri"], ref["tri"])
+    assert np.array_equal(mine["alias"], ref["alias"])
+    assert np.array_equal(mine["prob"], ref["prob"])   # bit-identical FP64 tables
+    assert np.array_equal(mine["pmf"], ref["pmf"])
+
+
+def test_env_tables_match_oracle(qpt, orc):
+    sc = g.instanced_env_scene(target_tris=1000, env_size=(256, 128))
+    c = qpt.Context(-1)
+    c.build_scene(sc)
+    eh, ew = sc.env.shape[:2]
+    rq, cq, pdf = c.debug_env_tables(eh, ew)
+    orq, ocq, opdf = orc.Scene(sc, build_bvh=False).env_tables()
+    assert np.array_equal(rq.astype(np.uint64), orq[:eh])
+    assert np.array_equal(cq.astype(np.uint64), ocq[:, :ew])
+    assert np.array_equal(pdf, opdf.astype(np.float32))
+
+
+@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=4)])
+def test_bvh_structure(qpt, make):
+    sc = make()
+    c = qpt.Context(-1)
+    c.ntri = sc.num_triangles
+    c.build_scene(sc)
+    st = c.build_bvh()
+    assert st.max_depth < 32
+    nodes, order = c.debug_bvh_nodes()
+    # every triangle appears in exactly one leaf, inside that leaf's box
+    assert np.array_equal(np.sort(order), np.arange(sc.num_triangles, dtype=np.uint32))
+    refs = nodes[:, 12:14].copy().view(np.int32)
+    boxes = [nodes[:, 0:6], nodes[:, 6:12]]
+    pos = sc.positions[sc.indices[order]]  # BVH order, (nt, 3, 3)
+    seen = np.zeros(sc.num_triangles, np.int32)
+    for k in range(nodes.shape[0]):
+        for ch in range(2):
+            r = int(refs[k, ch])
+            lo, hi = boxes[ch][k, 0:3], boxes[ch][k, 3:6]
+            if r >= 0:
+                # child box contains the child's own boxes
+                for cc in range(2):
+                    assert np.all(boxes[cc][r, 0:3] >= lo) and np.all(boxes[cc][r, 3:6] <= hi)
+            else:
+                p = ~np.int64(r) & 0xFFFFFFFF
+                first, cnt = p >> 3, (p & 7) + 1
+                tri = pos[first:first + cnt]
+                assert np.all(tri >= lo) and np.all(tri <= hi)
+                if not (nodes.shape[0] == 1 and ch == 1):
+                    seen[first:first + cnt] += 1
+    assert np.all(seen == 1)
