@@ -75,6 +75,8 @@ def lib():
         L.or_env_lookup.restype = C.c_double
         L.or_bsdf_batch.argtypes = [P, u32, P, P, P, u32, P, P]
         L.or_bsdf_sample_batch.argtypes = [P, u32, P, P, P, u32, P, P]
+        L.or_debug_path.argtypes = [P, u32, u32, u32, u32, u32, u32, u64, P, P, u32]
+        L.or_debug_path.restype = u32
         L.or_ggx_D.argtypes = [C.c_double, C.c_double]
         L.or_ggx_D.restype = C.c_double
         _lib = L
@@ -269,6 +271,13 @@ class Scene:
         ok = np.empty(u.shape[0], np.int32)
         lib().or_bsdf_sample_batch(self.h, m, _p(n), _p(wo), _p(u), u.shape[0], _p(wi), _p(ok))
         return ok.astype(bool), wi
+
+    def debug_path(self, px, py, pass_, max_depth=None, rr=True, mode=0, scramble=True):
+        L = np.empty(3)
+        log = np.zeros(8 * 256)
+        n = lib().or_debug_path(self.h, max_depth or self.sc.max_depth, int(rr), mode, int(scramble), px, py,
+                                pass_, _p(L), _p(log), log.shape[0])
+        return L, log[:n].reshape(-1, 8)
 
     def env_lookup(self, w):
         w = np.ascontiguousarray(w, np.float64)

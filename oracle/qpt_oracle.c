@@ -820,17 +820,23 @@ static v3 env_lookup(const or_scene *s, v3 w, double *pdf)
     return s->env[q];
 }
 
-/* Wachter-Binder style origin offset, emulated on the FP64 point: move each
- * coordinate by trunc(256 n_c) units in the last place of its FP32 value,
- * or by n_c / 65536 within 1/32 of the origin. */
+/* Wachter-Binder origin offset (reading of Sec. 2.2's front/back-side
+ * points): each coordinate moves by trunc(256 n_c) steps of the FP32 grid,
+ * counted on the bit pattern of its FP32 value (so a step across a power of
+ * two uses the finer spacing below it), or by n_c / 65536 within 1/32 of
+ * the origin. The oracle adds to its FP64 point exactly the displacement
+ * this rule gives to the FP32 rounding of that point. */
 static double offset1(double p, double n)
 {
     if (fabs(p) < 1.0 / 32.0) return p + n / 65536.0;
-    int e;
-    frexp(p, &e);                         /* |p| in [2^(e-1), 2^e) */
-    double ulp = ldexp(1.0, e - 1 - 23);
-    int k = (int)(256.0 * n);
-    return p + (double)k * ulp;
+    float pf = (float)p;
+    int32_t k = (int32_t)(float)(256.0f * (float)n);
+    int32_t bits;
+    memcpy(&bits, &pf, 4);
+    bits += pf < 0.0f ? -k : k;
+    float qf;
+    memcpy(&qf, &bits, 4);
+    return p + ((double)qf - (double)pf);
 }
 static v3 offset_ray(v3 p, v3 n) { return V3(offset1(p.x, n.x), offset1(p.y, n.y), offset1(p.z, n.z)); }
 
@@ -842,6 +848,17 @@ typedef struct {
 } or_opts;
 
 static inline double mis2(double a, double b) { return a * a / (a * a + b * b); }
+
+/* optional per-vertex log for single-path debugging (not thread-safe) */
+static double *g_log = NULL;
+static uint32_t g_log_n = 0, g_log_cap = 0;
+static void logv(double a, double b, double c, double d, double e, double f, double g, double h)
+{
+    if (!g_log || g_log_n + 8 > g_log_cap) return;
+    double *q = g_log + g_log_n;
+    q[0] = a; q[1] = b; q[2] = c; q[3] = d; q[4] = e; q[5] = f; q[6] = g; q[7] = h;
+    g_log_n += 8;
+}
 
 /* radiance estimate of one path for sample index i through film point (fx, fy) */
 static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t px, uint32_t py,
@@ -872,6 +889,8 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
         uint32_t t = (uint32_t)h.tri, m = s->mat[t];
         v3 a = s->p0[t], b = s->p1[t], c = s->p2[t];
         v3 x = add(a, add(mul(sub(b, a), h.b1), mul(sub(c, a), h.b2)));
+        logv(1, v, t, h.t, x.x, x.y, x.z, 0);
+        logv(2, o.x, o.y, o.z, d.x, d.y, d.z, 0);
         v3 ng = cross(sub(b, a), sub(c, a));
         double area2 = len(ng);
         ng = mul(ng, 1.0 / area2);
@@ -963,7 +982,9 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
                         hit64 sh;
                         (*nrays)++;
                         double tm = isinf(dist) ? INFINITY : dist * (1.0 - 1e-4);
-                        if (!trace64(s, xo, wi, tm, 1, 0, &sh)) L = add(L, contrib);
+                        int occ = trace64(s, xo, wi, tm, 1, 0, &sh);
+                        logv(3, occ, contrib.x, contrib.y, contrib.z, pl, w, 0);
+                        if (!occ) L = add(L, contrib);
                     }
                 }
             }
@@ -1070,6 +1091,21 @@ uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t 
     }
     pthread_mutex_destroy(&mu);
     return rays;
+}
+
+/* one path with a per-vertex log: records of 8 doubles,
+ * (1, v, tri, t, x) (2, ray o, ray d) (3, occluded, contrib, pl, w) */
+uint32_t or_debug_path(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble,
+                       uint32_t px, uint32_t py, uint64_t pass, double *L_out, double *log, uint32_t cap)
+{
+    or_opts op = {max_depth, rr, mode, scramble};
+    g_log = log; g_log_n = 0; g_log_cap = cap;
+    uint32_t nr = 0;
+    uint64_t i = or_pixel_index(s->W, s->H, px, py, pass);
+    v3 L = trace_path(s, &op, i, px, py, &nr);
+    g_log = NULL;
+    L_out[0] = L.x; L_out[1] = L.y; L_out[2] = L.z;
+    return g_log_n;
 }
 
 /* ---------------------------------------------- pieces exposed for pins */
