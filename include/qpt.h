@@ -107,8 +107,29 @@ typedef struct {
     uint64_t rays_extension; /* closest-hit rays traced since the last reset */
     uint64_t rays_shadow;    /* occlusion rays traced */
     uint64_t paths;          /* paths completed */
-    uint64_t passes;         /* 1-spp iterations completed */
+    uint64_t passes;         /* 1-spp iterations completed (paths / pixels) */
+    uint64_t nodes_extension;/* BVH node fetches of the closest-hit rays */
+    uint64_t tris_extension; /* triangle tests of the closest-hit rays */
+    uint64_t nodes_shadow;   /* BVH node fetches of the occlusion rays */
+    uint64_t tris_shadow;    /* triangle tests of the occlusion rays */
 } qpt_stats;
+
+/* kernel kinds reported by the profiler */
+enum {
+    QPT_K_CLEAR = 0,      /* queue counter reset */
+    QPT_K_GENERATE = 1,   /* enumeration, Halton film samples, camera rays */
+    QPT_K_TRACE = 2,      /* closest hit of extension rays */
+    QPT_K_SHADE = 3,      /* emission + MIS, NEE, BSDF sampling, roulette */
+    QPT_K_SHADOW = 4,     /* occlusion of shadow rays */
+    QPT_K_ACCUMULATE = 5, /* FP64 framebuffer and counts */
+    QPT_K_KINDS = 6
+};
+
+typedef struct {
+    uint32_t launches;    /* kernel launches timed */
+    uint32_t reserved;
+    double total_ms;      /* sum of the launches' durations (stream events) */
+} qpt_kernel_time;
 
 /* Create a context on HIP device `hip_device` that enqueues on `hip_stream`
  * (hipStream_t or NULL). QPT_E_UNSUPPORTED if the device is not gfx950.
@@ -158,6 +179,15 @@ int qpt_reset_accum(qpt_ctx *ctx);
 
 /* Synchronise and read the ray/path counters. */
 int qpt_get_stats(qpt_ctx *ctx, qpt_stats *out);
+
+/* Profiling: enable = 1 starts bracketing every kernel launch of
+ * qpt_render_pass with HIP events on the context's stream (previous
+ * records are dropped); enable = 0 stops. */
+int qpt_profile(qpt_ctx *ctx, int enable);
+
+/* Synchronise and sum the recorded launch durations per kernel kind into
+ * out[QPT_K_KINDS] (caller-owned host array). */
+int qpt_profile_read(qpt_ctx *ctx, qpt_kernel_time *out);
 
 /* ---- parity hooks: inputs and outputs are DEVICE pointers, enqueued on the
  * stream; call qpt_readback or synchronise the stream before reading ---- */

@@ -274,8 +274,53 @@ struct Layout {
 
 }  // namespace
 
+namespace {
+// events bracketing each kernel launch, read back once at the end
+struct EventProfiler : qpt::Profiler {
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin(int kind, hipStream_t s) override
+    {
+        hipEvent_t e = take();
+        if (e) (void)hipEventRecord(e, s);
+        recs.push_back({kind, e, nullptr});
+    }
+    void end(int, hipStream_t s) override
+    {
+        hipEvent_t e = take();
+        if (e) (void)hipEventRecord(e, s);
+        recs.back().b = e;
+    }
+    void clear()
+    {
+        recs.clear();
+        used = 0;
+    }
+    ~EventProfiler() override
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace
+
 struct qpt_ctx {
     int device = -1;
+    EventProfiler prof;
+    bool profiling = false;
     hipStream_t stream = nullptr;
     std::string err;
     bool scene_ok = false, bvh_ok = false, bound = false;
@@ -584,7 +629,7 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.sh_d = take((size_t)cap * 16);
     L.sh_c = take((size_t)cap * 16);
     L.counters = take(128 * 4);
-    L.stats = take(4 * 8);
+    L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
     L.total = o;
@@ -923,7 +968,7 @@ int qpt_reset_accum(qpt_ctx *c)
     size_t npix = (size_t)c->W * c->H;
     HIP_TRY(c, launch_fill_f64(c->pool.fb_sum, npix * 3, c->stream));
     HIP_TRY(c, launch_fill_u32(c->pool.fb_count, npix, 0, c->stream));
-    HIP_TRY(c, launch_fill_u32((uint32_t *)c->pool.stats, 8, 0, c->stream));
+    HIP_TRY(c, launch_fill_u32((uint32_t *)c->pool.stats, 16, 0, c->stream));
     return QPT_OK;
 }
 
@@ -948,14 +993,15 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         uint32_t per = std::max(1u, cap / npix);
         for (uint32_t done = 0; done < num_passes;) {
             uint32_t nb = std::min(per, num_passes - done);
-            HIP_TRY(c, launch_render_batch(f, c->pool, 0, npix, first_pass + done, nb, c->stream));
+            HIP_TRY(c, launch_render_batch(f, c->pool, 0, npix, first_pass + done, nb, c->stream,
+                                           c->profiling ? &c->prof : nullptr));
             done += nb;
         }
     } else {
         for (uint32_t j = 0; j < num_passes; ++j)
             for (uint32_t p0 = 0; p0 < npix; p0 += cap)
                 HIP_TRY(c, launch_render_batch(f, c->pool, p0, std::min(cap, npix - p0), first_pass + j, 1,
-                                               c->stream));
+                                               c->stream, c->profiling ? &c->prof : nullptr));
     }
     return QPT_OK;
 }
@@ -978,13 +1024,47 @@ int qpt_get_stats(qpt_ctx *c, qpt_stats *out)
     if (!c || !out) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
     DeviceGuard g(c->device);
-    unsigned long long s[4];
+    unsigned long long s[8];
     HIP_TRY(c, hipMemcpyAsync(s, c->pool.stats, sizeof s, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     out->rays_extension = s[0];
     out->rays_shadow = s[1];
     out->paths = s[2];
     out->passes = s[2] / ((uint64_t)c->W * c->H);
+    out->nodes_extension = s[4];
+    out->tris_extension = s[5];
+    out->nodes_shadow = s[6];
+    out->tris_shadow = s[7];
+    return QPT_OK;
+}
+
+int qpt_profile(qpt_ctx *c, int enable)
+{
+    if (!c) return QPT_E_INVALID;
+    if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
+    DeviceGuard g(c->device);
+    if (enable) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        c->prof.clear();
+    }
+    c->profiling = enable != 0;
+    return QPT_OK;
+}
+
+int qpt_profile_read(qpt_ctx *c, qpt_kernel_time *out)
+{
+    if (!c || !out) return QPT_E_INVALID;
+    if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < QPT_K_KINDS; ++k) out[k] = qpt_kernel_time{0, 0, 0.0};
+    for (const EventProfiler::Rec &r : c->prof.recs) {
+        if (!r.a || !r.b || r.kind < 0 || r.kind >= QPT_K_KINDS) continue;
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, r.a, r.b));
+        out[r.kind].launches++;
+        out[r.kind].total_ms += ms;
+    }
     return QPT_OK;
 }
 

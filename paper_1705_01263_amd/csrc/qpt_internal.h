@@ -99,16 +99,28 @@ struct Pool {
     float4 *sh_d;       // shadow ray d.xyz, slot (bits)
     float4 *sh_c;       // pending contribution rgb, -
     uint32_t *counters; // [0..63] ext counts per depth, [64..127] shadow counts
-    unsigned long long *stats;  // ext rays, shadow rays, paths, passes
+    // [0] ext rays [1] shadow rays [2] paths [3] - [4] ext node visits
+    // [5] ext triangle tests [6] shadow node visits [7] shadow triangle tests
+    unsigned long long *stats;
     double *fb_sum;     // W*H*3
     uint32_t *fb_count; // W*H
+};
+
+// kernel kinds timed by the optional profiler
+enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMULATE, K_KINDS };
+
+// brackets every kernel launch of a batch with stream events when set
+struct Profiler {
+    virtual void begin(int kind, hipStream_t s) = 0;
+    virtual void end(int kind, hipStream_t s) = 0;
+    virtual ~Profiler() {}
 };
 
 // kernel launchers (qpt_kernels.hip)
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
-                               uint64_t pass0, uint32_t npass, hipStream_t s);
+                               uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
 hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
                                     uint32_t n, int scramble, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);

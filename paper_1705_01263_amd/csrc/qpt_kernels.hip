@@ -242,7 +242,15 @@ struct HitRec {
     float t, b1, b2;
     uint32_t tri;   // BVH-order index
     uint32_t id;    // input id (tie-break)
+    uint32_t nodes, tests;  // traversal work: node fetches, triangle tests
 };
+
+// sum a per-lane count over the wave and add it to a 64-bit counter once
+__device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (__lane_id() == 0 && v) atomicAdd(ctr, (unsigned long long)v);
+}
 
 // Closest hit (ANY = false) or occlusion (ANY = true) through the BVH, with
 // a per-thread stack in LDS laid out [entry][thread] (bank-conflict free).
@@ -252,12 +260,15 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
     h.t = tmax;
     h.tri = kNoHit;
     h.id = kNoHit;
+    h.nodes = 0;
+    h.tests = 0;
     int sp = 0;
     int ref = 0;
     const int step = (int)blockDim.x;
     while (true) {
         if (ref >= 0) {
             const Node n = F.nodes[ref];
+            ++h.nodes;
             bool h0, h1;
             float t0, t1;
             node_test(n, r, h.t, h0, h1, t0, t1);
@@ -279,6 +290,7 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
             for (uint32_t k = 0; k < cnt; ++k) {
                 const Tri tr = F.tris[first + k];
                 float t, b1, b2;
+                ++h.tests;
                 if (!tri_test(r, tr.v0, tr.v1, tr.v2, tmax, t, b1, b2)) continue;
                 if (ANY) {
                     h.tri = first + k;
@@ -518,6 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(Frame F, Pool P, uint32_t v)
     __shared__ int stk[kStackSize * kBlock];
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];
+    uint32_t nodes = 0, tests = 0;
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t i = base + threadIdx.x;
         if (i >= n) break;
@@ -527,7 +540,11 @@ __global__ __launch_bounds__(kBlock) void k_trace(Frame F, Pool P, uint32_t v)
         HitRec h;
         traverse<false>(F, r, o.w, h, stk + threadIdx.x);
         P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
+        nodes += h.nodes;
+        tests += h.tests;
     }
+    wave_count(&P.stats[4], nodes);
+    wave_count(&P.stats[5], tests);
 }
 
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
@@ -710,19 +727,25 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
 {
     __shared__ int stk[kStackSize * kBlock];
     const uint32_t n = P.counters[64 + v];
+    uint32_t nodes = 0, tests = 0;
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t i = base + threadIdx.x;
         if (i >= n) break;
         float4 o = P.sh_o[i], d = P.sh_d[i];
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
-        if (!traverse<true>(F, r, o.w, h, stk + threadIdx.x)) {
+        bool occluded = traverse<true>(F, r, o.w, h, stk + threadIdx.x);
+        nodes += h.nodes;
+        tests += h.tests;
+        if (!occluded) {
             uint32_t slot = fbits(d.w);
             float4 c = P.sh_c[i];
             float4 L = P.rad[slot];
             P.rad[slot] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
         }
     }
+    wave_count(&P.stats[6], nodes);
+    wave_count(&P.stats[7], tests);
 }
 
 // FP64 accumulation in pass order and sample counts
@@ -812,19 +835,28 @@ hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s)
 }
 
 hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
-                               uint32_t npass, hipStream_t s)
+                               uint32_t npass, hipStream_t s, Profiler *prof)
 {
     uint32_t n = npix * npass;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(128), 0, s, P.counters, (size_t)128, 0u);
-    hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
+    auto timed = [&](int kind, auto &&launch) {
+        if (prof) prof->begin(kind, s);
+        launch();
+        if (prof) prof->end(kind, s);
+    };
+    timed(K_CLEAR, [&] { hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(128), 0, s, P.counters, (size_t)128, 0u); });
+    timed(K_GENERATE, [&] {
+        hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
+    });
     uint32_t g = blocks_for(n, 8192);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
-        hipLaunchKernelGGL(k_trace, dim3(g), dim3(kBlock), 0, s, F, P, v);
-        hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v);
-        hipLaunchKernelGGL(k_shadow, dim3(g), dim3(kBlock), 0, s, F, P, v);
+        timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(g), dim3(kBlock), 0, s, F, P, v); });
+        timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
+        timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(g), dim3(kBlock), 0, s, F, P, v); });
     }
-    hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix,
-                       npass);
+    timed(K_ACCUMULATE, [&] {
+        hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix,
+                           npass);
+    });
     return hipGetLastError();
 }
 

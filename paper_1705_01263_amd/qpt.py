@@ -51,14 +51,22 @@ class qpt_render_opts(C.Structure):
 
 class qpt_stats(C.Structure):
     _fields_ = [("rays_extension", C.c_uint64), ("rays_shadow", C.c_uint64), ("paths", C.c_uint64),
-                ("passes", C.c_uint64)]
+                ("passes", C.c_uint64), ("nodes_extension", C.c_uint64), ("tris_extension", C.c_uint64),
+                ("nodes_shadow", C.c_uint64), ("tris_shadow", C.c_uint64)]
+
+
+class qpt_kernel_time(C.Structure):
+    _fields_ = [("launches", C.c_uint32), ("reserved", C.c_uint32), ("total_ms", C.c_double)]
+
+
+KERNEL_KINDS = ["clear", "generate", "trace", "shade", "shadow", "accumulate"]
 
 
 EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
-    "qpt_debug_env_tables", "qpt_debug_bvh_nodes",
+    "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read",
 ]
 
 _lib = None
@@ -94,6 +102,8 @@ def lib():
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
             "qpt_debug_env_tables": ([P, P, P, P], i32),
             "qpt_debug_bvh_nodes": ([P, P, P, P], i32),
+            "qpt_profile": ([P, i32], i32),
+            "qpt_profile_read": ([P, C.POINTER(qpt_kernel_time)], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -201,6 +211,14 @@ class Context:
         s = qpt_stats()
         self.check(self.L.qpt_get_stats(self.h, C.byref(s)), "qpt_get_stats")
         return s
+
+    def profile(self, enable: bool) -> None:
+        self.check(self.L.qpt_profile(self.h, int(enable)), "qpt_profile")
+
+    def profile_read(self) -> dict:
+        arr = (qpt_kernel_time * len(KERNEL_KINDS))()
+        self.check(self.L.qpt_profile_read(self.h, arr), "qpt_profile_read")
+        return {k: (arr[i].launches, arr[i].total_ms) for i, k in enumerate(KERNEL_KINDS)}
 
     def debug_sample_bits(self, idx, dim, n, scramble, out) -> None:
         self.check(self.L.qpt_debug_sample_bits(self.h, _p(idx), _p(dim), n, int(scramble), _p(out)),
