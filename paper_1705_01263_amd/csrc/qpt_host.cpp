@@ -267,7 +267,7 @@ struct Builder {
 struct Layout {
     size_t nodes, tris, mats, emit_tri, alias_idx, alias_thr, emit_pmf, env_texel, env_row,
         env_col, env_cos, bases;
-    size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats;
+    size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats, gstack;
     size_t fb_sum, fb_count;
     size_t total;
 };
@@ -319,6 +319,7 @@ struct EventProfiler : qpt::Profiler {
 
 struct qpt_ctx {
     int device = -1;
+    uint32_t trav_threads = 0;  // traversal grid: CUs x resident blocks per CU x block size
     EventProfiler prof;
     bool profiling = false;
     hipStream_t stream = nullptr;
@@ -629,6 +630,7 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.sh_d = take((size_t)cap * 16);
     L.sh_c = take((size_t)cap * 16);
     L.counters = take(128 * 4);
+    L.gstack = take((size_t)c->trav_threads * kDeepStack * 4);
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
@@ -651,6 +653,7 @@ int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
     c->bases = make_bases();
+    c->trav_threads = 256 * kTravBlocksPerCU * kBlock;  // host-only contexts: sizing only
     if (hip_device >= 0) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
@@ -661,6 +664,7 @@ int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
             delete c;
             return QPT_E_UNSUPPORTED;
         }
+        c->trav_threads = (uint32_t)prop.multiProcessorCount * kTravBlocksPerCU * kBlock;
     }
     *out = c;
     return QPT_OK;
@@ -947,6 +951,8 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     p.sh_d = (float4 *)(w + L.sh_d);
     p.sh_c = (float4 *)(w + L.sh_c);
     p.counters = (uint32_t *)(w + L.counters);
+    p.gstack = (int *)(w + L.gstack);
+    p.trav_threads = c->trav_threads;
     p.stats = (unsigned long long *)(w + L.stats);
     p.fb_sum = (double *)(w + L.fb_sum);
     p.fb_count = (uint32_t *)(w + L.fb_count);
@@ -1098,7 +1104,7 @@ int qpt_debug_trace(qpt_ctx *c, const float *rays, uint32_t n, int any_hit, int 
     if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
-    HIP_TRY(c, launch_debug_trace(c->frame, rays, n, any_hit, brute_force, t, tri, b12, c->stream));
+    HIP_TRY(c, launch_debug_trace(c->frame, c->pool, rays, n, any_hit, brute_force, t, tri, b12, c->stream));
     return QPT_OK;
 }
 

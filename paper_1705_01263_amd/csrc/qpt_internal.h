@@ -7,8 +7,10 @@
 namespace qpt {
 
 constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
-constexpr uint32_t kStackSize = 32;      // traversal stack entries per ray (LDS)
-constexpr uint32_t kMaxTreeDepth = 32;   // builder guarantee: stack never overflows
+constexpr uint32_t kShortStack = 16;     // traversal stack entries per ray kept in LDS
+constexpr uint32_t kDeepStack = 16;      // further entries in a global overflow area
+constexpr uint32_t kMaxTreeDepth = 32;   // builder guarantee: kShortStack + kDeepStack suffice
+constexpr uint32_t kTravBlocksPerCU = 8; // traversal grid: 8 resident blocks x 4 waves per CU
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
 constexpr uint32_t kNoHit = 0xffffffffu;
 
@@ -98,7 +100,9 @@ struct Pool {
     float4 *sh_o;       // shadow ray o.xyz, tmax
     float4 *sh_d;       // shadow ray d.xyz, slot (bits)
     float4 *sh_c;       // pending contribution rgb, -
-    uint32_t *counters; // [0..63] ext counts per depth, [64..127] shadow counts
+    uint32_t *counters;     // [0..63] ext counts per depth, [64..127] shadow counts
+    int *gstack;            // traversal stack overflow, kDeepStack per traversal thread
+    uint32_t trav_threads;  // threads of the traversal grid (gstack stride)
     // [0] ext rays [1] shadow rays [2] paths [3] - [4] ext node visits
     // [5] ext triangle tests [6] shadow node visits [7] shadow triangle tests
     unsigned long long *stats;
@@ -124,7 +128,7 @@ hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, 
 hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
                                     uint32_t n, int scramble, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);
-hipError_t launch_debug_trace(const Frame &f, const float *rays, uint32_t n, int any_hit,
+hipError_t launch_debug_trace(const Frame &f, const Pool &pool, const float *rays, uint32_t n, int any_hit,
                               int brute, float *t, uint32_t *tri, float *b12, hipStream_t s);
 
 }  // namespace qpt

@@ -252,10 +252,13 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
     if (__lane_id() == 0 && v) atomicAdd(ctr, (unsigned long long)v);
 }
 
-// Closest hit (ANY = false) or occlusion (ANY = true) through the BVH, with
-// a per-thread stack in LDS laid out [entry][thread] (bank-conflict free).
+// Closest hit (ANY = false) or occlusion (ANY = true) through the BVH (Sec.
+// 2.3: watertight traversal). The stack keeps kShortStack entries per thread
+// in LDS, laid out [entry][thread] (bank-conflict free), and spills deeper
+// entries to a per-thread global area (stride gs); the small LDS footprint
+// lets 8 waves share a SIMD to hide the latency of the dependent node loads.
 template <bool ANY>
-__device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk)
+__device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs)
 {
     h.t = tmax;
     h.tri = kNoHit;
@@ -275,7 +278,8 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
             if (h0 && h1) {
                 bool swap = t1 < t0;
                 int nearr = swap ? n.d.y : n.d.x, farr = swap ? n.d.x : n.d.y;
-                stk[sp * step] = farr;
+                if (sp < (int)kShortStack) stk[sp * step] = farr;
+                else gstk[(sp - kShortStack) * gs] = farr;
                 ++sp;
                 ref = nearr;
                 continue;
@@ -308,7 +312,7 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
         }
         if (sp == 0) break;
         --sp;
-        ref = stk[sp * step];
+        ref = sp < (int)kShortStack ? stk[sp * step] : gstk[(sp - kShortStack) * gs];
     }
     return h.tri != kNoHit;
 }
@@ -524,12 +528,14 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
     P.q_ext[1][s] = s;
 }
 
-// closest hit for the extension rays queued at depth v
+// closest hit for the extension rays queued at depth v; the grid is sized to
+// what is resident on the chip and strides over the queue
 __global__ __launch_bounds__(kBlock) void k_trace(Frame F, Pool P, uint32_t v)
 {
-    __shared__ int stk[kStackSize * kBlock];
+    __shared__ int stk[kShortStack * kBlock];
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];
+    int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t nodes = 0, tests = 0;
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t i = base + threadIdx.x;
@@ -538,13 +544,40 @@ __global__ __launch_bounds__(kBlock) void k_trace(Frame F, Pool P, uint32_t v)
         float4 o = P.ray_o[slot], d = P.ray_d[slot];
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
-        traverse<false>(F, r, o.w, h, stk + threadIdx.x);
+        traverse<false>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
         P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
         nodes += h.nodes;
         tests += h.tests;
     }
     wave_count(&P.stats[4], nodes);
     wave_count(&P.stats[5], tests);
+}
+
+// occlusion test of the shadow rays queued at depth v; add unoccluded contributions
+__global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
+{
+    __shared__ int stk[kShortStack * kBlock];
+    const uint32_t n = P.counters[64 + v];
+    int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
+    uint32_t nodes = 0, tests = 0;
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        uint32_t i = base + threadIdx.x;
+        if (i >= n) break;
+        float4 o = P.sh_o[i], d = P.sh_d[i];
+        RayPre r = prepare(xyz(o), xyz(d));
+        HitRec h;
+        bool occluded = traverse<true>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+        nodes += h.nodes;
+        tests += h.tests;
+        if (!occluded) {
+            uint32_t slot = fbits(d.w);
+            float4 c = P.sh_c[i];
+            float4 L = P.rad[slot];
+            P.rad[slot] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
+        }
+    }
+    wave_count(&P.stats[6], nodes);
+    wave_count(&P.stats[7], tests);
 }
 
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
@@ -722,32 +755,6 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
     }
 }
 
-// occlusion test of the shadow rays queued at depth v; add unoccluded contributions
-__global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
-{
-    __shared__ int stk[kStackSize * kBlock];
-    const uint32_t n = P.counters[64 + v];
-    uint32_t nodes = 0, tests = 0;
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        uint32_t i = base + threadIdx.x;
-        if (i >= n) break;
-        float4 o = P.sh_o[i], d = P.sh_d[i];
-        RayPre r = prepare(xyz(o), xyz(d));
-        HitRec h;
-        bool occluded = traverse<true>(F, r, o.w, h, stk + threadIdx.x);
-        nodes += h.nodes;
-        tests += h.tests;
-        if (!occluded) {
-            uint32_t slot = fbits(d.w);
-            float4 c = P.sh_c[i];
-            float4 L = P.rad[slot];
-            P.rad[slot] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
-        }
-    }
-    wave_count(&P.stats[6], nodes);
-    wave_count(&P.stats[7], tests);
-}
-
 // FP64 accumulation in pass order and sample counts
 __global__ __launch_bounds__(kBlock) void k_accumulate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint32_t npass)
 {
@@ -793,17 +800,40 @@ __global__ void k_debug_pixel_index(Frame F, uint64_t pass, uint64_t *out)
     out[q] = pixel_index(F, q % F.W, q / F.W, pass);
 }
 
-template <bool ANY, bool BRUTE>
-__global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, const float *rays, uint32_t n, float *t,
+template <bool ANY>
+__global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, Pool P, const float *rays, uint32_t n, float *t,
                                                         uint32_t *tri, float *b12)
 {
-    __shared__ int stk[kStackSize * kBlock];
+    __shared__ int stk[kShortStack * kBlock];
+    int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        uint32_t q = base + threadIdx.x;
+        if (q >= n) break;
+        const float *ry = rays + 8 * (size_t)q;
+        RayPre r = prepare(mk(ry[0], ry[1], ry[2]), mk(ry[4], ry[5], ry[6]));
+        HitRec h;
+        bool hit = traverse<ANY>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
+        if (ANY) {
+            tri[q] = hit ? 1u : 0u;
+            continue;
+        }
+        tri[q] = hit ? h.id : kNoHit;
+        t[q] = hit ? h.t : INFINITY;
+        b12[2 * (size_t)q] = hit ? h.b1 : 0.0f;
+        b12[2 * (size_t)q + 1] = hit ? h.b2 : 0.0f;
+    }
+}
+
+template <bool ANY>
+__global__ __launch_bounds__(kBlock) void k_debug_brute(Frame F, const float *rays, uint32_t n, float *t,
+                                                        uint32_t *tri, float *b12)
+{
     uint32_t q = blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
     const float *ry = rays + 8 * (size_t)q;
     RayPre r = prepare(mk(ry[0], ry[1], ry[2]), mk(ry[4], ry[5], ry[6]));
     HitRec h;
-    bool hit = BRUTE ? brute_force<ANY>(F, r, ry[3], h) : traverse<ANY>(F, r, ry[3], h, stk + threadIdx.x);
+    bool hit = brute_force<ANY>(F, r, ry[3], h);
     if (ANY) {
         tri[q] = hit ? 1u : 0u;
         return;
@@ -848,10 +878,11 @@ hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uin
         hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
     });
     uint32_t g = blocks_for(n, 8192);
+    uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
-        timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(g), dim3(kBlock), 0, s, F, P, v); });
+        timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
-        timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(g), dim3(kBlock), 0, s, F, P, v); });
+        timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
     }
     timed(K_ACCUMULATE, [&] {
         hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix,
@@ -875,18 +906,19 @@ hipError_t launch_debug_pixel_index(const Frame &F, uint64_t pass, uint64_t *out
     return hipGetLastError();
 }
 
-hipError_t launch_debug_trace(const Frame &F, const float *rays, uint32_t n, int any_hit, int brute, float *t,
-                              uint32_t *tri, float *b12, hipStream_t s)
+hipError_t launch_debug_trace(const Frame &F, const Pool &P, const float *rays, uint32_t n, int any_hit,
+                              int brute, float *t, uint32_t *tri, float *b12, hipStream_t s)
 {
-    dim3 g(blocks_for(n, 1u << 30)), b(kBlock);
-    if (any_hit) {
-        if (brute) hipLaunchKernelGGL((k_debug_trace<true, true>), g, b, 0, s, F, rays, n, t, tri, b12);
-        else hipLaunchKernelGGL((k_debug_trace<true, false>), g, b, 0, s, F, rays, n, t, tri, b12);
-    } else {
-        if (brute) hipLaunchKernelGGL((k_debug_trace<false, true>), g, b, 0, s, F, rays, n, t, tri, b12);
-        else hipLaunchKernelGGL((k_debug_trace<false, false>), g, b, 0, s, F, rays, n, t, tri, b12);
+    dim3 b(kBlock);
+    if (brute) {
+        dim3 g(blocks_for(n, 1u << 30));
+        if (any_hit) hipLaunchKernelGGL((k_debug_brute<true>), g, b, 0, s, F, rays, n, t, tri, b12);
+        else hipLaunchKernelGGL((k_debug_brute<false>), g, b, 0, s, F, rays, n, t, tri, b12);
+        return hipGetLastError();
     }
+    dim3 g(blocks_for(n, P.trav_threads / kBlock));
+    if (any_hit) hipLaunchKernelGGL((k_debug_trace<true>), g, b, 0, s, F, P, rays, n, t, tri, b12);
+    else hipLaunchKernelGGL((k_debug_trace<false>), g, b, 0, s, F, P, rays, n, t, tri, b12);
     return hipGetLastError();
 }
-
 }  // namespace qpt

@@ -175,6 +175,39 @@ def test_image_parity_grid_subset(Renderer, orc):
     assert mean_e <= 1e-4 and frac <= 1e-3
 
 
+def test_image_parity_env_subset(Renderer, orc):
+    """4M-triangle instanced scene under the sun-and-sky map (2D CDF sampling), every 8th pixel."""
+    sc = g.make_config(2)
+    _say(f"[image] env 1920x1080 tris={sc.num_triangles} passes=2 D=16")
+    s, c, _ = _render(Renderer, sc, 2)
+    W, H = sc.width, sc.height
+    ys, xs = np.meshgrid(np.arange(0, H, 8), np.arange(0, W, 8), indexing="ij")
+    pix = (ys * W + xs).reshape(-1).astype(np.uint32)
+    so, _, co, _ = orc.Scene(sc).render(pixels=pix, npasses=2)
+    mean_e, frac, e = orc.image_parity(s[pix], so)
+    _say(f"    mean rel err {mean_e:.3e}, pixels > 1e-3: {frac:.4%}, max {e.max():.3e}")
+    assert np.all(c[pix] == 2)
+    assert mean_e <= 1e-4 and frac <= 1e-3
+
+
+def test_constant_sky_every_path(Renderer):
+    """Convex Lambert box under a constant sky: BSDF-sampled paths that hit it carry rho E exactly."""
+    rho, E = 0.6, 2.0
+    sc = g.convex_under_env(rho, E, width=32, height=32, max_depth=4)
+    _say("[sky] convex box under constant env, BSDF only")
+    s, c, _ = _render(Renderer, sc, 8, rr=False, mode=1)
+    m = s / c[:, None]
+    r32 = float(np.float32(rho))
+    frac = (E - m) / (E - r32 * E)
+    assert np.all(frac > -1e-5) and np.all(frac < 1 + 1e-5)
+    full = np.all(np.abs(frac - 1.0) < 1e-5, axis=1)
+    assert full.sum() > 100
+    # with NEE of the sky and MIS the object pixels still average rho E
+    s, c, _ = _render(Renderer, sc, 64, rr=False, mode=0)
+    m = (s / c[:, None])[full].mean(0)
+    assert np.allclose(m, r32 * E, rtol=2e-3), m
+
+
 def test_furnace_every_path(Renderer):
     E, rho, D = 1.0, 0.5, 8
     sc = g.furnace(E, rho, width=32, height=32, max_depth=D)
