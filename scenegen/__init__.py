@@ -513,6 +513,24 @@ def quad_over_plane(rho=0.7, Le=4.0, width=1, height=1, max_depth=2) -> Scene:
     return s
 
 
+# ----------------------------------------------------------- guide inputs
+
+GUIDE_SIZES = (32, 64, 64, 64, 40)
+
+
+def guide_init(seed: int = 7) -> np.ndarray:
+    """Initial FP32 parameters of the 32-64-64-64-40 network, He-uniform weights
+    (bound sqrt(6 / fan_in)) and zero biases, packed layer by layer as W (in x out,
+    row-major) then b. These are input data drawn from the seeded generator."""
+    rng = SplitMix64(seed)
+    out = []
+    for fi, fo in zip(GUIDE_SIZES[:-1], GUIDE_SIZES[1:]):
+        lim = math.sqrt(6.0 / fi)
+        out.append(rng.uniform(fi * fo, -lim, lim))
+        out.append(np.zeros(fo))
+    return np.concatenate(out).astype(np.float32)
+
+
 CONFIGS = {
     0: cornell,
     1: grid_scene,
