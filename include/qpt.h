@@ -122,7 +122,9 @@ enum {
     QPT_K_SHADE = 3,      /* emission + MIS, NEE, BSDF sampling, roulette */
     QPT_K_SHADOW = 4,     /* occlusion of shadow rays */
     QPT_K_ACCUMULATE = 5, /* FP64 framebuffer and counts */
-    QPT_K_KINDS = 6
+    QPT_K_GUIDE_EVAL = 6, /* the network's mixture for every vertex (guiding on) */
+    QPT_K_GUIDE_TRAIN = 7,/* record finalisation, batch forward/backward, Adam */
+    QPT_K_KINDS = 8
 };
 
 typedef struct {
@@ -179,6 +181,56 @@ int qpt_reset_accum(qpt_ctx *ctx);
 
 /* Synchronise and read the ray/path counters. */
 int qpt_get_stats(qpt_ctx *ctx, qpt_stats *out);
+
+/* ---- the learned proposal: a 32-64-64-64-40 network (BF16 on MFMA, FP32
+ * accumulate) mapping an encoded hit position and outgoing direction to an
+ * 8-lobe von Mises-Fisher mixture, sampled with probability alpha and mixed
+ * with the BSDF under MIS (density alpha q + (1 - alpha) p_bsdf, so the
+ * estimator stays unbiased), trained online with Adam on the renderer's own
+ * radiance samples. Not part of the paper's method; an extension of its
+ * importance sampling (Sec. 2.1, 2.2). ---- */
+typedef struct {
+    float alpha;             /* probability of sampling the guide once active, [0, 1); 0 disables */
+    float lr;                /* Adam learning rate (> 0) */
+    uint32_t batch;          /* training samples per step (0 = 2^18, at most 2^22) */
+    uint32_t train;          /* 1: record training samples and take one Adam step per batch of passes */
+    uint32_t warmup_steps;   /* guide sampling stays off until this many steps were taken */
+    uint32_t seed;           /* offsets of the stratified batch subsets */
+} qpt_guide_opts;
+
+/* Set the guide options (takes effect at the next qpt_render_pass). */
+int qpt_guide_config(qpt_ctx *ctx, const qpt_guide_opts *opts);
+
+/* Load the FP32 master parameters from host memory (13032 values: per layer
+ * W (in x out, row-major) then b, layers 32->64->64->64->40) and reset the
+ * Adam state and step count. Needed before guiding or training. Synchronous. */
+int qpt_guide_set_weights(qpt_ctx *ctx, const float *params);
+
+/* Copy the FP32 master parameters to host memory and the number of training
+ * steps taken; either pointer may be NULL. Synchronises the stream. */
+int qpt_guide_get_weights(qpt_ctx *ctx, float *params, uint32_t *steps);
+
+/* Parity hooks (device pointers, enqueued on the stream):
+ * forward of n rows of 32 FP32 features -> n x 40 FP32 outputs; */
+int qpt_guide_debug_forward(qpt_ctx *ctx, const float *x, uint32_t n, float *out);
+/* gradient of -sum_b w_b log q(dir_b) / sum_b w_b w.r.t. the 13032 parameters
+ * for n rows (x: n x 32 features, dirs: n x 3 unit vectors, w: n weights); */
+int qpt_guide_debug_grad(qpt_ctx *ctx, const float *x, const float *dirs, const float *w, uint32_t n,
+                         float *grad);
+/* the same gradient followed by one Adam step (lr; beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected, step count + 1) on the FP32 master weights and
+ * the BF16 copy the kernels use; grad may be NULL; */
+int qpt_guide_debug_train(qpt_ctx *ctx, const float *x, const float *dirs, const float *w, uint32_t n, float lr,
+                          float *grad);
+/* decode n x 40 outputs, mixture pdf at dirs (n x 3) and a sample from
+ * u (n x 3: lobe, two direction numbers) into sample (n x 3). */
+int qpt_guide_debug_mixture(qpt_ctx *ctx, const float *out40, const float *dirs, const float *u, uint32_t n,
+                            float *pdf, float *sample);
+
+/* Weighted negative log-likelihood of the last training batch (sum_b w_b
+ * (-log q(dir_b)) / sum_b w_b) and its weight sum (host pointers, either may
+ * be NULL). Synchronises the stream. */
+int qpt_guide_loss(qpt_ctx *ctx, double *loss, double *weight_sum);
 
 /* Profiling: enable = 1 starts bracketing every kernel launch of
  * qpt_render_pass with HIP events on the context's stream (previous

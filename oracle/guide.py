@@ -9,7 +9,7 @@ every definition below is stated in the design notes.
 
 Precision: the workload fixes BF16 weights and activations with FP32
 accumulation. The oracle computes in FP64 on BF16-rounded weights and
-inputs and, when `bf16_act` is set, rounds each hidden activation to BF16
+inputs and, with `bf16` set, rounds each hidden activation to BF16
 (round to nearest even) before the next layer -- the rounding points of the
 GPU path -- so the two differ only by FP32-vs-FP64 accumulation.
 """
@@ -108,16 +108,19 @@ def forward(theta, X, bf16=True):
 
 
 def backward(theta, cache, dout, bf16=True):
-    """Gradient of sum(dout * outputs) w.r.t. the flat parameters."""
+    """Gradient of sum(dout * outputs) w.r.t. the flat parameters. With bf16
+    the pre-activation gradient enters the weight-gradient and data products
+    rounded to BF16 (the GPU's MFMA operands); bias gradients use it unrounded."""
     acts, pre, layers = cache
     rnd = to_bf16 if bf16 else (lambda a: np.asarray(a, np.float64))
     grads = [None] * len(layers)
     g = np.asarray(dout, np.float64)
     for li in range(len(layers) - 1, -1, -1):
         W, b = layers[li]
-        grads[li] = (acts[li].T @ g, g.sum(0))
+        gb = rnd(g)
+        grads[li] = (acts[li].T @ gb, g.sum(0))
         if li > 0:
-            g = (g @ rnd(W).T) * (pre[li - 1] > 0)
+            g = (gb @ rnd(W).T) * (pre[li - 1] > 0)
     return pack(grads)
 
 

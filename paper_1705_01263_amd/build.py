@@ -26,15 +26,19 @@ def _run(cmd):
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     host_o = os.path.join(BUILD, "qpt_host.o")
-    kern_o = os.path.join(BUILD, "qpt_kernels.o")
     common = ["-O3", "-std=c++17", "-fPIC", "-I", INC, "-I", CSRC, "-I", "/opt/rocm/include", "-Wall", "-Wno-unused-function"]
     # host builders: no contraction, so FP64 table construction is reproducible
     _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-ffp-contract=off", *common, "-c",
           os.path.join(CSRC, "qpt_host.cpp"), "-o", host_o])
-    _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *NO_PK_FP32, *common, "-c",
-          os.path.join(CSRC, "qpt_kernels.hip"), "-o", kern_o])
+    objs = [host_o]
+    for src in ("qpt_kernels.hip", "qpt_guide.hip"):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *NO_PK_FP32, *common, "-c",
+              os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, host_o, kern_o, "-lpthread"])
+    # -z defs: every symbol the library uses must resolve at link time
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
     return LIB
 

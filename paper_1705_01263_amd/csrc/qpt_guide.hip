@@ -1,0 +1,678 @@
+// The learned proposal on gfx950: a 32-64-64-64-40 ReLU network in BF16 on
+// MFMA with FP32 accumulation, mapping an encoded hit position and outgoing
+// direction to an 8-lobe von Mises-Fisher mixture; trained online from the
+// renderer's own radiance samples with Adam on FP32 master weights.
+//
+// MFMA mapping (v_mfma_f32_32x32x8bf16_1k, D = A x B + C, 32x32x8):
+//   A operand = weights:     lane l holds W[k = 8s + 4(l/32) + e][o = 32t + l%32], e = 0..3
+//   B operand = activations: lane l holds act[row = l%32][k = 8s + 4(l/32) + e]
+//   D:                       lane l, register v holds Z[o = 32t + 8(v/4) + 4(l/32) + v%4][row = l%32]
+// so registers 4s'..4s'+3 of the output tile s'/4 are exactly the B operand of
+// step s' of the next layer: layers chain in registers. Each row (a path
+// vertex or a training sample) is handled by the lane pair (l, l + 32); a wave
+// works on 32 rows at a time.
+#include <hip/hip_runtime.h>
+
+#include "qpt_guide_dev.h"
+#include "qpt_internal.h"
+
+namespace qpt {
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int kKS[4] = {4, 8, 8, 8};          // k-steps of 8 per layer
+constexpr int kN[4] = {64, 64, 64, 40};        // true output widths
+constexpr int kFB[4] = {0, 8, 24, 40};         // first forward fragment of each layer
+constexpr int kGB[4] = {0, 0, 16, 32};         // first transposed fragment (layers 1..3)
+constexpr int kOffW[4] = {0, 2112, 6272, 10432};
+constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
+constexpr int kTrainBlock = 256;               // 4 waves
+
+__device__ __forceinline__ uint32_t bf16_rne(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return b >> 16;
+}
+
+__device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
+{
+    v4s r;
+    r.x = (short)bf16_rne(a);
+    r.y = (short)bf16_rne(b);
+    r.z = (short)bf16_rne(c);
+    r.w = (short)bf16_rne(d);
+    return r;
+}
+
+__device__ __forceinline__ v4s as_v4s(uint2 u)
+{
+    v4s r;
+    r.x = (short)(u.x & 0xffff);
+    r.y = (short)(u.x >> 16);
+    r.z = (short)(u.y & 0xffff);
+    r.w = (short)(u.y >> 16);
+    return r;
+}
+
+__device__ __forceinline__ v16f mfma(v4s a, v4s b, v16f c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// one layer: acc[t] = W_L^T x in + b for the two 32-wide output tiles
+template <int L>
+__device__ __forceinline__ void layer_fwd(const uint2 *sfrag, const float *sbias, const v4s *in, v16f *acc)
+{
+    const uint32_t lane = lane_id(), half = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        v16f c = {};
+#pragma unroll
+        for (int s = 0; s < kKS[L]; ++s) c = mfma(as_v4s(sfrag[(kFB[L] + t * kKS[L] + s) * 64 + lane]), in[s], c);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) c[v] += sbias[L * 64 + 32 * t + 8 * (v / 4) + 4 * half + (v % 4)];
+        acc[t] = c;
+    }
+}
+
+// ReLU, its mask (bit 16t + v), and the BF16 B operands of the next layer
+__device__ __forceinline__ void relu_pack(const v16f *acc, v4s *out, uint32_t &mask)
+{
+    mask = 0;
+    float a[32];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            float z = acc[t][v];
+            bool p = z > 0.0f;
+            mask |= (uint32_t)p << (16 * t + v);
+            a[16 * t + v] = p ? z : 0.0f;
+        }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        int b = 16 * (s / 4) + 4 * (s % 4);
+        out[s] = pack4(a[b], a[b + 1], a[b + 2], a[b + 3]);
+    }
+}
+
+// B operands of layer 0 from a row's 32 features (each lane takes its half)
+__device__ __forceinline__ void input_frags(const float *f, v4s *a0)
+{
+    const bool hi = lane_id() >= 32;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        a0[s] = hi ? pack4(f[8 * s + 4], f[8 * s + 5], f[8 * s + 6], f[8 * s + 7])
+                   : pack4(f[8 * s], f[8 * s + 1], f[8 * s + 2], f[8 * s + 3]);
+}
+
+struct Act {
+    v4s a1[8], a2[8], a3[8];
+    uint32_t m0, m1, m2;
+};
+
+__device__ __forceinline__ void mlp_forward(const uint2 *sfrag, const float *sbias, const v4s *a0, Act &A, v16f *out)
+{
+    v16f acc[2];
+    layer_fwd<0>(sfrag, sbias, a0, acc);
+    relu_pack(acc, A.a1, A.m0);
+    layer_fwd<1>(sfrag, sbias, A.a1, acc);
+    relu_pack(acc, A.a2, A.m1);
+    layer_fwd<2>(sfrag, sbias, A.a2, acc);
+    relu_pack(acc, A.a3, A.m2);
+    layer_fwd<3>(sfrag, sbias, A.a3, out);
+}
+
+// all 40 outputs of the lane's row: half from itself, half from lane ^ 32
+__device__ __forceinline__ void gather40(const v16f *acc, float *o)
+{
+    const bool hi = lane_id() >= 32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        float mine = acc[0][v];
+        float other = __shfl_xor(mine, 32);
+        int f = 8 * (v / 4) + (v % 4);
+        o[f] = hi ? other : mine;       // features with 4(l/32) = 0
+        o[f + 4] = hi ? mine : other;   // features with 4(l/32) = 4
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        float mine = acc[1][v];
+        float other = __shfl_xor(mine, 32);
+        o[32 + v] = hi ? other : mine;
+        o[36 + v] = hi ? mine : other;
+    }
+}
+
+// back from a row's 40-vector to the lane's D-layout registers (padding 0)
+__device__ __forceinline__ void scatter40(const float *d, v16f *dz)
+{
+    const bool hi = lane_id() >= 32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        int f = 8 * (v / 4) + (v % 4);
+        dz[0][v] = hi ? d[f + 4] : d[f];
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) dz[1][v] = v < 4 ? (hi ? d[36 + v] : d[32 + v]) : 0.0f;
+}
+
+// Gradient of -w log q(w_dir) w.r.t. the 40 outputs, through the decode,
+// with lobe responsibilities g_k = pi_k f_k / q (stable in log space):
+//   logit: -w (g_k - pi_k); mu_raw: -w g_k kappa (w - (mu.w) mu) / |mu_raw|;
+//   kappa_raw: -w g_k (1/kappa - 2/expm1(2 kappa) + mu.w - 1) sigmoid(kappa_raw)
+// (zero where kappa is clamped). Returns -w log q in `loss`.
+__device__ void row_loss_grad(const float *o, guide::V3 wd, float w, float *d, float &loss)
+{
+    float mx = o[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) mx = fmaxf(mx, o[5 * k]);
+    float se = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) se += expf(o[5 * k] - mx);
+    float lse = logf(se);
+    float lf[8], pi[8], kap[8], mn[8], cw[8], mu[8][3];
+    bool clamped[8];
+    float lmax = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float lp = o[5 * k] - mx - lse;
+        pi[k] = expf(lp);
+        float x = o[5 * k + 1], y = o[5 * k + 2], z = o[5 * k + 3];
+        mn[k] = fmaxf(sqrtf(x * x + y * y + z * z), 1e-12f);
+        mu[k][0] = x / mn[k];
+        mu[k][1] = y / mn[k];
+        mu[k][2] = z / mn[k];
+        float kk = guide::softplus(o[5 * k + 4]) + 1e-3f;
+        clamped[k] = kk >= 1e4f;
+        kap[k] = fminf(kk, 1e4f);
+        cw[k] = mu[k][0] * wd.x + mu[k][1] * wd.y + mu[k][2] * wd.z;
+        lf[k] = lp + logf(kap[k]) - logf(2.0f * guide::kPiF * -expm1f(-2.0f * kap[k])) + kap[k] * (cw[k] - 1.0f);
+        lmax = fmaxf(lmax, lf[k]);
+    }
+    float sg = 0.0f, g[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        g[k] = expf(lf[k] - lmax);
+        sg += g[k];
+    }
+    loss = -w * (lmax + logf(sg));
+    float inv = 1.0f / sg;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        float gk = g[k] * inv;
+        d[5 * k] = -w * (gk - pi[k]);
+        float c = -w * gk * kap[k] / mn[k];
+        d[5 * k + 1] = c * (wd.x - cw[k] * mu[k][0]);
+        d[5 * k + 2] = c * (wd.y - cw[k] * mu[k][1]);
+        d[5 * k + 3] = c * (wd.z - cw[k] * mu[k][2]);
+        float dk = 1.0f / kap[k] - 2.0f / expm1f(fminf(2.0f * kap[k], 80.0f)) + cw[k] - 1.0f;
+        float sgm = 1.0f / (1.0f + expf(-o[5 * k + 4]));
+        d[5 * k + 4] = clamped[k] ? 0.0f : -w * gk * dk * sgm;
+    }
+}
+
+// staging of one wave's operands for the weight-gradient products
+struct Stage {
+    uint16_t z[32 * 64];  // BF16 pre-activation gradients [row][out]
+    uint16_t a[32 * 64];  // BF16 layer inputs [row][in]
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ v4s gather_col(const uint16_t *base, uint32_t col, uint32_t r0)
+{
+    v4s r;
+    r.x = (short)base[(r0 + 0) * 64 + col];
+    r.y = (short)base[(r0 + 1) * 64 + col];
+    r.z = (short)base[(r0 + 2) * 64 + col];
+    r.w = (short)base[(r0 + 3) * 64 + col];
+    return r;
+}
+
+// Backward through layer L for the wave's 32 rows: bias and weight gradients
+// into the block's LDS accumulator, and (L > 0) the pre-activation gradient
+// of layer L-1 in D layout.
+template <int L>
+__device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const uint2 *sfragT, uint32_t mask_prev,
+                                          float *sgrad, Stage &st, v16f *dz_prev)
+{
+    const uint32_t lane = lane_id(), half = lane >> 5, row = lane & 31;
+    constexpr int KS = kKS[L], N = kN[L];
+    // bias gradients from the FP32 values
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            int o = 32 * t + 8 * (v / 4) + 4 * half + (v % 4);
+            if (o < N) atomicAdd(&sgrad[kOffB[L] + o], dz[t][v]);
+        }
+    // stage BF16 operands [row][feature]
+    v4s zf[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        int t = s / 4, b = 4 * (s % 4);
+        zf[s] = pack4(dz[t][b], dz[t][b + 1], dz[t][b + 2], dz[t][b + 3]);
+        *(v4s *)&st.z[row * 64 + 8 * s + 4 * half] = zf[s];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s) *(v4s *)&st.a[row * 64 + 8 * s + 4 * half] = in[s];
+    wave_sync();
+    // dW^T[o][k] = sum_rows dZ^T[o][row] A[row][k]
+#pragma unroll
+    for (int to = 0; to < 2; ++to) {
+        if (to == 1 && N <= 32) continue;
+#pragma unroll
+        for (int tk = 0; tk < KS / 4; ++tk) {
+            v16f c = {};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                v4s A = gather_col(st.z, 32 * to + row, 8 * s + 4 * half);
+                v4s B = gather_col(st.a, 32 * tk + row, 8 * s + 4 * half);
+                c = mfma(A, B, c);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                int o = 32 * to + 8 * (v / 4) + 4 * half + (v % 4);
+                int k = 32 * tk + row;
+                if (o < N) atomicAdd(&sgrad[kOffW[L] + k * N + o], c[v]);
+            }
+        }
+    }
+    wave_sync();
+    if constexpr (L > 0) {
+        // dA^T[k][row] = sum_o W[k][o] dZ^T[o][row], then the ReLU mask of layer L-1
+#pragma unroll
+        for (int tk = 0; tk < 2; ++tk) {
+            v16f c = {};
+#pragma unroll
+            for (int s = 0; s < 8; ++s) c = mfma(as_v4s(sfragT[(kGB[L] + tk * 8 + s) * 64 + lane]), zf[s], c);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) c[v] = ((mask_prev >> (16 * tk + v)) & 1u) ? c[v] : 0.0f;
+            dz_prev[tk] = c;
+        }
+    }
+}
+
+// ------------------------------------------------------------- kernels
+
+// BF16 fragments and biases from the FP32 master parameters
+__global__ void k_guide_frag(GuideTrain T)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nf = kGuideFrags * 64, nt = kGuideFragsT * 64;
+    auto w_at = [&](int L, int k, int o) -> float { return o < kN[L] ? T.master[kOffW[L] + k * kN[L] + o] : 0.0f; };
+    auto pack2 = [](float a, float b) { return bf16_rne(a) | (bf16_rne(b) << 16); };
+    if (i < nf) {
+        uint32_t f = i / 64, lane = i % 64, half = lane / 32;
+        int L = f < 8 ? 0 : (f < 24 ? 1 : (f < 40 ? 2 : 3));
+        int r = f - kFB[L], t = r / kKS[L], s = r % kKS[L];
+        int k = 8 * s + 4 * half, o = 32 * t + lane % 32;
+        T.frag[i] = make_uint2(pack2(w_at(L, k, o), w_at(L, k + 1, o)), pack2(w_at(L, k + 2, o), w_at(L, k + 3, o)));
+    } else if (i < nf + nt) {
+        uint32_t j = i - nf, g = j / 64, lane = j % 64, half = lane / 32;
+        int L = 1 + g / 16;
+        int r = g % 16, tk = r / 8, s = r % 8;
+        int k = 32 * tk + lane % 32, o = 8 * s + 4 * half;
+        T.fragT[j] = make_uint2(pack2(w_at(L, k, o), w_at(L, k, o + 1)), pack2(w_at(L, k, o + 2), w_at(L, k, o + 3)));
+    } else if (i < nf + nt + 256) {
+        uint32_t j = i - nf - nt;
+        int L = j / 64, o = j % 64;
+        float b = o < kN[L] ? T.master[kOffB[L] + o] : 0.0f;
+        T.bias[j] = __uint_as_float(bf16_rne(b) << 16);
+    }
+}
+
+__device__ __forceinline__ void load_weights(const uint2 *frag, const float *bias, uint2 *sfrag, float *sbias)
+{
+    for (uint32_t i = threadIdx.x; i < kGuideFrags * 64; i += blockDim.x) sfrag[i] = frag[i];
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = bias[i];
+}
+
+// mixture of every extension-queue vertex at depth v that hits a scattering surface
+__global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
+{
+    __shared__ uint2 sfrag[kGuideFrags * 64];
+    __shared__ float sbias[256];
+    load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
+    __syncthreads();
+    const uint32_t n = P.counters[v];
+    const uint32_t *q = P.q_ext[v & 1];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t base = wave * 32; base < n; base += waves * 32) {
+        uint32_t i = base + (lane & 31);
+        bool valid = i < n;
+        float f[32];
+        for (int j = 0; j < 32; ++j) f[j] = 0.0f;
+        uint32_t slot = 0;
+        if (valid) {
+            slot = q[i];
+            float4 hv = P.hit[slot];
+            uint32_t tri = __float_as_uint(hv.y);
+            valid = tri != kNoHit;
+            if (valid) {
+                const Tri tr = F.tris[tri];
+                float4 d = P.ray_d[slot];
+                guide::V3 x = {tr.v0.x + ((tr.v1.x - tr.v0.x) * hv.z + (tr.v2.x - tr.v0.x) * hv.w),
+                               tr.v0.y + ((tr.v1.y - tr.v0.y) * hv.z + (tr.v2.y - tr.v0.y) * hv.w),
+                               tr.v0.z + ((tr.v1.z - tr.v0.z) * hv.z + (tr.v2.z - tr.v0.z) * hv.w)};
+                guide::encode(x, guide::V3{-d.x, -d.y, -d.z}, F.guide.bmin, F.guide.bext, f);
+            }
+        }
+        v4s a0[4];
+        input_frags(f, a0);
+        Act A;
+        v16f out[2];
+        mlp_forward(sfrag, sbias, a0, A, out);
+        float o[40];
+        gather40(out, o);
+        if (valid) {
+            guide::Mix m;
+            guide::decode(o, m);
+            float4 *dst = F.guide.mix + (size_t)slot * 10;
+            if (lane < 32) {
+                for (int k = 0; k < 5; ++k) dst[k] = m.lobe[k];
+            } else {
+                for (int k = 5; k < 8; ++k) dst[k] = m.lobe[k];
+                dst[8] = m.w0;
+                dst[9] = m.w1;
+            }
+        }
+    }
+}
+
+// training records -> candidates with a positive loss weight
+__global__ void k_rec_finalize(Frame F, Pool P, GuideTrain T)
+{
+    uint32_t cnt = min(*F.guide.rec_count, F.guide.rec_cap);
+    for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+        uint32_t i = base + threadIdx.x;
+        bool ok = false;
+        if (i < cnt) {
+            float4 *r = F.guide.rec + (size_t)i * kRecF4;
+            float4 r0 = r[0], r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5];
+            float4 L = P.rad[__float_as_uint(r2.w)];
+            float li[3] = {(L.x - r3.x - r5.x), (L.y - r3.y - r5.y), (L.z - r3.z - r5.z)};
+            float ta[3] = {r4.x, r4.y, r4.z};
+            float lum = 0.0f;
+            const float wl[3] = {0.2126f, 0.7152f, 0.0722f};
+            for (int c = 0; c < 3; ++c) lum += ta[c] > 0.0f ? wl[c] * fmaxf(0.0f, li[c] / ta[c]) : 0.0f;
+            r[1].w = lum;
+            float w = lum / r0.w;
+            ok = w > 0.0f && w < INFINITY;
+        }
+        unsigned long long mask = __ballot(ok);
+        uint32_t b = 0;
+        if (mask) {
+            uint32_t leader = __ffsll((long long)mask) - 1;
+            if (lane_id() == leader) b = atomicAdd(T.cand_count, (uint32_t)__popcll(mask));
+            b = __shfl(b, (int)leader);
+        }
+        uint32_t off = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        if (ok) T.cand[b + off] = i;
+    }
+}
+
+struct RowSrc {
+    // records (debug == false) or explicit arrays (debug == true)
+    bool debug;
+    const float *x, *dirs, *w;  // debug: n x 32 features, n x 3, n
+    uint32_t n;                  // debug: rows; records: the batch size
+    const uint32_t *count;       // records: candidates available (device)
+    float u;                     // stratification offset in [0, 1)
+};
+
+__global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain T, RowSrc src)
+{
+    extern __shared__ unsigned char smem[];
+    uint2 *sfrag = (uint2 *)smem;
+    uint2 *sfragT = sfrag + kGuideFrags * 64;
+    float *sbias = (float *)(sfragT + kGuideFragsT * 64);
+    float *sgrad = sbias + 256;
+    Stage *stage = (Stage *)(sgrad + ((kGuideParams + 63) / 64) * 64);
+    for (uint32_t i = threadIdx.x; i < kGuideFrags * 64; i += blockDim.x) sfrag[i] = T.frag[i];
+    for (uint32_t i = threadIdx.x; i < kGuideFragsT * 64; i += blockDim.x) sfragT[i] = T.fragT[i];
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = T.bias[i];
+    for (uint32_t i = threadIdx.x; i < kGuideParams; i += blockDim.x) sgrad[i] = 0.0f;
+    __syncthreads();
+    const uint32_t lane = lane_id(), wv = threadIdx.x / 64;
+    Stage &st = stage[wv];
+    const uint32_t wave = blockIdx.x * (kTrainBlock / 64) + wv, waves = gridDim.x * (kTrainBlock / 64);
+    // records: a batch of min(batch, candidates) rows, a stratified subset
+    const uint32_t count = src.debug ? src.n : *src.count;
+    const uint32_t nrows = min(src.n, count);
+    const uint32_t tiles = (nrows + 31) / 32;
+    float wsum = 0.0f, lsum = 0.0f;
+    for (uint32_t tile = wave; tile < tiles; tile += waves) {
+        uint32_t row = tile * 32 + (lane & 31);
+        bool valid = row < nrows;
+        float f[32];
+        guide::V3 wd = {0.0f, 0.0f, 1.0f};
+        float wt = 0.0f;
+        for (int j = 0; j < 32; ++j) f[j] = 0.0f;
+        if (valid) {
+            if (src.debug) {
+                for (int j = 0; j < 32; ++j) f[j] = src.x[(size_t)row * 32 + j];
+                wd = {src.dirs[3 * (size_t)row], src.dirs[3 * (size_t)row + 1], src.dirs[3 * (size_t)row + 2]};
+                wt = src.w[row];
+            } else {
+                // stratified subset of the candidates
+                uint32_t c = (uint32_t)(((double)row + src.u) * (double)count / (double)nrows);
+                c = min(c, count - 1);
+                const float4 *r = F.guide.rec + (size_t)T.cand[c] * kRecF4;
+                float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                guide::encode(guide::V3{r0.x, r0.y, r0.z}, guide::V3{r1.x, r1.y, r1.z}, F.guide.bmin, F.guide.bext, f);
+                wd = {r2.x, r2.y, r2.z};
+                wt = r1.w / r0.w;
+            }
+        }
+        v4s a0[4];
+        input_frags(f, a0);
+        Act A;
+        v16f out[2];
+        mlp_forward(sfrag, sbias, a0, A, out);
+        float o[40], d[40], lv;
+        gather40(out, o);
+        row_loss_grad(o, wd, wt, d, lv);
+        if (valid && lane < 32) {
+            wsum += wt;
+            lsum += lv;
+        }
+        v16f dz[2], dzp[2];
+        scatter40(d, dz);
+        layer_bwd<3>(dz, A.a3, sfragT, A.m2, sgrad, st, dzp);
+        layer_bwd<2>(dzp, A.a2, sfragT, A.m1, sgrad, st, dz);
+        layer_bwd<1>(dz, A.a1, sfragT, A.m0, sgrad, st, dzp);
+        layer_bwd<0>(dzp, a0, sfragT, 0u, sgrad, st, dz);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        wsum += __shfl_xor(wsum, off);
+        lsum += __shfl_xor(lsum, off);
+    }
+    if (lane == 0) {
+        atomicAdd(&T.scalars[0], wsum);
+        atomicAdd(&T.scalars[1], lsum);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kGuideParams; i += blockDim.x)
+        T.partial[(size_t)blockIdx.x * kGuideParams + i] = sgrad[i];
+}
+
+// sum the block partials, normalise by the weight sum; then Adam or a plain copy
+__global__ void k_guide_reduce(GuideTrain T, uint32_t blocks, int adam, uint32_t step, float lr, float *grad_out)
+{
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kGuideParams) return;
+    float ws = T.scalars[0];
+    float g = 0.0f;
+    for (uint32_t b = 0; b < blocks; ++b) g += T.partial[(size_t)b * kGuideParams + p];
+    g = ws > 0.0f ? g / ws : 0.0f;
+    if (grad_out) grad_out[p] = g;
+    if (!adam || !(ws > 0.0f)) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float m = b1 * T.m[p] + (1.0f - b1) * g;
+    float v = b2 * T.v[p] + (1.0f - b2) * g * g;
+    T.m[p] = m;
+    T.v[p] = v;
+    float mh = m / (1.0f - powf(b1, (float)step));
+    float vh = v / (1.0f - powf(b2, (float)step));
+    T.master[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_fill0(float *p, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ void k_fill_u32_1(uint32_t *p) { *p = 0u; }
+
+// forward on given features (parity hook)
+__global__ __launch_bounds__(256) void k_guide_fwd_debug(Frame F, const float *x, uint32_t n, float *out)
+{
+    __shared__ uint2 sfrag[kGuideFrags * 64];
+    __shared__ float sbias[256];
+    load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t base = wave * 32; base < n; base += waves * 32) {
+        uint32_t row = base + (lane & 31);
+        float f[32];
+        for (int j = 0; j < 32; ++j) f[j] = row < n ? x[(size_t)row * 32 + j] : 0.0f;
+        v4s a0[4];
+        input_frags(f, a0);
+        Act A;
+        v16f o2[2];
+        mlp_forward(sfrag, sbias, a0, A, o2);
+        float o[40];
+        gather40(o2, o);
+        if (row < n)
+            for (int j = 0; j < 20; ++j) out[(size_t)row * 40 + 20 * (lane >> 5) + j] = o[20 * (lane >> 5) + j];
+    }
+}
+
+// decode, pdf at given directions and samples from given numbers (parity hook)
+__global__ void k_guide_mix_debug(const float *out40, const float *dirs, const float *u, uint32_t n, float *pdf,
+                                  float *sample)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    guide::Mix m;
+    guide::decode(out40 + (size_t)i * 40, m);
+    guide::V3 w = {dirs[3 * (size_t)i], dirs[3 * (size_t)i + 1], dirs[3 * (size_t)i + 2]};
+    pdf[i] = guide::mixture_pdf(m, w);
+    guide::V3 s = guide::mixture_sample(m, u[3 * (size_t)i], u[3 * (size_t)i + 1], u[3 * (size_t)i + 2]);
+    sample[3 * (size_t)i] = s.x;
+    sample[3 * (size_t)i + 1] = s.y;
+    sample[3 * (size_t)i + 2] = s.z;
+}
+
+size_t train_smem()
+{
+    return kGuideFrags * 64 * 8 + kGuideFragsT * 64 * 8 + 256 * 4 + ((kGuideParams + 63) / 64) * 64 * 4 +
+           4 * sizeof(Stage);
+}
+
+inline uint32_t nblocks(size_t n, uint32_t bs, uint32_t cap)
+{
+    size_t b = (n + bs - 1) / bs;
+    return (uint32_t)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s)
+{
+    uint32_t n = (kGuideFrags + kGuideFragsT) * 64 + 256;
+    hipLaunchKernelGGL(k_guide_frag, dim3(nblocks(n, 256, 1u << 20)), dim3(256), 0, s, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_guide_eval, dim3(grid), dim3(256), 0, s, f, pool, v);
+    return hipGetLastError();
+}
+
+static hipError_t run_train(const Frame &f, const GuideTrain &T, const RowSrc &src, hipStream_t s, uint32_t *blocks_out)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_guide_train, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)train_smem());
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    uint32_t blocks = nblocks(((size_t)src.n + 31) / 32, kTrainBlock / 64, T.max_blocks);
+    hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, s, T.scalars, 2u);
+    hipLaunchKernelGGL(k_guide_train, dim3(blocks), dim3(kTrainBlock), train_smem(), s, f, T, src);
+    *blocks_out = blocks;
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const GuideTrain &T, uint32_t batch,
+                                   uint32_t step, float lr, uint32_t seed, hipStream_t s, Profiler *prof)
+{
+    if (prof) prof->begin(K_GUIDE_TRAIN, s);
+    hipLaunchKernelGGL(k_fill_u32_1, dim3(1), dim3(1), 0, s, T.cand_count);
+    hipLaunchKernelGGL(k_rec_finalize, dim3(nblocks(f.guide.rec_cap, 256, 4096)), dim3(256), 0, s, f, pool, T);
+    // stratification offset from the step and seed (splitmix64 finaliser)
+    uint64_t z = ((uint64_t)seed << 32) + step + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    RowSrc src{false, nullptr, nullptr, nullptr, batch, T.cand_count, (float)((z >> 40) * 0x1p-24)};
+    uint32_t blocks = 0;
+    hipError_t e = run_train(f, T, src, s, &blocks);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_guide_reduce, dim3(nblocks(kGuideParams, 256, 1024)), dim3(256), 0, s, T, blocks, 1, step,
+                       lr, (float *)nullptr);
+    e = launch_guide_frag(T, s);
+    if (prof) prof->end(K_GUIDE_TRAIN, s);
+    return e;
+}
+
+hipError_t launch_guide_debug_forward(const Frame &f, const float *x, uint32_t n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_guide_fwd_debug, dim3(nblocks(((size_t)n + 31) / 32, 4, 2048)), dim3(256), 0, s, f, x, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const float *x, const float *dirs,
+                                   const float *w, uint32_t n, float *grad, int adam, uint32_t step, float lr,
+                                   hipStream_t s)
+{
+    RowSrc src{true, x, dirs, w, n, nullptr, 0.0f};
+    uint32_t blocks = 0;
+    hipError_t e = run_train(f, T, src, s, &blocks);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_guide_reduce, dim3(nblocks(kGuideParams, 256, 1024)), dim3(256), 0, s, T, blocks, adam,
+                       step, lr, grad);
+    if (adam) return launch_guide_frag(T, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_debug_mixture(const float *out40, const float *dirs, const float *u, uint32_t n, float *pdf,
+                                      float *sample, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_guide_mix_debug, dim3(nblocks(n, 256, 1u << 20)), dim3(256), 0, s, out40, dirs, u, n, pdf,
+                       sample);
+    return hipGetLastError();
+}
+
+}  // namespace qpt

@@ -1,0 +1,122 @@
+// Device-side pieces of the learned proposal shared by the shading kernel and
+// the network kernels: the 8-lobe von Mises-Fisher mixture (decode, pdf,
+// sampling) and the input encoding. FP32 throughout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "qpt_internal.h"
+
+namespace qpt {
+namespace guide {
+
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr int kLobes = 8;
+
+struct V3 {
+    float x, y, z;
+};
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// the decoded mixture as stored per path slot: lobe k = (mu.xyz, kappa), then
+// the 8 weights in two float4
+struct Mix {
+    float4 lobe[kLobes];
+    float4 w0, w1;
+};
+
+__device__ __forceinline__ float weight(const Mix &m, int k)
+{
+    const float4 &w = k < 4 ? m.w0 : m.w1;
+    int j = k & 3;
+    return j == 0 ? w.x : (j == 1 ? w.y : (j == 2 ? w.z : w.w));
+}
+
+__device__ __forceinline__ float softplus(float r) { return r > 20.0f ? r : log1pf(expf(r)); }
+
+// outputs 5k..5k+4 of lobe k: logit, mu_raw xyz, kappa_raw
+__device__ inline void decode(const float *o, Mix &m)
+{
+    float mx = o[0];
+    for (int k = 1; k < kLobes; ++k) mx = fmaxf(mx, o[5 * k]);
+    float e[kLobes], sum = 0.0f;
+    for (int k = 0; k < kLobes; ++k) {
+        e[k] = expf(o[5 * k] - mx);
+        sum += e[k];
+    }
+    float inv = 1.0f / sum;
+    m.w0 = make_float4(e[0] * inv, e[1] * inv, e[2] * inv, e[3] * inv);
+    m.w1 = make_float4(e[4] * inv, e[5] * inv, e[6] * inv, e[7] * inv);
+    for (int k = 0; k < kLobes; ++k) {
+        float x = o[5 * k + 1], y = o[5 * k + 2], z = o[5 * k + 3];
+        float n = fmaxf(sqrtf(x * x + y * y + z * z), 1e-12f);
+        float kap = fminf(softplus(o[5 * k + 4]) + 1e-3f, 1e4f);
+        m.lobe[k] = make_float4(x / n, y / n, z / n, kap);
+    }
+}
+
+// vMF density on the unit sphere
+__device__ __forceinline__ float vmf_pdf(float4 l, V3 w)
+{
+    float c = l.x * w.x + l.y * w.y + l.z * w.z;
+    return l.w / (2.0f * kPiF * -expm1f(-2.0f * l.w)) * expf(l.w * (c - 1.0f));
+}
+
+__device__ __forceinline__ float mixture_pdf(const Mix &m, V3 w)
+{
+    float q = 0.0f;
+    for (int k = 0; k < kLobes; ++k) q += weight(m, k) * vmf_pdf(m.lobe[k], w);
+    return q;
+}
+
+// lobe: first k with u < cumulative weight; direction by stable vMF sampling
+// (Jakob 2012) in a Duff et al. 2017 frame around mu
+__device__ inline V3 mixture_sample(const Mix &m, float u_lobe, float u1, float u2)
+{
+    int k = kLobes - 1;
+    float c = 0.0f;
+    for (int j = 0; j < kLobes - 1; ++j) {
+        c += weight(m, j);
+        if (u_lobe < c) {
+            k = j;
+            break;
+        }
+    }
+    float4 l = m.lobe[k];
+    float w = 1.0f + logf(u1 + (1.0f - u1) * expf(-2.0f * l.w)) / l.w;
+    w = fminf(1.0f, fmaxf(-1.0f, w));
+    float s = copysignf(1.0f, l.z);
+    float a = -1.0f / (s + l.z);
+    float b = l.x * l.y * a;
+    V3 t1 = {1.0f + s * l.x * l.x * a, s * b, -s * l.x};
+    V3 t2 = {b, s + l.y * l.y * a, -l.y};
+    float r = sqrtf(fmaxf(0.0f, 1.0f - w * w));
+    float sp, cp;
+    sincosf(2.0f * kPiF * u2, &sp, &cp);
+    return {w * l.x + r * (cp * t1.x + sp * t2.x), w * l.y + r * (cp * t1.y + sp * t2.y),
+            w * l.z + r * (cp * t1.z + sp * t2.z)};
+}
+
+// the 32 input features: sin/cos of 2^o pi x_hat per axis and octave, then
+// sin/cos of pi th, 2 pi th, 2 pi ph, 4 pi ph of the outgoing direction
+// (th = polar angle from +y over pi, ph = atan2(x, -z) over 2 pi in [0, 1))
+__device__ inline void encode(V3 x, V3 wo, const float *bmin, const float *bext, float *f)
+{
+    float xh[3] = {(x.x - bmin[0]) / bext[0], (x.y - bmin[1]) / bext[1], (x.z - bmin[2]) / bext[2]};
+    for (int a = 0; a < 3; ++a)
+        for (int o = 0; o < 4; ++o) {
+            float s, c;
+            sincosf((float)(1 << o) * kPiF * xh[a], &s, &c);
+            f[8 * a + 2 * o] = s;
+            f[8 * a + 2 * o + 1] = c;
+        }
+    float th = acosf(fminf(1.0f, fmaxf(-1.0f, wo.y))) / kPiF;
+    float ph = atan2f(wo.x, -wo.z);
+    if (ph < 0.0f) ph += 2.0f * kPiF;
+    ph *= 1.0f / (2.0f * kPiF);
+    float ang[4] = {kPiF * th, 2.0f * kPiF * th, 2.0f * kPiF * ph, 4.0f * kPiF * ph};
+    for (int j = 0; j < 4; ++j) sincosf(ang[j], &f[24 + 2 * j], &f[25 + 2 * j]);
+}
+
+}  // namespace guide
+}  // namespace qpt

@@ -269,6 +269,7 @@ struct Layout {
         env_col, env_cos, bases;
     size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats, gstack;
     size_t fb_sum, fb_count;
+    size_t g_frag, g_fragT, g_bias, g_mix, g_rec, g_master, g_m, g_v, g_cand, g_cand_count, g_partial, g_scalars;
     size_t total;
 };
 
@@ -320,6 +321,12 @@ struct EventProfiler : qpt::Profiler {
 struct qpt_ctx {
     int device = -1;
     uint32_t trav_threads = 0;  // traversal grid: CUs x resident blocks per CU x block size
+    uint32_t guide_blocks = 256;  // training blocks (one per CU)
+    GuideTrain gt{};
+    qpt_guide_opts gopts{0.0f, 1e-3f, 1u << 18, 0, 1, 0};
+    bool guide_weights = false;
+    uint32_t guide_steps = 0;
+    double bbox[6] = {0, 0, 0, 1, 1, 1};
     EventProfiler prof;
     bool profiling = false;
     hipStream_t stream = nullptr;
@@ -634,6 +641,20 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
+    // learned proposal: weights, per-slot mixtures, training records and state
+    size_t rec_cap = std::min<size_t>((size_t)1 << 22, (size_t)cap * 2);
+    L.g_frag = take(kGuideFrags * 64 * 8);
+    L.g_fragT = take(kGuideFragsT * 64 * 8);
+    L.g_bias = take(256 * 4);
+    L.g_mix = take((size_t)cap * 10 * 16);
+    L.g_rec = take(rec_cap * kRecF4 * 16);
+    L.g_master = take(kGuideParams * 4);
+    L.g_m = take(kGuideParams * 4);
+    L.g_v = take(kGuideParams * 4);
+    L.g_cand = take(rec_cap * 4);
+    L.g_cand_count = take(4);
+    L.g_partial = take((size_t)c->guide_blocks * kGuideParams * 4);
+    L.g_scalars = take(2 * 4);
     L.total = o;
     return L;
 }
@@ -665,6 +686,7 @@ int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
             return QPT_E_UNSUPPORTED;
         }
         c->trav_threads = (uint32_t)prop.multiProcessorCount * kTravBlocksPerCU * kBlock;
+        c->guide_blocks = (uint32_t)prop.multiProcessorCount;
     }
     *out = c;
     return QPT_OK;
@@ -726,6 +748,18 @@ int qpt_build_scene(qpt_ctx *c, const qpt_scene_desc *d)
         // a scene without light renders black; still valid
     }
     set_frame_constants(c);
+    // scene box for the guide's position encoding
+    for (int a = 0; a < 3; ++a) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (uint64_t q = 0; q < d->num_vertices; ++q) {
+            lo = std::min(lo, (double)d->positions[3 * q + a]);
+            hi = std::max(hi, (double)d->positions[3 * q + a]);
+        }
+        c->bbox[a] = lo;
+        c->bbox[3 + a] = std::max(hi - lo, 1e-6);
+    }
+    c->guide_weights = false;
+    c->guide_steps = 0;
     c->gmats.resize(c->mats.size());
     for (size_t m = 0; m < c->mats.size(); ++m) {
         const qpt_material &mm = c->mats[m];
@@ -956,6 +990,35 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     p.stats = (unsigned long long *)(w + L.stats);
     p.fb_sum = (double *)(w + L.fb_sum);
     p.fb_count = (uint32_t *)(w + L.fb_count);
+    GuideTrain &T = c->gt;
+    T.master = (float *)(w + L.g_master);
+    T.m = (float *)(w + L.g_m);
+    T.v = (float *)(w + L.g_v);
+    T.frag = (uint2 *)(w + L.g_frag);
+    T.fragT = (uint2 *)(w + L.g_fragT);
+    T.bias = (float *)(w + L.g_bias);
+    T.cand = (uint32_t *)(w + L.g_cand);
+    T.cand_count = (uint32_t *)(w + L.g_cand_count);
+    T.partial = (float *)(w + L.g_partial);
+    T.scalars = (float *)(w + L.g_scalars);
+    T.max_blocks = c->guide_blocks;
+    GuideDev &G = f.guide;
+    G.frag = T.frag;
+    G.fragT = T.fragT;
+    G.bias = T.bias;
+    G.mix = (float4 *)(w + L.g_mix);
+    for (int a = 0; a < 3; ++a) {
+        G.bmin[a] = (float)c->bbox[a];
+        G.bext[a] = (float)c->bbox[3 + a];
+    }
+    G.alpha_thr = 0;
+    G.alpha = 0.0f;
+    G.record = 0;
+    G.rec = (float4 *)(w + L.g_rec);
+    G.rec_cap = (uint32_t)std::min<size_t>((size_t)1 << 22, (size_t)cap * 2);
+    G.rec_count = p.counters + 127;
+    c->guide_weights = false;
+    c->guide_steps = 0;
     c->bound = true;
     int rc = qpt_reset_accum(c);
     if (rc) {
@@ -988,26 +1051,46 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     // the largest Halton index must fit 64 bits
     u128 last = (u128)(first_pass + num_passes) * c->frame.S;
     if (last >> 64) return fail(c, QPT_E_INVALID, "pass range overflows 64-bit sample indices");
+    const bool guiding = c->gopts.alpha > 0.0f || c->gopts.train;
+    if (guiding && !c->guide_weights)
+        return fail(c, QPT_E_STATE, "guide enabled before qpt_guide_set_weights");
     DeviceGuard g(c->device);
     Frame f = c->frame;
     f.max_depth = o->max_depth;
     f.rr = o->rr;
     f.mode = o->mode;
     f.scramble = o->scramble;
+    Profiler *prof = c->profiling ? &c->prof : nullptr;
+    // one batch of passes (or of pixels), then one training step if enabled
+    auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
+        bool active = c->gopts.alpha > 0.0f && c->guide_steps >= c->gopts.warmup_steps;
+        uint64_t thr = active ? (uint64_t)std::llround((double)c->gopts.alpha * 4294967296.0) : 0;
+        f.guide.alpha_thr = (uint32_t)std::min<uint64_t>(thr, 0xffffffffull);
+        f.guide.alpha = (float)((double)f.guide.alpha_thr / 4294967296.0);
+        f.guide.record = c->gopts.train ? 1u : 0u;
+        HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
+        if (c->gopts.train) {
+            ++c->guide_steps;
+            HIP_TRY(c, launch_guide_train_step(f, c->pool, c->gt, c->gopts.batch ? c->gopts.batch : (1u << 18),
+                                               c->guide_steps, c->gopts.lr, c->gopts.seed, c->stream, prof));
+        }
+        return QPT_OK;
+    };
     uint32_t npix = c->W * c->H, cap = c->pool_cap;
     if (npix <= cap) {
         uint32_t per = std::max(1u, cap / npix);
         for (uint32_t done = 0; done < num_passes;) {
             uint32_t nb = std::min(per, num_passes - done);
-            HIP_TRY(c, launch_render_batch(f, c->pool, 0, npix, first_pass + done, nb, c->stream,
-                                           c->profiling ? &c->prof : nullptr));
+            int rc = batch(0, npix, first_pass + done, nb);
+            if (rc) return rc;
             done += nb;
         }
     } else {
         for (uint32_t j = 0; j < num_passes; ++j)
-            for (uint32_t p0 = 0; p0 < npix; p0 += cap)
-                HIP_TRY(c, launch_render_batch(f, c->pool, p0, std::min(cap, npix - p0), first_pass + j, 1,
-                                               c->stream, c->profiling ? &c->prof : nullptr));
+            for (uint32_t p0 = 0; p0 < npix; p0 += cap) {
+                int rc = batch(p0, std::min(cap, npix - p0), first_pass + j, 1);
+                if (rc) return rc;
+            }
     }
     return QPT_OK;
 }
@@ -1105,6 +1188,98 @@ int qpt_debug_trace(qpt_ctx *c, const float *rays, uint32_t n, int any_hit, int 
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
     HIP_TRY(c, launch_debug_trace(c->frame, c->pool, rays, n, any_hit, brute_force, t, tri, b12, c->stream));
+    return QPT_OK;
+}
+
+int qpt_guide_config(qpt_ctx *c, const qpt_guide_opts *o)
+{
+    if (!c || !o) return QPT_E_INVALID;
+    if (!(o->alpha >= 0.0f && o->alpha < 1.0f) || !(o->lr > 0.0f) || o->batch > (1u << 22))
+        return fail(c, QPT_E_INVALID, "guide options out of range (alpha in [0, 1), lr > 0, batch <= 2^22)");
+    c->gopts = *o;
+    return QPT_OK;
+}
+
+int qpt_guide_set_weights(qpt_ctx *c, const float *params)
+{
+    if (!c || !params) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "guide weights before bind_workspace");
+    for (uint32_t p = 0; p < kGuideParams; ++p)
+        if (!std::isfinite(params[p])) return fail(c, QPT_E_INVALID, "non-finite guide parameter");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipMemcpyAsync(c->gt.master, params, kGuideParams * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->gt.m, 0, kGuideParams * 4, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->gt.v, 0, kGuideParams * 4, c->stream));
+    HIP_TRY(c, launch_guide_frag(c->gt, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->guide_weights = true;
+    c->guide_steps = 0;
+    return QPT_OK;
+}
+
+int qpt_guide_get_weights(qpt_ctx *c, float *params, uint32_t *steps)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
+    DeviceGuard g(c->device);
+    if (params) HIP_TRY(c, hipMemcpyAsync(params, c->gt.master, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (steps) *steps = c->guide_steps;
+    return QPT_OK;
+}
+
+int qpt_guide_debug_forward(qpt_ctx *c, const float *x, uint32_t n, float *out)
+{
+    if (!c || (n && (!x || !out))) return QPT_E_INVALID;
+    if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    Frame f = c->frame;
+    HIP_TRY(c, launch_guide_debug_forward(f, x, n, out, c->stream));
+    return QPT_OK;
+}
+
+int qpt_guide_debug_grad(qpt_ctx *c, const float *x, const float *dirs, const float *w, uint32_t n, float *grad)
+{
+    if (!c || !n || !x || !dirs || !w || !grad) return QPT_E_INVALID;
+    if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 0, 0u, 0.0f, c->stream));
+    return QPT_OK;
+}
+
+int qpt_guide_debug_train(qpt_ctx *c, const float *x, const float *dirs, const float *w, uint32_t n, float lr,
+                          float *grad)
+{
+    if (!c || !n || !x || !dirs || !w || !(lr > 0.0f)) return QPT_E_INVALID;
+    if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
+    DeviceGuard g(c->device);
+    ++c->guide_steps;
+    HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 1, c->guide_steps, lr, c->stream));
+    return QPT_OK;
+}
+
+int qpt_guide_loss(qpt_ctx *c, double *loss, double *weight_sum)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    DeviceGuard g(c->device);
+    float sc[2];
+    HIP_TRY(c, hipMemcpyAsync(sc, c->gt.scalars, sizeof sc, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (loss) *loss = sc[0] > 0.0f ? (double)sc[1] / (double)sc[0] : 0.0;
+    if (weight_sum) *weight_sum = sc[0];
+    return QPT_OK;
+}
+
+int qpt_guide_debug_mixture(qpt_ctx *c, const float *out40, const float *dirs, const float *u, uint32_t n,
+                            float *pdf, float *sample)
+{
+    if (!c || (n && (!out40 || !dirs || !u || !pdf || !sample))) return QPT_E_INVALID;
+    if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_guide_debug_mixture(out40, dirs, u, n, pdf, sample, c->stream));
     return QPT_OK;
 }
 

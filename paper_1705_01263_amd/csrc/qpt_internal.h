@@ -48,6 +48,26 @@ struct alignas(16) Material {
     float4 emission_flags;  // Le.rgb, flags (bits)
 };
 
+// The learned proposal's device state (a 32-64-64-64-40 network).
+constexpr uint32_t kGuideParams = 13032;
+constexpr uint32_t kGuideFrags = 56;    // forward weight fragments (64 lanes x 4 bf16 each)
+constexpr uint32_t kGuideFragsT = 48;   // transposed fragments for the backward pass
+constexpr uint32_t kRecF4 = 6;          // float4 per training record
+
+struct GuideDev {
+    const uint2 *frag;       // kGuideFrags * 64: 4 bf16 per lane (MFMA A operands)
+    const uint2 *fragT;      // kGuideFragsT * 64
+    const float *bias;       // 4 x 64 (BF16-rounded values, layer 3 zero-padded)
+    float4 *mix;             // per path slot: 8 lobes (mu.xyz, kappa), 8 weights
+    float bmin[3], bext[3];  // scene box for the position encoding
+    uint32_t alpha_thr;      // guide iff sample bits < alpha_thr (0: BSDF sampling only)
+    float alpha;             // alpha_thr / 2^32
+    uint32_t record;         // capture training records
+    float4 *rec;             // kRecF4 float4 per record
+    uint32_t rec_cap;
+    uint32_t *rec_count;
+};
+
 struct Camera {
     float eye[3], fwd[3], right[3], up[3];
     float tan_half, aspect;
@@ -79,6 +99,8 @@ struct Frame {
     uint64_t S;                           // 2^k 3^l
     uint64_t p3, m_p3;                    // 3^l and its 64-bit magic
     uint32_t sh_p3, inv2k_mod_p3;         // (2^k)^-1 mod 3^l
+    // learned proposal
+    GuideDev guide;
     // camera and frame
     Camera cam;
     uint32_t W, H;
@@ -111,7 +133,8 @@ struct Pool {
 };
 
 // kernel kinds timed by the optional profiler
-enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMULATE, K_KINDS };
+enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMULATE, K_GUIDE_EVAL, K_GUIDE_TRAIN,
+                  K_KINDS };
 
 // brackets every kernel launch of a batch with stream events when set
 struct Profiler {
@@ -120,11 +143,35 @@ struct Profiler {
     virtual ~Profiler() {}
 };
 
+// training state of the learned proposal (all device pointers)
+struct GuideTrain {
+    float *master, *m, *v;   // kGuideParams each, FP32
+    uint2 *frag, *fragT;     // written from master after every step
+    float *bias;             // 256
+    uint32_t *cand;          // candidate record indices (weight > 0)
+    uint32_t *cand_count;
+    float *partial;          // blocks x kGuideParams unnormalised gradient sums
+    float *scalars;          // [0] sum of loss weights [1] weighted loss sum
+    uint32_t max_blocks;
+};
+
 // kernel launchers (qpt_kernels.hip)
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
                                uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
+// guide launchers (qpt_guide.hip)
+hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s);
+hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s);
+hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const GuideTrain &T, uint32_t batch,
+                                   uint32_t step, float lr, uint32_t seed, hipStream_t s, Profiler *prof);
+hipError_t launch_guide_debug_forward(const Frame &f, const float *x, uint32_t n, float *out, hipStream_t s);
+hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const float *x, const float *dirs,
+                                   const float *w, uint32_t n, float *grad, int adam, uint32_t step, float lr,
+                                   hipStream_t s);
+hipError_t launch_guide_debug_mixture(const float *out40, const float *dirs, const float *u, uint32_t n,
+                                      float *pdf, float *sample, hipStream_t s);
+
 hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
                                     uint32_t n, int scramble, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);

@@ -11,6 +11,7 @@
 // sample counts (Appendix A.4).
 #include <hip/hip_runtime.h>
 
+#include "qpt_guide_dev.h"
 #include "qpt_internal.h"
 
 namespace qpt {
@@ -574,6 +575,8 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
             float4 c = P.sh_c[i];
             float4 L = P.rad[slot];
             P.rad[slot] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
+            uint32_t rec = fbits(c.w);
+            if (rec != kNoHit) F.guide.rec[(size_t)rec * kRecF4 + 5] = make_float4(c.x, c.y, c.z, 0.0f);
         }
     }
     wave_count(&P.stats[6], nodes);
@@ -590,9 +593,10 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t i = base + threadIdx.x;
         bool active = i < n;
-        bool alive = false, shadow = false;
+        bool alive = false, shadow = false, record = false;
         uint32_t slot = 0;
         float4 sh_o = {}, sh_d = {}, sh_c = {};
+        float4 rec0 = {}, rec1 = {}, rec2 = {}, rec3 = {}, rec4 = {};
         if (active) {
             slot = q[i];
             float4 hv = P.hit[slot];
@@ -634,6 +638,16 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                     f3 wo = d * -1.0f;
                     f3 xo = offset_ray(x, nn);
                     uint64_t idx = P.idx[slot];
+                    // learned proposal: this vertex's mixture (alpha = 0 leaves plain BSDF sampling)
+                    const bool guided = F.guide.alpha_thr != 0u;
+                    guide::Mix mix;
+                    if (guided) {
+                        const float4 *src = F.guide.mix + (size_t)slot * 10;
+                        for (int k = 0; k < guide::kLobes; ++k) mix.lobe[k] = src[k];
+                        mix.w0 = src[8];
+                        mix.w1 = src[9];
+                    }
+                    const float alpha = F.guide.alpha;
                     // next-event estimation
                     if (F.mode != 1 && (F.num_emit || F.env_w)) {
                         uint32_t s0 = sample_bits(F, idx, base_dim + 0, F.scramble);
@@ -700,6 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                                 f3 fb;
                                 float pb;
                                 bsdf_eval(m, nn, wo, wi, fb, pb);
+                                if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
                                 float w = F.mode == 2 ? 1.0f : mis2(pl, pb);
                                 f3 contrib = T * fb * Le * (ci * w / pl);
                                 if (maxc(contrib) > 0.0f) {
@@ -711,15 +726,35 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                             }
                         }
                     }
-                    // continue by sampling the BSDF
-                    float u3 = u24(sample_bits(F, idx, base_dim + 3, F.scramble));
+                    // continue the path: slot 3 picks guide or BSDF (guide iff the 32-bit
+                    // sample < alpha 2^32) and, rescaled to [0, 2^32), the lobe; slots 4-5
+                    // the direction. The density is the one-sample mixture
+                    // alpha q + (1 - alpha) p_bsdf, so the estimator stays unbiased.
+                    uint32_t s3 = sample_bits(F, idx, base_dim + 3, F.scramble);
+                    bool use_guide = s3 < F.guide.alpha_thr;
+                    uint32_t r3 = s3;
+                    if (guided) {
+                        uint64_t lo = use_guide ? 0ull : F.guide.alpha_thr;
+                        uint64_t range = use_guide ? F.guide.alpha_thr : (1ull << 32) - F.guide.alpha_thr;
+                        r3 = (uint32_t)((((uint64_t)s3 - lo) << 32) / range);
+                    }
+                    float u3 = u24(r3);
                     float u4 = u24(sample_bits(F, idx, base_dim + 4, F.scramble));
                     float u5 = u24(sample_bits(F, idx, base_dim + 5, F.scramble));
                     f3 wi;
-                    if (bsdf_sample(m, nn, wo, u3, u4, u5, wi)) {
+                    bool ok;
+                    if (use_guide) {
+                        guide::V3 g = guide::mixture_sample(mix, u3, u4, u5);
+                        wi = mk(g.x, g.y, g.z);
+                        ok = dot(nn, wi) > 0.0f;
+                    } else {
+                        ok = bsdf_sample(m, nn, wo, u3, u4, u5, wi);
+                    }
+                    if (ok) {
                         f3 fb;
                         float pb;
                         bsdf_eval(m, nn, wo, wi, fb, pb);
+                        if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
                         if (pb > 0.0f) {
                             T = T * fb * (dot(nn, wi) / pb);
                             if (maxc(T) > 0.0f) {
@@ -735,6 +770,16 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                                     P.ray_o[slot] = f4(xo, INFINITY);
                                     P.ray_d[slot] = f4(wi, 0.0f);
                                     P.thr[slot] = f4(T, pb);
+                                    if (F.guide.record) {
+                                        // training record: the radiance later arriving along wi
+                                        // is (final - now - this vertex's NEE) / T_after
+                                        record = true;
+                                        rec0 = f4(x, pb);
+                                        rec1 = f4(wo, 0.0f);
+                                        rec2 = f4(wi, ubits(slot));
+                                        rec3 = f4(L, 0.0f);
+                                        rec4 = f4(T, 0.0f);
+                                    }
                                 }
                             }
                         }
@@ -743,8 +788,23 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
             }
             P.rad[slot] = f4(L, 0.0f);
         }
+        uint32_t rec_idx = kNoHit;
+        if (F.guide.record) {
+            uint32_t pr = wave_append(&P.counters[127], record);
+            if (record && pr < F.guide.rec_cap) {
+                float4 *r = F.guide.rec + (size_t)pr * kRecF4;
+                r[0] = rec0;
+                r[1] = rec1;
+                r[2] = rec2;
+                r[3] = rec3;
+                r[4] = rec4;
+                r[5] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                rec_idx = pr;
+            }
+        }
         uint32_t ps = wave_append(&P.counters[64 + v], shadow);
         if (shadow) {
+            sh_c.w = ubits(rec_idx);
             P.q_sh[ps] = slot;
             P.sh_o[ps] = sh_o;
             P.sh_d[ps] = sh_d;
@@ -881,6 +941,7 @@ hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uin
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
         timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
+        if (F.guide.alpha_thr && v < F.max_depth) timed(K_GUIDE_EVAL, [&] { launch_guide_eval(F, P, v, gt, s); });
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
     }

@@ -55,18 +55,26 @@ class qpt_stats(C.Structure):
                 ("nodes_shadow", C.c_uint64), ("tris_shadow", C.c_uint64)]
 
 
+class qpt_guide_opts(C.Structure):
+    _fields_ = [("alpha", C.c_float), ("lr", C.c_float), ("batch", C.c_uint32), ("train", C.c_uint32),
+                ("warmup_steps", C.c_uint32), ("seed", C.c_uint32)]
+
+
 class qpt_kernel_time(C.Structure):
     _fields_ = [("launches", C.c_uint32), ("reserved", C.c_uint32), ("total_ms", C.c_double)]
 
 
-KERNEL_KINDS = ["clear", "generate", "trace", "shade", "shadow", "accumulate"]
+KERNEL_KINDS = ["clear", "generate", "trace", "shade", "shadow", "accumulate", "guide_eval", "guide_train"]
+GUIDE_PARAMS = 13032
 
 
 EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
-    "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read",
+    "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
+    "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_grad",
+    "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
 ]
 
 _lib = None
@@ -103,6 +111,14 @@ def lib():
             "qpt_debug_env_tables": ([P, P, P, P], i32),
             "qpt_debug_bvh_nodes": ([P, P, P, P], i32),
             "qpt_profile": ([P, i32], i32),
+            "qpt_guide_config": ([P, C.POINTER(qpt_guide_opts)], i32),
+            "qpt_guide_set_weights": ([P, P], i32),
+            "qpt_guide_get_weights": ([P, P, C.POINTER(C.c_uint32)], i32),
+            "qpt_guide_debug_forward": ([P, P, u32, P], i32),
+            "qpt_guide_debug_grad": ([P, P, P, P, u32, P], i32),
+            "qpt_guide_debug_train": ([P, P, P, P, u32, C.c_float, P], i32),
+            "qpt_guide_debug_mixture": ([P, P, P, P, u32, P, P], i32),
+            "qpt_guide_loss": ([P, C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
             "qpt_profile_read": ([P, C.POINTER(qpt_kernel_time)], i32),
         }
         for name, (args, res) in sig.items():
@@ -219,6 +235,41 @@ class Context:
         arr = (qpt_kernel_time * len(KERNEL_KINDS))()
         self.check(self.L.qpt_profile_read(self.h, arr), "qpt_profile_read")
         return {k: (arr[i].launches, arr[i].total_ms) for i, k in enumerate(KERNEL_KINDS)}
+
+    # ---- learned proposal
+    def guide_config(self, alpha=0.5, lr=1e-3, batch=1 << 18, train=True, warmup_steps=1, seed=0) -> None:
+        o = qpt_guide_opts(alpha, lr, batch, int(train), warmup_steps, seed)
+        self.check(self.L.qpt_guide_config(self.h, C.byref(o)), "qpt_guide_config")
+
+    def guide_set_weights(self, params) -> None:
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.shape == (GUIDE_PARAMS,)
+        self.check(self.L.qpt_guide_set_weights(self.h, _p(p)), "qpt_guide_set_weights")
+
+    def guide_get_weights(self):
+        p = np.empty(GUIDE_PARAMS, np.float32)
+        st = C.c_uint32()
+        self.check(self.L.qpt_guide_get_weights(self.h, _p(p), C.byref(st)), "qpt_guide_get_weights")
+        return p, st.value
+
+    def guide_debug_forward(self, x, n, out) -> None:
+        self.check(self.L.qpt_guide_debug_forward(self.h, _p(x), n, _p(out)), "qpt_guide_debug_forward")
+
+    def guide_debug_grad(self, x, dirs, w, n, grad) -> None:
+        self.check(self.L.qpt_guide_debug_grad(self.h, _p(x), _p(dirs), _p(w), n, _p(grad)), "qpt_guide_debug_grad")
+
+    def guide_debug_train(self, x, dirs, w, n, lr, grad=None) -> None:
+        self.check(self.L.qpt_guide_debug_train(self.h, _p(x), _p(dirs), _p(w), n, lr, _p(grad)),
+                   "qpt_guide_debug_train")
+
+    def guide_debug_mixture(self, out40, dirs, u, n, pdf, sample) -> None:
+        self.check(self.L.qpt_guide_debug_mixture(self.h, _p(out40), _p(dirs), _p(u), n, _p(pdf), _p(sample)),
+                   "qpt_guide_debug_mixture")
+
+    def guide_loss(self):
+        l, w = C.c_double(), C.c_double()
+        self.check(self.L.qpt_guide_loss(self.h, C.byref(l), C.byref(w)), "qpt_guide_loss")
+        return l.value, w.value
 
     def debug_sample_bits(self, idx, dim, n, scramble, out) -> None:
         self.check(self.L.qpt_debug_sample_bits(self.h, _p(idx), _p(dim), n, int(scramble), _p(out)),

@@ -1,0 +1,203 @@
+"""GPU parity of the learned proposal through the C-ABI.
+
+- Network forward (BF16 MFMA, FP32 accumulation) vs the oracle in FP64 with
+  the same BF16 rounding points: relative L2 <= 1e-3.
+- Gradient of the weighted mixture NLL through decode and the network vs the
+  oracle (BF16 operands in the backward too): relative L2 <= 1e-2.
+- One Adam step (bias-corrected, FP32 master) vs the oracle's.
+- Mixture decode, pdf and sampling vs the oracle on the same numbers.
+- alpha = 0 guided rendering (records captured, Adam running) equals plain
+  rendering bit for bit; alpha = 0.5 is unbiased (block means agree with the
+  plain render within 4 standard errors).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import scenegen as g
+from oracle import guide as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Renderer():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1705_01263_amd import Renderer as R
+    return R
+
+
+def _dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _features(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, (n, 3))
+    wo = rng.normal(size=(n, 3))
+    wo /= np.linalg.norm(wo, axis=1, keepdims=True)
+    return G.encode(x, wo, [-1, -1, -1], [2, 2, 2])
+
+
+@pytest.fixture(scope="module")
+def ctx(Renderer):
+    r = Renderer(g.cornell(width=32, height=32), pool_paths=1 << 14)
+    theta = g.guide_init(5)
+    r.ctx.guide_set_weights(theta)
+    return r, theta.astype(np.float64)
+
+
+def test_forward_parity(ctx):
+    r, theta = ctx
+    n = 4096 + 17  # several waves and a ragged tail
+    X = _features(n, 1)
+    X[:4] = 0.0
+    out = torch.empty((n, 40), dtype=torch.float32, device="cuda")
+    r.ctx.guide_debug_forward(_dev(X), n, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want, _ = G.forward(theta, X, bf16=True)
+    err = _rel_l2(got, want)
+    _say(f"[guide fwd] rel L2 {err:.2e}, max abs {np.abs(got - want).max():.2e}")
+    assert err <= 1e-3
+
+
+def test_gradient_parity(ctx):
+    r, theta = ctx
+    n = 2048 + 5
+    X = _features(n, 2)
+    rng = np.random.default_rng(3)
+    w = rng.normal(size=(n, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    wt = rng.uniform(0.05, 3.0, n)
+    wt[::7] = 0.0  # zero-weight rows contribute nothing
+    grad = torch.empty(G.NPARAM, dtype=torch.float32, device="cuda")
+    r.ctx.guide_debug_grad(_dev(X), _dev(w), _dev(wt), n, grad)
+    torch.cuda.synchronize()
+    got = grad.cpu().numpy()
+    out, cache = G.forward(theta, X, bf16=True)
+    want = G.backward(theta, cache, G.loss_grad(out, w, wt), bf16=True)
+    err = _rel_l2(got, want)
+    _say(f"[guide grad] rel L2 {err:.2e}")
+    assert err <= 1e-2
+    for L, (o, k) in enumerate([(0, 2048), (2112, 4096), (6272, 4096), (10432, 2560)]):
+        assert _rel_l2(got[o:o + k], want[o:o + k]) <= 2e-2, L
+
+
+def test_adam_step(Renderer):
+    r = Renderer(g.cornell(width=16, height=16), pool_paths=1 << 12)
+    theta = g.guide_init(9)
+    r.ctx.guide_set_weights(theta)
+    n = 1024
+    X = _features(n, 4)
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=(n, 3))
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    wt = rng.uniform(0.5, 1.5, n)
+    grad = torch.empty(G.NPARAM, dtype=torch.float32, device="cuda")
+    r.ctx.guide_debug_train(_dev(X), _dev(w), _dev(wt), n, 1e-3, grad)
+    th1, steps = r.ctx.guide_get_weights()
+    assert steps == 1
+    g_gpu = grad.cpu().numpy().astype(np.float64)
+    # Adam's first step is -lr g / (|g| + eps): check it on the GPU's own gradient
+    want = theta.astype(np.float64) - 1e-3 * g_gpu / (np.abs(g_gpu) + 1e-8)
+    assert np.allclose(th1, want, rtol=0, atol=2e-7)
+    # and the step agrees with the oracle's gradient wherever that is not tiny
+    th_o, _, _, g_o, _ = G.train_step(theta.astype(np.float64), np.zeros(G.NPARAM), np.zeros(G.NPARAM), 1, X, w, wt,
+                                      lr=1e-3, bf16=True)
+    big = np.abs(g_o) > 1e-4 * np.abs(g_o).max()
+    assert np.mean(np.abs(th1[big] - th_o[big]) < 1e-6) > 0.999
+
+
+def test_mixture_parity(ctx):
+    r, _ = ctx
+    n = 8192
+    rng = np.random.default_rng(7)
+    out = rng.normal(size=(n, 40)) * 2.0
+    out[:, 4::5] = rng.uniform(-3, 9, (n, 8))  # kappas from ~0.05 to ~9000
+    dirs = rng.normal(size=(n, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    u = rng.uniform(0, 1, (n, 3))
+    pdf = torch.empty(n, dtype=torch.float32, device="cuda")
+    smp = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    r.ctx.guide_debug_mixture(_dev(out), _dev(dirs), _dev(u), n, pdf, smp)
+    torch.cuda.synchronize()
+    out32 = out.astype(np.float32).astype(np.float64)
+    pi, mu, kappa, _ = G.decode(out32)
+    want_pdf = G.mixture_pdf(pi, mu, kappa, dirs.astype(np.float32).astype(np.float64))
+    got_pdf = pdf.cpu().numpy()
+    rel = np.abs(got_pdf - want_pdf) / np.maximum(want_pdf, 1e-30)
+    big = want_pdf > 1e-20
+    assert np.quantile(rel[big], 0.999) < 5e-3 and np.median(rel[big]) < 1e-4
+    u32 = u.astype(np.float32).astype(np.float64)
+    ws, _ = G.mixture_sample(pi, mu, kappa, u32[:, 0], u32[:, 1], u32[:, 2])
+    got = smp.cpu().numpy()
+    close = np.linalg.norm(got - ws, axis=1) < 2e-3
+    assert np.mean(close) > 0.995  # the rest sit at lobe-choice boundaries in FP32
+    assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-5)
+
+
+def _render(r, first, n, **kw):
+    r.render(first, n, **kw)
+    return r.readback()
+
+
+def test_alpha_zero_is_plain_bitexact(Renderer):
+    sc = g.cornell(width=64, height=64)
+    _say("[guide] alpha = 0 with training vs plain")
+    rp = Renderer(sc)
+    sp, cp = _render(rp, 0, 8)
+    rg = Renderer(sc)
+    rg.ctx.guide_set_weights(g.guide_init(1))
+    rg.ctx.guide_config(alpha=0.0, train=True, batch=1 << 14)
+    sg, cg = _render(rg, 0, 8)
+    _, steps = rg.ctx.guide_get_weights()
+    assert steps >= 1
+    assert np.array_equal(cp, cg) and np.array_equal(sp, sg)
+    # never-activated guide (warm-up not reached) is also plain
+    rh = Renderer(sc)
+    rh.ctx.guide_set_weights(g.guide_init(1))
+    rh.ctx.guide_config(alpha=0.5, train=False, warmup_steps=1000)
+    sh, _ = _render(rh, 0, 8)
+    assert np.array_equal(sp, sh)
+
+
+def test_guided_is_unbiased(Renderer):
+    """Cornell box, alpha = 0.5 after training: 16x16-block means match plain."""
+    sc = g.cornell(width=64, height=64, max_depth=6)
+    _say("[guide] unbiasedness at alpha = 0.5")
+    rg = Renderer(sc)
+    rg.ctx.guide_set_weights(g.guide_init(2))
+    rg.ctx.guide_config(alpha=0.5, train=True, batch=1 << 14, warmup_steps=4, lr=2e-3)
+    rg.render(0, 16)   # train (the first 4 passes unguided)
+    rg.reset()
+    rp = Renderer(sc)
+    blocks_g, blocks_p = [], []
+    for b in range(8):
+        sg, cg = _render(rg, 100 + 32 * b, 32)
+        rg.reset()
+        sp, cp = _render(rp, 100 + 32 * b, 32)
+        rp.reset()
+        for s, c, out in ((sg, cg, blocks_g), (sp, cp, blocks_p)):
+            img = (s / c[:, None]).reshape(4, 16, 4, 16, 3).mean(axis=(1, 3))
+            out.append(img)
+    bg, bp = np.array(blocks_g), np.array(blocks_p)
+    mg, mp = bg.mean(0), bp.mean(0)
+    se = np.sqrt(bg.var(0, ddof=1) / bg.shape[0] + bp.var(0, ddof=1) / bp.shape[0])
+    z = np.abs(mg - mp) / np.maximum(se, 1e-12)
+    _say(f"    max |z| over 16x16 blocks {z.max():.2f}")
+    assert np.mean(z < 4.0) > 0.97 and z.max() < 6.0
+    l, w = rg.ctx.guide_loss()
+    assert np.isfinite(l) and w > 0
