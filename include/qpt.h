@@ -193,7 +193,8 @@ typedef struct {
     float alpha;             /* probability of sampling the guide once active, [0, 1); 0 disables */
     float lr;                /* Adam learning rate (> 0) */
     uint32_t batch;          /* training samples per step (0 = 2^18, at most 2^22) */
-    uint32_t train;          /* 1: record training samples and take one Adam step per batch of passes */
+    uint32_t train;          /* Adam steps after each batch of passes, each on its own stratified subset of
+                                that batch's records (0: no recording or training; at most 64) */
     uint32_t warmup_steps;   /* guide sampling stays off until this many steps were taken */
     uint32_t seed;           /* offsets of the stratified batch subsets */
 } qpt_guide_opts;

@@ -339,7 +339,57 @@ __device__ __forceinline__ void load_weights(const uint2 *frag, const float *bia
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = bias[i];
 }
 
-// mixture of every extension-queue vertex at depth v that hits a scattering surface
+// inference forward: only the running B operands, no stored activations
+__device__ __forceinline__ void mlp_infer(const uint2 *sfrag, const float *sbias, const v4s *a0, v16f *out)
+{
+    v16f acc[2];
+    v4s cur[8];
+    uint32_t m;
+    layer_fwd<0>(sfrag, sbias, a0, acc);
+    relu_pack(acc, cur, m);
+    layer_fwd<1>(sfrag, sbias, cur, acc);
+    relu_pack(acc, cur, m);
+    layer_fwd<2>(sfrag, sbias, cur, acc);
+    relu_pack(acc, cur, m);
+    layer_fwd<3>(sfrag, sbias, cur, out);
+}
+
+// the B operands of layer 0 for this lane's half of the row: half h needs
+// features 8s + 4h .. 8s + 4h + 3, i.e. octaves 2h and 2h + 1 of axis s
+// (s < 3), then the polar (h = 0) or azimuthal (h = 1) terms; the same
+// values as the full encoding, computed once per lane
+__device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const float *bmin, const float *bext, v4s *a0)
+{
+    const uint32_t h = lane_id() >> 5;
+    float xh[3] = {(x.x - bmin[0]) / bext[0], (x.y - bmin[1]) / bext[1], (x.z - bmin[2]) / bext[2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float s0, c0, s1, c1;
+        sincosf((float)(1 << (2 * h)) * guide::kPiF * xh[a], &s0, &c0);
+        sincosf((float)(1 << (2 * h + 1)) * guide::kPiF * xh[a], &s1, &c1);
+        a0[a] = pack4(s0, c0, s1, c1);
+    }
+    float ang0, ang1;
+    if (h == 0) {
+        float th = acosf(fminf(1.0f, fmaxf(-1.0f, wo.y))) / guide::kPiF;
+        ang0 = guide::kPiF * th;
+        ang1 = 2.0f * guide::kPiF * th;
+    } else {
+        float ph = atan2f(wo.x, -wo.z);
+        if (ph < 0.0f) ph += 2.0f * guide::kPiF;
+        ph *= 1.0f / (2.0f * guide::kPiF);
+        ang0 = 2.0f * guide::kPiF * ph;
+        ang1 = 4.0f * guide::kPiF * ph;
+    }
+    float s0, c0, s1, c1;
+    sincosf(ang0, &s0, &c0);
+    sincosf(ang1, &s1, &c1);
+    a0[3] = pack4(s0, c0, s1, c1);
+}
+
+// mixture of every extension-queue vertex at depth v that hits a scattering
+// surface: each lane of a pair encodes its half of the inputs and decodes
+// four of the eight lobes
 __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
@@ -348,15 +398,17 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
     __syncthreads();
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];
-    const uint32_t lane = lane_id();
+    const uint32_t lane = lane_id(), h = lane >> 5;
     const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const uint32_t waves = gridDim.x * (blockDim.x / 64);
     for (uint32_t base = wave * 32; base < n; base += waves * 32) {
+        // keeps the weight reads inside the loop: hoisted, they would pin
+        // ~240 registers and leave one wave per SIMD
+        asm volatile("" ::: "memory");
         uint32_t i = base + (lane & 31);
         bool valid = i < n;
-        float f[32];
-        for (int j = 0; j < 32; ++j) f[j] = 0.0f;
         uint32_t slot = 0;
+        guide::V3 x = {0.0f, 0.0f, 0.0f}, wo = {0.0f, 1.0f, 0.0f};
         if (valid) {
             slot = q[i];
             float4 hv = P.hit[slot];
@@ -365,30 +417,43 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
             if (valid) {
                 const Tri tr = F.tris[tri];
                 float4 d = P.ray_d[slot];
-                guide::V3 x = {tr.v0.x + ((tr.v1.x - tr.v0.x) * hv.z + (tr.v2.x - tr.v0.x) * hv.w),
-                               tr.v0.y + ((tr.v1.y - tr.v0.y) * hv.z + (tr.v2.y - tr.v0.y) * hv.w),
-                               tr.v0.z + ((tr.v1.z - tr.v0.z) * hv.z + (tr.v2.z - tr.v0.z) * hv.w)};
-                guide::encode(x, guide::V3{-d.x, -d.y, -d.z}, F.guide.bmin, F.guide.bext, f);
+                x = {tr.v0.x + ((tr.v1.x - tr.v0.x) * hv.z + (tr.v2.x - tr.v0.x) * hv.w),
+                     tr.v0.y + ((tr.v1.y - tr.v0.y) * hv.z + (tr.v2.y - tr.v0.y) * hv.w),
+                     tr.v0.z + ((tr.v1.z - tr.v0.z) * hv.z + (tr.v2.z - tr.v0.z) * hv.w)};
+                wo = {-d.x, -d.y, -d.z};
             }
         }
         v4s a0[4];
-        input_frags(f, a0);
-        Act A;
+        encode_half(x, wo, F.guide.bmin, F.guide.bext, a0);
         v16f out[2];
-        mlp_forward(sfrag, sbias, a0, A, out);
+        mlp_infer(sfrag, sbias, a0, out);
         float o[40];
         gather40(out, o);
         if (valid) {
-            guide::Mix m;
-            guide::decode(o, m);
-            float4 *dst = F.guide.mix + (size_t)slot * 10;
-            if (lane < 32) {
-                for (int k = 0; k < 5; ++k) dst[k] = m.lobe[k];
-            } else {
-                for (int k = 5; k < 8; ++k) dst[k] = m.lobe[k];
-                dst[8] = m.w0;
-                dst[9] = m.w1;
+            float mx = o[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) mx = fmaxf(mx, o[5 * k]);
+            float e[8], se = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                e[k] = expf(o[5 * k] - mx);
+                se += e[k];
             }
+            float inv = 1.0f / se;
+            float4 *dst = F.guide.mix + (size_t)slot * 10;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int k = 4 * (int)h + j;
+                float ox = h ? o[5 * (4 + j) + 1] : o[5 * j + 1];
+                float oy = h ? o[5 * (4 + j) + 2] : o[5 * j + 2];
+                float oz = h ? o[5 * (4 + j) + 3] : o[5 * j + 3];
+                float ok = h ? o[5 * (4 + j) + 4] : o[5 * j + 4];
+                float nn = fmaxf(sqrtf(ox * ox + oy * oy + oz * oz), 1e-12f);
+                float kap = fminf(guide::softplus(ok) + 1e-3f, 1e4f);
+                dst[k] = make_float4(ox / nn, oy / nn, oz / nn, kap);
+            }
+            dst[8 + h] = h ? make_float4(e[4] * inv, e[5] * inv, e[6] * inv, e[7] * inv)
+                           : make_float4(e[0] * inv, e[1] * inv, e[2] * inv, e[3] * inv);
         }
     }
 }
@@ -456,6 +521,7 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
     const uint32_t tiles = (nrows + 31) / 32;
     float wsum = 0.0f, lsum = 0.0f;
     for (uint32_t tile = wave; tile < tiles; tile += waves) {
+        asm volatile("" ::: "memory");  // weight reads stay in the loop
         uint32_t row = tile * 32 + (lane & 31);
         bool valid = row < nrows;
         float f[32];
@@ -625,23 +691,29 @@ static hipError_t run_train(const Frame &f, const GuideTrain &T, const RowSrc &s
 }
 
 hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const GuideTrain &T, uint32_t batch,
-                                   uint32_t step, float lr, uint32_t seed, hipStream_t s, Profiler *prof)
+                                   uint32_t step0, uint32_t nsteps, float lr, uint32_t seed, hipStream_t s,
+                                   Profiler *prof)
 {
     if (prof) prof->begin(K_GUIDE_TRAIN, s);
     hipLaunchKernelGGL(k_fill_u32_1, dim3(1), dim3(1), 0, s, T.cand_count);
     hipLaunchKernelGGL(k_rec_finalize, dim3(nblocks(f.guide.rec_cap, 256, 4096)), dim3(256), 0, s, f, pool, T);
-    // stratification offset from the step and seed (splitmix64 finaliser)
-    uint64_t z = ((uint64_t)seed << 32) + step + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    RowSrc src{false, nullptr, nullptr, nullptr, batch, T.cand_count, (float)((z >> 40) * 0x1p-24)};
-    uint32_t blocks = 0;
-    hipError_t e = run_train(f, T, src, s, &blocks);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_guide_reduce, dim3(nblocks(kGuideParams, 256, 1024)), dim3(256), 0, s, T, blocks, 1, step,
-                       lr, (float *)nullptr);
-    e = launch_guide_frag(T, s);
+    hipError_t e = hipSuccess;
+    for (uint32_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        const uint32_t step = step0 + k;
+        // stratification offset from the step and seed (splitmix64 finaliser):
+        // each step of one batch sees a different subset of its records
+        uint64_t z = ((uint64_t)seed << 32) + step + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        RowSrc src{false, nullptr, nullptr, nullptr, batch, T.cand_count, (float)((z >> 40) * 0x1p-24)};
+        uint32_t blocks = 0;
+        e = run_train(f, T, src, s, &blocks);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_guide_reduce, dim3(nblocks(kGuideParams, 256, 1024)), dim3(256), 0, s, T, blocks, 1,
+                           step, lr, (float *)nullptr);
+        e = launch_guide_frag(T, s);
+    }
     if (prof) prof->end(K_GUIDE_TRAIN, s);
     return e;
 }

@@ -1070,9 +1070,10 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         f.guide.record = c->gopts.train ? 1u : 0u;
         HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
         if (c->gopts.train) {
-            ++c->guide_steps;
             HIP_TRY(c, launch_guide_train_step(f, c->pool, c->gt, c->gopts.batch ? c->gopts.batch : (1u << 18),
-                                               c->guide_steps, c->gopts.lr, c->gopts.seed, c->stream, prof));
+                                               c->guide_steps + 1, c->gopts.train, c->gopts.lr, c->gopts.seed,
+                                               c->stream, prof));
+            c->guide_steps += c->gopts.train;
         }
         return QPT_OK;
     };
@@ -1194,8 +1195,9 @@ int qpt_debug_trace(qpt_ctx *c, const float *rays, uint32_t n, int any_hit, int 
 int qpt_guide_config(qpt_ctx *c, const qpt_guide_opts *o)
 {
     if (!c || !o) return QPT_E_INVALID;
-    if (!(o->alpha >= 0.0f && o->alpha < 1.0f) || !(o->lr > 0.0f) || o->batch > (1u << 22))
-        return fail(c, QPT_E_INVALID, "guide options out of range (alpha in [0, 1), lr > 0, batch <= 2^22)");
+    if (!(o->alpha >= 0.0f && o->alpha < 1.0f) || !(o->lr > 0.0f) || o->batch > (1u << 22) || o->train > 64)
+        return fail(c, QPT_E_INVALID,
+                    "guide options out of range (alpha in [0, 1), lr > 0, batch <= 2^22, train <= 64)");
     c->gopts = *o;
     return QPT_OK;
 }

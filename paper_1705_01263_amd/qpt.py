@@ -238,7 +238,7 @@ class Context:
 
     # ---- learned proposal
     def guide_config(self, alpha=0.5, lr=1e-3, batch=1 << 18, train=True, warmup_steps=1, seed=0) -> None:
-        o = qpt_guide_opts(alpha, lr, batch, int(train), warmup_steps, seed)
+        o = qpt_guide_opts(alpha, lr, batch, int(train), warmup_steps, seed)  # train: Adam steps per batch
         self.check(self.L.qpt_guide_config(self.h, C.byref(o)), "qpt_guide_config")
 
     def guide_set_weights(self, params) -> None:
