@@ -365,8 +365,8 @@ __device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const flo
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float s0, c0, s1, c1;
-        sincosf((float)(1 << (2 * h)) * guide::kPiF * xh[a], &s0, &c0);
-        sincosf((float)(1 << (2 * h + 1)) * guide::kPiF * xh[a], &s1, &c1);
+        sincosf(guide::kOct[2 * h] * guide::kPiF * xh[a], &s0, &c0);
+        sincosf(guide::kOct[2 * h + 1] * guide::kPiF * xh[a], &s1, &c1);
         a0[a] = pack4(s0, c0, s1, c1);
     }
     float ang0, ang1;
@@ -387,17 +387,27 @@ __device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const flo
     a0[3] = pack4(s0, c0, s1, c1);
 }
 
-// mixture of every extension-queue vertex at depth v that hits a scattering
-// surface: each lane of a pair encodes its half of the inputs and decodes
-// four of the eight lobes
-__global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
+// rows of the inference kernel: the extension queue of depth v (a row is a
+// path slot whose ray hit a triangle), or explicit arrays for parity checks
+struct EvalSrc {
+    bool debug;
+    uint32_t v;              // queue: depth
+    const float *x, *wo;     // debug: n x 3 positions and outgoing directions
+    uint32_t n;              // debug: rows
+    float4 *out;             // debug: n x 10 float4 (queue rows write F.guide.mix)
+};
+
+// mixture of every row: each lane of a pair encodes its half of the inputs
+// and decodes four of the eight lobes
+__global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
     __shared__ float sbias[256];
     load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
     __syncthreads();
-    const uint32_t n = P.counters[v];
-    const uint32_t *q = P.q_ext[v & 1];
+    const uint32_t n = src.debug ? src.n : P.counters[src.v];
+    const uint32_t *q = P.q_ext[src.v & 1];
+    float4 *mix_out = src.debug ? src.out : F.guide.mix;
     const uint32_t lane = lane_id(), h = lane >> 5;
     const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const uint32_t waves = gridDim.x * (blockDim.x / 64);
@@ -409,7 +419,11 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
         bool valid = i < n;
         uint32_t slot = 0;
         guide::V3 x = {0.0f, 0.0f, 0.0f}, wo = {0.0f, 1.0f, 0.0f};
-        if (valid) {
+        if (valid && src.debug) {
+            slot = i;
+            x = {src.x[3 * (size_t)i], src.x[3 * (size_t)i + 1], src.x[3 * (size_t)i + 2]};
+            wo = {src.wo[3 * (size_t)i], src.wo[3 * (size_t)i + 1], src.wo[3 * (size_t)i + 2]};
+        } else if (valid) {
             slot = q[i];
             float4 hv = P.hit[slot];
             uint32_t tri = __float_as_uint(hv.y);
@@ -440,7 +454,7 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, uint32_t v)
                 se += e[k];
             }
             float inv = 1.0f / se;
-            float4 *dst = F.guide.mix + (size_t)slot * 10;
+            float4 *dst = mix_out + (size_t)slot * 10;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 int k = 4 * (int)h + j;
@@ -670,7 +684,16 @@ hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s)
 
 hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_guide_eval, dim3(grid), dim3(256), 0, s, f, pool, v);
+    EvalSrc src{false, v, nullptr, nullptr, 0u, nullptr};
+    hipLaunchKernelGGL(k_guide_eval, dim3(grid), dim3(256), 0, s, f, pool, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
+                                   float *mix, hipStream_t s)
+{
+    EvalSrc src{true, 0u, x, wo, n, (float4 *)mix};
+    hipLaunchKernelGGL(k_guide_eval, dim3(nblocks(((size_t)n + 31) / 32, 4, 2048)), dim3(256), 0, s, f, pool, src);
     return hipGetLastError();
 }
 

@@ -12,6 +12,17 @@ namespace guide {
 
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr int kLobes = 8;
+// frequency multipliers of the four position octaves
+#ifndef QPT_GUIDE_OCT
+#define QPT_GUIDE_OCT 0
+#endif
+#if QPT_GUIDE_OCT == 1
+__device__ constexpr float kOct[4] = {1.0f, 4.0f, 16.0f, 64.0f};
+#elif QPT_GUIDE_OCT == 2
+__device__ constexpr float kOct[4] = {2.0f, 8.0f, 32.0f, 128.0f};
+#else
+__device__ constexpr float kOct[4] = {1.0f, 2.0f, 4.0f, 8.0f};
+#endif
 
 struct V3 {
     float x, y, z;
@@ -106,7 +117,7 @@ __device__ inline void encode(V3 x, V3 wo, const float *bmin, const float *bext,
     for (int a = 0; a < 3; ++a)
         for (int o = 0; o < 4; ++o) {
             float s, c;
-            sincosf((float)(1 << o) * kPiF * xh[a], &s, &c);
+            sincosf(kOct[o] * kPiF * xh[a], &s, &c);
             f[8 * a + 2 * o] = s;
             f[8 * a + 2 * o + 1] = c;
         }

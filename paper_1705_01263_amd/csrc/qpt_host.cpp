@@ -1241,6 +1241,16 @@ int qpt_guide_debug_forward(qpt_ctx *c, const float *x, uint32_t n, float *out)
     return QPT_OK;
 }
 
+int qpt_guide_debug_eval(qpt_ctx *c, const float *x, const float *wo, uint32_t n, float *mix)
+{
+    if (!c || (n && (!x || !wo || !mix))) return QPT_E_INVALID;
+    if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_guide_debug_eval(c->frame, c->pool, x, wo, n, mix, c->stream));
+    return QPT_OK;
+}
+
 int qpt_guide_debug_grad(qpt_ctx *c, const float *x, const float *dirs, const float *w, uint32_t n, float *grad)
 {
     if (!c || !n || !x || !dirs || !w || !grad) return QPT_E_INVALID;

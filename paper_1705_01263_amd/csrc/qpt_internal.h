@@ -163,6 +163,8 @@ hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, 
 // guide launchers (qpt_guide.hip)
 hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s);
 hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s);
+hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
+                                   float *mix, hipStream_t s);
 hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const GuideTrain &T, uint32_t batch,
                                    uint32_t step0, uint32_t nsteps, float lr, uint32_t seed, hipStream_t s,
                                    Profiler *prof);

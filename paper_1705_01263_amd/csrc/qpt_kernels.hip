@@ -941,7 +941,7 @@ hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uin
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
         timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
-        if (F.guide.alpha_thr && v < F.max_depth) timed(K_GUIDE_EVAL, [&] { launch_guide_eval(F, P, v, gt, s); });
+        if (F.guide.alpha_thr && v < F.max_depth) timed(K_GUIDE_EVAL, [&] { (void)launch_guide_eval(F, P, v, gt, s); });  // errors surface below
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
     }

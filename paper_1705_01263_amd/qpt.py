@@ -73,7 +73,7 @@ EXPORTS = [
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
-    "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_grad",
+    "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_eval", "qpt_guide_debug_grad",
     "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
 ]
 
@@ -115,6 +115,7 @@ def lib():
             "qpt_guide_set_weights": ([P, P], i32),
             "qpt_guide_get_weights": ([P, P, C.POINTER(C.c_uint32)], i32),
             "qpt_guide_debug_forward": ([P, P, u32, P], i32),
+            "qpt_guide_debug_eval": ([P, P, P, u32, P], i32),
             "qpt_guide_debug_grad": ([P, P, P, P, u32, P], i32),
             "qpt_guide_debug_train": ([P, P, P, P, u32, C.c_float, P], i32),
             "qpt_guide_debug_mixture": ([P, P, P, P, u32, P, P], i32),
@@ -254,6 +255,9 @@ class Context:
 
     def guide_debug_forward(self, x, n, out) -> None:
         self.check(self.L.qpt_guide_debug_forward(self.h, _p(x), n, _p(out)), "qpt_guide_debug_forward")
+
+    def guide_debug_eval(self, x, wo, n, mix) -> None:
+        self.check(self.L.qpt_guide_debug_eval(self.h, _p(x), _p(wo), n, _p(mix)), "qpt_guide_debug_eval")
 
     def guide_debug_grad(self, x, dirs, w, n, grad) -> None:
         self.check(self.L.qpt_guide_debug_grad(self.h, _p(x), _p(dirs), _p(w), n, _p(grad)), "qpt_guide_debug_grad")

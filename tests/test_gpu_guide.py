@@ -2,6 +2,9 @@
 
 - Network forward (BF16 MFMA, FP32 accumulation) vs the oracle in FP64 with
   the same BF16 rounding points: relative L2 <= 1e-3.
+- The renderer's inference kernel (encoding, network, decode) vs the oracle's
+  encode -> forward -> decode: relative L2 <= 2e-3 for weights, means and
+  concentrations.
 - Gradient of the weighted mixture NLL through decode and the network vs the
   oracle (BF16 operands in the backward too): relative L2 <= 1e-2.
 - One Adam step (bias-corrected, FP32 master) vs the oracle's.
@@ -72,6 +75,37 @@ def test_forward_parity(ctx):
     err = _rel_l2(got, want)
     _say(f"[guide fwd] rel L2 {err:.2e}, max abs {np.abs(got - want).max():.2e}")
     assert err <= 1e-3
+
+
+def test_eval_parity(ctx):
+    """The renderer's inference kernel (half-row encoding per lane, decode of
+    four lobes per lane) against the oracle's encode -> forward -> decode."""
+    r, theta = ctx
+    n = 3000 + 13
+    rng = np.random.default_rng(11)
+    pos = r.sc.positions.astype(np.float64)
+    lo = pos.min(0)
+    ext = np.maximum(pos.max(0) - lo, 1e-6)
+    bmin, bext = lo.astype(np.float32).astype(np.float64), ext.astype(np.float32).astype(np.float64)
+    x = (lo + rng.uniform(0, 1, (n, 3)) * ext).astype(np.float32)
+    wo = rng.normal(size=(n, 3))
+    wo /= np.linalg.norm(wo, axis=1, keepdims=True)
+    wo = wo.astype(np.float32)
+    mix = torch.empty((n, 40), dtype=torch.float32, device="cuda")
+    r.ctx.guide_debug_eval(_dev(x), _dev(wo), n, mix)
+    torch.cuda.synchronize()
+    got = mix.cpu().numpy().astype(np.float64)
+    X = G.encode(x.astype(np.float64), wo.astype(np.float64), bmin, bext)
+    out, _ = G.forward(theta, X, bf16=True)
+    pi, mu, kappa, _ = G.decode(out)
+    g_lobes = got[:, :32].reshape(n, 8, 4)
+    e_pi = _rel_l2(got[:, 32:], pi)
+    e_mu = _rel_l2(g_lobes[:, :, :3], mu)
+    e_k = _rel_l2(g_lobes[:, :, 3], kappa)
+    _say(f"[guide eval] rel L2 pi {e_pi:.2e} mu {e_mu:.2e} kappa {e_k:.2e}")
+    assert e_pi <= 2e-3 and e_mu <= 2e-3 and e_k <= 2e-3
+    assert np.allclose(got[:, 32:].sum(1), 1.0, atol=1e-5)
+    assert np.allclose(np.linalg.norm(g_lobes[:, :, :3], axis=2), 1.0, atol=1e-5)
 
 
 def test_gradient_parity(ctx):
