@@ -32,7 +32,7 @@ METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64
 HBM_PEAK_GBS = 8000.0
 
 # algorithmic bytes per unit of work ("Measurement")
-NODE_BYTES, TRI_BYTES = 64, 48
+NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
 TRACE_RAY_BYTES = 4 + 32 + 16        # queue entry, ray (o, tmax, d), hit record
 SHADOW_RAY_BYTES = 48 + 32           # shadow ray + contribution, radiance read-modify-write
 SHADE_VERTEX_BYTES = 4 + 16 + 16 + 16 + 16 + 8 + 48 + 32 + 16   # reads + radiance write

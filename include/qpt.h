@@ -88,9 +88,9 @@ typedef struct {
 } qpt_bvh_opts;
 
 typedef struct {
-    uint32_t num_nodes;      /* inner nodes */
+    uint32_t num_nodes;      /* inner nodes of the 4-wide tree */
     uint32_t num_leaves;
-    uint32_t max_depth;      /* root = depth 0 */
+    uint32_t max_depth;      /* of the 4-wide tree's inner nodes, root = depth 0 */
     uint32_t reserved;
     double sah_cost;         /* SAH cost with unit traversal and intersection costs */
     double build_ms;
@@ -282,12 +282,14 @@ int qpt_debug_light_tables(const qpt_ctx *ctx, uint32_t *emit_tri, double *prob,
  * texel_pdf[env_height * env_width]. QPT_E_STATE without an environment. */
 int qpt_debug_env_tables(const qpt_ctx *ctx, uint32_t *row_q, uint32_t *col_q, float *texel_pdf);
 
-/* The GPU BVH: nodes16[num_nodes * 16] (each node: child-0 box lo.xyz hi.xyz,
- * child-1 box lo.xyz hi.xyz, two int32 child references: >= 0 inner node,
- * < 0 leaf with ~ref = first << 3 | (count - 1)) and tri_order[num_triangles]
- * (input id of each leaf-order triangle). Pointers may be NULL. After
- * qpt_build_bvh. */
-int qpt_debug_bvh_nodes(const qpt_ctx *ctx, float *nodes16, uint32_t *tri_order, uint32_t *num_nodes);
+/* The GPU BVH (4-wide): nodes32[num_nodes * 32], each node 32 values: the
+ * four children's boxes as lo.x[4], lo.y[4], lo.z[4], hi.x[4], hi.y[4],
+ * hi.z[4], then four int32 child references (>= 0 inner node, INT32_MIN
+ * unused slot, other < 0 leaf with ~ref = first << 3 | (count - 1)), then
+ * the number of used slots and three unused words; and
+ * tri_order[num_triangles] (input id of each leaf-order triangle). Pointers
+ * may be NULL. After qpt_build_bvh. */
+int qpt_debug_bvh_nodes(const qpt_ctx *ctx, float *nodes32, uint32_t *tri_order, uint32_t *num_nodes);
 
 #ifdef __cplusplus
 }

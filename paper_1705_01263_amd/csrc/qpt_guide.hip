@@ -403,9 +403,13 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
     __shared__ float sbias[256];
+    const uint32_t n = src.debug ? src.n : P.counters[src.v];
+    // the grid is sized for the largest queue: blocks without rows leave
+    // before staging the 28 KB of weights (uniform per block, so no barrier
+    // is skipped by part of a block)
+    if ((size_t)blockIdx.x * (blockDim.x / 2) >= n) return;
     load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
     __syncthreads();
-    const uint32_t n = src.debug ? src.n : P.counters[src.v];
     const uint32_t *q = P.q_ext[src.v & 1];
     float4 *mix_out = src.debug ? src.out : F.guide.mix;
     const uint32_t lane = lane_id(), h = lane >> 5;

@@ -326,6 +326,7 @@ struct qpt_ctx {
     qpt_guide_opts gopts{0.0f, 1e-3f, 1u << 18, 0, 1, 0};
     bool guide_weights = false;
     uint32_t guide_steps = 0;
+    uint32_t stack_need = 3;      // traversal stack entries per ray the BVH can require
     double bbox[6] = {0, 0, 0, 1, 1, 1};
     EventProfiler prof;
     bool profiling = false;
@@ -637,7 +638,7 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.sh_d = take((size_t)cap * 16);
     L.sh_c = take((size_t)cap * 16);
     L.counters = take(128 * 4);
-    L.gstack = take((size_t)c->trav_threads * kDeepStack * 4);
+    L.gstack = take((size_t)c->trav_threads * (c->stack_need > kShortStack ? c->stack_need - kShortStack : 1u) * 4);
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
@@ -804,79 +805,94 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
     int budget = 0;
     while ((1u << budget) < 2 * hw && budget < 6) ++budget;
     B.build(0, nt, 0, budget);
-    uint32_t nn = B.next.load();
-    if (B.max_depth.load() >= kMaxTreeDepth) return fail(c, QPT_E_INVALID, "BVH deeper than the traversal stack");
+    if (B.max_depth.load() >= kMaxTreeDepth) return fail(c, QPT_E_INVALID, "binary BVH deeper than its limit");
 
     // boxes padded outward so that rounding in the slab test never culls a
     // triangle the exact triangle test would report
     float pad = (float)(std::ldexp(std::max(maxabs, 1e-3), -18));
-    // flatten: inner nodes in depth-first order, leaves become references
-    std::vector<int32_t> remap(nn, -1);
-    std::vector<uint32_t> dfs;
-    dfs.reserve(nn);
-    std::vector<uint32_t> stack = {0};
-    while (!stack.empty()) {
-        uint32_t q = stack.back();
-        stack.pop_back();
-        const BuildNode &bn = B.nodes[q];
-        if (bn.count) continue;
-        remap[q] = (int32_t)dfs.size();
-        dfs.push_back(q);
-        stack.push_back((uint32_t)bn.right);
-        stack.push_back((uint32_t)bn.left);
-    }
-    auto ref_of = [&](uint32_t q) -> int32_t {
-        const BuildNode &bn = B.nodes[q];
-        if (bn.count) return ~(int32_t)((bn.first << 3) | (bn.count - 1));
-        return remap[q];
-    };
-    auto set_box = [&](float *dst, const BuildNode &bn) {
-        for (int a = 0; a < 3; ++a) {
-            dst[a] = bn.lo[a] - pad;
-            dst[3 + a] = bn.hi[a] + pad;
-        }
-    };
+    // collapse into a 4-wide tree: each node takes its binary node's two
+    // children and keeps opening the inner child of largest surface area
+    // until it has four; siblings are stored next to each other
+    auto leaf_ref = [&](const BuildNode &bn) -> int32_t { return ~(int32_t)((bn.first << 3) | (bn.count - 1)); };
     c->gnodes.clear();
-    uint32_t leaves = 0;
+    uint32_t leaves = 0, depth4 = 0;
     double sah = 0.0;
     const BuildNode &root = B.nodes[0];
-    float root_area = Builder::area(root.lo, root.hi);
-    if (root.count) {
-        // a single leaf: one inner node whose two children are that leaf (the
-        // duplicate test of the same triangles cannot change the closest hit)
-        Node n{};
-        float bx[6];
-        set_box(bx, root);
-        n.a = make_float4(bx[0], bx[1], bx[2], bx[3]);
-        n.b = make_float4(bx[4], bx[5], bx[0], bx[1]);
-        n.c = make_float4(bx[2], bx[3], bx[4], bx[5]);
-        n.d = make_int4(ref_of(0), ref_of(0), 0, 0);
-        c->gnodes.push_back(n);
-        leaves = 1;
-        sah = root.count;
-    } else {
-        c->gnodes.resize(dfs.size());
-        for (size_t k = 0; k < dfs.size(); ++k) {
-            const BuildNode &bn = B.nodes[dfs[k]];
-            const BuildNode &l = B.nodes[bn.left], &r = B.nodes[bn.right];
-            float b0[6], b1[6];
-            set_box(b0, l);
-            set_box(b1, r);
-            Node n;
-            n.a = make_float4(b0[0], b0[1], b0[2], b0[3]);
-            n.b = make_float4(b0[4], b0[5], b1[0], b1[1]);
-            n.c = make_float4(b1[2], b1[3], b1[4], b1[5]);
-            n.d = make_int4(ref_of(bn.left), ref_of(bn.right), 0, 0);
-            c->gnodes[k] = n;
-            float a = Builder::area(bn.lo, bn.hi) / root_area;
-            sah += a;
-            for (const BuildNode *ch : {&l, &r})
-                if (ch->count) {
-                    ++leaves;
-                    sah += Builder::area(ch->lo, ch->hi) / root_area * ch->count;
+    const float root_area = std::max(Builder::area(root.lo, root.hi), 1e-30f);
+    struct Item {
+        uint32_t q, slot, depth;
+    };
+    std::vector<Item> work;
+    c->gnodes.emplace_back();
+    work.push_back({0u, 0u, 0u});
+    while (!work.empty()) {
+        Item it = work.back();
+        work.pop_back();
+        depth4 = std::max(depth4, it.depth);
+        const BuildNode &bn = B.nodes[it.q];
+        uint32_t kids[4];
+        uint32_t nk = 0;
+        if (bn.count) {
+            kids[nk++] = it.q;  // the whole tree is one leaf
+        } else {
+            kids[nk++] = (uint32_t)bn.left;
+            kids[nk++] = (uint32_t)bn.right;
+            while (nk < 4) {
+                int best = -1;
+                float ba = -1.0f;
+                for (uint32_t k = 0; k < nk; ++k) {
+                    const BuildNode &ch = B.nodes[kids[k]];
+                    if (ch.count) continue;
+                    float a = Builder::area(ch.lo, ch.hi);
+                    if (a > ba) {
+                        ba = a;
+                        best = (int)k;
+                    }
                 }
+                if (best < 0) break;
+                const BuildNode &op = B.nodes[kids[best]];
+                kids[best] = (uint32_t)op.left;
+                kids[nk++] = (uint32_t)op.right;
+            }
         }
+        sah += Builder::area(bn.lo, bn.hi) / root_area;
+        float bx[6][4];
+        int32_t ref[4];
+        for (uint32_t k = 0; k < 4; ++k) {
+            if (k >= nk) {
+                for (int a = 0; a < 6; ++a) bx[a][k] = 0.0f;
+                ref[k] = kEmptyChild;
+                continue;
+            }
+            const BuildNode &ch = B.nodes[kids[k]];
+            for (int a = 0; a < 3; ++a) {
+                bx[a][k] = ch.lo[a] - pad;
+                bx[3 + a][k] = ch.hi[a] + pad;
+            }
+            if (ch.count) {
+                ref[k] = leaf_ref(ch);
+                ++leaves;
+                sah += Builder::area(ch.lo, ch.hi) / root_area * ch.count;
+            } else {
+                uint32_t slot = (uint32_t)c->gnodes.size();
+                c->gnodes.emplace_back();
+                ref[k] = (int32_t)slot;
+                work.push_back({kids[k], slot, it.depth + 1});
+            }
+        }
+        Node n;
+        n.lox = make_float4(bx[0][0], bx[0][1], bx[0][2], bx[0][3]);
+        n.loy = make_float4(bx[1][0], bx[1][1], bx[1][2], bx[1][3]);
+        n.loz = make_float4(bx[2][0], bx[2][1], bx[2][2], bx[2][3]);
+        n.hix = make_float4(bx[3][0], bx[3][1], bx[3][2], bx[3][3]);
+        n.hiy = make_float4(bx[4][0], bx[4][1], bx[4][2], bx[4][3]);
+        n.hiz = make_float4(bx[5][0], bx[5][1], bx[5][2], bx[5][3]);
+        n.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
+        n.pad = make_int4((int)nk, 0, 0, 0);
+        c->gnodes[it.slot] = n;
     }
+    // a ray at a node of depth d holds at most 3 (d + 1) stack entries
+    c->stack_need = 3 * (depth4 + 1);
     // triangles in leaf order
     c->gtris.resize(nt);
     c->emit_tri_bvh.assign(c->emit_input_tri.size(), 0);
@@ -900,7 +916,7 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
     if (stats) {
         stats->num_nodes = (uint32_t)c->gnodes.size();
         stats->num_leaves = leaves;
-        stats->max_depth = B.max_depth.load();
+        stats->max_depth = depth4;
         stats->reserved = 0;
         stats->sah_cost = sah;
         stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -1324,12 +1340,12 @@ int qpt_debug_env_tables(const qpt_ctx *c, uint32_t *row_q, uint32_t *col_q, flo
     return QPT_OK;
 }
 
-int qpt_debug_bvh_nodes(const qpt_ctx *c, float *nodes16, uint32_t *tri_order, uint32_t *num_nodes)
+int qpt_debug_bvh_nodes(const qpt_ctx *c, float *nodes32, uint32_t *tri_order, uint32_t *num_nodes)
 {
     if (!c || !num_nodes) return QPT_E_INVALID;
     if (!c->bvh_ok) return QPT_E_STATE;
     *num_nodes = (uint32_t)c->gnodes.size();
-    if (nodes16) std::memcpy(nodes16, c->gnodes.data(), c->gnodes.size() * sizeof(Node));
+    if (nodes32) std::memcpy(nodes32, c->gnodes.data(), c->gnodes.size() * sizeof(Node));
     if (tri_order)
         for (size_t k = 0; k < c->gtris.size(); ++k) std::memcpy(&tri_order[k], &c->gtris[k].v1.w, 4);
     return QPT_OK;

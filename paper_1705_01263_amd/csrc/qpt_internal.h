@@ -8,8 +8,7 @@ namespace qpt {
 
 constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
 constexpr uint32_t kShortStack = 16;     // traversal stack entries per ray kept in LDS
-constexpr uint32_t kDeepStack = 16;      // further entries in a global overflow area
-constexpr uint32_t kMaxTreeDepth = 32;   // builder guarantee: kShortStack + kDeepStack suffice
+constexpr uint32_t kMaxTreeDepth = 32;   // depth limit of the binary build tree
 constexpr uint32_t kTravBlocksPerCU = 8; // traversal grid: 8 resident blocks x 4 waves per CU
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
 constexpr uint32_t kNoHit = 0xffffffffu;
@@ -28,13 +27,16 @@ struct HaltonBase {
     uint64_t m64;      // magic for n/B, n < 2^64
 };
 
-// BVH2 node: both children's boxes plus child references (64 bytes).
-// ref >= 0: inner node index. ref < 0: leaf, ~ref = first << 3 | (count - 1).
+// 4-wide BVH node (128 bytes, one L2 line): the four children's boxes as
+// SoA float4 (component c = child c) and their references.
+// ref >= 0: inner node index; ref == kEmptyChild: unused slot;
+// other ref < 0: leaf, ~ref = first << 3 | (count - 1).
+constexpr int32_t kEmptyChild = (int32_t)0x80000000;
 struct alignas(16) Node {
-    float4 a;   // c0.lo.xyz, c0.hi.x
-    float4 b;   // c0.hi.yz,  c1.lo.xy
-    float4 c;   // c1.lo.z,   c1.hi.xyz
-    int4 d;     // ref0, ref1, -, -
+    float4 lox, loy, loz;
+    float4 hix, hiy, hiz;
+    int4 ref;
+    int4 pad;
 };
 
 // Triangle in BVH order (48 bytes): v0.w = material, v1.w = input id,
@@ -123,7 +125,7 @@ struct Pool {
     float4 *sh_d;       // shadow ray d.xyz, slot (bits)
     float4 *sh_c;       // pending contribution rgb, -
     uint32_t *counters;     // [0..63] ext counts per depth, [64..127] shadow counts
-    int *gstack;            // traversal stack overflow, kDeepStack per traversal thread
+    int *gstack;            // traversal stack overflow, deep_stack entries per traversal thread
     uint32_t trav_threads;  // threads of the traversal grid (gstack stride)
     // [0] ext rays [1] shadow rays [2] paths [3] - [4] ext node visits
     // [5] ext triangle tests [6] shadow node visits [7] shadow triangle tests

@@ -219,24 +219,32 @@ __device__ __forceinline__ bool tri_test(const RayPre &r, float4 v0, float4 v1, 
     return true;
 }
 
-// slab test of both children of a node against [0, tlim]
-__device__ __forceinline__ void node_test(const Node &n, const RayPre &r, float tlim, bool &h0, bool &h1,
-                                          float &tn0, float &tn1)
+// slab test of child c against [0, tlim]: a sort key (entry distance with
+// the child slot in the two low bits; entry distances are >= 0, so unsigned
+// order is distance order) or ~0 for a miss or an unused slot
+__device__ __forceinline__ uint32_t child_key(float lox, float loy, float loz, float hix, float hiy, float hiz,
+                                              int32_t ref, const RayPre &r, f3 oi, float tlim, uint32_t c)
 {
-    f3 oi = r.o * r.inv;
-    float lx0 = fmaf(n.a.x, r.inv.x, -oi.x), hx0 = fmaf(n.a.w, r.inv.x, -oi.x);
-    float ly0 = fmaf(n.a.y, r.inv.y, -oi.y), hy0 = fmaf(n.b.x, r.inv.y, -oi.y);
-    float lz0 = fmaf(n.a.z, r.inv.z, -oi.z), hz0 = fmaf(n.b.y, r.inv.z, -oi.z);
-    float lx1 = fmaf(n.b.z, r.inv.x, -oi.x), hx1 = fmaf(n.c.y, r.inv.x, -oi.x);
-    float ly1 = fmaf(n.b.w, r.inv.y, -oi.y), hy1 = fmaf(n.c.z, r.inv.y, -oi.y);
-    float lz1 = fmaf(n.c.x, r.inv.z, -oi.z), hz1 = fmaf(n.c.w, r.inv.z, -oi.z);
-    tn0 = fmaxf(fmaxf(fminf(lx0, hx0), fminf(ly0, hy0)), fmaxf(fminf(lz0, hz0), 0.0f));
-    float tf0 = fminf(fminf(fmaxf(lx0, hx0), fmaxf(ly0, hy0)), fminf(fmaxf(lz0, hz0), tlim));
-    tn1 = fmaxf(fmaxf(fminf(lx1, hx1), fminf(ly1, hy1)), fmaxf(fminf(lz1, hz1), 0.0f));
-    float tf1 = fminf(fminf(fmaxf(lx1, hx1), fmaxf(ly1, hy1)), fminf(fmaxf(lz1, hz1), tlim));
+    float lx = fmaf(lox, r.inv.x, -oi.x), hx = fmaf(hix, r.inv.x, -oi.x);
+    float ly = fmaf(loy, r.inv.y, -oi.y), hy = fmaf(hiy, r.inv.y, -oi.y);
+    float lz = fmaf(loz, r.inv.z, -oi.z), hz = fmaf(hiz, r.inv.z, -oi.z);
+    float tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), 0.0f));
+    float tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fminf(fmaxf(lz, hz), tlim));
     // the padded boxes make a relative slack of a few ulps harmless
-    h0 = tn0 <= tf0 * 1.0000005f;
-    h1 = tn1 <= tf1 * 1.0000005f;
+    bool hit = ref != kEmptyChild && tn <= tf * 1.0000005f;
+    return hit ? ((__float_as_uint(tn) & ~3u) | c) : ~0u;
+}
+
+__device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b)
+{
+    uint32_t lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+__device__ __forceinline__ int32_t child_ref(const int4 &ref, uint32_t c)
+{
+    return c == 0 ? ref.x : (c == 1 ? ref.y : (c == 2 ? ref.z : ref.w));
 }
 
 struct HitRec {
@@ -253,11 +261,15 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
     if (__lane_id() == 0 && v) atomicAdd(ctr, (unsigned long long)v);
 }
 
-// Closest hit (ANY = false) or occlusion (ANY = true) through the BVH (Sec.
-// 2.3: watertight traversal). The stack keeps kShortStack entries per thread
-// in LDS, laid out [entry][thread] (bank-conflict free), and spills deeper
-// entries to a per-thread global area (stride gs); the small LDS footprint
-// lets 8 waves share a SIMD to hide the latency of the dependent node loads.
+// Closest hit (ANY = false) or occlusion (ANY = true) through the 4-wide BVH
+// (Sec. 2.3: watertight traversal). At each node the four slab tests give
+// sort keys; a 5-comparator network orders them, the nearest hit child is
+// visited next and the others are pushed farthest first. The stack keeps
+// kShortStack entries per thread in LDS, laid out [entry][thread] (bank-
+// conflict free), and spills deeper entries to a per-thread global area
+// (stride gs) sized by the host for the tree's depth (at most 3 pushes per
+// level). Children are culled against the current closest t with a closed
+// interval, so the result does not depend on the visiting order.
 template <bool ANY>
 __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs)
 {
@@ -269,24 +281,30 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
     int sp = 0;
     int ref = 0;
     const int step = (int)blockDim.x;
+    const f3 oi = r.o * r.inv;
+    auto push = [&](int v) {
+        if (sp < (int)kShortStack) stk[sp * step] = v;
+        else gstk[(sp - kShortStack) * gs] = v;
+        ++sp;
+    };
     while (true) {
         if (ref >= 0) {
             const Node n = F.nodes[ref];
             ++h.nodes;
-            bool h0, h1;
-            float t0, t1;
-            node_test(n, r, h.t, h0, h1, t0, t1);
-            if (h0 && h1) {
-                bool swap = t1 < t0;
-                int nearr = swap ? n.d.y : n.d.x, farr = swap ? n.d.x : n.d.y;
-                if (sp < (int)kShortStack) stk[sp * step] = farr;
-                else gstk[(sp - kShortStack) * gs] = farr;
-                ++sp;
-                ref = nearr;
-                continue;
-            }
-            if (h0 || h1) {
-                ref = h0 ? n.d.x : n.d.y;
+            uint32_t k0 = child_key(n.lox.x, n.loy.x, n.loz.x, n.hix.x, n.hiy.x, n.hiz.x, n.ref.x, r, oi, h.t, 0);
+            uint32_t k1 = child_key(n.lox.y, n.loy.y, n.loz.y, n.hix.y, n.hiy.y, n.hiz.y, n.ref.y, r, oi, h.t, 1);
+            uint32_t k2 = child_key(n.lox.z, n.loy.z, n.loz.z, n.hix.z, n.hiy.z, n.hiz.z, n.ref.z, r, oi, h.t, 2);
+            uint32_t k3 = child_key(n.lox.w, n.loy.w, n.loz.w, n.hix.w, n.hiy.w, n.hiz.w, n.ref.w, r, oi, h.t, 3);
+            cswap(k0, k1);
+            cswap(k2, k3);
+            cswap(k0, k2);
+            cswap(k1, k3);
+            cswap(k1, k2);
+            if (k0 != ~0u) {
+                if (k3 != ~0u) push(child_ref(n.ref, k3 & 3u));
+                if (k2 != ~0u) push(child_ref(n.ref, k2 & 3u));
+                if (k1 != ~0u) push(child_ref(n.ref, k1 & 3u));
+                ref = child_ref(n.ref, k0 & 3u);
                 continue;
             }
         } else {

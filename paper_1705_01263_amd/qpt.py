@@ -309,7 +309,7 @@ class Context:
     def debug_bvh_nodes(self):
         nn = C.c_uint32()
         self.check(self.L.qpt_debug_bvh_nodes(self.h, None, None, C.byref(nn)), "qpt_debug_bvh_nodes")
-        nodes = np.empty((nn.value, 16), np.float32)
+        nodes = np.empty((nn.value, 32), np.float32)
         order = np.empty(self.ntri, np.uint32) if hasattr(self, "ntri") else None
         self.check(self.L.qpt_debug_bvh_nodes(self.h, _p(nodes), _p(order), C.byref(nn)), "qpt_debug_bvh_nodes")
         return nodes, order

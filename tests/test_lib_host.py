@@ -81,8 +81,12 @@ def test_env_tables_match_oracle(qpt, orc):
     assert np.array_equal(pdf, opdf.astype(np.float32))
 
 
-@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=4)])
+@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=4),
+                                  lambda: g.quad_over_plane()])
 def test_bvh_structure(qpt, make):
+    """The 4-wide tree: every triangle in exactly one leaf and inside its
+    box, every child box inside its parent's slot box, 2-4 used slots per
+    node (1 when the whole tree is one leaf), siblings stored together."""
     sc = make()
     c = qpt.Context(-1)
     c.ntri = sc.num_triangles
@@ -90,25 +94,40 @@ def test_bvh_structure(qpt, make):
     st = c.build_bvh()
     assert st.max_depth < 32
     nodes, order = c.debug_bvh_nodes()
-    # every triangle appears in exactly one leaf, inside that leaf's box
+    assert nodes.shape[0] == st.num_nodes
     assert np.array_equal(np.sort(order), np.arange(sc.num_triangles, dtype=np.uint32))
-    refs = nodes[:, 12:14].copy().view(np.int32)
-    boxes = [nodes[:, 0:6], nodes[:, 6:12]]
+    lo = nodes[:, 0:12].reshape(-1, 3, 4)   # [node, axis, child]
+    hi = nodes[:, 12:24].reshape(-1, 3, 4)
+    refs = nodes[:, 24:28].copy().view(np.int32)
+    used = nodes[:, 28:29].copy().view(np.int32)[:, 0]
     pos = sc.positions[sc.indices[order]]  # BVH order, (nt, 3, 3)
     seen = np.zeros(sc.num_triangles, np.int32)
+    parents = np.zeros(nodes.shape[0], np.int32)
+    leaves = 0
     for k in range(nodes.shape[0]):
-        for ch in range(2):
+        nu = int(used[k])
+        assert (2 <= nu <= 4) or (nodes.shape[0] == 1 and nu == 1)
+        for ch in range(4):
             r = int(refs[k, ch])
-            lo, hi = boxes[ch][k, 0:3], boxes[ch][k, 3:6]
+            if ch >= nu:
+                assert r == -(2 ** 31)
+                continue
+            assert r != -(2 ** 31)
+            blo, bhi = lo[k, :, ch], hi[k, :, ch]
             if r >= 0:
-                # child box contains the child's own boxes
-                for cc in range(2):
-                    assert np.all(boxes[cc][r, 0:3] >= lo) and np.all(boxes[cc][r, 3:6] <= hi)
+                parents[r] += 1
+                cu = int(used[r])
+                assert np.all(lo[r, :, :cu] >= blo[:, None]) and np.all(hi[r, :, :cu] <= bhi[:, None])
             else:
                 p = ~np.int64(r) & 0xFFFFFFFF
                 first, cnt = p >> 3, (p & 7) + 1
                 tri = pos[first:first + cnt]
-                assert np.all(tri >= lo) and np.all(tri <= hi)
-                if not (nodes.shape[0] == 1 and ch == 1):
-                    seen[first:first + cnt] += 1
+                assert np.all(tri >= blo) and np.all(tri <= bhi)
+                seen[first:first + cnt] += 1
+                leaves += 1
+        kids = [int(x) for x in refs[k, :nu] if x >= 0]
+        if kids:
+            assert max(kids) - min(kids) == len(kids) - 1  # siblings contiguous
     assert np.all(seen == 1)
+    assert parents[0] == 0 and np.all(parents[1:] == 1)
+    assert leaves == st.num_leaves
