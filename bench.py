@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
+GUIDE_ALPHA, GUIDE_WARMUP = 0.5, 8
 
 # algorithmic bytes per unit of work ("Measurement")
 NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
@@ -96,6 +97,97 @@ def cpu_baseline(sc, seconds: float):
     }
 
 
+def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: int, height: int, tris: int):
+    """Equal-time RMSE of the plain and the guided tracer on the slit workload.
+
+    Both runs get the same wall time on the same GPU, the guided one
+    including its online training from an untrained network. The error is
+    measured against (a) the plain tracer at `ref_passes` passes from an
+    independent pass range (FP64 accumulation, whole frame) and (b) the FP64
+    CPU oracle on a bounded pixel sample, also from an independent pass range.
+    """
+    import numpy as np
+    import torch
+
+    import oracle
+    import scenegen
+    from paper_1705_01263_amd import Renderer
+
+    sc = scenegen.slit_scene(width=width, height=height, target_tris=tris, max_depth=16)
+    _say(f"bench: equal-time workload {sc.name} tris={sc.num_triangles} {width}x{height} D=16")
+    r = Renderer(sc, device=0)
+
+    def run_for(budget, guided):
+        r.reset()
+        if guided:
+            r.ctx.guide_set_weights(scenegen.guide_init(1))
+            r.ctx.guide_config(alpha=GUIDE_ALPHA, lr=1e-3, batch=1 << 18, train=1, warmup_steps=GUIDE_WARMUP, seed=1)
+        else:
+            r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget:
+            r.render(n, 4)
+            n += 4
+            torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s, c = r.readback()
+        return s / c[:, None], n, dt
+
+    r.render(0, 4)  # warm-up (module load, first launches)
+    torch.cuda.synchronize()
+    plain, n_p, t_p = run_for(seconds, False)
+    guided, n_g, t_g = run_for(t_p, True)
+    loss = r.ctx.guide_loss()[0]
+    # GPU reference from passes no run above used
+    r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
+    r.reset()
+    t0 = time.perf_counter()
+    r.render(1 << 24, ref_passes)
+    s, c = r.readback()
+    ref = s / c[:, None]
+    t_ref = time.perf_counter() - t0
+    del r
+    torch.cuda.empty_cache()
+    rmse = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))
+    out = {
+        "workload": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth 16, sun and sky through a "
+                    "0.1-wide roof slit",
+        "seconds": round(t_p, 3),
+        "plain": {"passes": n_p, "seconds": round(t_p, 3), "rmse_vs_gpu_reference": rmse(plain, ref)},
+        "guided": {"passes": n_g, "seconds": round(t_g, 3), "rmse_vs_gpu_reference": rmse(guided, ref),
+                   "alpha": GUIDE_ALPHA, "train_steps": n_g // 4, "final_loss": round(loss, 4)},
+        "gpu_reference": {"passes": ref_passes, "first_pass": 1 << 24, "seconds": round(t_ref, 2)},
+    }
+    # FP64 oracle reference on a pixel sample
+    if oracle_seconds > 0:
+        t0 = time.perf_counter()
+        S = oracle.Scene(sc)
+        build_s = time.perf_counter() - t0
+        ys, xs = np.meshgrid(np.arange(height // 32, height, height // 16), np.arange(width // 64, width, width // 32),
+                             indexing="ij")
+        pix = (ys * width + xs).reshape(-1).astype(np.uint32)
+        threads = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1, 16)
+        acc = np.zeros((pix.shape[0], 3))
+        n_o = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < oracle_seconds:
+            s_o, _, cnt, _ = S.render(pixels=pix, pass0=(1 << 25) + n_o, npasses=16, nthreads=threads)
+            acc += s_o
+            n_o += 16
+        o_ref = acc / n_o
+        out["oracle_reference"] = {"pixels": int(pix.shape[0]), "passes": n_o, "first_pass": 1 << 25,
+                                   "threads": threads, "seconds": round(time.perf_counter() - t0, 1),
+                                   "bvh_build_s": round(build_s, 1)}
+        out["plain"]["rmse_vs_oracle_sample"] = rmse(plain[pix], o_ref)
+        out["guided"]["rmse_vs_oracle_sample"] = rmse(guided[pix], o_ref)
+        out["gpu_reference_rmse_vs_oracle_sample"] = rmse(ref[pix], o_ref)
+    out["guided_over_plain_rmse"] = round(out["guided"]["rmse_vs_gpu_reference"] /
+                                          out["plain"]["rmse_vs_gpu_reference"], 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +196,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-equal-time", action="store_true", help="skip the guided vs plain equal-time RMSE leg")
+    ap.add_argument("--et-seconds", type=float, default=1.5, help="wall time of each equal-time run")
+    ap.add_argument("--et-ref-passes", type=int, default=1024)
+    ap.add_argument("--et-oracle-seconds", type=float, default=10.0)
+    ap.add_argument("--et-size", type=str, default="1920x1080")
+    ap.add_argument("--et-tris", type=int, default=4_000_000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -196,6 +294,14 @@ def main():
         _say(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(sc, args.cpu_seconds)
 
+    et = None
+    if not args.no_equal_time:
+        del r
+        torch.cuda.empty_cache()
+        w, h = (int(v) for v in args.et_size.split("x"))
+        et = equal_time(args.et_seconds, args.et_ref_passes, args.et_oracle_seconds, w, h, args.et_tris)
+        _say(f"bench: equal time {et}")
+
     out = {
         "metric": METRIC, "value": round(mrays, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
@@ -208,6 +314,7 @@ def main():
         "rays_per_path": round((ext + sh) / paths, 3),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "equal_time_rmse": et,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)

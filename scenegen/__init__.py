@@ -296,6 +296,23 @@ def _random_surface_material(b: _Builder, rng: SplitMix64) -> int:
     return b.material(rho, roughness=alpha, flags=MAT_GGX)
 
 
+def cornell_indirect(seed: int = 1, width=128, height=128, spp=64, max_depth=8) -> Scene:
+    """The Cornell room with its light turned to face the ceiling 0.07 below
+    it: every visible surface is lit only indirectly, through the bright spot
+    the light throws on the ceiling."""
+    sc = cornell(seed, width, height, spp, max_depth)
+    em = np.nonzero(sc.emission.max(axis=1) > 0)[0]
+    lt = np.isin(sc.tri_material, em)
+    vids = np.unique(sc.indices[lt])
+    sc.positions = sc.positions.copy()
+    sc.positions[vids, 1] = np.float32(0.93)
+    sc.indices = sc.indices.copy()
+    sc.indices[lt] = sc.indices[lt][:, [0, 2, 1]]
+    sc.name = "cornell_indirect"
+    sc.validate()
+    return sc
+
+
 def grid_scene(seed: int = 2, width=1920, height=1080, spp=64, max_depth=12,
                grid=20, spacing=2.2) -> Scene:
     """Seeded grid of tessellated spheres and boxes on a ground plane, 256 textured emitters."""
