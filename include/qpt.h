@@ -197,6 +197,7 @@ typedef struct {
                                 that batch's records (0: no recording or training; at most 64) */
     uint32_t warmup_steps;   /* guide sampling stays off until this many steps were taken */
     uint32_t seed;           /* offsets of the stratified batch subsets */
+    uint32_t max_vertex;     /* guide (and record) at path vertices 1..max_vertex only; 0 = every vertex */
 } qpt_guide_opts;
 
 /* Set the guide options (takes effect at the next qpt_render_pass). */

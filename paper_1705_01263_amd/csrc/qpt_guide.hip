@@ -30,11 +30,10 @@ constexpr int kOffW[4] = {0, 2112, 6272, 10432};
 constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
 constexpr int kTrainBlock = 256;               // 4 waves
 
+// round to the nearest BF16, ties to even (v_cvt_pk_bf16_f32 on gfx950)
 __device__ __forceinline__ uint32_t bf16_rne(float f)
 {
-    uint32_t b = __float_as_uint(f);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return b >> 16;
+    return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
@@ -362,28 +361,29 @@ __device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const flo
 {
     const uint32_t h = lane_id() >> 5;
     float xh[3] = {(x.x - bmin[0]) / bext[0], (x.y - bmin[1]) / bext[1], (x.z - bmin[2]) / bext[2]};
+    const float m0 = 0.5f * guide::kOct[2 * h], m1 = 0.5f * guide::kOct[2 * h + 1];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float s0, c0, s1, c1;
-        sincosf(guide::kOct[2 * h] * guide::kPiF * xh[a], &s0, &c0);
-        sincosf(guide::kOct[2 * h + 1] * guide::kPiF * xh[a], &s1, &c1);
+        guide::sincos_rev(m0 * xh[a], &s0, &c0);
+        guide::sincos_rev(m1 * xh[a], &s1, &c1);
         a0[a] = pack4(s0, c0, s1, c1);
     }
-    float ang0, ang1;
+    float r0, r1;
     if (h == 0) {
         float th = acosf(fminf(1.0f, fmaxf(-1.0f, wo.y))) / guide::kPiF;
-        ang0 = guide::kPiF * th;
-        ang1 = 2.0f * guide::kPiF * th;
+        r0 = 0.5f * th;
+        r1 = th;
     } else {
         float ph = atan2f(wo.x, -wo.z);
         if (ph < 0.0f) ph += 2.0f * guide::kPiF;
         ph *= 1.0f / (2.0f * guide::kPiF);
-        ang0 = 2.0f * guide::kPiF * ph;
-        ang1 = 4.0f * guide::kPiF * ph;
+        r0 = ph;
+        r1 = 2.0f * ph;
     }
     float s0, c0, s1, c1;
-    sincosf(ang0, &s0, &c0);
-    sincosf(ang1, &s1, &c1);
+    guide::sincos_rev(r0, &s0, &c0);
+    guide::sincos_rev(r1, &s1, &c1);
     a0[3] = pack4(s0, c0, s1, c1);
 }
 
@@ -476,7 +476,9 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
     }
 }
 
-// training records -> candidates with a positive loss weight
+// training records -> candidates with a positive loss weight: the luminance
+// of the sample's own estimate f cos L_i / p of the scattering integral, so
+// that the network learns a density proportional to the integrand
 __global__ void k_rec_finalize(Frame F, Pool P, GuideTrain T)
 {
     uint32_t cnt = min(*F.guide.rec_count, F.guide.rec_cap);
@@ -485,15 +487,17 @@ __global__ void k_rec_finalize(Frame F, Pool P, GuideTrain T)
         bool ok = false;
         if (i < cnt) {
             float4 *r = F.guide.rec + (size_t)i * kRecF4;
-            float4 r0 = r[0], r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5];
+            float4 r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5];
             float4 L = P.rad[__float_as_uint(r2.w)];
             float li[3] = {(L.x - r3.x - r5.x), (L.y - r3.y - r5.y), (L.z - r3.z - r5.z)};
-            float ta[3] = {r4.x, r4.y, r4.z};
-            float lum = 0.0f;
+            float tb[3] = {r4.x, r4.y, r4.z};
+            float w = 0.0f;
             const float wl[3] = {0.2126f, 0.7152f, 0.0722f};
-            for (int c = 0; c < 3; ++c) lum += ta[c] > 0.0f ? wl[c] * fmaxf(0.0f, li[c] / ta[c]) : 0.0f;
-            r[1].w = lum;
-            float w = lum / r0.w;
+            for (int c = 0; c < 3; ++c) w += tb[c] > 0.0f ? wl[c] * fmaxf(0.0f, li[c] / tb[c]) : 0.0f;
+#if QPT_GUIDE_W2
+            w = w * w;
+#endif
+            r[1].w = w;
             ok = w > 0.0f && w < INFINITY;
         }
         unsigned long long mask = __ballot(ok);
@@ -559,7 +563,7 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
                 float4 r0 = r[0], r1 = r[1], r2 = r[2];
                 guide::encode(guide::V3{r0.x, r0.y, r0.z}, guide::V3{r1.x, r1.y, r1.z}, F.guide.bmin, F.guide.bext, f);
                 wd = {r2.x, r2.y, r2.z};
-                wt = r1.w / r0.w;
+                wt = r1.w;
             }
         }
         v4s a0[4];

@@ -323,7 +323,7 @@ struct qpt_ctx {
     uint32_t trav_threads = 0;  // traversal grid: CUs x resident blocks per CU x block size
     uint32_t guide_blocks = 256;  // training blocks (one per CU)
     GuideTrain gt{};
-    qpt_guide_opts gopts{0.0f, 1e-3f, 1u << 18, 0, 1, 0};
+    qpt_guide_opts gopts{0.0f, 1e-3f, 1u << 18, 0, 1, 0, 0};
     bool guide_weights = false;
     uint32_t guide_steps = 0;
     uint32_t stack_need = 3;      // traversal stack entries per ray the BVH can require
@@ -1084,6 +1084,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         f.guide.alpha_thr = (uint32_t)std::min<uint64_t>(thr, 0xffffffffull);
         f.guide.alpha = (float)((double)f.guide.alpha_thr / 4294967296.0);
         f.guide.record = c->gopts.train ? 1u : 0u;
+        f.guide.max_vertex = c->gopts.max_vertex ? c->gopts.max_vertex : 0xffffffffu;
         HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
         if (c->gopts.train) {
             HIP_TRY(c, launch_guide_train_step(f, c->pool, c->gt, c->gopts.batch ? c->gopts.batch : (1u << 18),

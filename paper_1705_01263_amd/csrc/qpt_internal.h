@@ -65,6 +65,7 @@ struct GuideDev {
     uint32_t alpha_thr;      // guide iff sample bits < alpha_thr (0: BSDF sampling only)
     float alpha;             // alpha_thr / 2^32
     uint32_t record;         // capture training records
+    uint32_t max_vertex;     // guide and record at path vertices 1..max_vertex
     float4 *rec;             // kRecF4 float4 per record
     uint32_t rec_cap;
     uint32_t *rec_count;

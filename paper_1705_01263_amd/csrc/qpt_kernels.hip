@@ -657,7 +657,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                     f3 xo = offset_ray(x, nn);
                     uint64_t idx = P.idx[slot];
                     // learned proposal: this vertex's mixture (alpha = 0 leaves plain BSDF sampling)
-                    const bool guided = F.guide.alpha_thr != 0u;
+                    const bool guided = F.guide.alpha_thr != 0u && v <= F.guide.max_vertex;
                     guide::Mix mix;
                     if (guided) {
                         const float4 *src = F.guide.mix + (size_t)slot * 10;
@@ -749,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                     // the direction. The density is the one-sample mixture
                     // alpha q + (1 - alpha) p_bsdf, so the estimator stays unbiased.
                     uint32_t s3 = sample_bits(F, idx, base_dim + 3, F.scramble);
-                    bool use_guide = s3 < F.guide.alpha_thr;
+                    bool use_guide = guided && s3 < F.guide.alpha_thr;
                     uint32_t r3 = s3;
                     if (guided) {
                         uint64_t lo = use_guide ? 0ull : F.guide.alpha_thr;
@@ -774,6 +774,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                         bsdf_eval(m, nn, wo, wi, fb, pb);
                         if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
                         if (pb > 0.0f) {
+                            f3 Tb = T;  // throughput before this vertex's scattering
                             T = T * fb * (dot(nn, wi) / pb);
                             if (maxc(T) > 0.0f) {
                                 alive = true;
@@ -781,22 +782,27 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                                     float qq = fminf(0.95f, maxc(T));
                                     qq = ceilf(qq * 16777216.0f) * 0x1p-24f;
                                     float u6 = u24(sample_bits(F, idx, base_dim + 6, F.scramble));
-                                    if (u6 < qq) T = T * (1.0f / qq);
-                                    else alive = false;
+                                    if (u6 < qq) {
+                                        T = T * (1.0f / qq);
+                                        Tb = Tb * (1.0f / qq);
+                                    } else {
+                                        alive = false;
+                                    }
                                 }
                                 if (alive) {
                                     P.ray_o[slot] = f4(xo, INFINITY);
                                     P.ray_d[slot] = f4(wi, 0.0f);
                                     P.thr[slot] = f4(T, pb);
-                                    if (F.guide.record) {
-                                        // training record: the radiance later arriving along wi
-                                        // is (final - now - this vertex's NEE) / T_after
+                                    if (F.guide.record && v <= F.guide.max_vertex) {
+                                        // training record: (final - now - this vertex's NEE) /
+                                        // T_before is this sample's estimate f cos L_i / p of
+                                        // the scattering integral (roulette folded into T_before)
                                         record = true;
                                         rec0 = f4(x, pb);
                                         rec1 = f4(wo, 0.0f);
                                         rec2 = f4(wi, ubits(slot));
                                         rec3 = f4(L, 0.0f);
-                                        rec4 = f4(T, 0.0f);
+                                        rec4 = f4(Tb, 0.0f);
                                     }
                                 }
                             }
@@ -959,7 +965,7 @@ hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uin
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
         timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
-        if (F.guide.alpha_thr && v < F.max_depth) timed(K_GUIDE_EVAL, [&] { (void)launch_guide_eval(F, P, v, gt, s); });  // errors surface below
+        if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex) timed(K_GUIDE_EVAL, [&] { (void)launch_guide_eval(F, P, v, gt, s); });  // errors surface below
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
     }

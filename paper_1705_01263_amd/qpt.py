@@ -57,7 +57,7 @@ class qpt_stats(C.Structure):
 
 class qpt_guide_opts(C.Structure):
     _fields_ = [("alpha", C.c_float), ("lr", C.c_float), ("batch", C.c_uint32), ("train", C.c_uint32),
-                ("warmup_steps", C.c_uint32), ("seed", C.c_uint32)]
+                ("warmup_steps", C.c_uint32), ("seed", C.c_uint32), ("max_vertex", C.c_uint32)]
 
 
 class qpt_kernel_time(C.Structure):
@@ -238,8 +238,10 @@ class Context:
         return {k: (arr[i].launches, arr[i].total_ms) for i, k in enumerate(KERNEL_KINDS)}
 
     # ---- learned proposal
-    def guide_config(self, alpha=0.5, lr=1e-3, batch=1 << 18, train=True, warmup_steps=1, seed=0) -> None:
-        o = qpt_guide_opts(alpha, lr, batch, int(train), warmup_steps, seed)  # train: Adam steps per batch
+    def guide_config(self, alpha=0.5, lr=1e-3, batch=1 << 18, train=True, warmup_steps=1, seed=0,
+                     max_vertex=0) -> None:
+        # train: Adam steps per batch of passes; max_vertex: guide vertices 1..max_vertex (0 = all)
+        o = qpt_guide_opts(alpha, lr, batch, int(train), warmup_steps, seed, max_vertex)
         self.check(self.L.qpt_guide_config(self.h, C.byref(o)), "qpt_guide_config")
 
     def guide_set_weights(self, params) -> None:
