@@ -140,6 +140,7 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
     plain, n_p, t_p = run_for(seconds, False)
     guided, n_g, t_g = run_for(t_p, True)
     loss = r.ctx.guide_loss()[0]
+    _, steps = r.ctx.guide_get_weights()
     # GPU reference from passes no run above used
     r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
     r.reset()
@@ -157,7 +158,7 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
         "seconds": round(t_p, 3),
         "plain": {"passes": n_p, "seconds": round(t_p, 3), "rmse_vs_gpu_reference": rmse(plain, ref)},
         "guided": {"passes": n_g, "seconds": round(t_g, 3), "rmse_vs_gpu_reference": rmse(guided, ref),
-                   "alpha": GUIDE_ALPHA, "train_steps": n_g // 4, "final_loss": round(loss, 4)},
+                   "alpha": GUIDE_ALPHA, "train_steps": int(steps), "final_loss": round(loss, 4)},
         "gpu_reference": {"passes": ref_passes, "first_pass": 1 << 24, "seconds": round(t_ref, 2)},
     }
     # FP64 oracle reference on a pixel sample
