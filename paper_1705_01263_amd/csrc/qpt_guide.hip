@@ -36,14 +36,15 @@ __device__ __forceinline__ uint32_t bf16_rne(float f)
     return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+// four floats -> four BF16 (round to nearest even), two per conversion
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
 {
-    v4s r;
-    r.x = (short)bf16_rne(a);
-    r.y = (short)bf16_rne(b);
-    r.z = (short)bf16_rne(c);
-    r.w = (short)bf16_rne(d);
-    return r;
+    uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+    uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){c, d}, v2bf));
+    return __builtin_bit_cast(v4s, make_uint2(lo, hi));
 }
 
 __device__ __forceinline__ v4s as_v4s(uint2 u)
@@ -70,11 +71,18 @@ __device__ __forceinline__ void layer_fwd(const uint2 *sfrag, const float *sbias
     const uint32_t lane = lane_id(), half = lane >> 5;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-        v16f c = {};
+        // the bias is the accumulator's initial value (four float4 reads)
+        v16f c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float4 b = *(const float4 *)&sbias[L * 64 + 32 * t + 8 * q + 4 * half];
+            c[4 * q] = b.x;
+            c[4 * q + 1] = b.y;
+            c[4 * q + 2] = b.z;
+            c[4 * q + 3] = b.w;
+        }
 #pragma unroll
         for (int s = 0; s < kKS[L]; ++s) c = mfma(as_v4s(sfrag[(kFB[L] + t * kKS[L] + s) * 64 + lane]), in[s], c);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) c[v] += sbias[L * 64 + 32 * t + 8 * (v / 4) + 4 * half + (v % 4)];
         acc[t] = c;
     }
 }
@@ -357,10 +365,10 @@ __device__ __forceinline__ void mlp_infer(const uint2 *sfrag, const float *sbias
 // features 8s + 4h .. 8s + 4h + 3, i.e. octaves 2h and 2h + 1 of axis s
 // (s < 3), then the polar (h = 0) or azimuthal (h = 1) terms; the same
 // values as the full encoding, computed once per lane
-__device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const float *bmin, const float *bext, v4s *a0)
+__device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const float *bmin, const float *binv, v4s *a0)
 {
     const uint32_t h = lane_id() >> 5;
-    float xh[3] = {(x.x - bmin[0]) / bext[0], (x.y - bmin[1]) / bext[1], (x.z - bmin[2]) / bext[2]};
+    float xh[3] = {(x.x - bmin[0]) * binv[0], (x.y - bmin[1]) * binv[1], (x.z - bmin[2]) * binv[2]};
     const float m0 = 0.5f * guide::kOct[2 * h], m1 = 0.5f * guide::kOct[2 * h + 1];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -369,18 +377,16 @@ __device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const flo
         guide::sincos_rev(m1 * xh[a], &s1, &c1);
         a0[a] = pack4(s0, c0, s1, c1);
     }
-    float r0, r1;
-    if (h == 0) {
-        float th = acosf(fminf(1.0f, fmaxf(-1.0f, wo.y))) / guide::kPiF;
-        r0 = 0.5f * th;
-        r1 = th;
-    } else {
-        float ph = atan2f(wo.x, -wo.z);
-        if (ph < 0.0f) ph += 2.0f * guide::kPiF;
-        ph *= 1.0f / (2.0f * guide::kPiF);
-        r0 = ph;
-        r1 = 2.0f * ph;
-    }
+    // lane half 0: th (one atan2 of (sin th, cos th)); half 1: ph -- one
+    // atan2 per lane with lane-dependent arguments, no divergence
+    float y = fminf(1.0f, fmaxf(-1.0f, wo.y));
+    float ay = h ? wo.x : sqrtf(fmaxf(0.0f, 1.0f - y * y));
+    float ax = h ? -wo.z : y;
+    float ang = guide::atan2_enc(ay, ax);
+    if (h && ang < 0.0f) ang += 2.0f * guide::kPiF;
+    float r1 = ang * (h ? 1.0f / (2.0f * guide::kPiF) : 1.0f / guide::kPiF);
+    float r0 = h ? r1 : 0.5f * r1;
+    r1 = h ? 2.0f * r1 : r1;
     float s0, c0, s1, c1;
     guide::sincos_rev(r0, &s0, &c0);
     guide::sincos_rev(r1, &s1, &c1);
@@ -402,7 +408,7 @@ struct EvalSrc {
 __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
-    __shared__ float sbias[256];
+    __shared__ __align__(16) float sbias[256];
     const uint32_t n = src.debug ? src.n : P.counters[src.v];
     // the grid is sized for the largest queue: blocks without rows leave
     // before staging the 28 KB of weights (uniform per block, so no barrier
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
             }
         }
         v4s a0[4];
-        encode_half(x, wo, F.guide.bmin, F.guide.bext, a0);
+        encode_half(x, wo, F.guide.bmin, F.guide.binv, a0);
         v16f out[2];
         mlp_infer(sfrag, sbias, a0, out);
         float o[40];
@@ -454,7 +460,7 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
             float e[8], se = 0.0f;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                e[k] = expf(o[5 * k] - mx);
+                e[k] = __expf(o[5 * k] - mx);
                 se += e[k];
             }
             float inv = 1.0f / se;
@@ -466,9 +472,10 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
                 float oy = h ? o[5 * (4 + j) + 2] : o[5 * j + 2];
                 float oz = h ? o[5 * (4 + j) + 3] : o[5 * j + 3];
                 float ok = h ? o[5 * (4 + j) + 4] : o[5 * j + 4];
-                float nn = fmaxf(sqrtf(ox * ox + oy * oy + oz * oz), 1e-12f);
-                float kap = fminf(guide::softplus(ok) + 1e-3f, 1e4f);
-                dst[k] = make_float4(ox / nn, oy / nn, oz / nn, kap);
+                float in = rsqrtf(fmaxf(ox * ox + oy * oy + oz * oz, 1e-24f));
+                float sp = ok > 20.0f ? ok : __logf(1.0f + __expf(ok));
+                float kap = fminf(sp + 1e-3f, 1e4f);
+                dst[k] = make_float4(ox * in, oy * in, oz * in, kap);
             }
             dst[8 + h] = h ? make_float4(e[4] * inv, e[5] * inv, e[6] * inv, e[7] * inv)
                            : make_float4(e[0] * inv, e[1] * inv, e[2] * inv, e[3] * inv);
@@ -561,7 +568,7 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
                 c = min(c, count - 1);
                 const float4 *r = F.guide.rec + (size_t)T.cand[c] * kRecF4;
                 float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                guide::encode(guide::V3{r0.x, r0.y, r0.z}, guide::V3{r1.x, r1.y, r1.z}, F.guide.bmin, F.guide.bext, f);
+                guide::encode(guide::V3{r0.x, r0.y, r0.z}, guide::V3{r1.x, r1.y, r1.z}, F.guide.bmin, F.guide.binv, f);
                 wd = {r2.x, r2.y, r2.z};
                 wt = r1.w;
             }
@@ -598,14 +605,24 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         T.partial[(size_t)blockIdx.x * kGuideParams + i] = sgrad[i];
 }
 
-// sum the block partials, normalise by the weight sum; then Adam or a plain copy
-__global__ void k_guide_reduce(GuideTrain T, uint32_t blocks, int adam, uint32_t step, float lr, float *grad_out)
+// sum the block partials, normalise by the weight sum; then Adam or a plain
+// copy. A block owns 64 parameters; its four waves each sum every fourth
+// partial (coalesced 256-byte rows), then wave 0 combines the four sums.
+constexpr uint32_t kReduceParams = 64;
+__global__ __launch_bounds__(256) void k_guide_reduce(GuideTrain T, uint32_t blocks, int adam, uint32_t step,
+                                                      float lr, float *grad_out)
 {
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kGuideParams) return;
-    float ws = T.scalars[0];
+    __shared__ float part[4][kReduceParams];
+    const uint32_t lane = threadIdx.x & 63u, grp = threadIdx.x >> 6;
+    const uint32_t p = blockIdx.x * kReduceParams + lane;
     float g = 0.0f;
-    for (uint32_t b = 0; b < blocks; ++b) g += T.partial[(size_t)b * kGuideParams + p];
+    if (p < kGuideParams)
+        for (uint32_t b = grp; b < blocks; b += 4) g += T.partial[(size_t)b * kGuideParams + p];
+    part[grp][lane] = g;
+    __syncthreads();
+    if (grp != 0 || p >= kGuideParams) return;
+    g = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    float ws = T.scalars[0];
     g = ws > 0.0f ? g / ws : 0.0f;
     if (grad_out) grad_out[p] = g;
     if (!adam || !(ws > 0.0f)) return;
@@ -631,7 +648,7 @@ __global__ void k_fill_u32_1(uint32_t *p) { *p = 0u; }
 __global__ __launch_bounds__(256) void k_guide_fwd_debug(Frame F, const float *x, uint32_t n, float *out)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
-    __shared__ float sbias[256];
+    __shared__ __align__(16) float sbias[256];
     load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
     __syncthreads();
     const uint32_t lane = lane_id();
@@ -741,7 +758,7 @@ hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const Guide
         uint32_t blocks = 0;
         e = run_train(f, T, src, s, &blocks);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_guide_reduce, dim3(nblocks(kGuideParams, 256, 1024)), dim3(256), 0, s, T, blocks, 1,
+        hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s, T, blocks, 1,
                            step, lr, (float *)nullptr);
         e = launch_guide_frag(T, s);
     }
@@ -764,7 +781,7 @@ hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const fl
     uint32_t blocks = 0;
     hipError_t e = run_train(f, T, src, s, &blocks);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_guide_reduce, dim3(nblocks(kGuideParams, 256, 1024)), dim3(256), 0, s, T, blocks, adam,
+    hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s, T, blocks, adam,
                        step, lr, grad);
     if (adam) return launch_guide_frag(T, s);
     return hipGetLastError();

@@ -37,6 +37,44 @@ __device__ __forceinline__ void sincos_rev(float r, float *s, float *c)
     *c = __builtin_amdgcn_cosf(r);
 }
 
+// atan2 with C's quadrant and signed-zero conventions, from a least-squares
+// polynomial for atan on [0, 1] fitted for this library (degree 6 in a^2,
+// |error| < 4e-7 rad in FP32); the encoding only feeds it to sin and cos
+__device__ __forceinline__ float atan2_enc(float y, float x)
+{
+    float ax = fabsf(x), ay = fabsf(y);
+    float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    float a = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    a = fminf(a, 1.0f);
+    float q = a * a;
+    float r = 0.006812187377363443f;
+    r = fmaf(r, q, -0.03360540792346001f);
+    r = fmaf(r, q, 0.07962503284215927f);
+    r = fmaf(r, q, -0.1323341578245163f);
+    r = fmaf(r, q, 0.19807834923267365f);
+    r = fmaf(r, q, -0.3331736922264099f);
+    r = fmaf(r, q, 0.9999961256980896f);
+    r *= a;
+    if (ay > ax) r = 0.5f * kPiF - r;
+    if (__builtin_signbit(x)) r = kPiF - r;
+    return __builtin_signbit(y) ? -r : r;
+}
+
+// encoding angles of an outgoing direction: th = polar angle from +y over
+// pi, ph = atan2(x, -z) over 2 pi in [0, 1)
+__device__ __forceinline__ float enc_theta(V3 wo)
+{
+    float y = fminf(1.0f, fmaxf(-1.0f, wo.y));
+    return atan2_enc(sqrtf(fmaxf(0.0f, 1.0f - y * y)), y) * (1.0f / kPiF);
+}
+
+__device__ __forceinline__ float enc_phi(V3 wo)
+{
+    float ph = atan2_enc(wo.x, -wo.z);
+    if (ph < 0.0f) ph += 2.0f * kPiF;
+    return ph * (1.0f / (2.0f * kPiF));
+}
+
 // the decoded mixture as stored per path slot: lobe k = (mu.xyz, kappa), then
 // the 8 weights in two float4
 struct Mix {
@@ -119,15 +157,12 @@ __device__ inline V3 mixture_sample(const Mix &m, float u_lobe, float u1, float 
 // the 32 input features: sin/cos of 2^o pi x_hat per axis and octave, then
 // sin/cos of pi th, 2 pi th, 2 pi ph, 4 pi ph of the outgoing direction
 // (th = polar angle from +y over pi, ph = atan2(x, -z) over 2 pi in [0, 1))
-__device__ inline void encode(V3 x, V3 wo, const float *bmin, const float *bext, float *f)
+__device__ inline void encode(V3 x, V3 wo, const float *bmin, const float *binv, float *f)
 {
-    float xh[3] = {(x.x - bmin[0]) / bext[0], (x.y - bmin[1]) / bext[1], (x.z - bmin[2]) / bext[2]};
+    float xh[3] = {(x.x - bmin[0]) * binv[0], (x.y - bmin[1]) * binv[1], (x.z - bmin[2]) * binv[2]};
     for (int a = 0; a < 3; ++a)
         for (int o = 0; o < 4; ++o) sincos_rev(0.5f * kOct[o] * xh[a], &f[8 * a + 2 * o], &f[8 * a + 2 * o + 1]);
-    float th = acosf(fminf(1.0f, fmaxf(-1.0f, wo.y))) / kPiF;
-    float ph = atan2f(wo.x, -wo.z);
-    if (ph < 0.0f) ph += 2.0f * kPiF;
-    ph *= 1.0f / (2.0f * kPiF);
+    float th = enc_theta(wo), ph = enc_phi(wo);
     float rev[4] = {0.5f * th, th, ph, 2.0f * ph};
     for (int j = 0; j < 4; ++j) sincos_rev(rev[j], &f[24 + 2 * j], &f[25 + 2 * j]);
 }

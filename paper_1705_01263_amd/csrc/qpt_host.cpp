@@ -1025,7 +1025,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.mix = (float4 *)(w + L.g_mix);
     for (int a = 0; a < 3; ++a) {
         G.bmin[a] = (float)c->bbox[a];
-        G.bext[a] = (float)c->bbox[3 + a];
+        G.binv[a] = (float)(1.0 / (double)(float)c->bbox[3 + a]);
     }
     G.alpha_thr = 0;
     G.alpha = 0.0f;
@@ -1085,6 +1085,13 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         f.guide.alpha = (float)((double)f.guide.alpha_thr / 4294967296.0);
         f.guide.record = c->gopts.train ? 1u : 0u;
         f.guide.max_vertex = c->gopts.max_vertex ? c->gopts.max_vertex : 0xffffffffu;
+        // a uniform subset of the vertices, about twice the batch per path of
+        // the batch, is enough to draw each step's stratified batch from
+        {
+            uint32_t b = c->gopts.batch ? c->gopts.batch : (1u << 18);
+            double keep = std::min(1.0, 2.0 * (double)b / ((double)np * (double)nb));
+            f.guide.rec_thr = keep >= 1.0 ? 0xffffffffu : (uint32_t)(keep * 4294967296.0);
+        }
         HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
         if (c->gopts.train) {
             HIP_TRY(c, launch_guide_train_step(f, c->pool, c->gt, c->gopts.batch ? c->gopts.batch : (1u << 18),

@@ -61,11 +61,12 @@ struct GuideDev {
     const uint2 *fragT;      // kGuideFragsT * 64
     const float *bias;       // 4 x 64 (BF16-rounded values, layer 3 zero-padded)
     float4 *mix;             // per path slot: 8 lobes (mu.xyz, kappa), 8 weights
-    float bmin[3], bext[3];  // scene box for the position encoding
+    float bmin[3], binv[3];  // scene box for the position encoding: min corner, 1 / extent
     uint32_t alpha_thr;      // guide iff sample bits < alpha_thr (0: BSDF sampling only)
     float alpha;             // alpha_thr / 2^32
     uint32_t record;         // capture training records
     uint32_t max_vertex;     // guide and record at path vertices 1..max_vertex
+    uint32_t rec_thr;        // record a vertex iff its hash < rec_thr (0xffffffff: every vertex)
     float4 *rec;             // kRecF4 float4 per record
     uint32_t rec_cap;
     uint32_t *rec_count;

@@ -601,6 +601,16 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
     wave_count(&P.stats[7], tests);
 }
 
+// which vertices leave a training record: a hash of the path's sample index
+// and the depth (splitmix64 finaliser), uniform over the batch
+__device__ __forceinline__ uint32_t rec_hash(uint64_t idx, uint32_t v)
+{
+    uint64_t z = idx * 0x9E3779B97F4A7C15ull + (uint64_t)v * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)((z ^ (z >> 31)) >> 32);
+}
+
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
 __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
 {
@@ -793,7 +803,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                                     P.ray_o[slot] = f4(xo, INFINITY);
                                     P.ray_d[slot] = f4(wi, 0.0f);
                                     P.thr[slot] = f4(T, pb);
-                                    if (F.guide.record && v <= F.guide.max_vertex) {
+                                    if (F.guide.record && v <= F.guide.max_vertex &&
+                                        (F.guide.rec_thr == 0xffffffffu || rec_hash(idx, v) < F.guide.rec_thr)) {
                                         // training record: (final - now - this vertex's NEE) /
                                         // T_before is this sample's estimate f cos L_i / p of
                                         // the scattering integral (roulette folded into T_before)

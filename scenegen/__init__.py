@@ -395,7 +395,11 @@ def instanced_env_scene(seed: int = 3, width=1920, height=1080, spp=256, max_dep
 
 def slit_scene(seed: int = 3, width=1920, height=1080, spp=64, max_depth=16,
                target_tris=4_000_000, env_size=(2048, 1024)) -> Scene:
-    """The instanced scene inside an enclosure whose roof leaves a 0.1-wide slit."""
+    """The instanced scene inside an enclosure whose roof leaves a 0.1-wide slit.
+
+    Sunlight through the slit lands on a thin strip near x = -11; the camera
+    stands at x = -5 and looks towards +x, at the half of the enclosure the
+    strip does not reach, so every pixel it sees is lit indirectly."""
     s = instanced_env_scene(seed, width, height, spp, max_depth, target_tris, env_size)
     b = _Builder()
     b.pos = [s.positions.astype(np.float64)]
@@ -416,7 +420,7 @@ def slit_scene(seed: int = 3, width=1920, height=1080, spp=64, max_depth=16,
     w = 0.05
     b.quad((-X, Y, -Z), (-w, Y, -Z), (-w, Y, Z), (-X, Y, Z), wall)    # roof, normal -y
     b.quad((w, Y, -Z), (X, Y, -Z), (X, Y, Z), (w, Y, Z), wall)
-    cam = Camera((0.0, 4.0, -28.0), (0.0, 2.0, 0.0), (0.0, 1.0, 0.0), 40.0)
+    cam = Camera((-5.0, 4.0, 0.0), (32.0, 3.0, 0.0), (0.0, 1.0, 0.0), 40.0)
     return b.scene("slit_enclosure", cam, width, height, spp, max_depth, env=s.env)
 
 
