@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
-GUIDE_ALPHA, GUIDE_WARMUP = 0.5, 8
+GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 8, 2
 
 # algorithmic bytes per unit of work ("Measurement")
 NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
@@ -121,7 +121,8 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
         r.reset()
         if guided:
             r.ctx.guide_set_weights(scenegen.guide_init(1))
-            r.ctx.guide_config(alpha=GUIDE_ALPHA, lr=1e-3, batch=1 << 18, train=1, warmup_steps=GUIDE_WARMUP, seed=1)
+            r.ctx.guide_config(alpha=GUIDE_ALPHA, lr=1e-3, batch=1 << 18, train=1, warmup_steps=GUIDE_WARMUP, seed=1,
+                               max_vertex=GUIDE_MAX_VERTEX)
         else:
             r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
         torch.cuda.synchronize()
@@ -158,7 +159,8 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
         "seconds": round(t_p, 3),
         "plain": {"passes": n_p, "seconds": round(t_p, 3), "rmse_vs_gpu_reference": rmse(plain, ref)},
         "guided": {"passes": n_g, "seconds": round(t_g, 3), "rmse_vs_gpu_reference": rmse(guided, ref),
-                   "alpha": GUIDE_ALPHA, "train_steps": int(steps), "final_loss": round(loss, 4)},
+                   "alpha": GUIDE_ALPHA, "guided_vertices": GUIDE_MAX_VERTEX, "lr": 1e-3, "batch": 1 << 18,
+                   "train_steps": int(steps), "final_loss": round(loss, 4)},
         "gpu_reference": {"passes": ref_passes, "first_pass": 1 << 24, "seconds": round(t_ref, 2)},
     }
     # FP64 oracle reference on a pixel sample
@@ -198,8 +200,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-equal-time", action="store_true", help="skip the guided vs plain equal-time RMSE leg")
-    ap.add_argument("--et-seconds", type=float, default=1.5, help="wall time of each equal-time run")
-    ap.add_argument("--et-ref-passes", type=int, default=1024)
+    ap.add_argument("--et-seconds", type=float, default=4.0, help="wall time of each equal-time run")
+    ap.add_argument("--et-ref-passes", type=int, default=2048)
     ap.add_argument("--et-oracle-seconds", type=float, default=10.0)
     ap.add_argument("--et-size", type=str, default="1920x1080")
     ap.add_argument("--et-tris", type=int, default=4_000_000)

@@ -217,8 +217,9 @@ int qpt_guide_get_weights(qpt_ctx *ctx, float *params, uint32_t *steps);
 int qpt_guide_debug_forward(qpt_ctx *ctx, const float *x, uint32_t n, float *out);
 /* the renderer's inference path on n explicit vertices (x: n x 3 positions,
  * wo: n x 3 unit outgoing directions; encoded against the scene's bounding
- * box) -> n x 40 FP32: lobe k's (mu xyz, kappa) at 4k..4k+3, then the 8
- * weights at 32..39; */
+ * box) -> n x 40 FP32, the mixture exactly as the renderer decodes it from
+ * its FP16 per-vertex storage: lobe k's (mu xyz, kappa) at 4k..4k+3, then
+ * the 8 weights at 32..39; */
 int qpt_guide_debug_eval(qpt_ctx *ctx, const float *x, const float *wo, uint32_t n, float *mix);
 /* gradient of -sum_b w_b log q(dir_b) / sum_b w_b w.r.t. the 13032 parameters
  * for n rows (x: n x 32 features, dirs: n x 3 unit vectors, w: n weights); */

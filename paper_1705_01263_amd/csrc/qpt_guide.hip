@@ -314,7 +314,9 @@ __device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const u
 // ------------------------------------------------------------- kernels
 
 // BF16 fragments and biases from the FP32 master parameters
-__global__ void k_guide_frag(GuideTrain T)
+// the BF16 operand tiles of the FP32 master weights, for training (T.frag,
+// T.fragT, T.bias) and, where given, for the renderer's published copies
+__global__ void k_guide_frag(GuideTrain T, uint2 *pub_a, float *pub_ab, uint2 *pub_b, float *pub_bb)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nf = kGuideFrags * 64, nt = kGuideFragsT * 64;
@@ -325,7 +327,10 @@ __global__ void k_guide_frag(GuideTrain T)
         int L = f < 8 ? 0 : (f < 24 ? 1 : (f < 40 ? 2 : 3));
         int r = f - kFB[L], t = r / kKS[L], s = r % kKS[L];
         int k = 8 * s + 4 * half, o = 32 * t + lane % 32;
-        T.frag[i] = make_uint2(pack2(w_at(L, k, o), w_at(L, k + 1, o)), pack2(w_at(L, k + 2, o), w_at(L, k + 3, o)));
+        uint2 v = make_uint2(pack2(w_at(L, k, o), w_at(L, k + 1, o)), pack2(w_at(L, k + 2, o), w_at(L, k + 3, o)));
+        T.frag[i] = v;
+        if (pub_a) pub_a[i] = v;
+        if (pub_b) pub_b[i] = v;
     } else if (i < nf + nt) {
         uint32_t j = i - nf, g = j / 64, lane = j % 64, half = lane / 32;
         int L = 1 + g / 16;
@@ -336,7 +341,10 @@ __global__ void k_guide_frag(GuideTrain T)
         uint32_t j = i - nf - nt;
         int L = j / 64, o = j % 64;
         float b = o < kN[L] ? T.master[kOffB[L] + o] : 0.0f;
-        T.bias[j] = __uint_as_float(bf16_rne(b) << 16);
+        float bq = __uint_as_float(bf16_rne(b) << 16);
+        T.bias[j] = bq;
+        if (pub_ab) pub_ab[j] = bq;
+        if (pub_bb) pub_bb[j] = bq;
     }
 }
 
@@ -400,7 +408,7 @@ struct EvalSrc {
     uint32_t v;              // queue: depth
     const float *x, *wo;     // debug: n x 3 positions and outgoing directions
     uint32_t n;              // debug: rows
-    float4 *out;             // debug: n x 10 float4 (queue rows write F.guide.mix)
+    uint4 *out;              // debug: n rows of 10 uint4 (the first 5 hold the packed mixture)
 };
 
 // mixture of every row: each lane of a pair encodes its half of the inputs
@@ -417,7 +425,8 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
     load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
     __syncthreads();
     const uint32_t *q = P.q_ext[src.v & 1];
-    float4 *mix_out = src.debug ? src.out : F.guide.mix;
+    uint4 *mix_out = src.debug ? src.out : F.guide.mix;
+    const uint32_t stride = src.debug ? 2 * guide::kMixU4 : guide::kMixU4;
     const uint32_t lane = lane_id(), h = lane >> 5;
     const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const uint32_t waves = gridDim.x * (blockDim.x / 64);
@@ -464,10 +473,10 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
                 se += e[k];
             }
             float inv = 1.0f / se;
-            float4 *dst = mix_out + (size_t)slot * 10;
+            uint4 *dst = mix_out + (size_t)slot * stride;
+            uint32_t q[8];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                int k = 4 * (int)h + j;
                 float ox = h ? o[5 * (4 + j) + 1] : o[5 * j + 1];
                 float oy = h ? o[5 * (4 + j) + 2] : o[5 * j + 2];
                 float oz = h ? o[5 * (4 + j) + 3] : o[5 * j + 3];
@@ -475,10 +484,15 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
                 float in = rsqrtf(fmaxf(ox * ox + oy * oy + oz * oz, 1e-24f));
                 float sp = ok > 20.0f ? ok : __logf(1.0f + __expf(ok));
                 float kap = fminf(sp + 1e-3f, 1e4f);
-                dst[k] = make_float4(ox * in, oy * in, oz * in, kap);
+                q[2 * j] = guide::pack_h2(ox * in, oy * in);
+                q[2 * j + 1] = guide::pack_h2(oz * in, kap);
             }
-            dst[8 + h] = h ? make_float4(e[4] * inv, e[5] * inv, e[6] * inv, e[7] * inv)
-                           : make_float4(e[0] * inv, e[1] * inv, e[2] * inv, e[3] * inv);
+            // lobes 4h .. 4h + 3 are uint4 2h and 2h + 1; weights 4h .. 4h + 3 half of uint4 4
+            dst[2 * h] = make_uint4(q[0], q[1], q[2], q[3]);
+            dst[2 * h + 1] = make_uint4(q[4], q[5], q[6], q[7]);
+            uint2 wq = h ? make_uint2(guide::pack_h2(e[4] * inv, e[5] * inv), guide::pack_h2(e[6] * inv, e[7] * inv))
+                         : make_uint2(guide::pack_h2(e[0] * inv, e[1] * inv), guide::pack_h2(e[2] * inv, e[3] * inv));
+            ((uint2 *)(dst + 4))[h] = wq;
         }
     }
 }
@@ -700,10 +714,12 @@ inline uint32_t nblocks(size_t n, uint32_t bs, uint32_t cap)
 
 }  // namespace
 
-hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s)
+hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s, uint2 *pub_a, float *pub_ab, uint2 *pub_b,
+                             float *pub_bb)
 {
     uint32_t n = (kGuideFrags + kGuideFragsT) * 64 + 256;
-    hipLaunchKernelGGL(k_guide_frag, dim3(nblocks(n, 256, 1u << 20)), dim3(256), 0, s, T);
+    hipLaunchKernelGGL(k_guide_frag, dim3(nblocks(n, 256, 1u << 20)), dim3(256), 0, s, T, pub_a, pub_ab, pub_b,
+                       pub_bb);
     return hipGetLastError();
 }
 
@@ -714,11 +730,29 @@ hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint3
     return hipGetLastError();
 }
 
+// packed mixtures (first 80 bytes of each 160-byte row) -> the decoded FP32
+// values the renderer uses, in place: 8 x (mu.xyz, kappa), then 8 weights
+__global__ void k_mix_unpack_debug(uint4 *rows, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 *row = rows + (size_t)i * 2 * guide::kMixU4;
+    uint4 packed[guide::kMixU4];
+    for (int j = 0; j < guide::kMixU4; ++j) packed[j] = row[j];
+    guide::Mix m;
+    guide::unpack_mix(packed, m);
+    float4 *out = (float4 *)row;
+    for (int k = 0; k < guide::kLobes; ++k) out[k] = m.lobe[k];
+    out[8] = m.w0;
+    out[9] = m.w1;
+}
+
 hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
                                    float *mix, hipStream_t s)
 {
-    EvalSrc src{true, 0u, x, wo, n, (float4 *)mix};
+    EvalSrc src{true, 0u, x, wo, n, (uint4 *)mix};
     hipLaunchKernelGGL(k_guide_eval, dim3(nblocks(((size_t)n + 31) / 32, 4, 2048)), dim3(256), 0, s, f, pool, src);
+    hipLaunchKernelGGL(k_mix_unpack_debug, dim3(nblocks(n, 256, 1u << 20)), dim3(256), 0, s, (uint4 *)mix, n);
     return hipGetLastError();
 }
 
@@ -738,13 +772,17 @@ static hipError_t run_train(const Frame &f, const GuideTrain &T, const RowSrc &s
     return hipGetLastError();
 }
 
-hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const GuideTrain &T, uint32_t batch,
-                                   uint32_t step0, uint32_t nsteps, float lr, uint32_t seed, hipStream_t s,
-                                   Profiler *prof)
+hipError_t launch_guide_finalize(const Frame &f, const Pool &pool, const GuideTrain &T, hipStream_t s)
 {
-    if (prof) prof->begin(K_GUIDE_TRAIN, s);
     hipLaunchKernelGGL(k_fill_u32_1, dim3(1), dim3(1), 0, s, T.cand_count);
     hipLaunchKernelGGL(k_rec_finalize, dim3(nblocks(f.guide.rec_cap, 256, 4096)), dim3(256), 0, s, f, pool, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_train_steps(const Frame &f, const GuideTrain &T, uint32_t batch, uint32_t step0,
+                                    uint32_t nsteps, float lr, uint32_t seed, hipStream_t s, uint2 *pub_frag,
+                                    float *pub_bias)
+{
     hipError_t e = hipSuccess;
     for (uint32_t k = 0; k < nsteps && e == hipSuccess; ++k) {
         const uint32_t step = step0 + k;
@@ -758,11 +796,11 @@ hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const Guide
         uint32_t blocks = 0;
         e = run_train(f, T, src, s, &blocks);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s, T, blocks, 1,
-                           step, lr, (float *)nullptr);
-        e = launch_guide_frag(T, s);
+        hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s,
+                           T, blocks, 1, step, lr, (float *)nullptr);
+        const bool last = k + 1 == nsteps;
+        e = launch_guide_frag(T, s, last ? pub_frag : nullptr, last ? pub_bias : nullptr, nullptr, nullptr);
     }
-    if (prof) prof->end(K_GUIDE_TRAIN, s);
     return e;
 }
 
@@ -775,7 +813,7 @@ hipError_t launch_guide_debug_forward(const Frame &f, const float *x, uint32_t n
 
 hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const float *x, const float *dirs,
                                    const float *w, uint32_t n, float *grad, int adam, uint32_t step, float lr,
-                                   hipStream_t s)
+                                   hipStream_t s, uint2 *pub_a, float *pub_ab, uint2 *pub_b, float *pub_bb)
 {
     RowSrc src{true, x, dirs, w, n, nullptr, 0.0f};
     uint32_t blocks = 0;
@@ -783,7 +821,7 @@ hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const fl
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s, T, blocks, adam,
                        step, lr, grad);
-    if (adam) return launch_guide_frag(T, s);
+    if (adam) return launch_guide_frag(T, s, pub_a, pub_ab, pub_b, pub_bb);
     return hipGetLastError();
 }
 

@@ -91,6 +91,48 @@ __device__ __forceinline__ float weight(const Mix &m, int k)
 
 __device__ __forceinline__ float softplus(float r) { return r > 20.0f ? r : log1pf(expf(r)); }
 
+// The mixture as stored per path slot, 80 bytes: uint4 j < 4 holds lobes 2j
+// and 2j + 1 as FP16 (mu.x, mu.y, mu.z, kappa); uint4 4 holds the eight
+// weights as FP16. The density the renderer samples and evaluates is the one
+// these stored values define, decoded by unpack_mix (means and weights
+// renormalised in FP32), so rounding to FP16 leaves the estimator unbiased.
+constexpr int kMixU4 = 5;
+
+typedef float v2f_ __attribute__((ext_vector_type(2)));
+typedef _Float16 v2h_ __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_h2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f_){a, b}, v2h_));
+}
+
+__device__ __forceinline__ float2 unpack_h2(uint32_t u)
+{
+    v2f_ f = __builtin_convertvector(__builtin_bit_cast(v2h_, u), v2f_);
+    return make_float2(f.x, f.y);
+}
+
+__device__ __forceinline__ float4 unit_lobe(float2 a, float2 b)
+{
+    float in = rsqrtf(fmaxf(a.x * a.x + a.y * a.y + b.x * b.x, 1e-24f));
+    return make_float4(a.x * in, a.y * in, b.x * in, b.y);
+}
+
+__device__ inline void unpack_mix(const uint4 *src, Mix &m)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        uint4 u = src[j];
+        m.lobe[2 * j] = unit_lobe(unpack_h2(u.x), unpack_h2(u.y));
+        m.lobe[2 * j + 1] = unit_lobe(unpack_h2(u.z), unpack_h2(u.w));
+    }
+    uint4 w = src[4];
+    float2 w01 = unpack_h2(w.x), w23 = unpack_h2(w.y), w45 = unpack_h2(w.z), w67 = unpack_h2(w.w);
+    float inv = 1.0f / (((w01.x + w01.y) + (w23.x + w23.y)) + ((w45.x + w45.y) + (w67.x + w67.y)));
+    m.w0 = make_float4(w01.x * inv, w01.y * inv, w23.x * inv, w23.y * inv);
+    m.w1 = make_float4(w45.x * inv, w45.y * inv, w67.x * inv, w67.y * inv);
+}
+
 // outputs 5k..5k+4 of lobe k: logit, mu_raw xyz, kappa_raw
 __device__ inline void decode(const float *o, Mix &m)
 {

@@ -269,7 +269,8 @@ struct Layout {
         env_col, env_cos, bases;
     size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats, gstack;
     size_t fb_sum, fb_count;
-    size_t g_frag, g_fragT, g_bias, g_mix, g_rec, g_master, g_m, g_v, g_cand, g_cand_count, g_partial, g_scalars;
+    size_t g_frag, g_fragT, g_bias, g_mix, g_master, g_m, g_v, g_partial, g_scalars;
+    size_t g_rec[2], g_cand[2], g_cand_count[2], g_pub_frag[2], g_pub_bias[2];
     size_t total;
 };
 
@@ -327,6 +328,17 @@ struct qpt_ctx {
     bool guide_weights = false;
     uint32_t guide_steps = 0;
     uint32_t stack_need = 3;      // traversal stack entries per ray the BVH can require
+    // training runs on a stream of its own, one batch behind the renderer
+    hipStream_t tstream = nullptr;
+    hipEvent_t ev_rec[2] = {nullptr, nullptr};    // batch k's records and candidates are ready
+    hipEvent_t ev_train[2] = {nullptr, nullptr};  // the step on buffer k has finished
+    bool train_pending[2] = {false, false};
+    uint64_t gbatch = 0;   // training batches issued
+    int last_buf = 0;      // buffer of the newest published weights
+    float4 *rec_buf[2] = {nullptr, nullptr};
+    uint32_t *cand_buf[2] = {nullptr, nullptr}, *cand_count_buf[2] = {nullptr, nullptr};
+    uint2 *pub_frag[2] = {nullptr, nullptr};
+    float *pub_bias[2] = {nullptr, nullptr};
     double bbox[6] = {0, 0, 0, 1, 1, 1};
     EventProfiler prof;
     bool profiling = false;
@@ -603,6 +615,10 @@ void set_frame_constants(qpt_ctx *c)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// training records per buffer: the renderer keeps a hashed subset of about
+// twice the batch per pass, so twice the pool (at most 2^21) is ample
+size_t guide_rec_cap(uint32_t cap) { return std::min<size_t>((size_t)1 << 21, (size_t)cap * 2); }
+
 Layout make_layout(const qpt_ctx *c, uint32_t cap)
 {
     Layout L{};
@@ -642,18 +658,24 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
-    // learned proposal: weights, per-slot mixtures, training records and state
-    size_t rec_cap = std::min<size_t>((size_t)1 << 22, (size_t)cap * 2);
+    // learned proposal: weights, per-slot mixtures, training records and
+    // state; records, candidates and the renderer's copy of the weights are
+    // double-buffered so a training step overlaps the next batch
+    size_t rec_cap = guide_rec_cap(cap);
     L.g_frag = take(kGuideFrags * 64 * 8);
     L.g_fragT = take(kGuideFragsT * 64 * 8);
     L.g_bias = take(256 * 4);
-    L.g_mix = take((size_t)cap * 10 * 16);
-    L.g_rec = take(rec_cap * kRecF4 * 16);
+    L.g_mix = take((size_t)cap * 5 * 16);
+    for (int k = 0; k < 2; ++k) {
+        L.g_rec[k] = take(rec_cap * kRecF4 * 16);
+        L.g_cand[k] = take(rec_cap * 4);
+        L.g_cand_count[k] = take(4);
+        L.g_pub_frag[k] = take(kGuideFrags * 64 * 8);
+        L.g_pub_bias[k] = take(256 * 4);
+    }
     L.g_master = take(kGuideParams * 4);
     L.g_m = take(kGuideParams * 4);
     L.g_v = take(kGuideParams * 4);
-    L.g_cand = take(rec_cap * 4);
-    L.g_cand_count = take(4);
     L.g_partial = take((size_t)c->guide_blocks * kGuideParams * 4);
     L.g_scalars = take(2 * 4);
     L.total = o;
@@ -661,6 +683,15 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
 }
 
 }  // namespace
+
+// wait for training work in flight on the context's training stream
+static hipError_t join_train(qpt_ctx *c)
+{
+    if (!c->tstream) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(c->tstream);
+    c->train_pending[0] = c->train_pending[1] = false;
+    return e;
+}
 
 // ================================================================== C-ABI
 
@@ -693,7 +724,20 @@ int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
     return QPT_OK;
 }
 
-void qpt_destroy(qpt_ctx *ctx) { delete ctx; }
+void qpt_destroy(qpt_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->tstream) {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->tstream);
+        for (int k = 0; k < 2; ++k) {
+            if (ctx->ev_rec[k]) (void)hipEventDestroy(ctx->ev_rec[k]);
+            if (ctx->ev_train[k]) (void)hipEventDestroy(ctx->ev_train[k]);
+        }
+        (void)hipStreamDestroy(ctx->tstream);
+    }
+    delete ctx;
+}
 
 const char *qpt_last_error(const qpt_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -945,6 +989,15 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     if (bytes < L.total) return fail(c, QPT_E_NOMEM, "workspace %zu bytes, need %zu", bytes, L.total);
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
+    HIP_TRY(c, join_train(c));
+    if (!c->tstream) {
+        // default priority; non-blocking so it can overlap a caller's legacy stream
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->tstream, hipStreamNonBlocking));
+        for (int k = 0; k < 2; ++k) {
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_train[k], hipEventDisableTiming));
+        }
+    }
     c->ws = (uint8_t *)device_ptr;
     c->ws_bytes = bytes;
     c->pool_cap = cap;
@@ -1013,8 +1066,17 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     T.frag = (uint2 *)(w + L.g_frag);
     T.fragT = (uint2 *)(w + L.g_fragT);
     T.bias = (float *)(w + L.g_bias);
-    T.cand = (uint32_t *)(w + L.g_cand);
-    T.cand_count = (uint32_t *)(w + L.g_cand_count);
+    for (int k = 0; k < 2; ++k) {
+        c->rec_buf[k] = (float4 *)(w + L.g_rec[k]);
+        c->cand_buf[k] = (uint32_t *)(w + L.g_cand[k]);
+        c->cand_count_buf[k] = (uint32_t *)(w + L.g_cand_count[k]);
+        c->pub_frag[k] = (uint2 *)(w + L.g_pub_frag[k]);
+        c->pub_bias[k] = (float *)(w + L.g_pub_bias[k]);
+    }
+    c->gbatch = 0;
+    c->last_buf = 0;
+    T.cand = c->cand_buf[0];
+    T.cand_count = c->cand_count_buf[0];
     T.partial = (float *)(w + L.g_partial);
     T.scalars = (float *)(w + L.g_scalars);
     T.max_blocks = c->guide_blocks;
@@ -1022,7 +1084,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.frag = T.frag;
     G.fragT = T.fragT;
     G.bias = T.bias;
-    G.mix = (float4 *)(w + L.g_mix);
+    G.mix = (uint4 *)(w + L.g_mix);
     for (int a = 0; a < 3; ++a) {
         G.bmin[a] = (float)c->bbox[a];
         G.binv[a] = (float)(1.0 / (double)(float)c->bbox[3 + a]);
@@ -1030,8 +1092,8 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.alpha_thr = 0;
     G.alpha = 0.0f;
     G.record = 0;
-    G.rec = (float4 *)(w + L.g_rec);
-    G.rec_cap = (uint32_t)std::min<size_t>((size_t)1 << 22, (size_t)cap * 2);
+    G.rec = c->rec_buf[0];
+    G.rec_cap = (uint32_t)guide_rec_cap(cap);
     G.rec_count = p.counters + 127;
     c->guide_weights = false;
     c->guide_steps = 0;
@@ -1092,12 +1154,40 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
             double keep = std::min(1.0, 2.0 * (double)b / ((double)np * (double)nb));
             f.guide.rec_thr = keep >= 1.0 ? 0xffffffffu : (uint32_t)(keep * 4294967296.0);
         }
+        // Weights, records and candidates are double-buffered: batch b renders
+        // with the weights the step of batch b - 2 published (its buffer,
+        // b mod 2, is free once that step has finished) while the step of
+        // batch b - 1 runs on the training stream. Any weights give an
+        // unbiased estimator; the lag only delays what the guide has learnt.
+        const bool train = c->gopts.train > 0;
+        const int k = train ? (int)(c->gbatch & 1) : c->last_buf;
+        if (guiding) {
+            if (c->train_pending[k]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[k], 0));
+            f.guide.frag = c->pub_frag[k];
+            f.guide.bias = c->pub_bias[k];
+            f.guide.rec = c->rec_buf[k];
+        }
         HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
-        if (c->gopts.train) {
-            HIP_TRY(c, launch_guide_train_step(f, c->pool, c->gt, c->gopts.batch ? c->gopts.batch : (1u << 18),
-                                               c->guide_steps + 1, c->gopts.train, c->gopts.lr, c->gopts.seed,
-                                               c->stream, prof));
+        if (train) {
+            GuideTrain T = c->gt;
+            T.cand = c->cand_buf[k];
+            T.cand_count = c->cand_count_buf[k];
+            // candidates now: the path radiance they read is overwritten by the next batch
+            if (prof) prof->begin(K_GUIDE_TRAIN, c->stream);
+            HIP_TRY(c, launch_guide_finalize(f, c->pool, T, c->stream));
+            if (prof) prof->end(K_GUIDE_TRAIN, c->stream);
+            HIP_TRY(c, hipEventRecord(c->ev_rec[k], c->stream));
+            HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[k], 0));
+            if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
+            HIP_TRY(c, launch_guide_train_steps(f, T, c->gopts.batch ? c->gopts.batch : (1u << 18),
+                                                c->guide_steps + 1, c->gopts.train, c->gopts.lr, c->gopts.seed,
+                                                c->tstream, c->pub_frag[k], c->pub_bias[k]));
+            if (prof) prof->end(K_GUIDE_TRAIN, c->tstream);
+            HIP_TRY(c, hipEventRecord(c->ev_train[k], c->tstream));
+            c->train_pending[k] = true;
+            c->last_buf = k;
             c->guide_steps += c->gopts.train;
+            ++c->gbatch;
         }
         return QPT_OK;
     };
@@ -1125,6 +1215,7 @@ int qpt_readback(qpt_ctx *c, double *sum_rgb, uint32_t *counts, int dst_is_devic
     if (!c) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "readback before bind_workspace");
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     size_t npix = (size_t)c->W * c->H;
     hipMemcpyKind k = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (sum_rgb) HIP_TRY(c, hipMemcpyAsync(sum_rgb, c->pool.fb_sum, npix * 3 * 8, k, c->stream));
@@ -1159,6 +1250,7 @@ int qpt_profile(qpt_ctx *c, int enable)
     DeviceGuard g(c->device);
     if (enable) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, join_train(c));
         c->prof.clear();
     }
     c->profiling = enable != 0;
@@ -1171,6 +1263,7 @@ int qpt_profile_read(qpt_ctx *c, qpt_kernel_time *out)
     if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, join_train(c));
     for (int k = 0; k < QPT_K_KINDS; ++k) out[k] = qpt_kernel_time{0, 0, 0.0};
     for (const EventProfiler::Rec &r : c->prof.recs) {
         if (!r.a || !r.b || r.kind < 0 || r.kind >= QPT_K_KINDS) continue;
@@ -1233,10 +1326,11 @@ int qpt_guide_set_weights(qpt_ctx *c, const float *params)
     for (uint32_t p = 0; p < kGuideParams; ++p)
         if (!std::isfinite(params[p])) return fail(c, QPT_E_INVALID, "non-finite guide parameter");
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     HIP_TRY(c, hipMemcpyAsync(c->gt.master, params, kGuideParams * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->gt.m, 0, kGuideParams * 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->gt.v, 0, kGuideParams * 4, c->stream));
-    HIP_TRY(c, launch_guide_frag(c->gt, c->stream));
+    HIP_TRY(c, launch_guide_frag(c->gt, c->stream, c->pub_frag[0], c->pub_bias[0], c->pub_frag[1], c->pub_bias[1]));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->guide_weights = true;
     c->guide_steps = 0;
@@ -1248,6 +1342,7 @@ int qpt_guide_get_weights(qpt_ctx *c, float *params, uint32_t *steps)
     if (!c) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     if (params) HIP_TRY(c, hipMemcpyAsync(params, c->gt.master, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (steps) *steps = c->guide_steps;
@@ -1260,6 +1355,7 @@ int qpt_guide_debug_forward(qpt_ctx *c, const float *x, uint32_t n, float *out)
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     Frame f = c->frame;
     HIP_TRY(c, launch_guide_debug_forward(f, x, n, out, c->stream));
     return QPT_OK;
@@ -1271,6 +1367,7 @@ int qpt_guide_debug_eval(qpt_ctx *c, const float *x, const float *wo, uint32_t n
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     HIP_TRY(c, launch_guide_debug_eval(c->frame, c->pool, x, wo, n, mix, c->stream));
     return QPT_OK;
 }
@@ -1280,7 +1377,9 @@ int qpt_guide_debug_grad(qpt_ctx *c, const float *x, const float *dirs, const fl
     if (!c || !n || !x || !dirs || !w || !grad) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
-    HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 0, 0u, 0.0f, c->stream));
+    HIP_TRY(c, join_train(c));
+    HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 0, 0u, 0.0f, c->stream, nullptr, nullptr,
+                                       nullptr, nullptr));
     return QPT_OK;
 }
 
@@ -1290,8 +1389,10 @@ int qpt_guide_debug_train(qpt_ctx *c, const float *x, const float *dirs, const f
     if (!c || !n || !x || !dirs || !w || !(lr > 0.0f)) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     ++c->guide_steps;
-    HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 1, c->guide_steps, lr, c->stream));
+    HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 1, c->guide_steps, lr, c->stream,
+                                       c->pub_frag[0], c->pub_bias[0], c->pub_frag[1], c->pub_bias[1]));
     return QPT_OK;
 }
 
@@ -1300,6 +1401,7 @@ int qpt_guide_loss(qpt_ctx *c, double *loss, double *weight_sum)
     if (!c) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
     DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
     float sc[2];
     HIP_TRY(c, hipMemcpyAsync(sc, c->gt.scalars, sizeof sc, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

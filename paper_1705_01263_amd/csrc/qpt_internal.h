@@ -60,7 +60,7 @@ struct GuideDev {
     const uint2 *frag;       // kGuideFrags * 64: 4 bf16 per lane (MFMA A operands)
     const uint2 *fragT;      // kGuideFragsT * 64
     const float *bias;       // 4 x 64 (BF16-rounded values, layer 3 zero-padded)
-    float4 *mix;             // per path slot: 8 lobes (mu.xyz, kappa), 8 weights
+    uint4 *mix;              // per path slot: the FP16 mixture, 5 uint4 (see unpack_mix)
     float bmin[3], binv[3];  // scene box for the position encoding: min corner, 1 / extent
     uint32_t alpha_thr;      // guide iff sample bits < alpha_thr (0: BSDF sampling only)
     float alpha;             // alpha_thr / 2^32
@@ -165,17 +165,19 @@ hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
                                uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
 // guide launchers (qpt_guide.hip)
-hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s);
+hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s, uint2 *pub_a, float *pub_ab, uint2 *pub_b,
+                             float *pub_bb);
 hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s);
 hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
                                    float *mix, hipStream_t s);
-hipError_t launch_guide_train_step(const Frame &f, const Pool &pool, const GuideTrain &T, uint32_t batch,
-                                   uint32_t step0, uint32_t nsteps, float lr, uint32_t seed, hipStream_t s,
-                                   Profiler *prof);
+hipError_t launch_guide_finalize(const Frame &f, const Pool &pool, const GuideTrain &T, hipStream_t s);
+hipError_t launch_guide_train_steps(const Frame &f, const GuideTrain &T, uint32_t batch, uint32_t step0,
+                                    uint32_t nsteps, float lr, uint32_t seed, hipStream_t s, uint2 *pub_frag,
+                                    float *pub_bias);
 hipError_t launch_guide_debug_forward(const Frame &f, const float *x, uint32_t n, float *out, hipStream_t s);
 hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const float *x, const float *dirs,
                                    const float *w, uint32_t n, float *grad, int adam, uint32_t step, float lr,
-                                   hipStream_t s);
+                                   hipStream_t s, uint2 *pub_a, float *pub_ab, uint2 *pub_b, float *pub_bb);
 hipError_t launch_guide_debug_mixture(const float *out40, const float *dirs, const float *u, uint32_t n,
                                       float *pdf, float *sample, hipStream_t s);
 

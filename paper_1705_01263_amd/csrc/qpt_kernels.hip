@@ -670,10 +670,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                     const bool guided = F.guide.alpha_thr != 0u && v <= F.guide.max_vertex;
                     guide::Mix mix;
                     if (guided) {
-                        const float4 *src = F.guide.mix + (size_t)slot * 10;
-                        for (int k = 0; k < guide::kLobes; ++k) mix.lobe[k] = src[k];
-                        mix.w0 = src[8];
-                        mix.w1 = src[9];
+                        guide::unpack_mix(F.guide.mix + (size_t)slot * guide::kMixU4, mix);
                     }
                     const float alpha = F.guide.alpha;
                     // next-event estimation
