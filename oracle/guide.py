@@ -9,9 +9,10 @@ every definition below is stated in the design notes.
 
 Precision: the workload fixes BF16 weights and activations with FP32
 accumulation. The oracle computes in FP64 on BF16-rounded weights and
-inputs and, with `bf16` set, rounds each hidden activation to BF16
-(round to nearest even) before the next layer -- the rounding points of the
-GPU path -- so the two differ only by FP32-vs-FP64 accumulation.
+inputs and, with `bf16` set, rounds each hidden activation and each
+backpropagated gradient to BF16 (round to nearest even) where the GPU path
+feeds them to its matrix units -- so the two differ only by FP32-vs-FP64
+accumulation.
 """
 from __future__ import annotations
 
@@ -109,8 +110,10 @@ def forward(theta, X, bf16=True):
 
 def backward(theta, cache, dout, bf16=True):
     """Gradient of sum(dout * outputs) w.r.t. the flat parameters. With bf16
-    the pre-activation gradient enters the weight-gradient and data products
-    rounded to BF16 (the GPU's MFMA operands); bias gradients use it unrounded."""
+    the pre-activation gradient enters every gradient product rounded to BF16
+    (the GPU's MFMA operands): the weight gradient, the bias gradient (a sum
+    over rows, i.e. a product with a column of ones) and the data gradient;
+    the sums themselves are exact here and FP32 on the GPU."""
     acts, pre, layers = cache
     rnd = to_bf16 if bf16 else (lambda a: np.asarray(a, np.float64))
     grads = [None] * len(layers)
@@ -118,7 +121,7 @@ def backward(theta, cache, dout, bf16=True):
     for li in range(len(layers) - 1, -1, -1):
         W, b = layers[li]
         gb = rnd(g)
-        grads[li] = (acts[li].T @ gb, g.sum(0))
+        grads[li] = (acts[li].T @ gb, gb.sum(0))
         if li > 0:
             g = (gb @ rnd(W).T) * (pre[li - 1] > 0)
     return pack(grads)

@@ -28,6 +28,7 @@ constexpr int kFB[4] = {0, 8, 24, 40};         // first forward fragment of each
 constexpr int kGB[4] = {0, 0, 16, 32};         // first transposed fragment (layers 1..3)
 constexpr int kOffW[4] = {0, 2112, 6272, 10432};
 constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
+constexpr int kIn[4] = {32, 64, 64, 64};          // layer input widths
 constexpr int kTrainBlock = 256;               // 4 waves
 
 // round to the nearest BF16, ties to even (v_cvt_pk_bf16_f32 on gfx950)
@@ -224,89 +225,97 @@ __device__ void row_loss_grad(const float *o, guide::V3 wd, float w, float *d, f
     }
 }
 
-// staging of one wave's operands for the weight-gradient products
-struct Stage {
-    uint16_t z[32 * 64];  // BF16 pre-activation gradients [row][out]
-    uint16_t a[32 * 64];  // BF16 layer inputs [row][in]
+// Training backward, block-cooperative. A block of four waves takes 128 rows
+// (32 per wave) per iteration. For each layer, every wave stages its rows'
+// BF16 pre-activation gradients dZ and layer inputs A in LDS, transposed
+// ([feature][row], 128 rows plus padding per feature), then each wave
+// multiplies one 32 x 32 tile of dW^T = dZ^T A over all 128 rows (the rows
+// are the MFMA reduction dimension) into an accumulator it keeps across
+// iterations, and one wave sums the rows of dZ for the bias gradient (a
+// product with a column of ones on 16 x 16 x 16 MFMA). Nothing is added
+// atomically; each gradient value is written once per block at the end.
+constexpr int kRowsPerIter = 128;
+constexpr int kStageRow = 132;   // BF16 per staged feature: 128 rows + 4 (bank-conflict-free b64 reads)
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v4s lds_b64(const uint16_t *p) { return __builtin_bit_cast(v4s, *(const uint2 *)p); }
+
+struct GradAcc {
+    v16f w[4];  // this wave's dW^T tile of each layer (layer 0: waves 0 and 1 only)
+    v4f b[4];   // bias gradient of layer `wave`, four 16-output tiles
 };
 
-__device__ __forceinline__ void wave_sync()
+// the dW^T tile of layer L owned by wave wv: output tile to = wv & 1, input
+// tile tk = wv >> 1 (layer 0 has one input tile: waves 2 and 3 own none)
+template <int L>
+__device__ __forceinline__ bool owns_tile(uint32_t wv, int &to, int &tk)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    to = (int)(wv & 1u);
+    tk = (int)(wv >> 1);
+    return tk < kKS[L] / 4;
 }
 
-__device__ __forceinline__ v4s gather_col(const uint16_t *base, uint32_t col, uint32_t r0)
-{
-    v4s r;
-    r.x = (short)base[(r0 + 0) * 64 + col];
-    r.y = (short)base[(r0 + 1) * 64 + col];
-    r.z = (short)base[(r0 + 2) * 64 + col];
-    r.w = (short)base[(r0 + 3) * 64 + col];
-    return r;
-}
-
-// Backward through layer L for the wave's 32 rows: bias and weight gradients
-// into the block's LDS accumulator, and (L > 0) the pre-activation gradient
-// of layer L-1 in D layout.
 template <int L>
 __device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const uint2 *sfragT, uint32_t mask_prev,
-                                          float *sgrad, Stage &st, v16f *dz_prev)
+                                          uint16_t *sZ, uint16_t *sA, uint32_t wv, GradAcc &acc, v16f *dz_prev)
 {
     const uint32_t lane = lane_id(), half = lane >> 5, row = lane & 31;
+    const uint32_t R = wv * 32 + row;  // the lane's row within the block's 128
     constexpr int KS = kKS[L], N = kN[L];
-    // bias gradients from the FP32 values
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int o = 32 * t + 8 * (v / 4) + 4 * half + (v % 4);
-            if (o < N) atomicAdd(&sgrad[kOffB[L] + o], dz[t][v]);
-        }
-    // stage BF16 operands [row][feature]
+    // BF16 operands: zf[s] = dZ[row][8s + 4 half + e] (the data-gradient B operand)
     v4s zf[8];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         int t = s / 4, b = 4 * (s % 4);
         zf[s] = pack4(dz[t][b], dz[t][b + 1], dz[t][b + 2], dz[t][b + 3]);
-        *(v4s *)&st.z[row * 64 + 8 * s + 4 * half] = zf[s];
     }
 #pragma unroll
-    for (int s = 0; s < KS; ++s) *(v4s *)&st.a[row * 64 + 8 * s + 4 * half] = in[s];
-    wave_sync();
-    // dW^T[o][k] = sum_rows dZ^T[o][row] A[row][k]
+    for (int s = 0; s < 8; ++s)
 #pragma unroll
-    for (int to = 0; to < 2; ++to) {
-        if (to == 1 && N <= 32) continue;
+        for (int e = 0; e < 4; ++e) sZ[(8 * s + 4 * half + e) * kStageRow + R] = (uint16_t)zf[s][e];
 #pragma unroll
-        for (int tk = 0; tk < KS / 4; ++tk) {
-            v16f c = {};
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                v4s A = gather_col(st.z, 32 * to + row, 8 * s + 4 * half);
-                v4s B = gather_col(st.a, 32 * tk + row, 8 * s + 4 * half);
-                c = mfma(A, B, c);
-            }
+        for (int e = 0; e < 4; ++e) sA[(8 * s + 4 * half + e) * kStageRow + R] = (uint16_t)in[s][e];
+    __syncthreads();
+    int to, tk;
+    if (owns_tile<L>(wv, to, tk) && !(to == 1 && N <= 32)) {
+        const uint16_t *za = sZ + (32 * to + row) * kStageRow + 4 * half;
+        const uint16_t *aa = sA + (32 * tk + row) * kStageRow + 4 * half;
+        v16f c = acc.w[L];
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                int o = 32 * to + 8 * (v / 4) + 4 * half + (v % 4);
-                int k = 32 * tk + row;
-                if (o < N) atomicAdd(&sgrad[kOffW[L] + k * N + o], c[v]);
-            }
+        for (int s = 0; s < kRowsPerIter / 8; ++s) c = mfma(lds_b64(za + 8 * s), lds_b64(aa + 8 * s), c);
+        acc.w[L] = c;
+    }
+    if (wv == (uint32_t)L) {
+        const v4s ones = {(short)0x3F80, (short)0x3F80, (short)0x3F80, (short)0x3F80};
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            if (16 * ot >= N) continue;
+            const uint16_t *za = sZ + (16 * ot + (lane & 15)) * kStageRow + 4 * (lane >> 4);
+            v4f c = acc.b[ot];
+#pragma unroll
+            for (int s = 0; s < kRowsPerIter / 16; ++s) c = mfma16(lds_b64(za + 16 * s), ones, c);
+            acc.b[ot] = c;
         }
     }
-    wave_sync();
+    __syncthreads();
     if constexpr (L > 0) {
         // dA^T[k][row] = sum_o W[k][o] dZ^T[o][row], then the ReLU mask of layer L-1
 #pragma unroll
-        for (int tk = 0; tk < 2; ++tk) {
+        for (int tkk = 0; tkk < 2; ++tkk) {
             v16f c = {};
 #pragma unroll
-            for (int s = 0; s < 8; ++s) c = mfma(as_v4s(sfragT[(kGB[L] + tk * 8 + s) * 64 + lane]), zf[s], c);
+            for (int s = 0; s < 8; ++s) c = mfma(as_v4s(sfragT[(kGB[L] + tkk * 8 + s) * 64 + lane]), zf[s], c);
 #pragma unroll
-            for (int v = 0; v < 16; ++v) c[v] = ((mask_prev >> (16 * tk + v)) & 1u) ? c[v] : 0.0f;
-            dz_prev[tk] = c;
+            for (int v = 0; v < 16; ++v) c[v] = ((mask_prev >> (16 * tkk + v)) & 1u) ? c[v] : 0.0f;
+            dz_prev[tkk] = c;
         }
     }
 }
@@ -497,9 +506,12 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
     }
 }
 
-// training records -> candidates with a positive loss weight: the luminance
-// of the sample's own estimate f cos L_i / p of the scattering integral, so
-// that the network learns a density proportional to the integrand
+// training records -> replay samples with a positive loss weight: the
+// luminance of the sample's own estimate f cos L_i / p of the scattering
+// integral, so that the network learns a density proportional to the
+// integrand. Samples are appended to a ring that keeps the newest ring_cap;
+// a weight estimated under an older proposal is still an estimate of the
+// same integrand, so older samples remain valid training data.
 __global__ void k_rec_finalize(Frame F, Pool P, GuideTrain T)
 {
     uint32_t cnt = min(*F.guide.rec_count, F.guide.rec_cap);
@@ -515,21 +527,27 @@ __global__ void k_rec_finalize(Frame F, Pool P, GuideTrain T)
             float w = 0.0f;
             const float wl[3] = {0.2126f, 0.7152f, 0.0722f};
             for (int c = 0; c < 3; ++c) w += tb[c] > 0.0f ? wl[c] * fmaxf(0.0f, li[c] / tb[c]) : 0.0f;
-#if QPT_GUIDE_W2
-            w = w * w;
-#endif
-            r[1].w = w;
             ok = w > 0.0f && w < INFINITY;
+            if (ok) {
+                r[1].w = w;
+            }
         }
         unsigned long long mask = __ballot(ok);
         uint32_t b = 0;
         if (mask) {
             uint32_t leader = __ffsll((long long)mask) - 1;
-            if (lane_id() == leader) b = atomicAdd(T.cand_count, (uint32_t)__popcll(mask));
+            if (lane_id() == leader) b = atomicAdd(T.ring_head, (uint32_t)__popcll(mask));
             b = __shfl(b, (int)leader);
         }
         uint32_t off = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-        if (ok) T.cand[b + off] = i;
+        if (ok) {
+            const float4 *r = F.guide.rec + (size_t)i * kRecF4;
+            float4 *q = T.ring + (size_t)((b + off) & (T.ring_cap - 1u)) * kRingF4;
+            float4 r0 = r[0], r1 = r[1], r2 = r[2];
+            q[0] = make_float4(r0.x, r0.y, r0.z, r1.w);
+            q[1] = make_float4(r1.x, r1.y, r1.z, 0.0f);
+            q[2] = make_float4(r2.x, r2.y, r2.z, 0.0f);
+        }
     }
 }
 
@@ -537,8 +555,8 @@ struct RowSrc {
     // records (debug == false) or explicit arrays (debug == true)
     bool debug;
     const float *x, *dirs, *w;  // debug: n x 32 features, n x 3, n
-    uint32_t n;                  // debug: rows; records: the batch size
-    const uint32_t *count;       // records: candidates available (device)
+    uint32_t n;                  // debug: rows; replay: the batch size
+    const uint32_t *count;       // replay: samples ever appended to the ring (device)
     float u;                     // stratification offset in [0, 1)
 };
 
@@ -548,24 +566,28 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
     uint2 *sfrag = (uint2 *)smem;
     uint2 *sfragT = sfrag + kGuideFrags * 64;
     float *sbias = (float *)(sfragT + kGuideFragsT * 64);
-    float *sgrad = sbias + 256;
-    Stage *stage = (Stage *)(sgrad + ((kGuideParams + 63) / 64) * 64);
+    uint16_t *sZ = (uint16_t *)(sbias + 256);
+    uint16_t *sA = sZ + 64 * kStageRow;
     for (uint32_t i = threadIdx.x; i < kGuideFrags * 64; i += blockDim.x) sfrag[i] = T.frag[i];
     for (uint32_t i = threadIdx.x; i < kGuideFragsT * 64; i += blockDim.x) sfragT[i] = T.fragT[i];
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = T.bias[i];
-    for (uint32_t i = threadIdx.x; i < kGuideParams; i += blockDim.x) sgrad[i] = 0.0f;
     __syncthreads();
     const uint32_t lane = lane_id(), wv = threadIdx.x / 64;
-    Stage &st = stage[wv];
-    const uint32_t wave = blockIdx.x * (kTrainBlock / 64) + wv, waves = gridDim.x * (kTrainBlock / 64);
-    // records: a batch of min(batch, candidates) rows, a stratified subset
-    const uint32_t count = src.debug ? src.n : *src.count;
+    // replay: a batch of min(batch, samples held) rows, a stratified subset
+    const uint32_t count = src.debug ? src.n : min(*src.count, T.ring_cap);
     const uint32_t nrows = min(src.n, count);
-    const uint32_t tiles = (nrows + 31) / 32;
+    const uint32_t iters = (nrows + kRowsPerIter - 1) / kRowsPerIter;
+    GradAcc acc;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+        acc.w[L] = (v16f){};
+        acc.b[L] = (v4f){};
+    }
     float wsum = 0.0f, lsum = 0.0f;
-    for (uint32_t tile = wave; tile < tiles; tile += waves) {
+    // every wave of a block runs the same iterations (block-wide barriers inside)
+    for (uint32_t it = blockIdx.x; it < iters; it += gridDim.x) {
         asm volatile("" ::: "memory");  // weight reads stay in the loop
-        uint32_t row = tile * 32 + (lane & 31);
+        uint32_t row = it * kRowsPerIter + wv * 32 + (lane & 31);
         bool valid = row < nrows;
         float f[32];
         guide::V3 wd = {0.0f, 0.0f, 1.0f};
@@ -577,14 +599,14 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
                 wd = {src.dirs[3 * (size_t)row], src.dirs[3 * (size_t)row + 1], src.dirs[3 * (size_t)row + 2]};
                 wt = src.w[row];
             } else {
-                // stratified subset of the candidates
+                // stratified subset of the ring's samples
                 uint32_t c = (uint32_t)(((double)row + src.u) * (double)count / (double)nrows);
                 c = min(c, count - 1);
-                const float4 *r = F.guide.rec + (size_t)T.cand[c] * kRecF4;
+                const float4 *r = T.ring + (size_t)c * kRingF4;
                 float4 r0 = r[0], r1 = r[1], r2 = r[2];
                 guide::encode(guide::V3{r0.x, r0.y, r0.z}, guide::V3{r1.x, r1.y, r1.z}, F.guide.bmin, F.guide.binv, f);
                 wd = {r2.x, r2.y, r2.z};
-                wt = r1.w;
+                wt = r0.w;
             }
         }
         v4s a0[4];
@@ -601,10 +623,10 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         }
         v16f dz[2], dzp[2];
         scatter40(d, dz);
-        layer_bwd<3>(dz, A.a3, sfragT, A.m2, sgrad, st, dzp);
-        layer_bwd<2>(dzp, A.a2, sfragT, A.m1, sgrad, st, dz);
-        layer_bwd<1>(dz, A.a1, sfragT, A.m0, sgrad, st, dzp);
-        layer_bwd<0>(dzp, a0, sfragT, 0u, sgrad, st, dz);
+        layer_bwd<3>(dz, A.a3, sfragT, A.m2, sZ, sA, wv, acc, dzp);
+        layer_bwd<2>(dzp, A.a2, sfragT, A.m1, sZ, sA, wv, acc, dz);
+        layer_bwd<1>(dz, A.a1, sfragT, A.m0, sZ, sA, wv, acc, dzp);
+        layer_bwd<0>(dzp, a0, sfragT, 0u, sZ, sA, wv, acc, dz);
     }
     for (int off = 32; off > 0; off >>= 1) {
         wsum += __shfl_xor(wsum, off);
@@ -614,9 +636,38 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         atomicAdd(&T.scalars[0], wsum);
         atomicAdd(&T.scalars[1], lsum);
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kGuideParams; i += blockDim.x)
-        T.partial[(size_t)blockIdx.x * kGuideParams + i] = sgrad[i];
+    // this block's gradient sums: every parameter written by exactly one lane
+    float *out_p = T.partial + (size_t)blockIdx.x * kGuideParams;
+    const uint32_t half = lane >> 5;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+        int to, tk;
+        bool own;
+        switch (L) {
+        case 0: own = owns_tile<0>(wv, to, tk); break;
+        case 1: own = owns_tile<1>(wv, to, tk); break;
+        case 2: own = owns_tile<2>(wv, to, tk); break;
+        default: own = owns_tile<3>(wv, to, tk); break;
+        }
+        if (!own) continue;
+        const int N = kN[L];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            int o = 32 * to + 8 * (v / 4) + 4 * (int)half + (v % 4);
+            int k = 32 * tk + (int)(lane & 31);
+            if (o < N) out_p[kOffW[L] + k * N + o] = acc.w[L][v];
+        }
+    }
+    if ((lane & 15) == 0) {
+        const int N = kN[wv];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int o = 16 * ot + 4 * (int)(lane >> 4) + v;
+                if (o < N) out_p[kOffB[wv] + o] = acc.b[ot][v];
+            }
+    }
 }
 
 // sum the block partials, normalise by the weight sum; then Adam or a plain
@@ -702,8 +753,7 @@ __global__ void k_guide_mix_debug(const float *out40, const float *dirs, const f
 
 size_t train_smem()
 {
-    return kGuideFrags * 64 * 8 + kGuideFragsT * 64 * 8 + 256 * 4 + ((kGuideParams + 63) / 64) * 64 * 4 +
-           4 * sizeof(Stage);
+    return kGuideFrags * 64 * 8 + kGuideFragsT * 64 * 8 + 256 * 4 + 2 * 64 * kStageRow * 2;
 }
 
 inline uint32_t nblocks(size_t n, uint32_t bs, uint32_t cap)
@@ -774,8 +824,13 @@ static hipError_t run_train(const Frame &f, const GuideTrain &T, const RowSrc &s
 
 hipError_t launch_guide_finalize(const Frame &f, const Pool &pool, const GuideTrain &T, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u32_1, dim3(1), dim3(1), 0, s, T.cand_count);
     hipLaunchKernelGGL(k_rec_finalize, dim3(nblocks(f.guide.rec_cap, 256, 4096)), dim3(256), 0, s, f, pool, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_guide_ring_clear(const GuideTrain &T, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32_1, dim3(1), dim3(1), 0, s, T.ring_head);
     return hipGetLastError();
 }
 
@@ -792,7 +847,7 @@ hipError_t launch_guide_train_steps(const Frame &f, const GuideTrain &T, uint32_
         z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
         z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
         z ^= z >> 31;
-        RowSrc src{false, nullptr, nullptr, nullptr, batch, T.cand_count, (float)((z >> 40) * 0x1p-24)};
+        RowSrc src{false, nullptr, nullptr, nullptr, batch, T.ring_head, (float)((z >> 40) * 0x1p-24)};
         uint32_t blocks = 0;
         e = run_train(f, T, src, s, &blocks);
         if (e != hipSuccess) break;

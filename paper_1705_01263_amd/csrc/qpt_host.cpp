@@ -269,8 +269,8 @@ struct Layout {
         env_col, env_cos, bases;
     size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats, gstack;
     size_t fb_sum, fb_count;
-    size_t g_frag, g_fragT, g_bias, g_mix, g_master, g_m, g_v, g_partial, g_scalars;
-    size_t g_rec[2], g_cand[2], g_cand_count[2], g_pub_frag[2], g_pub_bias[2];
+    size_t g_frag, g_fragT, g_bias, g_mix, g_rec, g_ring, g_ring_head, g_master, g_m, g_v, g_partial, g_scalars;
+    size_t g_pub_frag[2], g_pub_bias[2];
     size_t total;
 };
 
@@ -330,13 +330,11 @@ struct qpt_ctx {
     uint32_t stack_need = 3;      // traversal stack entries per ray the BVH can require
     // training runs on a stream of its own, one batch behind the renderer
     hipStream_t tstream = nullptr;
-    hipEvent_t ev_rec[2] = {nullptr, nullptr};    // batch k's records and candidates are ready
-    hipEvent_t ev_train[2] = {nullptr, nullptr};  // the step on buffer k has finished
+    hipEvent_t ev_rec[2] = {nullptr, nullptr};    // batch k's samples are in the ring
+    hipEvent_t ev_train[2] = {nullptr, nullptr};  // the step publishing into buffer k has finished
     bool train_pending[2] = {false, false};
     uint64_t gbatch = 0;   // training batches issued
     int last_buf = 0;      // buffer of the newest published weights
-    float4 *rec_buf[2] = {nullptr, nullptr};
-    uint32_t *cand_buf[2] = {nullptr, nullptr}, *cand_count_buf[2] = {nullptr, nullptr};
     uint2 *pub_frag[2] = {nullptr, nullptr};
     float *pub_bias[2] = {nullptr, nullptr};
     double bbox[6] = {0, 0, 0, 1, 1, 1};
@@ -615,9 +613,10 @@ void set_frame_constants(qpt_ctx *c)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// training records per buffer: the renderer keeps a hashed subset of about
-// twice the batch per pass, so twice the pool (at most 2^21) is ample
-size_t guide_rec_cap(uint32_t cap) { return std::min<size_t>((size_t)1 << 21, (size_t)cap * 2); }
+// training records per batch (vertices 1..max_vertex of each path, or a
+// hashed subset of the vertices when that would overflow)
+size_t guide_rec_cap(uint32_t cap) { return std::min<size_t>((size_t)1 << 22, (size_t)cap * 2); }
+constexpr uint32_t kGuideRing = 1u << 20;   // replay samples kept
 
 Layout make_layout(const qpt_ctx *c, uint32_t cap)
 {
@@ -658,18 +657,18 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
-    // learned proposal: weights, per-slot mixtures, training records and
-    // state; records, candidates and the renderer's copy of the weights are
+    // learned proposal: weights, per-slot mixtures, training records, the
+    // replay ring and optimiser state; the renderer's copy of the weights is
     // double-buffered so a training step overlaps the next batch
     size_t rec_cap = guide_rec_cap(cap);
     L.g_frag = take(kGuideFrags * 64 * 8);
     L.g_fragT = take(kGuideFragsT * 64 * 8);
     L.g_bias = take(256 * 4);
     L.g_mix = take((size_t)cap * 5 * 16);
+    L.g_rec = take(rec_cap * kRecF4 * 16);
+    L.g_ring = take((size_t)kGuideRing * kRingF4 * 16);
+    L.g_ring_head = take(4);
     for (int k = 0; k < 2; ++k) {
-        L.g_rec[k] = take(rec_cap * kRecF4 * 16);
-        L.g_cand[k] = take(rec_cap * 4);
-        L.g_cand_count[k] = take(4);
         L.g_pub_frag[k] = take(kGuideFrags * 64 * 8);
         L.g_pub_bias[k] = take(256 * 4);
     }
@@ -1067,16 +1066,14 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     T.fragT = (uint2 *)(w + L.g_fragT);
     T.bias = (float *)(w + L.g_bias);
     for (int k = 0; k < 2; ++k) {
-        c->rec_buf[k] = (float4 *)(w + L.g_rec[k]);
-        c->cand_buf[k] = (uint32_t *)(w + L.g_cand[k]);
-        c->cand_count_buf[k] = (uint32_t *)(w + L.g_cand_count[k]);
         c->pub_frag[k] = (uint2 *)(w + L.g_pub_frag[k]);
         c->pub_bias[k] = (float *)(w + L.g_pub_bias[k]);
     }
     c->gbatch = 0;
     c->last_buf = 0;
-    T.cand = c->cand_buf[0];
-    T.cand_count = c->cand_count_buf[0];
+    T.ring = (float4 *)(w + L.g_ring);
+    T.ring_head = (uint32_t *)(w + L.g_ring_head);
+    T.ring_cap = kGuideRing;
     T.partial = (float *)(w + L.g_partial);
     T.scalars = (float *)(w + L.g_scalars);
     T.max_blocks = c->guide_blocks;
@@ -1092,7 +1089,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.alpha_thr = 0;
     G.alpha = 0.0f;
     G.record = 0;
-    G.rec = c->rec_buf[0];
+    G.rec = (float4 *)(w + L.g_rec);
     G.rec_cap = (uint32_t)guide_rec_cap(cap);
     G.rec_count = p.counters + 127;
     c->guide_weights = false;
@@ -1147,32 +1144,32 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         f.guide.alpha = (float)((double)f.guide.alpha_thr / 4294967296.0);
         f.guide.record = c->gopts.train ? 1u : 0u;
         f.guide.max_vertex = c->gopts.max_vertex ? c->gopts.max_vertex : 0xffffffffu;
-        // a uniform subset of the vertices, about twice the batch per path of
-        // the batch, is enough to draw each step's stratified batch from
+        // every vertex 1..max_vertex leaves a record, unless a path could
+        // leave more than the buffer holds per path: then a uniform hashed subset
         {
-            uint32_t b = c->gopts.batch ? c->gopts.batch : (1u << 18);
-            double keep = std::min(1.0, 2.0 * (double)b / ((double)np * (double)nb));
+            double per_path = (double)std::min<uint32_t>(f.guide.max_vertex, o->max_depth);
+            double keep = std::min(1.0, (double)f.guide.rec_cap / (per_path * (double)np * (double)nb));
             f.guide.rec_thr = keep >= 1.0 ? 0xffffffffu : (uint32_t)(keep * 4294967296.0);
         }
-        // Weights, records and candidates are double-buffered: batch b renders
-        // with the weights the step of batch b - 2 published (its buffer,
-        // b mod 2, is free once that step has finished) while the step of
-        // batch b - 1 runs on the training stream. Any weights give an
-        // unbiased estimator; the lag only delays what the guide has learnt.
+        // The renderer's copy of the weights is double-buffered: batch b
+        // renders with the weights the step of batch b - 2 published (buffer
+        // b mod 2, free once that step has finished) while the step of batch
+        // b - 1 runs on the training stream. Any weights give an unbiased
+        // estimator; the lag only delays what the guide has learnt. Batch b's
+        // samples enter the replay ring right after it (they read path
+        // radiance the next batch overwrites), once step b - 1 has stopped
+        // reading the ring.
         const bool train = c->gopts.train > 0;
         const int k = train ? (int)(c->gbatch & 1) : c->last_buf;
         if (guiding) {
             if (c->train_pending[k]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[k], 0));
             f.guide.frag = c->pub_frag[k];
             f.guide.bias = c->pub_bias[k];
-            f.guide.rec = c->rec_buf[k];
         }
         HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
         if (train) {
             GuideTrain T = c->gt;
-            T.cand = c->cand_buf[k];
-            T.cand_count = c->cand_count_buf[k];
-            // candidates now: the path radiance they read is overwritten by the next batch
+            if (c->train_pending[1 - k]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[1 - k], 0));
             if (prof) prof->begin(K_GUIDE_TRAIN, c->stream);
             HIP_TRY(c, launch_guide_finalize(f, c->pool, T, c->stream));
             if (prof) prof->end(K_GUIDE_TRAIN, c->stream);
@@ -1331,6 +1328,7 @@ int qpt_guide_set_weights(qpt_ctx *c, const float *params)
     HIP_TRY(c, hipMemsetAsync(c->gt.m, 0, kGuideParams * 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->gt.v, 0, kGuideParams * 4, c->stream));
     HIP_TRY(c, launch_guide_frag(c->gt, c->stream, c->pub_frag[0], c->pub_bias[0], c->pub_frag[1], c->pub_bias[1]));
+    HIP_TRY(c, launch_guide_ring_clear(c->gt, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->guide_weights = true;
     c->guide_steps = 0;

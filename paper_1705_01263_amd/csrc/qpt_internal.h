@@ -55,6 +55,7 @@ constexpr uint32_t kGuideParams = 13032;
 constexpr uint32_t kGuideFrags = 56;    // forward weight fragments (64 lanes x 4 bf16 each)
 constexpr uint32_t kGuideFragsT = 48;   // transposed fragments for the backward pass
 constexpr uint32_t kRecF4 = 6;          // float4 per training record
+constexpr uint32_t kRingF4 = 3;         // float4 per replay sample: (x, weight), (wo, -), (wi, -)
 
 struct GuideDev {
     const uint2 *frag;       // kGuideFrags * 64: 4 bf16 per lane (MFMA A operands)
@@ -152,8 +153,9 @@ struct GuideTrain {
     float *master, *m, *v;   // kGuideParams each, FP32
     uint2 *frag, *fragT;     // written from master after every step
     float *bias;             // 256
-    uint32_t *cand;          // candidate record indices (weight > 0)
-    uint32_t *cand_count;
+    float4 *ring;            // replay ring of training samples, kRingF4 float4 each
+    uint32_t *ring_head;     // samples ever appended (the ring keeps the last ring_cap)
+    uint32_t ring_cap;       // a power of two
     float *partial;          // blocks x kGuideParams unnormalised gradient sums
     float *scalars;          // [0] sum of loss weights [1] weighted loss sum
     uint32_t max_blocks;
@@ -171,6 +173,7 @@ hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint3
 hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
                                    float *mix, hipStream_t s);
 hipError_t launch_guide_finalize(const Frame &f, const Pool &pool, const GuideTrain &T, hipStream_t s);
+hipError_t launch_guide_ring_clear(const GuideTrain &T, hipStream_t s);
 hipError_t launch_guide_train_steps(const Frame &f, const GuideTrain &T, uint32_t batch, uint32_t step0,
                                     uint32_t nsteps, float lr, uint32_t seed, hipStream_t s, uint2 *pub_frag,
                                     float *pub_bias);

@@ -7,6 +7,12 @@ writes per-kernel launch counts and durations.
 turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) into HBM bytes per launch of
 `kernel`, each counter scaled by what it reads for the calibration copy
 kernel of known size in the same run.
+
+`python -m paper_1705_01263_amd.profiling mfma <pmc_dir> <out.txt> --cmd "..."` summarises
+BF16 MFMA FLOPs and MFMA busy cycles of the network kernels.
+
+`python -m paper_1705_01263_amd.profiling guided [--size WxH --tris N --passes K]`
+runs a guided, training workload on the slit scene to be profiled.
 """
 from __future__ import annotations
 
@@ -23,6 +29,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def kernel_sha() -> str:
     src = os.path.join(ROOT, "paper_1705_01263_amd", "csrc", "qpt_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def guide_sha() -> str:
+    src = os.path.join(ROOT, "paper_1705_01263_amd", "csrc", "qpt_guide.hip")
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
@@ -93,6 +104,62 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, out_txt: str, cal
     return txt
 
 
+def summarize_mfma(pmc_dir: str, kernels, out_txt: str, cmd: str, simds: int = 1024) -> str:
+    """Per-dispatch MFMA and VALU activity of `kernels` from one rocprofv3
+    --pmc run with SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_VALU_MFMA_BUSY_CYCLES,
+    SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES and GRBM_GUI_ACTIVE.
+    MFMA FLOPs = MOPS_BF16 x 512; utilisation = MFMA busy cycles over
+    GRBM_GUI_ACTIVE x SIMDs (256 CUs x 4 on MI355X)."""
+    f = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)[0]
+    per = collections.defaultdict(lambda: collections.defaultdict(dict))  # kernel -> dispatch -> counter
+    dur = collections.defaultdict(dict)
+    for r in csv.DictReader(open(f)):
+        k = _short(r["Kernel_Name"])
+        d = r["Dispatch_Id"]
+        per[k][d][r["Counter_Name"]] = float(r["Counter_Value"])
+        dur[k][d] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    lines = ["# rocprofv3 --pmc MFMA / VALU summary", f"command: {cmd}", f"kernel_source_sha: {kernel_sha()}",
+             f"guide_source_sha: {guide_sha()}",
+             f"SIMDs: {simds}", ""]
+    for k in kernels:
+        if k not in per:
+            lines.append(f"{k}: no dispatches")
+            continue
+        ds = list(per[k])
+        avg = lambda c: sum(per[k][d].get(c, 0.0) for d in ds) / len(ds)
+        t_ns = sum(dur[k][d] for d in ds) / len(ds)
+        flops = avg("SQ_INSTS_VALU_MFMA_MOPS_BF16") * 512
+        busy, gui = avg("SQ_VALU_MFMA_BUSY_CYCLES"), avg("GRBM_GUI_ACTIVE")
+        lines += [f"{k}: dispatches {len(ds)}, avg duration {t_ns / 1e3:.2f} us",
+                  f"  BF16 MFMA FLOP per dispatch {flops:.4g} -> {flops / t_ns / 1e3:.2f} TFLOP/s "
+                  f"({100 * flops / t_ns / 1e3 / 2500.0:.2f}% of the 2.5 PFLOP/s dense BF16 peak)",
+                  f"  MFMA busy {100 * busy / max(gui * simds, 1):.2f}% of SIMD cycles "
+                  f"(SQ_VALU_MFMA_BUSY_CYCLES {busy:.4g}, GRBM_GUI_ACTIVE {gui:.4g})",
+                  f"  SQ_INSTS_VALU {avg('SQ_INSTS_VALU'):.4g}, SQ_ACTIVE_INST_VALU {avg('SQ_ACTIVE_INST_VALU'):.4g}, "
+                  f"SQ_BUSY_CU_CYCLES {avg('SQ_BUSY_CU_CYCLES'):.4g}"]
+    txt = "\n".join(lines) + "\n"
+    open(out_txt, "w").write(txt)
+    return txt
+
+
+def run_guided(width: int, height: int, tris: int, passes: int, alpha: float = 0.7, max_vertex: int = 2) -> None:
+    """A guided workload to profile: the slit scene with the guide training
+    one step per batch of passes from its first pass."""
+    import torch
+
+    import scenegen
+    from paper_1705_01263_amd import Renderer
+
+    sc = scenegen.slit_scene(width=width, height=height, target_tris=tris, max_depth=16)
+    r = Renderer(sc)
+    r.ctx.guide_set_weights(scenegen.guide_init(1))
+    r.ctx.guide_config(alpha=alpha, lr=1e-3, batch=1 << 18, train=1, warmup_steps=0, seed=1, max_vertex=max_vertex)
+    r.render(0, passes)
+    torch.cuda.synchronize()
+    _, steps = r.ctx.guide_get_weights()
+    print(f"guided: {passes} passes of {sc.name} {width}x{height}, {steps} Adam steps", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -107,11 +174,26 @@ def main():
     p.add_argument("out")
     p.add_argument("--calib-mib", type=int, required=True)
     p.add_argument("--cmd", required=True)
+    m = sub.add_parser("mfma")
+    m.add_argument("pmc_dir")
+    m.add_argument("out")
+    m.add_argument("--kernels", default="k_guide_eval,k_guide_train")
+    m.add_argument("--cmd", required=True)
+    gd = sub.add_parser("guided")
+    gd.add_argument("--size", default="1920x1080")
+    gd.add_argument("--tris", type=int, default=4_000_000)
+    gd.add_argument("--passes", type=int, default=8)
+    gd.add_argument("--max-vertex", type=int, default=2)
     a = ap.parse_args()
     if a.what == "trace":
         print(summarize_trace(a.src, a.out, a.cmd))
-    else:
+    elif a.what == "pmc":
         print(summarize_pmc(a.fetch_dir, a.write_dir, a.kernel, a.out, a.calib_mib, a.cmd))
+    elif a.what == "mfma":
+        print(summarize_mfma(a.pmc_dir, a.kernels.split(","), a.out, a.cmd))
+    else:
+        w, h = (int(v) for v in a.size.split("x"))
+        run_guided(w, h, a.tris, a.passes, max_vertex=a.max_vertex)
 
 
 if __name__ == "__main__":
