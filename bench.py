@@ -30,6 +30,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "grid": (1, "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
+                "1 spp per step, max depth 12, NEE+MIS, roulette"),
+    "city": (4, "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
+                "selection), 3840x2160 in pixel chunks of the path pool, 1 spp per step, max depth 16, NEE+MIS, "
+                "roulette"),
+}
 GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 8, 2
 
 # algorithmic bytes per unit of work ("Measurement")
@@ -90,6 +97,7 @@ def cpu_baseline(sc, seconds: float):
         "value": rays / dt / 1e6,
         "unit": "Mrays/s",
         "cores": threads,
+        "host_cpu": _host_cpu(),
         "kind": "oracle",
         "sample": f"every 8th pixel in x and y ({pix.shape[0]} px) of the {W}x{H} frame, passes 0..{passes - 1}, "
                   f"FP64 oracle, {rays} rays in {dt:.1f} s, BVH build ({build_s:.1f} s) excluded",
@@ -97,13 +105,36 @@ def cpu_baseline(sc, seconds: float):
     }
 
 
+def _host_cpu():
+    """CPU model and threads per core of this host, from /proc/cpuinfo."""
+    model, siblings, cores = "unknown", None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and model == "unknown":
+                model = v
+            elif k == "siblings" and siblings is None:
+                siblings = int(v)
+            elif k == "cpu cores" and cores is None:
+                cores = int(v)
+    except OSError:
+        pass
+    tpc = siblings // cores if siblings and cores else None
+    return {"model": model, "threads_per_core": tpc, "logical_cpus": os.cpu_count()}
+
+
 def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: int, height: int, tris: int):
     """Equal-time RMSE of the plain and the guided tracer on the slit workload.
 
-    Both runs get the same wall time on the same GPU, the guided one
-    including its online training from an untrained network. The error is
-    measured against (a) the plain tracer at `ref_passes` passes from an
-    independent pass range (FP64 accumulation, whole frame) and (b) the FP64
+    Both runs of a pair get the same wall time on the same GPU, the guided
+    one including its online training from an untrained network. Two
+    budgets: the plain tracer's time for 64 passes, and `seconds`. Two
+    cameras: looking at the half of the enclosure the sunlit strip does not
+    reach (the workload's camera: every pixel lit indirectly), and looking
+    along the enclosure at the strip. The error is measured against the plain
+    tracer at `ref_passes` passes from an independent pass range (FP64
+    accumulation, whole frame) and, for the first camera, against the FP64
     CPU oracle on a bounded pixel sample, also from an independent pass range.
     """
     import numpy as np
@@ -115,79 +146,92 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
 
     sc = scenegen.slit_scene(width=width, height=height, target_tris=tris, max_depth=16)
     _say(f"bench: equal-time workload {sc.name} tris={sc.num_triangles} {width}x{height} D=16")
-    r = Renderer(sc, device=0)
-
-    def run_for(budget, guided):
-        r.reset()
-        if guided:
-            r.ctx.guide_set_weights(scenegen.guide_init(1))
-            r.ctx.guide_config(alpha=GUIDE_ALPHA, lr=1e-3, batch=1 << 18, train=1, warmup_steps=GUIDE_WARMUP, seed=1,
-                               max_vertex=GUIDE_MAX_VERTEX)
-        else:
-            r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n = 0
-        while time.perf_counter() - t0 < budget:
-            r.render(n, 4)
-            n += 4
-            torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        s, c = r.readback()
-        return s / c[:, None], n, dt
-
-    r.render(0, 4)  # warm-up (module load, first launches)
-    torch.cuda.synchronize()
-    plain, n_p, t_p = run_for(seconds, False)
-    guided, n_g, t_g = run_for(t_p, True)
-    loss = r.ctx.guide_loss()[0]
-    _, steps = r.ctx.guide_get_weights()
-    # GPU reference from passes no run above used
-    r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
-    r.reset()
-    t0 = time.perf_counter()
-    r.render(1 << 24, ref_passes)
-    s, c = r.readback()
-    ref = s / c[:, None]
-    t_ref = time.perf_counter() - t0
-    del r
-    torch.cuda.empty_cache()
     rmse = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))
-    out = {
-        "workload": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth 16, sun and sky through a "
-                    "0.1-wide roof slit",
-        "seconds": round(t_p, 3),
-        "plain": {"passes": n_p, "seconds": round(t_p, 3), "rmse_vs_gpu_reference": rmse(plain, ref)},
-        "guided": {"passes": n_g, "seconds": round(t_g, 3), "rmse_vs_gpu_reference": rmse(guided, ref),
-                   "alpha": GUIDE_ALPHA, "guided_vertices": GUIDE_MAX_VERTEX, "lr": 1e-3, "batch": 1 << 18,
-                   "train_steps": int(steps), "final_loss": round(loss, 4)},
-        "gpu_reference": {"passes": ref_passes, "first_pass": 1 << 24, "seconds": round(t_ref, 2)},
-    }
-    # FP64 oracle reference on a pixel sample
-    if oracle_seconds > 0:
+    views = [("indirectly lit half (the workload's camera)", sc.camera),
+             ("along the enclosure, sunlit strip in view",
+              scenegen.Camera((0.0, 4.0, -28.0), (0.0, 2.0, 0.0), (0.0, 1.0, 0.0), 40.0))]
+    out = {"workload": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth 16, sun and sky "
+                       "through a 0.1-wide roof slit",
+           "guide": {"alpha": GUIDE_ALPHA, "guided_vertices": GUIDE_MAX_VERTEX, "lr": 1e-3, "batch": 1 << 18,
+                     "adam_steps_per_pass": 1, "warmup_steps": GUIDE_WARMUP},
+           "views": []}
+    for vi, (vname, cam) in enumerate(views):
+        sc.camera = cam
+        r = Renderer(sc, device=0)
+
+        def run(budget=None, passes=None, guided=False):
+            r.reset()
+            if guided:
+                r.ctx.guide_set_weights(scenegen.guide_init(1))
+                r.ctx.guide_config(alpha=GUIDE_ALPHA, lr=1e-3, batch=1 << 18, train=1, warmup_steps=GUIDE_WARMUP,
+                                   seed=1, max_vertex=GUIDE_MAX_VERTEX)
+            else:
+                r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = 0
+            while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
+                r.render(n, 4)
+                n += 4
+                torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s, c = r.readback()
+            steps = r.ctx.guide_get_weights()[1] if guided else 0
+            return s / c[:, None], n, dt, steps
+
+        r.render(0, 4)  # warm-up (module load, first launches)
+        torch.cuda.synchronize()
+        r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
+        r.reset()
         t0 = time.perf_counter()
-        S = oracle.Scene(sc)
-        build_s = time.perf_counter() - t0
-        ys, xs = np.meshgrid(np.arange(height // 32, height, height // 16), np.arange(width // 64, width, width // 32),
-                             indexing="ij")
-        pix = (ys * width + xs).reshape(-1).astype(np.uint32)
-        threads = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1, 16)
-        acc = np.zeros((pix.shape[0], 3))
-        n_o = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < oracle_seconds:
-            s_o, _, cnt, _ = S.render(pixels=pix, pass0=(1 << 25) + n_o, npasses=16, nthreads=threads)
-            acc += s_o
-            n_o += 16
-        o_ref = acc / n_o
-        out["oracle_reference"] = {"pixels": int(pix.shape[0]), "passes": n_o, "first_pass": 1 << 25,
-                                   "threads": threads, "seconds": round(time.perf_counter() - t0, 1),
-                                   "bvh_build_s": round(build_s, 1)}
-        out["plain"]["rmse_vs_oracle_sample"] = rmse(plain[pix], o_ref)
-        out["guided"]["rmse_vs_oracle_sample"] = rmse(guided[pix], o_ref)
-        out["gpu_reference_rmse_vs_oracle_sample"] = rmse(ref[pix], o_ref)
-    out["guided_over_plain_rmse"] = round(out["guided"]["rmse_vs_gpu_reference"] /
-                                          out["plain"]["rmse_vs_gpu_reference"], 4)
+        r.render(1 << 24, ref_passes)
+        s, c = r.readback()
+        ref = s / c[:, None]
+        t_ref = time.perf_counter() - t0
+        view = {"camera": vname, "gpu_reference": {"passes": ref_passes, "first_pass": 1 << 24,
+                                                   "seconds": round(t_ref, 2)}, "budgets": []}
+        img = {}
+        for label, kw in (("plain tracer's time for 64 passes", {"passes": 64}), (f"{seconds:g} s", {"budget": seconds})):
+            plain, n_p, t_p, _ = run(**kw)
+            guided, n_g, t_g, steps = run(budget=t_p, guided=True)
+            img[label] = (plain, guided)
+            view["budgets"].append({
+                "budget": label, "seconds": round(t_p, 3),
+                "plain": {"passes": n_p, "rmse_vs_gpu_reference": rmse(plain, ref)},
+                "guided": {"passes": n_g, "seconds": round(t_g, 3), "adam_steps": int(steps),
+                           "rmse_vs_gpu_reference": rmse(guided, ref),
+                           "final_loss": round(r.ctx.guide_loss()[0], 4)},
+                "guided_over_plain_rmse": round(rmse(guided, ref) / rmse(plain, ref), 4)})
+            _say(f"bench: equal time [{vname}, {label}] plain {n_p} passes, guided {n_g} passes, "
+                 f"ratio {view['budgets'][-1]['guided_over_plain_rmse']}")
+        del r
+        torch.cuda.empty_cache()
+        if vi == 0 and oracle_seconds > 0:
+            t0 = time.perf_counter()
+            S = oracle.Scene(sc)
+            build_s = time.perf_counter() - t0
+            ys, xs = np.meshgrid(np.arange(height // 32, height, height // 16),
+                                 np.arange(width // 64, width, width // 32), indexing="ij")
+            pix = (ys * width + xs).reshape(-1).astype(np.uint32)
+            threads = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1, 16)
+            acc = np.zeros((pix.shape[0], 3))
+            n_o = 0
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < oracle_seconds:
+                s_o, _, cnt, _ = S.render(pixels=pix, pass0=(1 << 25) + n_o, npasses=16, nthreads=threads)
+                acc += s_o
+                n_o += 16
+            o_ref = acc / n_o
+            del S
+            view["oracle_reference"] = {"pixels": int(pix.shape[0]), "passes": n_o, "first_pass": 1 << 25,
+                                        "threads": threads, "seconds": round(time.perf_counter() - t0, 1),
+                                        "bvh_build_s": round(build_s, 1),
+                                        "gpu_reference_rmse": rmse(ref[pix], o_ref)}
+            for bud in view["budgets"]:
+                plain, guided = img[bud["budget"]]
+                bud["plain"]["rmse_vs_oracle_sample"] = rmse(plain[pix], o_ref)
+                bud["guided"]["rmse_vs_oracle_sample"] = rmse(guided[pix], o_ref)
+        out["views"].append(view)
     return out
 
 
@@ -199,6 +243,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="grid",
+                    help="grid: the 0.97M-triangle 1080p scene (default); city: the 16M-triangle 4K city")
     ap.add_argument("--no-equal-time", action="store_true", help="skip the guided vs plain equal-time RMSE leg")
     ap.add_argument("--et-seconds", type=float, default=4.0, help="wall time of each equal-time run")
     ap.add_argument("--et-ref-passes", type=int, default=2048)
@@ -229,7 +275,7 @@ def main():
         torch.cuda.synchronize()
         _say(f"bench: copied {n} bytes for counter calibration")
         del src, dst
-    sc = scenegen.make_config(1)
+    sc = scenegen.make_config(WORKLOADS[args.workload][0])
     D = sc.max_depth
     _say(f"bench: scene {sc.name} tris={sc.num_triangles} {sc.width}x{sc.height} D={D}")
     r = Renderer(sc, device=0)
@@ -282,9 +328,16 @@ def main():
         n_l, ms = prof[dom]
         per_launch = byts[dom] / n_l
         achieved = per_launch / (ms / n_l * 1e-3) / 1e9
+        traffic = pmc_traffic(f"k_{dom}", "grid_1m") if args.workload == "grid" else None
+        stream = {"trace": ext * TRACE_RAY_BYTES, "shadow": sh * SHADOW_RAY_BYTES, "shade": byts["shade"]}[dom]
+        launch_s = ms / n_l * 1e-3
         roof = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": pmc_traffic(f"k_{dom}", "grid_1m"),
+                "traffic": traffic,
+                # compulsory streaming bytes only (no node or triangle fetches), and the
+                # HBM bytes the counters measured, over the same launch time
+                "frac_stream": round(stream / n_l / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                "frac_measured": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "bytes_per_launch": round(per_launch), "avg_launch_ms": round(ms / n_l, 4),
                 "nodes_per_ray": round(dn / max(ext, 1), 2), "tris_per_ray": round(dt_ / max(ext, 1), 2),
                 "shadow_nodes_per_ray": round(sn / max(sh, 1), 2),
@@ -309,8 +362,7 @@ def main():
         "metric": METRIC, "value": round(mrays, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, "
-                               "1920x1080, 1 spp per step, max depth 12, NEE+MIS, roulette",
+        "config": {"workload": WORKLOADS[args.workload][1],
                    "triangles": sc.num_triangles, "pixels": sc.width * sc.height, "max_depth": D,
                    "parallelism": "single GPU"},
         "mpaths_per_s": round(mpaths, 3),

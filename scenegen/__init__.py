@@ -445,7 +445,8 @@ def city(seed: int = 5, width=3840, height=2160, spp=1024, max_depth=16,
     b.quad((-L, 0, -L), (-L, 0, L), (L, 0, L), (L, 0, -L), ground)
     pos_chunks, idx_chunks, mat_chunks = [], [], []
     nv = 4
-    emit_budget = []
+    facades = []   # (first triangle after the ground plane, cells) per facade
+    ntri = 0
     for k in range(nb):
         gx, gz = k % blocks, k // blocks
         cx = (gx - blocks / 2 + 0.5) * spacing
@@ -467,6 +468,8 @@ def city(seed: int = 5, width=3840, height=2160, spp=1024, max_depth=16,
             # outward normal: edge (x1-x0) x up points outward for a counter-clockwise footprint seen from below
             t = np.concatenate([np.stack([q0, q3, q2], -1).reshape(-1, 3),
                                 np.stack([q0, q2, q1], -1).reshape(-1, 3)])
+            facades.append((ntri, nseg * ny))   # first triangle, cells (triangle j and j + cells)
+            ntri += t.shape[0]
             pos_chunks.append(P)
             idx_chunks.append(t + nv)
             mat_chunks.append(np.full(t.shape[0], mat, np.int64))
@@ -477,20 +480,28 @@ def city(seed: int = 5, width=3840, height=2160, spp=1024, max_depth=16,
         idx_chunks.append(np.array([[0, 2, 1], [0, 3, 2]]) + nv)
         mat_chunks.append(np.full(2, mat, np.int64))
         nv += 4
+        ntri += 2
     pos = np.concatenate([np.concatenate(b.pos)] + pos_chunks)
     idx = np.concatenate([np.concatenate(b.idx)] + idx_chunks)
     mat = np.concatenate([np.concatenate(b.mat)] + mat_chunks)
-    # pick emissive window cells (pairs of facade triangles) and give each its own material
-    nfac = idx.shape[0] - 2
-    pick = np.unique((rng.uniform(emissive_cells * 2, 0, nfac // 2).astype(np.int64)))[:emissive_cells]
+    # emissive window cells: both triangles of a picked facade cell get that
+    # cell's own material (lognormal intensity, warm tint)
+    starts = np.array([f[0] for f in facades], np.int64)
+    cells = np.array([f[1] for f in facades], np.int64)
+    first_cell = np.concatenate([[0], np.cumsum(cells)[:-1]])
+    total = int(cells.sum())
+    pick = np.unique(rng.uniform(emissive_cells * 2, 0, total).astype(np.int64))[:emissive_cells]
+    face = np.searchsorted(first_cell, pick, side="right") - 1
+    local = pick - first_cell[face]
+    tri_a = 2 + starts[face] + local                 # the ground plane's 2 triangles come first
+    tri_b = tri_a + cells[face]
     tint = np.array([1.0, 0.8, 0.55])
     E = np.exp(math.log(5.0) + 1.2 * rng.normal(pick.shape[0]))
     base_m = len(b.albedo)
     for j in range(pick.shape[0]):
         b.material((0.0, 0.0, 0.0), emission=E[j] * tint)
-    # the two triangles of a cell are not adjacent in the flat arrays; emit single triangles instead
-    tri_ids = 2 + pick * 2
-    mat[tri_ids] = base_m + np.arange(pick.shape[0])
+    mat[tri_a] = base_m + np.arange(pick.shape[0])
+    mat[tri_b] = base_m + np.arange(pick.shape[0])
     b.pos, b.idx, b.mat, b.nv = [pos], [idx], [mat], pos.shape[0]
     cam = Camera((0.0, 260.0, -900.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 50.0)
     return b.scene("city_16m", cam, width, height, spp, max_depth)

@@ -190,6 +190,23 @@ def test_image_parity_env_subset(Renderer, orc):
     assert mean_e <= 1e-4 and frac <= 1e-3
 
 
+def test_image_parity_city_subset(Renderer, orc):
+    """The city generator at 1/16 of its blocks (about 1M triangles, 5,000 emissive window cells
+    as triangle pairs, alias-table light selection) at the full 3840 x 2160: a pass exceeds the
+    path pool, so every pass is rendered in pixel chunks. Every 16th pixel, 2 passes."""
+    sc = g.city(blocks=16, target_tris=1_000_000, emissive_cells=5000)
+    _say(f"[image] city 3840x2160 tris={sc.num_triangles} passes=2 D=16")
+    s, c, _ = _render(Renderer, sc, 2)
+    W, H = sc.width, sc.height
+    ys, xs = np.meshgrid(np.arange(0, H, 16), np.arange(0, W, 16), indexing="ij")
+    pix = (ys * W + xs).reshape(-1).astype(np.uint32)
+    so, _, co, _ = orc.Scene(sc).render(pixels=pix, npasses=2)
+    mean_e, frac, e = orc.image_parity(s[pix], so)
+    _say(f"    mean rel err {mean_e:.3e}, pixels > 1e-3: {frac:.4%}, max {e.max():.3e}")
+    assert np.all(c == 2)
+    assert mean_e <= 1e-4 and frac <= 1e-3
+
+
 def test_constant_sky_every_path(Renderer):
     """Convex Lambert box under a constant sky: BSDF-sampled paths that hit it carry rho E exactly."""
     rho, E = 0.6, 2.0
