@@ -88,6 +88,7 @@ __device__ __forceinline__ float weight(const Mix &m, int k)
     int j = k & 3;
     return j == 0 ? w.x : (j == 1 ? w.y : (j == 2 ? w.z : w.w));
 }
+__device__ __forceinline__ float4 lobe(const Mix &m, int k) { return m.lobe[k]; }
 
 __device__ __forceinline__ float softplus(float r) { return r > 20.0f ? r : log1pf(expf(r)); }
 
@@ -116,6 +117,33 @@ __device__ __forceinline__ float4 unit_lobe(float2 a, float2 b)
 {
     float in = rsqrtf(fmaxf(a.x * a.x + a.y * a.y + b.x * b.x, 1e-24f));
     return make_float4(a.x * in, a.y * in, b.x * in, b.y);
+}
+
+// a stored mixture read in place, lobe by lobe (keeps the shading kernel's
+// registers free); decodes exactly as unpack_mix does
+struct MixRef {
+    const uint4 *p;
+    float winv;  // 1 / sum of the stored weights
+};
+
+__device__ __forceinline__ MixRef mix_ref(const uint4 *p)
+{
+    uint4 w = p[4];
+    float2 w01 = unpack_h2(w.x), w23 = unpack_h2(w.y), w45 = unpack_h2(w.z), w67 = unpack_h2(w.w);
+    return {p, 1.0f / (((w01.x + w01.y) + (w23.x + w23.y)) + ((w45.x + w45.y) + (w67.x + w67.y)))};
+}
+
+__device__ __forceinline__ float weight(const MixRef &m, int k)
+{
+    const uint32_t *w = (const uint32_t *)(m.p + 4);
+    float2 h = unpack_h2(w[k >> 1]);
+    return (k & 1 ? h.y : h.x) * m.winv;
+}
+
+__device__ __forceinline__ float4 lobe(const MixRef &m, int k)
+{
+    uint2 u = ((const uint2 *)m.p)[k];
+    return unit_lobe(unpack_h2(u.x), unpack_h2(u.y));
 }
 
 __device__ inline void unpack_mix(const uint4 *src, Mix &m)
@@ -161,16 +189,18 @@ __device__ __forceinline__ float vmf_pdf(float4 l, V3 w)
     return l.w / (2.0f * kPiF * -expm1f(-2.0f * l.w)) * expf(l.w * (c - 1.0f));
 }
 
-__device__ __forceinline__ float mixture_pdf(const Mix &m, V3 w)
+template <class M>
+__device__ __forceinline__ float mixture_pdf(const M &m, V3 w)
 {
     float q = 0.0f;
-    for (int k = 0; k < kLobes; ++k) q += weight(m, k) * vmf_pdf(m.lobe[k], w);
+    for (int k = 0; k < kLobes; ++k) q += weight(m, k) * vmf_pdf(lobe(m, k), w);
     return q;
 }
 
 // lobe: first k with u < cumulative weight; direction by stable vMF sampling
 // (Jakob 2012) in a Duff et al. 2017 frame around mu
-__device__ inline V3 mixture_sample(const Mix &m, float u_lobe, float u1, float u2)
+template <class M>
+__device__ inline V3 mixture_sample(const M &m, float u_lobe, float u1, float u2)
 {
     int k = kLobes - 1;
     float c = 0.0f;
@@ -181,7 +211,7 @@ __device__ inline V3 mixture_sample(const Mix &m, float u_lobe, float u1, float 
             break;
         }
     }
-    float4 l = m.lobe[k];
+    float4 l = lobe(m, k);
     float w = 1.0f + logf(u1 + (1.0f - u1) * expf(-2.0f * l.w)) / l.w;
     w = fminf(1.0f, fmaxf(-1.0f, w));
     float s = copysignf(1.0f, l.z);

@@ -549,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
 
 // closest hit for the extension rays queued at depth v; the grid is sized to
 // what is resident on the chip and strides over the queue
-__global__ __launch_bounds__(kBlock) void k_trace(Frame F, Pool P, uint32_t v)
+__global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v)
 {
     __shared__ int stk[kShortStack * kBlock];
     const uint32_t n = P.counters[v];
@@ -668,10 +668,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                     uint64_t idx = P.idx[slot];
                     // learned proposal: this vertex's mixture (alpha = 0 leaves plain BSDF sampling)
                     const bool guided = F.guide.alpha_thr != 0u && v <= F.guide.max_vertex;
-                    guide::Mix mix;
-                    if (guided) {
-                        guide::unpack_mix(F.guide.mix + (size_t)slot * guide::kMixU4, mix);
-                    }
+                    guide::MixRef mix{nullptr, 0.0f};
+                    if (guided) mix = guide::mix_ref(F.guide.mix + (size_t)slot * guide::kMixU4);
                     const float alpha = F.guide.alpha;
                     // next-event estimation
                     if (F.mode != 1 && (F.num_emit || F.env_w)) {
