@@ -32,9 +32,9 @@ METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "grid": (1, "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
-                "1 spp per step, max depth 12, NEE+MIS, roulette"),
+                "1 spp per step (passes batched four frames per launch sequence), max depth 12, NEE+MIS, roulette"),
     "city": (4, "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
-                "selection), 3840x2160 in pixel chunks of the path pool, 1 spp per step, max depth 16, NEE+MIS, "
+                "selection), 3840x2160, 1 spp per step (two frames per launch sequence), max depth 16, NEE+MIS, "
                 "roulette"),
 }
 GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 8, 2
@@ -281,8 +281,9 @@ def main():
     r = Renderer(sc, device=0)
     bs = r.bvh_stats
     _say(f"bench: bvh nodes={bs.num_nodes} leaves={bs.num_leaves} depth={bs.max_depth} build={bs.build_ms:.0f} ms")
-    for j in range(args.warmup):
-        r.render(j, 1)
+    # the passes go to the library as one range, which renders them in batches
+    # of as many whole passes as its path pool holds (four frames' worth)
+    r.render(0, args.warmup)
     torch.cuda.synchronize()
     _say(f"bench: warmup {args.warmup} passes done")
     st0 = r.stats()
@@ -292,8 +293,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    for j in range(args.steps):
-        r.render(args.warmup + j, 1)
+    r.render(args.warmup, args.steps)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

@@ -154,7 +154,11 @@ int qpt_build_scene(qpt_ctx *ctx, const qpt_scene_desc *desc);
 int qpt_build_bvh(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
 
 /* Bytes of device workspace needed for `pool_paths` concurrent paths
- * (0 = 2^21). Scene, BVH, path state, queues and framebuffer all live in it. */
+ * (0 = four frames' worth: the smallest power of two >= 4 W H, within
+ * [2^16, 2^24]). Passes are rendered in batches of as many whole passes as the
+ * pool holds (or in pixel chunks of one pass when a frame exceeds it); larger
+ * batches keep the queues of deep vertices full. Scene, BVH, path state,
+ * queues and framebuffer all live in it. */
 int qpt_workspace_size(const qpt_ctx *ctx, uint32_t pool_paths, size_t *bytes);
 
 /* Bind caller-owned device memory (256-byte aligned, `bytes` from
@@ -193,8 +197,9 @@ typedef struct {
     float alpha;             /* probability of sampling the guide once active, [0, 1); 0 disables */
     float lr;                /* Adam learning rate (> 0) */
     uint32_t batch;          /* training samples per step (0 = 2^18, at most 2^22) */
-    uint32_t train;          /* Adam steps after each batch of passes, each on its own stratified subset of
-                                that batch's records (0: no recording or training; at most 64) */
+    uint32_t train;          /* Adam steps per pass, taken after each batch of passes, each on its own
+                                stratified subset of the replay samples (0: no recording or training;
+                                at most 64) */
     uint32_t warmup_steps;   /* guide sampling stays off until this many steps were taken */
     uint32_t seed;           /* offsets of the stratified batch subsets */
     uint32_t max_vertex;     /* guide (and record) at path vertices 1..max_vertex only; 0 = every vertex */

@@ -613,6 +613,16 @@ void set_frame_constants(qpt_ctx *c)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// paths in flight when the caller leaves it to the library: four frames'
+// worth (a power of two in [2^16, 2^24]); batches of several one-sample
+// passes keep the short queues of deep vertices full
+uint32_t default_pool(const qpt_ctx *c)
+{
+    uint64_t want = 4ull * c->W * c->H, cap = 1u << 16;
+    while (cap < want && cap < (1u << 24)) cap <<= 1;
+    return (uint32_t)cap;
+}
+
 // training records per batch (vertices 1..max_vertex of each path, or a
 // hashed subset of the vertices when that would overflow)
 size_t guide_rec_cap(uint32_t cap) { return std::min<size_t>((size_t)1 << 22, (size_t)cap * 2); }
@@ -971,7 +981,7 @@ int qpt_workspace_size(const qpt_ctx *c, uint32_t pool_paths, size_t *bytes)
 {
     if (!c || !bytes) return QPT_E_INVALID;
     if (!c->scene_ok || !c->bvh_ok) return QPT_E_STATE;
-    uint32_t cap = pool_paths ? pool_paths : (1u << 21);
+    uint32_t cap = pool_paths ? pool_paths : default_pool(c);
     *bytes = make_layout(c, cap).total;
     return QPT_OK;
 }
@@ -982,7 +992,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
     if (!c->scene_ok || !c->bvh_ok) return fail(c, QPT_E_STATE, "bind_workspace before build_scene/build_bvh");
     if (!device_ptr || ((uintptr_t)device_ptr & 255)) return fail(c, QPT_E_INVALID, "workspace must be 256-byte aligned");
-    uint32_t cap = pool_paths ? pool_paths : (1u << 21);
+    uint32_t cap = pool_paths ? pool_paths : default_pool(c);
     if (cap < 64 || cap > (1u << 28)) return fail(c, QPT_E_INVALID, "pool_paths out of range");
     Layout L = make_layout(c, cap);
     if (bytes < L.total) return fail(c, QPT_E_NOMEM, "workspace %zu bytes, need %zu", bytes, L.total);
@@ -1137,6 +1147,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.scramble = o->scramble;
     Profiler *prof = c->profiling ? &c->prof : nullptr;
     // one batch of passes (or of pixels), then one training step if enabled
+    const uint32_t npix = c->W * c->H, cap = c->pool_cap;
     auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
         bool active = c->gopts.alpha > 0.0f && c->guide_steps >= c->gopts.warmup_steps;
         uint64_t thr = active ? (uint64_t)std::llround((double)c->gopts.alpha * 4294967296.0) : 0;
@@ -1169,26 +1180,32 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
         if (train) {
             GuideTrain T = c->gt;
-            if (c->train_pending[1 - k]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[1 - k], 0));
+            // the ring's readers (launched steps) finish before it is appended to
+            for (int kk = 0; kk < 2; ++kk)
+                if (c->train_pending[kk]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[kk], 0));
             if (prof) prof->begin(K_GUIDE_TRAIN, c->stream);
             HIP_TRY(c, launch_guide_finalize(f, c->pool, T, c->stream));
             if (prof) prof->end(K_GUIDE_TRAIN, c->stream);
-            HIP_TRY(c, hipEventRecord(c->ev_rec[k], c->stream));
-            HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[k], 0));
-            if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
-            HIP_TRY(c, launch_guide_train_steps(f, T, c->gopts.batch ? c->gopts.batch : (1u << 18),
-                                                c->guide_steps + 1, c->gopts.train, c->gopts.lr, c->gopts.seed,
-                                                c->tstream, c->pub_frag[k], c->pub_bias[k]));
-            if (prof) prof->end(K_GUIDE_TRAIN, c->tstream);
-            HIP_TRY(c, hipEventRecord(c->ev_train[k], c->tstream));
-            c->train_pending[k] = true;
-            c->last_buf = k;
-            c->guide_steps += c->gopts.train;
-            ++c->gbatch;
+            // `train` Adam steps per pass, taken when a batch completes its passes
+            // (a pass split into pixel chunks trains after its last chunk)
+            const uint32_t nsteps = (p0 + np >= npix) ? c->gopts.train * nb : 0u;
+            if (nsteps) {
+                HIP_TRY(c, hipEventRecord(c->ev_rec[k], c->stream));
+                HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[k], 0));
+                if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
+                HIP_TRY(c, launch_guide_train_steps(f, T, c->gopts.batch ? c->gopts.batch : (1u << 18),
+                                                    c->guide_steps + 1, nsteps, c->gopts.lr, c->gopts.seed,
+                                                    c->tstream, c->pub_frag[k], c->pub_bias[k]));
+                if (prof) prof->end(K_GUIDE_TRAIN, c->tstream);
+                HIP_TRY(c, hipEventRecord(c->ev_train[k], c->tstream));
+                c->train_pending[k] = true;
+                c->last_buf = k;
+                c->guide_steps += nsteps;
+                ++c->gbatch;
+            }
         }
         return QPT_OK;
     };
-    uint32_t npix = c->W * c->H, cap = c->pool_cap;
     if (npix <= cap) {
         uint32_t per = std::max(1u, cap / npix);
         for (uint32_t done = 0; done < num_passes;) {

@@ -290,7 +290,7 @@ def test_image_parity_city_subset(Renderer, orc):
     path pool, so every pass is rendered in pixel chunks. Every 16th pixel, 2 passes."""
     sc = g.city(blocks=16, target_tris=1_000_000, emissive_cells=5000)
     _say(f"[image] city 3840x2160 tris={sc.num_triangles} passes=2 D=16")
-    s, c, _ = _render(Renderer, sc, 2)
+    s, c, _ = _render(Renderer, sc, 2, pool_paths=1 << 21)
     W, H = sc.width, sc.height
     ys, xs = np.meshgrid(np.arange(0, H, 16), np.arange(0, W, 16), indexing="ij")
     pix = (ys * W + xs).reshape(-1).astype(np.uint32)
