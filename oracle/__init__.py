@@ -77,6 +77,14 @@ def lib():
         L.or_bsdf_sample_batch.argtypes = [P, u32, P, P, P, u32, P, P]
         L.or_debug_path.argtypes = [P, u32, u32, u32, u32, u32, u32, u64, P, P, u32]
         L.or_debug_path.restype = u32
+        L.or_light_tree.argtypes = [P, P, P, P, P, P, P, P]
+        L.or_light_tree.restype = u32
+        L.or_light_tree_sample.argtypes = [P, P, P, P, u32, P, P]
+        L.or_light_tree_sizes.argtypes = [P, P, P, P]
+        L.or_light_tree_estimate.argtypes = [P, u32, P, P]
+        L.or_light_tree_estimate.restype = C.c_float
+        L.or_light_tree_left_q.argtypes = [P, u32, P, P]
+        L.or_light_tree_left_q.restype = u32
         L.or_ggx_D.argtypes = [C.c_double, C.c_double]
         L.or_ggx_D.restype = C.c_double
         _lib = L
@@ -200,6 +208,46 @@ class Scene:
         L.or_scene_lights(self.h, _p(tri), _p(flux), _p(prob), _p(alias), _p(pmf))
         return dict(tri=tri, flux=flux, prob=prob, alias=alias, pmf=pmf)
 
+    def light_tree(self):
+        """The light tree's tables (Sec. 2.1.1 hierarchy, see the C source)."""
+        L = lib()
+        nn = L.or_light_tree(self.h, None, None, None, None, None, None, None)
+        ne = L.or_scene_num_emitters(self.h)
+        t = dict(center=np.empty((nn, 4), np.float32), flux=np.empty((nn, 6), np.float32),
+                 left=np.empty(nn, np.int32), first=np.empty(nn, np.uint32), count=np.empty(nn, np.uint32),
+                 emit=np.empty(ne, np.uint32), w=np.empty(ne, np.uint32))
+        if nn:
+            L.or_light_tree(self.h, _p(t["center"]), _p(t["flux"]), _p(t["left"]), _p(t["first"]),
+                            _p(t["count"]), _p(t["emit"]), _p(t["w"]))
+        return t
+
+    def light_tree_sample(self, S, x, n):
+        S = np.ascontiguousarray(S, np.uint64)
+        x = np.ascontiguousarray(x, np.float32).reshape(-1, 3)
+        n = np.ascontiguousarray(n, np.float32).reshape(-1, 3)
+        e = np.empty(S.shape[0], np.uint32)
+        size = np.empty(S.shape[0], np.uint64)
+        lib().or_light_tree_sample(self.h, _p(S), _p(x), _p(n), S.shape[0], _p(e), _p(size))
+        return e, size
+
+    def light_tree_sizes(self, x, n):
+        """Interval size (selection probability times 2^63) of every emitter."""
+        x = np.ascontiguousarray(x, np.float32)
+        n = np.ascontiguousarray(n, np.float32)
+        out = np.empty(lib().or_scene_num_emitters(self.h), np.uint64)
+        lib().or_light_tree_sizes(self.h, _p(x), _p(n), _p(out))
+        return out
+
+    def light_tree_estimate(self, node, x, n):
+        x = np.ascontiguousarray(x, np.float32)
+        n = np.ascontiguousarray(n, np.float32)
+        return float(lib().or_light_tree_estimate(self.h, node, _p(x), _p(n)))
+
+    def light_tree_left_q(self, node, x, n):
+        x = np.ascontiguousarray(x, np.float32)
+        n = np.ascontiguousarray(n, np.float32)
+        return int(lib().or_light_tree_left_q(self.h, node, _p(x), _p(n)))
+
     def env_tables(self):
         env = self.sc.env
         eh, ew = env.shape[:2]
@@ -218,8 +266,11 @@ class Scene:
         return t, tri
 
     def render(self, pixels=None, pass0=0, npasses=1, max_depth=None, rr=True, mode=0,
-               scramble=True, nthreads=None):
-        """FP64 sums, sums of squares and counts for the listed pixel ids (y*W+x)."""
+               scramble=True, nthreads=None, light_tree=False):
+        """FP64 sums, sums of squares and counts for the listed pixel ids (y*W+x).
+        light_tree selects triangle lights through the light tree instead of
+        the flux alias table."""
+        mode = int(mode) | (0x100 if light_tree else 0)
         sc = self.sc
         if max_depth is None:
             max_depth = sc.max_depth
@@ -272,7 +323,8 @@ class Scene:
         lib().or_bsdf_sample_batch(self.h, m, _p(n), _p(wo), _p(u), u.shape[0], _p(wi), _p(ok))
         return ok.astype(bool), wi
 
-    def debug_path(self, px, py, pass_, max_depth=None, rr=True, mode=0, scramble=True):
+    def debug_path(self, px, py, pass_, max_depth=None, rr=True, mode=0, scramble=True, light_tree=False):
+        mode = int(mode) | (0x100 if light_tree else 0)
         L = np.empty(3)
         log = np.zeros(8 * 256)
         n = lib().or_debug_path(self.h, max_depth or self.sc.max_depth, int(rr), mode, int(scramble), px, py,

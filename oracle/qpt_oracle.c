@@ -264,6 +264,16 @@ typedef struct {
     uint64_t *alias_thr;    /* take column c iff sample bits < thr[c] (2^32 scale) */
     double *emit_pmf;       /* realised selection probability of each emitter */
     int32_t *tri_emit;      /* triangle -> emitter index or -1 */
+    /* light tree (Sec. 2.1.1): nodes, leaf order of the emitters, cumulative
+     * 24-bit flux weights within each leaf */
+    uint32_t lt_nn;
+    float *lt_c;            /* 4 per node: centre xyz, radius */
+    float *lt_f;            /* 6 per node: flux per emission region */
+    int32_t *lt_left;       /* inner: first of the two children; leaf: -1 */
+    uint32_t *lt_first, *lt_count;
+    uint32_t *lt_emit;      /* leaf-order position -> emitter */
+    uint32_t *lt_pos;       /* emitter -> leaf-order position */
+    uint32_t *lt_w;         /* leaf-order position -> cumulative weight before it in its leaf */
     /* environment */
     uint32_t ew, eh;
     v3 *env;
@@ -391,6 +401,217 @@ static void build_light_pmf(or_scene *s)
         s->emit_pmf[c] += p_tri * pc * take;
         s->emit_pmf[s->alias_idx[c]] += p_tri * pc * (1.0 - take);
     }
+}
+
+/* ---------------------------------------------------------- light tree
+ *
+ * The paper's hierarchy for many triangle lights (Sec. 2.1.1), made definite:
+ * a binary tree over the emitters, split at the median of the longest axis
+ * of the centroids (ties by emitter index), leaves of at most 8 emitters.
+ * Each node keeps the bounding sphere of its triangles (centre and radius of
+ * the box) and, for each of six emission regions of the unit sphere (the
+ * dominant-axis cells +x, -x, +y, -y, +z, -z), the sum over its triangles of
+ * flux times an upper bound of the one-sided emission cosine within the
+ * region (the region lies in the cone of half-angle acos(1/sqrt 3) around its
+ * axis). Built in FP64, stored in FP32. */
+#define LT_LEAF 8
+
+static double lt_region_bound(v3 n, int region)
+{
+    int k = region / 2;
+    double sgn = (region & 1) ? -1.0 : 1.0;
+    double ca = fmax(-1.0, fmin(1.0, sgn * comp(n, k)));
+    double a = acos(ca), tc = acos(1.0 / sqrt(3.0));
+    return a <= tc ? 1.0 : fmax(0.0, cos(a - tc));
+}
+
+typedef struct {
+    or_scene *s;
+    uint32_t *items;  /* emitters, reordered into leaf order */
+    v3 *cen, *nrm;
+    uint32_t next;    /* nodes allocated */
+} lt_build;
+
+static int lt_axis_k;
+static const v3 *lt_cen_k;
+static int lt_cmp(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    double kx = comp(lt_cen_k[x], lt_axis_k), ky = comp(lt_cen_k[y], lt_axis_k);
+    if (kx != ky) return kx < ky ? -1 : 1;
+    return x < y ? -1 : (x > y);
+}
+
+static void lt_node(lt_build *b, uint32_t node, uint32_t first, uint32_t count)
+{
+    or_scene *s = b->s;
+    v3 lo = V3(INFINITY, INFINITY, INFINITY), hi = V3(-INFINITY, -INFINITY, -INFINITY);
+    v3 clo = lo, chi = hi;
+    double fl[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t q = first; q < first + count; ++q) {
+        uint32_t e = b->items[q], t = s->emit_tri[e];
+        v3 ps[3] = {s->p0[t], s->p1[t], s->p2[t]};
+        for (int j = 0; j < 3; ++j) {
+            lo = V3(fmin(lo.x, ps[j].x), fmin(lo.y, ps[j].y), fmin(lo.z, ps[j].z));
+            hi = V3(fmax(hi.x, ps[j].x), fmax(hi.y, ps[j].y), fmax(hi.z, ps[j].z));
+        }
+        v3 c = b->cen[e];
+        clo = V3(fmin(clo.x, c.x), fmin(clo.y, c.y), fmin(clo.z, c.z));
+        chi = V3(fmax(chi.x, c.x), fmax(chi.y, c.y), fmax(chi.z, c.z));
+        for (int r = 0; r < 6; ++r) fl[r] += s->emit_flux[e] * lt_region_bound(b->nrm[e], r);
+    }
+    v3 ctr = mul(add(lo, hi), 0.5);
+    double rad = 0.5 * len(sub(hi, lo));
+    s->lt_c[4 * node + 0] = (float)ctr.x;
+    s->lt_c[4 * node + 1] = (float)ctr.y;
+    s->lt_c[4 * node + 2] = (float)ctr.z;
+    s->lt_c[4 * node + 3] = (float)rad;
+    for (int r = 0; r < 6; ++r) s->lt_f[6 * node + r] = (float)fl[r];
+    s->lt_first[node] = first;
+    s->lt_count[node] = count;
+    if (count <= LT_LEAF) {
+        s->lt_left[node] = -1;
+        double tot = 0.0;
+        for (uint32_t q = first; q < first + count; ++q) tot += s->emit_flux[b->items[q]];
+        double acc = 0.0;
+        for (uint32_t q = first; q < first + count; ++q) {
+            double frac = tot > 0.0 ? acc / tot : (double)(q - first) / (double)count;
+            s->lt_w[q] = (uint32_t)nearbyint(frac * 16777216.0);
+            acc += s->emit_flux[b->items[q]];
+        }
+        return;
+    }
+    v3 ext = sub(chi, clo);
+    int axis = (ext.y > ext.x) ? 1 : 0;
+    if (ext.z > comp(ext, axis)) axis = 2;
+    lt_axis_k = axis;
+    lt_cen_k = b->cen;
+    qsort(b->items + first, count, sizeof(uint32_t), lt_cmp);
+    uint32_t half = count / 2;
+    uint32_t left = b->next;
+    b->next += 2;
+    s->lt_left[node] = (int32_t)left;
+    lt_node(b, left, first, half);
+    lt_node(b, left + 1, first + half, count - half);
+}
+
+static void build_light_tree(or_scene *s)
+{
+    if (!s->ne) return;
+    uint32_t cap = 2 * s->ne;
+    s->lt_c = (float *)malloc(sizeof(float) * 4 * cap);
+    s->lt_f = (float *)malloc(sizeof(float) * 6 * cap);
+    s->lt_left = (int32_t *)malloc(sizeof(int32_t) * cap);
+    s->lt_first = (uint32_t *)malloc(sizeof(uint32_t) * cap);
+    s->lt_count = (uint32_t *)malloc(sizeof(uint32_t) * cap);
+    s->lt_emit = (uint32_t *)malloc(sizeof(uint32_t) * s->ne);
+    s->lt_pos = (uint32_t *)malloc(sizeof(uint32_t) * s->ne);
+    s->lt_w = (uint32_t *)malloc(sizeof(uint32_t) * s->ne);
+    lt_build b = {s, s->lt_emit, (v3 *)malloc(sizeof(v3) * s->ne), (v3 *)malloc(sizeof(v3) * s->ne), 1};
+    for (uint32_t e = 0; e < s->ne; ++e) {
+        uint32_t t = s->emit_tri[e];
+        b.items[e] = e;
+        b.cen[e] = mul(add(add(s->p0[t], s->p1[t]), s->p2[t]), 1.0 / 3.0);
+        v3 n = cross(sub(s->p1[t], s->p0[t]), sub(s->p2[t], s->p0[t]));
+        double l = len(n);
+        b.nrm[e] = l > 0.0 ? mul(n, 1.0 / l) : V3(0, 0, 1);
+    }
+    lt_node(&b, 0, 0, s->ne);
+    s->lt_nn = b.next;
+    for (uint32_t q = 0; q < s->ne; ++q) s->lt_pos[s->lt_emit[q]] = q;
+    free(b.cen);
+    free(b.nrm);
+}
+
+/* Estimated contribution of a node at shading point x with normal n (both
+ * FP32, in FP32): emission-region flux towards x times a conservative bound
+ * of the cosine at x over the node's bounding sphere, over max(d^2, r^2). */
+static float lt_estimate(const or_scene *s, uint32_t node, const float *x, const float *n)
+{
+    const float *c = s->lt_c + 4 * node;
+    float dx = c[0] - x[0], dy = c[1] - x[1], dz = c[2] - x[2];
+    float d2 = (dx * dx + dy * dy) + dz * dz;
+    float r = c[3], r2 = r * r;
+    /* emission direction x - c: dominant axis, ties to the lower axis */
+    float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int k = 0;
+    float m = ax, ek = -dx;
+    if (ay > m) { k = 1; m = ay; ek = -dy; }
+    if (az > m) { k = 2; m = az; ek = -dz; }
+    float F = s->lt_f[6 * node + 2 * k + (ek < 0.0f ? 1 : 0)];
+    float cosx = 1.0f;
+    if (d2 > r2) {
+        float d = sqrtf(d2);
+        float sinb = r / d;
+        float cosb = sqrtf(1.0f - sinb * sinb);
+        float cosa = ((n[0] * dx + n[1] * dy) + n[2] * dz) / d;
+        if (cosa < cosb) {
+            float sina = sqrtf(fmaxf(0.0f, 1.0f - cosa * cosa));
+            cosx = fmaxf(0.0f, cosa * cosb + sina * sinb);
+        }
+    }
+    return F * cosx / fmaxf(d2, r2);
+}
+
+/* 24-bit probability of the left child, clamped to [1/16, 15/16] */
+static uint32_t lt_left_q(const or_scene *s, uint32_t node, const float *x, const float *n)
+{
+    int32_t l = s->lt_left[node];
+    float el = lt_estimate(s, (uint32_t)l, x, n), er = lt_estimate(s, (uint32_t)l + 1, x, n);
+    float sum = el + er;
+    float p = (sum > 0.0f && isfinite(sum)) ? el / sum : 0.5f;
+    p = fminf(fmaxf(p, 0.0625f), 0.9375f);
+    return (uint32_t)(p * 16777216.0f + 0.5f);
+}
+
+/* floor(R q / 2^24) exactly, R < 2^63, q <= 2^24 */
+static uint64_t lt_split(uint64_t R, uint32_t q)
+{
+    return (R >> 24) * q + (((R & 0xFFFFFFull) * q) >> 24);
+}
+
+/* Descend with the 63-bit sample S; returns the emitter and the size of its
+ * interval of [0, 2^63) (its realised selection probability times 2^63). */
+static uint32_t lt_sample(const or_scene *s, uint64_t S, const float *x, const float *n, uint64_t *size)
+{
+    uint64_t R = 1ull << 63;
+    uint32_t node = 0;
+    while (s->lt_left[node] >= 0) {
+        uint64_t T = lt_split(R, lt_left_q(s, node, x, n));
+        if (T < 1) T = 1;
+        if (T > R - 1) T = R - 1;
+        if (S < T) { R = T; node = (uint32_t)s->lt_left[node]; }
+        else { S -= T; R -= T; node = (uint32_t)s->lt_left[node] + 1; }
+    }
+    uint32_t f = s->lt_first[node], c = s->lt_count[node];
+    uint32_t j = c - 1;
+    for (uint32_t q = 1; q < c; ++q)
+        if (S < lt_split(R, s->lt_w[f + q])) { j = q - 1; break; }
+    uint64_t a = lt_split(R, s->lt_w[f + j]);
+    uint64_t z = j + 1 < c ? lt_split(R, s->lt_w[f + j + 1]) : R;
+    *size = z - a;
+    return s->lt_emit[f + j];
+}
+
+/* the same interval size for a given emitter, by the deterministic descent
+ * towards its leaf (for the MIS weight of an emitter hit) */
+static uint64_t lt_size_of(const or_scene *s, uint32_t e, const float *x, const float *n)
+{
+    uint32_t pos = s->lt_pos[e];
+    uint64_t R = 1ull << 63;
+    uint32_t node = 0;
+    while (s->lt_left[node] >= 0) {
+        uint32_t l = (uint32_t)s->lt_left[node];
+        uint64_t T = lt_split(R, lt_left_q(s, node, x, n));
+        if (T < 1) T = 1;
+        if (T > R - 1) T = R - 1;
+        if (pos < s->lt_first[l + 1]) { R = T; node = l; }
+        else { R -= T; node = l + 1; }
+    }
+    uint32_t f = s->lt_first[node], c = s->lt_count[node], j = pos - f;
+    uint64_t a = lt_split(R, s->lt_w[f + j]);
+    uint64_t z = j + 1 < c ? lt_split(R, s->lt_w[f + j + 1]) : R;
+    return z - a;
 }
 
 static void build_env(or_scene *s)
@@ -625,6 +846,7 @@ or_scene *or_scene_create(uint32_t nv, const float *pos, uint32_t nt, const uint
         s->flags[m] = flags[m];
     }
     build_lights(s);
+    build_light_tree(s);
     if (env && ew && eh) {
         s->ew = ew; s->eh = eh;
         s->env = (v3 *)malloc(sizeof(v3) * (size_t)ew * eh);
@@ -660,6 +882,8 @@ void or_scene_destroy(or_scene *s)
     free(s->albedo); free(s->emission); free(s->rough); free(s->flags);
     free(s->emit_tri); free(s->emit_flux); free(s->alias_prob); free(s->alias_idx);
     free(s->alias_thr); free(s->emit_pmf); free(s->tri_emit);
+    free(s->lt_c); free(s->lt_f); free(s->lt_left); free(s->lt_first); free(s->lt_count);
+    free(s->lt_emit); free(s->lt_pos); free(s->lt_w);
     free(s->env); free(s->row_q); free(s->col_q); free(s->env_texel_pdf);
     free(s->nodes); free(s->order);
     free(s);
@@ -845,7 +1069,15 @@ typedef struct {
     uint32_t rr;        /* Russian roulette from vertex 3 */
     uint32_t mode;      /* 0 MIS, 1 BSDF sampling only, 2 NEE only */
     uint32_t scramble;
+    uint32_t light_tree; /* select triangle lights through the light tree */
 } or_opts;
+
+/* the caller's mode word: MIS mode in the low byte, light tree in bit 8 */
+static or_opts make_opts(uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble)
+{
+    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u};
+    return op;
+}
 
 static inline double mis2(double a, double b) { return a * a / (a * a + b * b); }
 
@@ -873,6 +1105,9 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
     v3 o = s->eye;
     v3 L = V3(0, 0, 0), T = V3(1, 1, 1);
     double prev_pdf = 0.0;
+    v3 prev_n = V3(0, 0, 0);
+    const int tree = op->light_tree && s->ne;
+    const double p_tri = 1.0 - s->p_env;
     for (uint32_t v = 1; v <= op->max_depth; ++v) {
         hit64 h;
         (*nrays)++;
@@ -900,8 +1135,17 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
             v3 Le = emission_at(s, m, x);
             double w = 1.0;
             if (v > 1 && op->mode == 0) {
-                double pl = s->emit_pmf[s->tri_emit[t]] / (0.5 * area2) * h.t * h.t / (-dn);
+                double pe = s->emit_pmf[s->tri_emit[t]];
+                if (tree) {
+                    /* the tree's pdf seen from the previous vertex: its ray
+                     * origin and normal in FP32, as the sampling used them */
+                    float xf[3] = {(float)o.x, (float)o.y, (float)o.z};
+                    float nf[3] = {(float)prev_n.x, (float)prev_n.y, (float)prev_n.z};
+                    pe = p_tri * (double)lt_size_of(s, (uint32_t)s->tri_emit[t], xf, nf) * 0x1p-63;
+                }
+                double pl = pe / (0.5 * area2) * h.t * h.t / (-dn);
                 w = mis2(prev_pdf, pl);
+                logv(4, v, t, pe, pl, w, 0, 0);
             }
             L = add(L, mul(vmul(T, Le), w));
         }
@@ -946,9 +1190,23 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
                 pl = s->p_env * s->env_texel_pdf[q];
                 ok = pl > 0.0;
             } else {
-                uint32_t col = (uint32_t)(((u128)r * s->ne) / R);
                 uint32_t s7 = or_sample_bits(i, base + 7, W, H, op->scramble);
-                uint32_t e = (uint64_t)s7 < s->alias_thr[col] ? col : s->alias_idx[col];
+                uint32_t e;
+                double pe;
+                if (tree) {
+                    /* 63-bit sample: the 31 bits left of slot 0 (its top 31
+                     * bits without an environment), then slot 7 */
+                    uint64_t hi = s->env ? r : (uint64_t)(s0 >> 1);
+                    uint64_t S = (hi << 32) | s7, size;
+                    float xf[3] = {(float)xo.x, (float)xo.y, (float)xo.z};
+                    float nf[3] = {(float)n.x, (float)n.y, (float)n.z};
+                    e = lt_sample(s, S, xf, nf, &size);
+                    pe = p_tri * (double)size * 0x1p-63;
+                } else {
+                    uint32_t col = (uint32_t)(((u128)r * s->ne) / R);
+                    e = (uint64_t)s7 < s->alias_thr[col] ? col : s->alias_idx[col];
+                    pe = s->emit_pmf[e];
+                }
                 uint32_t lt = s->emit_tri[e];
                 double q1 = u24(or_sample_bits(i, base + 1, W, H, op->scramble));
                 double q2 = u24(or_sample_bits(i, base + 2, W, H, op->scramble));
@@ -966,8 +1224,8 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
                 double cl = -dot(nl, wi);
                 if (cl > 0.0) {
                     Le = emission_at(s, s->mat[lt], y);
-                    pl = s->emit_pmf[e] / (0.5 * la2) * d2 / cl;
-                    ok = 1;
+                    pl = pe / (0.5 * la2) * d2 / cl;
+                    ok = pl > 0.0;
                 }
             }
             if (ok) {
@@ -1002,6 +1260,7 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
         T = vmul(T, mul(f, dot(n, wi) / pb));
         if (!(maxc(T) > 0.0)) break;
         prev_pdf = pb;
+        prev_n = n;
         if (op->rr && v >= 3) {
             double q = fmin(0.95, maxc(T));
             float qf = (float)q;
@@ -1072,7 +1331,7 @@ uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t 
                    uint32_t npasses, double *sum, double *sumsq, uint32_t *count,
                    uint32_t nthreads)
 {
-    or_opts op = {max_depth, rr, mode, scramble};
+    or_opts op = make_opts(max_depth, rr, mode, scramble);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     pthread_t th[256];
@@ -1094,11 +1353,12 @@ uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t 
 }
 
 /* one path with a per-vertex log: records of 8 doubles,
- * (1, v, tri, t, x) (2, ray o, ray d) (3, occluded, contrib, pl, w) */
+ * (1, v, tri, t, x) (2, ray o, ray d) (3, occluded, contrib, pl, w)
+ * (4, v, tri, selection probability, pl, w) at an emitter hit under MIS */
 uint32_t or_debug_path(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble,
                        uint32_t px, uint32_t py, uint64_t pass, double *L_out, double *log, uint32_t cap)
 {
-    or_opts op = {max_depth, rr, mode, scramble};
+    or_opts op = make_opts(max_depth, rr, mode, scramble);
     g_log = log; g_log_n = 0; g_log_cap = cap;
     uint32_t nr = 0;
     uint64_t i = or_pixel_index(s->W, s->H, px, py, pass);
@@ -1109,6 +1369,49 @@ uint32_t or_debug_path(const or_scene *s, uint32_t max_depth, uint32_t rr, uint3
 }
 
 /* ---------------------------------------------- pieces exposed for pins */
+
+/* The light tree's tables: node count; with non-NULL arrays, per node the
+ * centre and radius (c4), region fluxes (f6), first child (-1 leaf), first
+ * and count of its emitters in leaf order; per leaf-order position the
+ * emitter and its cumulative 24-bit weight within its leaf. */
+uint32_t or_light_tree(const or_scene *s, float *c4, float *f6, int32_t *left, uint32_t *first,
+                       uint32_t *count, uint32_t *emit, uint32_t *w)
+{
+    if (!s->ne) return 0;
+    uint32_t nn = s->lt_nn;
+    if (c4) memcpy(c4, s->lt_c, sizeof(float) * 4 * nn);
+    if (f6) memcpy(f6, s->lt_f, sizeof(float) * 6 * nn);
+    if (left) memcpy(left, s->lt_left, sizeof(int32_t) * nn);
+    if (first) memcpy(first, s->lt_first, sizeof(uint32_t) * nn);
+    if (count) memcpy(count, s->lt_count, sizeof(uint32_t) * nn);
+    if (emit) memcpy(emit, s->lt_emit, sizeof(uint32_t) * s->ne);
+    if (w) memcpy(w, s->lt_w, sizeof(uint32_t) * s->ne);
+    return nn;
+}
+
+/* n queries at FP32 points x[3n] and normals nrm[3n] with 63-bit samples
+ * S[n]: chosen emitter and its interval size (probability times 2^63) */
+void or_light_tree_sample(const or_scene *s, const uint64_t *S, const float *x, const float *nrm, uint32_t n,
+                          uint32_t *e_out, uint64_t *size_out)
+{
+    for (uint32_t k = 0; k < n; ++k) e_out[k] = lt_sample(s, S[k], x + 3 * k, nrm + 3 * k, size_out + k);
+}
+
+/* interval size of every emitter (ne values) seen from one point */
+void or_light_tree_sizes(const or_scene *s, const float *x, const float *nrm, uint64_t *size_out)
+{
+    for (uint32_t e = 0; e < s->ne; ++e) size_out[e] = lt_size_of(s, e, x, nrm);
+}
+
+/* the node estimate and the left-child probability, for pins */
+float or_light_tree_estimate(const or_scene *s, uint32_t node, const float *x, const float *nrm)
+{
+    return lt_estimate(s, node, x, nrm);
+}
+uint32_t or_light_tree_left_q(const or_scene *s, uint32_t node, const float *x, const float *nrm)
+{
+    return s->lt_left[node] >= 0 ? lt_left_q(s, node, x, nrm) : 0;
+}
 
 void or_camera_ray(const or_scene *s, double fx, double fy, double *o, double *d)
 {

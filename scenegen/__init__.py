@@ -529,20 +529,64 @@ def convex_under_env(rho=0.6, E=2.0, width=8, height=8, max_depth=4) -> Scene:
     return b.scene("convex_env", cam, width, height, 1, max_depth, env=constant_env((E, E, E)))
 
 
-def quad_over_plane(rho=0.7, Le=4.0, width=1, height=1, max_depth=2) -> Scene:
-    """A one-sided square emitter above a Lambert plane; a narrow camera looks at one point."""
+def quad_over_plane(rho=0.7, Le=4.0, width=1, height=1, max_depth=2, subdiv=1) -> Scene:
+    """A one-sided square emitter above a Lambert plane; a narrow camera looks at one point.
+    subdiv > 1 splits the emitter into subdiv x subdiv cells (two triangles each)."""
     b = _Builder()
     m = b.material((rho, rho, rho))
     light = b.material((0, 0, 0), emission=(Le, Le, Le))
     L = 10.0
     b.quad((-L, 0, -L), (-L, 0, L), (L, 0, L), (L, 0, -L), m)
     y = 1.0
-    b.quad((-0.3, y, -0.2), (0.5, y, -0.2), (0.5, y, 0.4), (-0.3, y, 0.4), light)
+    xs = np.linspace(-0.3, 0.5, subdiv + 1)
+    zs = np.linspace(-0.2, 0.4, subdiv + 1)
+    for i in range(subdiv):
+        for j in range(subdiv):
+            b.quad((xs[i], y, zs[j]), (xs[i + 1], y, zs[j]), (xs[i + 1], y, zs[j + 1]), (xs[i], y, zs[j + 1]),
+                   light)
     cam = Camera((3.0, 2.0, 0.0), (0.2, 0.0, 0.1), (0.0, 1.0, 0.0), 0.002)
     s = b.scene("quad_over_plane", cam, width, height, 1, max_depth)
     s.extra["target"] = (0.2, 0.0, 0.1)
     s.extra["light_quad"] = [(-0.3, y, -0.2), (0.5, y, -0.2), (0.5, y, 0.4), (-0.3, y, 0.4)]
     return s
+
+
+def light_field(seed: int = 11, n_lights=2000, width=64, height=48, max_depth=6, env=False) -> Scene:
+    """Many small one-sided triangle lights of random orientation, size and
+    power (log-uniform over two decades) above a Lambert floor with a few
+    boxes: about half of them face away from the floor. The setting of a
+    light hierarchy: the flux-proportional choice wastes most shadow rays."""
+    rng = SplitMix64(seed)
+    b = _Builder()
+    floor = b.material((0.6, 0.6, 0.6))
+    grey = b.material((0.5, 0.45, 0.4))
+    L = 20.0
+    b.quad((-L, 0, -L), (-L, 0, L), (L, 0, L), (L, 0, -L), floor)
+    for k in range(6):
+        c = (rng.uniform(1, -12, 12)[0], 1.0, rng.uniform(1, -12, 12)[0])
+        v, t = box_mesh(c, (2.0, 2.0, 2.0), float(rng.uniform(1, 0, 90)[0]))
+        b.mesh(v, t, grey)
+    cen = np.stack([rng.uniform(n_lights, -15, 15), rng.uniform(n_lights, 0.5, 6.0),
+                    rng.uniform(n_lights, -15, 15)], 1)
+    nrm = np.stack([rng.normal(n_lights) for _ in range(3)], 1)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    size = rng.uniform(n_lights, 0.1, 0.4)
+    power = 10.0 ** rng.uniform(n_lights, -0.3, 1.7)
+    hue = rng.uniform(n_lights, 0.5, 1.0)
+    # two tangents per light; corners counter-clockwise seen from the front
+    a = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0, 0]]), np.array([[0, 1.0, 0]]))
+    t1 = np.cross(nrm, a)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(nrm, t1)
+    for k in range(n_lights):
+        m = b.material((0, 0, 0), emission=(power[k], power[k] * hue[k], power[k] * hue[k] * hue[k]))
+        p0 = cen[k] + size[k] * t1[k]
+        p1 = cen[k] + size[k] * (-0.5 * t1[k] + 0.866 * t2[k])
+        p2 = cen[k] + size[k] * (-0.5 * t1[k] - 0.866 * t2[k])
+        b.mesh(np.array([p0, p1, p2]), np.array([[0, 1, 2]]), m)
+    cam = Camera((0.0, 14.0, -26.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 50.0)
+    e = sky_env(64, 32) * 0.2 if env else None
+    return b.scene("light_field", cam, width, height, 1, max_depth, env=e)
 
 
 # ----------------------------------------------------------- guide inputs
