@@ -101,6 +101,9 @@ typedef struct {
     uint32_t rr;             /* 1: Russian roulette from vertex 3 */
     uint32_t mode;           /* 0: NEE + BSDF sampling with MIS, 1: BSDF sampling only, 2: NEE only */
     uint32_t scramble;       /* 1: linear digit scrambling of dimensions >= 2 */
+    uint32_t light_tree;     /* 0: triangle lights by flux (alias table), 1: through the light tree
+                                (the many-light hierarchy of Sec. 2.1.1; importance by distance,
+                                orientation and flux of its nodes) */
 } qpt_render_opts;
 
 typedef struct {
@@ -283,6 +286,30 @@ int qpt_debug_trace(qpt_ctx *ctx, const float *rays, uint32_t n, int any_hit, in
  * pointers may be NULL (query the count first). After qpt_build_scene. */
 int qpt_debug_light_tables(const qpt_ctx *ctx, uint32_t *emit_tri, double *prob, uint32_t *alias,
                            double *pmf, uint32_t *count);
+
+/* The light tree (Sec. 2.1.1 hierarchy), built with the scene: a binary tree
+ * over the emitters, split at the centroid median of the longest centroid
+ * extent (ties by emitter index), at most 8 emitters per leaf, children
+ * stored as adjacent pairs in depth-first order. Per node: sphere4[4 k..]
+ * centre xyz and radius of its bounding sphere; flux6[6 k..] its flux
+ * towards each emission region (+x, -x, +y, -y, +z, -z dominant-axis cells),
+ * each triangle's flux times the bound of its one-sided emission cosine over
+ * the region; left[k] first child (-1 for a leaf); first[k], count[k] its
+ * range in leaf order. Per leaf-order position q: emit[q] the emitter,
+ * weight[q] the 24-bit cumulative flux fraction before it within its leaf.
+ * *num_nodes receives the node count (0 without triangle lights); array
+ * pointers may be NULL. Host memory. After qpt_build_scene. */
+int qpt_debug_light_tree(const qpt_ctx *ctx, float *sphere4, float *flux6, int32_t *left, uint32_t *first,
+                         uint32_t *count, uint32_t *emit, uint32_t *weight, uint32_t *num_nodes);
+
+/* The renderer's light-tree choice for n queries (DEVICE pointers): 63-bit
+ * samples S[n] (bit 63 ignored), FP32 shading points x[3n] and unit normals
+ * nrm[3n]; writes the chosen emitter, its interval size (selection
+ * probability times 2^63) and the size that the descent steered to that
+ * emitter finds (what an emitter hit's MIS weight uses; equal to size).
+ * QPT_E_STATE before qpt_bind_workspace or without triangle lights. */
+int qpt_debug_light_sample(qpt_ctx *ctx, const uint64_t *S, const float *x, const float *nrm, uint32_t n,
+                           uint32_t *emitter, uint64_t *size, uint64_t *size_hit);
 
 /* Environment tables: row CDF row_q[env_height] (2^32 scale, row_q[0] = 0),
  * column CDFs col_q[env_height * env_width], texel solid-angle pdfs

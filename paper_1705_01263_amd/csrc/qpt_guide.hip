@@ -28,7 +28,6 @@ constexpr int kFB[4] = {0, 8, 24, 40};         // first forward fragment of each
 constexpr int kGB[4] = {0, 0, 16, 32};         // first transposed fragment (layers 1..3)
 constexpr int kOffW[4] = {0, 2112, 6272, 10432};
 constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
-constexpr int kIn[4] = {32, 64, 64, 64};          // layer input widths
 constexpr int kTrainBlock = 256;               // 4 waves
 
 // round to the nearest BF16, ties to even (v_cvt_pk_bf16_f32 on gfx950)

@@ -265,7 +265,8 @@ struct Builder {
 // ------------------------------------------------------------ the context
 
 struct Layout {
-    size_t nodes, tris, mats, emit_tri, alias_idx, alias_thr, emit_pmf, env_texel, env_row,
+    size_t nodes, tris, mats, emit_tri, alias_idx, alias_thr, emit_pmf, lt_nodes, lt_emit, lt_pos, lt_w,
+        env_texel, env_row,
         env_col, env_cos, bases;
     size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats, gstack;
     size_t fb_sum, fb_count;
@@ -358,6 +359,9 @@ struct qpt_ctx {
     std::vector<unsigned long long> alias_thr;
     std::vector<int32_t> tri_emit;
     double p_env = 0.0;
+    // light tree (node 0 = root) and its leaf order of the emitters
+    std::vector<LtNode> lt_nodes;
+    std::vector<uint32_t> lt_emit, lt_pos, lt_w;
     // environment tables
     std::vector<uint32_t> env_row, env_col;
     std::vector<float4> env_texel;
@@ -511,6 +515,114 @@ void build_lights(qpt_ctx *c)
         c->alias_thr[e] = (unsigned long long)std::ceil(c->alias_prob[e] * 4294967296.0);
 }
 
+// Light tree over the emitters (the hierarchy of Sec. 2.1.1). Each node takes
+// its emitter range in the order its parent's sort left it, accumulates its
+// corner box, centroid box and region fluxes over that range in FP64, then
+// sorts the range by centroid along the centroid box's longest axis (ties:
+// emitter index) and hands the lower half to the first of two adjacent
+// children. Nodes are numbered in depth-first order, left subtree first.
+// The importance estimate on the device bounds the emission cosine of a
+// region's triangles by the cone of half-angle acos(1/sqrt 3) that holds
+// the region.
+double region_cos_bound(Vec3 n, int region)
+{
+    double s = (region & 1) ? -1.0 : 1.0;
+    double c = s * (region < 2 ? n.x : region < 4 ? n.y : n.z);
+    double ang = std::acos(std::max(-1.0, std::min(1.0, c)));
+    double half = std::acos(1.0 / std::sqrt(3.0));
+    if (ang <= half) return 1.0;
+    return std::max(0.0, std::cos(ang - half));
+}
+
+void build_light_tree(qpt_ctx *c)
+{
+    const uint32_t ne = (uint32_t)c->emit_input_tri.size();
+    c->lt_nodes.clear();
+    c->lt_emit.clear();
+    c->lt_pos.clear();
+    c->lt_w.clear();
+    if (!ne) return;
+    std::vector<Vec3> cen(ne), nrm(ne);
+    for (uint32_t e = 0; e < ne; ++e) {
+        uint32_t t = c->emit_input_tri[e];
+        Vec3 a = corner(c, t, 0), b = corner(c, t, 1), d = corner(c, t, 2);
+        cen[e] = vscale(vadd(vadd(a, b), d), 1.0 / 3.0);
+        Vec3 n = vcross(vsub(b, a), vsub(d, a));
+        double l = vlen(n);
+        nrm[e] = l > 0.0 ? vscale(n, 1.0 / l) : Vec3{0.0, 0.0, 1.0};
+    }
+    std::vector<uint32_t> &ord = c->lt_emit;
+    ord.resize(ne);
+    for (uint32_t e = 0; e < ne; ++e) ord[e] = e;
+    c->lt_w.assign(ne, 0);
+    c->lt_nodes.assign(2 * (size_t)ne, LtNode{});
+    struct Work {
+        uint32_t node, first, count;
+    };
+    std::vector<Work> todo{{0, 0, ne}};
+    uint32_t next = 1;
+    while (!todo.empty()) {
+        Work wk = todo.back();
+        todo.pop_back();
+        const uint32_t first = wk.first, count = wk.count, end = first + count;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        double fl[6] = {0, 0, 0, 0, 0, 0};
+        for (uint32_t q = first; q < end; ++q) {
+            uint32_t e = ord[q], t = c->emit_input_tri[e];
+            for (int k = 0; k < 3; ++k) {
+                Vec3 p = corner(c, t, k);
+                const double pv[3] = {p.x, p.y, p.z};
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::fmin(lo[a], pv[a]);
+                    hi[a] = std::fmax(hi[a], pv[a]);
+                }
+            }
+            const double cv[3] = {cen[e].x, cen[e].y, cen[e].z};
+            for (int a = 0; a < 3; ++a) {
+                clo[a] = std::fmin(clo[a], cv[a]);
+                chi[a] = std::fmax(chi[a], cv[a]);
+            }
+            for (int r = 0; r < 6; ++r) fl[r] += c->emit_flux[e] * region_cos_bound(nrm[e], r);
+        }
+        LtNode &nd = c->lt_nodes[wk.node];
+        Vec3 mid = vscale(vadd(Vec3{lo[0], lo[1], lo[2]}, Vec3{hi[0], hi[1], hi[2]}), 0.5);
+        double radius = 0.5 * vlen(vsub(Vec3{hi[0], hi[1], hi[2]}, Vec3{lo[0], lo[1], lo[2]}));
+        nd.sphere = make_float4((float)mid.x, (float)mid.y, (float)mid.z, (float)radius);
+        for (int r = 0; r < 6; ++r) nd.flux[r] = (float)fl[r];
+        nd.first = first;
+        nd.count = count;
+        if (count <= kLtLeaf) {
+            // cumulative flux fractions in 24 bits (equal shares if the leaf has none)
+            nd.left = -1;
+            double total = 0.0, run = 0.0;
+            for (uint32_t q = first; q < end; ++q) total += c->emit_flux[ord[q]];
+            for (uint32_t q = first; q < end; ++q) {
+                double frac = total > 0.0 ? run / total : (double)(q - first) / (double)count;
+                c->lt_w[q] = (uint32_t)std::nearbyint(frac * 16777216.0);
+                run += c->emit_flux[ord[q]];
+            }
+            continue;
+        }
+        const double ext[3] = {chi[0] - clo[0], chi[1] - clo[1], chi[2] - clo[2]};
+        int axis = ext[1] > ext[0] ? 1 : 0;
+        if (ext[2] > ext[axis]) axis = 2;
+        auto key = [&](uint32_t e) { return axis == 0 ? cen[e].x : axis == 1 ? cen[e].y : cen[e].z; };
+        std::sort(ord.begin() + first, ord.begin() + end, [&](uint32_t x, uint32_t y) {
+            double kx = key(x), ky = key(y);
+            return kx != ky ? kx < ky : x < y;
+        });
+        const uint32_t half = count / 2, l = next;
+        next += 2;
+        nd.left = (int32_t)l;
+        todo.push_back({l + 1, first + half, count - half});
+        todo.push_back({l, first, half});
+    }
+    c->lt_nodes.resize(next);
+    c->lt_pos.assign(ne, 0);
+    for (uint32_t q = 0; q < ne; ++q) c->lt_pos[ord[q]] = q;
+}
+
 // probability the integer light-selection rule realises for each emitter
 void build_light_pmf(qpt_ctx *c)
 {
@@ -645,6 +757,10 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.alias_idx = take(ne * 4);
     L.alias_thr = take(ne * 8);
     L.emit_pmf = take(ne * 4);
+    L.lt_nodes = take(c->lt_nodes.size() * sizeof(LtNode));
+    L.lt_emit = take(ne * 4);
+    L.lt_pos = take(ne * 4);
+    L.lt_w = take(ne * 4);
     L.env_texel = take(c->env_texel.size() * sizeof(float4));
     L.env_row = take(c->env_row.size() * 4);
     L.env_col = take(c->env_col.size() * 4);
@@ -791,6 +907,7 @@ int qpt_build_scene(qpt_ctx *c, const qpt_scene_desc *d)
                   d->env_rgb ? d->env_rgb + 3ull * c->ew * c->eh : nullptr);
     c->cam = d->camera;
     build_lights(c);
+    build_light_tree(c);
     c->env_row.clear();
     c->env_col.clear();
     c->env_texel.clear();
@@ -1025,6 +1142,10 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     HIP_TRY(c, up(L.alias_idx, c->alias_idx.data(), c->alias_idx.size() * 4));
     HIP_TRY(c, up(L.alias_thr, c->alias_thr.data(), c->alias_thr.size() * 8));
     HIP_TRY(c, up(L.emit_pmf, pmf32.data(), pmf32.size() * 4));
+    HIP_TRY(c, up(L.lt_nodes, c->lt_nodes.data(), c->lt_nodes.size() * sizeof(LtNode)));
+    HIP_TRY(c, up(L.lt_emit, c->lt_emit.data(), c->lt_emit.size() * 4));
+    HIP_TRY(c, up(L.lt_pos, c->lt_pos.data(), c->lt_pos.size() * 4));
+    HIP_TRY(c, up(L.lt_w, c->lt_w.data(), c->lt_w.size() * 4));
     HIP_TRY(c, up(L.env_texel, c->env_texel.data(), c->env_texel.size() * sizeof(float4)));
     HIP_TRY(c, up(L.env_row, c->env_row.data(), c->env_row.size() * 4));
     HIP_TRY(c, up(L.env_col, c->env_col.data(), c->env_col.size() * 4));
@@ -1040,6 +1161,10 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     f.alias_idx = (const uint32_t *)(w + L.alias_idx);
     f.alias_thr = (const unsigned long long *)(w + L.alias_thr);
     f.emit_pmf = (const float *)(w + L.emit_pmf);
+    f.lt_nodes = (const LtNode *)(w + L.lt_nodes);
+    f.lt_emit = (const uint32_t *)(w + L.lt_emit);
+    f.lt_pos = (const uint32_t *)(w + L.lt_pos);
+    f.lt_w = (const uint32_t *)(w + L.lt_w);
     f.env_w = c->ew;
     f.env_h = c->eh;
     f.env_texel = (const float4 *)(w + L.env_texel);
@@ -1130,8 +1255,8 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
 {
     if (!c || !o) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
-    if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2)
-        return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2)");
+    if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1)
+        return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1)");
     if (!num_passes) return QPT_OK;
     // the largest Halton index must fit 64 bits
     u128 last = (u128)(first_pass + num_passes) * c->frame.S;
@@ -1145,6 +1270,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.rr = o->rr;
     f.mode = o->mode;
     f.scramble = o->scramble;
+    f.light_tree = o->light_tree;
     Profiler *prof = c->profiling ? &c->prof : nullptr;
     // one batch of passes (or of pixels), then one training step if enabled
     const uint32_t npix = c->W * c->H, cap = c->pool_cap;
@@ -1451,6 +1577,44 @@ int qpt_debug_light_tables(const qpt_ctx *c, uint32_t *emit_tri, double *prob, u
         if (alias) alias[e] = c->alias_idx[e];
         if (pmf) pmf[e] = c->emit_pmf[e];
     }
+    return QPT_OK;
+}
+
+int qpt_debug_light_tree(const qpt_ctx *c, float *sphere4, float *flux6, int32_t *left, uint32_t *first,
+                         uint32_t *count, uint32_t *emit, uint32_t *weight, uint32_t *num_nodes)
+{
+    if (!c || !num_nodes) return QPT_E_INVALID;
+    if (!c->scene_ok) return QPT_E_STATE;
+    const size_t nn = c->lt_nodes.size();
+    *num_nodes = (uint32_t)nn;
+    for (size_t k = 0; k < nn; ++k) {
+        const LtNode &nd = c->lt_nodes[k];
+        if (sphere4) {
+            sphere4[4 * k + 0] = nd.sphere.x;
+            sphere4[4 * k + 1] = nd.sphere.y;
+            sphere4[4 * k + 2] = nd.sphere.z;
+            sphere4[4 * k + 3] = nd.sphere.w;
+        }
+        if (flux6)
+            for (int r = 0; r < 6; ++r) flux6[6 * k + r] = nd.flux[r];
+        if (left) left[k] = nd.left;
+        if (first) first[k] = nd.first;
+        if (count) count[k] = nd.count;
+    }
+    if (emit) std::memcpy(emit, c->lt_emit.data(), c->lt_emit.size() * 4);
+    if (weight) std::memcpy(weight, c->lt_w.data(), c->lt_w.size() * 4);
+    return QPT_OK;
+}
+
+int qpt_debug_light_sample(qpt_ctx *c, const uint64_t *S, const float *x, const float *nrm, uint32_t n,
+                           uint32_t *emitter, uint64_t *size, uint64_t *size_hit)
+{
+    if (!c || (n && (!S || !x || !nrm || !emitter || !size || !size_hit))) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    if (c->emit_input_tri.empty()) return fail(c, QPT_E_STATE, "the scene has no triangle lights");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_debug_light_sample(c->frame, S, x, nrm, n, emitter, size, size_hit, c->stream));
     return QPT_OK;
 }
 

@@ -45,6 +45,21 @@ struct alignas(16) Tri {
     float4 v0, v1, v2;
 };
 
+// Light tree node (the many-light hierarchy of Sec. 2.1.1), 64 bytes:
+// bounding sphere of the node's triangles, flux towards each emission region
+// (the dominant-axis cells +x, -x, +y, -y, +z, -z of the sphere of
+// directions), first of its two adjacent children (-1 for a leaf) and its
+// range of emitters in leaf order.
+struct alignas(16) LtNode {
+    float4 sphere;    // centre xyz, radius
+    float flux[6];
+    int32_t left;
+    uint32_t first, count;
+    uint32_t pad[3];
+};
+static_assert(sizeof(LtNode) == 64, "light tree node is one 64-byte line");
+constexpr uint32_t kLtLeaf = 8;   // emitters per leaf at most
+
 struct alignas(16) Material {
     float4 albedo_rough;    // rho.rgb, alpha
     float4 emission_flags;  // Le.rgb, flags (bits)
@@ -91,6 +106,10 @@ struct Frame {
     const uint32_t *alias_idx;
     const unsigned long long *alias_thr;  // take column iff bits < thr (2^32 scale)
     const float *emit_pmf;                // realised selection probability
+    const LtNode *lt_nodes;               // light tree (root = node 0)
+    const uint32_t *lt_emit;              // leaf-order position -> emitter
+    const uint32_t *lt_pos;               // emitter -> leaf-order position
+    const uint32_t *lt_w;                 // leaf-order position -> cumulative 24-bit weight in its leaf
     // environment
     uint32_t env_w, env_h;
     const float4 *env_texel;              // rgb, solid-angle pdf
@@ -111,13 +130,14 @@ struct Frame {
     uint32_t W, H;
     // options
     uint32_t max_depth, rr, mode, scramble;
+    uint32_t light_tree;                  // select triangle lights through the light tree
 };
 
 // Path pool (structure of arrays, Sec. 3.1.1) and queues (Sec. 3.1.2).
 struct Pool {
     uint32_t cap;
     float4 *ray_o;      // o.xyz, tmax
-    float4 *ray_d;      // d.xyz, -
+    float4 *ray_d;      // d.xyz, previous vertex (triangle | back-face bit 31, as bits)
     float4 *hit;        // t, tri (BVH order, bits), b1, b2
     float4 *thr;        // throughput.rgb, pdf of the last BSDF sample
     float4 *rad;        // radiance.rgb, -
@@ -187,6 +207,9 @@ hipError_t launch_guide_debug_mixture(const float *out40, const float *dirs, con
 hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
                                     uint32_t n, int scramble, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);
+hipError_t launch_debug_light_sample(const Frame &f, const uint64_t *S, const float *x, const float *nrm,
+                                     uint32_t n, uint32_t *emitter, uint64_t *size, uint64_t *size_hit,
+                                     hipStream_t s);
 hipError_t launch_debug_trace(const Frame &f, const Pool &pool, const float *rays, uint32_t n, int any_hit,
                               int brute, float *t, uint32_t *tri, float *b12, hipStream_t s);
 

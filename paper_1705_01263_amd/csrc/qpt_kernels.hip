@@ -506,6 +506,137 @@ __device__ __forceinline__ uint32_t upper_search(const uint32_t *q, uint32_t n, 
     return lo;
 }
 
+// Unit geometric normal of a triangle and twice its area, each product and
+// sum rounded once: shading and the light tree's re-descent at a later
+// vertex must see the same bits.
+__device__ __forceinline__ f3 unit_normal(f3 a, f3 b, f3 c, float &area2)
+{
+#pragma clang fp contract(off)
+    const f3 e1 = b - a, e2 = c - a;
+    const f3 n = mk(e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x);
+    area2 = sqrtf((n.x * n.x + n.y * n.y) + n.z * n.z);
+    const float inv = 1.0f / area2;
+    return mk(n.x * inv, n.y * inv, n.z * inv);
+}
+
+// ------------------------------------------------------------ light tree
+//
+// Selection of a triangle light through the hierarchy of Sec. 2.1.1. A node's
+// importance at a shading point x with normal n is its flux towards the
+// emission region holding the direction from its centre to x, times an upper
+// bound of the cosine at x over its bounding sphere, over max(d^2, r^2); each
+// step rounds once, so the choice does not depend on the compiler's fusing.
+__device__ float lt_importance(const LtNode *nd, f3 x, f3 n)
+{
+#pragma clang fp contract(off)
+    const float4 sp = nd->sphere;
+    const float dx = sp.x - x.x, dy = sp.y - x.y, dz = sp.z - x.z;
+    const float d2 = (dx * dx + dy * dy) + dz * dz;
+    const float r = sp.w, r2 = r * r;
+    // region of the emission direction x - c: dominant axis (ties to the
+    // lower axis) and its sign
+    const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+    int k = 0;
+    float m = ax, ek = -dx;
+    if (ay > m) {
+        k = 1;
+        m = ay;
+        ek = -dy;
+    }
+    if (az > m) {
+        k = 2;
+        ek = -dz;
+    }
+    const float flux = nd->flux[2 * k + (ek < 0.0f ? 1 : 0)];
+    float cosx = 1.0f;
+    if (d2 > r2) {
+        const float d = sqrtf(d2);
+        const float sinb = r / d;
+        const float cosb = sqrtf(1.0f - sinb * sinb);
+        const float cosa = ((n.x * dx + n.y * dy) + n.z * dz) / d;
+        if (cosa < cosb) {
+            const float sina = sqrtf(fmaxf(0.0f, 1.0f - cosa * cosa));
+            cosx = fmaxf(0.0f, cosa * cosb + sina * sinb);
+        }
+    }
+    return flux * cosx / fmaxf(d2, r2);
+}
+
+// probability of the first child of the pair at `l`, in 24 bits, within [1/16, 15/16]
+__device__ uint32_t lt_left_q(const Frame &F, int32_t l, f3 x, f3 n)
+{
+#pragma clang fp contract(off)
+    const float el = lt_importance(F.lt_nodes + l, x, n), er = lt_importance(F.lt_nodes + l + 1, x, n);
+    const float sum = el + er;
+    float p = (sum > 0.0f && isfinite(sum)) ? el / sum : 0.5f;
+    p = fminf(fmaxf(p, 0.0625f), 0.9375f);
+    return (uint32_t)(p * 16777216.0f + 0.5f);
+}
+
+// floor(R q / 2^24) exactly (R < 2^63, q <= 2^24)
+__device__ __forceinline__ uint64_t lt_split(uint64_t R, uint32_t q)
+{
+    return (R >> 24) * q + (((R & 0xFFFFFFull) * q) >> 24);
+}
+
+// the first child's share of an interval of size R, kept inside [1, R - 1]
+__device__ __forceinline__ uint64_t lt_cut(uint64_t R, uint32_t q)
+{
+    const uint64_t T = lt_split(R, q);
+    return T < 1 ? 1 : (T > R - 1 ? R - 1 : T);
+}
+
+// Emitter chosen by the 63-bit sample S: the descent narrows [0, 2^63) to
+// the chosen leaf, whose cumulative weights split what is left. size = the
+// emitter's interval, its selection probability times 2^63.
+__device__ uint32_t lt_sample(const Frame &F, uint64_t S, f3 x, f3 n, uint64_t &size)
+{
+    uint64_t R = 1ull << 63;
+    int32_t node = 0, l = F.lt_nodes[0].left;
+    while (l >= 0) {
+        const uint64_t T = lt_cut(R, lt_left_q(F, l, x, n));
+        if (S < T) {
+            R = T;
+            node = l;
+        } else {
+            S -= T;
+            R -= T;
+            node = l + 1;
+        }
+        l = F.lt_nodes[node].left;
+    }
+    const uint32_t f = F.lt_nodes[node].first, c = F.lt_nodes[node].count;
+    uint32_t j = 0;  // weights rise within a leaf: count the bounds at or below S
+    for (uint32_t q = 1; q < c; ++q) j += S >= lt_split(R, F.lt_w[f + q]) ? 1u : 0u;
+    const uint64_t a = lt_split(R, F.lt_w[f + j]);
+    const uint64_t z = j + 1 < c ? lt_split(R, F.lt_w[f + j + 1]) : R;
+    size = z - a;
+    return F.lt_emit[f + j];
+}
+
+// the interval size of emitter e, by the same descent steered to its leaf
+__device__ uint64_t lt_size_of(const Frame &F, uint32_t e, f3 x, f3 n)
+{
+    const uint32_t pos = F.lt_pos[e];
+    uint64_t R = 1ull << 63;
+    int32_t node = 0, l = F.lt_nodes[0].left;
+    while (l >= 0) {
+        const uint64_t T = lt_cut(R, lt_left_q(F, l, x, n));
+        if (pos < F.lt_nodes[l + 1].first) {
+            R = T;
+            node = l;
+        } else {
+            R -= T;
+            node = l + 1;
+        }
+        l = F.lt_nodes[node].left;
+    }
+    const uint32_t c = F.lt_nodes[node].count, j = pos - F.lt_nodes[node].first;
+    const uint64_t a = lt_split(R, F.lt_w[pos]);
+    const uint64_t z = j + 1 < c ? lt_split(R, F.lt_w[pos + 1]) : R;
+    return z - a;
+}
+
 // ---------------------------------------------------------------- kernels
 
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
@@ -628,7 +759,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
         if (active) {
             slot = q[i];
             float4 hv = P.hit[slot];
-            f3 d = xyz(P.ray_d[slot]);
+            const float4 d4 = P.ray_d[slot];
+            f3 d = xyz(d4);
             float4 T4 = P.thr[slot];
             f3 T = xyz(T4);
             float prev_pdf = T4.w;
@@ -645,9 +777,8 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                 const Material m = F.mats[fbits(tr.v0.w)];
                 f3 a = xyz(tr.v0), b = xyz(tr.v1), c = xyz(tr.v2);
                 f3 x = a + ((b - a) * hv.z + (c - a) * hv.w);
-                f3 ng = cross(b - a, c - a);
-                float area2 = length(ng);
-                ng = ng * (1.0f / area2);
+                float area2;
+                f3 ng = unit_normal(a, b, c, area2);
                 float dn = dot(d, ng);
                 bool front = dn < 0.0f;
                 uint32_t em = fbits(tr.v2.w);
@@ -655,7 +786,21 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                     f3 Le = emission_at(m, x);
                     float w = 1.0f;
                     if (v > 1 && F.mode == 0) {
-                        float pl = F.emit_pmf[em] / (0.5f * area2) * hv.x * hv.x / (-dn);
+                        float pe;
+                        if (F.light_tree) {
+                            // the tree's probability of this emitter from the previous
+                            // vertex: its ray origin and oriented normal, as its NEE saw them
+                            const uint32_t pv = fbits(d4.w);
+                            const Tri pt = F.tris[pv & 0x7fffffffu];
+                            float pa2;
+                            f3 pn = unit_normal(xyz(pt.v0), xyz(pt.v1), xyz(pt.v2), pa2);
+                            if (pv >> 31) pn = pn * -1.0f;
+                            const uint64_t z = lt_size_of(F, em, xyz(P.ray_o[slot]), pn);
+                            pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
+                        } else {
+                            pe = F.emit_pmf[em];
+                        }
+                        float pl = pe / (0.5f * area2) * hv.x * hv.x / (-dn);
                         w = mis2(prev_pdf, pl);
                     }
                     L = L + T * Le * w;
@@ -705,10 +850,23 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                             pl = F.p_env * e.w;
                             ok = pl > 0.0f;
                         } else {
-                            // rr < R <= 2^32 and num_emit < 2^27: the product fits 64 bits
-                            uint32_t col = (uint32_t)((rr * (uint64_t)F.num_emit) >> (R == (1ull << 31) ? 31 : 32));
                             uint32_t s7 = sample_bits(F, idx, base_dim + 7, F.scramble);
-                            uint32_t e = (unsigned long long)s7 < F.alias_thr[col] ? col : F.alias_idx[col];
+                            uint32_t e;
+                            float pe;
+                            if (F.light_tree) {
+                                // 63-bit sample: what slot 0 leaves after the environment
+                                // choice (its top 31 bits without an environment), then slot 7
+                                const uint64_t hi = F.env_w ? rr : (uint64_t)(s0 >> 1);
+                                uint64_t z;
+                                e = lt_sample(F, (hi << 32) | s7, xo, nn, z);
+                                pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
+                            } else {
+                                // rr < R <= 2^32 and num_emit < 2^27: the product fits 64 bits
+                                uint32_t col =
+                                    (uint32_t)((rr * (uint64_t)F.num_emit) >> (R == (1ull << 31) ? 31 : 32));
+                                e = (unsigned long long)s7 < F.alias_thr[col] ? col : F.alias_idx[col];
+                                pe = F.emit_pmf[e];
+                            }
                             const Tri lt = F.tris[F.emit_tri[e]];
                             float q1 = u24(sample_bits(F, idx, base_dim + 1, F.scramble));
                             float q2 = u24(sample_bits(F, idx, base_dim + 2, F.scramble));
@@ -726,7 +884,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                             float cl = -dot(nl, wi);
                             if (cl > 0.0f) {
                                 Le = emission_at(F.mats[fbits(lt.v0.w)], y);
-                                pl = F.emit_pmf[e] / (0.5f * la2) * d2 / cl;
+                                pl = pe / (0.5f * la2) * d2 / cl;
                                 ok = pl > 0.0f;
                                 tmax = dist * (1.0f - 1e-4f);
                             }
@@ -796,7 +954,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                                 }
                                 if (alive) {
                                     P.ray_o[slot] = f4(xo, INFINITY);
-                                    P.ray_d[slot] = f4(wi, 0.0f);
+                                    P.ray_d[slot] = f4(wi, ubits(tri | (front ? 0u : 0x80000000u)));
                                     P.thr[slot] = f4(T, pb);
                                     if (F.guide.record && v <= F.guide.max_vertex &&
                                         (F.guide.rec_thr == 0xffffffffu || rec_hash(idx, v) < F.guide.rec_thr)) {
@@ -987,6 +1145,27 @@ hipError_t launch_debug_sample_bits(const Frame &F, const uint64_t *idx, const u
 {
     hipLaunchKernelGGL(k_debug_sample_bits, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, idx, dim, n,
                        scramble, out);
+    return hipGetLastError();
+}
+
+__global__ void k_debug_light_sample(Frame F, const uint64_t *S, const float *x, const float *nrm, uint32_t n,
+                                     uint32_t *emitter, uint64_t *size, uint64_t *size_hit)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const f3 xp = mk(x[3 * i], x[3 * i + 1], x[3 * i + 2]), np = mk(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]);
+    uint64_t z;
+    const uint32_t e = lt_sample(F, S[i] & 0x7fffffffffffffffull, xp, np, z);
+    emitter[i] = e;
+    size[i] = z;
+    size_hit[i] = lt_size_of(F, e, xp, np);
+}
+
+hipError_t launch_debug_light_sample(const Frame &F, const uint64_t *S, const float *x, const float *nrm, uint32_t n,
+                                     uint32_t *emitter, uint64_t *size, uint64_t *size_hit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_light_sample, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, S, x, nrm, n,
+                       emitter, size, size_hit);
     return hipGetLastError();
 }
 

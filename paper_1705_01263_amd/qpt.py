@@ -46,7 +46,8 @@ class qpt_bvh_stats(C.Structure):
 
 
 class qpt_render_opts(C.Structure):
-    _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32)]
+    _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32),
+                ("light_tree", C.c_uint32)]
 
 
 class qpt_stats(C.Structure):
@@ -72,6 +73,7 @@ EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
+    "qpt_debug_light_tree", "qpt_debug_light_sample",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
     "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_eval", "qpt_guide_debug_grad",
     "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
@@ -108,6 +110,8 @@ def lib():
             "qpt_debug_pixel_index": ([P, u64, P], i32),
             "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P], i32),
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
+            "qpt_debug_light_tree": ([P, P, P, P, P, P, P, P, C.POINTER(C.c_uint32)], i32),
+            "qpt_debug_light_sample": ([P, P, P, P, u32, P, P, P], i32),
             "qpt_debug_env_tables": ([P, P, P, P], i32),
             "qpt_debug_bvh_nodes": ([P, P, P, P], i32),
             "qpt_profile": ([P, i32], i32),
@@ -214,8 +218,8 @@ class Context:
         self.check(self.L.qpt_bind_workspace(self.h, C.c_void_p(ptr), nbytes, pool_paths), "qpt_bind_workspace")
 
     def render_pass(self, first_pass: int, num_passes: int, max_depth: int, rr: bool = True, mode: int = 0,
-                    scramble: bool = True) -> None:
-        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble))
+                    scramble: bool = True, light_tree: bool = False) -> None:
+        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree))
         self.check(self.L.qpt_render_pass(self.h, first_pass, num_passes, C.byref(o)), "qpt_render_pass")
 
     def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> None:
@@ -288,6 +292,27 @@ class Context:
         self.check(self.L.qpt_debug_trace(self.h, _p(rays), n, int(any_hit), int(brute_force), _p(t), _p(tri),
                                           _p(b12)), "qpt_debug_trace")
 
+    def debug_light_tree(self):
+        """The light tree's host tables (same keys as the oracle's)."""
+        nn = C.c_uint32()
+        self.check(self.L.qpt_debug_light_tree(self.h, None, None, None, None, None, None, None, C.byref(nn)),
+                   "qpt_debug_light_tree")
+        n = nn.value
+        ne = self.debug_light_tables()["tri"].shape[0]
+        t = dict(center=np.empty((n, 4), np.float32), flux=np.empty((n, 6), np.float32),
+                 left=np.empty(n, np.int32), first=np.empty(n, np.uint32), count=np.empty(n, np.uint32),
+                 emit=np.empty(ne, np.uint32), w=np.empty(ne, np.uint32))
+        self.check(self.L.qpt_debug_light_tree(self.h, _p(t["center"]), _p(t["flux"]), _p(t["left"]),
+                                               _p(t["first"]), _p(t["count"]), _p(t["emit"]), _p(t["w"]),
+                                               C.byref(nn)), "qpt_debug_light_tree")
+        return t
+
+    def debug_light_sample(self, S, x, nrm, n, emitter, size, size_hit) -> None:
+        """Device buffers: S (n uint64), x and nrm (3n float32) in; emitter
+        (n uint32), size and size_hit (n uint64) out."""
+        self.check(self.L.qpt_debug_light_sample(self.h, _p(S), _p(x), _p(nrm), n, _p(emitter), _p(size),
+                                                 _p(size_hit)), "qpt_debug_light_sample")
+
     def debug_light_tables(self):
         cnt = C.c_uint32()
         self.check(self.L.qpt_debug_light_tables(self.h, None, None, None, None, C.byref(cnt)),
@@ -338,8 +363,9 @@ class Renderer:
         self.ctx.bind_workspace(ptr, nbytes, pool_paths)
         self.W, self.H = sc.width, sc.height
 
-    def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True):
-        self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble)
+    def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True,
+               light_tree=False):
+        self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble, light_tree)
 
     def readback(self):
         s = np.empty((self.H * self.W, 3), np.float64)

@@ -131,3 +131,20 @@ def test_bvh_structure(qpt, make):
     assert np.all(seen == 1)
     assert parents[0] == 0 and np.all(parents[1:] == 1)
     assert leaves == st.num_leaves
+
+
+@pytest.mark.parametrize("make", [lambda: g.light_field(n_lights=700), lambda: g.light_field(n_lights=300, env=True),
+                                  lambda: g.grid_scene(grid=2), lambda: g.quad_over_plane(subdiv=12),
+                                  lambda: g.light_field(n_lights=5)])
+def test_light_tree_matches_oracle(qpt, orc, make):
+    """The library's light tree, built by its own code, equals the oracle's
+    table for table, bit for bit (same split rule, same FP64 sums in the
+    same order, same FP32 rounding)."""
+    sc = make()
+    c = qpt.Context(-1)
+    c.build_scene(sc)
+    mine = c.debug_light_tree()
+    ref = orc.Scene(sc, build_bvh=False).light_tree()
+    assert mine["left"].shape == ref["left"].shape
+    for k in ("center", "flux", "left", "first", "count", "emit", "w"):
+        assert np.array_equal(mine[k].view(np.uint32), ref[k].view(np.uint32)), k
