@@ -235,6 +235,64 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
     return out
 
 
+def light_select_equal_time(r, sc, seconds: float, ref_passes: int):
+    """Equal-time RMSE of triangle-light selection by the flux alias table and
+    by the light tree, on the renderer's own scene (the city: 10,000 emissive
+    window triangles). Reference: both estimators at `ref_passes` passes each
+    from an independent pass range, averaged (FP64 sums, whole frame). Each
+    contender renders whole two-frame batches from pass 0 until `seconds`
+    have passed (the tree gets the alias run's wall time). Also the shading
+    kernel's time per pass with each selector."""
+    import numpy as np
+    import torch
+
+    W, H = sc.width, sc.height
+    lum = np.array([0.2126, 0.7152, 0.0722])
+    ref = np.zeros((W * H, 3))
+    t_ref = {}
+    for tree in (False, True):
+        r.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.render(1 << 24, ref_passes, light_tree=tree)
+        s, c = r.readback()
+        t_ref[tree] = round(time.perf_counter() - t0, 2)
+        ref += 0.5 * s / c[:, None]
+    lit = ref @ lum > 0
+    out = {"reference": {"passes_each": ref_passes, "first_pass": 1 << 24, "seconds": t_ref[False] + t_ref[True],
+                         "lit_pixel_fraction": round(float(lit.mean()), 4)}}
+    budget = seconds
+    for name, tree in (("alias_table", False), ("light_tree", True)):
+        # shading kernel per pass, event-timed over 8 passes
+        r.reset()
+        r.ctx.profile(True)
+        r.render(1 << 26, 8, light_tree=tree)
+        r.ctx.profile(False)
+        prof = r.ctx.profile_read()
+        r.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget:
+            r.render(n, 2, light_tree=tree)
+            n += 2
+            torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if not tree:
+            budget = dt
+        s, c = r.readback()
+        img = s / c[:, None]
+        e = img - ref
+        out[name] = {"passes": n, "seconds": round(dt, 3), "ms_per_pass": round(dt * 1e3 / n, 3),
+                     "shade_ms_per_pass": round(prof["shade"][1] / 8, 3),
+                     "rmse": float(np.sqrt(np.mean(e ** 2))),
+                     "rel_rmse_lit": float(np.sqrt(np.mean(((e @ lum)[lit] / np.maximum((ref @ lum)[lit], 1e-3)) ** 2)))}
+        _say(f"bench: light selection {name}: {n} passes in {dt:.2f} s, rmse {out[name]['rmse']:.5f}")
+    out["tree_over_alias_rmse"] = round(out["light_tree"]["rmse"] / out["alias_table"]["rmse"], 4)
+    out["tree_over_alias_rel_rmse_lit"] = round(out["light_tree"]["rel_rmse_lit"] / out["alias_table"]["rel_rmse_lit"], 4)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +309,10 @@ def main():
     ap.add_argument("--et-oracle-seconds", type=float, default=10.0)
     ap.add_argument("--et-size", type=str, default="1920x1080")
     ap.add_argument("--et-tris", type=int, default=4_000_000)
+    ap.add_argument("--no-light-select", action="store_true",
+                    help="skip the alias table vs light tree equal-time leg (city workload only)")
+    ap.add_argument("--ls-seconds", type=float, default=2.0, help="wall time of each light-selection run")
+    ap.add_argument("--ls-ref-passes", type=int, default=512, help="reference passes per selector")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -350,6 +412,12 @@ def main():
         _say(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         cpu = cpu_baseline(sc, args.cpu_seconds)
 
+    ls = None
+    if args.workload == "city" and not args.no_light_select:
+        _say("bench: alias table vs light tree at equal time")
+        ls = light_select_equal_time(r, sc, args.ls_seconds, args.ls_ref_passes)
+        _say(f"bench: light selection {ls}")
+
     et = None
     if not args.no_equal_time:
         del r
@@ -370,6 +438,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "equal_time_rmse": et,
+        "light_selection_equal_time": ls,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)
