@@ -104,6 +104,12 @@ typedef struct {
     uint32_t light_tree;     /* 0: triangle lights by flux (alias table), 1: through the light tree
                                 (the many-light hierarchy of Sec. 2.1.1; importance by distance,
                                 orientation and flux of its nodes) */
+    uint32_t single_stream;  /* 0: consecutive batches of passes run two at a time (the caller's stream
+                                and a second stream of the library, each with its own path pool; the
+                                caller's stream waits for both before the call's later work), so a
+                                batch's deep vertices overlap the next batch's first ones; guided
+                                rendering always uses one stream. 1: one batch after another on the
+                                caller's stream. The image is the same bit for bit. */
 } qpt_render_opts;
 
 typedef struct {
@@ -156,12 +162,13 @@ int qpt_build_scene(qpt_ctx *ctx, const qpt_scene_desc *desc);
  * library with the library's own traversal). stats may be NULL. */
 int qpt_build_bvh(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
 
-/* Bytes of device workspace needed for `pool_paths` concurrent paths
- * (0 = four frames' worth: the smallest power of two >= 4 W H, within
+/* Bytes of device workspace needed for `pool_paths` concurrent paths per
+ * batch (0 = four frames' worth: the smallest power of two >= 4 W H, within
  * [2^16, 2^24]). Passes are rendered in batches of as many whole passes as the
  * pool holds (or in pixel chunks of one pass when a frame exceeds it); larger
- * batches keep the queues of deep vertices full. Scene, BVH, path state,
- * queues and framebuffer all live in it. */
+ * batches keep the queues of deep vertices full. The workspace holds two such
+ * pools, one per batch in flight. Scene, BVH, path state, queues and
+ * framebuffer all live in it. */
 int qpt_workspace_size(const qpt_ctx *ctx, uint32_t pool_paths, size_t *bytes);
 
 /* Bind caller-owned device memory (256-byte aligned, `bytes` from

@@ -268,7 +268,11 @@ struct Layout {
     size_t nodes, tris, mats, emit_tri, alias_idx, alias_thr, emit_pmf, lt_nodes, lt_emit, lt_pos, lt_w,
         env_texel, env_row,
         env_col, env_cos, bases;
-    size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, stats, gstack;
+    // per batch lane (two batches in flight): path state, queues, shadow rays, counters, stack
+    struct Lane {
+        size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, gstack;
+    } lane[2];
+    size_t stats;
     size_t fb_sum, fb_count;
     size_t g_frag, g_fragT, g_bias, g_mix, g_rec, g_ring, g_ring_head, g_master, g_m, g_v, g_partial, g_scalars;
     size_t g_pub_frag[2], g_pub_bias[2];
@@ -379,7 +383,13 @@ struct qpt_ctx {
     size_t ws_bytes = 0;
     uint32_t pool_cap = 0;
     Layout lay{};
-    Pool pool{};
+    Pool pool{};     // lane 0 (the caller's stream); the guide, debug hooks and readback use it
+    Pool pool_b{};   // lane 1 (the library's second stream)
+    // two batches in flight: lane 1's stream, and the events that order the
+    // lanes against the caller's stream and the framebuffer updates in pass order
+    hipStream_t lstream = nullptr;
+    hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr;
+    uint64_t batches = 0;
 };
 
 namespace {
@@ -766,20 +776,22 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.env_col = take(c->env_col.size() * 4);
     L.env_cos = take(c->env_cos.size() * 4);
     L.bases = take(kMaxDims * sizeof(HaltonBase));
-    L.ray_o = take((size_t)cap * 16);
-    L.ray_d = take((size_t)cap * 16);
-    L.hit = take((size_t)cap * 16);
-    L.thr = take((size_t)cap * 16);
-    L.rad = take((size_t)cap * 16);
-    L.idx = take((size_t)cap * 8);
-    L.q0 = take((size_t)cap * 4);
-    L.q1 = take((size_t)cap * 4);
-    L.qsh = take((size_t)cap * 4);
-    L.sh_o = take((size_t)cap * 16);
-    L.sh_d = take((size_t)cap * 16);
-    L.sh_c = take((size_t)cap * 16);
-    L.counters = take(128 * 4);
-    L.gstack = take((size_t)c->trav_threads * (c->stack_need > kShortStack ? c->stack_need - kShortStack : 1u) * 4);
+    for (Layout::Lane &ln : L.lane) {
+        ln.ray_o = take((size_t)cap * 16);
+        ln.ray_d = take((size_t)cap * 16);
+        ln.hit = take((size_t)cap * 16);
+        ln.thr = take((size_t)cap * 16);
+        ln.rad = take((size_t)cap * 16);
+        ln.idx = take((size_t)cap * 8);
+        ln.q0 = take((size_t)cap * 4);
+        ln.q1 = take((size_t)cap * 4);
+        ln.qsh = take((size_t)cap * 4);
+        ln.sh_o = take((size_t)cap * 16);
+        ln.sh_d = take((size_t)cap * 16);
+        ln.sh_c = take((size_t)cap * 16);
+        ln.counters = take(128 * 4);
+        ln.gstack = take((size_t)c->trav_threads * (c->stack_need > kShortStack ? c->stack_need - kShortStack : 1u) * 4);
+    }
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
@@ -860,6 +872,14 @@ void qpt_destroy(qpt_ctx *ctx)
             if (ctx->ev_train[k]) (void)hipEventDestroy(ctx->ev_train[k]);
         }
         (void)hipStreamDestroy(ctx->tstream);
+    }
+    if (ctx->lstream) {
+        DeviceGuard g(ctx->device);
+        (void)hipStreamSynchronize(ctx->lstream);
+        (void)hipEventDestroy(ctx->ev_lane_in);
+        (void)hipEventDestroy(ctx->ev_lane_out);
+        (void)hipEventDestroy(ctx->ev_acc);
+        (void)hipStreamDestroy(ctx->lstream);
     }
     delete ctx;
 }
@@ -1123,6 +1143,10 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
             HIP_TRY(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
             HIP_TRY(c, hipEventCreateWithFlags(&c->ev_train[k], hipEventDisableTiming));
         }
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->lstream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_in, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
     }
     c->ws = (uint8_t *)device_ptr;
     c->ws_bytes = bytes;
@@ -1173,26 +1197,29 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     f.env_cos = (const float *)(w + L.env_cos);
     f.p_env = (float)c->p_env;
     f.bases = (const HaltonBase *)(w + L.bases);
-    Pool &p = c->pool;
-    p.cap = cap;
-    p.ray_o = (float4 *)(w + L.ray_o);
-    p.ray_d = (float4 *)(w + L.ray_d);
-    p.hit = (float4 *)(w + L.hit);
-    p.thr = (float4 *)(w + L.thr);
-    p.rad = (float4 *)(w + L.rad);
-    p.idx = (unsigned long long *)(w + L.idx);
-    p.q_ext[0] = (uint32_t *)(w + L.q0);
-    p.q_ext[1] = (uint32_t *)(w + L.q1);
-    p.q_sh = (uint32_t *)(w + L.qsh);
-    p.sh_o = (float4 *)(w + L.sh_o);
-    p.sh_d = (float4 *)(w + L.sh_d);
-    p.sh_c = (float4 *)(w + L.sh_c);
-    p.counters = (uint32_t *)(w + L.counters);
-    p.gstack = (int *)(w + L.gstack);
-    p.trav_threads = c->trav_threads;
-    p.stats = (unsigned long long *)(w + L.stats);
-    p.fb_sum = (double *)(w + L.fb_sum);
-    p.fb_count = (uint32_t *)(w + L.fb_count);
+    for (int k = 0; k < 2; ++k) {
+        const Layout::Lane &ln = L.lane[k];
+        Pool &p = k ? c->pool_b : c->pool;
+        p.cap = cap;
+        p.ray_o = (float4 *)(w + ln.ray_o);
+        p.ray_d = (float4 *)(w + ln.ray_d);
+        p.hit = (float4 *)(w + ln.hit);
+        p.thr = (float4 *)(w + ln.thr);
+        p.rad = (float4 *)(w + ln.rad);
+        p.idx = (unsigned long long *)(w + ln.idx);
+        p.q_ext[0] = (uint32_t *)(w + ln.q0);
+        p.q_ext[1] = (uint32_t *)(w + ln.q1);
+        p.q_sh = (uint32_t *)(w + ln.qsh);
+        p.sh_o = (float4 *)(w + ln.sh_o);
+        p.sh_d = (float4 *)(w + ln.sh_d);
+        p.sh_c = (float4 *)(w + ln.sh_c);
+        p.counters = (uint32_t *)(w + ln.counters);
+        p.gstack = (int *)(w + ln.gstack);
+        p.trav_threads = c->trav_threads;
+        p.stats = (unsigned long long *)(w + L.stats);
+        p.fb_sum = (double *)(w + L.fb_sum);
+        p.fb_count = (uint32_t *)(w + L.fb_count);
+    }
     GuideTrain &T = c->gt;
     T.master = (float *)(w + L.g_master);
     T.m = (float *)(w + L.g_m);
@@ -1226,7 +1253,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.record = 0;
     G.rec = (float4 *)(w + L.g_rec);
     G.rec_cap = (uint32_t)guide_rec_cap(cap);
-    G.rec_count = p.counters + 127;
+    G.rec_count = c->pool.counters + 127;  // guided batches run on lane 0
     c->guide_weights = false;
     c->guide_steps = 0;
     c->bound = true;
@@ -1272,9 +1299,34 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.scramble = o->scramble;
     f.light_tree = o->light_tree;
     Profiler *prof = c->profiling ? &c->prof : nullptr;
+    // Two batches in flight (without the guide): consecutive batches alternate
+    // between the caller's stream and the library's second stream, each lane
+    // with its own path pool, so that one batch's deep vertices (few paths,
+    // latency-bound traversals) overlap the next batch's first vertices. The
+    // framebuffer stays updated in pass order: a batch's accumulation waits
+    // for the previous batch's. Lane 1 starts after the caller's earlier work
+    // and the caller's stream waits for lane 1 before this call returns.
+    const bool two_lanes = !guiding && !o->single_stream;
+    bool lane_b_used = false;
+    // the point lane 1 waits for: the caller's work before this call
+    if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_lane_in, c->stream));
     // one batch of passes (or of pixels), then one training step if enabled
     const uint32_t npix = c->W * c->H, cap = c->pool_cap;
     auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
+        if (two_lanes) {
+            const bool lane_b = (c->batches++ & 1) != 0;
+            hipStream_t s = lane_b ? c->lstream : c->stream;
+            if (lane_b && !lane_b_used) {
+                HIP_TRY(c, hipStreamWaitEvent(c->lstream, c->ev_lane_in, 0));
+                lane_b_used = true;
+            }
+            const Pool &P = lane_b ? c->pool_b : c->pool;
+            HIP_TRY(c, launch_render_paths(f, P, p0, np, pass0, nb, s, prof));
+            HIP_TRY(c, hipStreamWaitEvent(s, c->ev_acc, 0));
+            HIP_TRY(c, launch_accumulate(f, P, p0, np, nb, s, prof));
+            HIP_TRY(c, hipEventRecord(c->ev_acc, s));
+            return QPT_OK;
+        }
         bool active = c->gopts.alpha > 0.0f && c->guide_steps >= c->gopts.warmup_steps;
         uint64_t thr = active ? (uint64_t)std::llround((double)c->gopts.alpha * 4294967296.0) : 0;
         f.guide.alpha_thr = (uint32_t)std::min<uint64_t>(thr, 0xffffffffull);
@@ -1346,6 +1398,10 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
                 int rc = batch(p0, std::min(cap, npix - p0), first_pass + j, 1);
                 if (rc) return rc;
             }
+    }
+    if (lane_b_used) {
+        HIP_TRY(c, hipEventRecord(c->ev_lane_out, c->lstream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_lane_out, 0));
     }
     return QPT_OK;
 }

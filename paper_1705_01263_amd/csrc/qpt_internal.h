@@ -186,6 +186,11 @@ hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s);
 hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
                                uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
+// the same in two parts: the paths of a batch, then its framebuffer update
+hipError_t launch_render_paths(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
+                               uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
+hipError_t launch_accumulate(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix, uint32_t npass,
+                             hipStream_t s, Profiler *prof);
 // guide launchers (qpt_guide.hip)
 hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s, uint2 *pub_a, float *pub_ab, uint2 *pub_b,
                              float *pub_bb);

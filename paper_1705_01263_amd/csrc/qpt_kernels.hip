@@ -1112,7 +1112,7 @@ hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
+hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
                                uint32_t npass, hipStream_t s, Profiler *prof)
 {
     uint32_t n = npix * npass;
@@ -1133,11 +1133,24 @@ hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uin
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
     }
-    timed(K_ACCUMULATE, [&] {
-        hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix,
-                           npass);
-    });
     return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint32_t npass,
+                             hipStream_t s, Profiler *prof)
+{
+    if (prof) prof->begin(K_ACCUMULATE, s);
+    hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, npass);
+    if (prof) prof->end(K_ACCUMULATE, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
+                               uint32_t npass, hipStream_t s, Profiler *prof)
+{
+    hipError_t e = launch_render_paths(F, P, pix0, npix, pass0, npass, s, prof);
+    if (e != hipSuccess) return e;
+    return launch_accumulate(F, P, pix0, npix, npass, s, prof);
 }
 
 hipError_t launch_debug_sample_bits(const Frame &F, const uint64_t *idx, const uint32_t *dim, uint32_t n,

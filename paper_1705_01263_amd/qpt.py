@@ -47,7 +47,7 @@ class qpt_bvh_stats(C.Structure):
 
 class qpt_render_opts(C.Structure):
     _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32),
-                ("light_tree", C.c_uint32)]
+                ("light_tree", C.c_uint32), ("single_stream", C.c_uint32)]
 
 
 class qpt_stats(C.Structure):
@@ -218,8 +218,8 @@ class Context:
         self.check(self.L.qpt_bind_workspace(self.h, C.c_void_p(ptr), nbytes, pool_paths), "qpt_bind_workspace")
 
     def render_pass(self, first_pass: int, num_passes: int, max_depth: int, rr: bool = True, mode: int = 0,
-                    scramble: bool = True, light_tree: bool = False) -> None:
-        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree))
+                    scramble: bool = True, light_tree: bool = False, single_stream: bool = False) -> None:
+        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree), int(single_stream))
         self.check(self.L.qpt_render_pass(self.h, first_pass, num_passes, C.byref(o)), "qpt_render_pass")
 
     def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> None:
@@ -364,8 +364,9 @@ class Renderer:
         self.W, self.H = sc.width, sc.height
 
     def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True,
-               light_tree=False):
-        self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble, light_tree)
+               light_tree=False, single_stream=False):
+        self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble, light_tree,
+                             single_stream)
 
     def readback(self):
         s = np.empty((self.H * self.W, 3), np.float64)

@@ -342,6 +342,27 @@ def test_pass_split_is_bit_identical(Renderer):
     assert np.array_equal(a, c_)
 
 
+@pytest.mark.parametrize("pool", [1 << 12, 1 << 9])
+def test_two_lanes_bit_identical(Renderer, pool):
+    """Consecutive batches alternate between two streams with their own path
+    pools; the FP64 sums, counts and ray statistics equal one-stream rendering
+    bit for bit, also when a pass is split into pixel chunks (pool < frame)."""
+    sc = g.cornell(width=32, height=32)
+    _say(f"[lanes] cornell 32x32 pool={pool}")
+    out = []
+    for single in (True, False):
+        r = Renderer(sc, pool_paths=pool)
+        r.render(0, 21, single_stream=single)
+        r.render(21, 6, single_stream=single)
+        s, c = r.readback()
+        st = r.stats()
+        out.append((s, c, (st.rays_extension, st.rays_shadow, st.paths)))
+    (s1, c1, t1), (s2, c2, t2) = out
+    assert np.all(c1 == 27) and np.array_equal(c1, c2)
+    assert np.array_equal(s1, s2)
+    assert t1 == t2
+
+
 def test_counts_and_stats(Renderer):
     sc = g.cornell(width=32, height=32)
     _, c, r = _render(Renderer, sc, 5)
