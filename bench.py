@@ -4,7 +4,9 @@
 One step = one pass of the whole hot path over the frame (one sample per
 pixel: enumeration, Halton samples, camera rays, closest hit, emission with
 MIS, next-event estimation, BSDF sampling, roulette, occlusion, FP64
-accumulation), through the C-ABI on torch's current stream.
+accumulation), through the C-ABI on torch's current stream; the library runs
+two batches of passes at a time (that stream and one of its own, each with a
+path pool of four frames) and keeps the framebuffer updates in pass order.
 
 Workload: the seeded 0.97M-triangle grid of spheres and boxes (GGX over
 Lambert, 256 textured emitters), 1920x1080, max depth 12. Inputs are
@@ -13,7 +15,9 @@ resident in HBM before the timed region starts.
 Prints one JSON line: Mrays/s (extension + shadow rays per second) as
 `value`, Mpaths/s, a roofline entry for the dominant kernel (per-launch
 algorithmic bytes over its average launch time, HIP events inside the
-library on the launch stream) and the CPU oracle's rate on a bounded sample.
+library on the launch stream; launches of the two batches in flight share
+the GPU, so the same kernel is also timed on one stream, `isolated`) and the
+CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
@@ -32,10 +36,11 @@ METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "grid": (1, "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
-                "1 spp per step (passes batched four frames per launch sequence), max depth 12, NEE+MIS, roulette"),
+                "1 spp per step (passes batched four frames per launch sequence, two batches in flight), max depth 12, "
+                "NEE+MIS, roulette"),
     "city": (4, "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
-                "selection), 3840x2160, 1 spp per step (two frames per launch sequence), max depth 16, NEE+MIS, "
-                "roulette"),
+                "selection), 3840x2160, 1 spp per step (two frames per launch sequence, two batches in flight), max "
+                "depth 16, NEE+MIS, roulette"),
 }
 GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 8, 2
 
@@ -309,6 +314,8 @@ def main():
     ap.add_argument("--et-oracle-seconds", type=float, default=10.0)
     ap.add_argument("--et-size", type=str, default="1920x1080")
     ap.add_argument("--et-tris", type=int, default=4_000_000)
+    ap.add_argument("--single-stream", action="store_true",
+                    help="render the timed passes one batch at a time on one stream")
     ap.add_argument("--no-light-select", action="store_true",
                     help="skip the alias table vs light tree equal-time leg (city workload only)")
     ap.add_argument("--ls-seconds", type=float, default=2.0, help="wall time of each light-selection run")
@@ -355,7 +362,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    r.render(args.warmup, args.steps)
+    r.render(args.warmup, args.steps, single_stream=args.single_stream)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -377,33 +384,56 @@ def main():
     if not args.no_profile:
         prof = r.ctx.profile_read()
         kernels = {k: {"launches": n, "ms": round(ms, 3)} for k, (n, ms) in prof.items()}
-        dn = st1.nodes_extension - st0.nodes_extension
-        dt_ = st1.tris_extension - st0.tris_extension
-        sn = st1.nodes_shadow - st0.nodes_shadow
-        stt = st1.tris_shadow - st0.tris_shadow
-        byts = {
-            "trace": ext * TRACE_RAY_BYTES + dn * NODE_BYTES + dt_ * TRI_BYTES,
-            "shadow": sh * SHADOW_RAY_BYTES + sn * NODE_BYTES + stt * TRI_BYTES,
-            "shade": ext * SHADE_VERTEX_BYTES + (ext - paths) * SHADE_CONTINUE_BYTES + sh * SHADE_NEE_BYTES,
-        }
+
+        def kernel_bytes(a, b):
+            e, h = b.rays_extension - a.rays_extension, b.rays_shadow - a.rays_shadow
+            dn, dt_ = b.nodes_extension - a.nodes_extension, b.tris_extension - a.tris_extension
+            sn, stt = b.nodes_shadow - a.nodes_shadow, b.tris_shadow - a.tris_shadow
+            byts = {"trace": e * TRACE_RAY_BYTES + dn * NODE_BYTES + dt_ * TRI_BYTES,
+                    "shadow": h * SHADOW_RAY_BYTES + sn * NODE_BYTES + stt * TRI_BYTES,
+                    "shade": e * SHADE_VERTEX_BYTES + (e - (b.paths - a.paths)) * SHADE_CONTINUE_BYTES
+                             + h * SHADE_NEE_BYTES}
+            stream = {"trace": e * TRACE_RAY_BYTES, "shadow": h * SHADOW_RAY_BYTES, "shade": byts["shade"]}
+            counts = {"nodes_per_ray": round(dn / max(e, 1), 2), "tris_per_ray": round(dt_ / max(e, 1), 2),
+                      "shadow_nodes_per_ray": round(sn / max(h, 1), 2), "shadow_tris_per_ray": round(stt / max(h, 1), 2)}
+            return byts, stream, counts
+
+        byts, _, _ = kernel_bytes(st0, st1)
         dom = max(byts, key=lambda k: prof[k][1])
-        n_l, ms = prof[dom]
-        per_launch = byts[dom] / n_l
-        achieved = per_launch / (ms / n_l * 1e-3) / 1e9
-        traffic = pmc_traffic(f"k_{dom}", "grid_1m") if args.workload == "grid" else None
-        stream = {"trace": ext * TRACE_RAY_BYTES, "shadow": sh * SHADOW_RAY_BYTES, "shade": byts["shade"]}[dom]
+        # Per-launch durations are taken on one stream: with two batches in
+        # flight a launch's events also span its wait for the other batch's
+        # kernels. When the timed region ran two batches at a time, the same
+        # number of passes follows on one stream for the roofline.
+        if args.single_stream:
+            r_prof, r0, r1 = prof, st0, st1
+        else:
+            r0 = r.stats()
+            r.ctx.profile(True)
+            r.render(args.warmup + args.steps, args.steps, single_stream=True)
+            r.ctx.profile(False)
+            r_prof = r.ctx.profile_read()
+            r1 = r.stats()
+        rb, rstream, counts = kernel_bytes(r0, r1)
+        n_l, ms = r_prof[dom]
         launch_s = ms / n_l * 1e-3
+        per_launch = rb[dom] / n_l
+        achieved = per_launch / launch_s / 1e9
+        traffic = pmc_traffic(f"k_{dom}", "grid_1m") if args.workload == "grid" else None
         roof = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 # compulsory streaming bytes only (no node or triangle fetches), and the
                 # HBM bytes the counters measured, over the same launch time
-                "frac_stream": round(stream / n_l / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                "frac_stream": round(rstream[dom] / n_l / launch_s / 1e9 / HBM_PEAK_GBS, 4),
                 "frac_measured": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "bytes_per_launch": round(per_launch), "avg_launch_ms": round(ms / n_l, 4),
-                "nodes_per_ray": round(dn / max(ext, 1), 2), "tris_per_ray": round(dt_ / max(ext, 1), 2),
-                "shadow_nodes_per_ray": round(sn / max(sh, 1), 2),
-                "shadow_tris_per_ray": round(stt / max(sh, 1), 2)}
+                "launches": n_l, "timed_on": "one stream, %d passes after the timed region" % args.steps
+                if not args.single_stream else "the timed region (one stream)", **counts}
+        if not args.single_stream:
+            o_l, o_ms = prof[dom]
+            roof["two_batches_in_flight"] = {"launches": o_l, "avg_launch_event_ms": round(o_ms / o_l, 4),
+                                             "note": "event span per launch in the timed region, including "
+                                                     "waits for the other batch's kernels"}
         _say(f"bench: kernels {kernels}")
         _say(f"bench: roofline {roof}")
 
