@@ -77,6 +77,10 @@ def lib():
         L.or_bsdf_sample_batch.argtypes = [P, u32, P, P, P, u32, P, P]
         L.or_debug_path.argtypes = [P, u32, u32, u32, u32, u32, u32, u64, P, P, u32]
         L.or_debug_path.restype = u32
+        L.or_env_pyramid.argtypes = [P, P, P, P, P, P]
+        L.or_env_descend.argtypes = [P, P, P, P, i32, u32, P, P, P]
+        L.or_env_bin.argtypes = [P]
+        L.or_env_bin.restype = u32
         L.or_light_tree.argtypes = [P, P, P, P, P, P, P, P]
         L.or_light_tree.restype = u32
         L.or_light_tree_sample.argtypes = [P, P, P, P, u32, P, P]
@@ -89,6 +93,15 @@ def lib():
         L.or_ggx_D.restype = C.c_double
         _lib = L
     return _lib
+
+
+ENV_BINS = 256  # normal bins of the environment pyramid (16 x 16 octahedral)
+
+
+def env_bin(n) -> int:
+    """Normal bin of an FP32 normal (octahedral map, +y up)."""
+    n = np.ascontiguousarray(n, np.float32)
+    return int(lib().or_env_bin(_p(n)))
 
 
 def _p(a: np.ndarray):
@@ -208,6 +221,33 @@ class Scene:
         L.or_scene_lights(self.h, _p(tri), _p(flux), _p(prob), _p(alias), _p(pmf))
         return dict(tri=tri, flux=flux, prob=prob, alias=alias, pmf=pmf)
 
+    def env_pyramid(self):
+        """The environment pyramid's tables (Sec. 2.1.2; see the C source)."""
+        L = lib()
+        m, top, root = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        L.or_env_pyramid(self.h, C.byref(m), C.byref(top), C.byref(root), None, None)
+        m, top, root = m.value, top.value, root.value
+        if not m:
+            return dict(m=0)
+        q = np.empty(4 * (2 * (4 ** m - 1) // 3), np.uint32)
+        oq = np.empty(ENV_BINS * 4 * (1 + 2 * (4 ** top - 1) // 3), np.uint32)
+        L.or_env_pyramid(self.h, C.byref(C.c_uint32()), C.byref(C.c_uint32()), C.byref(C.c_uint32()), _p(q), _p(oq))
+        return dict(m=m, top=top, root=root, q=q, oq=oq.reshape(ENV_BINS, -1))
+
+    def env_descend(self, bins, u=None, v=None, rows=None, cols=None):
+        """Pyramid descents: with u, v sample; with rows, cols steer to those
+        texels. Returns rows, cols and the final intervals (ru, su, rv, sv)."""
+        bins = np.ascontiguousarray(bins, np.int32)
+        n = bins.shape[0]
+        steer = rows is not None
+        u = np.ascontiguousarray(np.zeros(n) if u is None else u, np.uint32)
+        v = np.ascontiguousarray(np.zeros(n) if v is None else v, np.uint32)
+        r = np.ascontiguousarray(np.zeros(n) if rows is None else rows, np.uint32)
+        c = np.ascontiguousarray(np.zeros(n) if cols is None else cols, np.uint32)
+        iv = np.empty((n, 4), np.uint64)
+        lib().or_env_descend(self.h, _p(bins), _p(u), _p(v), int(steer), n, _p(r), _p(c), _p(iv))
+        return r, c, iv
+
     def light_tree(self):
         """The light tree's tables (Sec. 2.1.1 hierarchy, see the C source)."""
         L = lib()
@@ -266,11 +306,12 @@ class Scene:
         return t, tri
 
     def render(self, pixels=None, pass0=0, npasses=1, max_depth=None, rr=True, mode=0,
-               scramble=True, nthreads=None, light_tree=False):
+               scramble=True, nthreads=None, light_tree=False, env_sampling=0):
         """FP64 sums, sums of squares and counts for the listed pixel ids (y*W+x).
         light_tree selects triangle lights through the light tree instead of
-        the flux alias table."""
-        mode = int(mode) | (0x100 if light_tree else 0)
+        the flux alias table; env_sampling 1 / 2 samples the environment by its
+        pyramid (2: with normal-weighted top levels) instead of the 2D CDF."""
+        mode = int(mode) | (0x100 if light_tree else 0) | (int(env_sampling) << 9)
         sc = self.sc
         if max_depth is None:
             max_depth = sc.max_depth
@@ -323,8 +364,9 @@ class Scene:
         lib().or_bsdf_sample_batch(self.h, m, _p(n), _p(wo), _p(u), u.shape[0], _p(wi), _p(ok))
         return ok.astype(bool), wi
 
-    def debug_path(self, px, py, pass_, max_depth=None, rr=True, mode=0, scramble=True, light_tree=False):
-        mode = int(mode) | (0x100 if light_tree else 0)
+    def debug_path(self, px, py, pass_, max_depth=None, rr=True, mode=0, scramble=True, light_tree=False,
+                   env_sampling=0):
+        mode = int(mode) | (0x100 if light_tree else 0) | (int(env_sampling) << 9)
         L = np.empty(3)
         log = np.zeros(8 * 256)
         n = lib().or_debug_path(self.h, max_depth or self.sc.max_depth, int(rr), mode, int(scramble), px, py,

@@ -281,6 +281,13 @@ typedef struct {
     uint64_t *col_q;        /* eh * (ew + 1) */
     double *env_texel_pdf;  /* solid-angle pdf of each texel under the integer CDFs */
     double p_env;
+    /* environment pyramid (Sec. 2.1.2): finest level m (W = 2^(m+1), H = 2^m;
+     * 0 = no pyramid), split probabilities of every node above the texels,
+     * and per normal bin those of the top levels */
+    uint32_t ep_m, ep_top;
+    uint32_t ep_root;       /* 24-bit probability of the left root (x < W/2) */
+    uint32_t *ep_q;         /* 4 per node of levels 0..m-1: column, row | left column, row | right column, 0 */
+    uint32_t *ep_oq;        /* per normal bin: root, 0, 0, 0, then 4 per node of levels 0..top-1 */
     /* camera */
     v3 eye, fwd, right, up;
     double tan_half, aspect;
@@ -653,6 +660,240 @@ static void build_env(or_scene *s)
     free(cdf);
 }
 
+/* ------------------------------------------------ environment pyramid
+ *
+ * Sec. 2.1.2 samples the environment by descending an image pyramid: its
+ * finest level is the lat-long map with each texel's intensity times its
+ * solid angle, each coarser level sums 2 x 2 nodes, and each step picks one
+ * child by its share. Made definite here: a map of W = 2^(m+1) by H = 2^m
+ * texels has levels k = 0..m of 2^(k+1) x 2^k nodes (level 0: the two
+ * halves of the sphere split at phi = pi). A step first picks the column of
+ * the child (left pair against right pair), then the row within it; both as
+ * 24-bit probabilities. Two 32-bit samples u (columns) and v (rows) are
+ * narrowed as integer intervals, so a texel's probability is exactly the
+ * product of its final interval sizes over 2^64, and the remainders place the
+ * direction inside the texel uniformly in solid angle.
+ *
+ * The paper's normal-aware variant weights the first few levels per
+ * discretised surface normal, conservatively. Here: 16 x 16 bins of an
+ * octahedral map of the normal (+y up), and at levels up to EP_TOP every node
+ * below them of level EP_TOP is weighted by a bound of the cosine between any
+ * normal of the bin and any direction of the node (the angle between the two
+ * bounding cones' axes less both half-angles); deeper levels are shared. */
+#define EP_K 16
+#define EP_TOP 5
+
+static uint32_t ep_nodes_above(uint32_t k) { return (uint32_t)((2ull * ((1ull << (2 * k)) - 1)) / 3); }
+
+static uint32_t ep_quant(double l, double r)
+{
+    if (!(l + r > 0.0)) return 1u << 23;
+    double q = nearbyint(l / (l + r) * 16777216.0);
+    if (l > 0.0 && q < 1.0) q = 1.0;
+    if (r > 0.0 && q > 16777215.0) q = 16777215.0;
+    return (uint32_t)q;
+}
+
+static v3 ep_dir(double th, double ph) { return V3(sin(th) * sin(ph), cos(th), -sin(th) * cos(ph)); }
+
+static double ep_angle(v3 a, v3 b) { return acos(fmax(-1.0, fmin(1.0, dot(a, b)))); }
+
+/* octahedral square (px, pz) in [-1, 1]^2 -> unit normal, +y up */
+static v3 ep_oct_decode(double px, double pz)
+{
+    double y = 1.0 - fabs(px) - fabs(pz);
+    if (y < 0.0) {
+        double fx = (1.0 - fabs(pz)) * (px >= 0.0 ? 1.0 : -1.0);
+        double fz = (1.0 - fabs(px)) * (pz >= 0.0 ? 1.0 : -1.0);
+        px = fx;
+        pz = fz;
+    }
+    return normalize(V3(px, y, pz));
+}
+
+/* normal bin of an FP32 normal, in FP32 */
+static uint32_t ep_bin(const float *n)
+{
+    float a = (fabsf(n[0]) + fabsf(n[1])) + fabsf(n[2]);
+    float px = n[0] / a, pz = n[2] / a;
+    if (n[1] < 0.0f) {
+        float fx = (1.0f - fabsf(pz)) * (px >= 0.0f ? 1.0f : -1.0f);
+        float fz = (1.0f - fabsf(px)) * (pz >= 0.0f ? 1.0f : -1.0f);
+        px = fx;
+        pz = fz;
+    }
+    int i = (int)floorf((px + 1.0f) * (0.5f * EP_K)), j = (int)floorf((pz + 1.0f) * (0.5f * EP_K));
+    i = i < 0 ? 0 : (i > EP_K - 1 ? EP_K - 1 : i);
+    j = j < 0 ? 0 : (j > EP_K - 1 ? EP_K - 1 : j);
+    return (uint32_t)(j * EP_K + i);
+}
+
+/* split probabilities of levels 0..levels-1 from level-`levels` weights wl
+ * (row-major, 2^(levels+1) x 2^levels); out: root q, then 4 per node */
+static void ep_splits(const double *wl, uint32_t levels, uint32_t *root, uint32_t *q)
+{
+    const double *cur = wl;
+    double *own = NULL;
+    for (int k = (int)levels - 1; k >= 0; --k) {
+        uint32_t cw = 2u << k, ch = 1u << k, fw = 2 * cw;
+        double *up = (double *)malloc(sizeof(double) * cw * ch);
+        for (uint32_t y = 0; y < ch; ++y)
+            for (uint32_t x = 0; x < cw; ++x) {
+                double a = cur[(size_t)(2 * y) * fw + 2 * x], b = cur[(size_t)(2 * y) * fw + 2 * x + 1];
+                double c = cur[(size_t)(2 * y + 1) * fw + 2 * x], d = cur[(size_t)(2 * y + 1) * fw + 2 * x + 1];
+                uint32_t *o = q + 4 * ((size_t)ep_nodes_above((uint32_t)k) + (size_t)y * cw + x);
+                o[0] = ep_quant(a + c, b + d);
+                o[1] = ep_quant(a, c);
+                o[2] = ep_quant(b, d);
+                o[3] = 0;
+                up[(size_t)y * cw + x] = ((a + b) + c) + d;
+            }
+        free(own);
+        own = up;
+        cur = up;
+    }
+    *root = ep_quant(cur[0], cur[1]);
+    free(own);
+}
+
+static void build_env_pyramid(or_scene *s)
+{
+    uint32_t W = s->ew, H = s->eh, m = 0;
+    while ((1u << m) < H) ++m;
+    if (H != (1u << m) || W != 2 * H || m < 1) return;  /* lat-long 2:1 powers of two only */
+    s->ep_m = m;
+    s->ep_top = m < EP_TOP ? m : EP_TOP;
+    double *w = (double *)malloc(sizeof(double) * (size_t)W * H);
+    for (uint32_t r = 0; r < H; ++r) {
+        double om = (2.0 * M_PI / W) * (cos(M_PI * r / H) - cos(M_PI * (r + 1) / H));
+        for (uint32_t c = 0; c < W; ++c) w[(size_t)r * W + c] = lum(s->env[(size_t)r * W + c]) * om;
+    }
+    s->ep_q = (uint32_t *)calloc(4 * (size_t)ep_nodes_above(m), sizeof(uint32_t));
+    ep_splits(w, m, &s->ep_root, s->ep_q);
+    /* level-top weights (sums of the texels below each node, same order) */
+    uint32_t t = s->ep_top, tw = 2u << t, th = 1u << t, sh = m - t;
+    double *wt = (double *)malloc(sizeof(double) * tw * th);
+    {
+        double *cur = w, *own = NULL;
+        for (uint32_t k = m; k > t; --k) {
+            uint32_t cw = 1u << k, ch = 1u << (k - 1), fw = 2 * cw;
+            double *up = (double *)malloc(sizeof(double) * cw * ch);
+            for (uint32_t y = 0; y < ch; ++y)
+                for (uint32_t x = 0; x < cw; ++x) {
+                    double a = cur[(size_t)(2 * y) * fw + 2 * x], b = cur[(size_t)(2 * y) * fw + 2 * x + 1];
+                    double c = cur[(size_t)(2 * y + 1) * fw + 2 * x], d = cur[(size_t)(2 * y + 1) * fw + 2 * x + 1];
+                    up[(size_t)y * cw + x] = ((a + b) + c) + d;
+                }
+            free(own);
+            own = up;
+            cur = up;
+        }
+        memcpy(wt, cur, sizeof(double) * tw * th);
+        free(own);
+    }
+    (void)sh;
+    /* bounding cones of the level-top cells and of the normal bins */
+    v3 *rc = (v3 *)malloc(sizeof(v3) * tw * th);
+    double *rd = (double *)malloc(sizeof(double) * tw * th);
+    for (uint32_t y = 0; y < th; ++y)
+        for (uint32_t x = 0; x < tw; ++x) {
+            double t0 = M_PI * y / th, t1 = M_PI * (y + 1) / th;
+            double p0 = 2.0 * M_PI * x / tw, p1 = 2.0 * M_PI * (x + 1) / tw;
+            v3 c = ep_dir(0.5 * (t0 + t1), 0.5 * (p0 + p1));
+            double d = fmax(fmax(ep_angle(c, ep_dir(t0, p0)), ep_angle(c, ep_dir(t0, p1))),
+                            fmax(ep_angle(c, ep_dir(t1, p0)), ep_angle(c, ep_dir(t1, p1))));
+            rc[(size_t)y * tw + x] = c;
+            rd[(size_t)y * tw + x] = d + 0.01;
+        }
+    uint32_t per = 4 * (1 + ep_nodes_above(t));
+    s->ep_oq = (uint32_t *)calloc((size_t)EP_K * EP_K * per, sizeof(uint32_t));
+    double *sw = (double *)malloc(sizeof(double) * tw * th);
+    const double cell = 2.0 / EP_K;
+    for (uint32_t b = 0; b < EP_K * EP_K; ++b) {
+        uint32_t i = b % EP_K, j = b / EP_K;
+        double x0 = -1.0 + cell * i, z0 = -1.0 + cell * j;
+        v3 bc = ep_oct_decode(x0 + 0.5 * cell, z0 + 0.5 * cell);
+        double g = 0.0;
+        for (int e = 0; e <= 16; ++e) {
+            double f = e / 16.0;
+            g = fmax(g, ep_angle(bc, ep_oct_decode(x0 + f * cell, z0)));
+            g = fmax(g, ep_angle(bc, ep_oct_decode(x0 + f * cell, z0 + cell)));
+            g = fmax(g, ep_angle(bc, ep_oct_decode(x0, z0 + f * cell)));
+            g = fmax(g, ep_angle(bc, ep_oct_decode(x0 + cell, z0 + f * cell)));
+        }
+        g += 0.02;
+        for (uint32_t q = 0; q < tw * th; ++q) {
+            double ang = ep_angle(bc, rc[q]) - g - rd[q];
+            double f = ang <= 0.0 ? 1.0 : (ang >= 0.5 * M_PI ? 0.0 : cos(ang));
+            sw[q] = wt[q] * f;
+        }
+        uint32_t *o = s->ep_oq + (size_t)b * per;
+        ep_splits(sw, t, &o[0], o + 4);
+    }
+    free(sw);
+    free(rc);
+    free(rd);
+    free(wt);
+    free(w);
+}
+
+static uint64_t ep_split(uint64_t R, uint32_t q)
+{
+    if (q == 0) return 0;
+    if (q >= (1u << 24)) return R;
+    uint64_t T = (R >> 24) * q + (((R & 0xFFFFFFull) * q) >> 24);
+    if (R >= 2) {
+        if (T < 1) T = 1;
+        if (T > R - 1) T = R - 1;
+    }
+    return T;
+}
+
+/* the split probabilities used at a node of level k for normal bin `bin`
+ * (-1: the shared, unoriented ones) */
+static const uint32_t *ep_node_q(const or_scene *s, int bin, uint32_t k, uint32_t y, uint32_t x)
+{
+    size_t at = (size_t)ep_nodes_above(k) + (size_t)y * (2u << k) + x;
+    if (bin >= 0 && k < s->ep_top) return s->ep_oq + (size_t)bin * 4 * (1 + ep_nodes_above(s->ep_top)) + 4 + 4 * at;
+    return s->ep_q + 4 * at;
+}
+
+static uint32_t ep_root_q(const or_scene *s, int bin)
+{
+    return bin >= 0 ? s->ep_oq[(size_t)bin * 4 * (1 + ep_nodes_above(s->ep_top))] : s->ep_root;
+}
+
+/* Descend with samples (u, v): texel (row, col) and the final intervals.
+ * With `steer`, follow the given texel instead (u, v ignored). */
+static void ep_descend(const or_scene *s, int bin, uint32_t u, uint32_t v, int steer, uint32_t *row,
+                       uint32_t *col, uint64_t *Ru, uint64_t *Su, uint64_t *Rv, uint64_t *Sv)
+{
+    uint32_t m = s->ep_m;
+    uint64_t ru = 1ull << 32, su = u, rv = 1ull << 32, sv = v;
+    uint32_t x, y = 0;
+    uint64_t T = ep_split(ru, ep_root_q(s, bin));
+    int right = steer ? (int)((*col >> m) & 1u) : (su >= T);
+    if (right) { su -= T; ru -= T; } else ru = T;
+    x = (uint32_t)right;
+    for (uint32_t k = 0; k < m; ++k) {
+        const uint32_t *q = ep_node_q(s, bin, k, y, x);
+        T = ep_split(ru, q[0]);
+        int cx = steer ? (int)((*col >> (m - 1 - k)) & 1u) : (su >= T);
+        if (cx) { su -= T; ru -= T; } else ru = T;
+        T = ep_split(rv, cx ? q[2] : q[1]);
+        int cy = steer ? (int)((*row >> (m - 1 - k)) & 1u) : (sv >= T);
+        if (cy) { sv -= T; rv -= T; } else rv = T;
+        x = 2 * x + (uint32_t)cx;
+        y = 2 * y + (uint32_t)cy;
+    }
+    *row = y;
+    *col = x;
+    *Ru = ru;
+    *Su = su;
+    *Rv = rv;
+    *Sv = sv;
+}
+
 /* ----------------------------------------------------------- FP64 BVH */
 
 static void tri_bounds(const or_scene *s, uint32_t t, v3 *lo, v3 *hi)
@@ -853,6 +1094,7 @@ or_scene *or_scene_create(uint32_t nv, const float *pos, uint32_t nt, const uint
         for (size_t q = 0; q < (size_t)ew * eh; ++q)
             s->env[q] = V3(env[3 * q], env[3 * q + 1], env[3 * q + 2]);
         build_env(s);
+        build_env_pyramid(s);
     }
     s->p_env = s->env ? (s->ne ? 0.5 : 1.0) : 0.0;
     build_light_pmf(s);
@@ -885,6 +1127,7 @@ void or_scene_destroy(or_scene *s)
     free(s->lt_c); free(s->lt_f); free(s->lt_left); free(s->lt_first); free(s->lt_count);
     free(s->lt_emit); free(s->lt_pos); free(s->lt_w);
     free(s->env); free(s->row_q); free(s->col_q); free(s->env_texel_pdf);
+    free(s->ep_q); free(s->ep_oq);
     free(s->nodes); free(s->order);
     free(s);
 }
@@ -1028,8 +1271,8 @@ static int bsdf_sample(const or_scene *s, uint32_t m, v3 n, v3 wo, double u3, do
     return dot(n, *wi) > 0.0;
 }
 
-/* environment radiance and texel pdf for a direction */
-static v3 env_lookup(const or_scene *s, v3 w, double *pdf)
+/* environment radiance and texel pdf for a direction (and its texel) */
+static v3 env_lookup_texel(const or_scene *s, v3 w, double *pdf, uint32_t *row, uint32_t *col)
 {
     double th = acos(fmax(-1.0, fmin(1.0, w.y)));
     double ph = atan2(w.x, -w.z);
@@ -1041,7 +1284,16 @@ static v3 env_lookup(const or_scene *s, v3 w, double *pdf)
     if (c >= s->ew) c = s->ew - 1;
     size_t q = (size_t)r * s->ew + c;
     if (pdf) *pdf = s->env_texel_pdf[q];
+    if (row) *row = (uint32_t)r;
+    if (col) *col = (uint32_t)c;
     return s->env[q];
+}
+static v3 env_lookup(const or_scene *s, v3 w, double *pdf) { return env_lookup_texel(s, w, pdf, NULL, NULL); }
+
+/* solid angle of a texel of row r */
+static double env_texel_omega(const or_scene *s, uint32_t r)
+{
+    return (2.0 * M_PI / s->ew) * (cos(M_PI * r / s->eh) - cos(M_PI * (r + 1) / s->eh));
 }
 
 /* Wachter-Binder origin offset (reading of Sec. 2.2's front/back-side
@@ -1070,12 +1322,14 @@ typedef struct {
     uint32_t mode;      /* 0 MIS, 1 BSDF sampling only, 2 NEE only */
     uint32_t scramble;
     uint32_t light_tree; /* select triangle lights through the light tree */
+    uint32_t env_pyramid; /* 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels */
 } or_opts;
 
-/* the caller's mode word: MIS mode in the low byte, light tree in bit 8 */
+/* the caller's mode word: MIS mode in the low byte, light tree in bit 8,
+ * environment sampling in bits 9-10 */
 static or_opts make_opts(uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble)
 {
-    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u};
+    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u, (mode >> 9) & 3u};
     return op;
 }
 
@@ -1107,6 +1361,7 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
     double prev_pdf = 0.0;
     v3 prev_n = V3(0, 0, 0);
     const int tree = op->light_tree && s->ne;
+    const int pyr = op->env_pyramid && s->ep_m;
     const double p_tri = 1.0 - s->p_env;
     for (uint32_t v = 1; v <= op->max_depth; ++v) {
         hit64 h;
@@ -1114,8 +1369,18 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
         if (!trace64(s, o, d, INFINITY, 0, 0, &h)) {
             if (s->env && (v == 1 || op->mode != 2)) {
                 double pe;
-                v3 Le = env_lookup(s, d, &pe);
+                uint32_t er, ec;
+                v3 Le = env_lookup_texel(s, d, &pe, &er, &ec);
                 double w = 1.0;
+                if (v > 1 && op->mode == 0 && pyr) {
+                    /* the pyramid's probability of this texel from the previous vertex */
+                    float nf[3] = {(float)prev_n.x, (float)prev_n.y, (float)prev_n.z};
+                    int bin = op->env_pyramid == 2 ? (int)ep_bin(nf) : -1;
+                    uint64_t ru, su, rv, sv;
+                    ep_descend(s, bin, 0, 0, 1, &er, &ec, &ru, &su, &rv, &sv);
+                    pe = (double)ru * (double)rv * 0x1p-64 / env_texel_omega(s, er);
+                    logv(5, v, er, ec, pe, 0, 0, 0);
+                }
                 if (v > 1 && op->mode == 0) w = mis2(prev_pdf, s->p_env * pe);
                 L = add(L, mul(vmul(T, Le), w));
             }
@@ -1173,13 +1438,25 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
             if (use_env) {
                 uint32_t s1 = or_sample_bits(i, base + 1, W, H, op->scramble);
                 uint32_t s2 = or_sample_bits(i, base + 2, W, H, op->scramble);
-                uint32_t row = 0;
-                while (row + 1 < s->eh && s->row_q[row + 1] <= s1) ++row;
-                const uint64_t *cq = s->col_q + (size_t)row * (s->ew + 1);
-                uint32_t col = 0;
-                while (col + 1 < s->ew && cq[col + 1] <= s2) ++col;
-                double fyr = (double)(s1 - s->row_q[row]) / (double)(s->row_q[row + 1] - s->row_q[row]);
-                double fxc = (double)(s2 - cq[col]) / (double)(cq[col + 1] - cq[col]);
+                uint32_t row = 0, col = 0;
+                double fyr, fxc, pt;
+                if (pyr) {
+                    /* pyramid: slot 2 narrows columns, slot 1 rows */
+                    float nf[3] = {(float)n.x, (float)n.y, (float)n.z};
+                    int bin = op->env_pyramid == 2 ? (int)ep_bin(nf) : -1;
+                    uint64_t ru, su, rv, sv;
+                    ep_descend(s, bin, s2, s1, 0, &row, &col, &ru, &su, &rv, &sv);
+                    fxc = (double)su / (double)ru;
+                    fyr = (double)sv / (double)rv;
+                    pt = (double)ru * (double)rv * 0x1p-64 / env_texel_omega(s, row);
+                } else {
+                    while (row + 1 < s->eh && s->row_q[row + 1] <= s1) ++row;
+                    const uint64_t *cq = s->col_q + (size_t)row * (s->ew + 1);
+                    while (col + 1 < s->ew && cq[col + 1] <= s2) ++col;
+                    fyr = (double)(s1 - s->row_q[row]) / (double)(s->row_q[row + 1] - s->row_q[row]);
+                    fxc = (double)(s2 - cq[col]) / (double)(cq[col + 1] - cq[col]);
+                    pt = s->env_texel_pdf[(size_t)row * s->ew + col];
+                }
                 double ct = cos(M_PI * row / s->eh), cb = cos(M_PI * (row + 1) / s->eh);
                 double cth = ct + fyr * (cb - ct);
                 double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
@@ -1187,7 +1464,7 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
                 wi = V3(sth * sin(ph), cth, -sth * cos(ph));
                 size_t q = (size_t)row * s->ew + col;
                 Le = s->env[q];
-                pl = s->p_env * s->env_texel_pdf[q];
+                pl = s->p_env * pt;
                 ok = pl > 0.0;
             } else {
                 uint32_t s7 = or_sample_bits(i, base + 7, W, H, op->scramble);
@@ -1354,7 +1631,8 @@ uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t 
 
 /* one path with a per-vertex log: records of 8 doubles,
  * (1, v, tri, t, x) (2, ray o, ray d) (3, occluded, contrib, pl, w)
- * (4, v, tri, selection probability, pl, w) at an emitter hit under MIS */
+ * (4, v, tri, selection probability, pl, w) at an emitter hit under MIS
+ * (5, v, row, col, texel pdf) at an environment hit under MIS with the pyramid */
 uint32_t or_debug_path(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble,
                        uint32_t px, uint32_t py, uint64_t pass, double *L_out, double *log, uint32_t cap)
 {
@@ -1402,6 +1680,32 @@ void or_light_tree_sizes(const or_scene *s, const float *x, const float *nrm, ui
 {
     for (uint32_t e = 0; e < s->ne; ++e) size_out[e] = lt_size_of(s, e, x, nrm);
 }
+
+/* The environment pyramid's tables: *m finest level (0: none), *top levels
+ * weighted per normal bin, *root; q (4 per node of levels 0..m-1) and oq
+ * (per bin: root, 0, 0, 0, then 4 per node of levels 0..top-1) if not NULL. */
+void or_env_pyramid(const or_scene *s, uint32_t *m, uint32_t *top, uint32_t *root, uint32_t *q, uint32_t *oq)
+{
+    *m = s->ep_m;
+    *top = s->ep_top;
+    *root = s->ep_root;
+    if (!s->ep_m) return;
+    if (q) memcpy(q, s->ep_q, sizeof(uint32_t) * 4 * ep_nodes_above(s->ep_m));
+    if (oq) memcpy(oq, s->ep_oq, sizeof(uint32_t) * (size_t)EP_K * EP_K * 4 * (1 + ep_nodes_above(s->ep_top)));
+}
+
+/* n descents: bin[k] (-1 unoriented), samples u[k] (columns), v[k] (rows);
+ * steer != 0 follows texel (row[k], col[k]) instead. Out: row, col and the
+ * final intervals ru, su, rv, sv (4 per query). */
+void or_env_descend(const or_scene *s, const int32_t *bin, const uint32_t *u, const uint32_t *v, int steer,
+                    uint32_t n, uint32_t *row, uint32_t *col, uint64_t *iv)
+{
+    for (uint32_t k = 0; k < n; ++k)
+        ep_descend(s, bin[k], u[k], v[k], steer, row + k, col + k, iv + 4 * k, iv + 4 * k + 1, iv + 4 * k + 2,
+                   iv + 4 * k + 3);
+}
+
+uint32_t or_env_bin(const float *n) { return ep_bin(n); }
 
 /* the node estimate and the left-child probability, for pins */
 float or_light_tree_estimate(const or_scene *s, uint32_t node, const float *x, const float *nrm)
