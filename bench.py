@@ -298,6 +298,72 @@ def light_select_equal_time(r, sc, seconds: float, ref_passes: int):
     return out
 
 
+def env_select_equal_time(seconds: float, ref_passes: int, width: int, height: int, tris: int):
+    """Equal-time RMSE of the three environment samplers: the 2D CDF, the
+    texel pyramid, and the pyramid with normal-weighted top levels (Sec.
+    2.1.2), on the sun-and-sky scene (open) and on the slit enclosure (the sky
+    reaches the inside through a slit). Reference: the 2D CDF and the
+    weighted pyramid at `ref_passes` passes each from pass 2^24, averaged.
+    Each sampler renders as many passes as fit in `seconds` (measured per
+    pass first, rounded down to whole four-pass batches)."""
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_1705_01263_amd import Renderer
+
+    lum = np.array([0.2126, 0.7152, 0.0722])
+    out = []
+    for name, make in (("sun and sky, open", lambda: scenegen.instanced_env_scene(width=width, height=height,
+                                                                                    target_tris=tris)),
+                       ("slit enclosure", lambda: scenegen.slit_scene(width=width, height=height, target_tris=tris,
+                                                                      max_depth=16))):
+        sc = make()
+        _say(f"bench: environment samplers on {sc.name} tris={sc.num_triangles} {width}x{height}")
+        r = Renderer(sc, device=0)
+        ref = np.zeros((width * height, 3))
+        t0 = time.perf_counter()
+        for es in (0, 2):
+            r.reset()
+            r.render(1 << 24, ref_passes, env_sampling=es)
+            s, c = r.readback()
+            ref += 0.5 * s / c[:, None]
+        res = {"scene": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth {sc.max_depth}, "
+                        "2048x1024 sun (peak 5e4, 0.5 degrees) and sky",
+               "reference": {"passes_each": ref_passes, "first_pass": 1 << 24,
+                             "seconds": round(time.perf_counter() - t0, 2)}}
+        lit = ref @ lum > 0
+        for label, es in (("cdf_2d", 0), ("pyramid", 1), ("pyramid_normal_weighted", 2)):
+            r.reset()
+            r.render(1 << 26, 4, env_sampling=es)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r.render(1 << 26, 16, env_sampling=es)
+            torch.cuda.synchronize()
+            per = (time.perf_counter() - t1) / 16
+            n = max(4, int(seconds / per) // 4 * 4)
+            r.reset()
+            st0 = r.stats()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r.render(0, n, env_sampling=es)
+            s, c = r.readback()
+            dt = time.perf_counter() - t1
+            st1 = r.stats()
+            e = s / c[:, None] - ref
+            res[label] = {"passes": n, "seconds": round(dt, 3), "ms_per_pass": round(dt * 1e3 / n, 3),
+                          "shadow_rays_per_path": round((st1.rays_shadow - st0.rays_shadow) / (st1.paths - st0.paths), 3),
+                          "rmse": float(np.sqrt(np.mean(e ** 2))),
+                          "rel_rmse_lit": float(np.sqrt(np.mean(((e @ lum)[lit] / np.maximum((ref @ lum)[lit], 1e-3)) ** 2)))}
+            _say(f"bench: {name} {label}: {n} passes in {dt:.2f} s, rmse {res[label]['rmse']:.6f}")
+        for label in ("pyramid", "pyramid_normal_weighted"):
+            res[f"{label}_over_cdf_rmse"] = round(res[label]["rmse"] / res["cdf_2d"]["rmse"], 4)
+        out.append(res)
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +386,10 @@ def main():
                     help="skip the alias table vs light tree equal-time leg (city workload only)")
     ap.add_argument("--ls-seconds", type=float, default=2.0, help="wall time of each light-selection run")
     ap.add_argument("--ls-ref-passes", type=int, default=512, help="reference passes per selector")
+    ap.add_argument("--env-select", action="store_true",
+                    help="also compare the environment samplers at equal time (sun-and-sky and slit scenes)")
+    ap.add_argument("--es-seconds", type=float, default=1.0)
+    ap.add_argument("--es-ref-passes", type=int, default=2048)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -448,9 +518,17 @@ def main():
         ls = light_select_equal_time(r, sc, args.ls_seconds, args.ls_ref_passes)
         _say(f"bench: light selection {ls}")
 
+    es_out = None
+    if args.env_select:
+        r = None
+        torch.cuda.empty_cache()
+        w, h = (int(v) for v in args.et_size.split("x"))
+        es_out = env_select_equal_time(args.es_seconds, args.es_ref_passes, w, h, args.et_tris)
+        _say(f"bench: environment samplers {es_out}")
+
     et = None
     if not args.no_equal_time:
-        del r
+        r = None
         torch.cuda.empty_cache()
         w, h = (int(v) for v in args.et_size.split("x"))
         et = equal_time(args.et_seconds, args.et_ref_passes, args.et_oracle_seconds, w, h, args.et_tris)
@@ -469,6 +547,7 @@ def main():
         "cpu_baseline": cpu,
         "equal_time_rmse": et,
         "light_selection_equal_time": ls,
+        "env_sampling_equal_time": es_out,
         "kernels": kernels,
     }
     print(json.dumps(out), flush=True)

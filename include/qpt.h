@@ -110,6 +110,11 @@ typedef struct {
                                 batch's deep vertices overlap the next batch's first ones; guided
                                 rendering always uses one stream. 1: one batch after another on the
                                 caller's stream. The image is the same bit for bit. */
+    uint32_t env_sampling;   /* environment NEE (Sec. 2.1.2): 0: 2D CDF over the texels; 1: descent
+                                of the texel pyramid; 2: the pyramid with its top levels weighted
+                                per surface-normal bin (16 x 16 octahedral cells, cosine bound over
+                                the bin and the cell). 1 and 2 need a 2:1 map of power-of-two size
+                                (QPT_E_INVALID otherwise); ignored without an environment. */
 } qpt_render_opts;
 
 typedef struct {
@@ -308,6 +313,31 @@ int qpt_debug_light_tables(const qpt_ctx *ctx, uint32_t *emit_tri, double *prob,
  * pointers may be NULL. Host memory. After qpt_build_scene. */
 int qpt_debug_light_tree(const qpt_ctx *ctx, float *sphere4, float *flux6, int32_t *left, uint32_t *first,
                          uint32_t *count, uint32_t *emit, uint32_t *weight, uint32_t *num_nodes);
+
+/* The environment pyramid built with the scene (2:1 power-of-two maps, see
+ * qpt_render_opts.env_sampling): *levels = m (W = 2^(m+1), H = 2^m; 0 = none),
+ * *top = levels weighted per normal bin (min(m, 5)), *root = 24-bit share of
+ * the left half (phi < pi). q: 4 words per node of levels 0..m-1 (level k has
+ * 2^(k+1) x 2^k nodes, row-major, after the 2 (4^k - 1) / 3 nodes above):
+ * 24-bit share of the left child column, of the upper row within the left
+ * column, within the right column, 0. Intensity x solid angle; a child
+ * without weight gets share 0 (or 2^24 for the other). oq: per normal bin
+ * b = 16 j + i (octahedral cell i along x, j along z), 4 (1 + nodes above
+ * level top) words: (root share, 0, 0, 0) then the nodes of levels
+ * 0..top-1 with cosine-weighted shares. Host memory; q and oq may be NULL.
+ * After qpt_build_scene. */
+int qpt_debug_env_pyramid(const qpt_ctx *ctx, uint32_t *levels, uint32_t *top, uint32_t *root, uint32_t *q,
+                          uint32_t *oq);
+
+/* The renderer's pyramid descent for n queries (DEVICE pointers): uv[2n]
+ * (u narrows columns, v rows), nrm[3n] FP32 normals (their bin is used when
+ * mode = 2; mode = 1 ignores them). Writes texel[n] = row W + col, iv[4n] =
+ * (column interval size, offset in it, row interval size, offset) and
+ * iv_hit[2n] = the two sizes the descent steered to that texel finds (what
+ * an environment hit's MIS weight uses; equal to the sampled ones).
+ * QPT_E_STATE before qpt_bind_workspace or without a pyramid. */
+int qpt_debug_env_sample(qpt_ctx *ctx, const uint32_t *uv, const float *nrm, uint32_t n, uint32_t mode,
+                         uint32_t *texel, uint64_t *iv, uint64_t *iv_hit);
 
 /* The renderer's light-tree choice for n queries (DEVICE pointers): 63-bit
  * samples S[n] (bit 63 ignored), FP32 shading points x[3n] and unit normals

@@ -266,7 +266,7 @@ struct Builder {
 
 struct Layout {
     size_t nodes, tris, mats, emit_tri, alias_idx, alias_thr, emit_pmf, lt_nodes, lt_emit, lt_pos, lt_w,
-        env_texel, env_row,
+        ep_q, ep_oq, env_texel, env_row,
         env_col, env_cos, bases;
     // per batch lane (two batches in flight): path state, queues, shadow rays, counters, stack
     struct Lane {
@@ -370,6 +370,10 @@ struct qpt_ctx {
     std::vector<uint32_t> env_row, env_col;
     std::vector<float4> env_texel;
     std::vector<float> env_cos;
+    // environment pyramid: finest level (0 = none), normal-weighted levels,
+    // left-root probability, 4 words per node (shared; then per normal bin)
+    uint32_t ep_m = 0, ep_top = 0, ep_root = 0;
+    std::vector<uint32_t> ep_q, ep_oq;
     // Halton + enumeration
     std::vector<HaltonBase> bases;
     Frame frame{};
@@ -650,6 +654,152 @@ void build_light_pmf(qpt_ctx *c)
     }
 }
 
+// ------------------------------------------------- environment pyramid
+//
+// Hierarchical sampling of the lat-long map (Sec. 2.1.2). Level m holds the
+// texels' intensity x solid angle (W = 2^(m+1), H = 2^m), level k < m the
+// sums ((a + b) + c) + d of its 2 x 2 children (a, b the upper row, left
+// first); a node's split is its children's column share, then the row share
+// within the chosen column, each a 24-bit probability. Per normal bin (16 x 16
+// octahedral cells, +y up) the levels above kEpTop use weights of the
+// level-kEpTop cells scaled by a bound of the cosine between any normal of
+// the bin and any direction of the cell, from bounding cones of both.
+constexpr uint32_t kEpBins = 16, kEpTop = 5;
+
+uint32_t ep_nodes_above(uint32_t k) { return (uint32_t)((2ull * ((1ull << (2 * k)) - 1)) / 3); }
+
+uint32_t ep_share(double l, double r)
+{
+    if (!(l + r > 0.0)) return 1u << 23;
+    double q = std::nearbyint(l / (l + r) * 16777216.0);
+    if (l > 0.0 && q < 1.0) q = 1.0;
+    if (r > 0.0 && q > 16777215.0) q = 16777215.0;
+    return (uint32_t)q;
+}
+
+// splits of levels 0..top-1 from the weights of level `top` (2^(top+1) x 2^top, row-major)
+void ep_fill_splits(const std::vector<double> &level_top, uint32_t top, uint32_t &root, uint32_t *q)
+{
+    std::vector<double> fine = level_top, coarse;
+    for (uint32_t k = top; k-- > 0;) {
+        const uint32_t w = 2u << k, h = 1u << k, fw = 2 * w;
+        coarse.assign((size_t)w * h, 0.0);
+        for (uint32_t y = 0; y < h; ++y)
+            for (uint32_t x = 0; x < w; ++x) {
+                const double a = fine[(size_t)(2 * y) * fw + 2 * x], b = fine[(size_t)(2 * y) * fw + 2 * x + 1];
+                const double cc = fine[(size_t)(2 * y + 1) * fw + 2 * x];
+                const double d = fine[(size_t)(2 * y + 1) * fw + 2 * x + 1];
+                uint32_t *o = q + 4 * ((size_t)ep_nodes_above(k) + (size_t)y * w + x);
+                o[0] = ep_share(a + cc, b + d);
+                o[1] = ep_share(a, cc);
+                o[2] = ep_share(b, d);
+                o[3] = 0;
+                coarse[(size_t)y * w + x] = ((a + b) + cc) + d;
+            }
+        fine.swap(coarse);
+    }
+    root = ep_share(fine[0], fine[1]);
+}
+
+Vec3 ep_direction(double theta, double phi)
+{
+    return {std::sin(theta) * std::sin(phi), std::cos(theta), -std::sin(theta) * std::cos(phi)};
+}
+
+double ep_angle(Vec3 a, Vec3 b)
+{
+    double d = a.x * b.x + a.y * b.y + a.z * b.z;
+    return std::acos(std::max(-1.0, std::min(1.0, d)));
+}
+
+Vec3 ep_from_octahedral(double px, double pz)
+{
+    double y = 1.0 - std::fabs(px) - std::fabs(pz);
+    if (y < 0.0) {
+        const double fx = (1.0 - std::fabs(pz)) * (px >= 0.0 ? 1.0 : -1.0);
+        const double fz = (1.0 - std::fabs(px)) * (pz >= 0.0 ? 1.0 : -1.0);
+        px = fx;
+        pz = fz;
+    }
+    Vec3 n{px, y, pz};
+    return vscale(n, 1.0 / vlen(n));
+}
+
+void build_env_pyramid(qpt_ctx *c)
+{
+    c->ep_m = c->ep_top = c->ep_root = 0;
+    c->ep_q.clear();
+    c->ep_oq.clear();
+    const uint32_t W = c->ew, H = c->eh;
+    uint32_t m = 0;
+    while ((1u << m) < H) ++m;
+    if (m < 1 || H != (1u << m) || W != 2 * H) return;
+    const uint32_t top = std::min(m, kEpTop);
+    // texel weights, then sums down to level `top`
+    std::vector<double> lvl((size_t)W * H);
+    for (uint32_t r = 0; r < H; ++r) {
+        const double om = (2.0 * kPi / W) * (std::cos(kPi * r / H) - std::cos(kPi * (r + 1) / H));
+        for (uint32_t x = 0; x < W; ++x) {
+            const float *L = &c->env[3 * ((size_t)r * W + x)];
+            lvl[(size_t)r * W + x] = luminance(L[0], L[1], L[2]) * om;
+        }
+    }
+    c->ep_q.assign(4 * (size_t)ep_nodes_above(m), 0);
+    ep_fill_splits(lvl, m, c->ep_root, c->ep_q.data());
+    for (uint32_t k = m; k > top; --k) {
+        const uint32_t w = 1u << k, h = 1u << (k - 1), fw = 2 * w;
+        std::vector<double> up((size_t)w * h);
+        for (uint32_t y = 0; y < h; ++y)
+            for (uint32_t x = 0; x < w; ++x) {
+                const double a = lvl[(size_t)(2 * y) * fw + 2 * x], b = lvl[(size_t)(2 * y) * fw + 2 * x + 1];
+                const double cc = lvl[(size_t)(2 * y + 1) * fw + 2 * x];
+                const double d = lvl[(size_t)(2 * y + 1) * fw + 2 * x + 1];
+                up[(size_t)y * w + x] = ((a + b) + cc) + d;
+            }
+        lvl.swap(up);
+    }
+    // bounding cones of the level-`top` cells
+    const uint32_t tw = 2u << top, th = 1u << top;
+    std::vector<Vec3> cell_axis((size_t)tw * th);
+    std::vector<double> cell_half((size_t)tw * th);
+    for (uint32_t y = 0; y < th; ++y)
+        for (uint32_t x = 0; x < tw; ++x) {
+            const double t0 = kPi * y / th, t1 = kPi * (y + 1) / th;
+            const double p0 = 2.0 * kPi * x / tw, p1 = 2.0 * kPi * (x + 1) / tw;
+            const Vec3 a = ep_direction(0.5 * (t0 + t1), 0.5 * (p0 + p1));
+            const double h0 = std::max(ep_angle(a, ep_direction(t0, p0)), ep_angle(a, ep_direction(t0, p1)));
+            const double h1 = std::max(ep_angle(a, ep_direction(t1, p0)), ep_angle(a, ep_direction(t1, p1)));
+            cell_axis[(size_t)y * tw + x] = a;
+            cell_half[(size_t)y * tw + x] = std::max(h0, h1) + 0.01;
+        }
+    const size_t per = 4 * (1 + (size_t)ep_nodes_above(top));
+    c->ep_oq.assign((size_t)kEpBins * kEpBins * per, 0);
+    std::vector<double> scaled((size_t)tw * th);
+    const double side = 2.0 / kEpBins;
+    for (uint32_t b = 0; b < kEpBins * kEpBins; ++b) {
+        const double x0 = -1.0 + side * (b % kEpBins), z0 = -1.0 + side * (b / kEpBins);
+        const Vec3 axis = ep_from_octahedral(x0 + 0.5 * side, z0 + 0.5 * side);
+        double half = 0.0;
+        for (int e = 0; e <= 16; ++e) {
+            const double f = e / 16.0;
+            half = std::max(half, ep_angle(axis, ep_from_octahedral(x0 + f * side, z0)));
+            half = std::max(half, ep_angle(axis, ep_from_octahedral(x0 + f * side, z0 + side)));
+            half = std::max(half, ep_angle(axis, ep_from_octahedral(x0, z0 + f * side)));
+            half = std::max(half, ep_angle(axis, ep_from_octahedral(x0 + side, z0 + f * side)));
+        }
+        half += 0.02;
+        for (size_t q = 0; q < scaled.size(); ++q) {
+            const double gap = ep_angle(axis, cell_axis[q]) - half - cell_half[q];
+            const double bound = gap <= 0.0 ? 1.0 : (gap >= 0.5 * kPi ? 0.0 : std::cos(gap));
+            scaled[q] = lvl[q] * bound;
+        }
+        uint32_t *o = c->ep_oq.data() + (size_t)b * per;
+        ep_fill_splits(scaled, top, o[0], o + 4);
+    }
+    c->ep_m = m;
+    c->ep_top = top;
+}
+
 void build_env(qpt_ctx *c)
 {
     uint32_t W = c->ew, H = c->eh;
@@ -771,6 +921,8 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.lt_emit = take(ne * 4);
     L.lt_pos = take(ne * 4);
     L.lt_w = take(ne * 4);
+    L.ep_q = take(c->ep_q.size() * 4);
+    L.ep_oq = take(c->ep_oq.size() * 4);
     L.env_texel = take(c->env_texel.size() * sizeof(float4));
     L.env_row = take(c->env_row.size() * 4);
     L.env_col = take(c->env_col.size() * 4);
@@ -933,6 +1085,7 @@ int qpt_build_scene(qpt_ctx *c, const qpt_scene_desc *d)
     c->env_texel.clear();
     c->env_cos.clear();
     if (c->ew) build_env(c);
+    build_env_pyramid(c);
     c->p_env = c->ew ? (c->emit_input_tri.empty() ? 1.0 : 0.5) : 0.0;
     build_light_pmf(c);
     if (c->emit_input_tri.empty() && !c->ew) {
@@ -1170,6 +1323,8 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     HIP_TRY(c, up(L.lt_emit, c->lt_emit.data(), c->lt_emit.size() * 4));
     HIP_TRY(c, up(L.lt_pos, c->lt_pos.data(), c->lt_pos.size() * 4));
     HIP_TRY(c, up(L.lt_w, c->lt_w.data(), c->lt_w.size() * 4));
+    HIP_TRY(c, up(L.ep_q, c->ep_q.data(), c->ep_q.size() * 4));
+    HIP_TRY(c, up(L.ep_oq, c->ep_oq.data(), c->ep_oq.size() * 4));
     HIP_TRY(c, up(L.env_texel, c->env_texel.data(), c->env_texel.size() * sizeof(float4)));
     HIP_TRY(c, up(L.env_row, c->env_row.data(), c->env_row.size() * 4));
     HIP_TRY(c, up(L.env_col, c->env_col.data(), c->env_col.size() * 4));
@@ -1196,6 +1351,12 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     f.env_col = (const uint32_t *)(w + L.env_col);
     f.env_cos = (const float *)(w + L.env_cos);
     f.p_env = (float)c->p_env;
+    f.ep_q = (const uint4 *)(w + L.ep_q);
+    f.ep_oq = (const uint4 *)(w + L.ep_oq);
+    f.ep_m = c->ep_m;
+    f.ep_top = c->ep_top;
+    f.ep_root = c->ep_root;
+    f.ep_stride = c->ep_m ? 1 + ep_nodes_above(c->ep_top) : 0;
     f.bases = (const HaltonBase *)(w + L.bases);
     for (int k = 0; k < 2; ++k) {
         const Layout::Lane &ln = L.lane[k];
@@ -1282,8 +1443,12 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
 {
     if (!c || !o) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
-    if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1)
-        return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1)");
+    if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1 ||
+        o->env_sampling > 2)
+        return fail(c, QPT_E_INVALID,
+                    "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, env_sampling 0..2)");
+    if (o->env_sampling && c->ew && !c->ep_m)
+        return fail(c, QPT_E_INVALID, "environment pyramid needs a 2:1 map of power-of-two size");
     if (!num_passes) return QPT_OK;
     // the largest Halton index must fit 64 bits
     u128 last = (u128)(first_pass + num_passes) * c->frame.S;
@@ -1298,6 +1463,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.mode = o->mode;
     f.scramble = o->scramble;
     f.light_tree = o->light_tree;
+    f.env_pyramid = c->ew ? o->env_sampling : 0;
     Profiler *prof = c->profiling ? &c->prof : nullptr;
     // Two batches in flight (without the guide): consecutive batches alternate
     // between the caller's stream and the library's second stream, each lane
@@ -1659,6 +1825,31 @@ int qpt_debug_light_tree(const qpt_ctx *c, float *sphere4, float *flux6, int32_t
     }
     if (emit) std::memcpy(emit, c->lt_emit.data(), c->lt_emit.size() * 4);
     if (weight) std::memcpy(weight, c->lt_w.data(), c->lt_w.size() * 4);
+    return QPT_OK;
+}
+
+int qpt_debug_env_pyramid(const qpt_ctx *c, uint32_t *levels, uint32_t *top, uint32_t *root, uint32_t *q,
+                          uint32_t *oq)
+{
+    if (!c || !levels || !top || !root) return QPT_E_INVALID;
+    if (!c->scene_ok) return QPT_E_STATE;
+    *levels = c->ep_m;
+    *top = c->ep_top;
+    *root = c->ep_root;
+    if (q) std::memcpy(q, c->ep_q.data(), c->ep_q.size() * 4);
+    if (oq) std::memcpy(oq, c->ep_oq.data(), c->ep_oq.size() * 4);
+    return QPT_OK;
+}
+
+int qpt_debug_env_sample(qpt_ctx *c, const uint32_t *uv, const float *nrm, uint32_t n, uint32_t mode,
+                         uint32_t *texel, uint64_t *iv, uint64_t *iv_hit)
+{
+    if (!c || (n && (!uv || !nrm || !texel || !iv || !iv_hit)) || mode < 1 || mode > 2) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    if (!c->ep_m) return fail(c, QPT_E_STATE, "no environment pyramid (needs a 2:1 power-of-two map)");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_debug_env_sample(c->frame, uv, nrm, n, mode, texel, iv, iv_hit, c->stream));
     return QPT_OK;
 }
 

@@ -117,6 +117,13 @@ struct Frame {
     const uint32_t *env_col;              // env_h * env_w
     const float *env_cos;                 // env_h + 1 row boundary cosines
     float p_env;                          // probability of choosing the environment
+    // environment pyramid (finest level ep_m, 0 = none): split probabilities
+    // (column, row | left column, row | right column, -) per node of levels
+    // 0..ep_m-1, and per normal bin (stride ep_stride) the left-root
+    // probability followed by the nodes of levels 0..ep_top-1
+    const uint4 *ep_q;
+    const uint4 *ep_oq;
+    uint32_t ep_m, ep_top, ep_root, ep_stride;
     // Halton
     const HaltonBase *bases;              // kMaxDims
     uint32_t k2, l3;                      // 2^k >= W, 3^l >= H
@@ -131,6 +138,7 @@ struct Frame {
     // options
     uint32_t max_depth, rr, mode, scramble;
     uint32_t light_tree;                  // select triangle lights through the light tree
+    uint32_t env_pyramid;                 // 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels
 };
 
 // Path pool (structure of arrays, Sec. 3.1.1) and queues (Sec. 3.1.2).
@@ -212,6 +220,8 @@ hipError_t launch_guide_debug_mixture(const float *out40, const float *dirs, con
 hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
                                     uint32_t n, int scramble, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);
+hipError_t launch_debug_env_sample(const Frame &f, const uint32_t *uv, const float *nrm, uint32_t n, uint32_t mode,
+                                   uint32_t *texel, uint64_t *iv, uint64_t *iv_hit, hipStream_t s);
 hipError_t launch_debug_light_sample(const Frame &f, const uint64_t *S, const float *x, const float *nrm,
                                      uint32_t n, uint32_t *emitter, uint64_t *size, uint64_t *size_hit,
                                      hipStream_t s);

@@ -482,15 +482,21 @@ __device__ __forceinline__ float mis2(float a, float b)
     return 1.0f / (1.0f + q * q);
 }
 
-__device__ float4 env_lookup(const Frame &F, f3 w)
+__device__ void env_texel_of(const Frame &F, f3 w, uint32_t &row, uint32_t &col)
 {
     float th = acosf(fminf(1.0f, fmaxf(-1.0f, w.y)));
     float ph = atan2f(w.x, -w.z);
     if (ph < 0.0f) ph += 2.0f * kPi;
     int r = (int)floorf(th / kPi * (float)F.env_h);
     int c = (int)floorf(ph / (2.0f * kPi) * (float)F.env_w);
-    r = min(max(r, 0), (int)F.env_h - 1);
-    c = min(max(c, 0), (int)F.env_w - 1);
+    row = (uint32_t)min(max(r, 0), (int)F.env_h - 1);
+    col = (uint32_t)min(max(c, 0), (int)F.env_w - 1);
+}
+
+__device__ float4 env_lookup(const Frame &F, f3 w)
+{
+    uint32_t r, c;
+    env_texel_of(F, w, r, c);
     return F.env_texel[(size_t)r * F.env_w + c];
 }
 
@@ -637,6 +643,113 @@ __device__ uint64_t lt_size_of(const Frame &F, uint32_t e, f3 x, f3 n)
     return z - a;
 }
 
+// the oriented normal of the previous vertex (its triangle and side bits, as
+// kept in the ray direction's spare word), rounded as shading rounded it there
+__device__ __forceinline__ f3 prev_normal(const Frame &F, float bits)
+{
+    const uint32_t pv = fbits(bits);
+    const Tri pt = F.tris[pv & 0x7fffffffu];
+    float a2;
+    const f3 n = unit_normal(xyz(pt.v0), xyz(pt.v1), xyz(pt.v2), a2);
+    return (pv >> 31) ? n * -1.0f : n;
+}
+
+// ------------------------------------------------- environment pyramid
+//
+// Hierarchical sampling of the environment (Sec. 2.1.2): from the two halves
+// of the sphere down to the texels, each step picks the child column by the
+// columns' shares of intensity x solid angle, then the row within it, as
+// 24-bit probabilities narrowing two 32-bit samples (u columns, v rows) as
+// integer intervals; a texel's probability is exactly the product of its two
+// final interval sizes over 2^64. With a normal bin, the top levels use the
+// bin's cosine-weighted splits.
+__device__ __forceinline__ uint32_t ep_nodes_above(uint32_t k)
+{
+    return (uint32_t)((2ull * ((1ull << (2 * k)) - 1)) / 3);
+}
+
+// normal bin: 16 x 16 cells of the octahedral map (+y up), each step rounded once
+__device__ uint32_t ep_bin(f3 n)
+{
+#pragma clang fp contract(off)
+    const float a = (fabsf(n.x) + fabsf(n.y)) + fabsf(n.z);
+    float px = n.x / a, pz = n.z / a;
+    if (n.y < 0.0f) {
+        const float fx = (1.0f - fabsf(pz)) * (px >= 0.0f ? 1.0f : -1.0f);
+        const float fz = (1.0f - fabsf(px)) * (pz >= 0.0f ? 1.0f : -1.0f);
+        px = fx;
+        pz = fz;
+    }
+    const int i = min(max((int)floorf((px + 1.0f) * 8.0f), 0), 15);
+    const int j = min(max((int)floorf((pz + 1.0f) * 8.0f), 0), 15);
+    return (uint32_t)(j * 16 + i);
+}
+
+// the first child's part of an interval of size R for a 24-bit share q
+// (0 and 2^24: a child without weight gets nothing)
+__device__ __forceinline__ uint64_t ep_split(uint64_t R, uint32_t q)
+{
+    if (q == 0) return 0;
+    if (q >= (1u << 24)) return R;
+    const uint64_t T = (R >> 24) * q + (((R & 0xFFFFFFull) * q) >> 24);
+    return R < 2 ? T : (T < 1 ? 1 : (T > R - 1 ? R - 1 : T));
+}
+
+// Sample the pyramid with (u, v), or with `steer` follow texel (row, col);
+// bin < 0 uses the shared splits only. Returns the texel and the final
+// intervals (sizes ru, rv; offsets su, sv inside them).
+__device__ void ep_descend(const Frame &F, int bin, uint32_t u, uint32_t v, bool steer, uint32_t &row,
+                           uint32_t &col, uint64_t &ru, uint64_t &su, uint64_t &rv, uint64_t &sv)
+{
+    const uint32_t m = F.ep_m;
+    const uint4 *oq = bin >= 0 ? F.ep_oq + (size_t)bin * F.ep_stride : nullptr;
+    ru = 1ull << 32;
+    su = u;
+    rv = 1ull << 32;
+    sv = v;
+    uint64_t T = ep_split(ru, oq ? oq[0].x : F.ep_root);
+    const bool right = steer ? ((col >> m) & 1u) != 0 : su >= T;
+    if (right) {
+        su -= T;
+        ru -= T;
+    } else {
+        ru = T;
+    }
+    uint32_t x = right ? 1u : 0u, y = 0;
+    for (uint32_t k = 0; k < m; ++k) {
+        const size_t at = (size_t)ep_nodes_above(k) + (size_t)y * (2u << k) + x;
+        const uint4 q = (oq && k < F.ep_top) ? oq[1 + at] : F.ep_q[at];
+        T = ep_split(ru, q.x);
+        const bool cx = steer ? ((col >> (m - 1 - k)) & 1u) != 0 : su >= T;
+        if (cx) {
+            su -= T;
+            ru -= T;
+        } else {
+            ru = T;
+        }
+        T = ep_split(rv, cx ? q.z : q.y);
+        const bool cy = steer ? ((row >> (m - 1 - k)) & 1u) != 0 : sv >= T;
+        if (cy) {
+            sv -= T;
+            rv -= T;
+        } else {
+            rv = T;
+        }
+        x = 2 * x + (cx ? 1u : 0u);
+        y = 2 * y + (cy ? 1u : 0u);
+    }
+    row = y;
+    col = x;
+}
+
+// solid-angle density of a texel of row `row` chosen with interval sizes ru, rv
+__device__ __forceinline__ float ep_pdf(const Frame &F, uint32_t row, uint64_t ru, uint64_t rv)
+{
+#pragma clang fp contract(off)
+    const float omega = (2.0f * kPi / (float)F.env_w) * (F.env_cos[row] - F.env_cos[row + 1]);
+    return ((float)ru * (float)rv * 0x1p-64f) / omega;
+}
+
 // ---------------------------------------------------------------- kernels
 
 __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t v)
@@ -768,8 +881,18 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
             uint32_t tri = fbits(hv.y);
             if (tri == kNoHit) {
                 if (F.env_w && (v == 1 || F.mode != 2)) {
-                    float4 e = env_lookup(F, d);
-                    float w = (v > 1 && F.mode == 0) ? mis2(prev_pdf, F.p_env * e.w) : 1.0f;
+                    uint32_t er, ec;
+                    env_texel_of(F, d, er, ec);
+                    const float4 e = F.env_texel[(size_t)er * F.env_w + ec];
+                    float pe = e.w;
+                    if (v > 1 && F.mode == 0 && F.env_pyramid) {
+                        // the pyramid's density of this texel from the previous vertex
+                        const int bin = F.env_pyramid == 2 ? (int)ep_bin(prev_normal(F, d4.w)) : -1;
+                        uint64_t ru, su, rv, sv;
+                        ep_descend(F, bin, 0u, 0u, true, er, ec, ru, su, rv, sv);
+                        pe = ep_pdf(F, er, ru, rv);
+                    }
+                    float w = (v > 1 && F.mode == 0) ? mis2(prev_pdf, F.p_env * pe) : 1.0f;
                     L = L + T * xyz(e) * w;
                 }
             } else {
@@ -790,12 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                         if (F.light_tree) {
                             // the tree's probability of this emitter from the previous
                             // vertex: its ray origin and oriented normal, as its NEE saw them
-                            const uint32_t pv = fbits(d4.w);
-                            const Tri pt = F.tris[pv & 0x7fffffffu];
-                            float pa2;
-                            f3 pn = unit_normal(xyz(pt.v0), xyz(pt.v1), xyz(pt.v2), pa2);
-                            if (pv >> 31) pn = pn * -1.0f;
-                            const uint64_t z = lt_size_of(F, em, xyz(P.ray_o[slot]), pn);
+                            const uint64_t z = lt_size_of(F, em, xyz(P.ray_o[slot]), prev_normal(F, d4.w));
                             pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
                         } else {
                             pe = F.emit_pmf[em];
@@ -832,13 +950,25 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                         if (use_env) {
                             uint32_t s1 = sample_bits(F, idx, base_dim + 1, F.scramble);
                             uint32_t s2 = sample_bits(F, idx, base_dim + 2, F.scramble);
-                            uint32_t row = upper_search(F.env_row, F.env_h, s1);
-                            const uint32_t *cq = F.env_col + (size_t)row * F.env_w;
-                            uint32_t col = upper_search(cq, F.env_w, s2);
-                            uint64_t r0 = F.env_row[row], r1 = row + 1 < F.env_h ? F.env_row[row + 1] : (1ull << 32);
-                            uint64_t c0 = cq[col], c1 = col + 1 < F.env_w ? cq[col + 1] : (1ull << 32);
-                            float fy = (float)(s1 - r0) / (float)(r1 - r0);
-                            float fx = (float)(s2 - c0) / (float)(c1 - c0);
+                            uint32_t row, col;
+                            float fx, fy, pt = 0.0f;
+                            if (F.env_pyramid) {
+                                // pyramid: slot 2 narrows the columns, slot 1 the rows
+                                const int bin = F.env_pyramid == 2 ? (int)ep_bin(nn) : -1;
+                                uint64_t ru, su, rv, sv;
+                                ep_descend(F, bin, s2, s1, false, row, col, ru, su, rv, sv);
+                                fx = (float)su / (float)ru;
+                                fy = (float)sv / (float)rv;
+                                pt = ep_pdf(F, row, ru, rv);
+                            } else {
+                                row = upper_search(F.env_row, F.env_h, s1);
+                                const uint32_t *cq = F.env_col + (size_t)row * F.env_w;
+                                col = upper_search(cq, F.env_w, s2);
+                                uint64_t r0 = F.env_row[row], r1 = row + 1 < F.env_h ? F.env_row[row + 1] : (1ull << 32);
+                                uint64_t c0 = cq[col], c1 = col + 1 < F.env_w ? cq[col + 1] : (1ull << 32);
+                                fy = (float)(s1 - r0) / (float)(r1 - r0);
+                                fx = (float)(s2 - c0) / (float)(c1 - c0);
+                            }
                             float ct = F.env_cos[row], cb = F.env_cos[row + 1];
                             float cth = ct + fy * (cb - ct);
                             float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
@@ -847,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
                             wi = mk(sth * sp, cth, -sth * cp);
                             float4 e = F.env_texel[(size_t)row * F.env_w + col];
                             Le = xyz(e);
-                            pl = F.p_env * e.w;
+                            pl = F.p_env * (F.env_pyramid ? pt : e.w);
                             ok = pl > 0.0f;
                         } else {
                             uint32_t s7 = sample_bits(F, idx, base_dim + 7, F.scramble);
@@ -1158,6 +1288,33 @@ hipError_t launch_debug_sample_bits(const Frame &F, const uint64_t *idx, const u
 {
     hipLaunchKernelGGL(k_debug_sample_bits, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, idx, dim, n,
                        scramble, out);
+    return hipGetLastError();
+}
+
+__global__ void k_debug_env_sample(Frame F, const uint32_t *uv, const float *nrm, uint32_t n, uint32_t mode,
+                                   uint32_t *texel, uint64_t *iv, uint64_t *iv_hit)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int bin = mode == 2 ? (int)ep_bin(mk(nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2])) : -1;
+    uint32_t row, col;
+    uint64_t ru, su, rv, sv;
+    ep_descend(F, bin, uv[2 * i], uv[2 * i + 1], false, row, col, ru, su, rv, sv);
+    texel[i] = row * F.env_w + col;
+    iv[4 * i] = ru;
+    iv[4 * i + 1] = su;
+    iv[4 * i + 2] = rv;
+    iv[4 * i + 3] = sv;
+    ep_descend(F, bin, 0u, 0u, true, row, col, ru, su, rv, sv);
+    iv_hit[2 * i] = ru;
+    iv_hit[2 * i + 1] = rv;
+}
+
+hipError_t launch_debug_env_sample(const Frame &F, const uint32_t *uv, const float *nrm, uint32_t n, uint32_t mode,
+                                   uint32_t *texel, uint64_t *iv, uint64_t *iv_hit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_env_sample, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, uv, nrm, n, mode,
+                       texel, iv, iv_hit);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ class qpt_bvh_stats(C.Structure):
 
 class qpt_render_opts(C.Structure):
     _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32),
-                ("light_tree", C.c_uint32), ("single_stream", C.c_uint32)]
+                ("light_tree", C.c_uint32), ("single_stream", C.c_uint32), ("env_sampling", C.c_uint32)]
 
 
 class qpt_stats(C.Structure):
@@ -73,7 +73,7 @@ EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
-    "qpt_debug_light_tree", "qpt_debug_light_sample",
+    "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
     "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_eval", "qpt_guide_debug_grad",
     "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
@@ -112,6 +112,9 @@ def lib():
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
             "qpt_debug_light_tree": ([P, P, P, P, P, P, P, P, C.POINTER(C.c_uint32)], i32),
             "qpt_debug_light_sample": ([P, P, P, P, u32, P, P, P], i32),
+            "qpt_debug_env_pyramid": ([P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), P, P],
+                                      i32),
+            "qpt_debug_env_sample": ([P, P, P, u32, u32, P, P, P], i32),
             "qpt_debug_env_tables": ([P, P, P, P], i32),
             "qpt_debug_bvh_nodes": ([P, P, P, P], i32),
             "qpt_profile": ([P, i32], i32),
@@ -218,8 +221,10 @@ class Context:
         self.check(self.L.qpt_bind_workspace(self.h, C.c_void_p(ptr), nbytes, pool_paths), "qpt_bind_workspace")
 
     def render_pass(self, first_pass: int, num_passes: int, max_depth: int, rr: bool = True, mode: int = 0,
-                    scramble: bool = True, light_tree: bool = False, single_stream: bool = False) -> None:
-        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree), int(single_stream))
+                    scramble: bool = True, light_tree: bool = False, single_stream: bool = False,
+                    env_sampling: int = 0) -> None:
+        o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree), int(single_stream),
+                            int(env_sampling))
         self.check(self.L.qpt_render_pass(self.h, first_pass, num_passes, C.byref(o)), "qpt_render_pass")
 
     def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> None:
@@ -307,6 +312,26 @@ class Context:
                                                C.byref(nn)), "qpt_debug_light_tree")
         return t
 
+    def debug_env_pyramid(self):
+        """The environment pyramid's host tables (same keys as the oracle's)."""
+        m, top, root = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        self.check(self.L.qpt_debug_env_pyramid(self.h, C.byref(m), C.byref(top), C.byref(root), None, None),
+                   "qpt_debug_env_pyramid")
+        m, top, root = m.value, top.value, root.value
+        if not m:
+            return dict(m=0)
+        q = np.empty(4 * (2 * (4 ** m - 1) // 3), np.uint32)
+        oq = np.empty(256 * 4 * (1 + 2 * (4 ** top - 1) // 3), np.uint32)
+        self.check(self.L.qpt_debug_env_pyramid(self.h, C.byref(C.c_uint32()), C.byref(C.c_uint32()),
+                                                C.byref(C.c_uint32()), _p(q), _p(oq)), "qpt_debug_env_pyramid")
+        return dict(m=m, top=top, root=root, q=q, oq=oq.reshape(256, -1))
+
+    def debug_env_sample(self, uv, nrm, n, mode, texel, iv, iv_hit) -> None:
+        """Device buffers: uv (2n uint32), nrm (3n float32) in; texel (n
+        uint32), iv (4n uint64), iv_hit (2n uint64) out."""
+        self.check(self.L.qpt_debug_env_sample(self.h, _p(uv), _p(nrm), n, mode, _p(texel), _p(iv), _p(iv_hit)),
+                   "qpt_debug_env_sample")
+
     def debug_light_sample(self, S, x, nrm, n, emitter, size, size_hit) -> None:
         """Device buffers: S (n uint64), x and nrm (3n float32) in; emitter
         (n uint32), size and size_hit (n uint64) out."""
@@ -364,9 +389,9 @@ class Renderer:
         self.W, self.H = sc.width, sc.height
 
     def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True,
-               light_tree=False, single_stream=False):
+               light_tree=False, single_stream=False, env_sampling=0):
         self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble, light_tree,
-                             single_stream)
+                             single_stream, env_sampling)
 
     def readback(self):
         s = np.empty((self.H * self.W, 3), np.float64)

@@ -148,3 +148,27 @@ def test_light_tree_matches_oracle(qpt, orc, make):
     assert mine["left"].shape == ref["left"].shape
     for k in ("center", "flux", "left", "first", "count", "emit", "w"):
         assert np.array_equal(mine[k].view(np.uint32), ref[k].view(np.uint32)), k
+
+
+@pytest.mark.parametrize("env", [(64, 32), (16, 8), (2048, 1024)])
+def test_env_pyramid_matches_oracle(qpt, orc, env):
+    """The library's environment pyramid, built by its own code, equals the
+    oracle's table for table, bit for bit."""
+    if env == (16, 8):
+        sc = g.convex_under_env()
+    else:
+        sc = g.instanced_env_scene(width=8, height=8, target_tris=2000, env_size=env)
+    c = qpt.Context(-1)
+    c.build_scene(sc)
+    mine = c.debug_env_pyramid()
+    ref = orc.Scene(sc, build_bvh=False).env_pyramid()
+    assert mine["m"] == ref["m"] > 0 and mine["top"] == ref["top"] and mine["root"] == ref["root"]
+    assert np.array_equal(mine["q"], ref["q"])
+    assert np.array_equal(mine["oq"], ref["oq"])
+
+
+def test_env_pyramid_absent_for_other_shapes(qpt):
+    sc = g.instanced_env_scene(width=8, height=8, target_tris=2000, env_size=(96, 48))
+    c = qpt.Context(-1)
+    c.build_scene(sc)
+    assert c.debug_env_pyramid()["m"] == 0
