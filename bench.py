@@ -380,6 +380,8 @@ def main():
     ap.add_argument("--et-oracle-seconds", type=float, default=10.0)
     ap.add_argument("--et-size", type=str, default="1920x1080")
     ap.add_argument("--et-tris", type=int, default=4_000_000)
+    ap.add_argument("--bvh-builder", type=int, choices=(0, 1), default=0,
+                    help="0: binned SAH on the host, 1: linear BVH built on the GPU")
     ap.add_argument("--single-stream", action="store_true",
                     help="render the timed passes one batch at a time on one stream")
     ap.add_argument("--no-light-select", action="store_true",
@@ -417,7 +419,7 @@ def main():
     sc = scenegen.make_config(WORKLOADS[args.workload][0])
     D = sc.max_depth
     _say(f"bench: scene {sc.name} tris={sc.num_triangles} {sc.width}x{sc.height} D={D}")
-    r = Renderer(sc, device=0)
+    r = Renderer(sc, device=0, bvh_builder=args.bvh_builder)
     bs = r.bvh_stats
     _say(f"bench: bvh nodes={bs.num_nodes} leaves={bs.num_leaves} depth={bs.max_depth} build={bs.build_ms:.0f} ms")
     # the passes go to the library as one range, which renders them in batches
@@ -543,6 +545,10 @@ def main():
                    "parallelism": "single GPU"},
         "mpaths_per_s": round(mpaths, 3),
         "rays_per_path": round((ext + sh) / paths, 3),
+        "bvh": {"builder": "GPU linear BVH (Morton, collapsed to 4-wide)" if args.bvh_builder else
+                "host binned SAH (collapsed to 4-wide)", "build_ms": round(bs.build_ms, 1),
+                "nodes": bs.num_nodes, "leaves": bs.num_leaves, "depth": bs.max_depth,
+                "sah_cost": round(bs.sah_cost, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "equal_time_rmse": et,

@@ -31,7 +31,7 @@ def build(verbose: bool = True) -> str:
     _run([HIPCC, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-ffp-contract=off", *common, "-c",
           os.path.join(CSRC, "qpt_host.cpp"), "-o", host_o])
     objs = [host_o]
-    for src in ("qpt_kernels.hip", "qpt_guide.hip"):
+    for src in ("qpt_kernels.hip", "qpt_guide.hip", "qpt_build.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([HIPCC, "-x", "hip", f"--offload-arch={ARCH}", *NO_PK_FP32, *common, "-c",
               os.path.join(CSRC, src), "-o", obj])

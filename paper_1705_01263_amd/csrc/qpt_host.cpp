@@ -1117,6 +1117,33 @@ int qpt_build_scene(qpt_ctx *c, const qpt_scene_desc *d)
     return QPT_OK;
 }
 
+// after either builder: overflow stack size, triangles in leaf order, the
+// emitters' leaf-order triangles
+static void finish_bvh(qpt_ctx *c, const std::vector<uint32_t> &order, uint32_t depth4)
+{
+    const uint32_t nt = (uint32_t)order.size();
+    // a ray at a node of depth d holds at most 3 (d + 1) stack entries
+    c->stack_need = 3 * (depth4 + 1);
+    c->gtris.resize(nt);
+    c->emit_tri_bvh.assign(c->emit_input_tri.size(), 0);
+    for (uint32_t k = 0; k < nt; ++k) {
+        uint32_t t = order[k];
+        const float *p0 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t]];
+        const float *p1 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + 1]];
+        const float *p2 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + 2]];
+        uint32_t m = c->tri_mat[t], e = c->tri_emit[t] >= 0 ? (uint32_t)c->tri_emit[t] : kNoHit;
+        float mf, tf, ef;
+        std::memcpy(&mf, &m, 4);
+        std::memcpy(&tf, &t, 4);
+        std::memcpy(&ef, &e, 4);
+        c->gtris[k].v0 = make_float4(p0[0], p0[1], p0[2], mf);
+        c->gtris[k].v1 = make_float4(p1[0], p1[1], p1[2], tf);
+        c->gtris[k].v2 = make_float4(p2[0], p2[1], p2[2], ef);
+        if (e != kNoHit) c->emit_tri_bvh[e] = k;
+    }
+    c->bvh_ok = true;
+}
+
 int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
 {
     if (!c) return QPT_E_INVALID;
@@ -1125,8 +1152,62 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
     auto t0 = std::chrono::steady_clock::now();
     uint32_t leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 4;
     uint32_t bins = opts && opts->sah_bins ? opts->sah_bins : 16;
-    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64) return fail(c, QPT_E_INVALID, "bad BVH options");
+    const uint32_t builder = opts ? opts->builder : 0;
+    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64 || builder > 1) return fail(c, QPT_E_INVALID, "bad BVH options");
     uint32_t nt = (uint32_t)c->tri_mat.size();
+    if (builder == 1 && c->device < 0) return fail(c, QPT_E_STATE, "the GPU builder needs a device context");
+    if (builder == 1 && nt > leaf) {
+        // linear BVH on the GPU, collapsed there into the 4-wide layout
+        double maxabs = 0.0;
+        for (size_t q = 0; q < c->idx.size(); ++q)
+            for (int a = 0; a < 3; ++a) maxabs = std::max(maxabs, (double)std::fabs(c->pos[3 * (size_t)c->idx[q] + a]));
+        const float pad = (float)(std::ldexp(std::max(maxabs, 1e-3), -18));
+        std::vector<uint32_t> order;
+        uint32_t depth4 = 0;
+        DeviceGuard g(c->device);
+        if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
+        hipError_t e = gpu_build_bvh(c->pos.data(), (uint32_t)(c->pos.size() / 3), c->idx.data(), nt, leaf, pad,
+                                     c->stream, c->gnodes, order, depth4);
+        if (e != hipSuccess) return fail(c, QPT_E_HIP, "GPU BVH build: %s", hipGetErrorString(e));
+        // leaves and the SAH cost of the 4-wide tree (node box = union of its slots)
+        auto area = [](float dx, float dy, float dz) { return 2.0 * ((double)dx * dy + (double)dy * dz + (double)dz * dx); };
+        uint32_t leaves = 0;
+        double sah = 0.0, root_area = 0.0;
+        for (size_t k = 0; k < c->gnodes.size(); ++k) {
+            const Node &nd = c->gnodes[k];
+            const float lo[3][4] = {{nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w}, {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w},
+                                    {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w}};
+            const float hi[3][4] = {{nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w}, {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w},
+                                    {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w}};
+            const int ref[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
+            float ulo[3] = {INFINITY, INFINITY, INFINITY}, uhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int q = 0; q < nd.pad.x; ++q) {
+                for (int a = 0; a < 3; ++a) {
+                    ulo[a] = std::min(ulo[a], lo[a][q]);
+                    uhi[a] = std::max(uhi[a], hi[a][q]);
+                }
+                if (ref[q] < 0) ++leaves;
+            }
+            const double na = area(uhi[0] - ulo[0], uhi[1] - ulo[1], uhi[2] - ulo[2]);
+            if (k == 0) root_area = std::max(na, 1e-30);
+            sah += na / root_area;
+            for (int q = 0; q < nd.pad.x; ++q)
+                if (ref[q] < 0)
+                    sah += area(hi[0][q] - lo[0][q], hi[1][q] - lo[1][q], hi[2][q] - lo[2][q]) / root_area *
+                           (double)((~(uint32_t)ref[q] & 7u) + 1u);
+        }
+        finish_bvh(c, order, depth4);
+        auto t1 = std::chrono::steady_clock::now();
+        if (stats) {
+            stats->num_nodes = (uint32_t)c->gnodes.size();
+            stats->num_leaves = leaves;
+            stats->max_depth = depth4;
+            stats->reserved = 0;
+            stats->sah_cost = sah;
+            stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        }
+        return QPT_OK;
+    }
     std::vector<PrimInfo> prim(nt);
     double maxabs = 0.0;
     for (uint32_t t = 0; t < nt; ++t) {
@@ -1234,27 +1315,7 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
         n.pad = make_int4((int)nk, 0, 0, 0);
         c->gnodes[it.slot] = n;
     }
-    // a ray at a node of depth d holds at most 3 (d + 1) stack entries
-    c->stack_need = 3 * (depth4 + 1);
-    // triangles in leaf order
-    c->gtris.resize(nt);
-    c->emit_tri_bvh.assign(c->emit_input_tri.size(), 0);
-    for (uint32_t k = 0; k < nt; ++k) {
-        uint32_t t = order[k];
-        const float *p0 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t]];
-        const float *p1 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + 1]];
-        const float *p2 = &c->pos[3 * (size_t)c->idx[3 * (size_t)t + 2]];
-        uint32_t m = c->tri_mat[t], e = c->tri_emit[t] >= 0 ? (uint32_t)c->tri_emit[t] : kNoHit;
-        float mf, tf, ef;
-        std::memcpy(&mf, &m, 4);
-        std::memcpy(&tf, &t, 4);
-        std::memcpy(&ef, &e, 4);
-        c->gtris[k].v0 = make_float4(p0[0], p0[1], p0[2], mf);
-        c->gtris[k].v1 = make_float4(p1[0], p1[1], p1[2], tf);
-        c->gtris[k].v2 = make_float4(p2[0], p2[1], p2[2], ef);
-        if (e != kNoHit) c->emit_tri_bvh[e] = k;
-    }
-    c->bvh_ok = true;
+    finish_bvh(c, order, depth4);
     auto t1 = std::chrono::steady_clock::now();
     if (stats) {
         stats->num_nodes = (uint32_t)c->gnodes.size();

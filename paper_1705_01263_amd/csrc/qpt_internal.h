@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace qpt {
 
 constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
@@ -188,6 +190,13 @@ struct GuideTrain {
     float *scalars;          // [0] sum of loss weights [1] weighted loss sum
     uint32_t max_blocks;
 };
+
+// GPU BVH build (qpt_build.hip): linear BVH over Morton-sorted centroids,
+// collapsed into 4-wide nodes on the device; allocates and frees its own
+// temporaries, synchronises `s`, returns the nodes (root first), the leaf
+// order of the triangles and the 4-wide depth. Needs nt > leaf.
+hipError_t gpu_build_bvh(const float *pos, uint32_t nv, const uint32_t *idx, uint32_t nt, uint32_t leaf, float pad,
+                         hipStream_t s, std::vector<Node> &nodes, std::vector<uint32_t> &order, uint32_t &depth);
 
 // kernel launchers (qpt_kernels.hip)
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);

@@ -856,7 +856,8 @@ __device__ __forceinline__ uint32_t rec_hash(uint64_t idx, uint32_t v)
 }
 
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
-__global__ __launch_bounds__(kBlock) void k_shade(Frame F, Pool P, uint32_t v)
+// (four blocks per CU: at most 128 VGPRs, four waves per SIMD, no spills)
+__global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v)
 {
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];

@@ -37,7 +37,7 @@ class qpt_scene_desc(C.Structure):
 
 
 class qpt_bvh_opts(C.Structure):
-    _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32)]
+    _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32), ("builder", C.c_uint32)]
 
 
 class qpt_bvh_stats(C.Structure):
@@ -206,8 +206,9 @@ class Context:
         self.check(self.L.qpt_build_scene(self.h, C.byref(d)), "qpt_build_scene")
         self.W, self.H = sc.width, sc.height
 
-    def build_bvh(self, max_leaf_size: int = 4, sah_bins: int = 16) -> qpt_bvh_stats:
-        o = qpt_bvh_opts(max_leaf_size, sah_bins)
+    def build_bvh(self, max_leaf_size: int = 4, sah_bins: int = 16, builder: int = 0) -> qpt_bvh_stats:
+        """builder 0: binned SAH on the host; 1: linear BVH on the GPU."""
+        o = qpt_bvh_opts(max_leaf_size, sah_bins, builder)
         st = qpt_bvh_stats()
         self.check(self.L.qpt_build_bvh(self.h, C.byref(o), C.byref(st)), "qpt_build_bvh")
         return st
@@ -370,7 +371,7 @@ class Context:
 class Renderer:
     """Scene + BVH + a torch-owned workspace on one GPU; renders 1-spp passes."""
 
-    def __init__(self, sc, device: int = 0, pool_paths: int = 0, stream=None):
+    def __init__(self, sc, device: int = 0, pool_paths: int = 0, stream=None, bvh_builder: int = 0):
         import torch
 
         self.torch = torch
@@ -380,7 +381,7 @@ class Renderer:
         self.ctx = Context(device, self.stream.cuda_stream)
         self.ctx.ntri = sc.num_triangles
         self.ctx.build_scene(sc)
-        self.bvh_stats = self.ctx.build_bvh()
+        self.bvh_stats = self.ctx.build_bvh(builder=bvh_builder)
         self.pool_paths = pool_paths
         nbytes = self.ctx.workspace_size(pool_paths)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
