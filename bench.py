@@ -175,9 +175,10 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             n = 0
+            # eight passes per call: two batches of four, the second overlapping the first's tail
             while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
-                r.render(n, 4)
-                n += 4
+                r.render(n, 8)
+                n += 8
                 torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s, c = r.readback()

@@ -274,7 +274,7 @@ struct Layout {
     } lane[2];
     size_t stats;
     size_t fb_sum, fb_count;
-    size_t g_frag, g_fragT, g_bias, g_mix, g_rec, g_ring, g_ring_head, g_master, g_m, g_v, g_partial, g_scalars;
+    size_t g_frag, g_fragT, g_bias, g_mix[2], g_rec[2], g_ring, g_ring_head, g_master, g_m, g_v, g_partial, g_scalars;
     size_t g_pub_frag[2], g_pub_bias[2];
     size_t total;
 };
@@ -392,7 +392,9 @@ struct qpt_ctx {
     // two batches in flight: lane 1's stream, and the events that order the
     // lanes against the caller's stream and the framebuffer updates in pass order
     hipStream_t lstream = nullptr;
-    hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr;
+    hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr, ev_fin = nullptr;
+    uint4 *lane_mix[2] = {nullptr, nullptr};     // per lane: the guide's mixture per slot
+    float4 *lane_rec[2] = {nullptr, nullptr};    // per lane: training records
     uint64_t batches = 0;
 };
 
@@ -954,8 +956,10 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.g_frag = take(kGuideFrags * 64 * 8);
     L.g_fragT = take(kGuideFragsT * 64 * 8);
     L.g_bias = take(256 * 4);
-    L.g_mix = take((size_t)cap * 5 * 16);
-    L.g_rec = take(rec_cap * kRecF4 * 16);
+    for (int k = 0; k < 2; ++k) {   // per lane: mixtures of its slots, its training records
+        L.g_mix[k] = take((size_t)cap * 5 * 16);
+        L.g_rec[k] = take(rec_cap * kRecF4 * 16);
+    }
     L.g_ring = take((size_t)kGuideRing * kRingF4 * 16);
     L.g_ring_head = take(4);
     for (int k = 0; k < 2; ++k) {
@@ -1031,6 +1035,7 @@ void qpt_destroy(qpt_ctx *ctx)
         (void)hipEventDestroy(ctx->ev_lane_in);
         (void)hipEventDestroy(ctx->ev_lane_out);
         (void)hipEventDestroy(ctx->ev_acc);
+        (void)hipEventDestroy(ctx->ev_fin);
         (void)hipStreamDestroy(ctx->lstream);
     }
     delete ctx;
@@ -1361,6 +1366,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_in, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fin, hipEventDisableTiming));
     }
     c->ws = (uint8_t *)device_ptr;
     c->ws_bytes = bytes;
@@ -1465,7 +1471,11 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.frag = T.frag;
     G.fragT = T.fragT;
     G.bias = T.bias;
-    G.mix = (uint4 *)(w + L.g_mix);
+    G.mix = (uint4 *)(w + L.g_mix[0]);
+    for (int k = 0; k < 2; ++k) {
+        c->lane_mix[k] = (uint4 *)(w + L.g_mix[k]);
+        c->lane_rec[k] = (float4 *)(w + L.g_rec[k]);
+    }
     for (int a = 0; a < 3; ++a) {
         G.bmin[a] = (float)c->bbox[a];
         G.binv[a] = (float)(1.0 / (double)(float)c->bbox[3 + a]);
@@ -1473,9 +1483,9 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.alpha_thr = 0;
     G.alpha = 0.0f;
     G.record = 0;
-    G.rec = (float4 *)(w + L.g_rec);
+    G.rec = (float4 *)(w + L.g_rec[0]);
     G.rec_cap = (uint32_t)guide_rec_cap(cap);
-    G.rec_count = c->pool.counters + 127;  // guided batches run on lane 0
+    G.rec_count = c->pool.counters + 127;
     c->guide_weights = false;
     c->guide_steps = 0;
     c->bound = true;
@@ -1526,34 +1536,32 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.light_tree = o->light_tree;
     f.env_pyramid = c->ew ? o->env_sampling : 0;
     Profiler *prof = c->profiling ? &c->prof : nullptr;
-    // Two batches in flight (without the guide): consecutive batches alternate
-    // between the caller's stream and the library's second stream, each lane
-    // with its own path pool, so that one batch's deep vertices (few paths,
-    // latency-bound traversals) overlap the next batch's first vertices. The
-    // framebuffer stays updated in pass order: a batch's accumulation waits
-    // for the previous batch's. Lane 1 starts after the caller's earlier work
-    // and the caller's stream waits for lane 1 before this call returns.
-    const bool two_lanes = !guiding && !o->single_stream;
+    // Two batches in flight: consecutive batches alternate between the
+    // caller's stream and the library's second stream, each lane with its own
+    // path pool (and, for the guide, its own mixtures and records), so that
+    // one batch's deep vertices (few paths, latency-bound traversals) overlap
+    // the next batch's first vertices. The framebuffer stays updated in pass
+    // order: a batch's accumulation waits for the previous batch's; training
+    // samples enter the replay ring one batch after another. Lane 1 starts
+    // after the caller's earlier work and the caller's stream waits for lane 1
+    // before this call returns.
+    const bool two_lanes = !o->single_stream;
     bool lane_b_used = false;
     // the point lane 1 waits for: the caller's work before this call
     if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_lane_in, c->stream));
     // one batch of passes (or of pixels), then one training step if enabled
     const uint32_t npix = c->W * c->H, cap = c->pool_cap;
     auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
-        if (two_lanes) {
-            const bool lane_b = (c->batches++ & 1) != 0;
-            hipStream_t s = lane_b ? c->lstream : c->stream;
-            if (lane_b && !lane_b_used) {
-                HIP_TRY(c, hipStreamWaitEvent(c->lstream, c->ev_lane_in, 0));
-                lane_b_used = true;
-            }
-            const Pool &P = lane_b ? c->pool_b : c->pool;
-            HIP_TRY(c, launch_render_paths(f, P, p0, np, pass0, nb, s, prof));
-            HIP_TRY(c, hipStreamWaitEvent(s, c->ev_acc, 0));
-            HIP_TRY(c, launch_accumulate(f, P, p0, np, nb, s, prof));
-            HIP_TRY(c, hipEventRecord(c->ev_acc, s));
-            return QPT_OK;
+        const bool lane_b = two_lanes && (c->batches++ & 1) != 0;
+        hipStream_t s = lane_b ? c->lstream : c->stream;
+        if (lane_b && !lane_b_used) {
+            HIP_TRY(c, hipStreamWaitEvent(c->lstream, c->ev_lane_in, 0));
+            lane_b_used = true;
         }
+        const Pool &P = lane_b ? c->pool_b : c->pool;
+        f.guide.mix = c->lane_mix[lane_b ? 1 : 0];
+        f.guide.rec = c->lane_rec[lane_b ? 1 : 0];
+        f.guide.rec_count = P.counters + 127;
         bool active = c->gopts.alpha > 0.0f && c->guide_steps >= c->gopts.warmup_steps;
         uint64_t thr = active ? (uint64_t)std::llround((double)c->gopts.alpha * 4294967296.0) : 0;
         f.guide.alpha_thr = (uint32_t)std::min<uint64_t>(thr, 0xffffffffull);
@@ -1573,29 +1581,35 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         // b - 1 runs on the training stream. Any weights give an unbiased
         // estimator; the lag only delays what the guide has learnt. Batch b's
         // samples enter the replay ring right after it (they read path
-        // radiance the next batch overwrites), once step b - 1 has stopped
-        // reading the ring.
+        // radiance the lane's next batch overwrites), once step b - 1 has
+        // stopped reading the ring.
         const bool train = c->gopts.train > 0;
         const int k = train ? (int)(c->gbatch & 1) : c->last_buf;
         if (guiding) {
-            if (c->train_pending[k]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[k], 0));
+            if (c->train_pending[k]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_train[k], 0));
             f.guide.frag = c->pub_frag[k];
             f.guide.bias = c->pub_bias[k];
         }
-        HIP_TRY(c, launch_render_batch(f, c->pool, p0, np, pass0, nb, c->stream, prof));
+        HIP_TRY(c, launch_render_paths(f, P, p0, np, pass0, nb, s, prof));
+        if (two_lanes) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_acc, 0));
+        HIP_TRY(c, launch_accumulate(f, P, p0, np, nb, s, prof));
+        if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_acc, s));
         if (train) {
             GuideTrain T = c->gt;
-            // the ring's readers (launched steps) finish before it is appended to
+            // the ring's readers (launched steps) finish before it is appended
+            // to, and batches append in order
             for (int kk = 0; kk < 2; ++kk)
-                if (c->train_pending[kk]) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_train[kk], 0));
-            if (prof) prof->begin(K_GUIDE_TRAIN, c->stream);
-            HIP_TRY(c, launch_guide_finalize(f, c->pool, T, c->stream));
-            if (prof) prof->end(K_GUIDE_TRAIN, c->stream);
+                if (c->train_pending[kk]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_train[kk], 0));
+            if (two_lanes) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_fin, 0));
+            if (prof) prof->begin(K_GUIDE_TRAIN, s);
+            HIP_TRY(c, launch_guide_finalize(f, P, T, s));
+            if (prof) prof->end(K_GUIDE_TRAIN, s);
+            if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_fin, s));
             // `train` Adam steps per pass, taken when a batch completes its passes
             // (a pass split into pixel chunks trains after its last chunk)
             const uint32_t nsteps = (p0 + np >= npix) ? c->gopts.train * nb : 0u;
             if (nsteps) {
-                HIP_TRY(c, hipEventRecord(c->ev_rec[k], c->stream));
+                HIP_TRY(c, hipEventRecord(c->ev_rec[k], s));
                 HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[k], 0));
                 if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
                 HIP_TRY(c, launch_guide_train_steps(f, T, c->gopts.batch ? c->gopts.batch : (1u << 18),
@@ -1611,26 +1625,31 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         }
         return QPT_OK;
     };
-    if (npix <= cap) {
-        uint32_t per = std::max(1u, cap / npix);
-        for (uint32_t done = 0; done < num_passes;) {
-            uint32_t nb = std::min(per, num_passes - done);
-            int rc = batch(0, npix, first_pass + done, nb);
-            if (rc) return rc;
-            done += nb;
-        }
-    } else {
-        for (uint32_t j = 0; j < num_passes; ++j)
-            for (uint32_t p0 = 0; p0 < npix; p0 += cap) {
-                int rc = batch(p0, std::min(cap, npix - p0), first_pass + j, 1);
+    auto all_batches = [&]() -> int {
+        if (npix <= cap) {
+            uint32_t per = std::max(1u, cap / npix);
+            for (uint32_t done = 0; done < num_passes;) {
+                uint32_t nb = std::min(per, num_passes - done);
+                int rc = batch(0, npix, first_pass + done, nb);
                 if (rc) return rc;
+                done += nb;
             }
-    }
+        } else {
+            for (uint32_t j = 0; j < num_passes; ++j)
+                for (uint32_t p0 = 0; p0 < npix; p0 += cap) {
+                    int rc = batch(p0, std::min(cap, npix - p0), first_pass + j, 1);
+                    if (rc) return rc;
+                }
+        }
+        return QPT_OK;
+    };
+    const int rc = all_batches();
+    // the caller's stream waits for lane 1 also when a launch failed midway
     if (lane_b_used) {
         HIP_TRY(c, hipEventRecord(c->ev_lane_out, c->lstream));
         HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_lane_out, 0));
     }
-    return QPT_OK;
+    return rc;
 }
 
 int qpt_readback(qpt_ctx *c, double *sum_rgb, uint32_t *counts, int dst_is_device)
