@@ -111,9 +111,10 @@ typedef struct {
     uint32_t single_stream;  /* 0: consecutive batches of passes run two at a time (the caller's stream
                                 and a second stream of the library, each with its own path pool; the
                                 caller's stream waits for both before the call's later work), so a
-                                batch's deep vertices overlap the next batch's first ones; guided
-                                rendering always uses one stream. 1: one batch after another on the
-                                caller's stream. The image is the same bit for bit. */
+                                batch's deep vertices overlap the next batch's first ones. 1: one
+                                batch after another on the caller's stream. The image is the same bit
+                                for bit (without the guide; guided images depend on the order in
+                                which training samples arrive either way). */
     uint32_t env_sampling;   /* environment NEE (Sec. 2.1.2): 0: 2D CDF over the texels; 1: descent
                                 of the texel pyramid; 2: the pyramid with its top levels weighted
                                 per surface-normal bin (16 x 16 octahedral cells, cosine bound over
