@@ -42,7 +42,7 @@ WORKLOADS = {
                 "selection), 3840x2160, 1 spp per step (two frames per launch sequence, two batches in flight), max "
                 "depth 16, NEE+MIS, roulette"),
 }
-GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 8, 2
+GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 64, 2  # the guide mixes in after 64 Adam steps
 
 # algorithmic bytes per unit of work ("Measurement")
 NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
