@@ -306,12 +306,13 @@ class Scene:
         return t, tri
 
     def render(self, pixels=None, pass0=0, npasses=1, max_depth=None, rr=True, mode=0,
-               scramble=True, nthreads=None, light_tree=False, env_sampling=0):
+               scramble=True, nthreads=None, light_tree=False, env_sampling=0, gauss=False):
         """FP64 sums, sums of squares and counts for the listed pixel ids (y*W+x).
         light_tree selects triangle lights through the light tree instead of
         the flux alias table; env_sampling 1 / 2 samples the environment by its
-        pyramid (2: with normal-weighted top levels) instead of the 2D CDF."""
-        mode = int(mode) | (0x100 if light_tree else 0) | (int(env_sampling) << 9)
+        pyramid (2: with normal-weighted top levels) instead of the 2D CDF;
+        gauss draws film samples from the Gaussian pixel filter."""
+        mode = int(mode) | (0x100 if light_tree else 0) | (int(env_sampling) << 9) | (0x800 if gauss else 0)
         sc = self.sc
         if max_depth is None:
             max_depth = sc.max_depth

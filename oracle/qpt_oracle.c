@@ -1323,13 +1323,14 @@ typedef struct {
     uint32_t scramble;
     uint32_t light_tree; /* select triangle lights through the light tree */
     uint32_t env_pyramid; /* 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels */
+    uint32_t gauss;       /* film samples from a Gaussian around the pixel centre instead of the box */
 } or_opts;
 
 /* the caller's mode word: MIS mode in the low byte, light tree in bit 8,
- * environment sampling in bits 9-10 */
+ * environment sampling in bits 9-10, Gaussian pixel filter in bit 11 */
 static or_opts make_opts(uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble)
 {
-    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u, (mode >> 9) & 3u};
+    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u, (mode >> 9) & 3u, (mode >> 11) & 1u};
     return op;
 }
 
@@ -1353,6 +1354,14 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
     const uint32_t W = s->W, H = s->H;
     double u0 = u24(or_sample_bits(i, 0, W, H, 0)), u1 = u24(or_sample_bits(i, 1, W, H, 0));
     double fx = px + u0, fy = py + u1;
+    if (op->gauss) {
+        /* filter importance sampling (Appendix A.1): a Gaussian whose 3 sigma
+         * range spans a 3 x 3 pixel block (sigma = 1/2 pixel) around the
+         * centre, untruncated, by the Box-Muller transform of the film sample */
+        double r = 0.5 * sqrt(-2.0 * log(1.0 - u0)), ph = 2.0 * M_PI * u1;
+        fx = px + 0.5 + r * cos(ph);
+        fy = py + 0.5 + r * sin(ph);
+    }
     double sx = (2.0 * fx / W - 1.0) * s->tan_half * s->aspect;
     double sy = (1.0 - 2.0 * fy / H) * s->tan_half;
     v3 d = normalize(add(s->fwd, add(mul(s->right, sx), mul(s->up, sy))));
