@@ -120,6 +120,10 @@ typedef struct {
                                 per surface-normal bin (16 x 16 octahedral cells, cosine bound over
                                 the bin and the cell). 1 and 2 need a 2:1 map of power-of-two size
                                 (QPT_E_INVALID otherwise); ignored without an environment. */
+    uint32_t filter;         /* pixel filter (Appendix A.1): 0: box (film sample uniform in the pixel);
+                                1: Gaussian of sigma 1/2 pixel (3 sigma spans 3 x 3 pixels) around the
+                                pixel centre, untruncated, by filter importance sampling (Box-Muller of
+                                the film sample); the sample still counts for its own pixel */
 } qpt_render_opts;
 
 typedef struct {
@@ -185,6 +189,19 @@ int qpt_workspace_size(const qpt_ctx *ctx, uint32_t pool_paths, size_t *bytes);
  * qpt_workspace_size) and upload the scene into it; the call returns after
  * the upload completed. Clears the framebuffer and statistics. */
 int qpt_bind_workspace(qpt_ctx *ctx, void *device_ptr, size_t bytes, uint32_t pool_paths);
+
+/* Ask enqueued rendering to stop (the paper's abort through host-mapped
+ * memory, Appendix A.4): a word in pinned host memory that the first batch of
+ * each pass reads on the GPU when it starts. Passes whose first batch starts
+ * after the request render nothing (no sums, no counts); a pass already
+ * started completes. Safe to call from another thread while the context's
+ * other calls run (the only such call). Afterwards qpt_render_pass returns
+ * QPT_E_ABORTED without enqueueing, and the next qpt_readback fills its
+ * buffers, returns QPT_E_ABORTED and clears the request. With whole-pass
+ * batches every pixel then has the same count c, and rendering passes
+ * [first + c, end) completes the image exactly as an uninterrupted run
+ * would. QPT_E_STATE before qpt_bind_workspace. */
+int qpt_abort(qpt_ctx *ctx);
 
 /* Enqueue iterations [first_pass, first_pass + num_passes), each one sample
  * per pixel over the whole frame (Sec. 3.2.2), and accumulate them into the

@@ -393,6 +393,8 @@ struct qpt_ctx {
     // lanes against the caller's stream and the framebuffer updates in pass order
     hipStream_t lstream = nullptr;
     hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr, ev_fin = nullptr;
+    uint32_t *abort_host = nullptr;              // pinned, mapped: the caller's stop request
+    uint32_t *abort_dev = nullptr;               // its device address
     uint4 *lane_mix[2] = {nullptr, nullptr};     // per lane: the guide's mixture per slot
     float4 *lane_rec[2] = {nullptr, nullptr};    // per lane: training records
     uint64_t batches = 0;
@@ -1036,6 +1038,7 @@ void qpt_destroy(qpt_ctx *ctx)
         (void)hipEventDestroy(ctx->ev_lane_out);
         (void)hipEventDestroy(ctx->ev_acc);
         (void)hipEventDestroy(ctx->ev_fin);
+        if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
         (void)hipStreamDestroy(ctx->lstream);
     }
     delete ctx;
@@ -1367,6 +1370,9 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fin, hipEventDisableTiming));
+        HIP_TRY(c, hipHostMalloc((void **)&c->abort_host, 64, hipHostMallocMapped));
+        HIP_TRY(c, hipHostGetDevicePointer((void **)&c->abort_dev, c->abort_host, 0));
+        __atomic_store_n(c->abort_host, 0u, __ATOMIC_SEQ_CST);
     }
     c->ws = (uint8_t *)device_ptr;
     c->ws_bytes = bytes;
@@ -1515,9 +1521,9 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     if (!c || !o) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
     if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1 ||
-        o->env_sampling > 2)
+        o->env_sampling > 2 || o->filter > 1)
         return fail(c, QPT_E_INVALID,
-                    "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, env_sampling 0..2)");
+                    "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, env_sampling 0..2, filter 0..1)");
     if (o->env_sampling && c->ew && !c->ep_m)
         return fail(c, QPT_E_INVALID, "environment pyramid needs a 2:1 map of power-of-two size");
     if (!num_passes) return QPT_OK;
@@ -1535,6 +1541,10 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.scramble = o->scramble;
     f.light_tree = o->light_tree;
     f.env_pyramid = c->ew ? o->env_sampling : 0;
+    f.gauss_filter = o->filter;
+    f.abort_word = c->abort_dev;
+    if (c->abort_host && __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST))
+        return fail(c, QPT_E_ABORTED, "aborted: qpt_readback reports the progress and clears the request");
     Profiler *prof = c->profiling ? &c->prof : nullptr;
     // Two batches in flight: consecutive batches alternate between the
     // caller's stream and the library's second stream, each lane with its own
@@ -1552,7 +1562,9 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     // one batch of passes (or of pixels), then one training step if enabled
     const uint32_t npix = c->W * c->H, cap = c->pool_cap;
     auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
-        const bool lane_b = two_lanes && (c->batches++ & 1) != 0;
+        // pixel chunks of one pass stay on one lane (its first chunk latches the
+        // abort decision for the rest); whole-pass batches alternate
+        const bool lane_b = two_lanes && (npix > cap ? ((pass0 - first_pass) & 1) != 0 : (c->batches++ & 1) != 0);
         hipStream_t s = lane_b ? c->lstream : c->stream;
         if (lane_b && !lane_b_used) {
             HIP_TRY(c, hipStreamWaitEvent(c->lstream, c->ev_lane_in, 0));
@@ -1663,6 +1675,17 @@ int qpt_readback(qpt_ctx *c, double *sum_rgb, uint32_t *counts, int dst_is_devic
     if (sum_rgb) HIP_TRY(c, hipMemcpyAsync(sum_rgb, c->pool.fb_sum, npix * 3 * 8, k, c->stream));
     if (counts) HIP_TRY(c, hipMemcpyAsync(counts, c->pool.fb_count, npix * 4, k, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // report (and clear) a stop request; the buffers hold what was rendered
+    if (c->abort_host && __atomic_exchange_n(c->abort_host, 0u, __ATOMIC_SEQ_CST))
+        return fail(c, QPT_E_ABORTED, "rendering was aborted: the counts show the passes done");
+    return QPT_OK;
+}
+
+int qpt_abort(qpt_ctx *c)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->abort_host) return QPT_E_STATE;
+    __atomic_store_n(c->abort_host, 1u, __ATOMIC_SEQ_CST);
     return QPT_OK;
 }
 

@@ -14,6 +14,9 @@ constexpr uint32_t kMaxTreeDepth = 32;   // depth limit of the binary build tree
 constexpr uint32_t kTravBlocksPerCU = 8; // traversal grid: 8 resident blocks x 4 waves per CU
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
 constexpr uint32_t kNoHit = 0xffffffffu;
+// per-lane counter words beyond the queue counts: the abort decision latched
+// by a pass's first batch, and whether the current batch renders nothing
+constexpr uint32_t kPassLatch = 125, kSkip = 126;
 
 // One base of the Halton sequence with its strength-reduced divisions
 // (Appendix A.2: integer evaluation, division by multiplication).
@@ -141,6 +144,8 @@ struct Frame {
     uint32_t max_depth, rr, mode, scramble;
     uint32_t light_tree;                  // select triangle lights through the light tree
     uint32_t env_pyramid;                 // 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels
+    uint32_t gauss_filter;                // film samples from the Gaussian pixel filter instead of the box
+    const uint32_t *abort_word;           // host-mapped: non-zero once the caller asked to stop
 };
 
 // Path pool (structure of arrays, Sec. 3.1.1) and queues (Sec. 3.1.2).
@@ -206,6 +211,7 @@ hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, 
 // the same in two parts: the paths of a batch, then its framebuffer update
 hipError_t launch_render_paths(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
                                uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
+// (a batch that starts a pass latches the abort word; its other pixel chunks follow it)
 hipError_t launch_accumulate(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix, uint32_t npass,
                              hipStream_t s, Profiler *prof);
 // guide launchers (qpt_guide.hip)

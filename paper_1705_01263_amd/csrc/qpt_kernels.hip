@@ -764,10 +764,26 @@ __global__ void k_fill_f64(double *p, size_t n)
         p[i] = 0.0;
 }
 
+// Start of a batch: clear the lane's counters; the batch that starts a pass
+// (its first pixel chunk) latches the caller's abort word, and every chunk of
+// the pass renders nothing when it was set, so a pass is done whole or not at all.
+__global__ void k_batch_begin(Pool P, const uint32_t *abort_word, uint32_t first_chunk)
+{
+    const uint32_t t = threadIdx.x;
+    if (t < 128 && t != kPassLatch && t != kSkip) P.counters[t] = 0;
+    if (t == 0) {
+        if (first_chunk)
+            P.counters[kPassLatch] =
+                abort_word ? __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) : 0u;
+        P.counters[kSkip] = P.counters[kPassLatch];
+    }
+}
+
 // camera rays for slots [0, n): slot s -> pixel pix0 + s % npix, pass pass0 + s / npix
 __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint64_t pass0,
                                                      uint32_t n)
 {
+    if (P.counters[kSkip]) return;  // aborted: no paths, every later stage sees empty queues
     uint32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s == 0) P.counters[1] = n;
     if (s >= n) return;
@@ -775,8 +791,17 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
     uint32_t p = pix0 + pl;
     uint32_t px = p % F.W, py = p / F.W;
     uint64_t i = pixel_index(F, px, py, pass0 + j);
-    float fx = (float)px + u24(sample_bits(F, i, 0, 0));
-    float fy = (float)py + u24(sample_bits(F, i, 1, 0));
+    const float u0 = u24(sample_bits(F, i, 0, 0)), u1 = u24(sample_bits(F, i, 1, 0));
+    float fx = (float)px + u0, fy = (float)py + u1;
+    if (F.gauss_filter) {
+        // filter importance sampling (Appendix A.1): Gaussian of sigma 1/2 pixel
+        // around the centre, untruncated, by Box-Muller (1 - u0 is exact and > 0)
+        const float r = 0.5f * sqrtf(-2.0f * logf(1.0f - u0));
+        float sn, cs;
+        sincospif(2.0f * u1, &sn, &cs);
+        fx = (float)px + 0.5f + r * cs;
+        fy = (float)py + 0.5f + r * sn;
+    }
     float sx = (2.0f * fx / (float)F.W - 1.0f) * F.cam.tan_half * F.cam.aspect;
     float sy = (1.0f - 2.0f * fy / (float)F.H) * F.cam.tan_half;
     f3 fwd = mk(F.cam.fwd[0], F.cam.fwd[1], F.cam.fwd[2]);
@@ -1137,6 +1162,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
 // FP64 accumulation in pass order and sample counts
 __global__ __launch_bounds__(kBlock) void k_accumulate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint32_t npass)
 {
+    if (P.counters[kSkip]) return;  // an aborted batch adds neither sums nor counts
     uint32_t q = blockIdx.x * kBlock + threadIdx.x;
     if (q == 0) {
         unsigned long long ext = 0, sh = 0;
@@ -1252,7 +1278,9 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
         launch();
         if (prof) prof->end(kind, s);
     };
-    timed(K_CLEAR, [&] { hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(128), 0, s, P.counters, (size_t)128, 0u); });
+    timed(K_CLEAR, [&] {
+        hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(128), 0, s, P, F.abort_word, pix0 == 0 ? 1u : 0u);
+    });
     timed(K_GENERATE, [&] {
         hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
     });

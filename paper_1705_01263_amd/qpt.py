@@ -47,7 +47,8 @@ class qpt_bvh_stats(C.Structure):
 
 class qpt_render_opts(C.Structure):
     _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32),
-                ("light_tree", C.c_uint32), ("single_stream", C.c_uint32), ("env_sampling", C.c_uint32)]
+                ("light_tree", C.c_uint32), ("single_stream", C.c_uint32), ("env_sampling", C.c_uint32),
+                ("filter", C.c_uint32)]
 
 
 class qpt_stats(C.Structure):
@@ -73,7 +74,7 @@ EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
-    "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
+    "qpt_abort", "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
     "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_eval", "qpt_guide_debug_grad",
     "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
@@ -110,6 +111,7 @@ def lib():
             "qpt_debug_pixel_index": ([P, u64, P], i32),
             "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P], i32),
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
+            "qpt_abort": ([P], i32),
             "qpt_debug_light_tree": ([P, P, P, P, P, P, P, P, C.POINTER(C.c_uint32)], i32),
             "qpt_debug_light_sample": ([P, P, P, P, u32, P, P, P], i32),
             "qpt_debug_env_pyramid": ([P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), P, P],
@@ -223,13 +225,21 @@ class Context:
 
     def render_pass(self, first_pass: int, num_passes: int, max_depth: int, rr: bool = True, mode: int = 0,
                     scramble: bool = True, light_tree: bool = False, single_stream: bool = False,
-                    env_sampling: int = 0) -> None:
+                    env_sampling: int = 0, gauss: bool = False) -> None:
         o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree), int(single_stream),
-                            int(env_sampling))
+                            int(env_sampling), int(gauss))
         self.check(self.L.qpt_render_pass(self.h, first_pass, num_passes, C.byref(o)), "qpt_render_pass")
 
-    def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> None:
-        self.check(self.L.qpt_readback(self.h, _p(sum_rgb), _p(counts), int(dst_is_device)), "qpt_readback")
+    def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> bool:
+        """Fill the buffers; True if rendering had been aborted (the request is then cleared)."""
+        rc = self.L.qpt_readback(self.h, _p(sum_rgb), _p(counts), int(dst_is_device))
+        if rc == QPT_E_ABORTED:
+            return True
+        self.check(rc, "qpt_readback")
+        return False
+
+    def abort(self) -> None:
+        self.check(self.L.qpt_abort(self.h), "qpt_abort")
 
     def reset_accum(self) -> None:
         self.check(self.L.qpt_reset_accum(self.h), "qpt_reset_accum")
@@ -390,14 +400,15 @@ class Renderer:
         self.W, self.H = sc.width, sc.height
 
     def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True,
-               light_tree=False, single_stream=False, env_sampling=0):
+               light_tree=False, single_stream=False, env_sampling=0, gauss=False):
         self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble, light_tree,
-                             single_stream, env_sampling)
+                             single_stream, env_sampling, gauss)
 
     def readback(self):
+        """FP64 sums and counts; `self.aborted` tells whether rendering had been aborted."""
         s = np.empty((self.H * self.W, 3), np.float64)
         c = np.empty(self.H * self.W, np.uint32)
-        self.ctx.readback(s, c)
+        self.aborted = self.ctx.readback(s, c)
         return s, c
 
     def reset(self):
