@@ -220,6 +220,14 @@ int qpt_readback(qpt_ctx *ctx, double *sum_rgb, uint32_t *counts, int dst_is_dev
 /* Zero the framebuffer, the counts and the statistics (enqueued on the stream). */
 int qpt_reset_accum(qpt_ctx *ctx);
 
+/* Resume from a checkpoint: load FP64 sums (W H 3) and per-pixel counts (W H)
+ * saved by qpt_readback (host memory, or device memory with src_is_device)
+ * into the framebuffer; rendering passes [c, ...) after a checkpoint taken
+ * with every count c continues the progressive image exactly as if it had
+ * not stopped (the sample indices of a pass do not depend on history).
+ * Synchronous. */
+int qpt_load_accum(qpt_ctx *ctx, const double *sum_rgb, const uint32_t *counts, int src_is_device);
+
 /* Synchronise and read the ray/path counters. */
 int qpt_get_stats(qpt_ctx *ctx, qpt_stats *out);
 
@@ -253,6 +261,16 @@ int qpt_guide_set_weights(qpt_ctx *ctx, const float *params);
 /* Copy the FP32 master parameters to host memory and the number of training
  * steps taken; either pointer may be NULL. Synchronises the stream. */
 int qpt_guide_get_weights(qpt_ctx *ctx, float *params, uint32_t *steps);
+
+/* Checkpoint of the guide's optimiser: FP32 master parameters, Adam first and
+ * second moments (13032 values each, host memory, any pointer may be NULL)
+ * and the step count (which drives the bias correction). Synchronous. */
+int qpt_guide_get_state(qpt_ctx *ctx, float *params, float *m, float *v, uint32_t *steps);
+
+/* Restore such a checkpoint (all three arrays required, finite, v >= 0).
+ * The replay ring of training samples starts empty; it refills from the
+ * next rendered batch. Synchronous. */
+int qpt_guide_set_state(qpt_ctx *ctx, const float *params, const float *m, const float *v, uint32_t steps);
 
 /* Parity hooks (device pointers, enqueued on the stream):
  * forward of n rows of 32 FP32 features -> n x 40 FP32 outputs; */

@@ -29,6 +29,7 @@ constexpr int kGB[4] = {0, 0, 16, 32};         // first transposed fragment (lay
 constexpr int kOffW[4] = {0, 2112, 6272, 10432};
 constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
 constexpr int kTrainBlock = 256;               // 4 waves
+static_assert(kTrainBlock == 256, "the per-block weight and loss sums add four waves");
 
 // round to the nearest BF16, ties to even (v_cvt_pk_bf16_f32 on gfx950)
 __device__ __forceinline__ uint32_t bf16_rne(float f)
@@ -631,9 +632,17 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         wsum += __shfl_xor(wsum, off);
         lsum += __shfl_xor(lsum, off);
     }
+    // the block's weight and loss sums, in wave order (no atomics: the step
+    // is a deterministic function of its rows)
+    __shared__ float swl[2][kTrainBlock / 64];
     if (lane == 0) {
-        atomicAdd(&T.scalars[0], wsum);
-        atomicAdd(&T.scalars[1], lsum);
+        swl[0][wv] = wsum;
+        swl[1][wv] = lsum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T.scalars[2 + 2 * blockIdx.x] = (swl[0][0] + swl[0][1]) + (swl[0][2] + swl[0][3]);
+        T.scalars[3 + 2 * blockIdx.x] = (swl[1][0] + swl[1][1]) + (swl[1][2] + swl[1][3]);
     }
     // this block's gradient sums: every parameter written by exactly one lane
     float *out_p = T.partial + (size_t)blockIdx.x * kGuideParams;
@@ -686,7 +695,17 @@ __global__ __launch_bounds__(256) void k_guide_reduce(GuideTrain T, uint32_t blo
     __syncthreads();
     if (grp != 0 || p >= kGuideParams) return;
     g = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-    float ws = T.scalars[0];
+    // the weight sum over the training blocks in block order (every thread
+    // forms the same sum); one thread keeps it and the loss sum for readers
+    float ws = 0.0f, ls = 0.0f;
+    for (uint32_t b = 0; b < blocks; ++b) {
+        ws += T.scalars[2 + 2 * b];
+        ls += T.scalars[3 + 2 * b];
+    }
+    if (blockIdx.x == 0 && lane == 0) {
+        T.scalars[0] = ws;
+        T.scalars[1] = ls;
+    }
     g = ws > 0.0f ? g / ws : 0.0f;
     if (grad_out) grad_out[p] = g;
     if (!adam || !(ws > 0.0f)) return;

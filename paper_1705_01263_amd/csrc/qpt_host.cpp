@@ -972,7 +972,7 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.g_m = take(kGuideParams * 4);
     L.g_v = take(kGuideParams * 4);
     L.g_partial = take((size_t)c->guide_blocks * kGuideParams * 4);
-    L.g_scalars = take(2 * 4);
+    L.g_scalars = take((2 + 2 * (size_t)c->guide_blocks) * 4);  // totals, then per training block
     L.total = o;
     return L;
 }
@@ -1504,6 +1504,20 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     return QPT_OK;
 }
 
+int qpt_load_accum(qpt_ctx *c, const double *sum_rgb, const uint32_t *counts, int src_is_device)
+{
+    if (!c || !sum_rgb || !counts) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "load_accum before bind_workspace");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
+    const size_t npix = (size_t)c->W * c->H;
+    const hipMemcpyKind k = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(c, hipMemcpyAsync(c->pool.fb_sum, sum_rgb, npix * 3 * 8, k, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->pool.fb_count, counts, npix * 4, k, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return QPT_OK;
+}
+
 int qpt_reset_accum(qpt_ctx *c)
 {
     if (!c) return QPT_E_INVALID;
@@ -1800,6 +1814,37 @@ int qpt_guide_set_weights(qpt_ctx *c, const float *params)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->guide_weights = true;
     c->guide_steps = 0;
+    return QPT_OK;
+}
+
+int qpt_guide_get_state(qpt_ctx *c, float *params, float *m, float *v, uint32_t *steps)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
+    DeviceGuard g(c->device);
+    HIP_TRY(c, join_train(c));
+    if (params) HIP_TRY(c, hipMemcpyAsync(params, c->gt.master, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
+    if (m) HIP_TRY(c, hipMemcpyAsync(m, c->gt.m, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
+    if (v) HIP_TRY(c, hipMemcpyAsync(v, c->gt.v, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (steps) *steps = c->guide_steps;
+    return QPT_OK;
+}
+
+int qpt_guide_set_state(qpt_ctx *c, const float *params, const float *m, const float *v, uint32_t steps)
+{
+    if (!c || !params || !m || !v) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "guide state before bind_workspace");
+    for (uint32_t p = 0; p < kGuideParams; ++p)
+        if (!std::isfinite(params[p]) || !std::isfinite(m[p]) || !(v[p] >= 0.0f) || !std::isfinite(v[p]))
+            return fail(c, QPT_E_INVALID, "guide state must be finite (second moments >= 0)");
+    int rc = qpt_guide_set_weights(c, params);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, hipMemcpyAsync(c->gt.m, m, kGuideParams * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->gt.v, v, kGuideParams * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->guide_steps = steps;
     return QPT_OK;
 }
 

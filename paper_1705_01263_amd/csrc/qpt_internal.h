@@ -192,7 +192,7 @@ struct GuideTrain {
     uint32_t *ring_head;     // samples ever appended (the ring keeps the last ring_cap)
     uint32_t ring_cap;       // a power of two
     float *partial;          // blocks x kGuideParams unnormalised gradient sums
-    float *scalars;          // [0] sum of loss weights [1] weighted loss sum
+    float *scalars;          // [0] sum of loss weights [1] weighted loss sum; then both per training block
     uint32_t max_blocks;
 };
 

@@ -74,7 +74,8 @@ EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
-    "qpt_abort", "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
+    "qpt_abort", "qpt_load_accum", "qpt_guide_get_state", "qpt_guide_set_state",
+    "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
     "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_eval", "qpt_guide_debug_grad",
     "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
@@ -112,6 +113,9 @@ def lib():
             "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P], i32),
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
             "qpt_abort": ([P], i32),
+            "qpt_load_accum": ([P, P, P, i32], i32),
+            "qpt_guide_get_state": ([P, P, P, P, C.POINTER(C.c_uint32)], i32),
+            "qpt_guide_set_state": ([P, P, P, P, u32], i32),
             "qpt_debug_light_tree": ([P, P, P, P, P, P, P, P, C.POINTER(C.c_uint32)], i32),
             "qpt_debug_light_sample": ([P, P, P, P, u32, P, P, P], i32),
             "qpt_debug_env_pyramid": ([P, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), P, P],
@@ -240,6 +244,21 @@ class Context:
 
     def abort(self) -> None:
         self.check(self.L.qpt_abort(self.h), "qpt_abort")
+
+    def load_accum(self, sum_rgb, counts, src_is_device: bool = False) -> None:
+        self.check(self.L.qpt_load_accum(self.h, _p(sum_rgb), _p(counts), int(src_is_device)), "qpt_load_accum")
+
+    def guide_get_state(self):
+        """(params, m, v, steps) of the guide's optimiser."""
+        p, m, v = (np.empty(GUIDE_PARAMS, np.float32) for _ in range(3))
+        st = C.c_uint32()
+        self.check(self.L.qpt_guide_get_state(self.h, _p(p), _p(m), _p(v), C.byref(st)), "qpt_guide_get_state")
+        return p, m, v, st.value
+
+    def guide_set_state(self, params, m, v, steps) -> None:
+        p, m, v = (np.ascontiguousarray(a, np.float32) for a in (params, m, v))
+        assert p.shape == m.shape == v.shape == (GUIDE_PARAMS,)
+        self.check(self.L.qpt_guide_set_state(self.h, _p(p), _p(m), _p(v), int(steps)), "qpt_guide_set_state")
 
     def reset_accum(self) -> None:
         self.check(self.L.qpt_reset_accum(self.h), "qpt_reset_accum")
