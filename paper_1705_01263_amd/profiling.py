@@ -11,6 +11,9 @@ kernel of known size in the same run.
 `python -m paper_1705_01263_amd.profiling mfma <pmc_dir> <out.txt> --cmd "..."` summarises
 BF16 MFMA FLOPs and MFMA busy cycles of the network kernels.
 
+`python -m paper_1705_01263_amd.profiling sweep <out.txt> [--min-log2 A --max-log2 B]` measures
+throughput against the path pool size, one batch at a time and two in flight.
+
 `python -m paper_1705_01263_amd.profiling guided [--size WxH --tris N --passes K]`
 runs a guided, training workload on the slit scene to be profiled.
 """
@@ -160,6 +163,53 @@ def run_guided(width: int, height: int, tris: int, passes: int, alpha: float = 0
     print(f"guided: {passes} passes of {sc.name} {width}x{height}, {steps} Adam steps", flush=True)
 
 
+def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
+    """Passes per launch sequence against throughput (the paper's Table 1 in
+    kind): the grid workload at 1080p with path pools from 2^min_log2 to
+    2^max_log2 slots, one batch at a time and two in flight; each setting
+    renders two pools' worth of passes (at least 8) after one untimed batch."""
+    import time
+
+    import torch
+
+    import scenegen
+    from paper_1705_01263_amd import Renderer
+
+    sc = scenegen.make_config(1)
+    npix = sc.width * sc.height
+    lines = ["# passes per launch sequence against throughput (grid, 0.97M triangles, 1920x1080, depth 12)",
+             f"command: {cmd}", f"kernel_source_sha: {kernel_sha()}", "",
+             f"{'pool (paths)':>14} {'frames/batch':>13} {'passes':>7} {'one stream Mrays/s':>19} "
+             f"{'two in flight Mrays/s':>22} {'Mpaths/s (two)':>15}"]
+    for lg in range(min_log2, max_log2 + 1):
+        pool = 1 << lg
+        frames = pool / npix
+        per = max(1, pool // npix)
+        passes = max(8, 2 * per)
+        r = Renderer(sc, pool_paths=pool)
+        res = []
+        for single in (True, False):
+            r.reset()
+            r.render(0, per, single_stream=single)
+            torch.cuda.synchronize()
+            st0 = r.stats()
+            t0 = time.perf_counter()
+            r.render(per, passes, single_stream=single)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st1 = r.stats()
+            rays = (st1.rays_extension - st0.rays_extension) + (st1.rays_shadow - st0.rays_shadow)
+            res.append((rays / dt / 1e6, passes * npix / dt / 1e6))
+        del r
+        torch.cuda.empty_cache()
+        lines.append(f"{'2^%d' % lg:>14} {frames:>13.3f} {passes:>7} {res[0][0]:>19.1f} {res[1][0]:>22.1f} "
+                     f"{res[1][1]:>15.1f}")
+        print(lines[-1], flush=True)
+    txt = "\n".join(lines) + "\n"
+    open(out_txt, "w").write(txt)
+    return txt
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -179,6 +229,10 @@ def main():
     m.add_argument("out")
     m.add_argument("--kernels", default="k_guide_eval,k_guide_train")
     m.add_argument("--cmd", required=True)
+    sw = sub.add_parser("sweep")
+    sw.add_argument("out")
+    sw.add_argument("--min-log2", type=int, default=15)
+    sw.add_argument("--max-log2", type=int, default=25)
     gd = sub.add_parser("guided")
     gd.add_argument("--size", default="1920x1080")
     gd.add_argument("--tris", type=int, default=4_000_000)
@@ -189,6 +243,10 @@ def main():
         print(summarize_trace(a.src, a.out, a.cmd))
     elif a.what == "pmc":
         print(summarize_pmc(a.fetch_dir, a.write_dir, a.kernel, a.out, a.calib_mib, a.cmd))
+    elif a.what == "sweep":
+        cmd = ("python -u -m paper_1705_01263_amd.profiling sweep " + a.out +
+               f" --min-log2 {a.min_log2} --max-log2 {a.max_log2}")
+        print(run_sweep(a.out, a.min_log2, a.max_log2, cmd))
     elif a.what == "mfma":
         print(summarize_mfma(a.pmc_dir, a.kernels.split(","), a.out, a.cmd))
     else:
