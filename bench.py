@@ -6,7 +6,7 @@ pixel: enumeration, Halton samples, camera rays, closest hit, emission with
 MIS, next-event estimation, BSDF sampling, roulette, occlusion, FP64
 accumulation), through the C-ABI on torch's current stream; the library runs
 two batches of passes at a time (that stream and one of its own, each with a
-path pool of four frames) and keeps the framebuffer updates in pass order.
+path pool of eight frames) and keeps the framebuffer updates in pass order.
 
 Workload: the seeded 0.97M-triangle grid of spheres and boxes (GGX over
 Lambert, 256 textured emitters), 1920x1080, max depth 12. Inputs are
@@ -36,10 +36,10 @@ METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "grid": (1, "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
-                "1 spp per step (passes batched four frames per launch sequence, two batches in flight), max depth 12, "
+                "1 spp per step (passes batched eight frames per launch sequence, two batches in flight), max depth 12, "
                 "NEE+MIS, roulette"),
     "city": (4, "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
-                "selection), 3840x2160, 1 spp per step (two frames per launch sequence, two batches in flight), max "
+                "selection), 3840x2160, 1 spp per step (four frames per launch sequence, two batches in flight), max "
                 "depth 16, NEE+MIS, roulette"),
 }
 GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 64, 2  # the guide mixes in after 64 Adam steps
@@ -175,10 +175,10 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             n = 0
-            # eight passes per call: two batches of four, the second overlapping the first's tail
+            # sixteen passes per call: two batches of eight, the second overlapping the first's tail
             while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
-                r.render(n, 8)
-                n += 8
+                r.render(n, 16)
+                n += 16
                 torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s, c = r.readback()
@@ -368,8 +368,8 @@ def env_select_equal_time(seconds: float, ref_passes: int, width: int, height: i
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=4, help="untimed passes (4 = one batch at 1080p)")
+    ap.add_argument("--steps", type=int, default=32, help="timed passes (32 = four batches at 1080p)")
+    ap.add_argument("--warmup", type=int, default=8, help="untimed passes (8 = one batch at 1080p)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
@@ -424,7 +424,7 @@ def main():
     bs = r.bvh_stats
     _say(f"bench: bvh nodes={bs.num_nodes} leaves={bs.num_leaves} depth={bs.max_depth} build={bs.build_ms:.0f} ms")
     # the passes go to the library as one range, which renders them in batches
-    # of as many whole passes as its path pool holds (four frames' worth)
+    # of as many whole passes as its path pool holds (eight frames' worth)
     r.render(0, args.warmup)
     torch.cuda.synchronize()
     _say(f"bench: warmup {args.warmup} passes done")
