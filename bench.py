@@ -269,10 +269,10 @@ def light_select_equal_time(r, sc, seconds: float, ref_passes: int):
                          "lit_pixel_fraction": round(float(lit.mean()), 4)}}
     budget = seconds
     for name, tree in (("alias_table", False), ("light_tree", True)):
-        # shading kernel per pass, event-timed over 8 passes
+        # shading kernel per pass, event-timed over 8 passes on one stream
         r.reset()
         r.ctx.profile(True)
-        r.render(1 << 26, 8, light_tree=tree)
+        r.render(1 << 26, 8, light_tree=tree, single_stream=True)
         r.ctx.profile(False)
         prof = r.ctx.profile_read()
         r.reset()
