@@ -779,7 +779,61 @@ __global__ void k_batch_begin(Pool P, const uint32_t *abort_word, uint32_t first
     }
 }
 
-// camera rays for slots [0, n): slot s -> pixel pix0 + s % npix, pass pass0 + s / npix
+// Position q of a whole frame in 8 x 8 tile order -> row-major pixel. Bands of
+// eight rows follow each other; inside a band the tiles go left to right and a
+// tile's pixels row by row; the last band and the last tile of a band are
+// narrower when H or W is not a multiple of 8. A bijection of [0, W H), so a
+// wave's 64 camera rays leave one compact block of the image.
+__device__ __forceinline__ uint32_t tile_pixel(uint32_t q, uint32_t W, uint32_t H)
+{
+    const uint32_t band = q / (8u * W);
+    const uint32_t r = q - band * 8u * W;
+    const uint32_t hy = min(8u, H - 8u * band);
+    const uint32_t tx = min(r / (8u * hy), (W - 1u) / 8u);
+    const uint32_t rem = r - tx * 8u * hy;
+    const uint32_t tw = min(8u, W - 8u * tx);
+    const uint32_t y = rem / tw;
+    return (8u * band + y) * W + 8u * tx + (rem - y * tw);
+}
+
+// Slots of a batch -> (position q in [0, npix), pass j in [0, npass)). A
+// whole-frame batch takes its positions in 8 x 8 tile order in groups of 64
+// (one wave) and lays out each group's npass passes next to each other: slot
+// = group * 64 npass + j * 64 + lane, the last group narrower when 64 does not
+// divide npix. Launches that stride over the slots then work on one band of
+// the image at a time, across every pass of the batch. Pixel chunks of a pass
+// larger than the pool (npass = 1) keep scanline order.
+struct SlotMap {
+    uint32_t full;  // complete groups of 64 positions
+    uint32_t tail;  // positions in the last, narrower group
+    uint32_t npass;
+};
+
+__device__ __forceinline__ SlotMap slot_map(uint32_t npix, uint32_t npass)
+{
+    return {npix / 64u, npix % 64u, npass};
+}
+
+__device__ __forceinline__ uint32_t slot_of(const SlotMap &m, uint32_t q, uint32_t j)
+{
+    const uint32_t g = q / 64u, lane = q % 64u;
+    const uint32_t w = g < m.full ? 64u : m.tail;
+    return g * 64u * m.npass + j * w + lane;
+}
+
+__device__ __forceinline__ void position_of(const SlotMap &m, uint32_t s, uint32_t &q, uint32_t &j)
+{
+    const uint32_t g = s / (64u * m.npass);
+    const uint32_t r = s - g * 64u * m.npass;
+    const uint32_t w = g < m.full ? 64u : m.tail;
+    j = r / w;
+    q = g * 64u + (r - j * w);
+}
+
+__device__ __forceinline__ bool whole_frame(const Frame &F, uint32_t npix) { return npix == F.W * F.H; }
+
+// camera rays for slots [0, n), n = npix npass: slot s -> (position, pass) as above,
+// pixel tile_pixel(position) of a whole frame, else pix0 + position
 __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint64_t pass0,
                                                      uint32_t n)
 {
@@ -787,8 +841,15 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
     uint32_t s = blockIdx.x * kBlock + threadIdx.x;
     if (s == 0) P.counters[1] = n;
     if (s >= n) return;
-    uint32_t pl = s % npix, j = s / npix;
-    uint32_t p = pix0 + pl;
+    uint32_t pl, j, p;
+    if (whole_frame(F, npix)) {
+        position_of(slot_map(npix, n / npix), s, pl, j);
+        p = tile_pixel(pl, F.W, F.H);
+    } else {
+        pl = s % npix;
+        j = s / npix;
+        p = pix0 + pl;
+    }
     uint32_t px = p % F.W, py = p / F.W;
     uint64_t i = pixel_index(F, px, py, pass0 + j);
     const float u0 = u24(sample_bits(F, i, 0, 0)), u1 = u24(sample_bits(F, i, 1, 0));
@@ -1175,10 +1236,12 @@ __global__ __launch_bounds__(kBlock) void k_accumulate(Frame F, Pool P, uint32_t
         P.stats[2] += (unsigned long long)npix * npass;
     }
     if (q >= npix) return;
-    uint32_t p = pix0 + q;
+    const bool whole = whole_frame(F, npix);
+    const SlotMap m = slot_map(npix, npass);
+    const uint32_t p = whole ? tile_pixel(q, F.W, F.H) : pix0 + q;
     double sx = P.fb_sum[3 * (size_t)p], sy = P.fb_sum[3 * (size_t)p + 1], sz = P.fb_sum[3 * (size_t)p + 2];
     for (uint32_t j = 0; j < npass; ++j) {
-        float4 L = P.rad[(size_t)j * npix + q];
+        float4 L = P.rad[whole ? slot_of(m, q, j) : (size_t)j * npix + q];
         sx += (double)L.x;
         sy += (double)L.y;
         sz += (double)L.z;

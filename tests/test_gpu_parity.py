@@ -328,15 +328,20 @@ def test_furnace_every_path(Renderer):
     assert np.allclose(s / c[:, None], want, rtol=2e-6)
 
 
-def test_pass_split_is_bit_identical(Renderer):
-    sc = g.cornell(width=64, height=48)
-    _say("[split] cornell 64x48, passes [0,8) vs [0,3)+[3,8) vs small pool")
+@pytest.mark.parametrize("W,H", [(64, 48), (61, 45)])
+def test_pass_split_is_bit_identical(Renderer, W, H):
+    """Whole-frame batches (pixels in 8 x 8 tile order, ragged tiles at the
+    right and bottom edges when W or H is not a multiple of 8) and pixel
+    chunks in scanline order give the same sums and counts bit for bit."""
+    sc = g.cornell(width=W, height=H)
+    _say(f"[split] cornell {W}x{H}, passes [0,8) vs [0,3)+[3,8) vs small pool")
     a, ca, r = _render(Renderer, sc, 8)
     r.reset()
     r.render(0, 3)
     r.render(3, 5)
     b, cb = r.readback()
     c_, cc, _ = _render(Renderer, sc, 8, pool_paths=1000)  # pixel chunks of 1000
+    assert np.all(ca == 8)
     assert np.array_equal(ca, cb) and np.array_equal(ca, cc)
     assert np.array_equal(a, b)
     assert np.array_equal(a, c_)
