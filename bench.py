@@ -35,16 +35,16 @@ sys.path.insert(0, ROOT)
 METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64 oracle"
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
-    "grid": (1, "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
+    "grid": ("grid_1m", "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
                 "1 spp per step (passes batched eight frames per launch sequence, two batches in flight), max depth 12, "
                 "NEE+MIS, roulette"),
-    "city": (4, "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
+    "city": ("city_16m", "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
                 "selection), 3840x2160, 1 spp per step (four frames per launch sequence, two batches in flight), max "
                 "depth 16, NEE+MIS, roulette"),
 }
 GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 64, 2  # the guide mixes in after 64 Adam steps
 
-# algorithmic bytes per unit of work ("Measurement")
+# algorithmic bytes per unit of work
 NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
 TRACE_RAY_BYTES = 4 + 32 + 16        # queue entry, ray (o, tmax, d), hit record
 SHADOW_RAY_BYTES = 48 + 32           # shadow ray + contribution, radiance read-modify-write
@@ -397,8 +397,8 @@ def main():
                     help="first copy a MIB-sized buffer once (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: measures one GPU (asked for --gpus {args.gpus}); "
+              "sharding over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -417,7 +417,7 @@ def main():
         torch.cuda.synchronize()
         _say(f"bench: copied {n} bytes for counter calibration")
         del src, dst
-    sc = scenegen.make_config(WORKLOADS[args.workload][0])
+    sc = scenegen.workload(WORKLOADS[args.workload][0])
     D = sc.max_depth
     _say(f"bench: scene {sc.name} tris={sc.num_triangles} {sc.width}x{sc.height} D={D}")
     r = Renderer(sc, device=0, bvh_builder=args.bvh_builder)

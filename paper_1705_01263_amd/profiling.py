@@ -175,7 +175,7 @@ def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
     import scenegen
     from paper_1705_01263_amd import Renderer
 
-    sc = scenegen.make_config(1)
+    sc = scenegen.workload("grid_1m")
     npix = sc.width * sc.height
     lines = ["# passes per launch sequence against throughput (grid, 0.97M triangles, 1920x1080, depth 12)",
              f"command: {cmd}", f"kernel_source_sha: {kernel_sha()}", "",

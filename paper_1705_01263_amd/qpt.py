@@ -93,7 +93,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1705_01263_amd.build")
         L = C.CDLL(LIB_PATH)
         P, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
         sig = {

@@ -607,21 +607,19 @@ def guide_init(seed: int = 7) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-CONFIGS = {
-    0: cornell,
-    1: grid_scene,
-    2: instanced_env_scene,
-    3: slit_scene,
-    4: city,
+# the named workloads, each with its fixed seed; the slit enclosure reuses the
+# instanced scene's seed (it is that scene plus a roof)
+WORKLOADS = {
+    "cornell": (cornell, 1),
+    "grid_1m": (grid_scene, 2),
+    "instanced_env_4m": (instanced_env_scene, 3),
+    "slit_enclosure": (slit_scene, 3),
+    "city_16m": (city, 5),
 }
 
 
-# the slit enclosure reuses the instanced scene's seed: it is that scene plus a roof
-SEEDS = {0: 1, 1: 2, 2: 3, 3: 3, 4: 5}
-
-
-def make_config(i: int, **kw) -> Scene:
-    """The five workload scenes, each from its fixed seed."""
-    fn = CONFIGS[i]
-    kw.setdefault("seed", SEEDS[i])
+def workload(name: str, **kw) -> Scene:
+    """One of the named workload scenes, from its fixed seed."""
+    fn, seed = WORKLOADS[name]
+    kw.setdefault("seed", seed)
     return fn(**kw)

@@ -39,7 +39,7 @@ def _dev(a):
 @pytest.mark.parametrize("which", ["cornell", "grid4", "quad", "city_sub"])
 def test_gpu_built_tree_structure(Renderer, which):
     from paper_1705_01263_amd import qpt
-    sc = {"cornell": lambda: g.make_config(0), "grid4": lambda: g.grid_scene(grid=4, width=64, height=64),
+    sc = {"cornell": lambda: g.workload("cornell"), "grid4": lambda: g.grid_scene(grid=4, width=64, height=64),
           "quad": lambda: g.quad_over_plane(),
           "city_sub": lambda: g.city(blocks=16, target_tris=1_000_000, emissive_cells=5000)}[which]()
     _say(f"[gpu bvh] structure {which} tris={sc.num_triangles}")
@@ -61,7 +61,7 @@ def test_gpu_built_tree_structure(Renderer, which):
 @pytest.mark.parametrize("which", ["cornell", "grid4"])
 def test_gpu_built_trace_bitexact(Renderer, orc, which):
     from test_gpu_parity import _ray_set
-    sc = g.make_config(0) if which == "cornell" else g.grid_scene(grid=4, width=64, height=64)
+    sc = g.workload("cornell") if which == "cornell" else g.grid_scene(grid=4, width=64, height=64)
     n = 20000 if which == "cornell" else 4000
     _say(f"[gpu bvh] trace {which} tris={sc.num_triangles} rays={n}")
     r = Renderer(sc, pool_paths=1 << 16, bvh_builder=1)
@@ -85,7 +85,7 @@ def test_gpu_built_trace_bitexact(Renderer, orc, which):
 
 @pytest.mark.parametrize("which", ["cornell", "grid"])
 def test_gpu_built_images_equal_host_built(Renderer, which):
-    sc = g.make_config(0) if which == "cornell" else g.make_config(1)
+    sc = g.workload("cornell") if which == "cornell" else g.workload("grid_1m")
     passes = 8 if which == "cornell" else 2
     _say(f"[gpu bvh] image {which} tris={sc.num_triangles} passes={passes}")
     out = []

@@ -25,7 +25,7 @@ def _dev(a, dtype=torch.float32):
 
 
 def test_framebuffer_resume(Renderer):
-    sc = g.make_config(0)
+    sc = g.workload("cornell")
     a = Renderer(sc)
     a.render(0, 10)
     s, c = a.readback()

@@ -92,7 +92,7 @@ def test_image_parity_sky(Renderer, orc, env_sampling, mode):
 def test_image_parity_env_subset(Renderer, orc):
     """The 4M-triangle instanced scene under the 2048 x 1024 sun-and-sky map,
     normal-weighted pyramid, every 8th pixel, 2 passes."""
-    sc = g.make_config(2)
+    sc = g.workload("instanced_env_4m")
     _say(f"[env pyramid] image env 1920x1080 tris={sc.num_triangles} passes=2 D=16")
     W, H = sc.width, sc.height
     ys, xs = np.meshgrid(np.arange(0, H, 8), np.arange(0, W, 8), indexing="ij")

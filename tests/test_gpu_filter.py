@@ -31,7 +31,7 @@ def Renderer():
 
 @pytest.mark.parametrize("mode", [0, 2])
 def test_image_parity_gauss(Renderer, orc, mode):
-    sc = g.make_config(0)
+    sc = g.workload("cornell")
     _say(f"[filter] cornell 128x128x16 gauss mode={mode}")
     r = Renderer(sc)
     r.render(0, sc.spp, mode=mode, gauss=True)

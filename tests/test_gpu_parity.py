@@ -107,7 +107,7 @@ def _ray_set(sc, n, seed):
 
 @pytest.mark.parametrize("which", ["cornell", "grid4"])
 def test_trace_bitexact(Renderer, orc, which):
-    sc = g.make_config(0) if which == "cornell" else g.grid_scene(grid=4, width=64, height=64)
+    sc = g.workload("cornell") if which == "cornell" else g.grid_scene(grid=4, width=64, height=64)
     n = 20000 if which == "cornell" else 4000
     _say(f"[trace] {which} tris={sc.num_triangles} rays={n}")
     r = Renderer(sc, pool_paths=1 << 16)
@@ -157,7 +157,7 @@ def test_trace_axis_rays_and_degenerate_triangles(Renderer, orc):
     """Rays exactly along +-x, +-y, +-z (reciprocal directions of 1e20 in the slab
     test) and rays aimed at a point-like, a collinear and a sliver triangle:
     ids, t and barycentrics bit-exact against the oracle's FP32 brute force."""
-    sc = _with_degenerate_triangles(g.make_config(0))
+    sc = _with_degenerate_triangles(g.workload("cornell"))
     rng = np.random.default_rng(21)
     n = 6000
     o = rng.uniform(0.02, 0.98, (n, 3))
@@ -244,7 +244,7 @@ def _render(Renderer, sc, passes, **kw):
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_image_parity_cornell(Renderer, orc, mode):
-    sc = g.make_config(0)
+    sc = g.workload("cornell")
     _say(f"[image] cornell 128x128x16 D=8 mode={mode}")
     s, c, _ = _render(Renderer, sc, sc.spp, mode=mode)
     assert np.all(c == sc.spp)
@@ -255,8 +255,8 @@ def test_image_parity_cornell(Renderer, orc, mode):
 
 
 def test_image_parity_grid_subset(Renderer, orc):
-    """configs[1] scene (0.97M tris, GGX, textured emitters) on every 8th pixel, 2 passes."""
-    sc = g.make_config(1)
+    """The 0.97M-triangle grid workload (GGX, textured emitters) at 1920 x 1080 on every 8th pixel, 2 passes."""
+    sc = g.workload("grid_1m")
     _say(f"[image] grid 1920x1080 tris={sc.num_triangles} passes=2 D=12")
     s, c, _ = _render(Renderer, sc, 2)
     W, H = sc.width, sc.height
@@ -271,7 +271,7 @@ def test_image_parity_grid_subset(Renderer, orc):
 
 def test_image_parity_env_subset(Renderer, orc):
     """4M-triangle instanced scene under the sun-and-sky map (2D CDF sampling), every 8th pixel."""
-    sc = g.make_config(2)
+    sc = g.workload("instanced_env_4m")
     _say(f"[image] env 1920x1080 tris={sc.num_triangles} passes=2 D=16")
     s, c, _ = _render(Renderer, sc, 2)
     W, H = sc.width, sc.height

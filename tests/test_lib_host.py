@@ -40,8 +40,8 @@ def test_call_order_and_errors(qpt):
     c = qpt.Context(-1)
     with pytest.raises(qpt.QptError):
         c.build_bvh()  # before build_scene
-    sc = g.make_config(0)
-    sc2 = g.make_config(0)
+    sc = g.workload("cornell")
+    sc2 = g.workload("cornell")
     sc2.indices = sc2.indices.copy()
     sc2.indices[0, 0] = 10_000  # out of range
     with pytest.raises(qpt.QptError):
@@ -57,7 +57,7 @@ def test_call_order_and_errors(qpt):
         c.render_pass(0, 1, 8)
 
 
-@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=2)])
+@pytest.mark.parametrize("make", [lambda: g.workload("cornell"), lambda: g.grid_scene(grid=2)])
 def test_light_tables_match_oracle(qpt, orc, make):
     sc = make()
     c = qpt.Context(-1)
@@ -82,7 +82,7 @@ def test_env_tables_match_oracle(qpt, orc):
     assert np.array_equal(pdf, opdf.astype(np.float32))
 
 
-@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=4),
+@pytest.mark.parametrize("make", [lambda: g.workload("cornell"), lambda: g.grid_scene(grid=4),
                                   lambda: g.quad_over_plane()])
 def test_bvh_structure(qpt, make):
     """The 4-wide tree: every triangle in exactly one leaf and inside its

@@ -39,7 +39,7 @@ def test_light_tables_grid_scene(orc):
 
 
 def test_untextured_flux_is_pi_area_luminance(orc):
-    sc = g.make_config(0)
+    sc = g.workload("cornell")
     S = orc.Scene(sc)
     L = S.lights()
     area = 0.25 * 0.25 / 2

@@ -23,7 +23,7 @@ def _rays32(o, d, tmax=np.inf):
 
 
 def test_axis_aligned_distance_exact(orc):
-    sc = g.make_config(0)
+    sc = g.workload("cornell")
     t, tri, _ = orc.trace_f32(sc, _rays32([0.25, 0.5, -1.0], [0.0, 0.0, 1.0]))
     assert t[0] == np.float32(2.0)
     assert tri[0] in (4, 5)  # the back wall z = 1
@@ -88,7 +88,7 @@ def _random_rays(sc, n, seed):
     return r
 
 
-@pytest.mark.parametrize("make", [lambda: g.make_config(0), lambda: g.grid_scene(grid=3)])
+@pytest.mark.parametrize("make", [lambda: g.workload("cornell"), lambda: g.grid_scene(grid=3)])
 def test_bvh_equals_brute_force_fp64(orc, make):
     sc = make()
     S = orc.Scene(sc)
