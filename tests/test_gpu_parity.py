@@ -301,6 +301,25 @@ def test_image_parity_city_subset(Renderer, orc):
     assert mean_e <= 1e-4 and frac <= 1e-3
 
 
+def test_image_parity_city_full_size(Renderer, orc):
+    """The 16M-triangle city at 3840 x 2160 in the benchmark's launch configuration (the
+    default pool: whole four-frame batches, two in flight), 2 passes, every 16th pixel in x
+    and y (32,400 pixels). The oracle builds its own BVH over all 16M triangles (about a
+    minute)."""
+    sc = g.workload("city_16m")
+    _say(f"[image] city 3840x2160 tris={sc.num_triangles} passes=2 D=16, default pool")
+    s, c, _ = _render(Renderer, sc, 2)
+    W, H = sc.width, sc.height
+    ys, xs = np.meshgrid(np.arange(5, H, 16), np.arange(3, W, 16), indexing="ij")
+    pix = (ys * W + xs).reshape(-1).astype(np.uint32)
+    _say("    oracle BVH build and render")
+    so, _, co, _ = orc.Scene(sc).render(pixels=pix, npasses=2)
+    mean_e, frac, e = orc.image_parity(s[pix], so)
+    _say(f"    mean rel err {mean_e:.3e}, pixels > 1e-3: {frac:.4%}, max {e.max():.3e}")
+    assert np.all(c == 2) and np.all(co == 2)
+    assert mean_e <= 1e-4 and frac <= 1e-3
+
+
 def test_constant_sky_every_path(Renderer):
     """Convex Lambert box under a constant sky: BSDF-sampled paths that hit it carry rho E exactly."""
     rho, E = 0.6, 2.0
