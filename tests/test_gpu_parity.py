@@ -284,6 +284,27 @@ def test_image_parity_env_subset(Renderer, orc):
     assert mean_e <= 1e-4 and frac <= 1e-3
 
 
+def test_image_parity_slit_full_size(Renderer, orc):
+    """The 4M-triangle slit enclosure (sun and sky through a 0.1-wide roof slit, the
+    equal-time workload) at 1920 x 1080 with the default pool, every 8th pixel. Most light
+    arrives over several bounces, so 64 passes, for enough lit samples (about 10% of the
+    pixels) to compare."""
+    sc = g.workload("slit_enclosure")
+    P = 64
+    _say(f"[image] slit 1920x1080 tris={sc.num_triangles} passes={P} D={sc.max_depth}")
+    s, c, _ = _render(Renderer, sc, P)
+    W, H = sc.width, sc.height
+    ys, xs = np.meshgrid(np.arange(3, H, 8), np.arange(5, W, 8), indexing="ij")
+    pix = (ys * W + xs).reshape(-1).astype(np.uint32)
+    so, _, co, _ = orc.Scene(sc).render(pixels=pix, npasses=P)
+    mean_e, frac, e = orc.image_parity(s[pix], so)
+    lit = float(np.mean(np.any(so > 0, axis=1)))
+    _say(f"    lit pixels {lit:.1%}, mean rel err {mean_e:.3e}, pixels > 1e-3: {frac:.4%}, max {e.max():.3e}")
+    assert np.all(c == P) and np.all(co == P)
+    assert lit > 0.05
+    assert mean_e <= 1e-4 and frac <= 1e-3
+
+
 def test_image_parity_city_subset(Renderer, orc):
     """The city generator at 1/16 of its blocks (about 1M triangles, 5,000 emissive window cells
     as triangle pairs, alias-table light selection) at the full 3840 x 2160: a pass exceeds the
