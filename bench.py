@@ -58,8 +58,12 @@ def _say(*a):
 
 
 def kernel_sha() -> str:
-    src = os.path.join(ROOT, "paper_1705_01263_amd", "csrc", "qpt_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """SHA of the path kernels and of the host side that builds the tree they
+    traverse and launches them: counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    for f in ("qpt_kernels.hip", "qpt_host.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_1705_01263_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def pmc_traffic(kernel: str, workload_tag: str):

@@ -83,7 +83,7 @@ typedef struct {
 } qpt_scene_desc;
 
 typedef struct {
-    uint32_t max_leaf_size;  /* triangles per leaf, 1..8 (0 = 4) */
+    uint32_t max_leaf_size;  /* triangles per leaf, 1..8 (0 = 3) */
     uint32_t sah_bins;       /* binned SAH bins, 4..64 (0 = 16) */
     uint32_t builder;        /* 0: binned SAH on the host; 1: linear BVH on the GPU (Morton order,
                                 Karras 2012), collapsed to the same 4-wide nodes on the device: a

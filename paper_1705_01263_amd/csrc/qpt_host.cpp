@@ -1158,7 +1158,9 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
     if (!c->scene_ok) return fail(c, QPT_E_STATE, "build_bvh before build_scene");
     c->bvh_ok = c->bound = false;
     auto t0 = std::chrono::steady_clock::now();
-    uint32_t leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 4;
+    // defaults: leaves of up to 3 triangles (measured: 2-3 trace 1-2% faster than 4, 6-8 up to
+    // 12% slower on the grid and city workloads), 16 bins (32 and 64 made no difference)
+    uint32_t leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 3;
     uint32_t bins = opts && opts->sah_bins ? opts->sah_bins : 16;
     const uint32_t builder = opts ? opts->builder : 0;
     if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64 || builder > 1) return fail(c, QPT_E_INVALID, "bad BVH options");

@@ -212,8 +212,9 @@ class Context:
         self.check(self.L.qpt_build_scene(self.h, C.byref(d)), "qpt_build_scene")
         self.W, self.H = sc.width, sc.height
 
-    def build_bvh(self, max_leaf_size: int = 4, sah_bins: int = 16, builder: int = 0) -> qpt_bvh_stats:
-        """builder 0: binned SAH on the host; 1: linear BVH on the GPU."""
+    def build_bvh(self, max_leaf_size: int = 0, sah_bins: int = 0, builder: int = 0) -> qpt_bvh_stats:
+        """builder 0: binned SAH on the host; 1: linear BVH on the GPU. Zero sizes take the
+        library's defaults (leaves of up to 3 triangles, 16 bins)."""
         o = qpt_bvh_opts(max_leaf_size, sah_bins, builder)
         st = qpt_bvh_stats()
         self.check(self.L.qpt_build_bvh(self.h, C.byref(o), C.byref(st)), "qpt_build_bvh")
