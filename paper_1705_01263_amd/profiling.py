@@ -46,6 +46,8 @@ def guide_sha() -> str:
 
 def _short(name: str) -> str:
     name = name.replace("qpt::(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
     return name.split("(")[0] if "(" in name else name
 
 
