@@ -11,7 +11,7 @@ namespace qpt {
 constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
 constexpr uint32_t kShortStack = 16;     // traversal stack entries per ray kept in LDS
 constexpr uint32_t kMaxTreeDepth = 32;   // depth limit of the binary build tree
-constexpr uint32_t kTravBlocksPerCU = 8; // traversal grid: 8 resident blocks x 4 waves per CU
+constexpr uint32_t kTravBlocksPerCU = 16; // traversal grid: 16 blocks of 4 waves per CU, twice what is resident
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
 constexpr uint32_t kNoHit = 0xffffffffu;
 // per-lane counter words beyond the queue counts: the abort decision latched

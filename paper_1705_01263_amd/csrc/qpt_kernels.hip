@@ -877,8 +877,9 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
     P.q_ext[1][s] = s;
 }
 
-// closest hit for the extension rays queued at depth v; the grid is sized to
-// what is resident on the chip and strides over the queue
+// closest hit for the extension rays queued at depth v; the grid holds twice
+// what is resident on the chip (a block that finishes early makes room for
+// one that has not started) and strides over the queue
 __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v)
 {
     __shared__ int stk[kShortStack * kBlock];
