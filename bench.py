@@ -495,7 +495,7 @@ def main():
         launch_s = ms / n_l * 1e-3
         per_launch = rb[dom] / n_l
         achieved = per_launch / launch_s / 1e9
-        traffic = pmc_traffic(f"k_{dom}", "grid_1m") if args.workload == "grid" else None
+        traffic = pmc_traffic(f"k_{dom}", WORKLOADS[args.workload][0])
         roof = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
