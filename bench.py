@@ -6,7 +6,7 @@ pixel: enumeration, Halton samples, camera rays, closest hit, emission with
 MIS, next-event estimation, BSDF sampling, roulette, occlusion, FP64
 accumulation), through the C-ABI on torch's current stream; the library runs
 two batches of passes at a time (that stream and one of its own, each with a
-path pool of eight frames) and keeps the framebuffer updates in pass order.
+path pool of sixteen frames) and keeps the framebuffer updates in pass order.
 
 Workload: the seeded 0.97M-triangle grid of spheres and boxes (GGX over
 Lambert, 256 textured emitters), 1920x1080, max depth 12. Inputs are
@@ -36,10 +36,10 @@ METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "grid": ("grid_1m", "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
-                "1 spp per step (passes batched eight frames per launch sequence, two batches in flight), max depth 12, "
+                "1 spp per step (passes batched sixteen frames per launch sequence, two batches in flight), max depth 12, "
                 "NEE+MIS, roulette"),
     "city": ("city_16m", "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
-                "selection), 3840x2160, 1 spp per step (four frames per launch sequence, two batches in flight), max "
+                "selection), 3840x2160, 1 spp per step (eight frames per launch sequence, two batches in flight), max "
                 "depth 16, NEE+MIS, roulette"),
 }
 GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 64, 2  # the guide mixes in after 64 Adam steps
@@ -179,10 +179,10 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             n = 0
-            # sixteen passes per call: two batches of eight, the second overlapping the first's tail
+            # 32 passes per call: two batches of sixteen, the second overlapping the first's tail
             while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
-                r.render(n, 16)
-                n += 16
+                r.render(n, 32)
+                n += 32
                 torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s, c = r.readback()

@@ -177,8 +177,8 @@ int qpt_build_scene(qpt_ctx *ctx, const qpt_scene_desc *desc);
 int qpt_build_bvh(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
 
 /* Bytes of device workspace needed for `pool_paths` concurrent paths per
- * batch (0 = eight frames' worth: the smallest power of two >= 8 W H, within
- * [2^16, 2^25]). Passes are rendered in batches of as many whole passes as the
+ * batch (0 = sixteen frames' worth: the smallest power of two >= 16 W H,
+ * within [2^16, 2^26]). Passes are rendered in batches of as many whole passes as the
  * pool holds (or in pixel chunks of one pass when a frame exceeds it); larger
  * batches keep the queues of deep vertices full. The workspace holds two such
  * pools, one per batch in flight. Scene, BVH, path state, queues and

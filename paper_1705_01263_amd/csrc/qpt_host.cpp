@@ -889,13 +889,14 @@ void set_frame_constants(qpt_ctx *c)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// paths per batch when the caller leaves it to the library: eight frames'
-// worth (a power of two in [2^16, 2^25]); batches of several one-sample
+// paths per batch when the caller leaves it to the library: sixteen frames'
+// worth (a power of two in [2^16, 2^26]; two such pools take 16 GB at 1080p
+// and 33 GB at 4K with the guide's buffers); batches of several one-sample
 // passes keep the short queues of deep vertices full
 uint32_t default_pool(const qpt_ctx *c)
 {
-    uint64_t want = 8ull * c->W * c->H, cap = 1u << 16;
-    while (cap < want && cap < (1u << 25)) cap <<= 1;
+    uint64_t want = 16ull * c->W * c->H, cap = 1u << 16;
+    while (cap < want && cap < (1u << 26)) cap <<= 1;
     return (uint32_t)cap;
 }
 

@@ -324,7 +324,7 @@ def test_image_parity_city_subset(Renderer, orc):
 
 def test_image_parity_city_full_size(Renderer, orc):
     """The 16M-triangle city at 3840 x 2160 in the benchmark's launch configuration (the
-    default pool: whole four-frame batches, two in flight), 2 passes, every 16th pixel in x
+    default pool: eight-frame batches, two in flight), 2 passes, every 16th pixel in x
     and y (32,400 pixels). The oracle builds its own BVH over all 16M triangles (about a
     minute)."""
     sc = g.workload("city_16m")
