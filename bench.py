@@ -373,7 +373,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=32, help="timed passes (32 = four batches at 1080p)")
-    ap.add_argument("--warmup", type=int, default=8, help="untimed passes (8 = one batch at 1080p)")
+    ap.add_argument("--warmup", type=int, default=16, help="untimed passes (16 = one batch at 1080p)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
