@@ -91,6 +91,19 @@ def lib():
         L.or_light_tree_left_q.restype = u32
         L.or_ggx_D.argtypes = [C.c_double, C.c_double]
         L.or_ggx_D.restype = C.c_double
+        L.or_round_bf16.argtypes = [C.c_double]
+        L.or_round_bf16.restype = C.c_double
+        L.or_round_fp16.argtypes = [C.c_double]
+        L.or_round_fp16.restype = C.c_double
+        L.or_guide_set.argtypes = [P, P, u32, u32, u32]
+        L.or_guide_mix.argtypes = [P, P, P, u32, P]
+        L.or_guide_forward.argtypes = [P, P, P, u32, P, P]
+        L.or_guide_mix_eval.argtypes = [P, P, P, u32, P, P]
+        L.or_plant.argtypes = [i32]
+        L.or_rec_hash.argtypes = [u64, u32]
+        L.or_rec_hash.restype = u32
+        L.or_records.argtypes = [P, u32, u32, u32, u32, P, u32, u64, u32, P, P, u32, P, u32]
+        L.or_records.restype = u32
         _lib = L
     return _lib
 
@@ -305,14 +318,66 @@ class Scene:
         lib().or_trace64(self.h, _p(rays), n, int(any_hit), int(brute), _p(t), _p(tri))
         return t, tri
 
+    def guide_set(self, params, alpha: float = 0.0, max_vertex: int = 0, rec_thr: int = 0xFFFFFFFF):
+        """Load a frozen guide (13032 FP32 parameters, rounded to BF16 here),
+        mixed in with probability alpha (its integer threshold round(alpha 2^32))
+        at vertices 1..max_vertex (0 = all) when a render passes guide=True."""
+        par = np.ascontiguousarray(params, np.float32)
+        assert par.shape == (13032,)
+        thr = min(int(round(float(alpha) * 2.0 ** 32)), 0xFFFFFFFF)
+        lib().or_guide_set(self.h, _p(par), thr, int(max_vertex), int(rec_thr))
+        self.guide_alpha_thr = thr
+
+    def guide_mix(self, x, wo):
+        """The frozen guide's mixture at vertices x with outgoing wo: weights (n x 8),
+        means (n x 8 x 3), concentrations (n x 8), after the FP16 storage step."""
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        wo = np.ascontiguousarray(wo, np.float64).reshape(-1, 3)
+        out = np.empty((x.shape[0], 40))
+        lib().or_guide_mix(self.h, _p(x), _p(wo), x.shape[0], _p(out))
+        lob = out[:, 8:].reshape(-1, 8, 4)
+        return out[:, :8], lob[:, :, :3], lob[:, :, 3]
+
+    def guide_forward(self, x, wo):
+        """Features (n x 32) and network outputs (n x 40) of the frozen guide."""
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        wo = np.ascontiguousarray(wo, np.float64).reshape(-1, 3)
+        f = np.empty((x.shape[0], 32))
+        o = np.empty((x.shape[0], 40))
+        lib().or_guide_forward(self.h, _p(x), _p(wo), x.shape[0], _p(f), _p(o))
+        return f, o
+
+    def records(self, pixels=None, pass0=0, npasses=1, max_depth=None, rr=True, mode=0, scramble=True,
+                guide=True, nthreads=None, cap=1 << 22):
+        """Render like `render` and return (sums, counts, records): the
+        training records of every path (pixel, pass, vertex, x, wo, wi, pdf,
+        weight, and nee: the luminance-weighted quotient of the vertex's own
+        next-event estimate that the weight leaves out), in no particular order."""
+        sc = self.sc
+        mode = int(mode) | (0x1000 if guide else 0)
+        pix = None if pixels is None else np.ascontiguousarray(pixels, np.uint32)
+        npix = sc.width * sc.height if pix is None else pix.shape[0]
+        s = np.zeros((npix, 3))
+        cnt = np.zeros(npix, np.uint32)
+        out = np.empty((cap, 15))
+        n = lib().or_records(self.h, max_depth or sc.max_depth, int(rr), mode, int(scramble), _p(pix), npix,
+                             pass0, npasses, _p(s), _p(cnt), nthreads or os.cpu_count() or 1, _p(out), cap)
+        assert n <= cap, "record buffer too small"
+        o = out[:n]
+        rec = dict(pixel=o[:, 0].astype(np.int64), pass_=o[:, 1].astype(np.int64), vertex=o[:, 2].astype(np.int64),
+                   x=o[:, 3:6], wo=o[:, 6:9], wi=o[:, 9:12], pdf=o[:, 12], weight=o[:, 13], nee=o[:, 14])
+        return s, cnt, rec
+
     def render(self, pixels=None, pass0=0, npasses=1, max_depth=None, rr=True, mode=0,
-               scramble=True, nthreads=None, light_tree=False, env_sampling=0, gauss=False):
+               scramble=True, nthreads=None, light_tree=False, env_sampling=0, gauss=False, guide=False):
         """FP64 sums, sums of squares and counts for the listed pixel ids (y*W+x).
         light_tree selects triangle lights through the light tree instead of
         the flux alias table; env_sampling 1 / 2 samples the environment by its
         pyramid (2: with normal-weighted top levels) instead of the 2D CDF;
-        gauss draws film samples from the Gaussian pixel filter."""
-        mode = int(mode) | (0x100 if light_tree else 0) | (int(env_sampling) << 9) | (0x800 if gauss else 0)
+        gauss draws film samples from the Gaussian pixel filter; guide mixes in
+        the frozen guide of `guide_set`."""
+        mode = (int(mode) | (0x100 if light_tree else 0) | (int(env_sampling) << 9) | (0x800 if gauss else 0)
+                | (0x1000 if guide else 0))
         sc = self.sc
         if max_depth is None:
             max_depth = sc.max_depth
@@ -383,6 +448,48 @@ class Scene:
 
 def ggx_D(cos_h: float, alpha: float) -> float:
     return lib().or_ggx_D(cos_h, alpha)
+
+
+def round_bf16(x: float) -> float:
+    """Nearest BF16 value (ties to even) of an FP64 number."""
+    return lib().or_round_bf16(float(x))
+
+
+def round_fp16(x: float) -> float:
+    """Nearest FP16 value (ties to even) of an FP64 number."""
+    return lib().or_round_fp16(float(x))
+
+
+def plant(which: int) -> None:
+    """Plant a known mistake in the oracle (tests of the pins only; 0 = none):
+    1 = the guide's mixture density reported twice too large, 2 = record
+    weights not divided by the throughput before their vertex, 3 = record
+    weights that keep their vertex's own next-event estimate."""
+    lib().or_plant(int(which))
+
+
+def rec_hash(idx: int, v: int) -> int:
+    """The training-record hash of a path's sample index and a depth."""
+    return lib().or_rec_hash(int(idx), int(v))
+
+
+def guide_mix_eval(w, mu, kappa, dirs=None, u=None):
+    """Density at dirs and samples from u (n x 3) of n explicit mixtures
+    (weights n x 8, means n x 8 x 3, concentrations n x 8)."""
+    w = np.asarray(w, np.float64).reshape(-1, 8)
+    n = w.shape[0]
+    mix = np.empty((n, 40))
+    mix[:, :8] = w
+    lob = np.concatenate([np.asarray(mu, np.float64).reshape(n, 8, 3),
+                          np.asarray(kappa, np.float64).reshape(n, 8, 1)], axis=2)
+    mix[:, 8:] = lob.reshape(n, 32)
+    mix = np.ascontiguousarray(mix)
+    d = None if dirs is None else np.ascontiguousarray(dirs, np.float64).reshape(n, 3)
+    uu = None if u is None else np.ascontiguousarray(u, np.float64).reshape(n, 3)
+    pdf = np.empty(n) if d is not None else None
+    smp = np.empty((n, 3)) if uu is not None else None
+    lib().or_guide_mix_eval(_p(mix), _p(d), _p(uu), n, _p(pdf), _p(smp))
+    return pdf, smp
 
 
 def image_parity(gpu_sum, oracle_sum):

@@ -296,6 +296,13 @@ typedef struct {
     bnode *nodes;
     uint32_t nnodes;
     uint32_t *order;
+    /* bounding box of every input position (the guide's position encoding) */
+    double bmin[3], bext[3];
+    /* the learned proposal, frozen (or_guide_set): BF16-rounded parameters,
+     * the integer threshold of the guide choice, guided vertices 1..g_maxv,
+     * and the record subset threshold of the training-record hash */
+    double *g_par;
+    uint32_t g_alpha_thr, g_maxv, g_rec_thr;
 } or_scene;
 
 #define MAT_GGX 1u
@@ -1060,7 +1067,6 @@ or_scene *or_scene_create(uint32_t nv, const float *pos, uint32_t nt, const uint
                           uint32_t ew, uint32_t eh, const float *env, const double *cam,
                           uint32_t W, uint32_t H, int build_bvh)
 {
-    (void)nv;
     or_scene *s = (or_scene *)calloc(1, sizeof(or_scene));
     s->nt = nt;
     s->p0 = (v3 *)malloc(sizeof(v3) * nt);
@@ -1106,6 +1112,15 @@ or_scene *or_scene_create(uint32_t nv, const float *pos, uint32_t nt, const uint
     s->tan_half = tan(0.5 * cam[9] * M_PI / 180.0);
     s->W = W; s->H = H;
     s->aspect = (double)W / (double)H;
+    for (int a = 0; a < 3; ++a) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (uint32_t q = 0; q < nv; ++q) {
+            lo = fmin(lo, (double)pos[3 * q + a]);
+            hi = fmax(hi, (double)pos[3 * q + a]);
+        }
+        s->bmin[a] = nv ? lo : 0.0;
+        s->bext[a] = nv ? fmax(hi - lo, 1e-6) : 1.0;
+    }
     if (build_bvh && nt) {
         s->nodes = (bnode *)malloc(sizeof(bnode) * 2 * nt);
         s->order = (uint32_t *)malloc(sizeof(uint32_t) * nt);
@@ -1129,6 +1144,7 @@ void or_scene_destroy(or_scene *s)
     free(s->env); free(s->row_q); free(s->col_q); free(s->env_texel_pdf);
     free(s->ep_q); free(s->ep_oq);
     free(s->nodes); free(s->order);
+    free(s->g_par);
     free(s);
 }
 
@@ -1316,6 +1332,219 @@ static double offset1(double p, double n)
 }
 static v3 offset_ray(v3 p, v3 n) { return V3(offset1(p.x, n.x), offset1(p.y, n.y), offset1(p.z, n.z)); }
 
+/* ------------------------------------------- the learned proposal (frozen)
+ *
+ * Not in the paper: the workload extends its importance sampling (Sec. 2.1,
+ * 2.2) by a directional proposal learned from the renderer's own samples and
+ * mixed one-sided with BSDF sampling under multiple importance sampling. The
+ * oracle evaluates a FROZEN network (parameters given by the caller) step by
+ * step as the design readings define it:
+ *   - features: the hit position normalised to the scene's box, and the
+ *     outgoing direction's polar angle (from +y, over pi) and azimuth
+ *     (atan2(x, -z) over 2 pi, in [0, 1)); sin and cos of 2^o pi x_a for
+ *     o = 0..3 per axis, then of pi th, 2 pi th, 2 pi ph, 4 pi ph;
+ *   - network 32 -> 64 -> 64 -> 64 -> 40, ReLU on the hidden layers, weights,
+ *     biases, inputs and hidden activations rounded to BF16 (ties to even),
+ *     sums in FP64 (the kernels sum in FP32);
+ *   - decode per lobe k (outputs 5k..5k+4: logit, mean xyz, concentration):
+ *     softmax weights, unit means, kappa = min(softplus + 1e-3, 1e4);
+ *   - the proposal is the mixture these parameters define after rounding
+ *     them to FP16 (ties to even), with the rounded means and weights
+ *     renormalised: any density gives an unbiased estimator, and this is the
+ *     one the renderer stores per path vertex;
+ *   - vMF lobe density kappa / (2 pi (1 - e^-2kappa)) e^(kappa (mu.w - 1));
+ *     sampling: the lobe is the first k whose cumulative weight exceeds u,
+ *     the cosine to the mean w = 1 + log(u1 + (1 - u1) e^-2kappa) / kappa
+ *     (Jakob 2012), the azimuth 2 pi u2 in a Duff et al. 2017 frame;
+ *   - one-sample mixture: the guide is taken iff the 32-bit sample of slot 3
+ *     is below alpha 2^32 (an integer threshold), the rest of that sample,
+ *     rescaled to [0, 2^32), picks the lobe (or the BSDF's own lobe); the
+ *     density is alpha q + (1 - alpha) p_bsdf, used in the throughput and in
+ *     both power-heuristic weights against next-event estimation. */
+
+#define G_LOBES 8
+static const int g_sizes[5] = {32, 64, 64, 64, 40};
+
+/* round to the binary format with `bits` significand bits (hidden bit
+ * included) whose smallest subnormal step is 2^sub, ties to even */
+static double round_fmt(double x, int bits, int sub)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    frexp(x, &e);                       /* |x| in [2^(e-1), 2^e) */
+    int q = e - bits;                   /* exponent of the last kept bit */
+    if (q < sub) q = sub;
+    return ldexp(nearbyint(ldexp(x, -q)), q);   /* default rounding: to nearest, ties to even */
+}
+double or_round_bf16(double x) { return round_fmt(x, 8, -133); }
+double or_round_fp16(double x) { return round_fmt(x, 11, -24); }
+
+/* Load a frozen guide: FP32 parameters (13032: per layer W (in x out,
+ * row-major) then b), alpha as its integer threshold (guide iff slot-3 bits
+ * < alpha_thr; 0 = off), guided vertices 1..max_vertex (0 = all) and the
+ * record-hash threshold (records of vertices whose hash is below it;
+ * 0xffffffff = all). */
+void or_guide_set(or_scene *s, const float *par, uint32_t alpha_thr, uint32_t max_vertex, uint32_t rec_thr)
+{
+    size_t n = 0;
+    for (int l = 0; l < 4; ++l) n += (size_t)g_sizes[l] * g_sizes[l + 1] + g_sizes[l + 1];
+    free(s->g_par);
+    s->g_par = (double *)malloc(sizeof(double) * n);
+    for (size_t k = 0; k < n; ++k) s->g_par[k] = or_round_bf16((double)par[k]);
+    s->g_alpha_thr = alpha_thr;
+    s->g_maxv = max_vertex ? max_vertex : 0xffffffffu;
+    s->g_rec_thr = rec_thr;
+}
+
+static void guide_features(const or_scene *s, v3 x, v3 wo, double f[32])
+{
+    double xh[3] = {(x.x - s->bmin[0]) / s->bext[0], (x.y - s->bmin[1]) / s->bext[1],
+                    (x.z - s->bmin[2]) / s->bext[2]};
+    for (int a = 0; a < 3; ++a)
+        for (int o = 0; o < 4; ++o) {
+            double ang = ldexp(M_PI, o) * xh[a];
+            f[8 * a + 2 * o] = sin(ang);
+            f[8 * a + 2 * o + 1] = cos(ang);
+        }
+    double th = acos(fmax(-1.0, fmin(1.0, wo.y))) / M_PI;
+    double ph = atan2(wo.x, -wo.z);
+    if (ph < 0.0) ph += 2.0 * M_PI;
+    ph /= 2.0 * M_PI;
+    double ang[4] = {M_PI * th, 2.0 * M_PI * th, 2.0 * M_PI * ph, 4.0 * M_PI * ph};
+    for (int j = 0; j < 4; ++j) {
+        f[24 + 2 * j] = sin(ang[j]);
+        f[25 + 2 * j] = cos(ang[j]);
+    }
+}
+
+/* network outputs for 32 features (BF16 rounding points as stated above) */
+static void guide_forward(const or_scene *s, const double feat[32], double out[40])
+{
+    double a[64], z[64];
+    for (int i = 0; i < 32; ++i) a[i] = or_round_bf16(feat[i]);
+    const double *p = s->g_par;
+    for (int l = 0; l < 4; ++l) {
+        const int fi = g_sizes[l], fo = g_sizes[l + 1];
+        const double *Wl = p, *bl = p + (size_t)fi * fo;
+        for (int o = 0; o < fo; ++o) {
+            double acc = bl[o];
+            for (int i = 0; i < fi; ++i) acc += a[i] * Wl[(size_t)i * fo + o];
+            z[o] = acc;
+        }
+        p = bl + fo;
+        if (l < 3)
+            for (int o = 0; o < fo; ++o) a[o] = or_round_bf16(z[o] > 0.0 ? z[o] : 0.0);
+        else
+            for (int o = 0; o < fo; ++o) out[o] = z[o];
+    }
+}
+
+typedef struct {
+    double w[G_LOBES];      /* lobe weights, sum 1 */
+    v3 mu[G_LOBES];         /* unit means */
+    double kappa[G_LOBES];
+} gmix;
+
+/* decode, then the FP16 storage of the proposal's parameters */
+static void guide_decode(const double out[40], gmix *m)
+{
+    double mx = out[0];
+    for (int k = 1; k < G_LOBES; ++k) mx = fmax(mx, out[5 * k]);
+    double e[G_LOBES], se = 0.0;
+    for (int k = 0; k < G_LOBES; ++k) {
+        e[k] = exp(out[5 * k] - mx);
+        se += e[k];
+    }
+    double wsum = 0.0;
+    for (int k = 0; k < G_LOBES; ++k) {
+        const double *o = out + 5 * k;
+        double n = fmax(sqrt(o[1] * o[1] + o[2] * o[2] + o[3] * o[3]), 1e-12);
+        double sp = o[4] > 30.0 ? o[4] : log1p(exp(o[4]));
+        double kap = fmin(sp + 1e-3, 1e4);
+        v3 mu = V3(or_round_fp16(o[1] / n), or_round_fp16(o[2] / n), or_round_fp16(o[3] / n));
+        double mn = fmax(len(mu), 1e-12);
+        m->mu[k] = mul(mu, 1.0 / mn);
+        m->kappa[k] = or_round_fp16(kap);
+        m->w[k] = or_round_fp16(e[k] / se);
+        wsum += m->w[k];
+    }
+    for (int k = 0; k < G_LOBES; ++k) m->w[k] /= wsum;
+}
+
+static double vmf_pdf(v3 mu, double kappa, v3 w)
+{
+    return kappa / (2.0 * M_PI * -expm1(-2.0 * kappa)) * exp(kappa * (dot(mu, w) - 1.0));
+}
+
+/* A deliberately planted mistake, for tests that show the pins catch it
+ * (0 = none; 1: the mixture density reported twice too large; 2: record
+ * weights not divided by the throughput before the vertex; 3: record weights
+ * that keep the vertex's own next-event estimate). Not thread-safe
+ * to change while rendering. */
+static int g_plant = 0;
+void or_plant(int which) { g_plant = which; }
+
+static double gmix_pdf(const gmix *m, v3 w)
+{
+    double q = 0.0;
+    for (int k = 0; k < G_LOBES; ++k) q += m->w[k] * vmf_pdf(m->mu[k], m->kappa[k], w);
+    return g_plant == 1 ? 2.0 * q : q;
+}
+
+static v3 gmix_sample(const gmix *m, double u, double u1, double u2)
+{
+    int k = G_LOBES - 1;
+    double c = 0.0;
+    for (int j = 0; j < G_LOBES - 1; ++j) {
+        c += m->w[j];
+        if (u < c) {
+            k = j;
+            break;
+        }
+    }
+    double kap = m->kappa[k];
+    double w = 1.0 + log(u1 + (1.0 - u1) * exp(-2.0 * kap)) / kap;
+    w = fmax(-1.0, fmin(1.0, w));
+    v3 t1, t2;
+    onb(m->mu[k], &t1, &t2);
+    double r = sqrt(fmax(0.0, 1.0 - w * w)), ph = 2.0 * M_PI * u2;
+    return add(mul(m->mu[k], w), add(mul(t1, r * cos(ph)), mul(t2, r * sin(ph))));
+}
+
+static void guide_mixture(const or_scene *s, v3 x, v3 wo, gmix *m)
+{
+    double f[32], out[40];
+    guide_features(s, x, wo, f);
+    guide_forward(s, f, out);
+    guide_decode(out, m);
+}
+
+/* which vertices leave a training record: the splitmix64 finaliser of the
+ * path's sample index and the depth, top 32 bits */
+static uint32_t rec_hash(uint64_t idx, uint32_t v)
+{
+    uint64_t z = idx * 0x9E3779B97F4A7C15ull + (uint64_t)v * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return (uint32_t)((z ^ (z >> 31)) >> 32);
+}
+
+/* Training record of a guided-depth vertex whose path continues: position,
+ * directions, the mixture density of the sampled direction, and the parts
+ * its weight is formed from at the path's end (radiance before the vertex's
+ * next-event estimate, that estimate, throughput before the scattering with
+ * roulette folded in). Weight = sum_c lum_c max(0, (L_end - L_before - NEE)_c
+ * / T_c) over the channels with T_c > 0: the sample's own estimate
+ * f cos L_i / p of the scattering integral. */
+typedef struct {
+    uint32_t v;
+    v3 x, wo, wi;
+    double pdf;
+    v3 Lb, nee, Tb;
+} grec;
+
+#define G_MAX_REC 256
+
 typedef struct {
     uint32_t max_depth;
     uint32_t rr;        /* Russian roulette from vertex 3 */
@@ -1324,13 +1553,17 @@ typedef struct {
     uint32_t light_tree; /* select triangle lights through the light tree */
     uint32_t env_pyramid; /* 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels */
     uint32_t gauss;       /* film samples from a Gaussian around the pixel centre instead of the box */
+    uint32_t guide;       /* the frozen guide of or_guide_set mixes in (when its alpha is not 0) */
+    uint32_t record;      /* collect training records (guide vertices whose path continues) */
 } or_opts;
 
 /* the caller's mode word: MIS mode in the low byte, light tree in bit 8,
- * environment sampling in bits 9-10, Gaussian pixel filter in bit 11 */
+ * environment sampling in bits 9-10, Gaussian pixel filter in bit 11, the
+ * frozen guide in bit 12, training records in bit 13 */
 static or_opts make_opts(uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble)
 {
-    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u, (mode >> 9) & 3u, (mode >> 11) & 1u};
+    or_opts op = {max_depth, rr, mode & 0xffu, scramble, (mode >> 8) & 1u, (mode >> 9) & 3u, (mode >> 11) & 1u,
+                  (mode >> 12) & 1u, (mode >> 13) & 1u};
     return op;
 }
 
@@ -1349,8 +1582,9 @@ static void logv(double a, double b, double c, double d, double e, double f, dou
 
 /* radiance estimate of one path for sample index i through film point (fx, fy) */
 static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t px, uint32_t py,
-                     uint32_t *nrays)
+                     uint32_t *nrays, grec *recs, uint32_t *nrec)
 {
+    if (nrec) *nrec = 0;
     const uint32_t W = s->W, H = s->H;
     double u0 = u24(or_sample_bits(i, 0, W, H, 0)), u1 = u24(or_sample_bits(i, 1, W, H, 0));
     double fx = px + u0, fy = py + u1;
@@ -1372,6 +1606,8 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
     const int tree = op->light_tree && s->ne;
     const int pyr = op->env_pyramid && s->ep_m;
     const double p_tri = 1.0 - s->p_env;
+    const int gon = op->guide && s->g_par && s->g_alpha_thr;
+    const double alpha = gon ? (double)s->g_alpha_thr * 0x1p-32 : 0.0;
     for (uint32_t v = 1; v <= op->max_depth; ++v) {
         hit64 h;
         (*nrays)++;
@@ -1429,6 +1665,12 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
         v3 wo = mul(d, -1.0);
         v3 xo = offset_ray(x, n);
         uint32_t base = 2 + 8 * (v - 1);
+        /* the guide's mixture at this vertex */
+        const int guided = gon && v <= s->g_maxv;
+        gmix mix;
+        if (guided) guide_mixture(s, x, wo, &mix);
+        const v3 L_before = L;
+        v3 nee = V3(0, 0, 0);
         /* next-event estimation */
         if (op->mode != 1 && (s->ne || s->env)) {
             uint32_t s0 = or_sample_bits(i, base + 0, W, H, op->scramble);
@@ -1520,6 +1762,7 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
                     v3 f;
                     double pb;
                     bsdf_eval(s, m, n, wo, wi, &f, &pb);
+                    if (guided) pb = alpha * gmix_pdf(&mix, wi) + (1.0 - alpha) * pb;
                     double w = op->mode == 2 ? 1.0 : mis2(pl, pb);
                     v3 contrib = mul(vmul(vmul(T, f), Le), ci * w / pl);
                     if (maxc(contrib) > 0.0) {
@@ -1528,21 +1771,41 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
                         double tm = isinf(dist) ? INFINITY : dist * (1.0 - 1e-4);
                         int occ = trace64(s, xo, wi, tm, 1, 0, &sh);
                         logv(3, occ, contrib.x, contrib.y, contrib.z, pl, w, 0);
-                        if (!occ) L = add(L, contrib);
+                        if (!occ) {
+                            L = add(L, contrib);
+                            nee = contrib;
+                        }
                     }
                 }
             }
         }
-        /* continue the path by sampling the BSDF */
-        double u3 = u24(or_sample_bits(i, base + 3, W, H, op->scramble));
+        /* continue the path: slot 3 chooses guide or BSDF (guide iff its bits
+         * are below alpha 2^32) and, its remainder rescaled to [0, 2^32), the
+         * lobe; slots 4-5 the direction */
+        uint32_t s3 = or_sample_bits(i, base + 3, W, H, op->scramble);
+        int use_guide = guided && s3 < s->g_alpha_thr;
+        uint32_t r3 = s3;
+        if (guided) {
+            uint64_t lo = use_guide ? 0 : s->g_alpha_thr;
+            uint64_t range = use_guide ? s->g_alpha_thr : (1ull << 32) - s->g_alpha_thr;
+            r3 = (uint32_t)((((uint64_t)s3 - lo) << 32) / range);
+        }
+        double u3 = u24(r3);
         double u4 = u24(or_sample_bits(i, base + 4, W, H, op->scramble));
         double u5 = u24(or_sample_bits(i, base + 5, W, H, op->scramble));
         v3 wi;
-        if (!bsdf_sample(s, m, n, wo, u3, u4, u5, &wi)) break;
+        if (use_guide) {
+            wi = gmix_sample(&mix, u3, u4, u5);
+            if (!(dot(n, wi) > 0.0)) break;
+        } else if (!bsdf_sample(s, m, n, wo, u3, u4, u5, &wi)) {
+            break;
+        }
         v3 f;
         double pb;
         bsdf_eval(s, m, n, wo, wi, &f, &pb);
+        if (guided) pb = alpha * gmix_pdf(&mix, wi) + (1.0 - alpha) * pb;
         if (!(pb > 0.0)) break;
+        v3 Tb = T;
         T = vmul(T, mul(f, dot(n, wi) / pb));
         if (!(maxc(T) > 0.0)) break;
         prev_pdf = pb;
@@ -1554,11 +1817,43 @@ static v3 trace_path(const or_scene *s, const or_opts *op, uint64_t i, uint32_t 
             double u6 = u24(or_sample_bits(i, base + 6, W, H, op->scramble));
             if (!(u6 < qq)) break;
             T = mul(T, 1.0 / qq);
+            Tb = mul(Tb, 1.0 / qq);
+        }
+        if (op->record && recs && v <= s->g_maxv && *nrec < G_MAX_REC &&
+            (s->g_rec_thr == 0xffffffffu || rec_hash(i, v) < s->g_rec_thr)) {
+            grec *r = &recs[(*nrec)++];
+            r->v = v;
+            r->x = x;
+            r->wo = wo;
+            r->wi = wi;
+            r->pdf = pb;
+            r->Lb = L_before;
+            r->nee = nee;
+            r->Tb = Tb;
         }
         o = xo;
         d = wi;
     }
     return L;
+}
+
+/* the weight of a record once its path has ended with radiance L (and, in
+ * *nee_w, the same luminance-weighted quotient of the vertex's own next-event
+ * estimate, which the weight leaves out) */
+static double rec_weight(const grec *r, v3 L, double *nee_w)
+{
+    const double wl[3] = {0.2126, 0.7152, 0.0722};
+    const double Lc[3] = {L.x, L.y, L.z}, bc[3] = {r->Lb.x, r->Lb.y, r->Lb.z};
+    const double nc[3] = {r->nee.x, r->nee.y, r->nee.z}, tc[3] = {r->Tb.x, r->Tb.y, r->Tb.z};
+    double w = 0.0, wn = 0.0;
+    for (int c = 0; c < 3; ++c)
+        if (tc[c] > 0.0) {
+            double own = g_plant == 3 ? 0.0 : nc[c];
+            w += wl[c] * fmax(0.0, (Lc[c] - bc[c] - own) / (g_plant == 2 ? 1.0 : tc[c]));
+            wn += wl[c] * nc[c] / tc[c];
+        }
+    if (nee_w) *nee_w = wn;
+    return w;
 }
 
 typedef struct {
@@ -1573,7 +1868,13 @@ typedef struct {
     uint64_t rays;
     volatile uint32_t *next;
     pthread_mutex_t *mu;
+    double *rec_out;        /* training records (or_records), OR_REC_COLS doubles each */
+    uint32_t rec_cap, *rec_n;
 } job;
+
+/* columns of a record row: pixel id, pass, vertex, x (3), wo (3), wi (3),
+ * mixture density of wi, weight, the vertex's own NEE term */
+#define OR_REC_COLS 15
 
 static void *worker(void *arg)
 {
@@ -1592,9 +1893,24 @@ static void *worker(void *arg)
             uint32_t px = p % s->W, py = p / s->W;
             for (uint32_t j = 0; j < jb->npasses; ++j) {
                 uint64_t i = or_pixel_index(s->W, s->H, px, py, jb->pass0 + j);
-                uint32_t nr = 0;
-                v3 L = trace_path(s, jb->op, i, px, py, &nr);
+                uint32_t nr = 0, nrec = 0;
+                grec recs[G_MAX_REC];
+                v3 L = trace_path(s, jb->op, i, px, py, &nr, jb->rec_out ? recs : NULL, &nrec);
                 rays += nr;
+                if (jb->rec_out && nrec) {
+                    pthread_mutex_lock(jb->mu);
+                    for (uint32_t k = 0; k < nrec && *jb->rec_n < jb->rec_cap; ++k) {
+                        double *o = jb->rec_out + (size_t)(*jb->rec_n)++ * OR_REC_COLS;
+                        const grec *r = &recs[k];
+                        double wn;
+                        double w = rec_weight(r, L, &wn);
+                        double row[OR_REC_COLS] = {p, (double)(jb->pass0 + j), r->v, r->x.x, r->x.y, r->x.z,
+                                                   r->wo.x, r->wo.y, r->wo.z, r->wi.x, r->wi.y, r->wi.z, r->pdf,
+                                                   w, wn};
+                        memcpy(o, row, sizeof row);
+                    }
+                    pthread_mutex_unlock(jb->mu);
+                }
                 jb->sum[3 * q] += L.x; jb->sum[3 * q + 1] += L.y; jb->sum[3 * q + 2] += L.z;
                 if (jb->sumsq) {
                     jb->sumsq[3 * q] += L.x * L.x;
@@ -1612,10 +1928,10 @@ static void *worker(void *arg)
 /* Render passes [pass0, pass0 + npasses) for npix pixels (ids p = y*W + x,
  * or all pixels when pix is NULL). Adds into caller-zeroed sum/sumsq/count,
  * one entry per listed pixel. Returns the number of rays traced. */
-uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode,
-                   uint32_t scramble, const uint32_t *pix, uint32_t npix, uint64_t pass0,
-                   uint32_t npasses, double *sum, double *sumsq, uint32_t *count,
-                   uint32_t nthreads)
+static uint64_t render_jobs(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode,
+                            uint32_t scramble, const uint32_t *pix, uint32_t npix, uint64_t pass0,
+                            uint32_t npasses, double *sum, double *sumsq, uint32_t *count,
+                            uint32_t nthreads, double *rec_out, uint32_t rec_cap, uint32_t *rec_n)
 {
     or_opts op = make_opts(max_depth, rr, mode, scramble);
     if (nthreads < 1) nthreads = 1;
@@ -1626,7 +1942,8 @@ uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t 
     pthread_mutex_t mu;
     pthread_mutex_init(&mu, NULL);
     for (uint32_t k = 0; k < nthreads; ++k) {
-        jobs[k] = (job){s, &op, pix, npix, pass0, npasses, sum, sumsq, count, 0, &next, &mu};
+        jobs[k] = (job){s, &op, pix, npix, pass0, npasses, sum, sumsq, count, 0, &next, &mu, rec_out, rec_cap,
+                        rec_n};
         pthread_create(&th[k], NULL, worker, &jobs[k]);
     }
     uint64_t rays = 0;
@@ -1636,6 +1953,29 @@ uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t 
     }
     pthread_mutex_destroy(&mu);
     return rays;
+}
+
+uint64_t or_render(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode,
+                   uint32_t scramble, const uint32_t *pix, uint32_t npix, uint64_t pass0,
+                   uint32_t npasses, double *sum, double *sumsq, uint32_t *count,
+                   uint32_t nthreads)
+{
+    return render_jobs(s, max_depth, rr, mode & ~(1u << 13), scramble, pix, npix, pass0, npasses, sum, sumsq,
+                       count, nthreads, NULL, 0, NULL);
+}
+
+/* The same rendering, also returning the training records of every path
+ * (in no particular order): rows of OR_REC_COLS doubles (pixel id, pass,
+ * vertex, x, wo, wi, mixture density, weight, NEE term), at most rec_cap of them;
+ * returns how many were produced (rows beyond rec_cap are dropped). */
+uint32_t or_records(const or_scene *s, uint32_t max_depth, uint32_t rr, uint32_t mode, uint32_t scramble,
+                    const uint32_t *pix, uint32_t npix, uint64_t pass0, uint32_t npasses, double *sum,
+                    uint32_t *count, uint32_t nthreads, double *rec_out, uint32_t rec_cap)
+{
+    uint32_t n = 0;
+    render_jobs(s, max_depth, rr, mode | (1u << 13), scramble, pix, npix, pass0, npasses, sum, NULL, count,
+                nthreads, rec_out, rec_cap, &n);
+    return n;
 }
 
 /* one path with a per-vertex log: records of 8 doubles,
@@ -1649,13 +1989,70 @@ uint32_t or_debug_path(const or_scene *s, uint32_t max_depth, uint32_t rr, uint3
     g_log = log; g_log_n = 0; g_log_cap = cap;
     uint32_t nr = 0;
     uint64_t i = or_pixel_index(s->W, s->H, px, py, pass);
-    v3 L = trace_path(s, &op, i, px, py, &nr);
+    v3 L = trace_path(s, &op, i, px, py, &nr, NULL, NULL);
     g_log = NULL;
     L_out[0] = L.x; L_out[1] = L.y; L_out[2] = L.z;
     return g_log_n;
 }
 
 /* ---------------------------------------------- pieces exposed for pins */
+
+/* the guide's mixture (after the FP16 storage step) at n vertices: x, wo
+ * (3 n each); out: 8 weights, 8 x (mu xyz, kappa) per row (40 values) */
+void or_guide_mix(const or_scene *s, const double *x, const double *wo, uint32_t n, double *out)
+{
+    for (uint32_t r = 0; r < n; ++r) {
+        gmix m;
+        guide_mixture(s, V3(x[3 * r], x[3 * r + 1], x[3 * r + 2]), V3(wo[3 * r], wo[3 * r + 1], wo[3 * r + 2]),
+                      &m);
+        double *o = out + 40 * (size_t)r;
+        for (int k = 0; k < G_LOBES; ++k) {
+            o[k] = m.w[k];
+            o[8 + 4 * k] = m.mu[k].x;
+            o[9 + 4 * k] = m.mu[k].y;
+            o[10 + 4 * k] = m.mu[k].z;
+            o[11 + 4 * k] = m.kappa[k];
+        }
+    }
+}
+
+/* the guide's features and network outputs at n vertices (32 and 40 per row) */
+void or_guide_forward(const or_scene *s, const double *x, const double *wo, uint32_t n, double *feat, double *out)
+{
+    for (uint32_t r = 0; r < n; ++r) {
+        double f[32], o[40];
+        guide_features(s, V3(x[3 * r], x[3 * r + 1], x[3 * r + 2]), V3(wo[3 * r], wo[3 * r + 1], wo[3 * r + 2]), f);
+        guide_forward(s, f, o);
+        if (feat) memcpy(feat + 32 * (size_t)r, f, sizeof f);
+        if (out) memcpy(out + 40 * (size_t)r, o, sizeof o);
+    }
+}
+
+/* density and samples of n explicit mixtures (rows of 40 as or_guide_mix
+ * writes them): pdf[r] at dirs[3r..], sample[3r..] from u[3r..] (lobe,
+ * cosine, azimuth numbers) */
+void or_guide_mix_eval(const double *mix, const double *dirs, const double *u, uint32_t n, double *pdf,
+                       double *sample)
+{
+    for (uint32_t r = 0; r < n; ++r) {
+        const double *o = mix + 40 * (size_t)r;
+        gmix m;
+        for (int k = 0; k < G_LOBES; ++k) {
+            m.w[k] = o[k];
+            m.mu[k] = V3(o[8 + 4 * k], o[9 + 4 * k], o[10 + 4 * k]);
+            m.kappa[k] = o[11 + 4 * k];
+        }
+        if (pdf) pdf[r] = gmix_pdf(&m, V3(dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2]));
+        if (sample) {
+            v3 w = gmix_sample(&m, u[3 * r], u[3 * r + 1], u[3 * r + 2]);
+            sample[3 * r] = w.x;
+            sample[3 * r + 1] = w.y;
+            sample[3 * r + 2] = w.z;
+        }
+    }
+}
+
+uint32_t or_rec_hash(uint64_t idx, uint32_t v) { return rec_hash(idx, v); }
 
 /* The light tree's tables: node count; with non-NULL arrays, per node the
  * centre and radius (c4), region fluxes (f6), first child (-1 leaf), first

@@ -607,6 +607,20 @@ def guide_init(seed: int = 7) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
+def guide_frozen(seed: int = 5, gain: float = 3.0, kappa_bias: float = 4.0) -> np.ndarray:
+    """Parameters of a fixed, untrained network whose mixtures are far from
+    uniform: He-uniform hidden layers as in guide_init, the output layer's
+    weights scaled by `gain` (uneven lobe weights, varied concentrations) and
+    `kappa_bias` on every lobe's concentration output (median kappa about 4).
+    Input data for parity tests of guided rendering."""
+    p = guide_init(seed).astype(np.float64)
+    o = sum(fi * fo + fo for fi, fo in zip(GUIDE_SIZES[:-2], GUIDE_SIZES[1:-1]))
+    fi, fo = GUIDE_SIZES[-2], GUIDE_SIZES[-1]
+    p[o:o + fi * fo] *= gain
+    p[o + fi * fo + 4:o + fi * fo + fo:5] = kappa_bias
+    return p.astype(np.float32)
+
+
 # the named workloads, each with its fixed seed; the slit enclosure reuses the
 # instanced scene's seed (it is that scene plus a roof)
 WORKLOADS = {
