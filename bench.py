@@ -6,18 +6,21 @@ pixel: enumeration, Halton samples, camera rays, closest hit, emission with
 MIS, next-event estimation, BSDF sampling, roulette, occlusion, FP64
 accumulation), through the C-ABI on torch's current stream; the library runs
 two batches of passes at a time (that stream and one of its own, each with a
-path pool of sixteen frames) and keeps the framebuffer updates in pass order.
+path pool of up to sixteen frames) and keeps the framebuffer updates in pass
+order.
 
-Workload: the seeded 0.97M-triangle grid of spheres and boxes (GGX over
-Lambert, 256 textured emitters), 1920x1080, max depth 12. Inputs are
-resident in HBM before the timed region starts.
+Workload (default): the seeded 16M-triangle procedural city with 10,000
+emissive window triangles (alias-table light selection), 3840x2160, max
+depth 16; `--workload grid` runs the 0.97M-triangle 1080p grid instead.
+Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line: Mrays/s (extension + shadow rays per second) as
 `value`, Mpaths/s, a roofline entry for the dominant kernel (per-launch
 algorithmic bytes over its average launch time, HIP events inside the
-library on the launch stream; launches of the two batches in flight share
-the GPU, so the same kernel is also timed on one stream, `isolated`) and the
-CPU oracle's rate on a bounded sample.
+library on the launch stream, timed on one stream right after the timed
+region because launches of the two batches in flight share the GPU), the CPU
+oracle's rate on a bounded sample, and the equal-time RMSE of the guided and
+the plain tracer (slit enclosure at 1080p and the city at 4K).
 """
 from __future__ import annotations
 
@@ -36,13 +39,15 @@ METRIC = "Mrays/s and Mpaths/s per GPU; equal-time RMSE, guided vs plain vs FP64
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "grid": ("grid_1m", "grid of 400 tessellated spheres/boxes, 0.97M triangles, 256 textured emitters, 1920x1080, "
-                "1 spp per step (passes batched sixteen frames per launch sequence, two batches in flight), max depth 12, "
+                "1 spp per step (passes in nearly equal batches of at most sixteen frames, two batches in flight), max "
+                "depth 12, "
                 "NEE+MIS, roulette"),
     "city": ("city_16m", "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
-                "selection), 3840x2160, 1 spp per step (eight frames per launch sequence, two batches in flight), max "
-                "depth 16, NEE+MIS, roulette"),
+                "selection), 3840x2160, 1 spp per step (passes in nearly equal batches of at most eight frames, two "
+                "batches in flight), max depth 16, NEE+MIS, roulette"),
 }
-GUIDE_ALPHA, GUIDE_WARMUP, GUIDE_MAX_VERTEX = 0.7, 64, 2  # the guide mixes in after 64 Adam steps
+# the guided tracer's settings in the equal-time legs
+GUIDE = {"alpha": 0.7, "warmup": 64, "max_vertex": 2, "lr": 1e-3, "batch": 1 << 18}
 
 # algorithmic bytes per unit of work
 NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
@@ -80,15 +85,19 @@ def pmc_traffic(kernel: str, workload_tag: str):
     return float(t.group(1))
 
 
-def cpu_baseline(sc, seconds: float):
-    """The FP64 oracle on every 8th pixel in x and y, passes until `seconds` of work."""
-    import numpy as np
-
+def oracle_scene(sc):
+    """The FP64 oracle's own copy of the scene (its BVH build timed)."""
     import oracle
 
     t0 = time.perf_counter()
     S = oracle.Scene(sc)
-    build_s = time.perf_counter() - t0
+    return S, time.perf_counter() - t0
+
+
+def cpu_baseline(S, sc, seconds: float, build_s: float):
+    """The FP64 oracle on every 8th pixel in x and y, passes until `seconds` of work."""
+    import numpy as np
+
     W, H = sc.width, sc.height
     ys, xs = np.meshgrid(np.arange(0, H, 8), np.arange(0, W, 8), indexing="ij")
     pix = (ys * W + xs).reshape(-1).astype(np.uint32)
@@ -98,9 +107,9 @@ def cpu_baseline(sc, seconds: float):
     passes = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        _, _, _, r = S.render(pixels=pix, pass0=passes, npasses=4, nthreads=threads)
+        _, _, _, r = S.render(pixels=pix, pass0=passes, npasses=2, nthreads=threads)
         rays += r
-        passes += 4
+        passes += 2
     dt = time.perf_counter() - t0
     return {
         "value": rays / dt / 1e6,
@@ -133,56 +142,58 @@ def _host_cpu():
     return {"model": model, "threads_per_core": tpc, "logical_cpus": os.cpu_count()}
 
 
-def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: int, height: int, tris: int):
-    """Equal-time RMSE of the plain and the guided tracer on the slit workload.
+def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle_scene=None,
+               oracle_seconds: float = 0.0, oracle_stride=(32, 16), guide=None):
+    """Equal-time RMSE of the plain and the guided tracer on one scene.
 
     Both runs of a pair get the same wall time on the same GPU, the guided
     one including its online training from an untrained network. Two
-    budgets: the plain tracer's time for 64 passes, and `seconds`. Two
-    cameras: looking at the half of the enclosure the sunlit strip does not
-    reach (the workload's camera: every pixel lit indirectly), and looking
-    along the enclosure at the strip. The error is measured against the plain
-    tracer at `ref_passes` passes from an independent pass range (FP64
-    accumulation, whole frame) and, for the first camera, against the FP64
-    CPU oracle on a bounded pixel sample, also from an independent pass range.
+    budgets: the plain tracer's time for 64 passes, and `seconds`. For each
+    camera in `views` the error is measured against the plain tracer at
+    2 x `ref_passes` passes from two independent pass ranges (FP64
+    accumulation, whole frame), with the reference's own error (estimated
+    from the difference of its halves) taken out of the squared errors
+    (`rmse`; the raw figure is `rmse_vs_gpu_reference`), and, for the first
+    camera, against the FP64 CPU oracle on a
+    bounded pixel sample (every `oracle_stride` pixels, also from an
+    independent pass range), whose own error against the GPU reference is
+    reported beside it. `per_call` passes go to the library per call (two
+    batches in flight).
     """
     import numpy as np
     import torch
 
-    import oracle
     import scenegen
     from paper_1705_01263_amd import Renderer
 
-    sc = scenegen.slit_scene(width=width, height=height, target_tris=tris, max_depth=16)
-    _say(f"bench: equal-time workload {sc.name} tris={sc.num_triangles} {width}x{height} D=16")
+    g = dict(GUIDE)
+    if guide:
+        g.update(guide)
+    width, height = sc.width, sc.height
     rmse = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))
-    views = [("indirectly lit half (the workload's camera)", sc.camera),
-             ("along the enclosure, sunlit strip in view",
-              scenegen.Camera((0.0, 4.0, -28.0), (0.0, 2.0, 0.0), (0.0, 1.0, 0.0), 40.0))]
-    out = {"workload": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth 16, sun and sky "
-                       "through a 0.1-wide roof slit",
-           "guide": {"alpha": GUIDE_ALPHA, "guided_vertices": GUIDE_MAX_VERTEX, "lr": 1e-3, "batch": 1 << 18,
-                     "adam_steps_per_pass": 1, "warmup_steps": GUIDE_WARMUP},
-           "views": []}
+    out = {"workload": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth {sc.max_depth}",
+           "guide": {"alpha": g["alpha"], "guided_vertices": g["max_vertex"], "lr": g["lr"], "batch": g["batch"],
+                     "adam_steps_per_pass": 1, "warmup_steps": g["warmup"]},
+           "passes_per_call": per_call, "views": []}
     for vi, (vname, cam) in enumerate(views):
-        sc.camera = cam
+        if cam is not None:
+            sc.camera = cam
         r = Renderer(sc, device=0)
 
         def run(budget=None, passes=None, guided=False):
             r.reset()
             if guided:
                 r.ctx.guide_set_weights(scenegen.guide_init(1))
-                r.ctx.guide_config(alpha=GUIDE_ALPHA, lr=1e-3, batch=1 << 18, train=1, warmup_steps=GUIDE_WARMUP,
-                                   seed=1, max_vertex=GUIDE_MAX_VERTEX)
+                r.ctx.guide_config(alpha=g["alpha"], lr=g["lr"], batch=g["batch"], train=1,
+                                   warmup_steps=g["warmup"], seed=1, max_vertex=g["max_vertex"])
             else:
                 r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             n = 0
-            # 32 passes per call: two batches of sixteen, the second overlapping the first's tail
             while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
-                r.render(n, 32)
-                n += 32
+                r.render(n, per_call)
+                n += per_call
                 torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s, c = r.readback()
@@ -192,14 +203,27 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
         r.render(0, 4)  # warm-up (module load, first launches)
         torch.cuda.synchronize()
         r.ctx.guide_config(alpha=0.0, lr=1e-3, batch=1 << 18, train=0, warmup_steps=0, seed=0)
-        r.reset()
+        # two references from disjoint pass ranges: their mean is the
+        # reference, and half their difference estimates its own error, which
+        # is removed from the squared errors compared (an error of the
+        # reference adds to every image's squared error alike and would pull
+        # every ratio toward 1)
         t0 = time.perf_counter()
-        r.render(1 << 24, ref_passes)
-        s, c = r.readback()
-        ref = s / c[:, None]
+        refs = []
+        for first in (1 << 24, (1 << 24) + (1 << 23)):
+            r.reset()
+            r.render(first, ref_passes)
+            s, c = r.readback()
+            refs.append(s / c[:, None])
+        ref = 0.5 * (refs[0] + refs[1])
+        ref_mse = np.mean((refs[0] - refs[1]) ** 2) / 4.0
+        del refs
         t_ref = time.perf_counter() - t0
-        view = {"camera": vname, "gpu_reference": {"passes": ref_passes, "first_pass": 1 << 24,
-                                                   "seconds": round(t_ref, 2)}, "budgets": []}
+        rmse_c = lambda a: float(np.sqrt(max(np.mean((a - ref) ** 2) - ref_mse, 0.0)))
+        view = {"camera": vname, "gpu_reference": {"passes": 2 * ref_passes, "first_passes": [1 << 24,
+                                                                                            (1 << 24) + (1 << 23)],
+                                                   "seconds": round(t_ref, 2),
+                                                   "own_rmse_estimate": float(np.sqrt(ref_mse))}, "budgets": []}
         img = {}
         for label, kw in (("plain tracer's time for 64 passes", {"passes": 64}), (f"{seconds:g} s", {"budget": seconds})):
             plain, n_p, t_p, _ = run(**kw)
@@ -207,35 +231,31 @@ def equal_time(seconds: float, ref_passes: int, oracle_seconds: float, width: in
             img[label] = (plain, guided)
             view["budgets"].append({
                 "budget": label, "seconds": round(t_p, 3),
-                "plain": {"passes": n_p, "rmse_vs_gpu_reference": rmse(plain, ref)},
+                "plain": {"passes": n_p, "rmse_vs_gpu_reference": rmse(plain, ref), "rmse": rmse_c(plain)},
                 "guided": {"passes": n_g, "seconds": round(t_g, 3), "adam_steps": int(steps),
-                           "rmse_vs_gpu_reference": rmse(guided, ref),
+                           "rmse_vs_gpu_reference": rmse(guided, ref), "rmse": rmse_c(guided),
                            "final_loss": round(r.ctx.guide_loss()[0], 4)},
-                "guided_over_plain_rmse": round(rmse(guided, ref) / rmse(plain, ref), 4)})
-            _say(f"bench: equal time [{vname}, {label}] plain {n_p} passes, guided {n_g} passes, "
+                "guided_over_plain_rmse": round(rmse_c(guided) / max(rmse_c(plain), 1e-30), 4)})
+            _say(f"bench: equal time [{sc.name}, {vname}, {label}] plain {n_p} passes, guided {n_g} passes, "
                  f"ratio {view['budgets'][-1]['guided_over_plain_rmse']}")
         del r
         torch.cuda.empty_cache()
-        if vi == 0 and oracle_seconds > 0:
-            t0 = time.perf_counter()
-            S = oracle.Scene(sc)
-            build_s = time.perf_counter() - t0
-            ys, xs = np.meshgrid(np.arange(height // 32, height, height // 16),
-                                 np.arange(width // 64, width, width // 32), indexing="ij")
+        if vi == 0 and oracle_scene is not None and oracle_seconds > 0:
+            sy, sx = oracle_stride[1], oracle_stride[0]
+            ys, xs = np.meshgrid(np.arange(height // (2 * sy), height, sy),
+                                 np.arange(width // (2 * sx), width, sx), indexing="ij")
             pix = (ys * width + xs).reshape(-1).astype(np.uint32)
             threads = min(len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 1, 16)
             acc = np.zeros((pix.shape[0], 3))
             n_o = 0
             t0 = time.perf_counter()
             while time.perf_counter() - t0 < oracle_seconds:
-                s_o, _, cnt, _ = S.render(pixels=pix, pass0=(1 << 25) + n_o, npasses=16, nthreads=threads)
+                s_o, _, cnt, _ = oracle_scene.render(pixels=pix, pass0=(1 << 25) + n_o, npasses=16, nthreads=threads)
                 acc += s_o
                 n_o += 16
             o_ref = acc / n_o
-            del S
             view["oracle_reference"] = {"pixels": int(pix.shape[0]), "passes": n_o, "first_pass": 1 << 25,
                                         "threads": threads, "seconds": round(time.perf_counter() - t0, 1),
-                                        "bvh_build_s": round(build_s, 1),
                                         "gpu_reference_rmse": rmse(ref[pix], o_ref)}
             for bud in view["budgets"]:
                 plain, guided = img[bud["budget"]]
@@ -372,19 +392,22 @@ def env_select_equal_time(seconds: float, ref_passes: int, width: int, height: i
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=32, help="timed passes (32 = four batches at 1080p)")
-    ap.add_argument("--warmup", type=int, default=16, help="untimed passes (16 = one batch at 1080p)")
+    ap.add_argument("--steps", type=int, default=24, help="timed passes (24 = three batches of eight frames at 4K)")
+    ap.add_argument("--warmup", type=int, default=8, help="untimed passes (8 = one batch at 4K)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="grid",
-                    help="grid: the 0.97M-triangle 1080p scene (default); city: the 16M-triangle 4K city")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="city",
+                    help="city: the 16M-triangle 4K city (default); grid: the 0.97M-triangle 1080p scene")
     ap.add_argument("--no-equal-time", action="store_true", help="skip the guided vs plain equal-time RMSE leg")
     ap.add_argument("--et-seconds", type=float, default=4.0, help="wall time of each equal-time run")
     ap.add_argument("--et-ref-passes", type=int, default=2048)
     ap.add_argument("--et-oracle-seconds", type=float, default=10.0)
     ap.add_argument("--et-size", type=str, default="1920x1080")
     ap.add_argument("--et-tris", type=int, default=4_000_000)
+    ap.add_argument("--et-city-seconds", type=float, default=4.0, help="wall time of each equal-time run on the city")
+    ap.add_argument("--et-city-ref-passes", type=int, default=512)
+    ap.add_argument("--no-et-city", action="store_true", help="skip the guided vs plain equal-time leg on the city")
     ap.add_argument("--bvh-builder", type=int, choices=(0, 1), default=0,
                     help="0: binned SAH on the host, 1: linear BVH built on the GPU")
     ap.add_argument("--single-stream", action="store_true",
@@ -475,12 +498,11 @@ def main():
                       "shadow_nodes_per_ray": round(sn / max(h, 1), 2), "shadow_tris_per_ray": round(stt / max(h, 1), 2)}
             return byts, stream, counts
 
-        byts, _, _ = kernel_bytes(st0, st1)
-        dom = max(byts, key=lambda k: prof[k][1])
         # Per-launch durations are taken on one stream: with two batches in
         # flight a launch's events also span its wait for the other batch's
         # kernels. When the timed region ran two batches at a time, the same
-        # number of passes follows on one stream for the roofline.
+        # number of passes follows on one stream for the roofline, and the
+        # dominant kernel is the one with the most time there.
         if args.single_stream:
             r_prof, r0, r1 = prof, st0, st1
         else:
@@ -491,6 +513,7 @@ def main():
             r_prof = r.ctx.profile_read()
             r1 = r.stats()
         rb, rstream, counts = kernel_bytes(r0, r1)
+        dom = max(rb, key=lambda k: r_prof[k][1])
         n_l, ms = r_prof[dom]
         launch_s = ms / n_l * 1e-3
         per_launch = rb[dom] / n_l
@@ -515,9 +538,12 @@ def main():
         _say(f"bench: roofline {roof}")
 
     cpu = None
+    S = None
     if not args.no_cpu_baseline:
-        _say(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        cpu = cpu_baseline(sc, args.cpu_seconds)
+        _say("bench: CPU oracle: building its scene")
+        S, build_s = oracle_scene(sc)
+        _say(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s after a {build_s:.1f} s build)")
+        cpu = cpu_baseline(S, sc, args.cpu_seconds, build_s)
 
     ls = None
     if args.workload == "city" and not args.no_light_select:
@@ -537,8 +563,25 @@ def main():
     if not args.no_equal_time:
         r = None
         torch.cuda.empty_cache()
+        et = []
+        if args.workload == "city" and not args.no_et_city:
+            _say("bench: equal time, guided vs plain, on the city")
+            et.append(equal_time(sc, [("the workload's camera", None)], args.et_city_seconds, args.et_city_ref_passes,
+                                 16, oracle_scene=S, oracle_seconds=args.et_oracle_seconds, oracle_stride=(64, 64)))
+            torch.cuda.empty_cache()
+        S = None
         w, h = (int(v) for v in args.et_size.split("x"))
-        et = equal_time(args.et_seconds, args.et_ref_passes, args.et_oracle_seconds, w, h, args.et_tris)
+        slit = scenegen.slit_scene(width=w, height=h, target_tris=args.et_tris, max_depth=16)
+        _say(f"bench: equal-time workload {slit.name} tris={slit.num_triangles} {w}x{h} D=16")
+        S_slit = None
+        if args.et_oracle_seconds > 0:
+            S_slit, _ = oracle_scene(slit)
+        et.append(equal_time(slit, [("indirectly lit half (the workload's camera)", None),
+                                    ("along the enclosure, sunlit strip in view",
+                                     scenegen.Camera((0.0, 4.0, -28.0), (0.0, 2.0, 0.0), (0.0, 1.0, 0.0), 40.0))],
+                             args.et_seconds, args.et_ref_passes, 32, oracle_scene=S_slit,
+                             oracle_seconds=args.et_oracle_seconds, oracle_stride=(64, 64)))
+        del S_slit
         _say(f"bench: equal time {et}")
 
     out = {

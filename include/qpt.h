@@ -178,9 +178,10 @@ int qpt_build_bvh(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
 
 /* Bytes of device workspace needed for `pool_paths` concurrent paths per
  * batch (0 = sixteen frames' worth: the smallest power of two >= 16 W H,
- * within [2^16, 2^26]). Passes are rendered in batches of as many whole passes as the
- * pool holds (or in pixel chunks of one pass when a frame exceeds it); larger
- * batches keep the queues of deep vertices full. The workspace holds two such
+ * within [2^16, 2^26]). A range of passes is rendered in as few batches of whole
+ * passes as the pool allows, of nearly equal size (or in pixel chunks of one
+ * pass when a frame exceeds the pool); larger batches keep the queues of deep
+ * vertices full. The workspace holds two such
  * pools, one per batch in flight. Scene, BVH, path state, queues and
  * framebuffer all live in it. */
 int qpt_workspace_size(const qpt_ctx *ctx, uint32_t pool_paths, size_t *bytes);
@@ -294,6 +295,25 @@ int qpt_guide_debug_train(qpt_ctx *ctx, const float *x, const float *dirs, const
  * u (n x 3: lobe, two direction numbers) into sample (n x 3). */
 int qpt_guide_debug_mixture(qpt_ctx *ctx, const float *out40, const float *dirs, const float *u, uint32_t n,
                             float *pdf, float *sample);
+
+/* The training records of the most recent batch of passes (the guide's
+ * record step: train > 0), with their identity, for parity checks. Per
+ * record (DEVICE pointers, cap rows each): ident[3 r..] = pixel id
+ * (y * width + x), pass, path vertex; rec[11 r..] = hit position x (3),
+ * outgoing direction wo (3), sampled direction wi (3), the mixture density
+ * of wi that the throughput used, and the record's weight: the luminance of
+ * (final path radiance - radiance before the vertex's next-event estimate -
+ * that estimate) / throughput before the scattering, per channel where that
+ * throughput is positive, each channel clamped at 0 (the sample's estimate
+ * f cos L_i / p of the scattering integral). Records whose weight is
+ * positive and finite are the ones the replay ring receives. *count = the
+ * number of records the batch holds (rows beyond cap are not written), in
+ * the order the shading kernel appended them. A vertex leaves a record when
+ * its path continues, the vertex is at most max_vertex deep, and (when the
+ * batch could overflow the record buffer) a hash of its sample index and
+ * depth falls below the kept fraction. Synchronises the stream.
+ * QPT_E_STATE before any qpt_render_pass on the bound workspace. */
+int qpt_guide_debug_records(qpt_ctx *ctx, uint32_t *ident, float *rec, uint32_t cap, uint32_t *count);
 
 /* Weighted negative log-likelihood of the last training batch (sum_b w_b
  * (-log q(dir_b)) / sum_b w_b) and its weight sum (host pointers, either may

@@ -520,13 +520,7 @@ __global__ void k_rec_finalize(Frame F, Pool P, GuideTrain T)
         bool ok = false;
         if (i < cnt) {
             float4 *r = F.guide.rec + (size_t)i * kRecF4;
-            float4 r2 = r[2], r3 = r[3], r4 = r[4], r5 = r[5];
-            float4 L = P.rad[__float_as_uint(r2.w)];
-            float li[3] = {(L.x - r3.x - r5.x), (L.y - r3.y - r5.y), (L.z - r3.z - r5.z)};
-            float tb[3] = {r4.x, r4.y, r4.z};
-            float w = 0.0f;
-            const float wl[3] = {0.2126f, 0.7152f, 0.0722f};
-            for (int c = 0; c < 3; ++c) w += tb[c] > 0.0f ? wl[c] * fmaxf(0.0f, li[c] / tb[c]) : 0.0f;
+            const float w = guide::record_weight(r[3], r[4], r[5], P.rad[__float_as_uint(r[2].w)]);
             ok = w > 0.0f && w < INFINITY;
             if (ok) {
                 r[1].w = w;

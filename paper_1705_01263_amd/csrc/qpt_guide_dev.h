@@ -226,6 +226,22 @@ __device__ inline V3 mixture_sample(const M &m, float u_lobe, float u1, float u2
             w * l.z + r * (cp * t1.z + sp * t2.z)};
 }
 
+// Weight of a training record once its path has ended with radiance L: the
+// luminance of (L - radiance before the vertex's NEE - that NEE) / the
+// throughput before the scattering (roulette folded in), per channel where
+// that throughput is positive, each channel clamped at 0: the sample's own
+// estimate f cos L_i / p of the scattering integral. r3 = radiance before
+// the NEE, r4 = throughput before the scattering, r5 = the NEE (0 if occluded).
+__device__ __forceinline__ float record_weight(float4 r3, float4 r4, float4 r5, float4 L)
+{
+    const float li[3] = {(L.x - r3.x - r5.x), (L.y - r3.y - r5.y), (L.z - r3.z - r5.z)};
+    const float tb[3] = {r4.x, r4.y, r4.z};
+    const float wl[3] = {0.2126f, 0.7152f, 0.0722f};
+    float w = 0.0f;
+    for (int c = 0; c < 3; ++c) w += tb[c] > 0.0f ? wl[c] * fmaxf(0.0f, li[c] / tb[c]) : 0.0f;
+    return w;
+}
+
 // the 32 input features: sin/cos of 2^o pi x_hat per axis and octave, then
 // sin/cos of pi th, 2 pi th, 2 pi ph, 4 pi ph of the outgoing direction
 // (th = polar angle from +y over pi, ph = atan2(x, -z) over 2 pi in [0, 1))

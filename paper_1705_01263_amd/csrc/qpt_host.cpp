@@ -398,6 +398,13 @@ struct qpt_ctx {
     uint4 *lane_mix[2] = {nullptr, nullptr};     // per lane: the guide's mixture per slot
     float4 *lane_rec[2] = {nullptr, nullptr};    // per lane: training records
     uint64_t batches = 0;
+    // the most recent batch (for the record hook): its lane, pixel range and passes
+    struct {
+        bool valid = false;
+        int lane = 0;
+        uint32_t p0 = 0, np = 0, nb = 0;
+        uint64_t pass0 = 0;
+    } last_batch;
 };
 
 namespace {
@@ -1497,6 +1504,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.rec_count = c->pool.counters + 127;
     c->guide_weights = false;
     c->guide_steps = 0;
+    c->last_batch.valid = false;
     c->bound = true;
     int rc = qpt_reset_accum(c);
     if (rc) {
@@ -1620,6 +1628,12 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
             f.guide.bias = c->pub_bias[k];
         }
         HIP_TRY(c, launch_render_paths(f, P, p0, np, pass0, nb, s, prof));
+        c->last_batch.valid = true;
+        c->last_batch.lane = lane_b ? 1 : 0;
+        c->last_batch.p0 = p0;
+        c->last_batch.np = np;
+        c->last_batch.nb = nb;
+        c->last_batch.pass0 = pass0;
         if (two_lanes) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_acc, 0));
         HIP_TRY(c, launch_accumulate(f, P, p0, np, nb, s, prof));
         if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_acc, s));
@@ -1656,9 +1670,13 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     };
     auto all_batches = [&]() -> int {
         if (npix <= cap) {
-            uint32_t per = std::max(1u, cap / npix);
-            for (uint32_t done = 0; done < num_passes;) {
-                uint32_t nb = std::min(per, num_passes - done);
+            // as few batches as the pool allows, of nearly equal size (20 passes
+            // with room for 16 are two batches of 10), so that both lanes have
+            // work of the same length to overlap
+            const uint32_t per = std::max(1u, cap / npix);
+            const uint32_t nbat = (num_passes + per - 1) / per;
+            for (uint32_t b = 0, done = 0; b < nbat; ++b) {
+                const uint32_t nb = num_passes / nbat + (b < num_passes % nbat ? 1u : 0u);
                 int rc = batch(0, npix, first_pass + done, nb);
                 if (rc) return rc;
                 done += nb;
@@ -1921,6 +1939,29 @@ int qpt_guide_loss(qpt_ctx *c, double *loss, double *weight_sum)
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (loss) *loss = sc[0] > 0.0f ? (double)sc[1] / (double)sc[0] : 0.0;
     if (weight_sum) *weight_sum = sc[0];
+    return QPT_OK;
+}
+
+int qpt_guide_debug_records(qpt_ctx *c, uint32_t *ident, float *rec, uint32_t cap, uint32_t *count)
+{
+    if (!c || !count || (cap && (!ident || !rec))) return QPT_E_INVALID;
+    if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
+    if (!c->last_batch.valid) return fail(c, QPT_E_STATE, "no batch rendered since the workspace was bound");
+    DeviceGuard g(c->device);
+    // the caller's stream has waited for lane 1 at the end of qpt_render_pass
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int lane = c->last_batch.lane;
+    const Pool &P = lane ? c->pool_b : c->pool;
+    uint32_t n = 0;
+    HIP_TRY(c, hipMemcpyAsync(&n, P.counters + 127, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    n = std::min<uint32_t>(n, c->frame.guide.rec_cap);
+    *count = n;
+    Frame f = c->frame;
+    f.guide.rec = c->lane_rec[lane];
+    HIP_TRY(c, launch_debug_records(f, P, c->last_batch.p0, c->last_batch.np, c->last_batch.pass0, c->last_batch.nb,
+                                    std::min(n, cap), ident, rec, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return QPT_OK;
 }
 

@@ -240,6 +240,8 @@ hipError_t launch_debug_env_sample(const Frame &f, const uint32_t *uv, const flo
 hipError_t launch_debug_light_sample(const Frame &f, const uint64_t *S, const float *x, const float *nrm,
                                      uint32_t n, uint32_t *emitter, uint64_t *size, uint64_t *size_hit,
                                      hipStream_t s);
+hipError_t launch_debug_records(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix, uint64_t pass0,
+                                uint32_t npass, uint32_t n, uint32_t *ident, float *out, hipStream_t s);
 hipError_t launch_debug_trace(const Frame &f, const Pool &pool, const float *rays, uint32_t n, int any_hit,
                               int brute, float *t, uint32_t *tri, float *b12, hipStream_t s);
 

@@ -1183,7 +1183,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
                                         rec0 = f4(x, pb);
                                         rec1 = f4(wo, 0.0f);
                                         rec2 = f4(wi, ubits(slot));
-                                        rec3 = f4(L, 0.0f);
+                                        rec3 = f4(L, ubits(v));
                                         rec4 = f4(Tb, 0.0f);
                                     }
                                 }
@@ -1374,6 +1374,46 @@ hipError_t launch_render_batch(const Frame &F, const Pool &P, uint32_t pix0, uin
     hipError_t e = launch_render_paths(F, P, pix0, npix, pass0, npass, s, prof);
     if (e != hipSuccess) return e;
     return launch_accumulate(F, P, pix0, npix, npass, s, prof);
+}
+
+// the training records of a lane's last batch with their identity: pixel,
+// pass and vertex of each, position, directions, density and the weight its
+// finalisation gives (the same device function), for parity checks
+__global__ void k_debug_records(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint64_t pass0, uint32_t npass,
+                                uint32_t n, uint32_t *ident, float *out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 *r = F.guide.rec + (size_t)i * kRecF4;
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+    const uint32_t slot = fbits(r2.w);
+    uint32_t pl, j, p;
+    if (whole_frame(F, npix)) {
+        position_of(slot_map(npix, npass), slot, pl, j);
+        p = tile_pixel(pl, F.W, F.H);
+    } else {
+        pl = slot % npix;
+        j = slot / npix;
+        p = pix0 + pl;
+    }
+    ident[3 * (size_t)i] = p;
+    ident[3 * (size_t)i + 1] = (uint32_t)(pass0 + j);
+    ident[3 * (size_t)i + 2] = fbits(r3.w);
+    float *o = out + 11 * (size_t)i;
+    o[0] = r0.x; o[1] = r0.y; o[2] = r0.z;
+    o[3] = r1.x; o[4] = r1.y; o[5] = r1.z;
+    o[6] = r2.x; o[7] = r2.y; o[8] = r2.z;
+    o[9] = r0.w;
+    o[10] = guide::record_weight(r3, r[4], r[5], P.rad[slot]);
+}
+
+hipError_t launch_debug_records(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
+                                uint32_t npass, uint32_t n, uint32_t *ident, float *out, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_records, dim3((n + 255) / 256), dim3(256), 0, s, F, P, pix0, npix, pass0, npass, n,
+                       ident, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_debug_sample_bits(const Frame &F, const uint64_t *idx, const uint32_t *dim, uint32_t n,

@@ -78,7 +78,7 @@ EXPORTS = [
     "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
     "qpt_guide_set_weights", "qpt_guide_get_weights", "qpt_guide_debug_forward", "qpt_guide_debug_eval", "qpt_guide_debug_grad",
-    "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_loss",
+    "qpt_guide_debug_train", "qpt_guide_debug_mixture", "qpt_guide_debug_records", "qpt_guide_loss",
 ]
 
 _lib = None
@@ -132,6 +132,7 @@ def lib():
             "qpt_guide_debug_grad": ([P, P, P, P, u32, P], i32),
             "qpt_guide_debug_train": ([P, P, P, P, u32, C.c_float, P], i32),
             "qpt_guide_debug_mixture": ([P, P, P, P, u32, P, P], i32),
+            "qpt_guide_debug_records": ([P, P, P, u32, C.POINTER(C.c_uint32)], i32),
             "qpt_guide_loss": ([P, C.POINTER(C.c_double), C.POINTER(C.c_double)], i32),
             "qpt_profile_read": ([P, C.POINTER(qpt_kernel_time)], i32),
         }
@@ -311,6 +312,12 @@ class Context:
     def guide_debug_mixture(self, out40, dirs, u, n, pdf, sample) -> None:
         self.check(self.L.qpt_guide_debug_mixture(self.h, _p(out40), _p(dirs), _p(u), n, _p(pdf), _p(sample)),
                    "qpt_guide_debug_mixture")
+
+    def guide_debug_records(self, ident, rec, cap) -> int:
+        n = C.c_uint32()
+        self.check(self.L.qpt_guide_debug_records(self.h, _p(ident), _p(rec), cap, C.byref(n)),
+                   "qpt_guide_debug_records")
+        return n.value
 
     def guide_loss(self):
         l, w = C.c_double(), C.c_double()
