@@ -21,9 +21,18 @@
  * (and unmodified) until qpt_destroy or the next qpt_bind_workspace. Output
  * buffers belong to the caller.
  *
- * Streams. All device work is enqueued on the stream given to qpt_create
- * (a hipStream_t; NULL = the default stream). Calls on one context are not
- * thread-safe; use one context per stream.
+ * The one exception is qpt_build_bvh_noalloc, which takes its temporaries
+ * from a fixed device region of the library's own (see there).
+ *
+ * Streams. All results are ordered on the stream given to qpt_create (a
+ * hipStream_t; NULL = the default stream): a call's device work is complete
+ * once that stream has reached the point after the call. Two more streams
+ * carry work that overlaps it -- the second batch in flight and the guide's
+ * training steps -- and the caller's stream waits on both with events before
+ * any later work. The caller may provide them (qpt_set_streams, e.g. two
+ * torch streams); otherwise qpt_bind_workspace creates them (default
+ * priority, non-blocking) and qpt_destroy destroys them. Calls on one
+ * context are not thread-safe; use one context per stream.
  *
  * Call order: create -> build_scene -> build_bvh -> workspace_size ->
  * bind_workspace -> render_pass* -> readback; violations return QPT_E_STATE.
@@ -88,7 +97,12 @@ typedef struct {
     uint32_t builder;        /* 0: binned SAH on the host; 1: linear BVH on the GPU (Morton order,
                                 Karras 2012), collapsed to the same 4-wide nodes on the device: a
                                 faster build of a lower-quality tree; needs a device context and
-                                allocates its temporaries with hipMalloc during the call */
+                                the caller's scratch below */
+    uint32_t reserved;
+    void *scratch;           /* builder 1: caller-owned DEVICE memory for the build's temporaries, at
+                                least qpt_bvh_scratch_size bytes, 256-byte aligned; free again when
+                                the call returns (the build synchronises the stream) */
+    size_t scratch_bytes;
 } qpt_bvh_opts;
 
 typedef struct {
@@ -175,6 +189,32 @@ int qpt_build_scene(qpt_ctx *ctx, const qpt_scene_desc *desc);
  * (Sec. 2.3: watertight traversal; Sec. 3.1 replaces the paper's ray casting
  * library with the library's own traversal). stats may be NULL. */
 int qpt_build_bvh(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
+
+/* Bytes of device scratch the GPU builder (qpt_bvh_opts.builder = 1) needs
+ * for the scene of the last qpt_build_scene: about 300 bytes per triangle
+ * plus 12 per vertex. */
+int qpt_bvh_scratch_size(qpt_ctx *ctx, size_t *bytes);
+
+/* For callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid allocation): the GPU builder
+ * (builder = 1 of qpt_bvh_opts; the other fields as there, scratch ignored)
+ * with its temporaries in a fixed region of the library, 64 MiB of device
+ * memory reserved on every GPU the library is loaded on, for as long as the
+ * process lives. It calls no hipMalloc, hipFree or other allocating routine.
+ * The scene must fit the region (about 200,000 triangles; qpt_bvh_scratch_size
+ * gives the bytes needed): QPT_E_INVALID otherwise, with a message. The
+ * result is the same tree, bit for bit, as qpt_build_bvh with builder = 1.
+ * All contexts on one GPU share the region: calls that overlap in time on
+ * one GPU (from several threads) race and must be serialised by the caller.
+ * Synchronises the stream. */
+int qpt_build_bvh_noalloc(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
+
+/* Streams for the second batch in flight and for the guide's training steps
+ * (hipStream_t each, not NULL, on the context's device; default priority
+ * recommended), owned by the caller and kept alive until qpt_destroy. Only
+ * before the first qpt_bind_workspace (QPT_E_STATE after it); without this
+ * call the library creates both there and destroys them in qpt_destroy. */
+int qpt_set_streams(qpt_ctx *ctx, void *lane_stream, void *train_stream);
 
 /* Bytes of device workspace needed for `pool_paths` concurrent paths per
  * batch (0 = sixteen frames' worth: the smallest power of two >= 16 W H,
@@ -345,9 +385,11 @@ int qpt_debug_pixel_index(qpt_ctx *ctx, uint64_t pass, uint64_t *out);
  * BVH (brute_force = 0) or against every triangle (brute_force = 1).
  * Closest hit: t[n], tri[n] (input triangle id, 0xffffffff on a miss),
  * b12[2n] barycentrics of vertices 1 and 2. any_hit = 1: tri[q] = 1 if
- * occluded, else 0 (t and b12 may be NULL). */
+ * occluded, else 0 (t and b12 may be NULL). stack_max (may be NULL; BVH
+ * mode only) receives each ray's deepest traversal stack: entries beyond
+ * the 16 kept in LDS spill to the workspace's overflow area. */
 int qpt_debug_trace(qpt_ctx *ctx, const float *rays, uint32_t n, int any_hit, int brute_force,
-                    float *t, uint32_t *tri, float *b12);
+                    float *t, uint32_t *tri, float *b12, uint32_t *stack_max);
 
 /* ---- host-table hooks (host memory, no device needed), for cross-checks of
  * the builders against an independent implementation ---- */

@@ -5,10 +5,10 @@
 // cites rapid GPU construction); the binned-SAH host builder stays the
 // default, this one trades tree quality for build time.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "qpt_internal.h"
@@ -244,20 +244,187 @@ __global__ void k_collapse(const uint2 *qin, const uint32_t *nin, uint2 *qout, u
     }
 }
 
+// ---- stable LSD radix sort of the 64-bit keys by their upper 30 bits (the
+// Morton code). The keys enter in triangle order (the id is the lower word),
+// so a stable sort by the code leaves equal codes in id order: the result is
+// the keys sorted as 64-bit integers. Each pass sorts by one 8-bit digit:
+// tiles of kTile keys count their digits, each digit's column of tile counts
+// is scanned, and the tiles scatter their keys to the digit's base plus the
+// tile's prefix plus the key's rank among equal digits in the tile.
+
+constexpr uint32_t kRadixItems = 16;                 // keys per thread and tile
+constexpr uint32_t kTile = kB * kRadixItems;         // 4096 keys per tile
+
+__device__ __forceinline__ uint32_t digit_of(unsigned long long key, uint32_t shift)
+{
+    return (uint32_t)(key >> shift) & 0xffu;
+}
+
+// hist[d * tiles + t] = keys of tile t with digit d
+__global__ __launch_bounds__(kB) void k_radix_hist(const unsigned long long *keys, uint32_t n, uint32_t shift,
+                                                   uint32_t tiles, uint32_t *hist)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * kTile;
+    for (uint32_t c = 0; c < kRadixItems; ++c) {
+        const size_t i = base + c * kB + threadIdx.x;
+        if (i < n) atomicAdd(&h[digit_of(keys[i], shift)], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// block d: exclusive scan of digit d's column of tile counts (in place) and
+// the digit's total
+__global__ __launch_bounds__(kB) void k_radix_colscan(uint32_t *hist, uint32_t tiles, uint32_t *total)
+{
+    __shared__ uint32_t part[kB];
+    uint32_t *col = hist + (size_t)blockIdx.x * tiles;
+    const uint32_t per = (tiles + kB - 1) / kB;
+    const uint32_t lo = min(tiles, threadIdx.x * per), hi = min(tiles, lo + per);
+    uint32_t sum = 0;
+    for (uint32_t t = lo; t < hi; ++t) sum += col[t];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < kB; off <<= 1) {   // inclusive scan of the partial sums
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (uint32_t t = lo; t < hi; ++t) {
+        const uint32_t v = col[t];
+        col[t] = run;
+        run += v;
+    }
+    if (threadIdx.x == kB - 1) total[blockIdx.x] = part[kB - 1];
+}
+
+// stable scatter: within a tile the keys keep their order per digit (chunks
+// of kB keys in order; inside a chunk, waves in order, lanes in order)
+__global__ __launch_bounds__(kB) void k_radix_scatter(const unsigned long long *keys, unsigned long long *out,
+                                                      uint32_t n, uint32_t shift, uint32_t tiles, const uint32_t *hist,
+                                                      const uint32_t *total)
+{
+    constexpr uint32_t kWaves = kB / 64;
+    __shared__ uint32_t base[256];           // digit base + this tile's prefix + keys of the digit so far
+    __shared__ uint32_t wcount[kWaves][256]; // keys per wave and digit in the current chunk
+    __shared__ uint32_t scan[256];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    // digit bases: exclusive scan of the digit totals
+    scan[tid] = total[tid];
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        const uint32_t v = tid >= off ? scan[tid - off] : 0u;
+        __syncthreads();
+        scan[tid] += v;
+        __syncthreads();
+    }
+    base[tid] = scan[tid] - total[tid] + hist[(size_t)tid * tiles + blockIdx.x];
+    for (uint32_t w = 0; w < kWaves; ++w) wcount[w][tid] = 0;
+    __syncthreads();
+    const size_t t0 = (size_t)blockIdx.x * kTile;
+    const unsigned long long below = (lane ? ~0ull >> (64 - lane) : 0ull);
+    for (uint32_t c = 0; c < kRadixItems; ++c) {
+        const size_t i = t0 + c * kB + tid;
+        const bool valid = i < n;
+        const unsigned long long key = valid ? keys[i] : 0ull;
+        const uint32_t d = valid ? digit_of(key, shift) : 256u;
+        // lanes of this wave with the same digit
+        unsigned long long peers = __ballot(valid);
+        for (uint32_t b = 0; b < 8; ++b) {
+            const unsigned long long m = __ballot(valid && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        const bool leader = valid && rank == 0;
+        if (leader) wcount[wv][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t off = base[d] + rank;
+            for (uint32_t w = 0; w < wv; ++w) off += wcount[w][d];
+            out[off] = key;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (uint32_t w = 0; w < kWaves; ++w) {
+            add += wcount[w][tid];
+            wcount[w][tid] = 0;
+        }
+        base[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill32(uint32_t *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)kB + threadIdx.x; i < n; i += (size_t)gridDim.x * kB) p[i] = 0u;
+}
+
 __global__ void k_order(const unsigned long long *k, uint32_t n, uint32_t *order)
 {
     for (uint32_t j = blockIdx.x * kB + threadIdx.x; j < n; j += gridDim.x * kB) order[j] = (uint32_t)(k[j] & 0xffffffffull);
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
-    }
-    hipError_t alloc(size_t bytes) { return hipMalloc(&p, std::max<size_t>(bytes, 16)); }
-    template <class T> T *as() const { return (T *)p; }
+// the builder's temporaries, carved from one caller-provided device region
+struct Scratch {
+    float *pos;
+    uint32_t *idx;
+    float4 *blo, *bhi;
+    float *cpart;
+    unsigned long long *keys, *sorted;
+    uint32_t *hist, *total;
+    int2 *child;
+    int *parent;
+    uint2 *range;
+    uint32_t *visits;
+    float *box;
+    Node *nodes;
+    uint2 *q0, *q1;
+    uint32_t *cnt;
+    uint32_t *order;
 };
+
+struct Carver {
+    char *base;
+    size_t off;
+    template <class T> T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = (T *)(base ? base + off : nullptr);
+        off += std::max<size_t>(count * sizeof(T), 16);
+        return p;
+    }
+};
+
+size_t carve(char *base, uint32_t nv, uint32_t nt, Scratch &S)
+{
+    const size_t g = grid_for(nt), tiles = (nt + kTile - 1) / kTile, nn = 2 * (size_t)nt - 1;
+    Carver c{base, 0};
+    S.pos = c.take<float>((size_t)nv * 3);
+    S.idx = c.take<uint32_t>((size_t)nt * 3);
+    S.blo = c.take<float4>(nt);
+    S.bhi = c.take<float4>(nt);
+    S.cpart = c.take<float>(g * 6);
+    S.keys = c.take<unsigned long long>(nt);
+    S.sorted = c.take<unsigned long long>(nt);
+    S.hist = c.take<uint32_t>(256 * tiles);
+    S.total = c.take<uint32_t>(256);
+    S.child = c.take<int2>(nt);
+    S.parent = c.take<int>(nn);
+    S.range = c.take<uint2>(nt);
+    S.visits = c.take<uint32_t>(nt);
+    S.box = c.take<float>(nn * 6);
+    S.nodes = c.take<Node>(nt);
+    S.q0 = c.take<uint2>(nt);
+    S.q1 = c.take<uint2>(nt);
+    S.cnt = c.take<uint32_t>(4);
+    S.order = c.take<uint32_t>(nt);
+    return c.off;
+}
 
 }  // namespace
 
@@ -267,25 +434,27 @@ struct DevBuf {
         if (e_ != hipSuccess) return e_;             \
     } while (0)
 
+size_t gpu_build_scratch_bytes(uint32_t nv, uint32_t nt)
+{
+    Scratch S;
+    return carve(nullptr, nv, nt, S);
+}
+
 hipError_t gpu_build_bvh(const float *pos, uint32_t nv, const uint32_t *idx, uint32_t nt, uint32_t leaf, float pad,
-                         hipStream_t s, std::vector<Node> &nodes, std::vector<uint32_t> &order, uint32_t &depth)
+                         void *scratch, size_t scratch_bytes, hipStream_t s, std::vector<Node> &nodes,
+                         std::vector<uint32_t> &order, uint32_t &depth)
 {
     const int n = (int)nt;
-    DevBuf d_pos, d_idx, d_blo, d_bhi, d_cpart, d_keys, d_sorted, d_tmp, d_child, d_parent, d_range, d_visits, d_box,
-        d_q0, d_q1, d_cnt, d_nodes, d_order;
+    Scratch S;
+    if (!scratch || carve(nullptr, nv, nt, S) > scratch_bytes) return hipErrorInvalidValue;
+    carve((char *)scratch, nv, nt, S);
     const uint32_t g = grid_for(nt);
-    BT(d_pos.alloc((size_t)nv * 12));
-    BT(d_idx.alloc((size_t)nt * 12));
-    BT(d_blo.alloc((size_t)nt * 16));
-    BT(d_bhi.alloc((size_t)nt * 16));
-    BT(d_cpart.alloc((size_t)g * 24));
-    BT(hipMemcpyAsync(d_pos.p, pos, (size_t)nv * 12, hipMemcpyHostToDevice, s));
-    BT(hipMemcpyAsync(d_idx.p, idx, (size_t)nt * 12, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_prim_boxes, dim3(g), dim3(kB), 0, s, d_pos.as<float>(), d_idx.as<uint32_t>(), nt,
-                       d_blo.as<float4>(), d_bhi.as<float4>(), d_cpart.as<float>());
+    BT(hipMemcpyAsync(S.pos, pos, (size_t)nv * 12, hipMemcpyHostToDevice, s));
+    BT(hipMemcpyAsync(S.idx, idx, (size_t)nt * 12, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_prim_boxes, dim3(g), dim3(kB), 0, s, S.pos, S.idx, nt, S.blo, S.bhi, S.cpart);
     BT(hipGetLastError());
     std::vector<float> part((size_t)g * 6);
-    BT(hipMemcpyAsync(part.data(), d_cpart.p, part.size() * 4, hipMemcpyDeviceToHost, s));
+    BT(hipMemcpyAsync(part.data(), S.cpart, part.size() * 4, hipMemcpyDeviceToHost, s));
     BT(hipStreamSynchronize(s));
     float cmin[3] = {INFINITY, INFINITY, INFINITY}, cmax[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t b = 0; b < g; ++b)
@@ -295,52 +464,43 @@ hipError_t gpu_build_bvh(const float *pos, uint32_t nv, const uint32_t *idx, uin
         }
     float sc[3];
     for (int a = 0; a < 3; ++a) sc[a] = cmax[a] > cmin[a] ? 1024.0f / (cmax[a] - cmin[a]) : 0.0f;
-    BT(d_keys.alloc((size_t)nt * 8));
-    BT(d_sorted.alloc((size_t)nt * 8));
-    hipLaunchKernelGGL(k_morton, dim3(g), dim3(kB), 0, s, d_blo.as<float4>(), d_bhi.as<float4>(), nt,
-                       make_float3(cmin[0], cmin[1], cmin[2]), make_float3(sc[0], sc[1], sc[2]),
-                       d_keys.as<unsigned long long>());
+    hipLaunchKernelGGL(k_morton, dim3(g), dim3(kB), 0, s, S.blo, S.bhi, nt, make_float3(cmin[0], cmin[1], cmin[2]),
+                       make_float3(sc[0], sc[1], sc[2]), S.keys);
     BT(hipGetLastError());
-    size_t tmp_bytes = 0;
-    BT(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, d_keys.as<unsigned long long>(),
-                                         d_sorted.as<unsigned long long>(), n, 0, 62, s));
-    BT(d_tmp.alloc(tmp_bytes));
-    BT(hipcub::DeviceRadixSort::SortKeys(d_tmp.p, tmp_bytes, d_keys.as<unsigned long long>(),
-                                         d_sorted.as<unsigned long long>(), n, 0, 62, s));
-    const size_t nn = 2 * (size_t)nt - 1;
-    BT(d_child.alloc((size_t)nt * 8));
-    BT(d_parent.alloc(nn * 4));
-    BT(d_range.alloc((size_t)nt * 8));
-    BT(d_visits.alloc((size_t)nt * 4));
-    BT(d_box.alloc(nn * 24));
-    BT(hipMemsetAsync(d_visits.p, 0, (size_t)nt * 4, s));
-    hipLaunchKernelGGL(k_hierarchy, dim3(g), dim3(kB), 0, s, d_sorted.as<unsigned long long>(), n, d_child.as<int2>(),
-                       d_parent.as<int>(), d_range.as<uint2>());
+    // four stable passes over the 30-bit code (bits 32..61 of the keys)
+    const uint32_t tiles = (nt + kTile - 1) / kTile;
+    unsigned long long *kin = S.keys, *kout = S.sorted;
+    for (uint32_t shift = 32; shift < 64; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(tiles), dim3(kB), 0, s, kin, nt, shift, tiles, S.hist);
+        BT(hipGetLastError());
+        hipLaunchKernelGGL(k_radix_colscan, dim3(256), dim3(kB), 0, s, S.hist, tiles, S.total);
+        BT(hipGetLastError());
+        hipLaunchKernelGGL(k_radix_scatter, dim3(tiles), dim3(kB), 0, s, kin, kout, nt, shift, tiles, S.hist, S.total);
+        BT(hipGetLastError());
+        std::swap(kin, kout);
+    }
+    const unsigned long long *sorted = kin;
+    hipLaunchKernelGGL(k_fill32, dim3(grid_for(nt)), dim3(kB), 0, s, S.visits, (size_t)nt);
     BT(hipGetLastError());
-    hipLaunchKernelGGL(k_refit, dim3(g), dim3(kB), 0, s, d_sorted.as<unsigned long long>(), d_blo.as<float4>(),
-                       d_bhi.as<float4>(), n, d_child.as<int2>(), d_parent.as<int>(), d_visits.as<uint32_t>(),
-                       d_box.as<float>());
+    hipLaunchKernelGGL(k_hierarchy, dim3(g), dim3(kB), 0, s, sorted, n, S.child, S.parent, S.range);
+    BT(hipGetLastError());
+    hipLaunchKernelGGL(k_refit, dim3(g), dim3(kB), 0, s, sorted, S.blo, S.bhi, n, S.child, S.parent, S.visits, S.box);
     BT(hipGetLastError());
     // collapse, one level per launch; a 4-wide node takes at least one binary
     // inner node, so n - 1 slots suffice
-    BT(d_nodes.alloc((size_t)nt * sizeof(Node)));
-    BT(d_q0.alloc((size_t)nt * 8));
-    BT(d_q1.alloc((size_t)nt * 8));
-    BT(d_cnt.alloc(16));
     const uint2 root = make_uint2(0u, 0u);
     const uint32_t init[4] = {1u, 0u, 1u, 0u};  // queue 0 count, queue 1 count, nodes used, -
-    BT(hipMemcpyAsync(d_q0.p, &root, 8, hipMemcpyHostToDevice, s));
-    BT(hipMemcpyAsync(d_cnt.p, init, 16, hipMemcpyHostToDevice, s));
-    uint32_t *cnt = d_cnt.as<uint32_t>();
+    BT(hipMemcpyAsync(S.q0, &root, 8, hipMemcpyHostToDevice, s));
+    BT(hipMemcpyAsync(S.cnt, init, 16, hipMemcpyHostToDevice, s));
     uint32_t pending = 1, levels = 0;
     while (pending) {
-        uint2 *qin = (levels & 1) ? d_q1.as<uint2>() : d_q0.as<uint2>();
-        uint2 *qout = (levels & 1) ? d_q0.as<uint2>() : d_q1.as<uint2>();
-        uint32_t *nin = cnt + (levels & 1), *nout = cnt + ((levels + 1) & 1);
+        uint2 *qin = (levels & 1) ? S.q1 : S.q0;
+        uint2 *qout = (levels & 1) ? S.q0 : S.q1;
+        uint32_t *nin = S.cnt + (levels & 1), *nout = S.cnt + ((levels + 1) & 1);
         const uint32_t zero = 0;
         BT(hipMemcpyAsync(nout, &zero, 4, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_collapse, dim3(grid_for(pending)), dim3(kB), 0, s, qin, nin, qout, nout, cnt + 2, n, leaf,
-                           pad, d_child.as<int2>(), d_range.as<uint2>(), d_box.as<float>(), d_nodes.as<Node>());
+        hipLaunchKernelGGL(k_collapse, dim3(grid_for(pending)), dim3(kB), 0, s, qin, nin, qout, nout, S.cnt + 2, n,
+                           leaf, pad, S.child, S.range, S.box, S.nodes);
         BT(hipGetLastError());
         BT(hipMemcpyAsync(&pending, nout, 4, hipMemcpyDeviceToHost, s));
         BT(hipStreamSynchronize(s));
@@ -348,17 +508,44 @@ hipError_t gpu_build_bvh(const float *pos, uint32_t nv, const uint32_t *idx, uin
         if (levels > 128) return hipErrorUnknown;  // a key tree of 62 bits is far shallower
     }
     uint32_t used = 0;
-    BT(hipMemcpyAsync(&used, cnt + 2, 4, hipMemcpyDeviceToHost, s));
-    BT(d_order.alloc((size_t)nt * 4));
-    hipLaunchKernelGGL(k_order, dim3(g), dim3(kB), 0, s, d_sorted.as<unsigned long long>(), nt, d_order.as<uint32_t>());
+    BT(hipMemcpyAsync(&used, S.cnt + 2, 4, hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_order, dim3(g), dim3(kB), 0, s, sorted, nt, S.order);
     BT(hipGetLastError());
     BT(hipStreamSynchronize(s));
     nodes.resize(used);
     order.resize(nt);
-    BT(hipMemcpyAsync(nodes.data(), d_nodes.p, (size_t)used * sizeof(Node), hipMemcpyDeviceToHost, s));
-    BT(hipMemcpyAsync(order.data(), d_order.p, (size_t)nt * 4, hipMemcpyDeviceToHost, s));
+    BT(hipMemcpyAsync(nodes.data(), S.nodes, (size_t)used * sizeof(Node), hipMemcpyDeviceToHost, s));
+    BT(hipMemcpyAsync(order.data(), S.order, (size_t)nt * 4, hipMemcpyDeviceToHost, s));
     BT(hipStreamSynchronize(s));
     depth = levels - 1;
+    return hipSuccess;
+}
+
+// ---- a build scratch region that needs no allocation: a file-scope device
+// array of kStaticScratch bytes, resident on every GPU that loads the library
+// until the process ends. Host code never passes the array's name to a
+// kernel: its device address is looked up once per device.
+namespace {
+__device__ __align__(256) unsigned char scratch[kStaticScratch];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+}  // namespace
+
+hipError_t static_scratch(int device, void **ptr)
+{
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        BT(hipGetDevice(&cur));
+        if (cur != device) BT(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
     return hipSuccess;
 }
 

@@ -335,6 +335,8 @@ struct qpt_ctx {
     uint32_t stack_need = 3;      // traversal stack entries per ray the BVH can require
     // training runs on a stream of its own, one batch behind the renderer
     hipStream_t tstream = nullptr;
+    bool own_tstream = false, own_lstream = false;   // created here (else the caller's, not destroyed)
+    void *static_scratch = nullptr;                  // this device's allocation-free build region
     hipEvent_t ev_rec[2] = {nullptr, nullptr};    // batch k's samples are in the ring
     hipEvent_t ev_train[2] = {nullptr, nullptr};  // the step publishing into buffer k has finished
     bool train_pending[2] = {false, false};
@@ -1022,6 +1024,11 @@ int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
         }
         c->trav_threads = (uint32_t)prop.multiProcessorCount * kTravBlocksPerCU * kBlock;
         c->guide_blocks = (uint32_t)prop.multiProcessorCount;
+        // this device's address of the allocation-free build region (looked up once per device)
+        if (static_scratch(hip_device, &c->static_scratch) != hipSuccess) {
+            delete c;
+            return QPT_E_HIP;
+        }
     }
     *out = c;
     return QPT_OK;
@@ -1033,23 +1040,38 @@ void qpt_destroy(qpt_ctx *ctx)
     if (ctx->tstream) {
         DeviceGuard g(ctx->device);
         (void)hipStreamSynchronize(ctx->tstream);
-        for (int k = 0; k < 2; ++k) {
-            if (ctx->ev_rec[k]) (void)hipEventDestroy(ctx->ev_rec[k]);
-            if (ctx->ev_train[k]) (void)hipEventDestroy(ctx->ev_train[k]);
-        }
-        (void)hipStreamDestroy(ctx->tstream);
+        if (ctx->own_tstream) (void)hipStreamDestroy(ctx->tstream);
     }
-    if (ctx->lstream) {
+    for (int k = 0; k < 2; ++k) {
         DeviceGuard g(ctx->device);
-        (void)hipStreamSynchronize(ctx->lstream);
+        if (ctx->ev_rec[k]) (void)hipEventDestroy(ctx->ev_rec[k]);
+        if (ctx->ev_train[k]) (void)hipEventDestroy(ctx->ev_train[k]);
+    }
+    if (ctx->ev_lane_in) {
+        DeviceGuard g(ctx->device);
+        if (ctx->lstream) (void)hipStreamSynchronize(ctx->lstream);
         (void)hipEventDestroy(ctx->ev_lane_in);
         (void)hipEventDestroy(ctx->ev_lane_out);
         (void)hipEventDestroy(ctx->ev_acc);
         (void)hipEventDestroy(ctx->ev_fin);
         if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
+    }
+    if (ctx->lstream && ctx->own_lstream) {
+        DeviceGuard g(ctx->device);
         (void)hipStreamDestroy(ctx->lstream);
     }
     delete ctx;
+}
+
+int qpt_set_streams(qpt_ctx *c, void *lane_stream, void *train_stream)
+{
+    if (!c || !lane_stream || !train_stream) return QPT_E_INVALID;
+    if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
+    if (c->ev_lane_in) return fail(c, QPT_E_STATE, "set_streams after the first bind_workspace");
+    c->lstream = (hipStream_t)lane_stream;
+    c->tstream = (hipStream_t)train_stream;
+    c->own_lstream = c->own_tstream = false;
+    return QPT_OK;
 }
 
 const char *qpt_last_error(const qpt_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -1160,71 +1182,116 @@ static void finish_bvh(qpt_ctx *c, const std::vector<uint32_t> &order, uint32_t 
     c->bvh_ok = true;
 }
 
+// the GPU builder (linear BVH, collapsed there into the 4-wide layout) with
+// its temporaries in the device region [scratch, scratch + bytes)
+static int build_bvh_gpu(qpt_ctx *c, uint32_t leaf, void *scratch, size_t bytes, qpt_bvh_stats *stats,
+                         std::chrono::steady_clock::time_point t0)
+{
+    const uint32_t nt = (uint32_t)c->tri_mat.size(), nv = (uint32_t)(c->pos.size() / 3);
+    const size_t need = gpu_build_scratch_bytes(nv, nt);
+    if (bytes < need)
+        return fail(c, QPT_E_NOMEM, "GPU BVH build needs %zu bytes of scratch, %zu given", need, bytes);
+    double maxabs = 0.0;
+    for (size_t q = 0; q < c->idx.size(); ++q)
+        for (int a = 0; a < 3; ++a) maxabs = std::max(maxabs, (double)std::fabs(c->pos[3 * (size_t)c->idx[q] + a]));
+    const float pad = (float)(std::ldexp(std::max(maxabs, 1e-3), -18));
+    std::vector<uint32_t> order;
+    uint32_t depth4 = 0;
+    DeviceGuard g(c->device);
+    if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
+    hipError_t e = gpu_build_bvh(c->pos.data(), nv, c->idx.data(), nt, leaf, pad, scratch, bytes, c->stream, c->gnodes,
+                                 order, depth4);
+    if (e != hipSuccess) return fail(c, QPT_E_HIP, "GPU BVH build: %s", hipGetErrorString(e));
+    // leaves and the SAH cost of the 4-wide tree (node box = union of its slots)
+    auto area = [](float dx, float dy, float dz) { return 2.0 * ((double)dx * dy + (double)dy * dz + (double)dz * dx); };
+    uint32_t leaves = 0;
+    double sah = 0.0, root_area = 0.0;
+    for (size_t k = 0; k < c->gnodes.size(); ++k) {
+        const Node &nd = c->gnodes[k];
+        const float lo[3][4] = {{nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w}, {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w},
+                                {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w}};
+        const float hi[3][4] = {{nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w}, {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w},
+                                {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w}};
+        const int ref[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
+        float ulo[3] = {INFINITY, INFINITY, INFINITY}, uhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int q = 0; q < nd.pad.x; ++q) {
+            for (int a = 0; a < 3; ++a) {
+                ulo[a] = std::min(ulo[a], lo[a][q]);
+                uhi[a] = std::max(uhi[a], hi[a][q]);
+            }
+            if (ref[q] < 0) ++leaves;
+        }
+        const double na = area(uhi[0] - ulo[0], uhi[1] - ulo[1], uhi[2] - ulo[2]);
+        if (k == 0) root_area = std::max(na, 1e-30);
+        sah += na / root_area;
+        for (int q = 0; q < nd.pad.x; ++q)
+            if (ref[q] < 0)
+                sah += area(hi[0][q] - lo[0][q], hi[1][q] - lo[1][q], hi[2][q] - lo[2][q]) / root_area *
+                       (double)((~(uint32_t)ref[q] & 7u) + 1u);
+    }
+    finish_bvh(c, order, depth4);
+    auto t1 = std::chrono::steady_clock::now();
+    if (stats) {
+        stats->num_nodes = (uint32_t)c->gnodes.size();
+        stats->num_leaves = leaves;
+        stats->max_depth = depth4;
+        stats->reserved = 0;
+        stats->sah_cost = sah;
+        stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    return QPT_OK;
+}
+
+static int bvh_opts(qpt_ctx *c, const qpt_bvh_opts *opts, uint32_t &leaf, uint32_t &bins, uint32_t &builder)
+{
+    // defaults: leaves of up to 3 triangles (measured: 2-3 trace 1-2% faster than 4, 6-8 up to
+    // 12% slower on the grid and city workloads), 16 bins (32 and 64 made no difference)
+    leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 3;
+    bins = opts && opts->sah_bins ? opts->sah_bins : 16;
+    builder = opts ? opts->builder : 0;
+    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64 || builder > 1) return fail(c, QPT_E_INVALID, "bad BVH options");
+    return QPT_OK;
+}
+
+int qpt_bvh_scratch_size(qpt_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return QPT_E_INVALID;
+    if (!c->scene_ok) return fail(c, QPT_E_STATE, "bvh_scratch_size before build_scene");
+    *bytes = gpu_build_scratch_bytes((uint32_t)(c->pos.size() / 3), (uint32_t)c->tri_mat.size());
+    return QPT_OK;
+}
+
+int qpt_build_bvh_noalloc(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
+{
+    if (!c) return QPT_E_INVALID;
+    if (!c->scene_ok) return fail(c, QPT_E_STATE, "build_bvh before build_scene");
+    if (c->device < 0) return fail(c, QPT_E_STATE, "the GPU builder needs a device context");
+    uint32_t leaf, bins, builder;
+    if (int rc = bvh_opts(c, opts, leaf, bins, builder)) return rc;
+    const uint32_t nt = (uint32_t)c->tri_mat.size();
+    if (nt <= leaf) return fail(c, QPT_E_INVALID, "the GPU builder needs more triangles than a leaf holds");
+    const size_t need = gpu_build_scratch_bytes((uint32_t)(c->pos.size() / 3), nt);
+    if (need > kStaticScratch)
+        return fail(c, QPT_E_INVALID, "scene too large for the allocation-free build: %zu bytes of scratch needed, "
+                    "the library's static region holds %zu", need, kStaticScratch);
+    if (!c->static_scratch) return fail(c, QPT_E_STATE, "no static scratch region on this device");
+    c->bvh_ok = c->bound = false;
+    return build_bvh_gpu(c, leaf, c->static_scratch, kStaticScratch, stats, std::chrono::steady_clock::now());
+}
+
 int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
 {
     if (!c) return QPT_E_INVALID;
     if (!c->scene_ok) return fail(c, QPT_E_STATE, "build_bvh before build_scene");
     c->bvh_ok = c->bound = false;
     auto t0 = std::chrono::steady_clock::now();
-    // defaults: leaves of up to 3 triangles (measured: 2-3 trace 1-2% faster than 4, 6-8 up to
-    // 12% slower on the grid and city workloads), 16 bins (32 and 64 made no difference)
-    uint32_t leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 3;
-    uint32_t bins = opts && opts->sah_bins ? opts->sah_bins : 16;
-    const uint32_t builder = opts ? opts->builder : 0;
-    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64 || builder > 1) return fail(c, QPT_E_INVALID, "bad BVH options");
+    uint32_t leaf, bins, builder;
+    if (int rc = bvh_opts(c, opts, leaf, bins, builder)) return rc;
     uint32_t nt = (uint32_t)c->tri_mat.size();
     if (builder == 1 && c->device < 0) return fail(c, QPT_E_STATE, "the GPU builder needs a device context");
     if (builder == 1 && nt > leaf) {
-        // linear BVH on the GPU, collapsed there into the 4-wide layout
-        double maxabs = 0.0;
-        for (size_t q = 0; q < c->idx.size(); ++q)
-            for (int a = 0; a < 3; ++a) maxabs = std::max(maxabs, (double)std::fabs(c->pos[3 * (size_t)c->idx[q] + a]));
-        const float pad = (float)(std::ldexp(std::max(maxabs, 1e-3), -18));
-        std::vector<uint32_t> order;
-        uint32_t depth4 = 0;
-        DeviceGuard g(c->device);
-        if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
-        hipError_t e = gpu_build_bvh(c->pos.data(), (uint32_t)(c->pos.size() / 3), c->idx.data(), nt, leaf, pad,
-                                     c->stream, c->gnodes, order, depth4);
-        if (e != hipSuccess) return fail(c, QPT_E_HIP, "GPU BVH build: %s", hipGetErrorString(e));
-        // leaves and the SAH cost of the 4-wide tree (node box = union of its slots)
-        auto area = [](float dx, float dy, float dz) { return 2.0 * ((double)dx * dy + (double)dy * dz + (double)dz * dx); };
-        uint32_t leaves = 0;
-        double sah = 0.0, root_area = 0.0;
-        for (size_t k = 0; k < c->gnodes.size(); ++k) {
-            const Node &nd = c->gnodes[k];
-            const float lo[3][4] = {{nd.lox.x, nd.lox.y, nd.lox.z, nd.lox.w}, {nd.loy.x, nd.loy.y, nd.loy.z, nd.loy.w},
-                                    {nd.loz.x, nd.loz.y, nd.loz.z, nd.loz.w}};
-            const float hi[3][4] = {{nd.hix.x, nd.hix.y, nd.hix.z, nd.hix.w}, {nd.hiy.x, nd.hiy.y, nd.hiy.z, nd.hiy.w},
-                                    {nd.hiz.x, nd.hiz.y, nd.hiz.z, nd.hiz.w}};
-            const int ref[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
-            float ulo[3] = {INFINITY, INFINITY, INFINITY}, uhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-            for (int q = 0; q < nd.pad.x; ++q) {
-                for (int a = 0; a < 3; ++a) {
-                    ulo[a] = std::min(ulo[a], lo[a][q]);
-                    uhi[a] = std::max(uhi[a], hi[a][q]);
-                }
-                if (ref[q] < 0) ++leaves;
-            }
-            const double na = area(uhi[0] - ulo[0], uhi[1] - ulo[1], uhi[2] - ulo[2]);
-            if (k == 0) root_area = std::max(na, 1e-30);
-            sah += na / root_area;
-            for (int q = 0; q < nd.pad.x; ++q)
-                if (ref[q] < 0)
-                    sah += area(hi[0][q] - lo[0][q], hi[1][q] - lo[1][q], hi[2][q] - lo[2][q]) / root_area *
-                           (double)((~(uint32_t)ref[q] & 7u) + 1u);
-        }
-        finish_bvh(c, order, depth4);
-        auto t1 = std::chrono::steady_clock::now();
-        if (stats) {
-            stats->num_nodes = (uint32_t)c->gnodes.size();
-            stats->num_leaves = leaves;
-            stats->max_depth = depth4;
-            stats->reserved = 0;
-            stats->sah_cost = sah;
-            stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        }
-        return QPT_OK;
+        if (!opts->scratch) return fail(c, QPT_E_INVALID, "the GPU builder needs caller scratch (qpt_bvh_scratch_size)");
+        return build_bvh_gpu(c, leaf, opts->scratch, opts->scratch_bytes, stats, t0);
     }
     std::vector<PrimInfo> prim(nt);
     double maxabs = 0.0;
@@ -1368,14 +1435,22 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
     HIP_TRY(c, join_train(c));
-    if (!c->tstream) {
-        // default priority; non-blocking so it can overlap a caller's legacy stream
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->tstream, hipStreamNonBlocking));
+    if (!c->ev_lane_in) {
+        // the second lane's and the training stream: the caller's (qpt_set_streams), else
+        // the library's own, default priority, non-blocking so they can overlap a
+        // caller's legacy stream
+        if (!c->tstream) {
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->tstream, hipStreamNonBlocking));
+            c->own_tstream = true;
+        }
+        if (!c->lstream) {
+            HIP_TRY(c, hipStreamCreateWithFlags(&c->lstream, hipStreamNonBlocking));
+            c->own_lstream = true;
+        }
         for (int k = 0; k < 2; ++k) {
             HIP_TRY(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
             HIP_TRY(c, hipEventCreateWithFlags(&c->ev_train[k], hipEventDisableTiming));
         }
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->lstream, hipStreamNonBlocking));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_in, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
@@ -1798,14 +1873,15 @@ int qpt_debug_pixel_index(qpt_ctx *c, uint64_t pass, uint64_t *out)
 }
 
 int qpt_debug_trace(qpt_ctx *c, const float *rays, uint32_t n, int any_hit, int brute_force, float *t,
-                    uint32_t *tri, float *b12)
+                    uint32_t *tri, float *b12, uint32_t *stack_max)
 {
     if (!c || (n && (!rays || !tri))) return QPT_E_INVALID;
     if (!any_hit && n && (!t || !b12)) return fail(c, QPT_E_INVALID, "closest hit needs t and b12");
     if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
-    HIP_TRY(c, launch_debug_trace(c->frame, c->pool, rays, n, any_hit, brute_force, t, tri, b12, c->stream));
+    HIP_TRY(c, launch_debug_trace(c->frame, c->pool, rays, n, any_hit, brute_force, t, tri, b12,
+                                  brute_force ? nullptr : stack_max, c->stream));
     return QPT_OK;
 }
 

@@ -197,11 +197,19 @@ struct GuideTrain {
 };
 
 // GPU BVH build (qpt_build.hip): linear BVH over Morton-sorted centroids,
-// collapsed into 4-wide nodes on the device; allocates and frees its own
-// temporaries, synchronises `s`, returns the nodes (root first), the leaf
-// order of the triangles and the 4-wide depth. Needs nt > leaf.
+// collapsed into 4-wide nodes on the device. Its temporaries come from the
+// device region `scratch` (at least gpu_build_scratch_bytes(nv, nt) bytes,
+// hipErrorInvalidValue otherwise); synchronises `s`, returns the nodes (root
+// first), the leaf order of the triangles and the 4-wide depth. Needs nt > leaf.
+size_t gpu_build_scratch_bytes(uint32_t nv, uint32_t nt);
 hipError_t gpu_build_bvh(const float *pos, uint32_t nv, const uint32_t *idx, uint32_t nt, uint32_t leaf, float pad,
-                         hipStream_t s, std::vector<Node> &nodes, std::vector<uint32_t> &order, uint32_t &depth);
+                         void *scratch, size_t scratch_bytes, hipStream_t s, std::vector<Node> &nodes,
+                         std::vector<uint32_t> &order, uint32_t &depth);
+// The library's one allocation-free scratch region: a file-scope device array
+// of kStaticScratch bytes per GPU (qpt_build.hip), its device address looked
+// up once per device (hipGetSymbolAddress with that device current).
+constexpr size_t kStaticScratch = (size_t)64 << 20;
+hipError_t static_scratch(int device, void **ptr);
 
 // kernel launchers (qpt_kernels.hip)
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
@@ -243,6 +251,6 @@ hipError_t launch_debug_light_sample(const Frame &f, const uint64_t *S, const fl
 hipError_t launch_debug_records(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix, uint64_t pass0,
                                 uint32_t npass, uint32_t n, uint32_t *ident, float *out, hipStream_t s);
 hipError_t launch_debug_trace(const Frame &f, const Pool &pool, const float *rays, uint32_t n, int any_hit,
-                              int brute, float *t, uint32_t *tri, float *b12, hipStream_t s);
+                              int brute, float *t, uint32_t *tri, float *b12, uint32_t *depth, hipStream_t s);
 
 }  // namespace qpt

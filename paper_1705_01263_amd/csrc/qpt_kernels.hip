@@ -252,6 +252,7 @@ struct HitRec {
     uint32_t tri;   // BVH-order index
     uint32_t id;    // input id (tie-break)
     uint32_t nodes, tests;  // traversal work: node fetches, triangle tests
+    uint32_t depth;         // deepest traversal stack (DEPTH = true only)
 };
 
 // sum a per-lane count over the wave and add it to a 64-bit counter once
@@ -270,7 +271,7 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
 // (stride gs) sized by the host for the tree's depth (at most 3 pushes per
 // level). Children are culled against the current closest t with a closed
 // interval, so the result does not depend on the visiting order.
-template <bool ANY>
+template <bool ANY, bool DEPTH = false>
 __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs)
 {
     h.t = tmax;
@@ -278,6 +279,7 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
     h.id = kNoHit;
     h.nodes = 0;
     h.tests = 0;
+    h.depth = 0;
     int sp = 0;
     int ref = 0;
     const int step = (int)blockDim.x;
@@ -286,6 +288,7 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
         if (sp < (int)kShortStack) stk[sp * step] = v;
         else gstk[(sp - kShortStack) * gs] = v;
         ++sp;
+        if (DEPTH) h.depth = max(h.depth, (uint32_t)sp);
     };
     while (true) {
         if (ref >= 0) {
@@ -1271,7 +1274,7 @@ __global__ void k_debug_pixel_index(Frame F, uint64_t pass, uint64_t *out)
 
 template <bool ANY>
 __global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, Pool P, const float *rays, uint32_t n, float *t,
-                                                        uint32_t *tri, float *b12)
+                                                        uint32_t *tri, float *b12, uint32_t *depth)
 {
     __shared__ int stk[kShortStack * kBlock];
     int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
@@ -1281,7 +1284,8 @@ __global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, Pool P, const f
         const float *ry = rays + 8 * (size_t)q;
         RayPre r = prepare(mk(ry[0], ry[1], ry[2]), mk(ry[4], ry[5], ry[6]));
         HitRec h;
-        bool hit = traverse<ANY>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
+        bool hit = traverse<ANY, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
+        if (depth) depth[q] = h.depth;
         if (ANY) {
             tri[q] = hit ? 1u : 0u;
             continue;
@@ -1480,7 +1484,7 @@ hipError_t launch_debug_pixel_index(const Frame &F, uint64_t pass, uint64_t *out
 }
 
 hipError_t launch_debug_trace(const Frame &F, const Pool &P, const float *rays, uint32_t n, int any_hit,
-                              int brute, float *t, uint32_t *tri, float *b12, hipStream_t s)
+                              int brute, float *t, uint32_t *tri, float *b12, uint32_t *depth, hipStream_t s)
 {
     dim3 b(kBlock);
     if (brute) {
@@ -1490,8 +1494,8 @@ hipError_t launch_debug_trace(const Frame &F, const Pool &P, const float *rays, 
         return hipGetLastError();
     }
     dim3 g(blocks_for(n, P.trav_threads / kBlock));
-    if (any_hit) hipLaunchKernelGGL((k_debug_trace<true>), g, b, 0, s, F, P, rays, n, t, tri, b12);
-    else hipLaunchKernelGGL((k_debug_trace<false>), g, b, 0, s, F, P, rays, n, t, tri, b12);
+    if (any_hit) hipLaunchKernelGGL((k_debug_trace<true>), g, b, 0, s, F, P, rays, n, t, tri, b12, depth);
+    else hipLaunchKernelGGL((k_debug_trace<false>), g, b, 0, s, F, P, rays, n, t, tri, b12, depth);
     return hipGetLastError();
 }
 }  // namespace qpt

@@ -37,7 +37,8 @@ class qpt_scene_desc(C.Structure):
 
 
 class qpt_bvh_opts(C.Structure):
-    _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32), ("builder", C.c_uint32)]
+    _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32), ("builder", C.c_uint32),
+                ("reserved", C.c_uint32), ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
 
 
 class qpt_bvh_stats(C.Structure):
@@ -71,7 +72,8 @@ GUIDE_PARAMS = 13032
 
 
 EXPORTS = [
-    "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_workspace_size",
+    "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_build_bvh_noalloc",
+    "qpt_bvh_scratch_size", "qpt_set_streams", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
     "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
     "qpt_abort", "qpt_load_accum", "qpt_guide_get_state", "qpt_guide_set_state",
@@ -102,6 +104,9 @@ def lib():
             "qpt_last_error": ([P], C.c_char_p),
             "qpt_build_scene": ([P, C.POINTER(qpt_scene_desc)], i32),
             "qpt_build_bvh": ([P, C.POINTER(qpt_bvh_opts), C.POINTER(qpt_bvh_stats)], i32),
+            "qpt_build_bvh_noalloc": ([P, C.POINTER(qpt_bvh_opts), C.POINTER(qpt_bvh_stats)], i32),
+            "qpt_bvh_scratch_size": ([P, C.POINTER(C.c_size_t)], i32),
+            "qpt_set_streams": ([P, P, P], i32),
             "qpt_workspace_size": ([P, u32, C.POINTER(C.c_size_t)], i32),
             "qpt_bind_workspace": ([P, P, C.c_size_t, u32], i32),
             "qpt_render_pass": ([P, u64, u32, C.POINTER(qpt_render_opts)], i32),
@@ -110,7 +115,7 @@ def lib():
             "qpt_get_stats": ([P, C.POINTER(qpt_stats)], i32),
             "qpt_debug_sample_bits": ([P, P, P, u32, i32, P], i32),
             "qpt_debug_pixel_index": ([P, u64, P], i32),
-            "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P], i32),
+            "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P, P], i32),
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
             "qpt_abort": ([P], i32),
             "qpt_load_accum": ([P, P, P, i32], i32),
@@ -213,13 +218,30 @@ class Context:
         self.check(self.L.qpt_build_scene(self.h, C.byref(d)), "qpt_build_scene")
         self.W, self.H = sc.width, sc.height
 
-    def build_bvh(self, max_leaf_size: int = 0, sah_bins: int = 0, builder: int = 0) -> qpt_bvh_stats:
-        """builder 0: binned SAH on the host; 1: linear BVH on the GPU. Zero sizes take the
-        library's defaults (leaves of up to 3 triangles, 16 bins)."""
-        o = qpt_bvh_opts(max_leaf_size, sah_bins, builder)
+    def build_bvh(self, max_leaf_size: int = 0, sah_bins: int = 0, builder: int = 0, scratch=None,
+                  scratch_bytes: int = 0) -> qpt_bvh_stats:
+        """builder 0: binned SAH on the host; 1: linear BVH on the GPU, its temporaries in the
+        caller's device memory `scratch` (a pointer, at least bvh_scratch_size() bytes). Zero
+        sizes take the library's defaults (leaves of up to 3 triangles, 16 bins)."""
+        o = qpt_bvh_opts(max_leaf_size, sah_bins, builder, 0, scratch, scratch_bytes)
         st = qpt_bvh_stats()
         self.check(self.L.qpt_build_bvh(self.h, C.byref(o), C.byref(st)), "qpt_build_bvh")
         return st
+
+    def build_bvh_noalloc(self, max_leaf_size: int = 0) -> qpt_bvh_stats:
+        o = qpt_bvh_opts(max_leaf_size, 0, 1, 0, None, 0)
+        st = qpt_bvh_stats()
+        self.check(self.L.qpt_build_bvh_noalloc(self.h, C.byref(o), C.byref(st)), "qpt_build_bvh_noalloc")
+        return st
+
+    def bvh_scratch_size(self) -> int:
+        n = C.c_size_t()
+        self.check(self.L.qpt_bvh_scratch_size(self.h, C.byref(n)), "qpt_bvh_scratch_size")
+        return n.value
+
+    def set_streams(self, lane_stream: int, train_stream: int) -> None:
+        self.check(self.L.qpt_set_streams(self.h, C.c_void_p(lane_stream), C.c_void_p(train_stream)),
+                   "qpt_set_streams")
 
     def workspace_size(self, pool_paths: int = 0) -> int:
         n = C.c_size_t()
@@ -331,9 +353,9 @@ class Context:
     def debug_pixel_index(self, pass_: int, out) -> None:
         self.check(self.L.qpt_debug_pixel_index(self.h, pass_, _p(out)), "qpt_debug_pixel_index")
 
-    def debug_trace(self, rays, n, any_hit, brute_force, t, tri, b12) -> None:
+    def debug_trace(self, rays, n, any_hit, brute_force, t, tri, b12, stack_max=None) -> None:
         self.check(self.L.qpt_debug_trace(self.h, _p(rays), n, int(any_hit), int(brute_force), _p(t), _p(tri),
-                                          _p(b12)), "qpt_debug_trace")
+                                          _p(b12), _p(stack_max)), "qpt_debug_trace")
 
     def debug_light_tree(self):
         """The light tree's host tables (same keys as the oracle's)."""
@@ -416,9 +438,18 @@ class Renderer:
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = Context(device, self.stream.cuda_stream)
+        # the second batch in flight and the guide's training run on torch streams (default priority)
+        self.aux_streams = (torch.cuda.Stream(self.device), torch.cuda.Stream(self.device))
+        self.ctx.set_streams(self.aux_streams[0].cuda_stream, self.aux_streams[1].cuda_stream)
         self.ctx.ntri = sc.num_triangles
         self.ctx.build_scene(sc)
-        self.bvh_stats = self.ctx.build_bvh(builder=bvh_builder)
+        if bvh_builder == 1:
+            nb = self.ctx.bvh_scratch_size()
+            tmp = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self.bvh_stats = self.ctx.build_bvh(builder=1, scratch=(tmp.data_ptr() + 255) & ~255, scratch_bytes=nb)
+            del tmp
+        else:
+            self.bvh_stats = self.ctx.build_bvh(builder=bvh_builder)
         self.pool_paths = pool_paths
         nbytes = self.ctx.workspace_size(pool_paths)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

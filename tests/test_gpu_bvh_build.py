@@ -36,6 +36,46 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 
 
+def _gpu_build(c):
+    """The GPU builder with its temporaries in a torch scratch tensor."""
+    nb = c.bvh_scratch_size()
+    tmp = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    return c.build_bvh(builder=1, scratch=(tmp.data_ptr() + 255) & ~255, scratch_bytes=nb)
+
+
+def _spread10(v):
+    v = v.astype(np.uint64) & 0x3FF
+    v = (v | (v << 16)) & 0x030000FF
+    v = (v | (v << 8)) & 0x0300F00F
+    v = (v | (v << 4)) & 0x030C30C3
+    v = (v | (v << 2)) & 0x09249249
+    return v
+
+
+def test_gpu_build_sorts_by_morton_code(Renderer):
+    """The builder's radix sort: the leaf order of the triangles is their
+    stable order by the 30-bit Morton code of the box centre (FP32, the
+    centroid box scaled to 1024 cells per axis), equal codes by triangle id,
+    computed here independently with numpy."""
+    from paper_1705_01263_amd import qpt
+    sc = g.city(blocks=8, target_tris=200_000, emissive_cells=500)
+    c = qpt.Context(0)
+    c.ntri = sc.num_triangles
+    c.build_scene(sc)
+    _gpu_build(c)
+    _, order = c.debug_bvh_nodes()
+    P = sc.positions.astype(np.float32)[sc.indices.astype(np.int64)]
+    lo, hi = P.min(1), P.max(1)
+    cen = np.float32(0.5) * (lo + hi)
+    cmin, cmax = cen.min(0), cen.max(0)
+    scale = np.where(cmax > cmin, np.float32(1024.0) / (cmax - cmin), np.float32(0.0)).astype(np.float32)
+    q = np.clip((cen - cmin) * scale, np.float32(0.0), np.float32(1023.0)).astype(np.uint32)
+    code = (_spread10(q[:, 0]) << 2) | (_spread10(q[:, 1]) << 1) | _spread10(q[:, 2])
+    want = np.argsort(code, kind="stable").astype(np.uint32)
+    _say(f"[gpu bvh] sort check over {sc.num_triangles} triangles, distinct codes {np.unique(code).shape[0]}")
+    assert np.array_equal(order, want)
+
+
 @pytest.mark.parametrize("which", ["cornell", "grid4", "quad", "city_sub"])
 def test_gpu_built_tree_structure(Renderer, which):
     from paper_1705_01263_amd import qpt
@@ -46,7 +86,7 @@ def test_gpu_built_tree_structure(Renderer, which):
     c = qpt.Context(0)
     c.ntri = sc.num_triangles
     c.build_scene(sc)
-    st = c.build_bvh(builder=1)
+    st = _gpu_build(c)
     _say(f"    nodes {st.num_nodes} leaves {st.num_leaves} depth {st.max_depth} sah {st.sah_cost:.1f} "
          f"build {st.build_ms:.1f} ms")
     nodes, order = c.debug_bvh_nodes()

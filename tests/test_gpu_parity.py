@@ -65,7 +65,7 @@ def test_sample_bits_bitexact(Renderer, orc, W, H):
 
 
 @pytest.mark.parametrize("W,H,passes", [(128, 128, (0, 1, 15, 1 << 20)), (1920, 1080, (0, 63, 1 << 30)),
-                                        (5, 4, (0, 7))])
+                                        (3840, 2160, (0, 1023, 1 << 30)), (5, 4, (0, 7))])
 def test_pixel_index_bitexact(Renderer, orc, W, H, passes):
     _say(f"[pixel_index] W={W} H={H}")
     sc = g.cornell(width=W, height=H)
