@@ -54,7 +54,7 @@ WORKLOADS = {
 GUIDE = {"alpha": 0.7, "warmup": 64, "max_vertex": 2, "lr": 1e-3, "batch": 1 << 18}
 
 # algorithmic bytes per unit of work
-NODE_BYTES, TRI_BYTES = 128, 48   # 4-wide node (four child boxes + references), triangle
+TRI_BYTES = 48   # triangle (three float4 corners); a 4-wide node is 64 bytes quantised, 128 in full (bvh stats)
 TRACE_RAY_BYTES = 4 + 32 + 16        # queue entry, ray (o, tmax, d), hit record
 SHADOW_RAY_BYTES = 48 + 32           # shadow ray + contribution, radiance read-modify-write
 SHADE_VERTEX_BYTES = 4 + 16 + 16 + 16 + 16 + 8 + 48 + 32 + 16   # reads + radiance write
@@ -87,7 +87,8 @@ def _short(name: str) -> str:
     name = name.replace("qpt::(anonymous namespace)::", "")
     if name.startswith("void "):
         name = name[5:]
-    return name.split("(")[0] if "(" in name else name
+    name = name.split("(")[0] if "(" in name else name
+    return name.split("<")[0]  # template instances under one name
 
 
 def kernel_durations(path: str):
@@ -673,6 +674,8 @@ def main():
     ap.add_argument("--et-city-seconds", type=float, default=4.0, help="wall time of each equal-time run on the city")
     ap.add_argument("--et-city-ref-passes", type=int, default=512)
     ap.add_argument("--no-et-city", action="store_true", help="skip the guided vs plain equal-time leg on the city")
+    ap.add_argument("--node-format", type=int, choices=(0, 1), default=0,
+                    help="device tree: 0: quantised 64-byte nodes, 1: full-precision 128-byte nodes")
     ap.add_argument("--bvh-builder", type=int, choices=(0, 1), default=0,
                     help="0: binned SAH on the host, 1: linear BVH built on the GPU")
     ap.add_argument("--single-stream", action="store_true",
@@ -724,7 +727,7 @@ def main():
     sc = scenegen.workload(WORKLOADS[args.workload][0])
     D = sc.max_depth
     _say(f"bench: scene {sc.name} tris={sc.num_triangles} {sc.width}x{sc.height} D={D}")
-    r = Renderer(sc, device=0, bvh_builder=args.bvh_builder)
+    r = Renderer(sc, device=0, bvh_builder=args.bvh_builder, node_format=args.node_format)
     bs = r.bvh_stats
     _say(f"bench: bvh nodes={bs.num_nodes} leaves={bs.num_leaves} depth={bs.max_depth} build={bs.build_ms:.0f} ms")
     # the passes go to the library as one range, which renders them in batches
@@ -766,8 +769,9 @@ def main():
             e, h = b.rays_extension - a.rays_extension, b.rays_shadow - a.rays_shadow
             dn, dt_ = b.nodes_extension - a.nodes_extension, b.tris_extension - a.tris_extension
             sn, stt = b.nodes_shadow - a.nodes_shadow, b.tris_shadow - a.tris_shadow
-            byts = {"trace": e * TRACE_RAY_BYTES + dn * NODE_BYTES + dt_ * TRI_BYTES,
-                    "shadow": h * SHADOW_RAY_BYTES + sn * NODE_BYTES + stt * TRI_BYTES,
+            nb = r.bvh_stats.node_bytes
+            byts = {"trace": e * TRACE_RAY_BYTES + dn * nb + dt_ * TRI_BYTES,
+                    "shadow": h * SHADOW_RAY_BYTES + sn * nb + stt * TRI_BYTES,
                     "shade": e * SHADE_VERTEX_BYTES + (e - (b.paths - a.paths)) * SHADE_CONTINUE_BYTES
                              + h * SHADE_NEE_BYTES}
             stream = {"trace": e * TRACE_RAY_BYTES, "shadow": h * SHADOW_RAY_BYTES, "shade": byts["shade"]}
@@ -872,7 +876,7 @@ def main():
         "rays_per_path": round((ext + sh) / paths, 3),
         "bvh": {"builder": "GPU linear BVH (Morton, collapsed to 4-wide)" if args.bvh_builder else
                 "host binned SAH (collapsed to 4-wide)", "build_ms": round(bs.build_ms, 1),
-                "nodes": bs.num_nodes, "leaves": bs.num_leaves, "depth": bs.max_depth,
+                "nodes": bs.num_nodes, "node_bytes": bs.node_bytes, "leaves": bs.num_leaves, "depth": bs.max_depth,
                 "sah_cost": round(bs.sah_cost, 2)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -98,7 +98,9 @@ typedef struct {
                                 Karras 2012), collapsed to the same 4-wide nodes on the device: a
                                 faster build of a lower-quality tree; needs a device context and
                                 the caller's scratch below */
-    uint32_t reserved;
+    uint32_t node_format;    /* device tree: 0: quantised 64-byte 4-wide nodes (child boxes as 8-bit
+                                steps of a per-axis power-of-two grid, rounded outwards: the same
+                                hits, half the node bytes); 1: full-precision 128-byte nodes */
     void *scratch;           /* builder 1: caller-owned DEVICE memory for the build's temporaries, at
                                 least qpt_bvh_scratch_size bytes, 256-byte aligned; free again when
                                 the call returns (the build synchronises the stream) */
@@ -109,7 +111,7 @@ typedef struct {
     uint32_t num_nodes;      /* inner nodes of the 4-wide tree */
     uint32_t num_leaves;
     uint32_t max_depth;      /* of the 4-wide tree's inner nodes, root = depth 0 */
-    uint32_t reserved;
+    uint32_t node_bytes;     /* bytes per node of the device tree (64 quantised, 128 full) */
     double sah_cost;         /* SAH cost with unit traversal and intersection costs */
     double build_ms;
 } qpt_bvh_stats;

@@ -381,6 +381,7 @@ struct qpt_ctx {
     Frame frame{};
     // BVH in GPU layout
     std::vector<Node> gnodes;
+    uint32_t node_format = kNodeQuant;   // of the device tree (qpt_bvh_opts.node_format)
     std::vector<Tri> gtris;
     std::vector<Material> gmats;
     std::vector<uint32_t> emit_tri_bvh;
@@ -923,7 +924,7 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
         o = align256(o + std::max<size_t>(bytes, 1));
         return at;
     };
-    L.nodes = take(c->gnodes.size() * sizeof(Node));
+    L.nodes = take(c->gnodes.size() * (c->node_format == kNodeQuant ? sizeof(QNode) : sizeof(Node)));
     L.tris = take(c->gtris.size() * sizeof(Tri));
     L.mats = take(c->gmats.size() * sizeof(Material));
     size_t ne = c->emit_input_tri.size();
@@ -1155,6 +1156,63 @@ int qpt_build_scene(qpt_ctx *c, const qpt_scene_desc *d)
     return QPT_OK;
 }
 
+// A full-precision 4-wide node -> its 64-byte quantised form: per axis the
+// smallest power-of-two step 2^e with 255 steps spanning the union of the
+// used children's boxes; each child's box rounded outwards to whole steps
+// from the union's lower corner (exact in FP64, so the quantised box holds
+// the full one). Unused slots keep an empty reference (and an inverted box).
+static QNode quantize_node(const Node &n)
+{
+    const float lo[3][4] = {{n.lox.x, n.lox.y, n.lox.z, n.lox.w}, {n.loy.x, n.loy.y, n.loy.z, n.loy.w},
+                            {n.loz.x, n.loz.y, n.loz.z, n.loz.w}};
+    const float hi[3][4] = {{n.hix.x, n.hix.y, n.hix.z, n.hix.w}, {n.hiy.x, n.hiy.y, n.hiy.z, n.hiy.w},
+                            {n.hiz.x, n.hiz.y, n.hiz.z, n.hiz.w}};
+    const int32_t ref[4] = {n.ref.x, n.ref.y, n.ref.z, n.ref.w};
+    float org[3] = {INFINITY, INFINITY, INFINITY}, top[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t used = 0;
+    for (int q = 0; q < 4; ++q) {
+        if (ref[q] == kEmptyChild) continue;
+        ++used;
+        for (int a = 0; a < 3; ++a) {
+            org[a] = std::min(org[a], lo[a][q]);
+            top[a] = std::max(top[a], hi[a][q]);
+        }
+    }
+    uint32_t ebias[3], qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        if (!used) org[a] = top[a] = 0.0f;
+        const double ext = (double)top[a] - (double)org[a];
+        int e = -126;
+        if (ext > 0.0) {
+            e = std::max(-126, (int)std::ceil(std::log2(ext / 255.0)));
+            while (e > -126 && std::ldexp(255.0, e - 1) >= ext) --e;
+            while (std::ldexp(255.0, e) < ext) ++e;
+        }
+        ebias[a] = (uint32_t)(e + 127);
+        for (int q = 0; q < 4; ++q) {
+            uint32_t l = 255, h = 0;  // unused: an inverted box
+            if (ref[q] != kEmptyChild) {
+                l = (uint32_t)std::floor(std::ldexp((double)lo[a][q] - (double)org[a], -e));
+                h = (uint32_t)std::ceil(std::ldexp((double)hi[a][q] - (double)org[a], -e));
+                l = std::min(l, 255u);
+                h = std::min(h, 255u);
+            }
+            qlo[a] |= l << (8 * q);
+            qhi[a] |= h << (8 * q);
+        }
+    }
+    QNode out;
+    uint32_t ox, oy, oz;
+    std::memcpy(&ox, &org[0], 4);
+    std::memcpy(&oy, &org[1], 4);
+    std::memcpy(&oz, &org[2], 4);
+    out.w0 = make_uint4(ox, oy, oz, ebias[0] | (ebias[1] << 8) | (ebias[2] << 16) | (used << 24));
+    out.w1 = make_uint4(qlo[0], qlo[1], qlo[2], qhi[0]);
+    out.w2 = make_uint4(qhi[1], qhi[2], (uint32_t)ref[0], (uint32_t)ref[1]);
+    out.w3 = make_uint4((uint32_t)ref[2], (uint32_t)ref[3], 0u, 0u);
+    return out;
+}
+
 // after either builder: overflow stack size, triangles in leaf order, the
 // emitters' leaf-order triangles
 static void finish_bvh(qpt_ctx *c, const std::vector<uint32_t> &order, uint32_t depth4)
@@ -1235,7 +1293,7 @@ static int build_bvh_gpu(qpt_ctx *c, uint32_t leaf, void *scratch, size_t bytes,
         stats->num_nodes = (uint32_t)c->gnodes.size();
         stats->num_leaves = leaves;
         stats->max_depth = depth4;
-        stats->reserved = 0;
+        stats->node_bytes = c->node_format == kNodeQuant ? (uint32_t)sizeof(QNode) : (uint32_t)sizeof(Node);
         stats->sah_cost = sah;
         stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
@@ -1249,7 +1307,8 @@ static int bvh_opts(qpt_ctx *c, const qpt_bvh_opts *opts, uint32_t &leaf, uint32
     leaf = opts && opts->max_leaf_size ? opts->max_leaf_size : 3;
     bins = opts && opts->sah_bins ? opts->sah_bins : 16;
     builder = opts ? opts->builder : 0;
-    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64 || builder > 1) return fail(c, QPT_E_INVALID, "bad BVH options");
+    if (leaf < 1 || leaf > 8 || bins < 4 || bins > 64 || builder > 1 || (opts && opts->node_format > 1))
+        return fail(c, QPT_E_INVALID, "bad BVH options");
     return QPT_OK;
 }
 
@@ -1270,6 +1329,7 @@ int qpt_build_bvh_noalloc(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *s
     if (int rc = bvh_opts(c, opts, leaf, bins, builder)) return rc;
     const uint32_t nt = (uint32_t)c->tri_mat.size();
     if (nt <= leaf) return fail(c, QPT_E_INVALID, "the GPU builder needs more triangles than a leaf holds");
+    c->node_format = opts ? opts->node_format : kNodeQuant;
     const size_t need = gpu_build_scratch_bytes((uint32_t)(c->pos.size() / 3), nt);
     if (need > kStaticScratch)
         return fail(c, QPT_E_INVALID, "scene too large for the allocation-free build: %zu bytes of scratch needed, "
@@ -1287,6 +1347,7 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
     auto t0 = std::chrono::steady_clock::now();
     uint32_t leaf, bins, builder;
     if (int rc = bvh_opts(c, opts, leaf, bins, builder)) return rc;
+    c->node_format = opts ? opts->node_format : kNodeQuant;
     uint32_t nt = (uint32_t)c->tri_mat.size();
     if (builder == 1 && c->device < 0) return fail(c, QPT_E_STATE, "the GPU builder needs a device context");
     if (builder == 1 && nt > leaf) {
@@ -1406,7 +1467,7 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
         stats->num_nodes = (uint32_t)c->gnodes.size();
         stats->num_leaves = leaves;
         stats->max_depth = depth4;
-        stats->reserved = 0;
+        stats->node_bytes = c->node_format == kNodeQuant ? (uint32_t)sizeof(QNode) : (uint32_t)sizeof(Node);
         stats->sah_cost = sah;
         stats->build_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
@@ -1470,7 +1531,14 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     };
     std::vector<float> pmf32(c->emit_pmf.size());
     for (size_t e = 0; e < pmf32.size(); ++e) pmf32[e] = (float)c->emit_pmf[e];
-    HIP_TRY(c, up(L.nodes, c->gnodes.data(), c->gnodes.size() * sizeof(Node)));
+    if (c->node_format == kNodeQuant) {
+        std::vector<QNode> q(c->gnodes.size());
+        for (size_t k = 0; k < q.size(); ++k) q[k] = quantize_node(c->gnodes[k]);
+        HIP_TRY(c, up(L.nodes, q.data(), q.size() * sizeof(QNode)));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));  // q is freed on return
+    } else {
+        HIP_TRY(c, up(L.nodes, c->gnodes.data(), c->gnodes.size() * sizeof(Node)));
+    }
     HIP_TRY(c, up(L.tris, c->gtris.data(), c->gtris.size() * sizeof(Tri)));
     HIP_TRY(c, up(L.mats, c->gmats.data(), c->gmats.size() * sizeof(Material)));
     HIP_TRY(c, up(L.emit_tri, c->emit_tri_bvh.data(), c->emit_tri_bvh.size() * 4));
@@ -1490,6 +1558,8 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     HIP_TRY(c, up(L.bases, c->bases.data(), kMaxDims * sizeof(HaltonBase)));
     Frame &f = c->frame;
     f.nodes = (const Node *)(w + L.nodes);
+    f.qnodes = (const QNode *)(w + L.nodes);
+    f.node_format = c->node_format;
     f.tris = (const Tri *)(w + L.tris);
     f.mats = (const Material *)(w + L.mats);
     f.num_tris = (uint32_t)c->gtris.size();

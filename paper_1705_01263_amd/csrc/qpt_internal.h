@@ -44,6 +44,23 @@ struct alignas(16) Node {
     int4 pad;
 };
 
+// The same node quantised to 64 bytes (half an L2 line, four 16-byte loads):
+// the children's boxes as 8-bit steps on a per-axis power-of-two grid from
+// the lower corner of their union, rounded outwards (each child box holds
+// its full-precision box), so traversal visits a superset of the nodes it
+// would with full boxes and finds the same closest hit.
+//   w0: lower corner xyz (FP32), biased exponents of the three grid steps
+//       (bytes 0-2: 2^(e - 127)) and the number of used slots (byte 3);
+//   w1: lo.x, lo.y, lo.z, hi.x steps, byte c = child c;
+//   w2: hi.y, hi.z steps, references of children 0 and 1;
+//   w3: references of children 2 and 3, two unused words.
+struct alignas(16) QNode {
+    uint4 w0, w1, w2, w3;
+};
+static_assert(sizeof(QNode) == 64, "quantised node is 64 bytes");
+// node formats of the device tree
+constexpr uint32_t kNodeQuant = 0, kNodeFull = 1;
+
 // Triangle in BVH order (48 bytes): v0.w = material, v1.w = input id,
 // v2.w = emitter index (or kNoHit).
 struct alignas(16) Tri {
@@ -101,7 +118,9 @@ struct Camera {
 // Everything a kernel needs, by value (device pointers into the workspace).
 struct Frame {
     // scene
-    const Node *nodes;
+    const Node *nodes;                    // node_format kNodeFull
+    const QNode *qnodes;                  // node_format kNodeQuant
+    uint32_t node_format;
     const Tri *tris;
     const Material *mats;
     uint32_t num_tris;

@@ -219,20 +219,49 @@ __device__ __forceinline__ bool tri_test(const RayPre &r, float4 v0, float4 v1, 
     return true;
 }
 
-// slab test of child c against [0, tlim]: a sort key (entry distance with
-// the child slot in the two low bits; entry distances are >= 0, so unsigned
-// order is distance order) or ~0 for a miss or an unused slot
-__device__ __forceinline__ uint32_t child_key(float lox, float loy, float loz, float hix, float hiy, float hiz,
-                                              int32_t ref, const RayPre &r, f3 oi, float tlim, uint32_t c)
+// slab test of child c against [0, tlim] from the distances to its six
+// planes: a sort key (entry distance with the child slot in the two low bits;
+// entry distances are >= 0, so unsigned order is distance order) or ~0 for a
+// miss or an unused slot
+__device__ __forceinline__ uint32_t key_from_t(float lx, float hx, float ly, float hy, float lz, float hz,
+                                               int32_t ref, float tlim, uint32_t c)
 {
-    float lx = fmaf(lox, r.inv.x, -oi.x), hx = fmaf(hix, r.inv.x, -oi.x);
-    float ly = fmaf(loy, r.inv.y, -oi.y), hy = fmaf(hiy, r.inv.y, -oi.y);
-    float lz = fmaf(loz, r.inv.z, -oi.z), hz = fmaf(hiz, r.inv.z, -oi.z);
     float tn = fmaxf(fmaxf(fminf(lx, hx), fminf(ly, hy)), fmaxf(fminf(lz, hz), 0.0f));
     float tf = fminf(fminf(fmaxf(lx, hx), fmaxf(ly, hy)), fminf(fmaxf(lz, hz), tlim));
     // the padded boxes make a relative slack of a few ulps harmless
     bool hit = ref != kEmptyChild && tn <= tf * 1.0000005f;
     return hit ? ((__float_as_uint(tn) & ~3u) | c) : ~0u;
+}
+
+__device__ __forceinline__ uint32_t child_key(float lox, float loy, float loz, float hix, float hiy, float hiz,
+                                              int32_t ref, const RayPre &r, f3 oi, float tlim, uint32_t c)
+{
+    return key_from_t(fmaf(lox, r.inv.x, -oi.x), fmaf(hix, r.inv.x, -oi.x), fmaf(loy, r.inv.y, -oi.y),
+                      fmaf(hiy, r.inv.y, -oi.y), fmaf(loz, r.inv.z, -oi.z), fmaf(hiz, r.inv.z, -oi.z), ref, tlim, c);
+}
+
+// the four children of a quantised node: plane distances as q s + b per axis,
+// with s = grid step / direction and b = (corner - origin) / direction
+__device__ __forceinline__ void qnode_keys(const QNode &n, const RayPre &r, float tlim, uint32_t k[4], int32_t ref[4])
+{
+    const float sx = __uint_as_float((n.w0.w & 0xffu) << 23) * r.inv.x;
+    const float sy = __uint_as_float(((n.w0.w >> 8) & 0xffu) << 23) * r.inv.y;
+    const float sz = __uint_as_float(((n.w0.w >> 16) & 0xffu) << 23) * r.inv.z;
+    const float bx = (__uint_as_float(n.w0.x) - r.o.x) * r.inv.x;
+    const float by = (__uint_as_float(n.w0.y) - r.o.y) * r.inv.y;
+    const float bz = (__uint_as_float(n.w0.z) - r.o.z) * r.inv.z;
+    ref[0] = (int32_t)n.w2.z;
+    ref[1] = (int32_t)n.w2.w;
+    ref[2] = (int32_t)n.w3.x;
+    ref[3] = (int32_t)n.w3.y;
+#pragma unroll
+    for (uint32_t c = 0; c < 4; ++c) {
+        const uint32_t sh = 8 * c;
+        const float lx = fmaf((float)((n.w1.x >> sh) & 0xffu), sx, bx), hx = fmaf((float)((n.w1.w >> sh) & 0xffu), sx, bx);
+        const float ly = fmaf((float)((n.w1.y >> sh) & 0xffu), sy, by), hy = fmaf((float)((n.w2.x >> sh) & 0xffu), sy, by);
+        const float lz = fmaf((float)((n.w1.z >> sh) & 0xffu), sz, bz), hz = fmaf((float)((n.w2.y >> sh) & 0xffu), sz, bz);
+        k[c] = key_from_t(lx, hx, ly, hy, lz, hz, ref[c], tlim, c);
+    }
 }
 
 __device__ __forceinline__ void cswap(uint32_t &a, uint32_t &b)
@@ -271,7 +300,7 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
 // (stride gs) sized by the host for the tree's depth (at most 3 pushes per
 // level). Children are culled against the current closest t with a closed
 // interval, so the result does not depend on the visiting order.
-template <bool ANY, bool DEPTH = false>
+template <bool ANY, bool QN, bool DEPTH = false>
 __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs)
 {
     h.t = tmax;
@@ -292,22 +321,37 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
     };
     while (true) {
         if (ref >= 0) {
-            const Node n = F.nodes[ref];
             ++h.nodes;
-            uint32_t k0 = child_key(n.lox.x, n.loy.x, n.loz.x, n.hix.x, n.hiy.x, n.hiz.x, n.ref.x, r, oi, h.t, 0);
-            uint32_t k1 = child_key(n.lox.y, n.loy.y, n.loz.y, n.hix.y, n.hiy.y, n.hiz.y, n.ref.y, r, oi, h.t, 1);
-            uint32_t k2 = child_key(n.lox.z, n.loy.z, n.loz.z, n.hix.z, n.hiy.z, n.hiz.z, n.ref.z, r, oi, h.t, 2);
-            uint32_t k3 = child_key(n.lox.w, n.loy.w, n.loz.w, n.hix.w, n.hiy.w, n.hiz.w, n.ref.w, r, oi, h.t, 3);
+            uint32_t k0, k1, k2, k3;
+            int4 nref;
+            if (QN) {
+                const QNode n = F.qnodes[ref];
+                uint32_t k[4];
+                int32_t rf[4];
+                qnode_keys(n, r, h.t, k, rf);
+                k0 = k[0];
+                k1 = k[1];
+                k2 = k[2];
+                k3 = k[3];
+                nref = make_int4(rf[0], rf[1], rf[2], rf[3]);
+            } else {
+                const Node n = F.nodes[ref];
+                k0 = child_key(n.lox.x, n.loy.x, n.loz.x, n.hix.x, n.hiy.x, n.hiz.x, n.ref.x, r, oi, h.t, 0);
+                k1 = child_key(n.lox.y, n.loy.y, n.loz.y, n.hix.y, n.hiy.y, n.hiz.y, n.ref.y, r, oi, h.t, 1);
+                k2 = child_key(n.lox.z, n.loy.z, n.loz.z, n.hix.z, n.hiy.z, n.hiz.z, n.ref.z, r, oi, h.t, 2);
+                k3 = child_key(n.lox.w, n.loy.w, n.loz.w, n.hix.w, n.hiy.w, n.hiz.w, n.ref.w, r, oi, h.t, 3);
+                nref = n.ref;
+            }
             cswap(k0, k1);
             cswap(k2, k3);
             cswap(k0, k2);
             cswap(k1, k3);
             cswap(k1, k2);
             if (k0 != ~0u) {
-                if (k3 != ~0u) push(child_ref(n.ref, k3 & 3u));
-                if (k2 != ~0u) push(child_ref(n.ref, k2 & 3u));
-                if (k1 != ~0u) push(child_ref(n.ref, k1 & 3u));
-                ref = child_ref(n.ref, k0 & 3u);
+                if (k3 != ~0u) push(child_ref(nref, k3 & 3u));
+                if (k2 != ~0u) push(child_ref(nref, k2 & 3u));
+                if (k1 != ~0u) push(child_ref(nref, k1 & 3u));
+                ref = child_ref(nref, k0 & 3u);
                 continue;
             }
         } else {
@@ -883,6 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
 // closest hit for the extension rays queued at depth v; the grid holds twice
 // what is resident on the chip (a block that finishes early makes room for
 // one that has not started) and strides over the queue
+template <bool QN>
 __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v)
 {
     __shared__ int stk[kShortStack * kBlock];
@@ -897,7 +942,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v
         float4 o = P.ray_o[slot], d = P.ray_d[slot];
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
-        traverse<false>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+        traverse<false, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
         P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
         nodes += h.nodes;
         tests += h.tests;
@@ -907,6 +952,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v
 }
 
 // occlusion test of the shadow rays queued at depth v; add unoccluded contributions
+template <bool QN>
 __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
 {
     __shared__ int stk[kShortStack * kBlock];
@@ -919,7 +965,7 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
         float4 o = P.sh_o[i], d = P.sh_d[i];
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
-        bool occluded = traverse<true>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+        bool occluded = traverse<true, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
         nodes += h.nodes;
         tests += h.tests;
         if (!occluded) {
@@ -1284,7 +1330,9 @@ __global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, Pool P, const f
         const float *ry = rays + 8 * (size_t)q;
         RayPre r = prepare(mk(ry[0], ry[1], ry[2]), mk(ry[4], ry[5], ry[6]));
         HitRec h;
-        bool hit = traverse<ANY, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
+        bool hit = F.node_format == kNodeQuant
+                       ? traverse<ANY, true, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads)
+                       : traverse<ANY, false, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
         if (depth) depth[q] = h.depth;
         if (ANY) {
             tri[q] = hit ? 1u : 0u;
@@ -1355,10 +1403,16 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
     uint32_t g = blocks_for(n, 8192);
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
-        timed(K_TRACE, [&] { hipLaunchKernelGGL(k_trace, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
+        timed(K_TRACE, [&] {
+            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+            else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+        });
         if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex) timed(K_GUIDE_EVAL, [&] { (void)launch_guide_eval(F, P, v, gt, s); });  // errors surface below
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
-        timed(K_SHADOW, [&] { hipLaunchKernelGGL(k_shadow, dim3(gt), dim3(kBlock), 0, s, F, P, v); });
+        timed(K_SHADOW, [&] {
+            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+            else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+        });
     }
     return hipGetLastError();
 }

@@ -38,12 +38,12 @@ class qpt_scene_desc(C.Structure):
 
 class qpt_bvh_opts(C.Structure):
     _fields_ = [("max_leaf_size", C.c_uint32), ("sah_bins", C.c_uint32), ("builder", C.c_uint32),
-                ("reserved", C.c_uint32), ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
+                ("node_format", C.c_uint32), ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
 
 
 class qpt_bvh_stats(C.Structure):
     _fields_ = [("num_nodes", C.c_uint32), ("num_leaves", C.c_uint32), ("max_depth", C.c_uint32),
-                ("reserved", C.c_uint32), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
+                ("node_bytes", C.c_uint32), ("sah_cost", C.c_double), ("build_ms", C.c_double)]
 
 
 class qpt_render_opts(C.Structure):
@@ -219,11 +219,12 @@ class Context:
         self.W, self.H = sc.width, sc.height
 
     def build_bvh(self, max_leaf_size: int = 0, sah_bins: int = 0, builder: int = 0, scratch=None,
-                  scratch_bytes: int = 0) -> qpt_bvh_stats:
+                  scratch_bytes: int = 0, node_format: int = 0) -> qpt_bvh_stats:
         """builder 0: binned SAH on the host; 1: linear BVH on the GPU, its temporaries in the
         caller's device memory `scratch` (a pointer, at least bvh_scratch_size() bytes). Zero
-        sizes take the library's defaults (leaves of up to 3 triangles, 16 bins)."""
-        o = qpt_bvh_opts(max_leaf_size, sah_bins, builder, 0, scratch, scratch_bytes)
+        sizes take the library's defaults (leaves of up to 3 triangles, 16 bins). node_format
+        0: quantised 64-byte nodes on the device, 1: full-precision 128-byte nodes."""
+        o = qpt_bvh_opts(max_leaf_size, sah_bins, builder, node_format, scratch, scratch_bytes)
         st = qpt_bvh_stats()
         self.check(self.L.qpt_build_bvh(self.h, C.byref(o), C.byref(st)), "qpt_build_bvh")
         return st
@@ -430,7 +431,8 @@ class Context:
 class Renderer:
     """Scene + BVH + a torch-owned workspace on one GPU; renders 1-spp passes."""
 
-    def __init__(self, sc, device: int = 0, pool_paths: int = 0, stream=None, bvh_builder: int = 0):
+    def __init__(self, sc, device: int = 0, pool_paths: int = 0, stream=None, bvh_builder: int = 0,
+                 node_format: int = 0):
         import torch
 
         self.torch = torch
@@ -446,10 +448,11 @@ class Renderer:
         if bvh_builder == 1:
             nb = self.ctx.bvh_scratch_size()
             tmp = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
-            self.bvh_stats = self.ctx.build_bvh(builder=1, scratch=(tmp.data_ptr() + 255) & ~255, scratch_bytes=nb)
+            self.bvh_stats = self.ctx.build_bvh(builder=1, scratch=(tmp.data_ptr() + 255) & ~255, scratch_bytes=nb,
+                                                node_format=node_format)
             del tmp
         else:
-            self.bvh_stats = self.ctx.build_bvh(builder=bvh_builder)
+            self.bvh_stats = self.ctx.build_bvh(builder=bvh_builder, node_format=node_format)
         self.pool_paths = pool_paths
         nbytes = self.ctx.workspace_size(pool_paths)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
