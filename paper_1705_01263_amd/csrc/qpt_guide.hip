@@ -3,14 +3,19 @@
 // direction to an 8-lobe von Mises-Fisher mixture; trained online from the
 // renderer's own radiance samples with Adam on FP32 master weights.
 //
-// MFMA mapping (v_mfma_f32_32x32x8bf16_1k, D = A x B + C, 32x32x8):
-//   A operand = weights:     lane l holds W[k = 8s + 4(l/32) + e][o = 32t + l%32], e = 0..3
-//   B operand = activations: lane l holds act[row = l%32][k = 8s + 4(l/32) + e]
-//   D:                       lane l, register v holds Z[o = 32t + 8(v/4) + 4(l/32) + v%4][row = l%32]
-// so registers 4s'..4s'+3 of the output tile s'/4 are exactly the B operand of
-// step s' of the next layer: layers chain in registers. Each row (a path
-// vertex or a training sample) is handled by the lane pair (l, l + 32); a wave
-// works on 32 rows at a time.
+// MFMA mapping (gfx950's v_mfma_f32_32x32x16_bf16, D = A x B + C, 32x32x16).
+// Operands are kept as 4-element fragments of 8-wide k-blocks s:
+//   A fragment = weights:     lane l holds W[k = 8s + 4(l/32) + e][o = 32t + l%32], e = 0..3
+//   B fragment = activations: lane l holds act[row = l%32][k = 8s + 4(l/32) + e]
+//   D:                        lane l, register v holds Z[o = 32t + 8(v/4) + 4(l/32) + v%4][row = l%32]
+// so registers 4s'..4s'+3 of the output tile s'/4 are exactly the B fragment
+// of block s' of the next layer: layers chain in registers. One 16-deep MFMA
+// takes fragments 2s and 2s + 1 of both operands as its 8 elements per lane:
+// the hardware pairs element e of A and B lanes for one reduction index, and
+// both operands map (lane half, e) to the same k = 16s + 8(e/4) + 4(l/32) +
+// e%4, so the product is the sum over the 16 k of the block in another order.
+// Each row (a path vertex or a training sample) is handled by the lane pair
+// (l, l + 32); a wave works on 32 rows at a time.
 #include <hip/hip_runtime.h>
 
 #include "qpt_guide_dev.h"
@@ -20,6 +25,8 @@ namespace qpt {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef short v2s __attribute__((ext_vector_type(2)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kKS[4] = {4, 8, 8, 8};          // k-steps of 8 per layer
@@ -58,9 +65,17 @@ __device__ __forceinline__ v4s as_v4s(uint2 u)
     return r;
 }
 
-__device__ __forceinline__ v16f mfma(v4s a, v4s b, v16f c)
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v8bf cat8(v4s lo, v4s hi)
 {
-    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_bit_cast(v8bf, (v8s){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+}
+
+// D += A B over a 16-deep block given as two 8-deep fragments of each operand
+__device__ __forceinline__ v16f mfma2(v4s a0, v4s a1, v4s b0, v4s b1, v16f c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(cat8(a0, a1), cat8(b0, b1), c, 0, 0, 0);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -83,7 +98,10 @@ __device__ __forceinline__ void layer_fwd(const uint2 *sfrag, const float *sbias
             c[4 * q + 3] = b.w;
         }
 #pragma unroll
-        for (int s = 0; s < kKS[L]; ++s) c = mfma(as_v4s(sfrag[(kFB[L] + t * kKS[L] + s) * 64 + lane]), in[s], c);
+        for (int s = 0; s < kKS[L]; s += 2) {
+            const uint2 *f = sfrag + (kFB[L] + t * kKS[L] + s) * 64 + lane;
+            c = mfma2(as_v4s(f[0]), as_v4s(f[64]), in[s], in[s + 1], c);
+        }
         acc[t] = c;
     }
 }
@@ -239,9 +257,10 @@ constexpr int kStageRow = 132;   // BF16 per staged feature: 128 rows + 4 (bank-
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c)
+// 16 x 16 x 32: the same pairing of two 4-element fragments per operand
+__device__ __forceinline__ v4f mfma16x2(v4s a0, v4s a1, v4s b0, v4s b1, v4f c)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(cat8(a0, a1), cat8(b0, b1), c, 0, 0, 0);
 }
 
 __device__ __forceinline__ v4s lds_b64(const uint16_t *p) { return __builtin_bit_cast(v4s, *(const uint2 *)p); }
@@ -290,7 +309,8 @@ __device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const u
         const uint16_t *aa = sA + (32 * tk + row) * kStageRow + 4 * half;
         v16f c = acc.w[L];
 #pragma unroll
-        for (int s = 0; s < kRowsPerIter / 8; ++s) c = mfma(lds_b64(za + 8 * s), lds_b64(aa + 8 * s), c);
+        for (int s = 0; s < kRowsPerIter / 8; s += 2)
+            c = mfma2(lds_b64(za + 8 * s), lds_b64(za + 8 * s + 8), lds_b64(aa + 8 * s), lds_b64(aa + 8 * s + 8), c);
         acc.w[L] = c;
     }
     if (wv == (uint32_t)L) {
@@ -301,7 +321,7 @@ __device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const u
             const uint16_t *za = sZ + (16 * ot + (lane & 15)) * kStageRow + 4 * (lane >> 4);
             v4f c = acc.b[ot];
 #pragma unroll
-            for (int s = 0; s < kRowsPerIter / 16; ++s) c = mfma16(lds_b64(za + 16 * s), ones, c);
+            for (int s = 0; s < kRowsPerIter / 16; s += 2) c = mfma16x2(lds_b64(za + 16 * s), lds_b64(za + 16 * s + 16), ones, ones, c);
             acc.b[ot] = c;
         }
     }
@@ -312,7 +332,10 @@ __device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const u
         for (int tkk = 0; tkk < 2; ++tkk) {
             v16f c = {};
 #pragma unroll
-            for (int s = 0; s < 8; ++s) c = mfma(as_v4s(sfragT[(kGB[L] + tkk * 8 + s) * 64 + lane]), zf[s], c);
+            for (int s = 0; s < 8; s += 2) {
+                const uint2 *f = sfragT + (kGB[L] + tkk * 8 + s) * 64 + lane;
+                c = mfma2(as_v4s(f[0]), as_v4s(f[64]), zf[s], zf[s + 1], c);
+            }
 #pragma unroll
             for (int v = 0; v < 16; ++v) c[v] = ((mask_prev >> (16 * tkk + v)) & 1u) ? c[v] : 0.0f;
             dz_prev[tkk] = c;
@@ -363,18 +386,33 @@ __device__ __forceinline__ void load_weights(const uint2 *frag, const float *bia
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = bias[i];
 }
 
+// ReLU and BF16 operands without the mask (inference): round to BF16 first,
+// then a 16-bit signed max with 0 per half word (a BF16 value is negative
+// exactly when its sign bit is set, and rounding keeps the sign), the same
+// bits as rounding max(z, 0)
+__device__ __forceinline__ void relu_pack_infer(const v16f *acc, v4s *out)
+{
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int t = s / 4, b = 4 * (s % 4);
+        const uint2 u = __builtin_bit_cast(uint2, pack4(acc[t][b], acc[t][b + 1], acc[t][b + 2], acc[t][b + 3]));
+        const v2s lo = __builtin_elementwise_max(__builtin_bit_cast(v2s, u.x), (v2s){0, 0});
+        const v2s hi = __builtin_elementwise_max(__builtin_bit_cast(v2s, u.y), (v2s){0, 0});
+        out[s] = __builtin_bit_cast(v4s, make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)));
+    }
+}
+
 // inference forward: only the running B operands, no stored activations
 __device__ __forceinline__ void mlp_infer(const uint2 *sfrag, const float *sbias, const v4s *a0, v16f *out)
 {
     v16f acc[2];
     v4s cur[8];
-    uint32_t m;
     layer_fwd<0>(sfrag, sbias, a0, acc);
-    relu_pack(acc, cur, m);
+    relu_pack_infer(acc, cur);
     layer_fwd<1>(sfrag, sbias, cur, acc);
-    relu_pack(acc, cur, m);
+    relu_pack_infer(acc, cur);
     layer_fwd<2>(sfrag, sbias, cur, acc);
-    relu_pack(acc, cur, m);
+    relu_pack_infer(acc, cur);
     layer_fwd<3>(sfrag, sbias, cur, out);
 }
 
