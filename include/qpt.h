@@ -140,6 +140,11 @@ typedef struct {
                                 1: Gaussian of sigma 1/2 pixel (3 sigma spans 3 x 3 pixels) around the
                                 pixel centre, untruncated, by filter importance sampling (Box-Muller of
                                 the film sample); the sample still counts for its own pixel */
+    uint32_t tail_depth;     /* the wavefront's tail (Sec. 3.1.3): 0: one launch per kernel and depth
+                                to the end; k in 1..max_depth: from depth k on, one launch (a
+                                megakernel) takes every path still alive to its end, vertex after
+                                vertex in one thread, with the same per-vertex code (the same image
+                                bit for bit). Ignored while the guide samples or records. */
 } qpt_render_opts;
 
 typedef struct {
@@ -163,7 +168,8 @@ enum {
     QPT_K_ACCUMULATE = 5, /* FP64 framebuffer and counts */
     QPT_K_GUIDE_EVAL = 6, /* the network's mixture for every vertex (guiding on) */
     QPT_K_GUIDE_TRAIN = 7,/* record finalisation, batch forward/backward, Adam */
-    QPT_K_KINDS = 8
+    QPT_K_TAIL = 8,       /* the batch's remaining paths in one launch (render option tail_depth) */
+    QPT_K_KINDS = 9
 };
 
 typedef struct {

@@ -1691,9 +1691,9 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     if (!c || !o) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
     if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1 ||
-        o->env_sampling > 2 || o->filter > 1)
-        return fail(c, QPT_E_INVALID,
-                    "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, env_sampling 0..2, filter 0..1)");
+        o->env_sampling > 2 || o->filter > 1 || o->tail_depth > o->max_depth)
+        return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, "
+                                      "env_sampling 0..2, filter 0..1, tail_depth 0..max_depth)");
     if (o->env_sampling && c->ew && !c->ep_m)
         return fail(c, QPT_E_INVALID, "environment pyramid needs a 2:1 map of power-of-two size");
     if (!num_passes) return QPT_OK;
@@ -1712,6 +1712,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.light_tree = o->light_tree;
     f.env_pyramid = c->ew ? o->env_sampling : 0;
     f.gauss_filter = o->filter;
+    f.tail_depth = o->tail_depth;
     f.abort_word = c->abort_dev;
     if (c->abort_host && __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST))
         return fail(c, QPT_E_ABORTED, "aborted: qpt_readback reports the progress and clears the request");

@@ -164,6 +164,7 @@ struct Frame {
     uint32_t light_tree;                  // select triangle lights through the light tree
     uint32_t env_pyramid;                 // 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels
     uint32_t gauss_filter;                // film samples from the Gaussian pixel filter instead of the box
+    uint32_t tail_depth;                  // 0, or the depth from which one launch finishes every path
     const uint32_t *abort_word;           // host-mapped: non-zero once the caller asked to stop
 };
 
@@ -193,7 +194,7 @@ struct Pool {
 
 // kernel kinds timed by the optional profiler
 enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMULATE, K_GUIDE_EVAL, K_GUIDE_TRAIN,
-                  K_KINDS };
+                  K_TAIL, K_KINDS };
 
 // brackets every kernel launch of a batch with stream events when set
 struct Profiler {

@@ -991,6 +991,259 @@ __device__ __forceinline__ uint32_t rec_hash(uint64_t idx, uint32_t v)
     return (uint32_t)((z ^ (z >> 31)) >> 32);
 }
 
+// what shading one path vertex produces besides the slot's own state: a
+// shadow ray with its pending contribution, whether the path continues, and
+// a training record
+struct ShadeOut {
+    bool alive, shadow, record;
+    float4 sh_o, sh_d, sh_c;
+    float4 rec[5];
+};
+
+// emission with MIS, next-event estimation, BSDF (or guide) sampling and
+// roulette at vertex v of the path in `slot` (its hit already traced): updates
+// the slot's ray, throughput and radiance (the NEE contribution stays pending
+// in o.sh_c until its shadow ray is traced)
+__device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32_t v, uint32_t slot, ShadeOut &o)
+{
+    const uint32_t base_dim = 2 + 8 * (v - 1);
+    o.alive = o.shadow = o.record = false;
+    float4 hv = P.hit[slot];
+    const float4 d4 = P.ray_d[slot];
+    f3 d = xyz(d4);
+    float4 T4 = P.thr[slot];
+    f3 T = xyz(T4);
+    float prev_pdf = T4.w;
+    f3 L = xyz(P.rad[slot]);
+    uint32_t tri = fbits(hv.y);
+    if (tri == kNoHit) {
+        if (F.env_w && (v == 1 || F.mode != 2)) {
+            uint32_t er, ec;
+            env_texel_of(F, d, er, ec);
+            const float4 e = F.env_texel[(size_t)er * F.env_w + ec];
+            float pe = e.w;
+            if (v > 1 && F.mode == 0 && F.env_pyramid) {
+                // the pyramid's density of this texel from the previous vertex
+                const int bin = F.env_pyramid == 2 ? (int)ep_bin(prev_normal(F, d4.w)) : -1;
+                uint64_t ru, su, rv, sv;
+                ep_descend(F, bin, 0u, 0u, true, er, ec, ru, su, rv, sv);
+                pe = ep_pdf(F, er, ru, rv);
+            }
+            float w = (v > 1 && F.mode == 0) ? mis2(prev_pdf, F.p_env * pe) : 1.0f;
+            L = L + T * xyz(e) * w;
+        }
+    } else {
+        const Tri tr = F.tris[tri];
+        const Material m = F.mats[fbits(tr.v0.w)];
+        f3 a = xyz(tr.v0), b = xyz(tr.v1), c = xyz(tr.v2);
+        f3 x = a + ((b - a) * hv.z + (c - a) * hv.w);
+        float area2;
+        f3 ng = unit_normal(a, b, c, area2);
+        float dn = dot(d, ng);
+        bool front = dn < 0.0f;
+        uint32_t em = fbits(tr.v2.w);
+        if (front && em != kNoHit && !(v > 1 && F.mode == 2)) {
+            f3 Le = emission_at(m, x);
+            float w = 1.0f;
+            if (v > 1 && F.mode == 0) {
+                float pe;
+                if (F.light_tree) {
+                    // the tree's probability of this emitter from the previous
+                    // vertex: its ray origin and oriented normal, as its NEE saw them
+                    const uint64_t z = lt_size_of(F, em, xyz(P.ray_o[slot]), prev_normal(F, d4.w));
+                    pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
+                } else {
+                    pe = F.emit_pmf[em];
+                }
+                float pl = pe / (0.5f * area2) * hv.x * hv.x / (-dn);
+                w = mis2(prev_pdf, pl);
+            }
+            L = L + T * Le * w;
+        }
+        bool scatters = maxc(xyz(m.albedo_rough)) > 0.0f || (fbits(m.emission_flags.w) & 1u);
+        if (v < F.max_depth && scatters) {
+            f3 nn = front ? ng : ng * -1.0f;
+            f3 wo = d * -1.0f;
+            f3 xo = offset_ray(x, nn);
+            uint64_t idx = P.idx[slot];
+            // learned proposal: this vertex's mixture (alpha = 0 leaves plain BSDF sampling)
+            const bool guided = F.guide.alpha_thr != 0u && v <= F.guide.max_vertex;
+            guide::MixRef mix{nullptr, 0.0f};
+            if (guided) mix = guide::mix_ref(F.guide.mix + (size_t)slot * guide::kMixU4);
+            const float alpha = F.guide.alpha;
+            // next-event estimation
+            if (F.mode != 1 && (F.num_emit || F.env_w)) {
+                uint32_t s0 = sample_bits(F, idx, base_dim + 0, F.scramble);
+                bool use_env = F.env_w != 0;
+                uint64_t rr = s0, R = 1ull << 32;
+                if (F.env_w && F.num_emit) {
+                    use_env = s0 < 0x80000000u;
+                    rr = s0 - 0x80000000u;
+                    R = 1ull << 31;
+                }
+                f3 wi, Le;
+                float pl = 0.0f, tmax = INFINITY;
+                bool ok = false;
+                if (use_env) {
+                    uint32_t s1 = sample_bits(F, idx, base_dim + 1, F.scramble);
+                    uint32_t s2 = sample_bits(F, idx, base_dim + 2, F.scramble);
+                    uint32_t row, col;
+                    float fx, fy, pt = 0.0f;
+                    if (F.env_pyramid) {
+                        // pyramid: slot 2 narrows the columns, slot 1 the rows
+                        const int bin = F.env_pyramid == 2 ? (int)ep_bin(nn) : -1;
+                        uint64_t ru, su, rv, sv;
+                        ep_descend(F, bin, s2, s1, false, row, col, ru, su, rv, sv);
+                        fx = (float)su / (float)ru;
+                        fy = (float)sv / (float)rv;
+                        pt = ep_pdf(F, row, ru, rv);
+                    } else {
+                        row = upper_search(F.env_row, F.env_h, s1);
+                        const uint32_t *cq = F.env_col + (size_t)row * F.env_w;
+                        col = upper_search(cq, F.env_w, s2);
+                        uint64_t r0 = F.env_row[row], r1 = row + 1 < F.env_h ? F.env_row[row + 1] : (1ull << 32);
+                        uint64_t c0 = cq[col], c1 = col + 1 < F.env_w ? cq[col + 1] : (1ull << 32);
+                        fy = (float)(s1 - r0) / (float)(r1 - r0);
+                        fx = (float)(s2 - c0) / (float)(c1 - c0);
+                    }
+                    float ct = F.env_cos[row], cb = F.env_cos[row + 1];
+                    float cth = ct + fy * (cb - ct);
+                    float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
+                    float sp, cp;
+                    sincosf(2.0f * kPi * ((float)col + fx) / (float)F.env_w, &sp, &cp);
+                    wi = mk(sth * sp, cth, -sth * cp);
+                    float4 e = F.env_texel[(size_t)row * F.env_w + col];
+                    Le = xyz(e);
+                    pl = F.p_env * (F.env_pyramid ? pt : e.w);
+                    ok = pl > 0.0f;
+                } else {
+                    uint32_t s7 = sample_bits(F, idx, base_dim + 7, F.scramble);
+                    uint32_t e;
+                    float pe;
+                    if (F.light_tree) {
+                        // 63-bit sample: what slot 0 leaves after the environment
+                        // choice (its top 31 bits without an environment), then slot 7
+                        const uint64_t hi = F.env_w ? rr : (uint64_t)(s0 >> 1);
+                        uint64_t z;
+                        e = lt_sample(F, (hi << 32) | s7, xo, nn, z);
+                        pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
+                    } else {
+                        // rr < R <= 2^32 and num_emit < 2^27: the product fits 64 bits
+                        uint32_t col =
+                            (uint32_t)((rr * (uint64_t)F.num_emit) >> (R == (1ull << 31) ? 31 : 32));
+                        e = (unsigned long long)s7 < F.alias_thr[col] ? col : F.alias_idx[col];
+                        pe = F.emit_pmf[e];
+                    }
+                    const Tri lt = F.tris[F.emit_tri[e]];
+                    float q1 = u24(sample_bits(F, idx, base_dim + 1, F.scramble));
+                    float q2 = u24(sample_bits(F, idx, base_dim + 2, F.scramble));
+                    float su = sqrtf(q1);
+                    float b0 = 1.0f - su, bb1 = q2 * su, bb2 = su * (1.0f - q2);
+                    f3 la = xyz(lt.v0), lb = xyz(lt.v1), lc = xyz(lt.v2);
+                    f3 y = la * b0 + lb * bb1 + lc * bb2;
+                    f3 nl = cross(lb - la, lc - la);
+                    float la2 = length(nl);
+                    nl = nl * (1.0f / la2);
+                    f3 dv = y - xo;
+                    float d2 = dot(dv, dv);
+                    float dist = sqrtf(d2);
+                    wi = dv * (1.0f / dist);
+                    float cl = -dot(nl, wi);
+                    if (cl > 0.0f) {
+                        Le = emission_at(F.mats[fbits(lt.v0.w)], y);
+                        pl = pe / (0.5f * la2) * d2 / cl;
+                        ok = pl > 0.0f;
+                        tmax = dist * (1.0f - 1e-4f);
+                    }
+                }
+                if (ok) {
+                    float ci = dot(nn, wi);
+                    if (ci > 0.0f) {
+                        f3 fb;
+                        float pb;
+                        bsdf_eval(m, nn, wo, wi, fb, pb);
+                        if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
+                        float w = F.mode == 2 ? 1.0f : mis2(pl, pb);
+                        f3 contrib = T * fb * Le * (ci * w / pl);
+                        if (maxc(contrib) > 0.0f) {
+                            o.shadow = true;
+                            o.sh_o = f4(xo, tmax);
+                            o.sh_d = f4(wi, ubits(slot));
+                            o.sh_c = f4(contrib, 0.0f);
+                        }
+                    }
+                }
+            }
+            // continue the path: slot 3 picks guide or BSDF (guide iff the 32-bit
+            // sample < alpha 2^32) and, rescaled to [0, 2^32), the lobe; slots 4-5
+            // the direction. The density is the one-sample mixture
+            // alpha q + (1 - alpha) p_bsdf, so the estimator stays unbiased.
+            uint32_t s3 = sample_bits(F, idx, base_dim + 3, F.scramble);
+            bool use_guide = guided && s3 < F.guide.alpha_thr;
+            uint32_t r3 = s3;
+            if (guided) {
+                uint64_t lo = use_guide ? 0ull : F.guide.alpha_thr;
+                uint64_t range = use_guide ? F.guide.alpha_thr : (1ull << 32) - F.guide.alpha_thr;
+                r3 = (uint32_t)((((uint64_t)s3 - lo) << 32) / range);
+            }
+            float u3 = u24(r3);
+            float u4 = u24(sample_bits(F, idx, base_dim + 4, F.scramble));
+            float u5 = u24(sample_bits(F, idx, base_dim + 5, F.scramble));
+            f3 wi;
+            bool ok;
+            if (use_guide) {
+                guide::V3 g = guide::mixture_sample(mix, u3, u4, u5);
+                wi = mk(g.x, g.y, g.z);
+                ok = dot(nn, wi) > 0.0f;
+            } else {
+                ok = bsdf_sample(m, nn, wo, u3, u4, u5, wi);
+            }
+            if (ok) {
+                f3 fb;
+                float pb;
+                bsdf_eval(m, nn, wo, wi, fb, pb);
+                if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
+                if (pb > 0.0f) {
+                    f3 Tb = T;  // throughput before this vertex's scattering
+                    T = T * fb * (dot(nn, wi) / pb);
+                    if (maxc(T) > 0.0f) {
+                        o.alive = true;
+                        if (F.rr && v >= 3) {
+                            float qq = fminf(0.95f, maxc(T));
+                            qq = ceilf(qq * 16777216.0f) * 0x1p-24f;
+                            float u6 = u24(sample_bits(F, idx, base_dim + 6, F.scramble));
+                            if (u6 < qq) {
+                                T = T * (1.0f / qq);
+                                Tb = Tb * (1.0f / qq);
+                            } else {
+                                o.alive = false;
+                            }
+                        }
+                        if (o.alive) {
+                            P.ray_o[slot] = f4(xo, INFINITY);
+                            P.ray_d[slot] = f4(wi, ubits(tri | (front ? 0u : 0x80000000u)));
+                            P.thr[slot] = f4(T, pb);
+                            if (F.guide.record && v <= F.guide.max_vertex &&
+                                (F.guide.rec_thr == 0xffffffffu || rec_hash(idx, v) < F.guide.rec_thr)) {
+                                // training record: (final - now - this vertex's NEE) /
+                                // T_before is this sample's estimate f cos L_i / p of
+                                // the scattering integral (roulette folded into T_before)
+                                o.record = true;
+                                o.rec[0] = f4(x, pb);
+                                o.rec[1] = f4(wo, 0.0f);
+                                o.rec[2] = f4(wi, ubits(slot));
+                                o.rec[3] = f4(L, ubits(v));
+                                o.rec[4] = f4(Tb, 0.0f);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    P.rad[slot] = f4(L, 0.0f);
+}
+
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
 // (four blocks per CU: at most 128 VGPRs, four waves per SIMD, no spills)
 __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v)
@@ -998,275 +1251,107 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];
     uint32_t *qn = P.q_ext[(v + 1) & 1];
-    const uint32_t base_dim = 2 + 8 * (v - 1);
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t i = base + threadIdx.x;
         bool active = i < n;
-        bool alive = false, shadow = false, record = false;
         uint32_t slot = 0;
-        float4 sh_o = {}, sh_d = {}, sh_c = {};
-        float4 rec0 = {}, rec1 = {}, rec2 = {}, rec3 = {}, rec4 = {};
+        // zero-initialised: the outputs stay in registers (no spills at 128 VGPRs)
+        ShadeOut o;
+        o.alive = o.shadow = o.record = false;
+        o.sh_o = o.sh_d = o.sh_c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (active) {
             slot = q[i];
-            float4 hv = P.hit[slot];
-            const float4 d4 = P.ray_d[slot];
-            f3 d = xyz(d4);
-            float4 T4 = P.thr[slot];
-            f3 T = xyz(T4);
-            float prev_pdf = T4.w;
-            f3 L = xyz(P.rad[slot]);
-            uint32_t tri = fbits(hv.y);
-            if (tri == kNoHit) {
-                if (F.env_w && (v == 1 || F.mode != 2)) {
-                    uint32_t er, ec;
-                    env_texel_of(F, d, er, ec);
-                    const float4 e = F.env_texel[(size_t)er * F.env_w + ec];
-                    float pe = e.w;
-                    if (v > 1 && F.mode == 0 && F.env_pyramid) {
-                        // the pyramid's density of this texel from the previous vertex
-                        const int bin = F.env_pyramid == 2 ? (int)ep_bin(prev_normal(F, d4.w)) : -1;
-                        uint64_t ru, su, rv, sv;
-                        ep_descend(F, bin, 0u, 0u, true, er, ec, ru, su, rv, sv);
-                        pe = ep_pdf(F, er, ru, rv);
-                    }
-                    float w = (v > 1 && F.mode == 0) ? mis2(prev_pdf, F.p_env * pe) : 1.0f;
-                    L = L + T * xyz(e) * w;
-                }
-            } else {
-                const Tri tr = F.tris[tri];
-                const Material m = F.mats[fbits(tr.v0.w)];
-                f3 a = xyz(tr.v0), b = xyz(tr.v1), c = xyz(tr.v2);
-                f3 x = a + ((b - a) * hv.z + (c - a) * hv.w);
-                float area2;
-                f3 ng = unit_normal(a, b, c, area2);
-                float dn = dot(d, ng);
-                bool front = dn < 0.0f;
-                uint32_t em = fbits(tr.v2.w);
-                if (front && em != kNoHit && !(v > 1 && F.mode == 2)) {
-                    f3 Le = emission_at(m, x);
-                    float w = 1.0f;
-                    if (v > 1 && F.mode == 0) {
-                        float pe;
-                        if (F.light_tree) {
-                            // the tree's probability of this emitter from the previous
-                            // vertex: its ray origin and oriented normal, as its NEE saw them
-                            const uint64_t z = lt_size_of(F, em, xyz(P.ray_o[slot]), prev_normal(F, d4.w));
-                            pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
-                        } else {
-                            pe = F.emit_pmf[em];
-                        }
-                        float pl = pe / (0.5f * area2) * hv.x * hv.x / (-dn);
-                        w = mis2(prev_pdf, pl);
-                    }
-                    L = L + T * Le * w;
-                }
-                bool scatters = maxc(xyz(m.albedo_rough)) > 0.0f || (fbits(m.emission_flags.w) & 1u);
-                if (v < F.max_depth && scatters) {
-                    f3 nn = front ? ng : ng * -1.0f;
-                    f3 wo = d * -1.0f;
-                    f3 xo = offset_ray(x, nn);
-                    uint64_t idx = P.idx[slot];
-                    // learned proposal: this vertex's mixture (alpha = 0 leaves plain BSDF sampling)
-                    const bool guided = F.guide.alpha_thr != 0u && v <= F.guide.max_vertex;
-                    guide::MixRef mix{nullptr, 0.0f};
-                    if (guided) mix = guide::mix_ref(F.guide.mix + (size_t)slot * guide::kMixU4);
-                    const float alpha = F.guide.alpha;
-                    // next-event estimation
-                    if (F.mode != 1 && (F.num_emit || F.env_w)) {
-                        uint32_t s0 = sample_bits(F, idx, base_dim + 0, F.scramble);
-                        bool use_env = F.env_w != 0;
-                        uint64_t rr = s0, R = 1ull << 32;
-                        if (F.env_w && F.num_emit) {
-                            use_env = s0 < 0x80000000u;
-                            rr = s0 - 0x80000000u;
-                            R = 1ull << 31;
-                        }
-                        f3 wi, Le;
-                        float pl = 0.0f, tmax = INFINITY;
-                        bool ok = false;
-                        if (use_env) {
-                            uint32_t s1 = sample_bits(F, idx, base_dim + 1, F.scramble);
-                            uint32_t s2 = sample_bits(F, idx, base_dim + 2, F.scramble);
-                            uint32_t row, col;
-                            float fx, fy, pt = 0.0f;
-                            if (F.env_pyramid) {
-                                // pyramid: slot 2 narrows the columns, slot 1 the rows
-                                const int bin = F.env_pyramid == 2 ? (int)ep_bin(nn) : -1;
-                                uint64_t ru, su, rv, sv;
-                                ep_descend(F, bin, s2, s1, false, row, col, ru, su, rv, sv);
-                                fx = (float)su / (float)ru;
-                                fy = (float)sv / (float)rv;
-                                pt = ep_pdf(F, row, ru, rv);
-                            } else {
-                                row = upper_search(F.env_row, F.env_h, s1);
-                                const uint32_t *cq = F.env_col + (size_t)row * F.env_w;
-                                col = upper_search(cq, F.env_w, s2);
-                                uint64_t r0 = F.env_row[row], r1 = row + 1 < F.env_h ? F.env_row[row + 1] : (1ull << 32);
-                                uint64_t c0 = cq[col], c1 = col + 1 < F.env_w ? cq[col + 1] : (1ull << 32);
-                                fy = (float)(s1 - r0) / (float)(r1 - r0);
-                                fx = (float)(s2 - c0) / (float)(c1 - c0);
-                            }
-                            float ct = F.env_cos[row], cb = F.env_cos[row + 1];
-                            float cth = ct + fy * (cb - ct);
-                            float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
-                            float sp, cp;
-                            sincosf(2.0f * kPi * ((float)col + fx) / (float)F.env_w, &sp, &cp);
-                            wi = mk(sth * sp, cth, -sth * cp);
-                            float4 e = F.env_texel[(size_t)row * F.env_w + col];
-                            Le = xyz(e);
-                            pl = F.p_env * (F.env_pyramid ? pt : e.w);
-                            ok = pl > 0.0f;
-                        } else {
-                            uint32_t s7 = sample_bits(F, idx, base_dim + 7, F.scramble);
-                            uint32_t e;
-                            float pe;
-                            if (F.light_tree) {
-                                // 63-bit sample: what slot 0 leaves after the environment
-                                // choice (its top 31 bits without an environment), then slot 7
-                                const uint64_t hi = F.env_w ? rr : (uint64_t)(s0 >> 1);
-                                uint64_t z;
-                                e = lt_sample(F, (hi << 32) | s7, xo, nn, z);
-                                pe = (1.0f - F.p_env) * ((float)z * 0x1p-63f);
-                            } else {
-                                // rr < R <= 2^32 and num_emit < 2^27: the product fits 64 bits
-                                uint32_t col =
-                                    (uint32_t)((rr * (uint64_t)F.num_emit) >> (R == (1ull << 31) ? 31 : 32));
-                                e = (unsigned long long)s7 < F.alias_thr[col] ? col : F.alias_idx[col];
-                                pe = F.emit_pmf[e];
-                            }
-                            const Tri lt = F.tris[F.emit_tri[e]];
-                            float q1 = u24(sample_bits(F, idx, base_dim + 1, F.scramble));
-                            float q2 = u24(sample_bits(F, idx, base_dim + 2, F.scramble));
-                            float su = sqrtf(q1);
-                            float b0 = 1.0f - su, bb1 = q2 * su, bb2 = su * (1.0f - q2);
-                            f3 la = xyz(lt.v0), lb = xyz(lt.v1), lc = xyz(lt.v2);
-                            f3 y = la * b0 + lb * bb1 + lc * bb2;
-                            f3 nl = cross(lb - la, lc - la);
-                            float la2 = length(nl);
-                            nl = nl * (1.0f / la2);
-                            f3 dv = y - xo;
-                            float d2 = dot(dv, dv);
-                            float dist = sqrtf(d2);
-                            wi = dv * (1.0f / dist);
-                            float cl = -dot(nl, wi);
-                            if (cl > 0.0f) {
-                                Le = emission_at(F.mats[fbits(lt.v0.w)], y);
-                                pl = pe / (0.5f * la2) * d2 / cl;
-                                ok = pl > 0.0f;
-                                tmax = dist * (1.0f - 1e-4f);
-                            }
-                        }
-                        if (ok) {
-                            float ci = dot(nn, wi);
-                            if (ci > 0.0f) {
-                                f3 fb;
-                                float pb;
-                                bsdf_eval(m, nn, wo, wi, fb, pb);
-                                if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
-                                float w = F.mode == 2 ? 1.0f : mis2(pl, pb);
-                                f3 contrib = T * fb * Le * (ci * w / pl);
-                                if (maxc(contrib) > 0.0f) {
-                                    shadow = true;
-                                    sh_o = f4(xo, tmax);
-                                    sh_d = f4(wi, ubits(slot));
-                                    sh_c = f4(contrib, 0.0f);
-                                }
-                            }
-                        }
-                    }
-                    // continue the path: slot 3 picks guide or BSDF (guide iff the 32-bit
-                    // sample < alpha 2^32) and, rescaled to [0, 2^32), the lobe; slots 4-5
-                    // the direction. The density is the one-sample mixture
-                    // alpha q + (1 - alpha) p_bsdf, so the estimator stays unbiased.
-                    uint32_t s3 = sample_bits(F, idx, base_dim + 3, F.scramble);
-                    bool use_guide = guided && s3 < F.guide.alpha_thr;
-                    uint32_t r3 = s3;
-                    if (guided) {
-                        uint64_t lo = use_guide ? 0ull : F.guide.alpha_thr;
-                        uint64_t range = use_guide ? F.guide.alpha_thr : (1ull << 32) - F.guide.alpha_thr;
-                        r3 = (uint32_t)((((uint64_t)s3 - lo) << 32) / range);
-                    }
-                    float u3 = u24(r3);
-                    float u4 = u24(sample_bits(F, idx, base_dim + 4, F.scramble));
-                    float u5 = u24(sample_bits(F, idx, base_dim + 5, F.scramble));
-                    f3 wi;
-                    bool ok;
-                    if (use_guide) {
-                        guide::V3 g = guide::mixture_sample(mix, u3, u4, u5);
-                        wi = mk(g.x, g.y, g.z);
-                        ok = dot(nn, wi) > 0.0f;
-                    } else {
-                        ok = bsdf_sample(m, nn, wo, u3, u4, u5, wi);
-                    }
-                    if (ok) {
-                        f3 fb;
-                        float pb;
-                        bsdf_eval(m, nn, wo, wi, fb, pb);
-                        if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
-                        if (pb > 0.0f) {
-                            f3 Tb = T;  // throughput before this vertex's scattering
-                            T = T * fb * (dot(nn, wi) / pb);
-                            if (maxc(T) > 0.0f) {
-                                alive = true;
-                                if (F.rr && v >= 3) {
-                                    float qq = fminf(0.95f, maxc(T));
-                                    qq = ceilf(qq * 16777216.0f) * 0x1p-24f;
-                                    float u6 = u24(sample_bits(F, idx, base_dim + 6, F.scramble));
-                                    if (u6 < qq) {
-                                        T = T * (1.0f / qq);
-                                        Tb = Tb * (1.0f / qq);
-                                    } else {
-                                        alive = false;
-                                    }
-                                }
-                                if (alive) {
-                                    P.ray_o[slot] = f4(xo, INFINITY);
-                                    P.ray_d[slot] = f4(wi, ubits(tri | (front ? 0u : 0x80000000u)));
-                                    P.thr[slot] = f4(T, pb);
-                                    if (F.guide.record && v <= F.guide.max_vertex &&
-                                        (F.guide.rec_thr == 0xffffffffu || rec_hash(idx, v) < F.guide.rec_thr)) {
-                                        // training record: (final - now - this vertex's NEE) /
-                                        // T_before is this sample's estimate f cos L_i / p of
-                                        // the scattering integral (roulette folded into T_before)
-                                        record = true;
-                                        rec0 = f4(x, pb);
-                                        rec1 = f4(wo, 0.0f);
-                                        rec2 = f4(wi, ubits(slot));
-                                        rec3 = f4(L, ubits(v));
-                                        rec4 = f4(Tb, 0.0f);
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-            }
-            P.rad[slot] = f4(L, 0.0f);
+            shade_slot(F, P, v, slot, o);
         }
         uint32_t rec_idx = kNoHit;
         if (F.guide.record) {
-            uint32_t pr = wave_append(&P.counters[127], record);
-            if (record && pr < F.guide.rec_cap) {
+            uint32_t pr = wave_append(&P.counters[127], o.record);
+            if (o.record && pr < F.guide.rec_cap) {
                 float4 *r = F.guide.rec + (size_t)pr * kRecF4;
-                r[0] = rec0;
-                r[1] = rec1;
-                r[2] = rec2;
-                r[3] = rec3;
-                r[4] = rec4;
+                r[0] = o.rec[0];
+                r[1] = o.rec[1];
+                r[2] = o.rec[2];
+                r[3] = o.rec[3];
+                r[4] = o.rec[4];
                 r[5] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 rec_idx = pr;
             }
         }
-        uint32_t ps = wave_append(&P.counters[64 + v], shadow);
-        if (shadow) {
-            sh_c.w = ubits(rec_idx);
+        uint32_t ps = wave_append(&P.counters[64 + v], o.shadow);
+        if (o.shadow) {
+            o.sh_c.w = ubits(rec_idx);
             P.q_sh[ps] = slot;
-            P.sh_o[ps] = sh_o;
-            P.sh_d[ps] = sh_d;
-            P.sh_c[ps] = sh_c;
+            P.sh_o[ps] = o.sh_o;
+            P.sh_d[ps] = o.sh_d;
+            P.sh_c[ps] = o.sh_c;
         }
-        uint32_t pe = wave_append(&P.counters[v + 1], alive);
-        if (alive) qn[pe] = slot;
+        uint32_t pe = wave_append(&P.counters[v + 1], o.alive);
+        if (o.alive) qn[pe] = slot;
+    }
+}
+
+// The tail of a batch in one launch (Sec. 3.1.3: a megakernel once few
+// paths are left): every path still queued at depth v0 runs to its end in one
+// thread -- closest hit, shading, its shadow ray, depth after depth -- with
+// the same device code as the per-depth kernels, so its radiance is the same
+// bit for bit. Rays of deeper vertices are added to the per-depth counters as
+// the per-depth kernels would count them. Not for guided rendering (records
+// and the per-vertex mixtures live in the per-depth kernels).
+template <bool QN>
+__global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0)
+{
+    __shared__ int stk[kShortStack * kBlock];
+    __shared__ uint32_t cnt_ext[64], cnt_sh[64];
+    if (threadIdx.x < 64) {
+        cnt_ext[threadIdx.x] = 0;
+        cnt_sh[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const uint32_t n = P.counters[v0];
+    const uint32_t *q = P.q_ext[v0 & 1];
+    int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
+    uint32_t en = 0, et = 0, sn = 0, st = 0;
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t i = base + threadIdx.x;
+        if (i >= n) break;
+        const uint32_t slot = q[i];
+        for (uint32_t v = v0;; ++v) {
+            const float4 o4 = P.ray_o[slot], d4 = P.ray_d[slot];
+            RayPre r = prepare(xyz(o4), xyz(d4));
+            HitRec h;
+            traverse<false, QN>(F, r, o4.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+            P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
+            en += h.nodes;
+            et += h.tests;
+            ShadeOut o;
+            o.sh_o = o.sh_d = o.sh_c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            shade_slot(F, P, v, slot, o);
+            if (o.shadow) {
+                atomicAdd(&cnt_sh[v], 1u);
+                RayPre rs = prepare(xyz(o.sh_o), xyz(o.sh_d));
+                HitRec hs;
+                const bool occluded = traverse<true, QN>(F, rs, o.sh_o.w, hs, stk + threadIdx.x, gstk, P.trav_threads);
+                sn += hs.nodes;
+                st += hs.tests;
+                if (!occluded) {
+                    const float4 L = P.rad[slot];
+                    P.rad[slot] = make_float4(L.x + o.sh_c.x, L.y + o.sh_c.y, L.z + o.sh_c.z, L.w);
+                }
+            }
+            if (!o.alive) break;
+            atomicAdd(&cnt_ext[v + 1], 1u);
+        }
+    }
+    wave_count(&P.stats[4], en);
+    wave_count(&P.stats[5], et);
+    wave_count(&P.stats[6], sn);
+    wave_count(&P.stats[7], st);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        if (cnt_ext[threadIdx.x]) atomicAdd(&P.counters[threadIdx.x], cnt_ext[threadIdx.x]);
+        if (cnt_sh[threadIdx.x]) atomicAdd(&P.counters[64 + threadIdx.x], cnt_sh[threadIdx.x]);
     }
 }
 
@@ -1402,7 +1487,16 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
     });
     uint32_t g = blocks_for(n, 8192);
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
+    const bool tail_ok = F.tail_depth >= 1 && !F.guide.alpha_thr && !F.guide.record;
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
+        if (tail_ok && v == F.tail_depth) {
+            // the rest of the batch's paths in one launch (traversal grid, four blocks per CU resident)
+            timed(K_TAIL, [&] {
+                if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_tail<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+                else hipLaunchKernelGGL(k_tail<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+            });
+            break;
+        }
         timed(K_TRACE, [&] {
             if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
             else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
