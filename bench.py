@@ -59,7 +59,7 @@ TRACE_RAY_BYTES = 4 + 32 + 16        # queue entry, ray (o, tmax, d), hit record
 SHADOW_RAY_BYTES = 48 + 32           # shadow ray + contribution, radiance read-modify-write
 SHADE_VERTEX_BYTES = 4 + 16 + 16 + 16 + 16 + 8 + 48 + 32 + 16   # reads + radiance write
 SHADE_CONTINUE_BYTES = 16 + 16 + 16 + 4                           # next ray, throughput, queue
-SHADE_NEE_BYTES = 4 + 48 + 48 + 8 + 4 + 4                         # shadow record, light tri, alias, pmf
+SHADE_NEE_BYTES = 48 + 48 + 8 + 4 + 4                             # shadow record, light tri, alias, pmf
 
 
 def _say(*a):
@@ -252,8 +252,10 @@ def run_guided(width: int, height: int, tris: int, passes: int, alpha: float = 0
 def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
     """Passes per launch sequence against throughput (the paper's Table 1 in
     kind): the grid workload at 1080p with path pools from 2^min_log2 to
-    2^max_log2 slots, one batch at a time and two in flight; each setting
-    renders two pools' worth of passes (at least 8) after one untimed batch."""
+    2^max_log2 slots; per pool: one batch at a time, two in flight, the
+    megakernel tail from depth 4 (one stream), and, for pools of whole frames,
+    regeneration through a quarter of the pool's slots. Each setting renders
+    two pools' worth of passes (at least 8) after one untimed batch."""
     import time
 
     import torch
@@ -265,22 +267,27 @@ def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
     npix = sc.width * sc.height
     lines = ["# passes per launch sequence against throughput (grid, 0.97M triangles, 1920x1080, depth 12)",
              f"command: {cmd}", f"kernel_source_sha: {kernel_sha()}", "",
-             f"{'pool (paths)':>14} {'frames/batch':>13} {'passes':>7} {'one stream Mrays/s':>19} "
-             f"{'two in flight Mrays/s':>22} {'Mpaths/s (two)':>15}"]
+             "Mrays/s per schedule: one batch at a time; two batches in flight; one at a time with the",
+             "megakernel tail from depth 4; regeneration with live slots = pool / 4 (whole-frame batches only)", "",
+             f"{'pool (paths)':>14} {'frames/batch':>13} {'passes':>7} {'one stream':>11} {'two in flight':>14} "
+             f"{'tail from 4':>12} {'regeneration':>13} {'Mpaths/s (best)':>16}"]
     for lg in range(min_log2, max_log2 + 1):
         pool = 1 << lg
         frames = pool / npix
         per = max(1, pool // npix)
         passes = max(8, 2 * per)
         r = Renderer(sc, pool_paths=pool)
+        schedules = [{"single_stream": True}, {"single_stream": False}, {"single_stream": True, "tail_depth": 4}]
+        if pool >= npix:
+            schedules.append({"regen_paths": pool // 4})
         res = []
-        for single in (True, False):
+        for kw in schedules:
             r.reset()
-            r.render(0, per, single_stream=single)
+            r.render(0, per, **kw)
             torch.cuda.synchronize()
             st0 = r.stats()
             t0 = time.perf_counter()
-            r.render(per, passes, single_stream=single)
+            r.render(per, passes, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             st1 = r.stats()
@@ -288,13 +295,13 @@ def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
             res.append((rays / dt / 1e6, passes * npix / dt / 1e6))
         del r
         torch.cuda.empty_cache()
-        lines.append(f"{'2^%d' % lg:>14} {frames:>13.3f} {passes:>7} {res[0][0]:>19.1f} {res[1][0]:>22.1f} "
-                     f"{res[1][1]:>15.1f}")
+        cols = [f"{x[0]:.1f}" for x in res] + ["--"] * (4 - len(res))
+        lines.append(f"{'2^%d' % lg:>14} {frames:>13.3f} {passes:>7} {cols[0]:>11} {cols[1]:>14} {cols[2]:>12} "
+                     f"{cols[3]:>13} {max(x[1] for x in res):>16.1f}")
         print(lines[-1], flush=True)
     txt = "\n".join(lines) + "\n"
     open(out_txt, "w").write(txt)
     return txt
-
 
 
 def pmc_traffic(kernel: str, workload_tag: str):

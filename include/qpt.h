@@ -145,6 +145,18 @@ typedef struct {
                                 megakernel) takes every path still alive to its end, vertex after
                                 vertex in one thread, with the same per-vertex code (the same image
                                 bit for bit). Ignored while the guide samples or records. */
+    uint32_t regen_paths;    /* regeneration of terminated paths (Sec. 3.1.3): 0: every path of a batch
+                                has a state slot of its own from its camera ray to its end; n > 0: the
+                                batch's paths run through n state slots (64 <= n <= the workspace's
+                                pool, QPT_E_INVALID otherwise), and once more than half of them are
+                                free, the free slots start the batch's next paths; every iteration
+                                traces, shades and occludes the live paths whatever their depth. The
+                                image and the ray counts are the same bit for bit. Batches then run
+                                one at a time on the caller's stream (single_stream implied), and the
+                                host waits on the stream now and then to learn when a batch has
+                                finished. Applies to batches of whole frames (a frame no larger than
+                                the pool) without the guide; ignored otherwise, and tail_depth is
+                                ignored while it applies. */
 } qpt_render_opts;
 
 typedef struct {

@@ -270,7 +270,7 @@ struct Layout {
         env_col, env_cos, bases;
     // per batch lane (two batches in flight): path state, queues, shadow rays, counters, stack
     struct Lane {
-        size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qsh, sh_o, sh_d, sh_c, counters, gstack;
+        size_t ray_o, ray_d, hit, thr, rad, idx, q0, q1, qdead, pv, sh_o, sh_d, sh_c, counters, gstack;
     } lane[2];
     size_t stats;
     size_t fb_sum, fb_count;
@@ -396,7 +396,8 @@ struct qpt_ctx {
     // lanes against the caller's stream and the framebuffer updates in pass order
     hipStream_t lstream = nullptr;
     hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr, ev_fin = nullptr;
-    uint32_t *abort_host = nullptr;              // pinned, mapped: the caller's stop request
+    hipEvent_t ev_regen[2] = {nullptr, nullptr};  // regeneration: a chunk of iterations has copied its paths left
+    uint32_t *abort_host = nullptr;              // pinned, mapped: the caller's stop request (word 0)
     uint32_t *abort_dev = nullptr;               // its device address
     uint4 *lane_mix[2] = {nullptr, nullptr};     // per lane: the guide's mixture per slot
     float4 *lane_rec[2] = {nullptr, nullptr};    // per lane: training records
@@ -943,7 +944,8 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.env_col = take(c->env_col.size() * 4);
     L.env_cos = take(c->env_cos.size() * 4);
     L.bases = take(kMaxDims * sizeof(HaltonBase));
-    for (Layout::Lane &ln : L.lane) {
+    for (int lane = 0; lane < 2; ++lane) {
+        Layout::Lane &ln = L.lane[lane];
         ln.ray_o = take((size_t)cap * 16);
         ln.ray_d = take((size_t)cap * 16);
         ln.hit = take((size_t)cap * 16);
@@ -952,7 +954,8 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
         ln.idx = take((size_t)cap * 8);
         ln.q0 = take((size_t)cap * 4);
         ln.q1 = take((size_t)cap * 4);
-        ln.qsh = take((size_t)cap * 4);
+        ln.qdead = take((size_t)cap * 4);
+        ln.pv = take(lane == 0 ? (size_t)cap * 8 : 0);   // regeneration runs on the first lane only
         ln.sh_o = take((size_t)cap * 16);
         ln.sh_d = take((size_t)cap * 16);
         ln.sh_c = take((size_t)cap * 16);
@@ -1055,6 +1058,8 @@ void qpt_destroy(qpt_ctx *ctx)
         (void)hipEventDestroy(ctx->ev_lane_out);
         (void)hipEventDestroy(ctx->ev_acc);
         (void)hipEventDestroy(ctx->ev_fin);
+        for (int k = 0; k < 2; ++k)
+            if (ctx->ev_regen[k]) (void)hipEventDestroy(ctx->ev_regen[k]);
         if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
     }
     if (ctx->lstream && ctx->own_lstream) {
@@ -1516,6 +1521,8 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fin, hipEventDisableTiming));
+        for (int k = 0; k < 2; ++k) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_regen[k], hipEventDisableTiming));
+        // word 0: the stop request; words 8-9: regeneration's paths left per chunk
         HIP_TRY(c, hipHostMalloc((void **)&c->abort_host, 64, hipHostMallocMapped));
         HIP_TRY(c, hipHostGetDevicePointer((void **)&c->abort_dev, c->abort_host, 0));
         __atomic_store_n(c->abort_host, 0u, __ATOMIC_SEQ_CST);
@@ -1598,7 +1605,8 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
         p.idx = (unsigned long long *)(w + ln.idx);
         p.q_ext[0] = (uint32_t *)(w + ln.q0);
         p.q_ext[1] = (uint32_t *)(w + ln.q1);
-        p.q_sh = (uint32_t *)(w + ln.qsh);
+        p.q_dead = (uint32_t *)(w + ln.qdead);
+        p.pv = k ? nullptr : (uint2 *)(w + ln.pv);
         p.sh_o = (float4 *)(w + ln.sh_o);
         p.sh_d = (float4 *)(w + ln.sh_d);
         p.sh_c = (float4 *)(w + ln.sh_c);
@@ -1691,9 +1699,11 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     if (!c || !o) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
     if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1 ||
-        o->env_sampling > 2 || o->filter > 1 || o->tail_depth > o->max_depth)
+        o->env_sampling > 2 || o->filter > 1 || o->tail_depth > o->max_depth ||
+        (o->regen_paths && (o->regen_paths < 64 || o->regen_paths > c->pool_cap)))
         return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, "
-                                      "env_sampling 0..2, filter 0..1, tail_depth 0..max_depth)");
+                                      "env_sampling 0..2, filter 0..1, tail_depth 0..max_depth, regen_paths 0 or "
+                                      "64..pool)");
     if (o->env_sampling && c->ew && !c->ep_m)
         return fail(c, QPT_E_INVALID, "environment pyramid needs a 2:1 map of power-of-two size");
     if (!num_passes) return QPT_OK;
@@ -1726,12 +1736,15 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     // samples enter the replay ring one batch after another. Lane 1 starts
     // after the caller's earlier work and the caller's stream waits for lane 1
     // before this call returns.
-    const bool two_lanes = !o->single_stream;
+    // regeneration: whole-frame batches of the plain tracer, one at a time
+    const uint32_t npix = c->W * c->H, cap = c->pool_cap;
+    const bool regen = o->regen_paths && !guiding && npix <= cap;
+    f.regen = regen ? o->regen_paths : 0u;
+    const bool two_lanes = !o->single_stream && !regen;
     bool lane_b_used = false;
     // the point lane 1 waits for: the caller's work before this call
     if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_lane_in, c->stream));
     // one batch of passes (or of pixels), then one training step if enabled
-    const uint32_t npix = c->W * c->H, cap = c->pool_cap;
     auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
         // pixel chunks of one pass stay on one lane (its first chunk latches the
         // abort decision for the rest); whole-pass batches alternate
@@ -1773,7 +1786,8 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
             f.guide.frag = c->pub_frag[k];
             f.guide.bias = c->pub_bias[k];
         }
-        HIP_TRY(c, launch_render_paths(f, P, p0, np, pass0, nb, s, prof));
+        if (regen) HIP_TRY(c, launch_render_regen(f, P, np, pass0, nb, s, prof, c->abort_host + 8, c->ev_regen));
+        else HIP_TRY(c, launch_render_paths(f, P, p0, np, pass0, nb, s, prof));
         c->last_batch.valid = true;
         c->last_batch.lane = lane_b ? 1 : 0;
         c->last_batch.p0 = p0;

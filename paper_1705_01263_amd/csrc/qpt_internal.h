@@ -17,6 +17,11 @@ constexpr uint32_t kNoHit = 0xffffffffu;
 // per-lane counter words beyond the queue counts: the abort decision latched
 // by a pass's first batch, and whether the current batch renders nothing
 constexpr uint32_t kPassLatch = 125, kSkip = 126;
+// regeneration (render option regen_paths): the two ping-pong queue counts,
+// the shadow-ray count of the current iteration, the terminated slots, the
+// next path id to start, and the paths not yet finished (alive + not started);
+// above the per-depth counts (depth <= 32) and below the shadow counts
+constexpr uint32_t kRgQ0 = 40, kRgQ1 = 41, kRgSh = 42, kRgDead = 43, kRgNext = 44, kRgLeft = 45;
 
 // One base of the Halton sequence with its strength-reduced divisions
 // (Appendix A.2: integer evaluation, division by multiplication).
@@ -165,6 +170,7 @@ struct Frame {
     uint32_t env_pyramid;                 // 0: 2D CDF, 1: pyramid, 2: pyramid with normal-weighted top levels
     uint32_t gauss_filter;                // film samples from the Gaussian pixel filter instead of the box
     uint32_t tail_depth;                  // 0, or the depth from which one launch finishes every path
+    uint32_t regen;                       // live path slots while regenerating (0: one path per slot)
     const uint32_t *abort_word;           // host-mapped: non-zero once the caller asked to stop
 };
 
@@ -175,10 +181,11 @@ struct Pool {
     float4 *ray_d;      // d.xyz, previous vertex (triangle | back-face bit 31, as bits)
     float4 *hit;        // t, tri (BVH order, bits), b1, b2
     float4 *thr;        // throughput.rgb, pdf of the last BSDF sample
-    float4 *rad;        // radiance.rgb, -
+    float4 *rad;        // radiance.rgb, - (indexed by the path's id in the batch; the slot without regeneration)
     unsigned long long *idx;   // Halton index of the path
     uint32_t *q_ext[2]; // extension-ray queues (ping-pong)
-    uint32_t *q_sh;     // shadow queue -> slot
+    uint32_t *q_dead;   // regeneration: slots whose paths terminated since the last regeneration
+    uint2 *pv;          // regeneration: per slot, the id of its path in the batch and its next vertex
     float4 *sh_o;       // shadow ray o.xyz, tmax
     float4 *sh_d;       // shadow ray d.xyz, slot (bits)
     float4 *sh_c;       // pending contribution rgb, -
@@ -239,6 +246,13 @@ hipError_t launch_render_batch(const Frame &f, const Pool &pool, uint32_t pix0, 
 // the same in two parts: the paths of a batch, then its framebuffer update
 hipError_t launch_render_paths(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix,
                                uint64_t pass0, uint32_t npass, hipStream_t s, Profiler *prof);
+// the paths of a whole-frame batch through f.regen live slots with
+// regeneration: iterations are launched in chunks; `left` (host-mapped, two
+// words) receives the paths not yet finished after each chunk, `ev` (two
+// events) marks each chunk's copy. Returns hipErrorUnknown if the paths do
+// not finish within the iteration bound.
+hipError_t launch_render_regen(const Frame &f, const Pool &pool, uint32_t npix, uint64_t pass0, uint32_t npass,
+                               hipStream_t s, Profiler *prof, uint32_t *left, hipEvent_t ev[2]);
 // (a batch that starts a pass latches the abort word; its other pixel chunks follow it)
 hipError_t launch_accumulate(const Frame &f, const Pool &pool, uint32_t pix0, uint32_t npix, uint32_t npass,
                              hipStream_t s, Profiler *prof);

@@ -11,6 +11,8 @@
 // sample counts (Appendix A.4).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qpt_guide_dev.h"
 #include "qpt_internal.h"
 
@@ -300,6 +302,14 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
 // (stride gs) sized by the host for the tree's depth (at most 3 pushes per
 // level). Children are culled against the current closest t with a closed
 // interval, so the result does not depend on the visiting order.
+//
+// Inner nodes and leaves are processed in separate loops so that a wave runs
+// either kind of work with most lanes active: a lane that reaches a leaf
+// postpones it and keeps descending, and the wave leaves the node loop only
+// when a vote (ballot over the lanes still in it) finds that every one of them
+// holds a leaf; then the postponed leaves, and any leaves that follow them on
+// the stack, are tested. Postponing only delays the updates of the closest t,
+// which cull later children, so the hit is the same.
 template <bool ANY, bool QN, bool DEPTH = false>
 __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs)
 {
@@ -310,17 +320,26 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
     h.tests = 0;
     h.depth = 0;
     int sp = 0;
-    int ref = 0;
     const int step = (int)blockDim.x;
     const f3 oi = r.o * r.inv;
+    // the empty stack pops a reference no child carries
+    constexpr int32_t kDone = kEmptyChild;
     auto push = [&](int v) {
         if (sp < (int)kShortStack) stk[sp * step] = v;
         else gstk[(sp - kShortStack) * gs] = v;
         ++sp;
         if (DEPTH) h.depth = max(h.depth, (uint32_t)sp);
     };
-    while (true) {
-        if (ref >= 0) {
+    auto pop = [&]() -> int32_t {
+        if (sp == 0) return kDone;
+        --sp;
+        return sp < (int)kShortStack ? stk[sp * step] : gstk[(sp - kShortStack) * gs];
+    };
+    int32_t ref = 0;       // next inner node (>= 0) or leaf (< 0, not kDone), or kDone
+    int32_t leaf = 0;      // the postponed leaf, valid while has_leaf
+    bool has_leaf = false;
+    while (ref != kDone) {
+        while (ref >= 0) {
             ++h.nodes;
             uint32_t k0, k1, k2, k3;
             int4 nref;
@@ -352,11 +371,19 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
                 if (k2 != ~0u) push(child_ref(nref, k2 & 3u));
                 if (k1 != ~0u) push(child_ref(nref, k1 & 3u));
                 ref = child_ref(nref, k0 & 3u);
-                continue;
+            } else {
+                ref = pop();
             }
-        } else {
-            uint32_t payload = ~(uint32_t)ref;
-            uint32_t first = payload >> 3, cnt = (payload & 7u) + 1u;
+            if (ref < 0 && ref != kDone && !has_leaf) {
+                leaf = ref;
+                has_leaf = true;
+                ref = pop();
+            }
+            if (__ballot(!has_leaf) == 0ull) break;
+        }
+        while (has_leaf) {
+            const uint32_t payload = ~(uint32_t)leaf;
+            const uint32_t first = payload >> 3, cnt = (payload & 7u) + 1u;
             for (uint32_t k = 0; k < cnt; ++k) {
                 const Tri tr = F.tris[first + k];
                 float t, b1, b2;
@@ -366,7 +393,7 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
                     h.tri = first + k;
                     return true;
                 }
-                uint32_t id = fbits(tr.v1.w);
+                const uint32_t id = fbits(tr.v1.w);
                 if (t < h.t || (t == h.t && id < h.id)) {
                     h.t = t;
                     h.b1 = b1;
@@ -375,10 +402,14 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
                     h.id = id;
                 }
             }
+            // a leaf that follows on the stack is tested right away
+            if (ref < 0 && ref != kDone) {
+                leaf = ref;
+                ref = pop();
+            } else {
+                has_leaf = false;
+            }
         }
-        if (sp == 0) break;
-        --sp;
-        ref = sp < (int)kShortStack ? stk[sp * step] : gstk[(sp - kShortStack) * gs];
     }
     return h.tri != kNoHit;
 }
@@ -879,22 +910,20 @@ __device__ __forceinline__ void position_of(const SlotMap &m, uint32_t s, uint32
 
 __device__ __forceinline__ bool whole_frame(const Frame &F, uint32_t npix) { return npix == F.W * F.H; }
 
-// camera rays for slots [0, n), n = npix npass: slot s -> (position, pass) as above,
-// pixel tile_pixel(position) of a whole frame, else pix0 + position
-__global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint64_t pass0,
-                                                     uint32_t n)
+// The camera path with id `pid` of a batch of npass passes over npix pixels
+// (pid -> (position, pass) as above; pixel tile_pixel(position) of a whole
+// frame, else pix0 + position), started in state slot s: its camera ray,
+// unit throughput, its Halton index, and zero radiance at rad[pid].
+__device__ __forceinline__ void start_path(const Frame &F, const Pool &P, uint32_t s, uint32_t pid, uint32_t pix0,
+                                           uint32_t npix, uint32_t npass, uint64_t pass0)
 {
-    if (P.counters[kSkip]) return;  // aborted: no paths, every later stage sees empty queues
-    uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-    if (s == 0) P.counters[1] = n;
-    if (s >= n) return;
     uint32_t pl, j, p;
     if (whole_frame(F, npix)) {
-        position_of(slot_map(npix, n / npix), s, pl, j);
+        position_of(slot_map(npix, npass), pid, pl, j);
         p = tile_pixel(pl, F.W, F.H);
     } else {
-        pl = s % npix;
-        j = s / npix;
+        pl = pid % npix;
+        j = pid / npix;
         p = pix0 + pl;
     }
     uint32_t px = p % F.W, py = p / F.W;
@@ -919,20 +948,32 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
     P.ray_o[s] = make_float4(F.cam.eye[0], F.cam.eye[1], F.cam.eye[2], INFINITY);
     P.ray_d[s] = f4(d, 0.0f);
     P.thr[s] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
-    P.rad[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    P.rad[pid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     P.idx[s] = i;
+}
+
+// camera rays for slots [0, n), n = npix npass, one path per slot
+__global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t pix0, uint32_t npix, uint64_t pass0,
+                                                     uint32_t n)
+{
+    if (P.counters[kSkip]) return;  // aborted: no paths, every later stage sees empty queues
+    uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    if (s == 0) P.counters[1] = n;
+    if (s >= n) return;
+    start_path(F, P, s, s, pix0, npix, n / npix, pass0);
     P.q_ext[1][s] = s;
 }
 
-// closest hit for the extension rays queued at depth v; the grid holds twice
-// what is resident on the chip (a block that finishes early makes room for
-// one that has not started) and strides over the queue
+// closest hit for the extension rays of queue q_ext[qsel] (counters[cnt]
+// entries: the queue of one depth, or of one iteration when regenerating);
+// the grid holds twice what is resident on the chip (a block that finishes
+// early makes room for one that has not started) and strides over the queue
 template <bool QN>
-__global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v)
+__global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t cnt, uint32_t qsel)
 {
     __shared__ int stk[kShortStack * kBlock];
-    const uint32_t n = P.counters[v];
-    const uint32_t *q = P.q_ext[v & 1];
+    const uint32_t n = P.counters[cnt];
+    const uint32_t *q = P.q_ext[qsel];
     int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t nodes = 0, tests = 0;
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
@@ -951,12 +992,13 @@ __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t v
     wave_count(&P.stats[5], tests);
 }
 
-// occlusion test of the shadow rays queued at depth v; add unoccluded contributions
+// occlusion test of the counters[cnt] shadow rays of a depth (or iteration);
+// add unoccluded contributions to the radiance of their paths
 template <bool QN>
-__global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
+__global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t cnt)
 {
     __shared__ int stk[kShortStack * kBlock];
-    const uint32_t n = P.counters[64 + v];
+    const uint32_t n = P.counters[cnt];
     int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t nodes = 0, tests = 0;
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
@@ -969,10 +1011,10 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t v)
         nodes += h.nodes;
         tests += h.tests;
         if (!occluded) {
-            uint32_t slot = fbits(d.w);
+            uint32_t rs = fbits(d.w);
             float4 c = P.sh_c[i];
-            float4 L = P.rad[slot];
-            P.rad[slot] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
+            float4 L = P.rad[rs];
+            P.rad[rs] = make_float4(L.x + c.x, L.y + c.y, L.z + c.z, L.w);
             uint32_t rec = fbits(c.w);
             if (rec != kNoHit) F.guide.rec[(size_t)rec * kRecF4 + 5] = make_float4(c.x, c.y, c.z, 0.0f);
         }
@@ -1002,9 +1044,11 @@ struct ShadeOut {
 
 // emission with MIS, next-event estimation, BSDF (or guide) sampling and
 // roulette at vertex v of the path in `slot` (its hit already traced): updates
-// the slot's ray, throughput and radiance (the NEE contribution stays pending
-// in o.sh_c until its shadow ray is traced)
-__device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32_t v, uint32_t slot, ShadeOut &o)
+// the slot's ray and throughput and the path's radiance rad[rs] (rs = the
+// path's id in the batch; the NEE contribution stays pending in o.sh_c until
+// its shadow ray is traced)
+__device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32_t v, uint32_t slot, uint32_t rs,
+                                           ShadeOut &o)
 {
     const uint32_t base_dim = 2 + 8 * (v - 1);
     o.alive = o.shadow = o.record = false;
@@ -1014,7 +1058,7 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
     float4 T4 = P.thr[slot];
     f3 T = xyz(T4);
     float prev_pdf = T4.w;
-    f3 L = xyz(P.rad[slot]);
+    f3 L = xyz(P.rad[rs]);
     uint32_t tri = fbits(hv.y);
     if (tri == kNoHit) {
         if (F.env_w && (v == 1 || F.mode != 2)) {
@@ -1168,7 +1212,7 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
                         if (maxc(contrib) > 0.0f) {
                             o.shadow = true;
                             o.sh_o = f4(xo, tmax);
-                            o.sh_d = f4(wi, ubits(slot));
+                            o.sh_d = f4(wi, ubits(rs));
                             o.sh_c = f4(contrib, 0.0f);
                         }
                     }
@@ -1225,13 +1269,13 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
                             P.thr[slot] = f4(T, pb);
                             if (F.guide.record && v <= F.guide.max_vertex &&
                                 (F.guide.rec_thr == 0xffffffffu || rec_hash(idx, v) < F.guide.rec_thr)) {
-                                // training record: (final - now - this vertex's NEE) /
+                                // training record: (final - (now + this vertex's NEE)) /
                                 // T_before is this sample's estimate f cos L_i / p of
                                 // the scattering integral (roulette folded into T_before)
                                 o.record = true;
                                 o.rec[0] = f4(x, pb);
                                 o.rec[1] = f4(wo, 0.0f);
-                                o.rec[2] = f4(wi, ubits(slot));
+                                o.rec[2] = f4(wi, ubits(rs));
                                 o.rec[3] = f4(L, ubits(v));
                                 o.rec[4] = f4(Tb, 0.0f);
                             }
@@ -1241,7 +1285,7 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
             }
         }
     }
-    P.rad[slot] = f4(L, 0.0f);
+    P.rad[rs] = f4(L, 0.0f);
 }
 
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
@@ -1262,7 +1306,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
         for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (active) {
             slot = q[i];
-            shade_slot(F, P, v, slot, o);
+            shade_slot(F, P, v, slot, slot, o);
         }
         uint32_t rec_idx = kNoHit;
         if (F.guide.record) {
@@ -1281,7 +1325,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
         uint32_t ps = wave_append(&P.counters[64 + v], o.shadow);
         if (o.shadow) {
             o.sh_c.w = ubits(rec_idx);
-            P.q_sh[ps] = slot;
             P.sh_o[ps] = o.sh_o;
             P.sh_d[ps] = o.sh_d;
             P.sh_c[ps] = o.sh_c;
@@ -1289,6 +1332,121 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
         uint32_t pe = wave_append(&P.counters[v + 1], o.alive);
         if (o.alive) qn[pe] = slot;
     }
+}
+
+// ---- regeneration (Sec. 3.1.3: terminated sample states are restarted with
+// new samples once more than half of the states in memory are free). A
+// whole-frame batch of N = npix npass paths runs through L state slots: slot
+// s holds path pv[s].x (its id in the batch, the slot it would have without
+// regeneration) at vertex pv[s].y. The path's radiance stays at rad[id], so
+// the accumulation in pass order is unchanged and every path computes the
+// same bits as without regeneration. Iteration t traces and shades the queue
+// q_ext[t & 1] (counters[kRgQ0 + (t & 1)]) whatever the depth of each path in it.
+
+// the first min(L, N) paths of the batch into slots [0, min(L, N))
+__global__ __launch_bounds__(kBlock) void k_regen_init(Frame F, Pool P, uint32_t npix, uint64_t pass0,
+                                                       uint32_t npass, uint32_t L)
+{
+    const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+    const bool skip = P.counters[kSkip] != 0;  // aborted: nothing to render
+    const uint32_t N = npix * npass;
+    const uint32_t n = skip ? 0u : min(L, N);
+    if (s == 0) {
+        P.counters[kRgQ0] = n;
+        P.counters[kRgQ1] = 0;
+        P.counters[kRgSh] = 0;
+        P.counters[kRgDead] = 0;
+        P.counters[kRgNext] = n;
+        P.counters[kRgLeft] = skip ? 0u : N;
+    }
+    if (s >= n) return;
+    start_path(F, P, s, s, 0, npix, npass, pass0);
+    P.pv[s] = make_uint2(s, 1u);
+    P.q_ext[0][s] = s;
+}
+
+// shading of iteration t: each slot at its own vertex; continuing paths join
+// the next iteration's queue, terminated slots the dead list (plain
+// rendering: no guide, no training records)
+__global__ __launch_bounds__(kBlock, 4) void k_shade_regen(Frame F, Pool P, uint32_t t)
+{
+    const uint32_t n = P.counters[kRgQ0 + (t & 1)];
+    const uint32_t *q = P.q_ext[t & 1];
+    uint32_t *qn = P.q_ext[(t + 1) & 1];
+    uint32_t *cn = &P.counters[kRgQ0 + ((t + 1) & 1)];
+    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const bool active = i < n;
+        uint32_t slot = 0;
+        ShadeOut o;
+        o.alive = o.shadow = o.record = false;
+        o.sh_o = o.sh_d = o.sh_c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (active) {
+            slot = q[i];
+            const uint2 pv = P.pv[slot];
+            shade_slot(F, P, pv.y, slot, pv.x, o);
+            if (o.alive) P.pv[slot] = make_uint2(pv.x, pv.y + 1u);
+        }
+        const uint32_t ps = wave_append(&P.counters[kRgSh], o.shadow);
+        if (o.shadow) {
+            o.sh_c.w = ubits(kNoHit);
+            P.sh_o[ps] = o.sh_o;
+            P.sh_d[ps] = o.sh_d;
+            P.sh_c[ps] = o.sh_c;
+        }
+        const uint32_t pe = wave_append(cn, o.alive);
+        if (o.alive) qn[pe] = slot;
+        const bool dead = active && !o.alive;
+        const uint32_t pd = wave_append(&P.counters[kRgDead], dead);
+        if (dead) P.q_dead[pd] = slot;
+    }
+}
+
+// paths to start after an iteration: the free slots once more than half of
+// the L slots are free, as long as paths of the batch remain to start
+__device__ __forceinline__ uint32_t regen_count(const Pool &P, uint32_t L, uint32_t N)
+{
+    const uint32_t dead = P.counters[kRgDead], next = P.counters[kRgNext];
+    return (2ull * dead > L && next < N) ? min(dead, N - next) : 0u;
+}
+
+// restart free slot k with path next + k, appended to the next iteration's
+// queue after the paths that continue (counters updated by k_regen_commit)
+__global__ __launch_bounds__(kBlock) void k_regen(Frame F, Pool P, uint32_t t, uint32_t npix, uint64_t pass0,
+                                                  uint32_t npass, uint32_t L)
+{
+    const uint32_t N = npix * npass;
+    const uint32_t k = regen_count(P, L, N);
+    const uint32_t next = P.counters[kRgNext];
+    const uint32_t at = P.counters[kRgQ0 + ((t + 1) & 1)];
+    uint32_t *qn = P.q_ext[(t + 1) & 1];
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
+        const uint32_t s = P.q_dead[i];
+        start_path(F, P, s, next + i, 0, npix, npass, pass0);
+        P.pv[s] = make_uint2(next + i, 1u);
+        qn[at + i] = s;
+    }
+}
+
+// one thread after iteration t and its regeneration: the iteration's rays
+// into the statistics, the next queue's length, the dead list emptied (slots
+// left over once every path has started are never needed again), the current
+// queue's and the shadow count cleared for reuse, and the paths left
+__global__ void k_regen_commit(Pool P, uint32_t t, uint32_t N, uint32_t L)
+{
+    const uint32_t k = regen_count(P, L, N);
+    const uint32_t ci = kRgQ0 + (t & 1), cn = kRgQ0 + ((t + 1) & 1);
+    P.stats[0] += P.counters[ci];
+    P.stats[1] += P.counters[kRgSh];
+    if (k) {
+        P.counters[kRgDead] = 0;
+        P.counters[kRgNext] += k;
+    }
+    P.counters[cn] += k;
+    P.counters[ci] = 0;
+    P.counters[kRgSh] = 0;
+    P.counters[kRgLeft] = P.counters[cn] + (N - P.counters[kRgNext]);
 }
 
 // The tail of a batch in one launch (Sec. 3.1.3: a megakernel once few
@@ -1327,7 +1485,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0
             ShadeOut o;
             o.sh_o = o.sh_d = o.sh_c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            shade_slot(F, P, v, slot, o);
+            shade_slot(F, P, v, slot, slot, o);
             if (o.shadow) {
                 atomicAdd(&cnt_sh[v], 1u);
                 RayPre rs = prepare(xyz(o.sh_o), xyz(o.sh_d));
@@ -1498,15 +1656,71 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
             break;
         }
         timed(K_TRACE, [&] {
-            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
-            else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v, v & 1);
+            else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v, v & 1);
         });
         if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex) timed(K_GUIDE_EVAL, [&] { (void)launch_guide_eval(F, P, v, gt, s); });  // errors surface below
         timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] {
-            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
-            else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
+            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
+            else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
         });
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_regen(const Frame &F, const Pool &P, uint32_t npix, uint64_t pass0, uint32_t npass,
+                               hipStream_t s, Profiler *prof, uint32_t *left, hipEvent_t ev[2])
+{
+    const uint32_t N = npix * npass, L = std::min(F.regen, N);
+    auto timed = [&](int kind, auto &&launch) {
+        if (prof) prof->begin(kind, s);
+        launch();
+        if (prof) prof->end(kind, s);
+    };
+    timed(K_CLEAR, [&] { hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(128), 0, s, P, F.abort_word, 1u); });
+    timed(K_GENERATE, [&] {
+        hipLaunchKernelGGL(k_regen_init, dim3(blocks_for(L, 1u << 30)), dim3(kBlock), 0, s, F, P, npix, pass0, npass, L);
+    });
+    const uint32_t g = blocks_for(L, 8192), gt = blocks_for(L, P.trav_threads / kBlock);
+    auto iteration = [&](uint32_t t) {
+        const uint32_t c = kRgQ0 + (t & 1);
+        timed(K_TRACE, [&] {
+            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, c, t & 1);
+            else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, c, t & 1);
+        });
+        timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade_regen, dim3(g), dim3(kBlock), 0, s, F, P, t); });
+        timed(K_SHADOW, [&] {
+            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, kRgSh);
+            else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, kRgSh);
+        });
+        timed(K_GENERATE, [&] {
+            hipLaunchKernelGGL(k_regen, dim3(g), dim3(kBlock), 0, s, F, P, t, npix, pass0, npass, L);
+            hipLaunchKernelGGL(k_regen_commit, dim3(1), dim3(1), 0, s, P, t, N, L);
+        });
+    };
+    // Each iteration advances every live path by one vertex; one that leaves
+    // more than half of the slots free is followed by a regeneration that
+    // fills them, so at most every other iteration has fewer than L / 2 paths
+    // while paths remain to start, and once all have started the last ones
+    // end within max_depth iterations.
+    const uint64_t bound = 4ull * (uint64_t)N * F.max_depth / L + 2ull * F.max_depth + 16;
+    // Iterations go out in chunks; after each chunk the paths left are copied
+    // to host memory, and the chunk before the previous one is checked before
+    // the next goes out, so the queue never runs dry while the host waits.
+    constexpr uint32_t kChunk = 4;
+    uint32_t t = 0;
+    for (uint64_t chunk = 0;; ++chunk) {
+        if (chunk >= 2) {
+            hipError_t e = hipEventSynchronize(ev[chunk & 1]);
+            if (e != hipSuccess) return e;
+            if (__atomic_load_n(&left[chunk & 1], __ATOMIC_ACQUIRE) == 0) break;
+        }
+        if (t > bound) return hipErrorUnknown;
+        for (uint32_t k = 0; k < kChunk; ++k) iteration(t++);
+        hipError_t e = hipMemcpyAsync(&left[chunk & 1], P.counters + kRgLeft, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[chunk & 1], s);
+        if (e != hipSuccess) return e;
     }
     return hipGetLastError();
 }
