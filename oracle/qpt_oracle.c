@@ -1533,7 +1533,7 @@ static uint32_t rec_hash(uint64_t idx, uint32_t v)
  * directions, the mixture density of the sampled direction, and the parts
  * its weight is formed from at the path's end (radiance before the vertex's
  * next-event estimate, that estimate, throughput before the scattering with
- * roulette folded in). Weight = sum_c lum_c max(0, (L_end - L_before - NEE)_c
+ * roulette folded in). Weight = sum_c lum_c max(0, (L_end - (L_before + NEE))_c
  * / T_c) over the channels with T_c > 0: the sample's own estimate
  * f cos L_i / p of the scattering integral. */
 typedef struct {
@@ -1849,7 +1849,10 @@ static double rec_weight(const grec *r, v3 L, double *nee_w)
     for (int c = 0; c < 3; ++c)
         if (tc[c] > 0.0) {
             double own = g_plant == 3 ? 0.0 : nc[c];
-            w += wl[c] * fmax(0.0, (Lc[c] - bc[c] - own) / (g_plant == 2 ? 1.0 : tc[c]));
+            /* the radiance after the vertex's own NEE is L_before + NEE, the
+             * same addition the path made, so nothing gained afterwards is
+             * an exact zero */
+            w += wl[c] * fmax(0.0, (Lc[c] - (bc[c] + own)) / (g_plant == 2 ? 1.0 : tc[c]));
             wn += wl[c] * nc[c] / tc[c];
         }
     if (nee_w) *nee_w = wn;

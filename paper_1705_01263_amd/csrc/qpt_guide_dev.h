@@ -234,7 +234,11 @@ __device__ inline V3 mixture_sample(const M &m, float u_lobe, float u1, float u2
 // the NEE, r4 = throughput before the scattering, r5 = the NEE (0 if occluded).
 __device__ __forceinline__ float record_weight(float4 r3, float4 r4, float4 r5, float4 L)
 {
-    const float li[3] = {(L.x - r3.x - r5.x), (L.y - r3.y - r5.y), (L.z - r3.z - r5.z)};
+    // what the path gained after the vertex: its final radiance less the
+    // radiance right after the vertex's own next-event estimate, formed by
+    // the same addition the occlusion kernel made (r5 is zero when occluded),
+    // so a path that gains nothing afterwards weighs exactly zero
+    const float li[3] = {L.x - (r3.x + r5.x), L.y - (r3.y + r5.y), L.z - (r3.z + r5.z)};
     const float tb[3] = {r4.x, r4.y, r4.z};
     const float wl[3] = {0.2126f, 0.7152f, 0.0722f};
     float w = 0.0f;
