@@ -5,11 +5,14 @@ traversal and intersection), through the C-ABI:
   id, t, barycentrics) and occlusion through the BVH equal the GPU's brute
   force over every triangle, bit for bit, on a few thousand rays each:
   camera rays of the workload's camera, random rays aimed at vertices and
-  edges, and (city) street-level rays along the blocks whose traversal
-  stacks outgrow the 16 entries kept in LDS and spill to the workspace --
-  the test counts them and requires some;
+  edges, and (city) street-level rays along the blocks; the deepest
+  traversal stack of each ray is reported;
 - a subset of the same rays against the oracle's FP32 brute force (C, run
-  on host threads), bit for bit.
+  on host threads), bit for bit;
+- a comb of 120,000 sliver triangles whose boxes all contain one line while
+  the triangles miss it: rays along the line open every node, so their
+  stacks outgrow the 16 entries kept in LDS and spill to the workspace (the
+  test requires it), and BVH equals brute force bit for bit there too.
 """
 import math
 import sys
@@ -122,10 +125,8 @@ def test_fullsize_hits_bitexact(Renderer, orc, which):
     _say(f"    hits {hit.sum()}, deepest stack {depth.max()}, rays past the LDS stack (> 16): {(depth > 16).sum()}")
     assert np.array_equal(tri, tri_b)
     assert np.array_equal(t[hit], t_b[hit]) and np.array_equal(b[hit], b_b[hit])
-    if which == "city_16m":
-        assert (depth > 16).sum() >= 10, "street-level rays should spill the LDS stack"
-        spill = depth > 16
-        assert np.array_equal(tri[spill], tri_b[spill])
+    # rays whose stack spilled past the LDS entries (the comb test below makes
+    # sure some do) are part of the comparison above
     _, occ, _, _ = _trace(r, rays, True, 0)
     _, occ_b, _, _ = _trace(r, rays, True, 1)
     assert np.array_equal(occ, occ_b)
@@ -142,3 +143,51 @@ def test_fullsize_hits_bitexact(Renderer, orc, which):
     assert np.array_equal(tri[sub], tri_o)
     h = tri_o != 0xFFFFFFFF
     assert np.array_equal(t[sub][h], t_o[h]) and np.array_equal(b[sub][h], b_o[h])
+
+
+def _comb(n=120_000):
+    """Sliver triangles in the planes x = 0.001 k, each spanning y, z in
+    [-0.01, 0.01] x [-0.005, 0.01] (a box around the x axis) while the
+    triangle lies above the line from (-0.01, 0.01) to (0.01, -0.005) in
+    (y, z) and so misses the axis; a wall at x = n / 1000 + 1 ends it."""
+    b = g._Builder()
+    m = b.material((0.5, 0.5, 0.5))
+    x = 0.001 * np.arange(n, dtype=np.float64)
+    v = np.zeros((n, 3, 3))
+    v[:, :, 0] = x[:, None]
+    v[:, 0, 1:] = (-0.01, 0.01)
+    v[:, 1, 1:] = (0.01, 0.01)
+    v[:, 2, 1:] = (0.01, -0.005)
+    b.mesh(v.reshape(-1, 3), np.arange(3 * n).reshape(-1, 3), m)
+    xe = 0.001 * n + 1.0
+    b.quad((xe, -1, -1), (xe, -1, 1), (xe, 1, 1), (xe, 1, -1), m)
+    cam = g.Camera((-1.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), 10.0)
+    return b.scene("comb", cam, 16, 16, 1, 4)
+
+
+def test_stack_spill_comb(Renderer, orc):
+    sc = _comb()
+    rng = np.random.default_rng(5)
+    n = 256
+    # along the axis (inside every box), with small offsets that keep them inside
+    o = np.stack([np.full(n, -1.0), rng.uniform(-0.004, 0.004, n), rng.uniform(-0.004, 0.0, n)], 1)
+    d = np.stack([np.ones(n), rng.normal(0, 1e-6, n), rng.normal(0, 1e-6, n)], 1)
+    rays = _pack(o, d)
+    _say(f"[stack spill] comb: {sc.num_triangles} triangles, {n} rays along the axis")
+    r = Renderer(sc, pool_paths=1 << 16)
+    t, tri, b, depth = _trace(r, rays, False, 0)
+    t_b, tri_b, b_b, _ = _trace(r, rays, False, 1)
+    hit = tri != 0xFFFFFFFF
+    spill = int((depth > 16).sum())
+    _say(f"    hits {hit.sum()}, deepest stack {depth.max()}, rays past the LDS stack (> 16): {spill}")
+    assert spill >= n // 2, "rays along the comb should spill the LDS stack"
+    assert np.array_equal(tri, tri_b)
+    assert np.array_equal(t[hit], t_b[hit]) and np.array_equal(b[hit], b_b[hit])
+    _, occ, _, _ = _trace(r, rays, True, 0)
+    _, occ_b, _, _ = _trace(r, rays, True, 1)
+    assert np.array_equal(occ, occ_b) and np.array_equal(occ.astype(bool), hit)
+    # the rays that hit end on the wall; against the oracle's FP32 brute force
+    t_o, tri_o, b_o = _oracle_f32(orc, sc, rays[:32], threads=8)
+    assert np.array_equal(tri[:32], tri_o)
+    h = tri_o != 0xFFFFFFFF
+    assert np.array_equal(t[:32][h], t_o[h]) and np.array_equal(b[:32][h], b_o[h])
