@@ -137,3 +137,36 @@ def test_env_pyramid_absent_for_other_shapes(qpt):
     c = qpt.Context(-1)
     c.build_scene(sc)
     assert c.debug_env_pyramid()["m"] == 0
+
+
+def test_binding_struct_layout_matches_header(qpt, tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C header gives its counterpart (gcc, C99), so the argument
+    marshalling passes what the library reads."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = [n for n in dir(qpt) if n.startswith("qpt_") and isinstance(getattr(qpt, n), type)
+               and issubclass(getattr(qpt, n), C.Structure)]
+    assert "qpt_render_opts" in structs and "qpt_guide_opts" in structs
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qpt.h"', "int main(void) {"]
+    for n in structs:
+        lines.append(f'  printf("{n} size %zu\\n", sizeof({n}));')
+        for f, _ in getattr(qpt, n)._fields_:
+            lines.append(f'  printf("{n} {f} %zu\\n", offsetof({n}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.check_call([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(root, "include"), str(src), "-o",
+                           str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for n in structs:
+        cls = getattr(qpt, n)
+        assert int(got[f"{n} size"]) == C.sizeof(cls), n
+        for f, _ in cls._fields_:
+            assert int(got[f"{n} {f}"]) == getattr(cls, f).offset, (n, f)
