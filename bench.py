@@ -60,6 +60,11 @@ SHADOW_RAY_BYTES = 48 + 32           # shadow ray + contribution, radiance read-
 SHADE_VERTEX_BYTES = 4 + 16 + 16 + 16 + 16 + 8 + 48 + 32 + 16   # reads + radiance write
 SHADE_CONTINUE_BYTES = 16 + 16 + 16 + 4                           # next ray, throughput, queue
 SHADE_NEE_BYTES = 48 + 48 + 8 + 4 + 4                             # shadow record, light tri, alias, pmf
+# the same with the compressed path state: direction 8 (octahedral pair and
+# previous vertex), throughput and density 8, hit record 12
+TRACE_RAY_BYTES_C = 4 + 16 + 8 + 12
+SHADE_VERTEX_BYTES_C = 4 + 12 + 8 + 8 + 16 + 8 + 48 + 32 + 16
+SHADE_CONTINUE_BYTES_C = 16 + 8 + 8 + 4
 
 
 def _say(*a):
@@ -153,12 +158,15 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, out_txt: str, cal
     return txt
 
 
-def summarize_mfma(pmc_dir: str, kernels, out_txt: str, cmd: str, simds: int = 1024) -> str:
+def summarize_mfma(pmc_dir: str, kernels, out_txt: str, cmd: str, simds: int = 1024, xcds: int = 8) -> str:
     """Per-dispatch MFMA and VALU activity of `kernels` from one rocprofv3
     --pmc run with SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_VALU_MFMA_BUSY_CYCLES,
     SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES and GRBM_GUI_ACTIVE.
-    MFMA FLOPs = MOPS_BF16 x 512; utilisation = MFMA busy cycles over
-    GRBM_GUI_ACTIVE x SIMDs (256 CUs x 4 on MI355X)."""
+    MFMA FLOPs = MOPS_BF16 x 512. GRBM_GUI_ACTIVE comes summed over the
+    chip's XCDs (its value over a dispatch's duration is xcds x the clock),
+    so the dispatch's elapsed cycles are GRBM_GUI_ACTIVE / xcds, and MFMA
+    utilisation = MFMA busy cycles over (elapsed cycles x SIMDs), 256 CUs x
+    4 SIMDs on MI355X."""
     f = glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True)[0]
     per = collections.defaultdict(lambda: collections.defaultdict(dict))  # kernel -> dispatch -> counter
     dur = collections.defaultdict(dict)
@@ -179,11 +187,13 @@ def summarize_mfma(pmc_dir: str, kernels, out_txt: str, cmd: str, simds: int = 1
         t_ns = sum(dur[k][d] for d in ds) / len(ds)
         flops = avg("SQ_INSTS_VALU_MFMA_MOPS_BF16") * 512
         busy, gui = avg("SQ_VALU_MFMA_BUSY_CYCLES"), avg("GRBM_GUI_ACTIVE")
+        cyc = gui / xcds
         lines += [f"{k}: dispatches {len(ds)}, avg duration {t_ns / 1e3:.2f} us",
                   f"  BF16 MFMA FLOP per dispatch {flops:.4g} -> {flops / t_ns / 1e3:.2f} TFLOP/s "
                   f"({100 * flops / t_ns / 1e3 / 2500.0:.2f}% of the 2.5 PFLOP/s dense BF16 peak)",
-                  f"  MFMA busy {100 * busy / max(gui * simds, 1):.2f}% of SIMD cycles "
-                  f"(SQ_VALU_MFMA_BUSY_CYCLES {busy:.4g}, GRBM_GUI_ACTIVE {gui:.4g})",
+                  f"  MFMA busy {100 * busy / max(cyc * simds, 1):.2f}% of SIMD cycles "
+                  f"(SQ_VALU_MFMA_BUSY_CYCLES {busy:.4g}; GRBM_GUI_ACTIVE {gui:.4g}, summed over {xcds} XCDs: "
+                  f"{cyc:.4g} cycles, {cyc / t_ns:.2f} GHz)",
                   f"  SQ_INSTS_VALU {avg('SQ_INSTS_VALU'):.4g}, SQ_ACTIVE_INST_VALU {avg('SQ_ACTIVE_INST_VALU'):.4g}, "
                   f"SQ_BUSY_CU_CYCLES {avg('SQ_BUSY_CU_CYCLES'):.4g}"]
     txt = "\n".join(lines) + "\n"
@@ -687,6 +697,8 @@ def main():
                     help="0: binned SAH on the host, 1: linear BVH built on the GPU")
     ap.add_argument("--single-stream", action="store_true",
                     help="render the timed passes one batch at a time on one stream")
+    ap.add_argument("--compress-state", action="store_true",
+                    help="path state in the compressed layout (octahedral directions, half-precision throughput)")
     ap.add_argument("--no-light-select", action="store_true",
                     help="skip the alias table vs light tree equal-time leg (city workload only)")
     ap.add_argument("--ls-seconds", type=float, default=2.0, help="wall time of each light-selection run")
@@ -739,7 +751,8 @@ def main():
     _say(f"bench: bvh nodes={bs.num_nodes} leaves={bs.num_leaves} depth={bs.max_depth} build={bs.build_ms:.0f} ms")
     # the passes go to the library as one range, which renders them in batches
     # of as many whole passes as its path pool holds (eight frames' worth)
-    r.render(0, args.warmup)
+    cs = args.compress_state
+    r.render(0, args.warmup, compress_state=cs)
     torch.cuda.synchronize()
     _say(f"bench: warmup {args.warmup} passes done")
     st0 = r.stats()
@@ -749,7 +762,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    r.render(args.warmup, args.steps, single_stream=args.single_stream)
+    r.render(args.warmup, args.steps, single_stream=args.single_stream, compress_state=cs)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -777,11 +790,12 @@ def main():
             dn, dt_ = b.nodes_extension - a.nodes_extension, b.tris_extension - a.tris_extension
             sn, stt = b.nodes_shadow - a.nodes_shadow, b.tris_shadow - a.tris_shadow
             nb = r.bvh_stats.node_bytes
-            byts = {"trace": e * TRACE_RAY_BYTES + dn * nb + dt_ * TRI_BYTES,
+            tr_b, sv_b, sc_b = ((TRACE_RAY_BYTES_C, SHADE_VERTEX_BYTES_C, SHADE_CONTINUE_BYTES_C) if cs else
+                                (TRACE_RAY_BYTES, SHADE_VERTEX_BYTES, SHADE_CONTINUE_BYTES))
+            byts = {"trace": e * tr_b + dn * nb + dt_ * TRI_BYTES,
                     "shadow": h * SHADOW_RAY_BYTES + sn * nb + stt * TRI_BYTES,
-                    "shade": e * SHADE_VERTEX_BYTES + (e - (b.paths - a.paths)) * SHADE_CONTINUE_BYTES
-                             + h * SHADE_NEE_BYTES}
-            stream = {"trace": e * TRACE_RAY_BYTES, "shadow": h * SHADOW_RAY_BYTES, "shade": byts["shade"]}
+                    "shade": e * sv_b + (e - (b.paths - a.paths)) * sc_b + h * SHADE_NEE_BYTES}
+            stream = {"trace": e * tr_b, "shadow": h * SHADOW_RAY_BYTES, "shade": byts["shade"]}
             counts = {"nodes_per_ray": round(dn / max(e, 1), 2), "tris_per_ray": round(dt_ / max(e, 1), 2),
                       "shadow_nodes_per_ray": round(sn / max(h, 1), 2), "shadow_tris_per_ray": round(stt / max(h, 1), 2)}
             return byts, stream, counts
@@ -796,7 +810,7 @@ def main():
         else:
             r0 = r.stats()
             r.ctx.profile(True)
-            r.render(args.warmup + args.steps, args.steps, single_stream=True)
+            r.render(args.warmup + args.steps, args.steps, single_stream=True, compress_state=cs)
             r.ctx.profile(False)
             r_prof = r.ctx.profile_read()
             r1 = r.stats()
@@ -806,7 +820,8 @@ def main():
         launch_s = ms / n_l * 1e-3
         per_launch = rb[dom] / n_l
         achieved = per_launch / launch_s / 1e9
-        traffic = pmc_traffic(f"k_{dom}", WORKLOADS[args.workload][0])
+        # the committed counter summaries were taken with the full-precision state
+        traffic = None if cs else pmc_traffic(f"k_{dom}", WORKLOADS[args.workload][0])
         roof = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
@@ -878,6 +893,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][1],
                    "triangles": sc.num_triangles, "pixels": sc.width * sc.height, "max_depth": D,
+                   "path_state": "compressed" if cs else "full precision",
                    "parallelism": "single GPU"},
         "mpaths_per_s": round(mpaths, 3),
         "rays_per_path": round((ext + sh) / paths, 3),

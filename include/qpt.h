@@ -157,6 +157,15 @@ typedef struct {
                                 finished. Applies to batches of whole frames (a frame no larger than
                                 the pool) without the guide; ignored otherwise, and tail_depth is
                                 ignored while it applies. */
+    uint32_t compress_state; /* path state layout (Sec. 3.1.1): 0: full precision; 1: compressed, the
+                                next ray's direction as an octahedral pair of 16-bit values (within
+                                6.5e-5 rad), the throughput and the last sampling density in half
+                                precision, the hit's barycentrics as 16-bit fixed point: 28 bytes of
+                                the 48 per path kept between kernels instead of 48 (origin, radiance
+                                and index unchanged). A sampled direction is quantised where it is
+                                sampled, so the BSDF, the densities and the traced ray agree; the
+                                image is no longer the full-precision one bit for bit but estimates
+                                the same radiance (within the Monte Carlo error; tests). */
 } qpt_render_opts;
 
 typedef struct {

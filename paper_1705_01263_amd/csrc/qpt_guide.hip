@@ -20,6 +20,7 @@
 
 #include "qpt_guide_dev.h"
 #include "qpt_internal.h"
+#include "qpt_state_dev.h"
 
 namespace qpt {
 namespace {
@@ -491,12 +492,12 @@ __global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src
             wo = {src.wo[3 * (size_t)i], src.wo[3 * (size_t)i + 1], src.wo[3 * (size_t)i + 2]};
         } else if (valid) {
             slot = q[i];
-            float4 hv = P.hit[slot];
+            float4 hv = state::load_hit(F, P, slot);
             uint32_t tri = __float_as_uint(hv.y);
             valid = tri != kNoHit;
             if (valid) {
                 const Tri tr = F.tris[tri];
-                float4 d = P.ray_d[slot];
+                float4 d = state::load_dir(F, P, slot);
                 x = {tr.v0.x + ((tr.v1.x - tr.v0.x) * hv.z + (tr.v2.x - tr.v0.x) * hv.w),
                      tr.v0.y + ((tr.v1.y - tr.v0.y) * hv.z + (tr.v2.y - tr.v0.y) * hv.w),
                      tr.v0.z + ((tr.v1.z - tr.v0.z) * hv.z + (tr.v2.z - tr.v0.z) * hv.w)};

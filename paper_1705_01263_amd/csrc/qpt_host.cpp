@@ -337,9 +337,11 @@ struct qpt_ctx {
     hipStream_t tstream = nullptr;
     bool own_tstream = false, own_lstream = false;   // created here (else the caller's, not destroyed)
     void *static_scratch = nullptr;                  // this device's allocation-free build region
-    hipEvent_t ev_rec[2] = {nullptr, nullptr};    // batch k's samples are in the ring
+    hipEvent_t ev_rec[2] = {nullptr, nullptr};    // lane k's latest batch has been rendered
+    hipEvent_t ev_fin[2] = {nullptr, nullptr};    // lane k's latest batch's samples are in the ring
     hipEvent_t ev_train[2] = {nullptr, nullptr};  // the step publishing into buffer k has finished
     bool train_pending[2] = {false, false};
+    bool fin_pending[2] = {false, false};
     uint64_t gbatch = 0;   // training batches issued
     int last_buf = 0;      // buffer of the newest published weights
     uint2 *pub_frag[2] = {nullptr, nullptr};
@@ -395,7 +397,7 @@ struct qpt_ctx {
     // two batches in flight: lane 1's stream, and the events that order the
     // lanes against the caller's stream and the framebuffer updates in pass order
     hipStream_t lstream = nullptr;
-    hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr, ev_fin = nullptr;
+    hipEvent_t ev_lane_in = nullptr, ev_lane_out = nullptr, ev_acc = nullptr;
     hipEvent_t ev_regen[2] = {nullptr, nullptr};  // regeneration: a chunk of iterations has copied its paths left
     uint32_t *abort_host = nullptr;              // pinned, mapped: the caller's stop request (word 0)
     uint32_t *abort_dev = nullptr;               // its device address
@@ -959,7 +961,7 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
         ln.sh_o = take((size_t)cap * 16);
         ln.sh_d = take((size_t)cap * 16);
         ln.sh_c = take((size_t)cap * 16);
-        ln.counters = take(128 * 4);
+        ln.counters = take(kCounters * 4);
         ln.gstack = take((size_t)c->trav_threads * (c->stack_need > kShortStack ? c->stack_need - kShortStack : 1u) * 4);
     }
     L.stats = take(8 * 8);
@@ -999,6 +1001,7 @@ static hipError_t join_train(qpt_ctx *c)
     if (!c->tstream) return hipSuccess;
     hipError_t e = hipStreamSynchronize(c->tstream);
     c->train_pending[0] = c->train_pending[1] = false;
+    c->fin_pending[0] = c->fin_pending[1] = false;
     return e;
 }
 
@@ -1049,6 +1052,7 @@ void qpt_destroy(qpt_ctx *ctx)
     for (int k = 0; k < 2; ++k) {
         DeviceGuard g(ctx->device);
         if (ctx->ev_rec[k]) (void)hipEventDestroy(ctx->ev_rec[k]);
+        if (ctx->ev_fin[k]) (void)hipEventDestroy(ctx->ev_fin[k]);
         if (ctx->ev_train[k]) (void)hipEventDestroy(ctx->ev_train[k]);
     }
     if (ctx->ev_lane_in) {
@@ -1057,7 +1061,6 @@ void qpt_destroy(qpt_ctx *ctx)
         (void)hipEventDestroy(ctx->ev_lane_in);
         (void)hipEventDestroy(ctx->ev_lane_out);
         (void)hipEventDestroy(ctx->ev_acc);
-        (void)hipEventDestroy(ctx->ev_fin);
         for (int k = 0; k < 2; ++k)
             if (ctx->ev_regen[k]) (void)hipEventDestroy(ctx->ev_regen[k]);
         if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
@@ -1515,12 +1518,12 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
         }
         for (int k = 0; k < 2; ++k) {
             HIP_TRY(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
+            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fin[k], hipEventDisableTiming));
             HIP_TRY(c, hipEventCreateWithFlags(&c->ev_train[k], hipEventDisableTiming));
         }
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_in, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fin, hipEventDisableTiming));
         for (int k = 0; k < 2; ++k) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_regen[k], hipEventDisableTiming));
         // word 0: the stop request; words 8-9: regeneration's paths left per chunk
         HIP_TRY(c, hipHostMalloc((void **)&c->abort_host, 64, hipHostMallocMapped));
@@ -1700,10 +1703,10 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     if (!c->bound) return fail(c, QPT_E_STATE, "render_pass before bind_workspace");
     if (o->max_depth < 1 || 2 + 8 * (o->max_depth - 1) > kMaxDims || o->mode > 2 || o->light_tree > 1 ||
         o->env_sampling > 2 || o->filter > 1 || o->tail_depth > o->max_depth ||
-        (o->regen_paths && (o->regen_paths < 64 || o->regen_paths > c->pool_cap)))
+        (o->regen_paths && (o->regen_paths < 64 || o->regen_paths > c->pool_cap)) || o->compress_state > 1)
         return fail(c, QPT_E_INVALID, "bad render options (max_depth 1..32, mode 0..2, light_tree 0..1, "
                                       "env_sampling 0..2, filter 0..1, tail_depth 0..max_depth, regen_paths 0 or "
-                                      "64..pool)");
+                                      "64..pool, compress_state 0..1)");
     if (o->env_sampling && c->ew && !c->ep_m)
         return fail(c, QPT_E_INVALID, "environment pyramid needs a 2:1 map of power-of-two size");
     if (!num_passes) return QPT_OK;
@@ -1723,6 +1726,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.env_pyramid = c->ew ? o->env_sampling : 0;
     f.gauss_filter = o->filter;
     f.tail_depth = o->tail_depth;
+    f.compress = o->compress_state;
     f.abort_word = c->abort_dev;
     if (c->abort_host && __atomic_load_n(c->abort_host, __ATOMIC_SEQ_CST))
         return fail(c, QPT_E_ABORTED, "aborted: qpt_readback reports the progress and clears the request");
@@ -1755,6 +1759,10 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
             lane_b_used = true;
         }
         const Pool &P = lane_b ? c->pool_b : c->pool;
+        const int lane = lane_b ? 1 : 0;
+        // the lane's path pool and training records are free again once the
+        // training stream has finalised the lane's previous batch
+        if (c->fin_pending[lane]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_fin[lane], 0));
         f.guide.mix = c->lane_mix[lane_b ? 1 : 0];
         f.guide.rec = c->lane_rec[lane_b ? 1 : 0];
         f.guide.rec_count = P.counters + 127;
@@ -1776,9 +1784,10 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         // b mod 2, free once that step has finished) while the step of batch
         // b - 1 runs on the training stream. Any weights give an unbiased
         // estimator; the lag only delays what the guide has learnt. Batch b's
-        // samples enter the replay ring right after it (they read path
-        // radiance the lane's next batch overwrites), once step b - 1 has
-        // stopped reading the ring.
+        // samples enter the replay ring on the training stream, behind the
+        // steps already there (the only readers of the ring), so no render
+        // lane waits for training; the lane's next batch, which overwrites
+        // the path radiance the samples are formed from, waits for that.
         const bool train = c->gopts.train > 0;
         const int k = train ? (int)(c->gbatch & 1) : c->last_buf;
         if (guiding) {
@@ -1799,32 +1808,27 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_acc, s));
         if (train) {
             GuideTrain T = c->gt;
-            // the ring's readers (launched steps) finish before it is appended
-            // to, and batches append in order
-            for (int kk = 0; kk < 2; ++kk)
-                if (c->train_pending[kk]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_train[kk], 0));
-            if (two_lanes) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_fin, 0));
-            if (prof) prof->begin(K_GUIDE_TRAIN, s);
-            HIP_TRY(c, launch_guide_finalize(f, P, T, s));
-            if (prof) prof->end(K_GUIDE_TRAIN, s);
-            if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_fin, s));
+            // finalisation in batch order on the training stream (see above)
+            HIP_TRY(c, hipEventRecord(c->ev_rec[lane], s));
+            HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[lane], 0));
+            if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
+            HIP_TRY(c, launch_guide_finalize(f, P, T, c->tstream));
+            HIP_TRY(c, hipEventRecord(c->ev_fin[lane], c->tstream));
+            c->fin_pending[lane] = true;
             // `train` Adam steps per pass, taken when a batch completes its passes
             // (a pass split into pixel chunks trains after its last chunk)
             const uint32_t nsteps = (p0 + np >= npix) ? c->gopts.train * nb : 0u;
             if (nsteps) {
-                HIP_TRY(c, hipEventRecord(c->ev_rec[k], s));
-                HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[k], 0));
-                if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
                 HIP_TRY(c, launch_guide_train_steps(f, T, c->gopts.batch ? c->gopts.batch : (1u << 18),
                                                     c->guide_steps + 1, nsteps, c->gopts.lr, c->gopts.seed,
                                                     c->tstream, c->pub_frag[k], c->pub_bias[k]));
-                if (prof) prof->end(K_GUIDE_TRAIN, c->tstream);
                 HIP_TRY(c, hipEventRecord(c->ev_train[k], c->tstream));
                 c->train_pending[k] = true;
                 c->last_buf = k;
                 c->guide_steps += nsteps;
                 ++c->gbatch;
             }
+            if (prof) prof->end(K_GUIDE_TRAIN, c->tstream);
         }
         return QPT_OK;
     };

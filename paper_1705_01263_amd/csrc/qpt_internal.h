@@ -19,9 +19,21 @@ constexpr uint32_t kNoHit = 0xffffffffu;
 constexpr uint32_t kPassLatch = 125, kSkip = 126;
 // regeneration (render option regen_paths): the two ping-pong queue counts,
 // the shadow-ray count of the current iteration, the terminated slots, the
-// next path id to start, and the paths not yet finished (alive + not started);
-// above the per-depth counts (depth <= 32) and below the shadow counts
-constexpr uint32_t kRgQ0 = 40, kRgQ1 = 41, kRgSh = 42, kRgDead = 43, kRgNext = 44, kRgLeft = 45;
+// next path id to start, and the paths not yet finished (alive + not started),
+// in the second half of the lane's 256 counter words; the three that every
+// wave of the shading kernel appends to sit in cache lines of their own
+constexpr uint32_t kCounters = 256;
+constexpr uint32_t kRgQ0 = 128, kRgQ1 = 160, kRgSh = 192, kRgDead = 224, kRgNext = 129, kRgLeft = 130;
+// the queue count word of iteration t's queue q_ext[t & 1]
+__host__ __device__ constexpr uint32_t rg_queue_count(uint32_t t) { return (t & 1u) ? kRgQ1 : kRgQ0; }
+static_assert(kRgQ0 != kRgQ1 && kRgQ0 != kRgSh && kRgQ0 != kRgDead && kRgQ0 != kRgNext && kRgQ0 != kRgLeft &&
+                  kRgQ1 != kRgSh && kRgQ1 != kRgDead && kRgQ1 != kRgNext && kRgQ1 != kRgLeft && kRgSh != kRgDead &&
+                  kRgSh != kRgNext && kRgSh != kRgLeft && kRgDead != kRgNext && kRgDead != kRgLeft &&
+                  kRgNext != kRgLeft,
+              "regeneration counter words are distinct");
+static_assert(kRgQ0 >= 128 && kRgQ1 < kCounters && kRgSh < kCounters && kRgDead < kCounters && kRgNext >= 128 &&
+                  kRgLeft >= 128 && kRgLeft < kCounters,
+              "regeneration counters lie above the per-depth and shadow counts");
 
 // One base of the Halton sequence with its strength-reduced divisions
 // (Appendix A.2: integer evaluation, division by multiplication).
@@ -171,6 +183,7 @@ struct Frame {
     uint32_t gauss_filter;                // film samples from the Gaussian pixel filter instead of the box
     uint32_t tail_depth;                  // 0, or the depth from which one launch finishes every path
     uint32_t regen;                       // live path slots while regenerating (0: one path per slot)
+    uint32_t compress;                    // path state in the compressed layout (qpt_state_dev.h)
     const uint32_t *abort_word;           // host-mapped: non-zero once the caller asked to stop
 };
 

@@ -15,6 +15,7 @@
 
 #include "qpt_guide_dev.h"
 #include "qpt_internal.h"
+#include "qpt_state_dev.h"
 
 namespace qpt {
 
@@ -848,7 +849,7 @@ __global__ void k_fill_f64(double *p, size_t n)
 __global__ void k_batch_begin(Pool P, const uint32_t *abort_word, uint32_t first_chunk)
 {
     const uint32_t t = threadIdx.x;
-    if (t < 128 && t != kPassLatch && t != kSkip) P.counters[t] = 0;
+    if (t < kCounters && t != kPassLatch && t != kSkip) P.counters[t] = 0;
     if (t == 0) {
         if (first_chunk)
             P.counters[kPassLatch] =
@@ -945,9 +946,10 @@ __device__ __forceinline__ void start_path(const Frame &F, const Pool &P, uint32
     f3 rt = mk(F.cam.right[0], F.cam.right[1], F.cam.right[2]);
     f3 up = mk(F.cam.up[0], F.cam.up[1], F.cam.up[2]);
     f3 d = normalize(fwd + (rt * sx + up * sy));
+    state::quantise_dir(F, d.x, d.y, d.z);
     P.ray_o[s] = make_float4(F.cam.eye[0], F.cam.eye[1], F.cam.eye[2], INFINITY);
-    P.ray_d[s] = f4(d, 0.0f);
-    P.thr[s] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    state::store_dir(F, P, s, f4(d, 0.0f));
+    state::store_thr(F, P, s, make_float4(1.0f, 1.0f, 1.0f, 0.0f));
     P.rad[pid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     P.idx[s] = i;
 }
@@ -980,11 +982,11 @@ __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t c
         uint32_t i = base + threadIdx.x;
         if (i >= n) break;
         uint32_t slot = q[i];
-        float4 o = P.ray_o[slot], d = P.ray_d[slot];
+        float4 o = P.ray_o[slot], d = state::load_dir(F, P, slot);
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
         traverse<false, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
-        P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
+        state::store_hit(F, P, slot, make_float4(h.t, ubits(h.tri), h.b1, h.b2));
         nodes += h.nodes;
         tests += h.tests;
     }
@@ -1052,10 +1054,10 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
 {
     const uint32_t base_dim = 2 + 8 * (v - 1);
     o.alive = o.shadow = o.record = false;
-    float4 hv = P.hit[slot];
-    const float4 d4 = P.ray_d[slot];
+    float4 hv = state::load_hit(F, P, slot);
+    const float4 d4 = state::load_dir(F, P, slot);
     f3 d = xyz(d4);
-    float4 T4 = P.thr[slot];
+    float4 T4 = state::load_thr(F, P, slot);
     f3 T = xyz(T4);
     float prev_pdf = T4.w;
     f3 L = xyz(P.rad[rs]);
@@ -1242,6 +1244,11 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
             } else {
                 ok = bsdf_sample(m, nn, wo, u3, u4, u5, wi);
             }
+            if (ok && F.compress) {
+                // the direction the compressed state holds is the one sampled
+                state::quantise_dir(F, wi.x, wi.y, wi.z);
+                ok = dot(nn, wi) > 0.0f;
+            }
             if (ok) {
                 f3 fb;
                 float pb;
@@ -1265,8 +1272,8 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
                         }
                         if (o.alive) {
                             P.ray_o[slot] = f4(xo, INFINITY);
-                            P.ray_d[slot] = f4(wi, ubits(tri | (front ? 0u : 0x80000000u)));
-                            P.thr[slot] = f4(T, pb);
+                            state::store_dir(F, P, slot, f4(wi, ubits(tri | (front ? 0u : 0x80000000u))));
+                            state::store_thr(F, P, slot, f4(T, pb));
                             if (F.guide.record && v <= F.guide.max_vertex &&
                                 (F.guide.rec_thr == 0xffffffffu || rec_hash(idx, v) < F.guide.rec_thr)) {
                                 // training record: (final - (now + this vertex's NEE)) /
@@ -1341,7 +1348,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
 // regeneration) at vertex pv[s].y. The path's radiance stays at rad[id], so
 // the accumulation in pass order is unchanged and every path computes the
 // same bits as without regeneration. Iteration t traces and shades the queue
-// q_ext[t & 1] (counters[kRgQ0 + (t & 1)]) whatever the depth of each path in it.
+// q_ext[t & 1] (counters[rg_queue_count(t)]) whatever the depth of each path in it.
 
 // the first min(L, N) paths of the batch into slots [0, min(L, N))
 __global__ __launch_bounds__(kBlock) void k_regen_init(Frame F, Pool P, uint32_t npix, uint64_t pass0,
@@ -1370,10 +1377,10 @@ __global__ __launch_bounds__(kBlock) void k_regen_init(Frame F, Pool P, uint32_t
 // rendering: no guide, no training records)
 __global__ __launch_bounds__(kBlock, 4) void k_shade_regen(Frame F, Pool P, uint32_t t)
 {
-    const uint32_t n = P.counters[kRgQ0 + (t & 1)];
+    const uint32_t n = P.counters[rg_queue_count(t)];
     const uint32_t *q = P.q_ext[t & 1];
     uint32_t *qn = P.q_ext[(t + 1) & 1];
-    uint32_t *cn = &P.counters[kRgQ0 + ((t + 1) & 1)];
+    uint32_t *cn = &P.counters[rg_queue_count(t + 1)];
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const uint32_t i = base + threadIdx.x;
         const bool active = i < n;
@@ -1419,7 +1426,7 @@ __global__ __launch_bounds__(kBlock) void k_regen(Frame F, Pool P, uint32_t t, u
     const uint32_t N = npix * npass;
     const uint32_t k = regen_count(P, L, N);
     const uint32_t next = P.counters[kRgNext];
-    const uint32_t at = P.counters[kRgQ0 + ((t + 1) & 1)];
+    const uint32_t at = P.counters[rg_queue_count(t + 1)];
     uint32_t *qn = P.q_ext[(t + 1) & 1];
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < k; i += gridDim.x * kBlock) {
         const uint32_t s = P.q_dead[i];
@@ -1436,7 +1443,7 @@ __global__ __launch_bounds__(kBlock) void k_regen(Frame F, Pool P, uint32_t t, u
 __global__ void k_regen_commit(Pool P, uint32_t t, uint32_t N, uint32_t L)
 {
     const uint32_t k = regen_count(P, L, N);
-    const uint32_t ci = kRgQ0 + (t & 1), cn = kRgQ0 + ((t + 1) & 1);
+    const uint32_t ci = rg_queue_count(t), cn = rg_queue_count(t + 1);
     P.stats[0] += P.counters[ci];
     P.stats[1] += P.counters[kRgSh];
     if (k) {
@@ -1475,11 +1482,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0
         if (i >= n) break;
         const uint32_t slot = q[i];
         for (uint32_t v = v0;; ++v) {
-            const float4 o4 = P.ray_o[slot], d4 = P.ray_d[slot];
+            const float4 o4 = P.ray_o[slot], d4 = state::load_dir(F, P, slot);
             RayPre r = prepare(xyz(o4), xyz(d4));
             HitRec h;
             traverse<false, QN>(F, r, o4.w, h, stk + threadIdx.x, gstk, P.trav_threads);
-            P.hit[slot] = make_float4(h.t, ubits(h.tri), h.b1, h.b2);
+            state::store_hit(F, P, slot, make_float4(h.t, ubits(h.tri), h.b1, h.b2));
             en += h.nodes;
             et += h.tests;
             ShadeOut o;
@@ -1638,7 +1645,7 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
         if (prof) prof->end(kind, s);
     };
     timed(K_CLEAR, [&] {
-        hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(128), 0, s, P, F.abort_word, pix0 == 0 ? 1u : 0u);
+        hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(kCounters), 0, s, P, F.abort_word, pix0 == 0 ? 1u : 0u);
     });
     timed(K_GENERATE, [&] {
         hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
@@ -1678,13 +1685,13 @@ hipError_t launch_render_regen(const Frame &F, const Pool &P, uint32_t npix, uin
         launch();
         if (prof) prof->end(kind, s);
     };
-    timed(K_CLEAR, [&] { hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(128), 0, s, P, F.abort_word, 1u); });
+    timed(K_CLEAR, [&] { hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(kCounters), 0, s, P, F.abort_word, 1u); });
     timed(K_GENERATE, [&] {
         hipLaunchKernelGGL(k_regen_init, dim3(blocks_for(L, 1u << 30)), dim3(kBlock), 0, s, F, P, npix, pass0, npass, L);
     });
     const uint32_t g = blocks_for(L, 8192), gt = blocks_for(L, P.trav_threads / kBlock);
     auto iteration = [&](uint32_t t) {
-        const uint32_t c = kRgQ0 + (t & 1);
+        const uint32_t c = rg_queue_count(t);
         timed(K_TRACE, [&] {
             if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, c, t & 1);
             else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, c, t & 1);

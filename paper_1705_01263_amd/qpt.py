@@ -49,7 +49,8 @@ class qpt_bvh_stats(C.Structure):
 class qpt_render_opts(C.Structure):
     _fields_ = [("max_depth", C.c_uint32), ("rr", C.c_uint32), ("mode", C.c_uint32), ("scramble", C.c_uint32),
                 ("light_tree", C.c_uint32), ("single_stream", C.c_uint32), ("env_sampling", C.c_uint32),
-                ("filter", C.c_uint32), ("tail_depth", C.c_uint32), ("regen_paths", C.c_uint32)]
+                ("filter", C.c_uint32), ("tail_depth", C.c_uint32), ("regen_paths", C.c_uint32),
+                ("compress_state", C.c_uint32)]
 
 
 class qpt_stats(C.Structure):
@@ -254,9 +255,10 @@ class Context:
 
     def render_pass(self, first_pass: int, num_passes: int, max_depth: int, rr: bool = True, mode: int = 0,
                     scramble: bool = True, light_tree: bool = False, single_stream: bool = False,
-                    env_sampling: int = 0, gauss: bool = False, tail_depth: int = 0, regen_paths: int = 0) -> None:
+                    env_sampling: int = 0, gauss: bool = False, tail_depth: int = 0, regen_paths: int = 0,
+                    compress_state: bool = False) -> None:
         o = qpt_render_opts(max_depth, int(rr), mode, int(scramble), int(light_tree), int(single_stream),
-                            int(env_sampling), int(gauss), int(tail_depth), int(regen_paths))
+                            int(env_sampling), int(gauss), int(tail_depth), int(regen_paths), int(compress_state))
         self.check(self.L.qpt_render_pass(self.h, first_pass, num_passes, C.byref(o)), "qpt_render_pass")
 
     def readback(self, sum_rgb=None, counts=None, dst_is_device: bool = False) -> bool:
@@ -461,9 +463,10 @@ class Renderer:
         self.W, self.H = sc.width, sc.height
 
     def render(self, first_pass: int, num_passes: int, max_depth=None, rr=True, mode=0, scramble=True,
-               light_tree=False, single_stream=False, env_sampling=0, gauss=False, tail_depth=0, regen_paths=0):
+               light_tree=False, single_stream=False, env_sampling=0, gauss=False, tail_depth=0, regen_paths=0,
+               compress_state=False):
         self.ctx.render_pass(first_pass, num_passes, max_depth or self.sc.max_depth, rr, mode, scramble, light_tree,
-                             single_stream, env_sampling, gauss, tail_depth, regen_paths)
+                             single_stream, env_sampling, gauss, tail_depth, regen_paths, compress_state)
 
     def readback(self):
         """FP64 sums and counts; `self.aborted` tells whether rendering had been aborted."""
