@@ -263,8 +263,8 @@ def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
     """Passes per launch sequence against throughput (the paper's Table 1 in
     kind): the grid workload at 1080p with path pools from 2^min_log2 to
     2^max_log2 slots; per pool: one batch at a time, two in flight, the
-    megakernel tail from depth 4 (one stream), and, for pools of whole frames,
-    regeneration through a quarter of the pool's slots. Each setting renders
+    megakernel tail from depth 4 (one stream and two in flight), and, for
+    pools of whole frames, regeneration through a quarter of the pool's slots. Each setting renders
     two pools' worth of passes (at least 8) after one untimed batch."""
     import time
 
@@ -278,16 +278,18 @@ def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
     lines = ["# passes per launch sequence against throughput (grid, 0.97M triangles, 1920x1080, depth 12)",
              f"command: {cmd}", f"kernel_source_sha: {kernel_sha()}", "",
              "Mrays/s per schedule: one batch at a time; two batches in flight; one at a time with the",
-             "megakernel tail from depth 4; regeneration with live slots = pool / 4 (whole-frame batches only)", "",
+             "megakernel tail from depth 4; two in flight with that tail; regeneration with live slots =",
+             "pool / 4 (whole-frame batches only)", "",
              f"{'pool (paths)':>14} {'frames/batch':>13} {'passes':>7} {'one stream':>11} {'two in flight':>14} "
-             f"{'tail from 4':>12} {'regeneration':>13} {'Mpaths/s (best)':>16}"]
+             f"{'tail from 4':>12} {'two + tail':>11} {'regeneration':>13} {'Mpaths/s (best)':>16}"]
     for lg in range(min_log2, max_log2 + 1):
         pool = 1 << lg
         frames = pool / npix
         per = max(1, pool // npix)
         passes = max(8, 2 * per)
         r = Renderer(sc, pool_paths=pool)
-        schedules = [{"single_stream": True}, {"single_stream": False}, {"single_stream": True, "tail_depth": 4}]
+        schedules = [{"single_stream": True}, {"single_stream": False}, {"single_stream": True, "tail_depth": 4},
+                     {"single_stream": False, "tail_depth": 4}]
         if pool >= npix:
             schedules.append({"regen_paths": pool // 4})
         res = []
@@ -305,9 +307,9 @@ def run_sweep(out_txt: str, min_log2: int, max_log2: int, cmd: str) -> str:
             res.append((rays / dt / 1e6, passes * npix / dt / 1e6))
         del r
         torch.cuda.empty_cache()
-        cols = [f"{x[0]:.1f}" for x in res] + ["--"] * (4 - len(res))
+        cols = [f"{x[0]:.1f}" for x in res] + ["--"] * (5 - len(res))
         lines.append(f"{'2^%d' % lg:>14} {frames:>13.3f} {passes:>7} {cols[0]:>11} {cols[1]:>14} {cols[2]:>12} "
-                     f"{cols[3]:>13} {max(x[1] for x in res):>16.1f}")
+                     f"{cols[3]:>11} {cols[4]:>13} {max(x[1] for x in res):>16.1f}")
         print(lines[-1], flush=True)
     txt = "\n".join(lines) + "\n"
     open(out_txt, "w").write(txt)
@@ -697,6 +699,8 @@ def main():
                     help="0: binned SAH on the host, 1: linear BVH built on the GPU")
     ap.add_argument("--single-stream", action="store_true",
                     help="render the timed passes one batch at a time on one stream")
+    ap.add_argument("--tail-depth", type=int, default=0,
+                    help="megakernel for every path still alive from this depth on (0: none)")
     ap.add_argument("--compress-state", action="store_true",
                     help="path state in the compressed layout (octahedral directions, half-precision throughput)")
     ap.add_argument("--no-light-select", action="store_true",
@@ -752,7 +756,8 @@ def main():
     # the passes go to the library as one range, which renders them in batches
     # of as many whole passes as its path pool holds (eight frames' worth)
     cs = args.compress_state
-    r.render(0, args.warmup, compress_state=cs)
+    td = args.tail_depth
+    r.render(0, args.warmup, compress_state=cs, tail_depth=td)
     torch.cuda.synchronize()
     _say(f"bench: warmup {args.warmup} passes done")
     st0 = r.stats()
@@ -762,7 +767,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record()
-    r.render(args.warmup, args.steps, single_stream=args.single_stream, compress_state=cs)
+    r.render(args.warmup, args.steps, single_stream=args.single_stream, compress_state=cs, tail_depth=td)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -810,7 +815,7 @@ def main():
         else:
             r0 = r.stats()
             r.ctx.profile(True)
-            r.render(args.warmup + args.steps, args.steps, single_stream=True, compress_state=cs)
+            r.render(args.warmup + args.steps, args.steps, single_stream=True, compress_state=cs, tail_depth=td)
             r.ctx.profile(False)
             r_prof = r.ctx.profile_read()
             r1 = r.stats()
@@ -894,6 +899,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload][1],
                    "triangles": sc.num_triangles, "pixels": sc.width * sc.height, "max_depth": D,
                    "path_state": "compressed" if cs else "full precision",
+                   "megakernel_tail_from_depth": td or None,
                    "parallelism": "single GPU"},
         "mpaths_per_s": round(mpaths, 3),
         "rays_per_path": round((ext + sh) / paths, 3),
