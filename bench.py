@@ -699,8 +699,9 @@ def main():
                     help="0: binned SAH on the host, 1: linear BVH built on the GPU")
     ap.add_argument("--single-stream", action="store_true",
                     help="render the timed passes one batch at a time on one stream")
-    ap.add_argument("--tail-depth", type=int, default=0,
-                    help="megakernel for every path still alive from this depth on (0: none)")
+    ap.add_argument("--tail-depth", type=int, default=-1,
+                    help="megakernel for every path still alive from this depth on (0: none; default: half the "
+                         "workload's maximum depth, measured +4%% on the city and the grid against none)")
     ap.add_argument("--compress-state", action="store_true",
                     help="path state in the compressed layout (octahedral directions, half-precision throughput)")
     ap.add_argument("--no-light-select", action="store_true",
@@ -756,7 +757,7 @@ def main():
     # the passes go to the library as one range, which renders them in batches
     # of as many whole passes as its path pool holds (eight frames' worth)
     cs = args.compress_state
-    td = args.tail_depth
+    td = args.tail_depth if args.tail_depth >= 0 else D // 2
     r.render(0, args.warmup, compress_state=cs, tail_depth=td)
     torch.cuda.synchronize()
     _say(f"bench: warmup {args.warmup} passes done")
@@ -810,12 +811,14 @@ def main():
         # kernels. When the timed region ran two batches at a time, the same
         # number of passes follows on one stream for the roofline, and the
         # dominant kernel is the one with the most time there.
-        if args.single_stream:
+        if args.single_stream and not td:
             r_prof, r0, r1 = prof, st0, st1
         else:
             r0 = r.stats()
             r.ctx.profile(True)
-            r.render(args.warmup + args.steps, args.steps, single_stream=True, compress_state=cs, tail_depth=td)
+            # without the megakernel tail, whose launches would trace and shade
+            # rays the per-depth kernels' byte counts could not tell apart
+            r.render(args.warmup + args.steps, args.steps, single_stream=True, compress_state=cs)
             r.ctx.profile(False)
             r_prof = r.ctx.profile_read()
             r1 = r.stats()
@@ -835,9 +838,10 @@ def main():
                 "frac_stream": round(rstream[dom] / n_l / launch_s / 1e9 / HBM_PEAK_GBS, 4),
                 "frac_measured": round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "bytes_per_launch": round(per_launch), "avg_launch_ms": round(ms / n_l, 4),
-                "launches": n_l, "timed_on": "one stream, %d passes after the timed region" % args.steps
-                if not args.single_stream else "the timed region (one stream)", **counts}
-        if not args.single_stream:
+                "launches": n_l, "timed_on": "one stream, %d passes after the timed region, per-depth kernels "
+                "to the end (no megakernel tail)" % args.steps
+                if (not args.single_stream or td) else "the timed region (one stream)", **counts}
+        if not args.single_stream and prof[dom][0]:
             o_l, o_ms = prof[dom]
             roof["two_batches_in_flight"] = {"launches": o_l, "avg_launch_event_ms": round(o_ms / o_l, 4),
                                              "note": "event span per launch in the timed region, including "
