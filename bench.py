@@ -653,7 +653,7 @@ def summarize_main(argv):
     m = sub.add_parser("mfma")
     m.add_argument("pmc_dir")
     m.add_argument("out")
-    m.add_argument("--kernels", default="k_guide_eval,k_guide_train")
+    m.add_argument("--kernels", default="k_shade_guided,k_guide_train")
     m.add_argument("--cmd", required=True)
     c = sub.add_parser("counters")
     c.add_argument("out")

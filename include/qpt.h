@@ -144,7 +144,9 @@ typedef struct {
                                 to the end; k in 1..max_depth: from depth k on, one launch (a
                                 megakernel) takes every path still alive to its end, vertex after
                                 vertex in one thread, with the same per-vertex code (the same image
-                                bit for bit). Ignored while the guide samples or records. */
+                                bit for bit). While the guide samples or records, only past the
+                                guided vertices (k > the guide's max_vertex, not 0); ignored
+                                otherwise. */
     uint32_t regen_paths;    /* regeneration of terminated paths (Sec. 3.1.3): 0: every path of a batch
                                 has a state slot of its own from its camera ray to its end; n > 0: the
                                 batch's paths run through n state slots (64 <= n <= the workspace's
@@ -187,7 +189,8 @@ enum {
     QPT_K_SHADE = 3,      /* emission + MIS, NEE, BSDF sampling, roulette */
     QPT_K_SHADOW = 4,     /* occlusion of shadow rays */
     QPT_K_ACCUMULATE = 5, /* FP64 framebuffer and counts */
-    QPT_K_GUIDE_EVAL = 6, /* the network's mixture for every vertex (guiding on) */
+    QPT_K_SHADE_GUIDED = 6, /* shading of the guided vertices with the network's mixture computed
+                               in the same launch (guiding on) */
     QPT_K_GUIDE_TRAIN = 7,/* record finalisation, batch forward/backward, Adam */
     QPT_K_TAIL = 8,       /* the batch's remaining paths in one launch (render option tail_depth) */
     QPT_K_KINDS = 9

@@ -1,111 +1,27 @@
 // The learned proposal on gfx950: a 32-64-64-64-40 ReLU network in BF16 on
 // MFMA with FP32 accumulation, mapping an encoded hit position and outgoing
 // direction to an 8-lobe von Mises-Fisher mixture; trained online from the
-// renderer's own radiance samples with Adam on FP32 master weights.
-//
-// MFMA mapping (gfx950's v_mfma_f32_32x32x16_bf16, D = A x B + C, 32x32x16).
-// Operands are kept as 4-element fragments of 8-wide k-blocks s:
-//   A fragment = weights:     lane l holds W[k = 8s + 4(l/32) + e][o = 32t + l%32], e = 0..3
-//   B fragment = activations: lane l holds act[row = l%32][k = 8s + 4(l/32) + e]
-//   D:                        lane l, register v holds Z[o = 32t + 8(v/4) + 4(l/32) + v%4][row = l%32]
-// so registers 4s'..4s'+3 of the output tile s'/4 are exactly the B fragment
-// of block s' of the next layer: layers chain in registers. One 16-deep MFMA
-// takes fragments 2s and 2s + 1 of both operands as its 8 elements per lane:
-// the hardware pairs element e of A and B lanes for one reduction index, and
-// both operands map (lane half, e) to the same k = 16s + 8(e/4) + 4(l/32) +
-// e%4, so the product is the sum over the 16 k of the block in another order.
-// Each row (a path vertex or a training sample) is handled by the lane pair
-// (l, l + 32); a wave works on 32 rows at a time.
+// renderer's own radiance samples with Adam on FP32 master weights. The
+// operand layout of the MFMA tiles and the inference path are in
+// qpt_guide_mlp.h; this file holds training, the fragment builder and the
+// standalone inference kernel.
 #include <hip/hip_runtime.h>
 
 #include "qpt_guide_dev.h"
+#include "qpt_guide_mlp.h"
 #include "qpt_internal.h"
 #include "qpt_state_dev.h"
 
 namespace qpt {
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
-typedef short v8s __attribute__((ext_vector_type(8)));
-typedef short v2s __attribute__((ext_vector_type(2)));
-typedef float v16f __attribute__((ext_vector_type(16)));
+using namespace mlp;
 
-constexpr int kKS[4] = {4, 8, 8, 8};          // k-steps of 8 per layer
-constexpr int kN[4] = {64, 64, 64, 40};        // true output widths
-constexpr int kFB[4] = {0, 8, 24, 40};         // first forward fragment of each layer
 constexpr int kGB[4] = {0, 0, 16, 32};         // first transposed fragment (layers 1..3)
 constexpr int kOffW[4] = {0, 2112, 6272, 10432};
 constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
 constexpr int kTrainBlock = 256;               // 4 waves
 static_assert(kTrainBlock == 256, "the per-block weight and loss sums add four waves");
-
-// round to the nearest BF16, ties to even (v_cvt_pk_bf16_f32 on gfx950)
-__device__ __forceinline__ uint32_t bf16_rne(float f)
-{
-    return (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)f);
-}
-
-typedef float v2f __attribute__((ext_vector_type(2)));
-typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
-
-// four floats -> four BF16 (round to nearest even), two per conversion
-__device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
-{
-    uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
-    uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){c, d}, v2bf));
-    return __builtin_bit_cast(v4s, make_uint2(lo, hi));
-}
-
-__device__ __forceinline__ v4s as_v4s(uint2 u)
-{
-    v4s r;
-    r.x = (short)(u.x & 0xffff);
-    r.y = (short)(u.x >> 16);
-    r.z = (short)(u.y & 0xffff);
-    r.w = (short)(u.y >> 16);
-    return r;
-}
-
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ v8bf cat8(v4s lo, v4s hi)
-{
-    return __builtin_bit_cast(v8bf, (v8s){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
-}
-
-// D += A B over a 16-deep block given as two 8-deep fragments of each operand
-__device__ __forceinline__ v16f mfma2(v4s a0, v4s a1, v4s b0, v4s b1, v16f c)
-{
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(cat8(a0, a1), cat8(b0, b1), c, 0, 0, 0);
-}
-
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-
-// one layer: acc[t] = W_L^T x in + b for the two 32-wide output tiles
-template <int L>
-__device__ __forceinline__ void layer_fwd(const uint2 *sfrag, const float *sbias, const v4s *in, v16f *acc)
-{
-    const uint32_t lane = lane_id(), half = lane >> 5;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        // the bias is the accumulator's initial value (four float4 reads)
-        v16f c;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            float4 b = *(const float4 *)&sbias[L * 64 + 32 * t + 8 * q + 4 * half];
-            c[4 * q] = b.x;
-            c[4 * q + 1] = b.y;
-            c[4 * q + 2] = b.z;
-            c[4 * q + 3] = b.w;
-        }
-#pragma unroll
-        for (int s = 0; s < kKS[L]; s += 2) {
-            const uint2 *f = sfrag + (kFB[L] + t * kKS[L] + s) * 64 + lane;
-            c = mfma2(as_v4s(f[0]), as_v4s(f[64]), in[s], in[s + 1], c);
-        }
-        acc[t] = c;
-    }
-}
 
 // ReLU, its mask (bit 16t + v), and the BF16 B operands of the next layer
 __device__ __forceinline__ void relu_pack(const v16f *acc, v4s *out, uint32_t &mask)
@@ -360,8 +276,12 @@ __global__ void k_guide_frag(GuideTrain T, uint2 *pub_a, float *pub_ab, uint2 *p
         int L = f < 8 ? 0 : (f < 24 ? 1 : (f < 40 ? 2 : 3));
         int r = f - kFB[L], t = r / kKS[L], s = r % kKS[L];
         int k = 8 * s + 4 * half, o = 32 * t + lane % 32;
-        uint2 v = make_uint2(pack2(w_at(L, k, o), w_at(L, k + 1, o)), pack2(w_at(L, k + 2, o), w_at(L, k + 3, o)));
+        auto frag = [&](int oo) {
+            return make_uint2(pack2(w_at(L, k, oo), w_at(L, k + 1, oo)), pack2(w_at(L, k + 2, oo), w_at(L, k + 3, oo)));
+        };
+        uint2 v = frag(o);
         T.frag[i] = v;
+        if (L == 3) v = frag(pub_out_row(o));
         if (pub_a) pub_a[i] = v;
         if (pub_b) pub_b[i] = v;
     } else if (i < nf + nt) {
@@ -373,175 +293,50 @@ __global__ void k_guide_frag(GuideTrain T, uint2 *pub_a, float *pub_ab, uint2 *p
     } else if (i < nf + nt + 256) {
         uint32_t j = i - nf - nt;
         int L = j / 64, o = j % 64;
-        float b = o < kN[L] ? T.master[kOffB[L] + o] : 0.0f;
-        float bq = __uint_as_float(bf16_rne(b) << 16);
+        auto bias = [&](int oo) { return __uint_as_float(bf16_rne(oo < kN[L] ? T.master[kOffB[L] + oo] : 0.0f) << 16); };
+        float bq = bias(o);
         T.bias[j] = bq;
+        if (L == 3) bq = bias(pub_out_row(o));
         if (pub_ab) pub_ab[j] = bq;
         if (pub_bb) pub_bb[j] = bq;
     }
 }
 
-__device__ __forceinline__ void load_weights(const uint2 *frag, const float *bias, uint2 *sfrag, float *sbias)
-{
-    for (uint32_t i = threadIdx.x; i < kGuideFrags * 64; i += blockDim.x) sfrag[i] = frag[i];
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = bias[i];
-}
-
-// ReLU and BF16 operands without the mask (inference): round to BF16 first,
-// then a 16-bit signed max with 0 per half word (a BF16 value is negative
-// exactly when its sign bit is set, and rounding keeps the sign), the same
-// bits as rounding max(z, 0)
-__device__ __forceinline__ void relu_pack_infer(const v16f *acc, v4s *out)
-{
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int t = s / 4, b = 4 * (s % 4);
-        const uint2 u = __builtin_bit_cast(uint2, pack4(acc[t][b], acc[t][b + 1], acc[t][b + 2], acc[t][b + 3]));
-        const v2s lo = __builtin_elementwise_max(__builtin_bit_cast(v2s, u.x), (v2s){0, 0});
-        const v2s hi = __builtin_elementwise_max(__builtin_bit_cast(v2s, u.y), (v2s){0, 0});
-        out[s] = __builtin_bit_cast(v4s, make_uint2(__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)));
-    }
-}
-
-// inference forward: only the running B operands, no stored activations
-__device__ __forceinline__ void mlp_infer(const uint2 *sfrag, const float *sbias, const v4s *a0, v16f *out)
-{
-    v16f acc[2];
-    v4s cur[8];
-    layer_fwd<0>(sfrag, sbias, a0, acc);
-    relu_pack_infer(acc, cur);
-    layer_fwd<1>(sfrag, sbias, cur, acc);
-    relu_pack_infer(acc, cur);
-    layer_fwd<2>(sfrag, sbias, cur, acc);
-    relu_pack_infer(acc, cur);
-    layer_fwd<3>(sfrag, sbias, cur, out);
-}
-
-// the B operands of layer 0 for this lane's half of the row: half h needs
-// features 8s + 4h .. 8s + 4h + 3, i.e. octaves 2h and 2h + 1 of axis s
-// (s < 3), then the polar (h = 0) or azimuthal (h = 1) terms; the same
-// values as the full encoding, computed once per lane
-__device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const float *bmin, const float *binv, v4s *a0)
-{
-    const uint32_t h = lane_id() >> 5;
-    float xh[3] = {(x.x - bmin[0]) * binv[0], (x.y - bmin[1]) * binv[1], (x.z - bmin[2]) * binv[2]};
-    const float m0 = 0.5f * guide::kOct[2 * h], m1 = 0.5f * guide::kOct[2 * h + 1];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float s0, c0, s1, c1;
-        guide::sincos_rev(m0 * xh[a], &s0, &c0);
-        guide::sincos_rev(m1 * xh[a], &s1, &c1);
-        a0[a] = pack4(s0, c0, s1, c1);
-    }
-    // lane half 0: th (one atan2 of (sin th, cos th)); half 1: ph -- one
-    // atan2 per lane with lane-dependent arguments, no divergence
-    float y = fminf(1.0f, fmaxf(-1.0f, wo.y));
-    float ay = h ? wo.x : sqrtf(fmaxf(0.0f, 1.0f - y * y));
-    float ax = h ? -wo.z : y;
-    float ang = guide::atan2_enc(ay, ax);
-    if (h && ang < 0.0f) ang += 2.0f * guide::kPiF;
-    float r1 = ang * (h ? 1.0f / (2.0f * guide::kPiF) : 1.0f / guide::kPiF);
-    float r0 = h ? r1 : 0.5f * r1;
-    r1 = h ? 2.0f * r1 : r1;
-    float s0, c0, s1, c1;
-    guide::sincos_rev(r0, &s0, &c0);
-    guide::sincos_rev(r1, &s1, &c1);
-    a0[3] = pack4(s0, c0, s1, c1);
-}
-
-// rows of the inference kernel: the extension queue of depth v (a row is a
-// path slot whose ray hit a triangle), or explicit arrays for parity checks
+// rows of the inference parity hook: n positions and outgoing directions (n x 3
+// each) and n output rows of 10 uint4 (the first 5 hold the packed mixture)
 struct EvalSrc {
-    bool debug;
-    uint32_t v;              // queue: depth
-    const float *x, *wo;     // debug: n x 3 positions and outgoing directions
-    uint32_t n;              // debug: rows
-    uint4 *out;              // debug: n rows of 10 uint4 (the first 5 hold the packed mixture)
+    const float *x, *wo;
+    uint32_t n;
+    uint4 *out;
 };
 
 // mixture of every row: each lane of a pair encodes its half of the inputs
 // and decodes four of the eight lobes
-__global__ __launch_bounds__(256) void k_guide_eval(Frame F, Pool P, EvalSrc src)
+// the mixture of every row (parity hook: explicit positions and directions)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_guide_eval(Frame F, EvalSrc src)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
     __shared__ __align__(16) float sbias[256];
-    const uint32_t n = src.debug ? src.n : P.counters[src.v];
-    // the grid is sized for the largest queue: blocks without rows leave
-    // before staging the 28 KB of weights (uniform per block, so no barrier
-    // is skipped by part of a block)
-    if ((size_t)blockIdx.x * (blockDim.x / 2) >= n) return;
+    const uint32_t n = src.n;
+    if ((size_t)blockIdx.x * (blockDim.x / 2) >= n) return;  // uniform per block
     load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
     __syncthreads();
-    const uint32_t *q = P.q_ext[src.v & 1];
-    uint4 *mix_out = src.debug ? src.out : F.guide.mix;
-    const uint32_t stride = src.debug ? 2 * guide::kMixU4 : guide::kMixU4;
-    const uint32_t lane = lane_id(), h = lane >> 5;
+    const uint32_t lane = lane_id();
     const uint32_t wave = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     const uint32_t waves = gridDim.x * (blockDim.x / 64);
     for (uint32_t base = wave * 32; base < n; base += waves * 32) {
         // keeps the weight reads inside the loop: hoisted, they would pin
         // ~240 registers and leave one wave per SIMD
         asm volatile("" ::: "memory");
-        uint32_t i = base + (lane & 31);
-        bool valid = i < n;
-        uint32_t slot = 0;
+        const uint32_t i = base + (lane & 31);
+        const bool valid = i < n;
         guide::V3 x = {0.0f, 0.0f, 0.0f}, wo = {0.0f, 1.0f, 0.0f};
-        if (valid && src.debug) {
-            slot = i;
+        if (valid) {
             x = {src.x[3 * (size_t)i], src.x[3 * (size_t)i + 1], src.x[3 * (size_t)i + 2]};
             wo = {src.wo[3 * (size_t)i], src.wo[3 * (size_t)i + 1], src.wo[3 * (size_t)i + 2]};
-        } else if (valid) {
-            slot = q[i];
-            float4 hv = state::load_hit(F, P, slot);
-            uint32_t tri = __float_as_uint(hv.y);
-            valid = tri != kNoHit;
-            if (valid) {
-                const Tri tr = F.tris[tri];
-                float4 d = state::load_dir(F, P, slot);
-                x = {tr.v0.x + ((tr.v1.x - tr.v0.x) * hv.z + (tr.v2.x - tr.v0.x) * hv.w),
-                     tr.v0.y + ((tr.v1.y - tr.v0.y) * hv.z + (tr.v2.y - tr.v0.y) * hv.w),
-                     tr.v0.z + ((tr.v1.z - tr.v0.z) * hv.z + (tr.v2.z - tr.v0.z) * hv.w)};
-                wo = {-d.x, -d.y, -d.z};
-            }
         }
-        v4s a0[4];
-        encode_half(x, wo, F.guide.bmin, F.guide.binv, a0);
-        v16f out[2];
-        mlp_infer(sfrag, sbias, a0, out);
-        float o[40];
-        gather40(out, o);
-        if (valid) {
-            float mx = o[0];
-#pragma unroll
-            for (int k = 1; k < 8; ++k) mx = fmaxf(mx, o[5 * k]);
-            float e[8], se = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                e[k] = __expf(o[5 * k] - mx);
-                se += e[k];
-            }
-            float inv = 1.0f / se;
-            uint4 *dst = mix_out + (size_t)slot * stride;
-            uint32_t q[8];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float ox = h ? o[5 * (4 + j) + 1] : o[5 * j + 1];
-                float oy = h ? o[5 * (4 + j) + 2] : o[5 * j + 2];
-                float oz = h ? o[5 * (4 + j) + 3] : o[5 * j + 3];
-                float ok = h ? o[5 * (4 + j) + 4] : o[5 * j + 4];
-                float in = rsqrtf(fmaxf(ox * ox + oy * oy + oz * oz, 1e-24f));
-                float sp = ok > 20.0f ? ok : __logf(1.0f + __expf(ok));
-                float kap = fminf(sp + 1e-3f, 1e4f);
-                q[2 * j] = guide::pack_h2(ox * in, oy * in);
-                q[2 * j + 1] = guide::pack_h2(oz * in, kap);
-            }
-            // lobes 4h .. 4h + 3 are uint4 2h and 2h + 1; weights 4h .. 4h + 3 half of uint4 4
-            dst[2 * h] = make_uint4(q[0], q[1], q[2], q[3]);
-            dst[2 * h + 1] = make_uint4(q[4], q[5], q[6], q[7]);
-            uint2 wq = h ? make_uint2(guide::pack_h2(e[4] * inv, e[5] * inv), guide::pack_h2(e[6] * inv, e[7] * inv))
-                         : make_uint2(guide::pack_h2(e[0] * inv, e[1] * inv), guide::pack_h2(e[2] * inv, e[3] * inv));
-            ((uint2 *)(dst + 4))[h] = wq;
-        }
+        infer_pair(sfrag, sbias, x, wo, F.guide.bmin, F.guide.binv, valid,
+                   src.out + (size_t)(valid ? i : 0) * 2 * guide::kMixU4);
     }
 }
 
@@ -760,7 +555,7 @@ __global__ void k_fill0(float *p, uint32_t n)
 
 __global__ void k_fill_u32_1(uint32_t *p) { *p = 0u; }
 
-// forward on given features (parity hook)
+// forward on given features (parity hook; the training fragments, network order)
 __global__ __launch_bounds__(256) void k_guide_fwd_debug(Frame F, const float *x, uint32_t n, float *out)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
@@ -824,13 +619,6 @@ hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s, uint2 *pub_a, f
     return hipGetLastError();
 }
 
-hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s)
-{
-    EvalSrc src{false, v, nullptr, nullptr, 0u, nullptr};
-    hipLaunchKernelGGL(k_guide_eval, dim3(grid), dim3(256), 0, s, f, pool, src);
-    return hipGetLastError();
-}
-
 // packed mixtures (first 80 bytes of each 160-byte row) -> the decoded FP32
 // values the renderer uses, in place: 8 x (mu.xyz, kappa), then 8 weights
 __global__ void k_mix_unpack_debug(uint4 *rows, uint32_t n)
@@ -851,8 +639,8 @@ __global__ void k_mix_unpack_debug(uint4 *rows, uint32_t n)
 hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
                                    float *mix, hipStream_t s)
 {
-    EvalSrc src{true, 0u, x, wo, n, (uint4 *)mix};
-    hipLaunchKernelGGL(k_guide_eval, dim3(nblocks(((size_t)n + 31) / 32, 4, 2048)), dim3(256), 0, s, f, pool, src);
+    EvalSrc src{x, wo, n, (uint4 *)mix};
+    hipLaunchKernelGGL(k_guide_eval, dim3(nblocks(((size_t)n + 31) / 32, 4, 2048)), dim3(256), 0, s, f, src);
     hipLaunchKernelGGL(k_mix_unpack_debug, dim3(nblocks(n, 256, 1u << 20)), dim3(256), 0, s, (uint4 *)mix, n);
     return hipGetLastError();
 }

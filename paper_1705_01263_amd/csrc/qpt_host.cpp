@@ -274,7 +274,7 @@ struct Layout {
     } lane[2];
     size_t stats;
     size_t fb_sum, fb_count;
-    size_t g_frag, g_fragT, g_bias, g_mix[2], g_rec[2], g_ring, g_ring_head, g_master, g_m, g_v, g_partial, g_scalars;
+    size_t g_frag, g_fragT, g_bias, g_rec[2], g_ring, g_ring_head, g_master, g_m, g_v, g_partial, g_scalars;
     size_t g_pub_frag[2], g_pub_bias[2];
     size_t total;
 };
@@ -401,7 +401,6 @@ struct qpt_ctx {
     hipEvent_t ev_regen[2] = {nullptr, nullptr};  // regeneration: a chunk of iterations has copied its paths left
     uint32_t *abort_host = nullptr;              // pinned, mapped: the caller's stop request (word 0)
     uint32_t *abort_dev = nullptr;               // its device address
-    uint4 *lane_mix[2] = {nullptr, nullptr};     // per lane: the guide's mixture per slot
     float4 *lane_rec[2] = {nullptr, nullptr};    // per lane: training records
     uint64_t batches = 0;
     // the most recent batch (for the record hook): its lane, pixel range and passes
@@ -967,17 +966,14 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
     L.stats = take(8 * 8);
     L.fb_sum = take((size_t)c->W * c->H * 3 * 8);
     L.fb_count = take((size_t)c->W * c->H * 4);
-    // learned proposal: weights, per-slot mixtures, training records, the
+    // learned proposal: weights, training records, the
     // replay ring and optimiser state; the renderer's copy of the weights is
     // double-buffered so a training step overlaps the next batch
     size_t rec_cap = guide_rec_cap(cap);
     L.g_frag = take(kGuideFrags * 64 * 8);
     L.g_fragT = take(kGuideFragsT * 64 * 8);
     L.g_bias = take(256 * 4);
-    for (int k = 0; k < 2; ++k) {   // per lane: mixtures of its slots, its training records
-        L.g_mix[k] = take((size_t)cap * 5 * 16);
-        L.g_rec[k] = take(rec_cap * kRecF4 * 16);
-    }
+    for (int k = 0; k < 2; ++k) L.g_rec[k] = take(rec_cap * kRecF4 * 16);  // per lane: its training records
     L.g_ring = take((size_t)kGuideRing * kRingF4 * 16);
     L.g_ring_head = take(4);
     for (int k = 0; k < 2; ++k) {
@@ -1643,9 +1639,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     G.frag = T.frag;
     G.fragT = T.fragT;
     G.bias = T.bias;
-    G.mix = (uint4 *)(w + L.g_mix[0]);
     for (int k = 0; k < 2; ++k) {
-        c->lane_mix[k] = (uint4 *)(w + L.g_mix[k]);
         c->lane_rec[k] = (float4 *)(w + L.g_rec[k]);
     }
     for (int a = 0; a < 3; ++a) {
@@ -1763,7 +1757,6 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         // the lane's path pool and training records are free again once the
         // training stream has finalised the lane's previous batch
         if (c->fin_pending[lane]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_fin[lane], 0));
-        f.guide.mix = c->lane_mix[lane_b ? 1 : 0];
         f.guide.rec = c->lane_rec[lane_b ? 1 : 0];
         f.guide.rec_count = P.counters + 127;
         bool active = c->gopts.alpha > 0.0f && c->guide_steps >= c->gopts.warmup_steps;
@@ -2065,7 +2058,11 @@ int qpt_guide_debug_eval(qpt_ctx *c, const float *x, const float *wo, uint32_t n
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
     HIP_TRY(c, join_train(c));
-    HIP_TRY(c, launch_guide_debug_eval(c->frame, c->pool, x, wo, n, mix, c->stream));
+    // the renderer's copy of the newest weights (its output order, see k_guide_frag)
+    Frame f = c->frame;
+    f.guide.frag = c->pub_frag[c->last_buf];
+    f.guide.bias = c->pub_bias[c->last_buf];
+    HIP_TRY(c, launch_guide_debug_eval(f, c->pool, x, wo, n, mix, c->stream));
     return QPT_OK;
 }
 

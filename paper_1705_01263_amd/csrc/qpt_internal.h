@@ -12,6 +12,9 @@ constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
 constexpr uint32_t kShortStack = 16;     // traversal stack entries per ray kept in LDS
 constexpr uint32_t kMaxTreeDepth = 32;   // depth limit of the binary build tree
 constexpr uint32_t kTravBlocksPerCU = 16; // traversal grid: 16 blocks of 4 waves per CU, twice what is resident
+constexpr uint32_t kShadeGuidedBlock = 512;     // guided shading: 8 waves share the weights in LDS
+constexpr uint32_t kShadeGuidedBlocksPerCU = 2;  // 69 KB of LDS per block (weights, 512 mixtures)
+constexpr uint32_t kShadeGuidedGridPerCU = 8;    // its grid: blocks per CU
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
 constexpr uint32_t kNoHit = 0xffffffffu;
 // per-lane counter words beyond the queue counts: the abort decision latched
@@ -115,7 +118,6 @@ struct GuideDev {
     const uint2 *frag;       // kGuideFrags * 64: 4 bf16 per lane (MFMA A operands)
     const uint2 *fragT;      // kGuideFragsT * 64
     const float *bias;       // 4 x 64 (BF16-rounded values, layer 3 zero-padded)
-    uint4 *mix;              // per path slot: the FP16 mixture, 5 uint4 (see unpack_mix)
     float bmin[3], binv[3];  // scene box for the position encoding: min corner, 1 / extent
     uint32_t alpha_thr;      // guide iff sample bits < alpha_thr (0: BSDF sampling only)
     float alpha;             // alpha_thr / 2^32
@@ -213,7 +215,7 @@ struct Pool {
 };
 
 // kernel kinds timed by the optional profiler
-enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMULATE, K_GUIDE_EVAL, K_GUIDE_TRAIN,
+enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMULATE, K_SHADE_GUIDED, K_GUIDE_TRAIN,
                   K_TAIL, K_KINDS };
 
 // brackets every kernel launch of a batch with stream events when set
@@ -272,7 +274,6 @@ hipError_t launch_accumulate(const Frame &f, const Pool &pool, uint32_t pix0, ui
 // guide launchers (qpt_guide.hip)
 hipError_t launch_guide_frag(const GuideTrain &T, hipStream_t s, uint2 *pub_a, float *pub_ab, uint2 *pub_b,
                              float *pub_bb);
-hipError_t launch_guide_eval(const Frame &f, const Pool &pool, uint32_t v, uint32_t grid, hipStream_t s);
 hipError_t launch_guide_debug_eval(const Frame &f, const Pool &pool, const float *x, const float *wo, uint32_t n,
                                    float *mix, hipStream_t s);
 hipError_t launch_guide_finalize(const Frame &f, const Pool &pool, const GuideTrain &T, hipStream_t s);

@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "qpt_guide_dev.h"
+#include "qpt_guide_mlp.h"
 #include "qpt_internal.h"
 #include "qpt_state_dev.h"
 
@@ -1048,9 +1049,10 @@ struct ShadeOut {
 // roulette at vertex v of the path in `slot` (its hit already traced): updates
 // the slot's ray and throughput and the path's radiance rad[rs] (rs = the
 // path's id in the batch; the NEE contribution stays pending in o.sh_c until
-// its shadow ray is traced)
+// its shadow ray is traced). mix_row: the vertex's packed mixture (a guided
+// vertex), or null (BSDF sampling alone)
 __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32_t v, uint32_t slot, uint32_t rs,
-                                           ShadeOut &o)
+                                           ShadeOut &o, const uint4 *mix_row = nullptr)
 {
     const uint32_t base_dim = 2 + 8 * (v - 1);
     o.alive = o.shadow = o.record = false;
@@ -1112,10 +1114,11 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
             f3 wo = d * -1.0f;
             f3 xo = offset_ray(x, nn);
             uint64_t idx = P.idx[slot];
-            // learned proposal: this vertex's mixture (alpha = 0 leaves plain BSDF sampling)
-            const bool guided = F.guide.alpha_thr != 0u && v <= F.guide.max_vertex;
+            // learned proposal: this vertex's mixture (given only at the guided
+            // vertices, and only with alpha > 0)
+            const bool guided = mix_row != nullptr;
             guide::MixRef mix{nullptr, 0.0f};
-            if (guided) mix = guide::mix_ref(F.guide.mix + (size_t)slot * guide::kMixU4);
+            if (guided) mix = guide::mix_ref(mix_row);
             const float alpha = F.guide.alpha;
             // next-event estimation
             if (F.mode != 1 && (F.num_emit || F.env_w)) {
@@ -1297,6 +1300,44 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
 
 // emission with MIS, next-event estimation, BSDF sampling and roulette at depth v
 // (four blocks per CU: at most 128 VGPRs, four waves per SIMD, no spills)
+// a shaded vertex's outputs: its training record, its shadow ray and its
+// place in the next depth's queue (wave-aggregated appends)
+__device__ __forceinline__ void shade_emit(const Frame &F, const Pool &P, uint32_t v, uint32_t slot, ShadeOut &o,
+                                           uint32_t *qn)
+{
+    uint32_t rec_idx = kNoHit;
+    if (F.guide.record) {
+        uint32_t pr = wave_append(&P.counters[127], o.record);
+        if (o.record && pr < F.guide.rec_cap) {
+            float4 *r = F.guide.rec + (size_t)pr * kRecF4;
+            r[0] = o.rec[0];
+            r[1] = o.rec[1];
+            r[2] = o.rec[2];
+            r[3] = o.rec[3];
+            r[4] = o.rec[4];
+            r[5] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            rec_idx = pr;
+        }
+    }
+    uint32_t ps = wave_append(&P.counters[64 + v], o.shadow);
+    if (o.shadow) {
+        o.sh_c.w = ubits(rec_idx);
+        P.sh_o[ps] = o.sh_o;
+        P.sh_d[ps] = o.sh_d;
+        P.sh_c[ps] = o.sh_c;
+    }
+    uint32_t pe = wave_append(&P.counters[v + 1], o.alive);
+    if (o.alive) qn[pe] = slot;
+}
+
+__device__ __forceinline__ void shade_out_init(ShadeOut &o)
+{
+    // zero-initialised: the outputs stay in registers (no spills at 128 VGPRs)
+    o.alive = o.shadow = o.record = false;
+    o.sh_o = o.sh_d = o.sh_c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v)
 {
     const uint32_t n = P.counters[v];
@@ -1304,40 +1345,73 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
     uint32_t *qn = P.q_ext[(v + 1) & 1];
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t i = base + threadIdx.x;
-        bool active = i < n;
         uint32_t slot = 0;
-        // zero-initialised: the outputs stay in registers (no spills at 128 VGPRs)
         ShadeOut o;
-        o.alive = o.shadow = o.record = false;
-        o.sh_o = o.sh_d = o.sh_c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (active) {
+        shade_out_init(o);
+        if (i < n) {
             slot = q[i];
             shade_slot(F, P, v, slot, slot, o);
         }
-        uint32_t rec_idx = kNoHit;
-        if (F.guide.record) {
-            uint32_t pr = wave_append(&P.counters[127], o.record);
-            if (o.record && pr < F.guide.rec_cap) {
-                float4 *r = F.guide.rec + (size_t)pr * kRecF4;
-                r[0] = o.rec[0];
-                r[1] = o.rec[1];
-                r[2] = o.rec[2];
-                r[3] = o.rec[3];
-                r[4] = o.rec[4];
-                r[5] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                rec_idx = pr;
+        shade_emit(F, P, v, slot, o, qn);
+    }
+}
+
+// Shading of a guided vertex with the network's inference in the same
+// launch: the block's weights in LDS, each wave's 64 mixtures computed on the
+// matrix cores into LDS (packed, 80 bytes a row) and read there by the lane
+// that shades the row -- the mixture never goes through HBM, and the hit and
+// direction loads serve both. Blocks of 8 waves share one copy of the weights
+// (69 KB of LDS a block, two blocks and 16 waves per CU, as many as the
+// plain shading kernel keeps). A wave touches only its own 64 rows of the
+// mixtures, so after the weights are staged the waves synchronise with
+// themselves only. Blocks without rows leave before staging the weights
+// (uniform per block, so the one block barrier is reached by all).
+__global__ __launch_bounds__(kShadeGuidedBlock, kShadeGuidedBlocksPerCU) void k_shade_guided(Frame F, Pool P, uint32_t v)
+{
+    __shared__ uint2 sfrag[kGuideFrags * 64];
+    __shared__ __align__(16) float sbias[256];
+    __shared__ uint4 smix[kShadeGuidedBlock * guide::kMixU4];
+    const uint32_t n = P.counters[v];
+    if ((size_t)blockIdx.x * kShadeGuidedBlock >= n) return;
+    mlp::load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
+    __syncthreads();
+    const uint32_t *q = P.q_ext[v & 1];
+    uint32_t *qn = P.q_ext[(v + 1) & 1];
+    uint4 *wave_rows = smix + (threadIdx.x & ~63u) * guide::kMixU4;
+    // the wave's rows are written by the lane pairs and read by their own
+    // lanes: ordered within the wave (fences at wavefront scope and a wave
+    // barrier, also before the next pass overwrites them)
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (uint32_t base = blockIdx.x * kShadeGuidedBlock; base < n; base += gridDim.x * kShadeGuidedBlock) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t slot = 0;
+        bool valid = false;
+        guide::V3 x = {0.0f, 0.0f, 0.0f}, wo = {0.0f, 1.0f, 0.0f};
+        if (i < n) {
+            slot = q[i];
+            const float4 hv = state::load_hit(F, P, slot);
+            const uint32_t tri = fbits(hv.y);
+            if (tri != kNoHit) {
+                const Tri tr = F.tris[tri];
+                const float4 d = state::load_dir(F, P, slot);
+                x = {tr.v0.x + ((tr.v1.x - tr.v0.x) * hv.z + (tr.v2.x - tr.v0.x) * hv.w),
+                     tr.v0.y + ((tr.v1.y - tr.v0.y) * hv.z + (tr.v2.y - tr.v0.y) * hv.w),
+                     tr.v0.z + ((tr.v1.z - tr.v0.z) * hv.z + (tr.v2.z - tr.v0.z) * hv.w)};
+                wo = {-d.x, -d.y, -d.z};
+                valid = true;
             }
         }
-        uint32_t ps = wave_append(&P.counters[64 + v], o.shadow);
-        if (o.shadow) {
-            o.sh_c.w = ubits(rec_idx);
-            P.sh_o[ps] = o.sh_o;
-            P.sh_d[ps] = o.sh_d;
-            P.sh_c[ps] = o.sh_c;
-        }
-        uint32_t pe = wave_append(&P.counters[v + 1], o.alive);
-        if (o.alive) qn[pe] = slot;
+        wave_sync();
+        mlp::infer_wave64(sfrag, sbias, x, wo, valid, F.guide.bmin, F.guide.binv, wave_rows);
+        wave_sync();
+        ShadeOut o;
+        shade_out_init(o);
+        if (i < n) shade_slot(F, P, v, slot, slot, o, smix + threadIdx.x * guide::kMixU4);
+        shade_emit(F, P, v, slot, o, qn);
     }
 }
 
@@ -1461,8 +1535,8 @@ __global__ void k_regen_commit(Pool P, uint32_t t, uint32_t N, uint32_t L)
 // thread -- closest hit, shading, its shadow ray, depth after depth -- with
 // the same device code as the per-depth kernels, so its radiance is the same
 // bit for bit. Rays of deeper vertices are added to the per-depth counters as
-// the per-depth kernels would count them. Not for guided rendering (records
-// and the per-vertex mixtures live in the per-depth kernels).
+// the per-depth kernels would count them. With the guide on it starts past
+// the guided vertices (records and mixtures stay in the per-depth kernels).
 template <bool QN>
 __global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0)
 {
@@ -1652,7 +1726,17 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
     });
     uint32_t g = blocks_for(n, 8192);
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
-    const bool tail_ok = F.tail_depth >= 1 && !F.guide.alpha_thr && !F.guide.record;
+    // guided shading: four times the blocks resident at once, each staging
+    // the weights once (a grid of only the resident blocks balances badly
+    // when the other batch in flight holds part of the GPU)
+    uint32_t gg = (uint32_t)std::min<size_t>(((size_t)n + kShadeGuidedBlock - 1) / kShadeGuidedBlock,
+                                             P.trav_threads / kBlock / kTravBlocksPerCU * kShadeGuidedGridPerCU);
+    // with the guide on, the tail may start only past its last guided
+    // vertex: the mixtures and the training records belong to the per-depth
+    // kernels, while the tail's vertices sample the BSDF alone (their MIS
+    // reads the previous vertex's sampling density from the path state)
+    const bool guide_on = F.guide.alpha_thr || F.guide.record;
+    const bool tail_ok = F.tail_depth >= 1 && (!guide_on || F.tail_depth > F.guide.max_vertex);
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
         if (tail_ok && v == F.tail_depth) {
             // the rest of the batch's paths in one launch (traversal grid, four blocks per CU resident)
@@ -1666,8 +1750,10 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
             if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v, v & 1);
             else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v, v & 1);
         });
-        if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex) timed(K_GUIDE_EVAL, [&] { (void)launch_guide_eval(F, P, v, gt, s); });  // errors surface below
-        timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
+        if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex)
+            timed(K_SHADE_GUIDED, [&] { hipLaunchKernelGGL(k_shade_guided, dim3(gg), dim3(kShadeGuidedBlock), 0, s, F, P, v); });
+        else
+            timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] {
             if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
             else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);

@@ -68,7 +68,7 @@ class qpt_kernel_time(C.Structure):
     _fields_ = [("launches", C.c_uint32), ("reserved", C.c_uint32), ("total_ms", C.c_double)]
 
 
-KERNEL_KINDS = ["clear", "generate", "trace", "shade", "shadow", "accumulate", "guide_eval", "guide_train", "tail"]
+KERNEL_KINDS = ["clear", "generate", "trace", "shade", "shadow", "accumulate", "shade_guided", "guide_train", "tail"]
 GUIDE_PARAMS = 13032
 
 
