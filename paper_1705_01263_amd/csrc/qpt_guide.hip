@@ -92,72 +92,71 @@ __device__ __forceinline__ void gather40(const v16f *acc, float *o)
     }
 }
 
-// back from a row's 40-vector to the lane's D-layout registers (padding 0)
-__device__ __forceinline__ void scatter40(const float *d, v16f *dz)
-{
-    const bool hi = lane_id() >= 32;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        int f = 8 * (v / 4) + (v % 4);
-        dz[0][v] = hi ? d[f + 4] : d[f];
-    }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) dz[1][v] = v < 4 ? (hi ? d[36 + v] : d[32 + v]) : 0.0f;
-}
-
 // Gradient of -w log q(w_dir) w.r.t. the 40 outputs, through the decode,
 // with lobe responsibilities g_k = pi_k f_k / q (stable in log space):
 //   logit: -w (g_k - pi_k); mu_raw: -w g_k kappa (w - (mu.w) mu) / |mu_raw|;
 //   kappa_raw: -w g_k (1/kappa - 2/expm1(2 kappa) + mu.w - 1) sigmoid(kappa_raw)
-// (zero where kappa is clamped). Returns -w log q in `loss`.
-__device__ void row_loss_grad(const float *o, guide::V3 wd, float w, float *d, float &loss)
+// (zero where kappa is clamped), and -w log q in `loss`. The outputs are in
+// the fragments' order (frag_out_row): lane half h holds the five parameters
+// of lobes 4h + j in out[0][j], out[0][4 + j], out[0][8 + j], out[0][12 + j]
+// and out[1][j], computes their gradient in the same registers of dz (the
+// padding rows get 0), and exchanges only the softmax's and the mixture's
+// normalisers with its partner lane. With e = expm1(-2 kappa), the vMF
+// normaliser kappa / (2 pi (1 - exp(-2 kappa))) is kappa / (2 pi (-e)) and
+// 2 / expm1(2 kappa) = -2 (1 + e) / e: one expm1 per lobe, accurate for the
+// smallest kappa (1e-3), where the two terms of the kappa gradient cancel.
+__device__ __forceinline__ void pair_loss_grad(const v16f *out, guide::V3 wd, float w, v16f *dz, float &loss)
 {
-    float mx = o[0];
-#pragma unroll
-    for (int k = 1; k < 8; ++k) mx = fmaxf(mx, o[5 * k]);
+    float mx = fmaxf(fmaxf(out[0][0], out[0][1]), fmaxf(out[0][2], out[0][3]));
+    mx = fmaxf(mx, __shfl_xor(mx, 32));
     float se = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) se += expf(o[5 * k] - mx);
-    float lse = logf(se);
-    float lf[8], pi[8], kap[8], mn[8], cw[8], mu[8][3];
-    bool clamped[8];
+    for (int j = 0; j < 4; ++j) se += __expf(out[0][j] - mx);
+    se += __shfl_xor(se, 32);
+    const float lse = __logf(se);
+    float lp[4], kap[4], inv_mn[4], cw[4], mu[4][3], em[4], lf[4];
+    bool clamped[4];
     float lmax = -INFINITY;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        float lp = o[5 * k] - mx - lse;
-        pi[k] = expf(lp);
-        float x = o[5 * k + 1], y = o[5 * k + 2], z = o[5 * k + 3];
-        mn[k] = fmaxf(sqrtf(x * x + y * y + z * z), 1e-12f);
-        mu[k][0] = x / mn[k];
-        mu[k][1] = y / mn[k];
-        mu[k][2] = z / mn[k];
-        float kk = guide::softplus(o[5 * k + 4]) + 1e-3f;
-        clamped[k] = kk >= 1e4f;
-        kap[k] = fminf(kk, 1e4f);
-        cw[k] = mu[k][0] * wd.x + mu[k][1] * wd.y + mu[k][2] * wd.z;
-        lf[k] = lp + logf(kap[k]) - logf(2.0f * guide::kPiF * -expm1f(-2.0f * kap[k])) + kap[k] * (cw[k] - 1.0f);
-        lmax = fmaxf(lmax, lf[k]);
+    for (int j = 0; j < 4; ++j) {
+        lp[j] = out[0][j] - mx - lse;
+        const float x = out[0][4 + j], y = out[0][8 + j], z = out[0][12 + j];
+        inv_mn[j] = 1.0f / fmaxf(sqrtf(x * x + y * y + z * z), 1e-12f);
+        mu[j][0] = x * inv_mn[j];
+        mu[j][1] = y * inv_mn[j];
+        mu[j][2] = z * inv_mn[j];
+        const float kk = guide::softplus(out[1][j]) + 1e-3f;
+        clamped[j] = kk >= 1e4f;
+        kap[j] = fminf(kk, 1e4f);
+        cw[j] = mu[j][0] * wd.x + mu[j][1] * wd.y + mu[j][2] * wd.z;
+        em[j] = expm1f(-2.0f * kap[j]);
+        lf[j] = lp[j] + __logf(kap[j] / (2.0f * guide::kPiF * -em[j])) + kap[j] * (cw[j] - 1.0f);
+        lmax = fmaxf(lmax, lf[j]);
     }
-    float sg = 0.0f, g[8];
+    lmax = fmaxf(lmax, __shfl_xor(lmax, 32));
+    float g[4], sg = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        g[k] = expf(lf[k] - lmax);
-        sg += g[k];
+    for (int j = 0; j < 4; ++j) {
+        g[j] = __expf(lf[j] - lmax);
+        sg += g[j];
     }
-    loss = -w * (lmax + logf(sg));
-    float inv = 1.0f / sg;
+    sg += __shfl_xor(sg, 32);
+    loss = -w * (lmax + __logf(sg));
+    const float inv = 1.0f / sg;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        float gk = g[k] * inv;
-        d[5 * k] = -w * (gk - pi[k]);
-        float c = -w * gk * kap[k] / mn[k];
-        d[5 * k + 1] = c * (wd.x - cw[k] * mu[k][0]);
-        d[5 * k + 2] = c * (wd.y - cw[k] * mu[k][1]);
-        d[5 * k + 3] = c * (wd.z - cw[k] * mu[k][2]);
-        float dk = 1.0f / kap[k] - 2.0f / expm1f(fminf(2.0f * kap[k], 80.0f)) + cw[k] - 1.0f;
-        float sgm = 1.0f / (1.0f + expf(-o[5 * k + 4]));
-        d[5 * k + 4] = clamped[k] ? 0.0f : -w * gk * dk * sgm;
+    for (int j = 0; j < 4; ++j) {
+        const float gk = g[j] * inv;
+        dz[0][j] = -w * (gk - __expf(lp[j]));
+        const float c = -w * gk * kap[j] * inv_mn[j];
+        dz[0][4 + j] = c * (wd.x - cw[j] * mu[j][0]);
+        dz[0][8 + j] = c * (wd.y - cw[j] * mu[j][1]);
+        dz[0][12 + j] = c * (wd.z - cw[j] * mu[j][2]);
+        const float dk = 1.0f / kap[j] + 2.0f * (1.0f + em[j]) / em[j] + cw[j] - 1.0f;
+        const float sgm = 1.0f / (1.0f + __expf(-out[1][j]));
+        dz[1][j] = clamped[j] ? 0.0f : -w * gk * dk * sgm;
     }
+#pragma unroll
+    for (int v = 4; v < 16; ++v) dz[1][v] = 0.0f;
 }
 
 // Training backward, block-cooperative. A block of four waves takes 128 rows
@@ -279,9 +278,8 @@ __global__ void k_guide_frag(GuideTrain T, uint2 *pub_a, float *pub_ab, uint2 *p
         auto frag = [&](int oo) {
             return make_uint2(pack2(w_at(L, k, oo), w_at(L, k + 1, oo)), pack2(w_at(L, k + 2, oo), w_at(L, k + 3, oo)));
         };
-        uint2 v = frag(o);
+        const uint2 v = frag(L == 3 ? frag_out_row(o) : o);
         T.frag[i] = v;
-        if (L == 3) v = frag(pub_out_row(o));
         if (pub_a) pub_a[i] = v;
         if (pub_b) pub_b[i] = v;
     } else if (i < nf + nt) {
@@ -289,14 +287,14 @@ __global__ void k_guide_frag(GuideTrain T, uint2 *pub_a, float *pub_ab, uint2 *p
         int L = 1 + g / 16;
         int r = g % 16, tk = r / 8, s = r % 8;
         int k = 32 * tk + lane % 32, o = 8 * s + 4 * half;
-        T.fragT[j] = make_uint2(pack2(w_at(L, k, o), w_at(L, k, o + 1)), pack2(w_at(L, k, o + 2), w_at(L, k, o + 3)));
+        auto w_row = [&](int r) { return w_at(L, k, L == 3 ? frag_out_row(r) : r); };
+        T.fragT[j] = make_uint2(pack2(w_row(o), w_row(o + 1)), pack2(w_row(o + 2), w_row(o + 3)));
     } else if (i < nf + nt + 256) {
         uint32_t j = i - nf - nt;
         int L = j / 64, o = j % 64;
         auto bias = [&](int oo) { return __uint_as_float(bf16_rne(oo < kN[L] ? T.master[kOffB[L] + oo] : 0.0f) << 16); };
-        float bq = bias(o);
+        const float bq = bias(L == 3 ? frag_out_row(o) : o);
         T.bias[j] = bq;
-        if (L == 3) bq = bias(pub_out_row(o));
         if (pub_ab) pub_ab[j] = bq;
         if (pub_bb) pub_bb[j] = bq;
     }
@@ -400,7 +398,7 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
     for (uint32_t i = threadIdx.x; i < kGuideFragsT * 64; i += blockDim.x) sfragT[i] = T.fragT[i];
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) sbias[i] = T.bias[i];
     __syncthreads();
-    const uint32_t lane = lane_id(), wv = threadIdx.x / 64;
+    const uint32_t lane = lane_id(), wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);  // uniform per wave
     // replay: a batch of min(batch, samples held) rows, a stratified subset
     const uint32_t count = src.debug ? src.n : min(*src.count, T.ring_cap);
     const uint32_t nrows = min(src.n, count);
@@ -418,7 +416,7 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         uint32_t row = it * kRowsPerIter + wv * 32 + (lane & 31);
         bool valid = row < nrows;
         float f[32];
-        guide::V3 wd = {0.0f, 0.0f, 1.0f};
+        guide::V3 wd = {0.0f, 0.0f, 1.0f}, xs = {0.0f, 0.0f, 0.0f}, wos = {0.0f, 1.0f, 0.0f};
         float wt = 0.0f;
         for (int j = 0; j < 32; ++j) f[j] = 0.0f;
         if (valid) {
@@ -432,25 +430,25 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
                 c = min(c, count - 1);
                 const float4 *r = T.ring + (size_t)c * kRingF4;
                 float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                guide::encode(guide::V3{r0.x, r0.y, r0.z}, guide::V3{r1.x, r1.y, r1.z}, F.guide.bmin, F.guide.binv, f);
+                xs = {r0.x, r0.y, r0.z};
+                wos = {r1.x, r1.y, r1.z};
                 wd = {r2.x, r2.y, r2.z};
                 wt = r0.w;
             }
         }
         v4s a0[4];
-        input_frags(f, a0);
+        if (src.debug) input_frags(f, a0);
+        else encode_half(xs, wos, F.guide.bmin, F.guide.binv, a0);
         Act A;
         v16f out[2];
         mlp_forward(sfrag, sbias, a0, A, out);
-        float o[40], d[40], lv;
-        gather40(out, o);
-        row_loss_grad(o, wd, wt, d, lv);
+        v16f dz[2], dzp[2];
+        float lv;
+        pair_loss_grad(out, wd, wt, dz, lv);
         if (valid && lane < 32) {
             wsum += wt;
             lsum += lv;
         }
-        v16f dz[2], dzp[2];
-        scatter40(d, dz);
         layer_bwd<3>(dz, A.a3, sfragT, A.m2, sZ, sA, wv, acc, dzp);
         layer_bwd<2>(dzp, A.a2, sfragT, A.m1, sZ, sA, wv, acc, dz);
         layer_bwd<1>(dz, A.a1, sfragT, A.m0, sZ, sA, wv, acc, dzp);
@@ -489,9 +487,9 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         const int N = kN[L];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            int o = 32 * to + 8 * (v / 4) + 4 * (int)half + (v % 4);
+            int o = 32 * to + 8 * (v / 4) + 4 * (int)half + (v % 4);  // accumulator row
             int k = 32 * tk + (int)(lane & 31);
-            if (o < N) out_p[kOffW[L] + k * N + o] = acc.w[L][v];
+            if (o < N) out_p[kOffW[L] + k * N + (L == 3 ? frag_out_row(o) : o)] = acc.w[L][v];
         }
     }
     if ((lane & 15) == 0) {
@@ -500,8 +498,8 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
         for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int o = 16 * ot + 4 * (int)(lane >> 4) + v;
-                if (o < N) out_p[kOffB[wv] + o] = acc.b[ot][v];
+                int o = 16 * ot + 4 * (int)(lane >> 4) + v;  // accumulator row
+                if (o < N) out_p[kOffB[wv] + (wv == 3 ? frag_out_row(o) : o)] = acc.b[ot][v];
             }
     }
 }
@@ -555,7 +553,7 @@ __global__ void k_fill0(float *p, uint32_t n)
 
 __global__ void k_fill_u32_1(uint32_t *p) { *p = 0u; }
 
-// forward on given features (parity hook; the training fragments, network order)
+// forward on given features (parity hook; outputs in the network's order)
 __global__ __launch_bounds__(256) void k_guide_fwd_debug(Frame F, const float *x, uint32_t n, float *out)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
@@ -575,9 +573,9 @@ __global__ __launch_bounds__(256) void k_guide_fwd_debug(Frame F, const float *x
         v16f o2[2];
         mlp_forward(sfrag, sbias, a0, A, o2);
         float o[40];
-        gather40(o2, o);
+        gather40(o2, o);  // accumulator rows: row r holds network output frag_out_row(r)
         if (row < n)
-            for (int j = 0; j < 20; ++j) out[(size_t)row * 40 + 20 * (lane >> 5) + j] = o[20 * (lane >> 5) + j];
+            for (int r = 20 * (lane >> 5); r < 20 * (lane >> 5) + 20; ++r) out[(size_t)row * 40 + frag_out_row(r)] = o[r];
     }
 }
 

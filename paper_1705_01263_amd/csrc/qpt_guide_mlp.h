@@ -166,14 +166,15 @@ __device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const flo
     a0[3] = pack4(s0, c0, s1, c1);
 }
 
-// The renderer's copies order the last layer's outputs by parameter, then
-// lobe: accumulator row 8c + k holds parameter c (0: weight logit, 1-3: mean
-// direction, 4: concentration) of lobe k, which is network output 5k + c. A
-// lane of the 32 x 32 output tile holds rows 8q + 4h + r (h its lane half), so
-// each lane ends up with all five parameters of lobes 4h .. 4h + 3 and decodes
-// them without exchanging outputs with its partner lane. Training keeps the
-// network's own order.
-__host__ __device__ constexpr int pub_out_row(int r) { return r < 40 ? 5 * (r % 8) + r / 8 : r; }
+// Every BF16 copy of the weights (training's and the renderer's) orders the
+// last layer's outputs by parameter, then lobe: accumulator row 8c + k holds
+// parameter c (0: weight logit, 1-3: mean direction, 4: concentration) of
+// lobe k, which is network output 5k + c (the FP32 master parameters keep
+// the network's order). A lane of the 32 x 32 output tile holds rows
+// 8q + 4h + r (h its lane half), so each lane ends up with all five
+// parameters of lobes 4h .. 4h + 3 and decodes them, or takes their
+// gradient, without exchanging outputs with its partner lane.
+__host__ __device__ constexpr int frag_out_row(int r) { return r < 40 ? 5 * (r % 8) + r / 8 : r; }
 
 // The mixture of the lane pair's row (both lanes of the pair pass the row's
 // hit point x and outgoing direction wo) in its packed form at dst (kMixU4
@@ -190,7 +191,7 @@ __device__ __forceinline__ void infer_pair(const uint2 *sfrag, const float *sbia
     encode_half(x, wo, bmin, binv, a0);
     v16f out[2];
     mlp_infer(sfrag, sbias, a0, out);
-    // this lane's lobes 4h + j (the renderer's output order, pub_out_row):
+    // this lane's lobes 4h + j (the fragments' output order, frag_out_row):
     // logit out[0][j], mean direction out[0][4 + j], out[0][8 + j],
     // out[0][12 + j], concentration out[1][j]
     float mx = fmaxf(fmaxf(out[0][0], out[0][1]), fmaxf(out[0][2], out[0][3]));
