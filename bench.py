@@ -84,8 +84,11 @@ def kernel_sha() -> str:
 # profiling workloads (`python bench.py summarize ...`, `--sweep`, `--profile-guided`)
 
 def guide_sha() -> str:
-    src = os.path.join(ROOT, "paper_1705_01263_amd", "csrc", "qpt_guide.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """SHA of the guide's kernels (training, inference and the mixture code)."""
+    h = hashlib.sha256()
+    for f in ("qpt_guide.hip", "qpt_guide_mlp.h", "qpt_guide_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_1705_01263_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _short(name: str) -> str:
@@ -243,7 +246,9 @@ def summarize_counters(pmc_dirs, kernels, out_txt: str, cmd: str) -> str:
 
 def run_guided(width: int, height: int, tris: int, passes: int, alpha: float = 0.7, max_vertex: int = 2) -> None:
     """A guided workload to profile: the slit scene with the guide training
-    one step per batch of passes from its first pass."""
+    one Adam step per pass from its first pass, two batches in flight and the
+    megakernel tail from half the maximum depth (the equal-time leg's
+    schedule)."""
     import torch
 
     import scenegen
@@ -253,7 +258,7 @@ def run_guided(width: int, height: int, tris: int, passes: int, alpha: float = 0
     r = Renderer(sc)
     r.ctx.guide_set_weights(scenegen.guide_init(1))
     r.ctx.guide_config(alpha=alpha, lr=1e-3, batch=1 << 18, train=1, warmup_steps=0, seed=1, max_vertex=max_vertex)
-    r.render(0, passes)
+    r.render(0, passes, tail_depth=sc.max_depth // 2)
     torch.cuda.synchronize()
     _, steps = r.ctx.guide_get_weights()
     print(f"guided: {passes} passes of {sc.name} {width}x{height}, {steps} Adam steps", flush=True)
@@ -388,7 +393,7 @@ def _host_cpu():
 
 
 def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle_scene=None,
-               oracle_seconds: float = 0.0, oracle_stride=(32, 16), guide=None):
+               oracle_seconds: float = 0.0, oracle_stride=(32, 16), guide=None, tail_depth=None):
     """Equal-time RMSE of the plain and the guided tracer on one scene.
 
     Both runs of a pair get the same wall time on the same GPU, the guided
@@ -403,7 +408,9 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
     bounded pixel sample (every `oracle_stride` pixels, also from an
     independent pass range), whose own error against the GPU reference is
     reported beside it. `per_call` passes go to the library per call (two
-    batches in flight).
+    batches in flight); both tracers (and the references) render with the
+    megakernel tail from `tail_depth` (default: half the maximum depth,
+    past the guided vertices), as the throughput leg does.
     """
     import numpy as np
     import torch
@@ -414,12 +421,13 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
     g = dict(GUIDE)
     if guide:
         g.update(guide)
+    td = sc.max_depth // 2 if tail_depth is None else tail_depth
     width, height = sc.width, sc.height
     rmse = lambda a, b: float(np.sqrt(np.mean((a - b) ** 2)))
     out = {"workload": f"{sc.name}: {sc.num_triangles} triangles, {width}x{height}, max depth {sc.max_depth}",
            "guide": {"alpha": g["alpha"], "guided_vertices": g["max_vertex"], "lr": g["lr"], "batch": g["batch"],
                      "adam_steps_per_pass": 1, "warmup_steps": g["warmup"]},
-           "passes_per_call": per_call, "views": []}
+           "passes_per_call": per_call, "tail_depth": td, "views": []}
     for vi, (vname, cam) in enumerate(views):
         if cam is not None:
             sc.camera = cam
@@ -437,7 +445,7 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
             t0 = time.perf_counter()
             n = 0
             while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
-                r.render(n, per_call)
+                r.render(n, per_call, tail_depth=td)
                 n += per_call
                 torch.cuda.synchronize()
             dt = time.perf_counter() - t0
@@ -457,7 +465,7 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
         refs = []
         for first in (1 << 24, (1 << 24) + (1 << 23)):
             r.reset()
-            r.render(first, ref_passes)
+            r.render(first, ref_passes, tail_depth=td)
             s, c = r.readback()
             refs.append(s / c[:, None])
         ref = 0.5 * (refs[0] + refs[1])

@@ -386,7 +386,7 @@ struct RowSrc {
     float u;                     // stratification offset in [0, 1)
 };
 
-__global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain T, RowSrc src)
+__global__ __launch_bounds__(kTrainBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_guide_train(Frame F, GuideTrain T, RowSrc src)
 {
     extern __shared__ unsigned char smem[];
     uint2 *sfrag = (uint2 *)smem;
@@ -504,12 +504,51 @@ __global__ __launch_bounds__(kTrainBlock) void k_guide_train(Frame F, GuideTrain
     }
 }
 
-// sum the block partials, normalise by the weight sum; then Adam or a plain
-// copy. A block owns 64 parameters; its four waves each sum every fourth
-// partial (coalesced 256-byte rows), then wave 0 combines the four sums.
 constexpr uint32_t kReduceParams = 64;
+// Where master parameter p sits in the BF16 copies (the inverse of the
+// fragment builder's map): the 16-bit element of the forward fragments, of
+// the transposed ones (layers 1-3; -1 otherwise) and of the bias table.
+struct FragSlot {
+    int fwd, tr, bias;
+};
+
+__device__ __forceinline__ FragSlot frag_slot(uint32_t p)
+{
+    FragSlot r{-1, -1, -1};
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+        const int N = kN[L];
+        const int q = (int)p - kOffW[L];
+        if (q < 0) break;
+        if (q < kOffB[L] - kOffW[L]) {  // weight W_L[k][o]
+            const int k = q / N, o = q % N;
+            const int row = L == 3 ? frag_in_row(o) : o;  // accumulator row of output o
+            const int f = kFB[L] + (row / 32) * kKS[L] + k / 8;
+            r.fwd = (f * 64 + 32 * ((k % 8) / 4) + row % 32) * 4 + k % 4;
+            if (L > 0) {
+                const int g = kGB[L] + (k / 32) * 8 + row / 8;
+                r.tr = (g * 64 + 32 * ((row % 8) / 4) + k % 32) * 4 + row % 4;
+            }
+            return r;
+        }
+        if (q < kOffB[L] - kOffW[L] + N) {  // bias b_L[o]
+            const int o = q - (kOffB[L] - kOffW[L]);
+            r.bias = L * 64 + (L == 3 ? frag_in_row(o) : o);
+            return r;
+        }
+    }
+    return r;
+}
+
+// sum the block partials, normalise by the weight sum; then Adam or a plain
+// copy. With Adam, the updated parameter also goes straight into the BF16
+// copies training reads (and, where given, the renderer's published copies):
+// no separate pass over the parameters per step. A block owns 64
+// parameters; its four waves each sum every fourth partial (coalesced
+// 256-byte rows), then wave 0 combines the four sums.
 __global__ __launch_bounds__(256) void k_guide_reduce(GuideTrain T, uint32_t blocks, int adam, uint32_t step,
-                                                      float lr, float *grad_out)
+                                                      float lr, float *grad_out, uint2 *pub_a, float *pub_ab,
+                                                      uint2 *pub_b, float *pub_bb)
 {
     __shared__ float part[4][kReduceParams];
     const uint32_t lane = threadIdx.x & 63u, grp = threadIdx.x >> 6;
@@ -542,13 +581,22 @@ __global__ __launch_bounds__(256) void k_guide_reduce(GuideTrain T, uint32_t blo
     T.v[p] = v;
     float mh = m / (1.0f - powf(b1, (float)step));
     float vh = v / (1.0f - powf(b2, (float)step));
-    T.master[p] -= lr * mh / (sqrtf(vh) + eps);
-}
-
-__global__ void k_fill0(float *p, uint32_t n)
-{
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
+    const float w = T.master[p] - lr * mh / (sqrtf(vh) + eps);
+    T.master[p] = w;
+    const FragSlot fs = frag_slot(p);
+    const uint16_t h = (uint16_t)bf16_rne(w);
+    if (fs.fwd >= 0) {
+        ((uint16_t *)T.frag)[fs.fwd] = h;
+        if (pub_a) ((uint16_t *)pub_a)[fs.fwd] = h;
+        if (pub_b) ((uint16_t *)pub_b)[fs.fwd] = h;
+    }
+    if (fs.tr >= 0) ((uint16_t *)T.fragT)[fs.tr] = h;
+    if (fs.bias >= 0) {
+        const float bq = __uint_as_float((uint32_t)h << 16);
+        T.bias[fs.bias] = bq;
+        if (pub_ab) pub_ab[fs.bias] = bq;
+        if (pub_bb) pub_bb[fs.bias] = bq;
+    }
 }
 
 __global__ void k_fill_u32_1(uint32_t *p) { *p = 0u; }
@@ -653,7 +701,6 @@ static hipError_t run_train(const Frame &f, const GuideTrain &T, const RowSrc &s
         attr = true;
     }
     uint32_t blocks = nblocks(((size_t)src.n + 31) / 32, kTrainBlock / 64, T.max_blocks);
-    hipLaunchKernelGGL(k_fill0, dim3(1), dim3(64), 0, s, T.scalars, 2u);
     hipLaunchKernelGGL(k_guide_train, dim3(blocks), dim3(kTrainBlock), train_smem(), s, f, T, src);
     *blocks_out = blocks;
     return hipGetLastError();
@@ -688,10 +735,12 @@ hipError_t launch_guide_train_steps(const Frame &f, const GuideTrain &T, uint32_
         uint32_t blocks = 0;
         e = run_train(f, T, src, s, &blocks);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s,
-                           T, blocks, 1, step, lr, (float *)nullptr);
+        // the last step of the batch also publishes the weights for the renderer
         const bool last = k + 1 == nsteps;
-        e = launch_guide_frag(T, s, last ? pub_frag : nullptr, last ? pub_bias : nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s,
+                           T, blocks, 1, step, lr, (float *)nullptr, last ? pub_frag : nullptr,
+                           last ? pub_bias : nullptr, (uint2 *)nullptr, (float *)nullptr);
+        e = hipGetLastError();
     }
     return e;
 }
@@ -712,8 +761,7 @@ hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const fl
     hipError_t e = run_train(f, T, src, s, &blocks);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_guide_reduce, dim3((kGuideParams + kReduceParams - 1) / kReduceParams), dim3(256), 0, s, T, blocks, adam,
-                       step, lr, grad);
-    if (adam) return launch_guide_frag(T, s, pub_a, pub_ab, pub_b, pub_bb);
+                       step, lr, grad, pub_a, pub_ab, pub_b, pub_bb);
     return hipGetLastError();
 }
 

@@ -175,6 +175,8 @@ __device__ __forceinline__ void encode_half(guide::V3 x, guide::V3 wo, const flo
 // parameters of lobes 4h .. 4h + 3 and decodes them, or takes their
 // gradient, without exchanging outputs with its partner lane.
 __host__ __device__ constexpr int frag_out_row(int r) { return r < 40 ? 5 * (r % 8) + r / 8 : r; }
+// and its inverse: the accumulator row of network output o
+__host__ __device__ constexpr int frag_in_row(int o) { return o < 40 ? 8 * (o % 5) + o / 5 : o; }
 
 // The mixture of the lane pair's row (both lanes of the pair pass the row's
 // hit point x and outgoing direction wo) in its packed form at dst (kMixU4
