@@ -20,8 +20,8 @@ using namespace mlp;
 constexpr int kGB[4] = {0, 0, 16, 32};         // first transposed fragment (layers 1..3)
 constexpr int kOffW[4] = {0, 2112, 6272, 10432};
 constexpr int kOffB[4] = {2048, 6208, 10368, 12992};
-constexpr int kTrainBlock = 256;               // 4 waves
-static_assert(kTrainBlock == 256, "the per-block weight and loss sums add four waves");
+constexpr int kTrainBlock = 512;               // 8 waves: two row halves of the four gradient-tile owners
+static_assert(kTrainBlock == 512, "the per-block weight and loss sums add eight waves");
 
 // ReLU, its mask (bit 16t + v), and the BF16 B operands of the next layer
 __device__ __forceinline__ void relu_pack(const v16f *acc, v4s *out, uint32_t &mask)
@@ -159,17 +159,21 @@ __device__ __forceinline__ void pair_loss_grad(const v16f *out, guide::V3 wd, fl
     for (int v = 4; v < 16; ++v) dz[1][v] = 0.0f;
 }
 
-// Training backward, block-cooperative. A block of four waves takes 128 rows
-// (32 per wave) per iteration. For each layer, every wave stages its rows'
+// Training backward, block-cooperative. A block of eight waves takes 256
+// rows (32 per wave) per iteration, two waves per SIMD to hide the MFMA and
+// LDS latencies of each other. For each layer, every wave stages its rows'
 // BF16 pre-activation gradients dZ and layer inputs A in LDS, transposed
-// ([feature][row], 128 rows plus padding per feature), then each wave
-// multiplies one 32 x 32 tile of dW^T = dZ^T A over all 128 rows (the rows
-// are the MFMA reduction dimension) into an accumulator it keeps across
-// iterations, and one wave sums the rows of dZ for the bias gradient (a
-// product with a column of ones on 16 x 16 x 16 MFMA). Nothing is added
-// atomically; each gradient value is written once per block at the end.
-constexpr int kRowsPerIter = 128;
-constexpr int kStageRow = 132;   // BF16 per staged feature: 128 rows + 4 (bank-conflict-free b64 reads)
+// ([feature][row], 256 rows plus padding per feature), then waves w and
+// w + 4 multiply the same 32 x 32 tile of dW^T = dZ^T A, over rows 0-127 and
+// 128-255 respectively (the rows are the MFMA reduction dimension), into
+// accumulators they keep across iterations, and waves L and 4 + L sum the
+// two halves' rows of dZ for layer L's bias gradient (a product with a
+// column of ones on 16 x 16 x 32 MFMA). Nothing is added atomically: the
+// halves are combined in a fixed order and each gradient value is written
+// once per block at the end.
+constexpr int kRowsPerIter = 256;
+constexpr int kRowsPerOwner = 128;  // rows of an iteration in one wave's gradient tiles
+constexpr int kStageRow = 260;   // BF16 per staged feature: 256 rows + 4 (bank-conflict-free b64 reads)
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -182,17 +186,19 @@ __device__ __forceinline__ v4f mfma16x2(v4s a0, v4s a1, v4s b0, v4s b1, v4f c)
 __device__ __forceinline__ v4s lds_b64(const uint16_t *p) { return __builtin_bit_cast(v4s, *(const uint2 *)p); }
 
 struct GradAcc {
-    v16f w[4];  // this wave's dW^T tile of each layer (layer 0: waves 0 and 1 only)
-    v4f b[4];   // bias gradient of layer `wave`, four 16-output tiles
+    v16f w[4];  // this wave's dW^T tile of each layer over its row half (layer 0: owners 0 and 1 only)
+    v4f b[4];   // bias gradient of layer `wave & 3` over its row half, four 16-output tiles
 };
 
-// the dW^T tile of layer L owned by wave wv: output tile to = wv & 1, input
-// tile tk = wv >> 1 (layer 0 has one input tile: waves 2 and 3 own none)
+// the dW^T tile of layer L owned by wave wv (both row halves): owner
+// u = wv & 3, output tile to = u & 1, input tile tk = u >> 1 (layer 0 has
+// one input tile: owners 2 and 3 have none)
 template <int L>
 __device__ __forceinline__ bool owns_tile(uint32_t wv, int &to, int &tk)
 {
-    to = (int)(wv & 1u);
-    tk = (int)(wv >> 1);
+    const uint32_t u = wv & 3u;
+    to = (int)(u & 1u);
+    tk = (int)(u >> 1);
     return tk < kKS[L] / 4;
 }
 
@@ -220,24 +226,25 @@ __device__ __forceinline__ void layer_bwd(const v16f *dz, const v4s *in, const u
         for (int e = 0; e < 4; ++e) sA[(8 * s + 4 * half + e) * kStageRow + R] = (uint16_t)in[s][e];
     __syncthreads();
     int to, tk;
+    const uint32_t r0 = kRowsPerOwner * (wv >> 2);  // this wave's row half
     if (owns_tile<L>(wv, to, tk) && !(to == 1 && N <= 32)) {
-        const uint16_t *za = sZ + (32 * to + row) * kStageRow + 4 * half;
-        const uint16_t *aa = sA + (32 * tk + row) * kStageRow + 4 * half;
+        const uint16_t *za = sZ + (32 * to + row) * kStageRow + r0 + 4 * half;
+        const uint16_t *aa = sA + (32 * tk + row) * kStageRow + r0 + 4 * half;
         v16f c = acc.w[L];
 #pragma unroll
-        for (int s = 0; s < kRowsPerIter / 8; s += 2)
+        for (int s = 0; s < kRowsPerOwner / 8; s += 2)
             c = mfma2(lds_b64(za + 8 * s), lds_b64(za + 8 * s + 8), lds_b64(aa + 8 * s), lds_b64(aa + 8 * s + 8), c);
         acc.w[L] = c;
     }
-    if (wv == (uint32_t)L) {
+    if ((wv & 3u) == (uint32_t)L) {
         const v4s ones = {(short)0x3F80, (short)0x3F80, (short)0x3F80, (short)0x3F80};
 #pragma unroll
         for (int ot = 0; ot < 4; ++ot) {
             if (16 * ot >= N) continue;
-            const uint16_t *za = sZ + (16 * ot + (lane & 15)) * kStageRow + 4 * (lane >> 4);
+            const uint16_t *za = sZ + (16 * ot + (lane & 15)) * kStageRow + r0 + 4 * (lane >> 4);
             v4f c = acc.b[ot];
 #pragma unroll
-            for (int s = 0; s < kRowsPerIter / 16; s += 2) c = mfma16x2(lds_b64(za + 16 * s), lds_b64(za + 16 * s + 16), ones, ones, c);
+            for (int s = 0; s < kRowsPerOwner / 16; s += 2) c = mfma16x2(lds_b64(za + 16 * s), lds_b64(za + 16 * s + 16), ones, ones, c);
             acc.b[ot] = c;
         }
     }
@@ -465,12 +472,20 @@ __global__ __launch_bounds__(kTrainBlock) __attribute__((amdgpu_waves_per_eu(2))
         swl[0][wv] = wsum;
         swl[1][wv] = lsum;
     }
+    // the staged weights and rows are done with: the LDS holds the upper row
+    // halves' partial gradients from here on
     __syncthreads();
     if (threadIdx.x == 0) {
-        T.scalars[2 + 2 * blockIdx.x] = (swl[0][0] + swl[0][1]) + (swl[0][2] + swl[0][3]);
-        T.scalars[3 + 2 * blockIdx.x] = (swl[1][0] + swl[1][1]) + (swl[1][2] + swl[1][3]);
+        T.scalars[2 + 2 * blockIdx.x] = ((swl[0][0] + swl[0][1]) + (swl[0][2] + swl[0][3])) +
+                                        ((swl[0][4] + swl[0][5]) + (swl[0][6] + swl[0][7]));
+        T.scalars[3 + 2 * blockIdx.x] = ((swl[1][0] + swl[1][1]) + (swl[1][2] + swl[1][3])) +
+                                        ((swl[1][4] + swl[1][5]) + (swl[1][6] + swl[1][7]));
     }
-    // this block's gradient sums: every parameter written by exactly one lane
+    // this block's gradient sums: the lower half's partial plus the upper
+    // half's, every parameter written by exactly one lane
+    float *comb = (float *)smem;  // 4 owners x 64 lanes x 16 floats
+    float *mine = comb + ((wv & 3u) * 64 + lane) * 16;
+    const bool upper = wv >= 4;
     float *out_p = T.partial + (size_t)blockIdx.x * kGuideParams;
     const uint32_t half = lane >> 5;
 #pragma unroll
@@ -483,23 +498,35 @@ __global__ __launch_bounds__(kTrainBlock) __attribute__((amdgpu_waves_per_eu(2))
         case 2: own = owns_tile<2>(wv, to, tk); break;
         default: own = owns_tile<3>(wv, to, tk); break;
         }
-        if (!own) continue;
-        const int N = kN[L];
+        if (own && upper)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int o = 32 * to + 8 * (v / 4) + 4 * (int)half + (v % 4);  // accumulator row
-            int k = 32 * tk + (int)(lane & 31);
-            if (o < N) out_p[kOffW[L] + k * N + (L == 3 ? frag_out_row(o) : o)] = acc.w[L][v];
+            for (int v = 0; v < 16; ++v) mine[v] = acc.w[L][v];
+        __syncthreads();
+        if (own && !upper) {
+            const int N = kN[L];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                int o = 32 * to + 8 * (v / 4) + 4 * (int)half + (v % 4);  // accumulator row
+                int k = 32 * tk + (int)(lane & 31);
+                if (o < N) out_p[kOffW[L] + k * N + (L == 3 ? frag_out_row(o) : o)] = acc.w[L][v] + mine[v];
+            }
         }
+        __syncthreads();
     }
-    if ((lane & 15) == 0) {
+    if (upper)
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) mine[4 * ot + v] = acc.b[ot][v];
+    __syncthreads();
+    if (!upper && (lane & 15) == 0) {
         const int N = kN[wv];
 #pragma unroll
         for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 int o = 16 * ot + 4 * (int)(lane >> 4) + v;  // accumulator row
-                if (o < N) out_p[kOffB[wv] + (wv == 3 ? frag_out_row(o) : o)] = acc.b[ot][v];
+                if (o < N) out_p[kOffB[wv] + (wv == 3 ? frag_out_row(o) : o)] = acc.b[ot][v] + mine[4 * ot + v];
             }
     }
 }
@@ -553,9 +580,19 @@ __global__ __launch_bounds__(256) void k_guide_reduce(GuideTrain T, uint32_t blo
     __shared__ float part[4][kReduceParams];
     const uint32_t lane = threadIdx.x & 63u, grp = threadIdx.x >> 6;
     const uint32_t p = blockIdx.x * kReduceParams + lane;
-    float g = 0.0f;
-    if (p < kGuideParams)
-        for (uint32_t b = grp; b < blocks; b += 4) g += T.partial[(size_t)b * kGuideParams + p];
+    // every fourth partial from grp on, into four running sums (partials
+    // grp + 16 i + 4 j go to sum j): four loads in flight per lane instead of
+    // one chain of dependent loads; a fixed order, so the step stays a
+    // deterministic function of its rows
+    float g4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (p < kGuideParams) {
+        uint32_t b = grp;
+        for (; b + 12 < blocks; b += 16)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) g4[j] += T.partial[(size_t)(b + 4 * j) * kGuideParams + p];
+        for (int j = 0; b < blocks; b += 4, ++j) g4[j] += T.partial[(size_t)b * kGuideParams + p];
+    }
+    float g = (g4[0] + g4[1]) + (g4[2] + g4[3]);
     part[grp][lane] = g;
     __syncthreads();
     if (grp != 0 || p >= kGuideParams) return;
