@@ -1386,7 +1386,9 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
     float pad = (float)(std::ldexp(std::max(maxabs, 1e-3), -18));
     // collapse into a 4-wide tree: each node takes its binary node's two
     // children and keeps opening the inner child of largest surface area
-    // until it has four; siblings are stored next to each other
+    // until it has four; siblings are stored next to each other. Nodes are
+    // numbered breadth-first until kTopNodes exist (the top levels, which
+    // the traversal keeps in LDS, come first), depth-first after that.
     auto leaf_ref = [&](const BuildNode &bn) -> int32_t { return ~(int32_t)((bn.first << 3) | (bn.count - 1)); };
     c->gnodes.clear();
     uint32_t leaves = 0, depth4 = 0;
@@ -1397,11 +1399,24 @@ int qpt_build_bvh(qpt_ctx *c, const qpt_bvh_opts *opts, qpt_bvh_stats *stats)
         uint32_t q, slot, depth;
     };
     std::vector<Item> work;
+    size_t head = 0;  // breadth-first while head <= work.size() marks a queue
+    bool bfs = true;
     c->gnodes.emplace_back();
     work.push_back({0u, 0u, 0u});
-    while (!work.empty()) {
-        Item it = work.back();
-        work.pop_back();
+    while (head < work.size()) {
+        if (bfs && c->gnodes.size() >= kTopNodes) {
+            // the rest of the queue becomes the depth-first stack
+            work.erase(work.begin(), work.begin() + (std::ptrdiff_t)head);
+            head = 0;
+            bfs = false;
+        }
+        Item it;
+        if (bfs) {
+            it = work[head++];
+        } else {
+            it = work.back();
+            work.pop_back();
+        }
         depth4 = std::max(depth4, it.depth);
         const BuildNode &bn = B.nodes[it.q];
         uint32_t kids[4];
@@ -1566,6 +1581,7 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     f.nodes = (const Node *)(w + L.nodes);
     f.qnodes = (const QNode *)(w + L.nodes);
     f.node_format = c->node_format;
+    f.top_nodes = c->node_format == kNodeQuant ? (uint32_t)std::min<size_t>(kTopNodes, c->gnodes.size()) : 0u;
     f.tris = (const Tri *)(w + L.tris);
     f.mats = (const Material *)(w + L.mats);
     f.num_tris = (uint32_t)c->gtris.size();

@@ -9,7 +9,11 @@
 namespace qpt {
 
 constexpr uint32_t kMaxDims = 256;       // sample dimensions with a base table
-constexpr uint32_t kShortStack = 16;     // traversal stack entries per ray kept in LDS
+constexpr uint32_t kShortStack = 15;     // traversal stack entries per ray kept in LDS
+// the tree's first nodes (its top levels: the host numbers them breadth-first)
+// are copied into LDS by every traversal block: 4 KB of quantised nodes, so
+// that 8 blocks of 256 threads still fit one CU with their stacks (8 x 19 KB)
+constexpr uint32_t kTopNodes = 64;
 constexpr uint32_t kMaxTreeDepth = 32;   // depth limit of the binary build tree
 constexpr uint32_t kTravBlocksPerCU = 16; // traversal grid: 16 blocks of 4 waves per CU, twice what is resident
 constexpr uint32_t kShadeGuidedBlock = 512;     // guided shading: 8 waves share the weights in LDS
@@ -140,6 +144,7 @@ struct Frame {
     const Node *nodes;                    // node_format kNodeFull
     const QNode *qnodes;                  // node_format kNodeQuant
     uint32_t node_format;
+    uint32_t top_nodes;                   // nodes [0, top_nodes) staged in LDS (quantised tree; <= kTopNodes)
     const Tri *tris;
     const Material *mats;
     uint32_t num_tris;

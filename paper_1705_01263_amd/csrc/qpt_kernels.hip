@@ -305,6 +305,11 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
 // level). Children are culled against the current closest t with a closed
 // interval, so the result does not depend on the visiting order.
 //
+// With TOP, the nodes below F.top_nodes (the tree's top levels) come from the
+// block's copy in LDS (`top`, filled by stage_top) instead of global memory:
+// every ray starts at the root, so these few nodes are fetched by every ray
+// and their copy in LDS takes them off the chain of dependent global loads.
+//
 // Inner nodes and leaves are processed in separate loops so that a wave runs
 // either kind of work with most lanes active: a lane that reaches a leaf
 // postpones it and keeps descending, and the wave leaves the node loop only
@@ -312,8 +317,9 @@ __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
 // holds a leaf; then the postponed leaves, and any leaves that follow them on
 // the stack, are tested. Postponing only delays the updates of the closest t,
 // which cull later children, so the hit is the same.
-template <bool ANY, bool QN, bool DEPTH = false>
-__device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs)
+template <bool ANY, bool QN, bool DEPTH = false, bool TOP = false>
+__device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h, int *stk, int *gstk, size_t gs,
+                         const QNode *top = nullptr)
 {
     h.t = tmax;
     h.tri = kNoHit;
@@ -346,7 +352,7 @@ __device__ bool traverse(const Frame &F, const RayPre &r, float tmax, HitRec &h,
             uint32_t k0, k1, k2, k3;
             int4 nref;
             if (QN) {
-                const QNode n = F.qnodes[ref];
+                const QNode n = (TOP && (uint32_t)ref < F.top_nodes) ? top[ref] : F.qnodes[ref];
                 uint32_t k[4];
                 int32_t rf[4];
                 qnode_keys(n, r, h.t, k, rf);
@@ -967,6 +973,16 @@ __global__ __launch_bounds__(kBlock) void k_generate(Frame F, Pool P, uint32_t p
     P.q_ext[1][s] = s;
 }
 
+// the tree's first F.top_nodes nodes into the block's LDS copy; every thread
+// of the block calls it (it ends with the block barrier)
+__device__ __forceinline__ void stage_top(const Frame &F, QNode *top)
+{
+    const uint4 *src = (const uint4 *)F.qnodes;
+    uint4 *dst = (uint4 *)top;
+    for (uint32_t i = threadIdx.x; i < 4 * F.top_nodes; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+}
+
 // closest hit for the extension rays of queue q_ext[qsel] (counters[cnt]
 // entries: the queue of one depth, or of one iteration when regenerating);
 // the grid holds twice what is resident on the chip (a block that finishes
@@ -975,7 +991,11 @@ template <bool QN>
 __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t cnt, uint32_t qsel)
 {
     __shared__ int stk[kShortStack * kBlock];
+    __shared__ QNode top[QN ? kTopNodes : 1];
     const uint32_t n = P.counters[cnt];
+    // blocks without rays leave before staging (uniform per block)
+    if ((size_t)blockIdx.x * kBlock >= n) return;
+    if (QN) stage_top(F, top);
     const uint32_t *q = P.q_ext[qsel];
     int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t nodes = 0, tests = 0;
@@ -986,7 +1006,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_trace(Frame F, Pool P, uint32_t c
         float4 o = P.ray_o[slot], d = state::load_dir(F, P, slot);
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
-        traverse<false, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+        traverse<false, QN, false, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads, top);
         state::store_hit(F, P, slot, make_float4(h.t, ubits(h.tri), h.b1, h.b2));
         nodes += h.nodes;
         tests += h.tests;
@@ -1001,7 +1021,10 @@ template <bool QN>
 __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t cnt)
 {
     __shared__ int stk[kShortStack * kBlock];
+    __shared__ QNode top[QN ? kTopNodes : 1];
     const uint32_t n = P.counters[cnt];
+    if ((size_t)blockIdx.x * kBlock >= n) return;
+    if (QN) stage_top(F, top);
     int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t nodes = 0, tests = 0;
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
@@ -1010,7 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_shadow(Frame F, Pool P, uint32_t cnt
         float4 o = P.sh_o[i], d = P.sh_d[i];
         RayPre r = prepare(xyz(o), xyz(d));
         HitRec h;
-        bool occluded = traverse<true, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+        bool occluded = traverse<true, QN, false, QN>(F, r, o.w, h, stk + threadIdx.x, gstk, P.trav_threads, top);
         nodes += h.nodes;
         tests += h.tests;
         if (!occluded) {
@@ -1541,11 +1564,13 @@ template <bool QN>
 __global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0)
 {
     __shared__ int stk[kShortStack * kBlock];
+    __shared__ QNode top[QN ? kTopNodes : 1];
     __shared__ uint32_t cnt_ext[64], cnt_sh[64];
     if (threadIdx.x < 64) {
         cnt_ext[threadIdx.x] = 0;
         cnt_sh[threadIdx.x] = 0;
     }
+    if (QN) stage_top(F, top);
     __syncthreads();
     const uint32_t n = P.counters[v0];
     const uint32_t *q = P.q_ext[v0 & 1];
@@ -1559,7 +1584,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0
             const float4 o4 = P.ray_o[slot], d4 = state::load_dir(F, P, slot);
             RayPre r = prepare(xyz(o4), xyz(d4));
             HitRec h;
-            traverse<false, QN>(F, r, o4.w, h, stk + threadIdx.x, gstk, P.trav_threads);
+            traverse<false, QN, false, QN>(F, r, o4.w, h, stk + threadIdx.x, gstk, P.trav_threads, top);
             state::store_hit(F, P, slot, make_float4(h.t, ubits(h.tri), h.b1, h.b2));
             en += h.nodes;
             et += h.tests;
@@ -1571,7 +1596,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tail(Frame F, Pool P, uint32_t v0
                 atomicAdd(&cnt_sh[v], 1u);
                 RayPre rs = prepare(xyz(o.sh_o), xyz(o.sh_d));
                 HitRec hs;
-                const bool occluded = traverse<true, QN>(F, rs, o.sh_o.w, hs, stk + threadIdx.x, gstk, P.trav_threads);
+                const bool occluded =
+                    traverse<true, QN, false, QN>(F, rs, o.sh_o.w, hs, stk + threadIdx.x, gstk, P.trav_threads, top);
                 sn += hs.nodes;
                 st += hs.tests;
                 if (!occluded) {
@@ -1647,6 +1673,10 @@ __global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, Pool P, const f
                                                         uint32_t *tri, float *b12, uint32_t *depth)
 {
     __shared__ int stk[kShortStack * kBlock];
+    __shared__ QNode top[kTopNodes];
+    if ((size_t)blockIdx.x * kBlock >= n) return;
+    const bool qn = F.node_format == kNodeQuant;
+    if (qn) stage_top(F, top);
     int *gstk = P.gstack + (size_t)(blockIdx.x * kBlock + threadIdx.x);
     for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         uint32_t q = base + threadIdx.x;
@@ -1654,9 +1684,8 @@ __global__ __launch_bounds__(kBlock) void k_debug_trace(Frame F, Pool P, const f
         const float *ry = rays + 8 * (size_t)q;
         RayPre r = prepare(mk(ry[0], ry[1], ry[2]), mk(ry[4], ry[5], ry[6]));
         HitRec h;
-        bool hit = F.node_format == kNodeQuant
-                       ? traverse<ANY, true, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads)
-                       : traverse<ANY, false, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
+        bool hit = qn ? traverse<ANY, true, true, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads, top)
+                      : traverse<ANY, false, true>(F, r, ry[3], h, stk + threadIdx.x, gstk, P.trav_threads);
         if (depth) depth[q] = h.depth;
         if (ANY) {
             tri[q] = hit ? 1u : 0u;

@@ -11,7 +11,7 @@ traversal and intersection), through the C-ABI:
   on host threads), bit for bit;
 - a comb of 120,000 sliver triangles whose boxes all contain one line while
   the triangles miss it: rays along the line open every node, so their
-  stacks outgrow the 16 entries kept in LDS and spill to the workspace (the
+  stacks outgrow the 15 entries kept in LDS and spill to the workspace (the
   test requires it), and BVH equals brute force bit for bit there too.
 """
 import math
@@ -24,6 +24,8 @@ import pytest
 import scenegen as g
 
 pytestmark = pytest.mark.gpu
+# traversal stack entries per ray kept in LDS (deeper entries spill to the workspace)
+SHORT_STACK = 15
 torch = pytest.importorskip("torch")
 
 
@@ -122,7 +124,7 @@ def test_fullsize_hits_bitexact(Renderer, orc, which):
     t, tri, b, depth = _trace(r, rays, False, 0)
     t_b, tri_b, b_b, _ = _trace(r, rays, False, 1)
     hit = tri != 0xFFFFFFFF
-    _say(f"    hits {hit.sum()}, deepest stack {depth.max()}, rays past the LDS stack (> 16): {(depth > 16).sum()}")
+    _say(f"    hits {hit.sum()}, deepest stack {depth.max()}, rays past the LDS stack (> {SHORT_STACK}): {(depth > SHORT_STACK).sum()}")
     assert np.array_equal(tri, tri_b)
     assert np.array_equal(t[hit], t_b[hit]) and np.array_equal(b[hit], b_b[hit])
     # rays whose stack spilled past the LDS entries (the comb test below makes
@@ -139,7 +141,7 @@ def test_fullsize_hits_bitexact(Renderer, orc, which):
     sub = np.sort(np.concatenate([order[:m // 4], rng.choice(n, m - m // 4, replace=False)]))
     sub = np.unique(sub)
     t_o, tri_o, b_o = _oracle_f32(orc, sc, rays[sub])
-    _say(f"    oracle subset {sub.shape[0]} rays, of them past the LDS stack: {(depth[sub] > 16).sum()}")
+    _say(f"    oracle subset {sub.shape[0]} rays, of them past the LDS stack: {(depth[sub] > SHORT_STACK).sum()}")
     assert np.array_equal(tri[sub], tri_o)
     h = tri_o != 0xFFFFFFFF
     assert np.array_equal(t[sub][h], t_o[h]) and np.array_equal(b[sub][h], b_o[h])
@@ -178,8 +180,8 @@ def test_stack_spill_comb(Renderer, orc):
     t, tri, b, depth = _trace(r, rays, False, 0)
     t_b, tri_b, b_b, _ = _trace(r, rays, False, 1)
     hit = tri != 0xFFFFFFFF
-    spill = int((depth > 16).sum())
-    _say(f"    hits {hit.sum()}, deepest stack {depth.max()}, rays past the LDS stack (> 16): {spill}")
+    spill = int((depth > SHORT_STACK).sum())
+    _say(f"    hits {hit.sum()}, deepest stack {depth.max()}, rays past the LDS stack (> {SHORT_STACK}): {spill}")
     assert spill >= n // 2, "rays along the comb should spill the LDS stack"
     assert np.array_equal(tri, tri_b)
     assert np.array_equal(t[hit], t_b[hit]) and np.array_equal(b[hit], b_b[hit])

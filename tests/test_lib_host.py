@@ -98,6 +98,43 @@ def test_bvh_structure(qpt, make):
     check_bvh4(nodes, order, sc, st.num_nodes, st.num_leaves)
 
 
+TOP_NODES = 64  # nodes the traversal kernels keep in LDS
+
+
+@pytest.mark.parametrize("make", [lambda: g.grid_scene(grid=4), lambda: g.city(blocks=4, target_tris=60_000,
+                                                                              emissive_cells=50)])
+def test_bvh_top_levels_first(qpt, make):
+    """The host builder numbers the tree breadth-first until TOP_NODES nodes
+    exist: the first TOP_NODES node numbers go to whole top levels in level
+    order (depth never decreases along them, and every node above the
+    deepest of them is among them), the root is node 0, and every node is
+    reachable from it exactly once (check_bvh4 covers the rest)."""
+    sc = make()
+    c = qpt.Context(-1)
+    c.build_scene(sc)
+    st = c.build_bvh()
+    nodes, _ = c.debug_bvh_nodes()
+    assert st.num_nodes > 2 * TOP_NODES
+    refs = nodes[:, 24:28].copy().view(np.int32)
+    used = nodes[:, 28:29].copy().view(np.int32)[:, 0]
+    depth = np.full(nodes.shape[0], -1, np.int64)
+    depth[0] = 0
+    frontier = [0]
+    while frontier:
+        nxt = []
+        for k in frontier:
+            for r in refs[k, :used[k]]:
+                if r >= 0:
+                    assert depth[r] == -1
+                    depth[r] = depth[k] + 1
+                    nxt.append(int(r))
+        frontier = nxt
+    assert np.all(depth >= 0)
+    top = depth[:TOP_NODES]
+    assert np.all(np.diff(top) >= 0), "the first nodes are in level order"
+    assert np.all(np.nonzero(depth < top[-1])[0] < TOP_NODES), "whole levels above the last staged one"
+
+
 @pytest.mark.parametrize("make", [lambda: g.light_field(n_lights=700), lambda: g.light_field(n_lights=300, env=True),
                                   lambda: g.grid_scene(grid=2), lambda: g.quad_over_plane(subdiv=12),
                                   lambda: g.light_field(n_lights=5)])
