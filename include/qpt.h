@@ -26,13 +26,17 @@
  *
  * Streams. All results are ordered on the stream given to qpt_create (a
  * hipStream_t; NULL = the default stream): a call's device work is complete
- * once that stream has reached the point after the call. Two more streams
- * carry work that overlaps it -- the second batch in flight and the guide's
- * training steps -- and the caller's stream waits on both with events before
- * any later work. The caller may provide them (qpt_set_streams, e.g. two
- * torch streams); otherwise qpt_bind_workspace creates them (default
- * priority, non-blocking) and qpt_destroy destroys them. Calls on one
- * context are not thread-safe; use one context per stream.
+ * once that stream has reached the point after the call. One more stream
+ * carries the second batch in flight (and the guide's training steps of the
+ * batches it renders), and the caller's stream waits on it with an event
+ * before any later work. The caller may provide it (qpt_set_streams);
+ * otherwise qpt_bind_workspace creates it (default priority, non-blocking)
+ * and qpt_destroy destroys it. The two batches overlap only while the two
+ * streams sit on different hardware queues of the device: HIP gives a new
+ * stream its least-used queue, so a stream the library creates after the
+ * caller's avoids the caller's queue while queues are to spare, whereas a
+ * stream taken from a round-robin pool (torch's) can land on it. Calls on
+ * one context are not thread-safe; use one context per stream.
  *
  * Call order: create -> build_scene -> build_bvh -> workspace_size ->
  * bind_workspace -> render_pass* -> readback; violations return QPT_E_STATE.
@@ -241,12 +245,15 @@ int qpt_bvh_scratch_size(qpt_ctx *ctx, size_t *bytes);
  * Synchronises the stream. */
 int qpt_build_bvh_noalloc(qpt_ctx *ctx, const qpt_bvh_opts *opts, qpt_bvh_stats *stats);
 
-/* Streams for the second batch in flight and for the guide's training steps
- * (hipStream_t each, not NULL, on the context's device; default priority
- * recommended), owned by the caller and kept alive until qpt_destroy. Only
- * before the first qpt_bind_workspace (QPT_E_STATE after it); without this
- * call the library creates both there and destroys them in qpt_destroy. */
-int qpt_set_streams(qpt_ctx *ctx, void *lane_stream, void *train_stream);
+/* The stream of the second batch in flight (a hipStream_t, not NULL and not
+ * the context's own stream, on the context's device, on a hardware queue of
+ * its own; default priority recommended), owned by the caller and kept alive
+ * until qpt_destroy. The guide's finalisation and training steps run on the
+ * stream of the batch they follow. Only before the first qpt_bind_workspace
+ * (QPT_E_STATE after it); without this call the library creates the stream
+ * there and destroys it in qpt_destroy. QPT_E_INVALID for a NULL stream or
+ * the context's own. */
+int qpt_set_streams(qpt_ctx *ctx, void *lane_stream);
 
 /* Bytes of device workspace needed for `pool_paths` concurrent paths per
  * batch (0 = sixteen frames' worth: the smallest power of two >= 16 W H,

@@ -333,15 +333,13 @@ struct qpt_ctx {
     bool guide_weights = false;
     uint32_t guide_steps = 0;
     uint32_t stack_need = 3;      // traversal stack entries per ray the BVH can require
-    // training runs on a stream of its own, one batch behind the renderer
-    hipStream_t tstream = nullptr;
-    bool own_tstream = false, own_lstream = false;   // created here (else the caller's, not destroyed)
+    // training runs on the lane that rendered the batch, right after it
+    bool own_lstream = false;                        // created here (else the caller's, not destroyed)
     void *static_scratch = nullptr;                  // this device's allocation-free build region
-    hipEvent_t ev_rec[2] = {nullptr, nullptr};    // lane k's latest batch has been rendered
-    hipEvent_t ev_fin[2] = {nullptr, nullptr};    // lane k's latest batch's samples are in the ring
     hipEvent_t ev_train[2] = {nullptr, nullptr};  // the step publishing into buffer k has finished
+    hipEvent_t ev_tdone = nullptr;                // the latest batch's samples and steps are done
     bool train_pending[2] = {false, false};
-    bool fin_pending[2] = {false, false};
+    bool tdone_pending = false;
     uint64_t gbatch = 0;   // training batches issued
     int last_buf = 0;      // buffer of the newest published weights
     uint2 *pub_frag[2] = {nullptr, nullptr};
@@ -991,16 +989,6 @@ Layout make_layout(const qpt_ctx *c, uint32_t cap)
 
 }  // namespace
 
-// wait for training work in flight on the context's training stream
-static hipError_t join_train(qpt_ctx *c)
-{
-    if (!c->tstream) return hipSuccess;
-    hipError_t e = hipStreamSynchronize(c->tstream);
-    c->train_pending[0] = c->train_pending[1] = false;
-    c->fin_pending[0] = c->fin_pending[1] = false;
-    return e;
-}
-
 // ================================================================== C-ABI
 
 extern "C" {
@@ -1040,16 +1028,13 @@ int qpt_create(int hip_device, void *hip_stream, qpt_ctx **out)
 void qpt_destroy(qpt_ctx *ctx)
 {
     if (!ctx) return;
-    if (ctx->tstream) {
-        DeviceGuard g(ctx->device);
-        (void)hipStreamSynchronize(ctx->tstream);
-        if (ctx->own_tstream) (void)hipStreamDestroy(ctx->tstream);
-    }
     for (int k = 0; k < 2; ++k) {
         DeviceGuard g(ctx->device);
-        if (ctx->ev_rec[k]) (void)hipEventDestroy(ctx->ev_rec[k]);
-        if (ctx->ev_fin[k]) (void)hipEventDestroy(ctx->ev_fin[k]);
         if (ctx->ev_train[k]) (void)hipEventDestroy(ctx->ev_train[k]);
+    }
+    if (ctx->ev_tdone) {
+        DeviceGuard g(ctx->device);
+        (void)hipEventDestroy(ctx->ev_tdone);
     }
     if (ctx->ev_lane_in) {
         DeviceGuard g(ctx->device);
@@ -1068,14 +1053,14 @@ void qpt_destroy(qpt_ctx *ctx)
     delete ctx;
 }
 
-int qpt_set_streams(qpt_ctx *c, void *lane_stream, void *train_stream)
+int qpt_set_streams(qpt_ctx *c, void *lane_stream)
 {
-    if (!c || !lane_stream || !train_stream) return QPT_E_INVALID;
+    if (!c || !lane_stream) return QPT_E_INVALID;
     if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
     if (c->ev_lane_in) return fail(c, QPT_E_STATE, "set_streams after the first bind_workspace");
+    if ((hipStream_t)lane_stream == c->stream) return fail(c, QPT_E_INVALID, "the second lane needs a stream of its own");
     c->lstream = (hipStream_t)lane_stream;
-    c->tstream = (hipStream_t)train_stream;
-    c->own_lstream = c->own_tstream = false;
+    c->own_lstream = false;
     return QPT_OK;
 }
 
@@ -1514,24 +1499,19 @@ int qpt_bind_workspace(qpt_ctx *c, void *device_ptr, size_t bytes, uint32_t pool
     if (bytes < L.total) return fail(c, QPT_E_NOMEM, "workspace %zu bytes, need %zu", bytes, L.total);
     DeviceGuard g(c->device);
     if (!g.ok) return fail(c, QPT_E_HIP, "hipSetDevice failed");
-    HIP_TRY(c, join_train(c));
     if (!c->ev_lane_in) {
-        // the second lane's and the training stream: the caller's (qpt_set_streams), else
-        // the library's own, default priority, non-blocking so they can overlap a
-        // caller's legacy stream
-        if (!c->tstream) {
-            HIP_TRY(c, hipStreamCreateWithFlags(&c->tstream, hipStreamNonBlocking));
-            c->own_tstream = true;
-        }
+        // the second lane's stream: the caller's (qpt_set_streams), else the
+        // library's own, default priority, non-blocking so it can overlap a
+        // caller's legacy stream. HIP places a new stream on its least-used
+        // hardware queue, which keeps it off the caller's queue while the
+        // device has queues to spare; two lanes sharing one queue would run
+        // one after the other.
         if (!c->lstream) {
             HIP_TRY(c, hipStreamCreateWithFlags(&c->lstream, hipStreamNonBlocking));
             c->own_lstream = true;
         }
-        for (int k = 0; k < 2; ++k) {
-            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_rec[k], hipEventDisableTiming));
-            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fin[k], hipEventDisableTiming));
-            HIP_TRY(c, hipEventCreateWithFlags(&c->ev_train[k], hipEventDisableTiming));
-        }
+        for (int k = 0; k < 2; ++k) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_train[k], hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->ev_tdone, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_in, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_lane_out, hipEventDisableTiming));
         HIP_TRY(c, hipEventCreateWithFlags(&c->ev_acc, hipEventDisableTiming));
@@ -1686,7 +1666,6 @@ int qpt_load_accum(qpt_ctx *c, const double *sum_rgb, const uint32_t *counts, in
     if (!c || !sum_rgb || !counts) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "load_accum before bind_workspace");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     const size_t npix = (size_t)c->W * c->H;
     const hipMemcpyKind k = src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIP_TRY(c, hipMemcpyAsync(c->pool.fb_sum, sum_rgb, npix * 3 * 8, k, c->stream));
@@ -1756,8 +1735,12 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
     f.regen = regen ? o->regen_paths : 0u;
     const bool two_lanes = !o->single_stream && !regen;
     bool lane_b_used = false;
-    // the point lane 1 waits for: the caller's work before this call
+    // the point lane 1 waits for: the caller's work before this call, which
+    // the caller's stream orders after all work of earlier calls (lane 1's
+    // included), so no wait on an event of an earlier call is needed
     if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_lane_in, c->stream));
+    c->train_pending[0] = c->train_pending[1] = false;
+    c->tdone_pending = false;
     // one batch of passes (or of pixels), then one training step if enabled
     auto batch = [&](uint32_t p0, uint32_t np, uint64_t pass0, uint32_t nb) -> int {
         // pixel chunks of one pass stay on one lane (its first chunk latches the
@@ -1770,10 +1753,7 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         }
         const Pool &P = lane_b ? c->pool_b : c->pool;
         const int lane = lane_b ? 1 : 0;
-        // the lane's path pool and training records are free again once the
-        // training stream has finalised the lane's previous batch
-        if (c->fin_pending[lane]) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_fin[lane], 0));
-        f.guide.rec = c->lane_rec[lane_b ? 1 : 0];
+        f.guide.rec = c->lane_rec[lane];
         f.guide.rec_count = P.counters + 127;
         bool active = c->gopts.alpha > 0.0f && c->guide_steps >= c->gopts.warmup_steps;
         uint64_t thr = active ? (uint64_t)std::llround((double)c->gopts.alpha * 4294967296.0) : 0;
@@ -1790,13 +1770,16 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         }
         // The renderer's copy of the weights is double-buffered: batch b
         // renders with the weights the step of batch b - 2 published (buffer
-        // b mod 2, free once that step has finished) while the step of batch
-        // b - 1 runs on the training stream. Any weights give an unbiased
-        // estimator; the lag only delays what the guide has learnt. Batch b's
-        // samples enter the replay ring on the training stream, behind the
-        // steps already there (the only readers of the ring), so no render
-        // lane waits for training; the lane's next batch, which overwrites
-        // the path radiance the samples are formed from, waits for that.
+        // b mod 2) while the other lane renders batch b - 1 and then takes its
+        // step. Any weights give an unbiased estimator; the lag only delays
+        // what the guide has learnt. A batch's samples enter the replay ring
+        // and its steps run on the lane that rendered it, right after the
+        // batch (the lane's next batch overwrites the path radiance the
+        // samples are formed from, and renders with the weights these steps
+        // publish), behind the previous batch's steps on the other lane (the
+        // ring and the Adam state are shared), so steps keep batch order. No
+        // third stream: one that shared a hardware queue with a lane would
+        // hold that lane's kernels behind its waits.
         const bool train = c->gopts.train > 0;
         const int k = train ? (int)(c->gbatch & 1) : c->last_buf;
         if (guiding) {
@@ -1817,27 +1800,26 @@ int qpt_render_pass(qpt_ctx *c, uint64_t first_pass, uint32_t num_passes, const 
         if (two_lanes) HIP_TRY(c, hipEventRecord(c->ev_acc, s));
         if (train) {
             GuideTrain T = c->gt;
-            // finalisation in batch order on the training stream (see above)
-            HIP_TRY(c, hipEventRecord(c->ev_rec[lane], s));
-            HIP_TRY(c, hipStreamWaitEvent(c->tstream, c->ev_rec[lane], 0));
-            if (prof) prof->begin(K_GUIDE_TRAIN, c->tstream);
-            HIP_TRY(c, launch_guide_finalize(f, P, T, c->tstream));
-            HIP_TRY(c, hipEventRecord(c->ev_fin[lane], c->tstream));
-            c->fin_pending[lane] = true;
+            // finalisation and steps in batch order (see above)
+            if (c->tdone_pending) HIP_TRY(c, hipStreamWaitEvent(s, c->ev_tdone, 0));
+            if (prof) prof->begin(K_GUIDE_TRAIN, s);
+            HIP_TRY(c, launch_guide_finalize(f, P, T, s));
             // `train` Adam steps per pass, taken when a batch completes its passes
             // (a pass split into pixel chunks trains after its last chunk)
             const uint32_t nsteps = (p0 + np >= npix) ? c->gopts.train * nb : 0u;
             if (nsteps) {
                 HIP_TRY(c, launch_guide_train_steps(f, T, c->gopts.batch ? c->gopts.batch : (1u << 18),
                                                     c->guide_steps + 1, nsteps, c->gopts.lr, c->gopts.seed,
-                                                    c->tstream, c->pub_frag[k], c->pub_bias[k]));
-                HIP_TRY(c, hipEventRecord(c->ev_train[k], c->tstream));
+                                                    s, c->pub_frag[k], c->pub_bias[k]));
+                HIP_TRY(c, hipEventRecord(c->ev_train[k], s));
                 c->train_pending[k] = true;
                 c->last_buf = k;
                 c->guide_steps += nsteps;
                 ++c->gbatch;
             }
-            if (prof) prof->end(K_GUIDE_TRAIN, c->tstream);
+            HIP_TRY(c, hipEventRecord(c->ev_tdone, s));
+            c->tdone_pending = true;
+            if (prof) prof->end(K_GUIDE_TRAIN, s);
         }
         return QPT_OK;
     };
@@ -1877,7 +1859,6 @@ int qpt_readback(qpt_ctx *c, double *sum_rgb, uint32_t *counts, int dst_is_devic
     if (!c) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "readback before bind_workspace");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     size_t npix = (size_t)c->W * c->H;
     hipMemcpyKind k = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (sum_rgb) HIP_TRY(c, hipMemcpyAsync(sum_rgb, c->pool.fb_sum, npix * 3 * 8, k, c->stream));
@@ -1923,7 +1904,6 @@ int qpt_profile(qpt_ctx *c, int enable)
     DeviceGuard g(c->device);
     if (enable) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        HIP_TRY(c, join_train(c));
         c->prof.clear();
     }
     c->profiling = enable != 0;
@@ -1936,7 +1916,6 @@ int qpt_profile_read(qpt_ctx *c, qpt_kernel_time *out)
     if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
     DeviceGuard g(c->device);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, join_train(c));
     for (int k = 0; k < QPT_K_KINDS; ++k) out[k] = qpt_kernel_time{0, 0, 0.0};
     for (const EventProfiler::Rec &r : c->prof.recs) {
         if (!r.a || !r.b || r.kind < 0 || r.kind >= QPT_K_KINDS) continue;
@@ -2000,7 +1979,6 @@ int qpt_guide_set_weights(qpt_ctx *c, const float *params)
     for (uint32_t p = 0; p < kGuideParams; ++p)
         if (!std::isfinite(params[p])) return fail(c, QPT_E_INVALID, "non-finite guide parameter");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     HIP_TRY(c, hipMemcpyAsync(c->gt.master, params, kGuideParams * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->gt.m, 0, kGuideParams * 4, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->gt.v, 0, kGuideParams * 4, c->stream));
@@ -2017,7 +1995,6 @@ int qpt_guide_get_state(qpt_ctx *c, float *params, float *m, float *v, uint32_t 
     if (!c) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     if (params) HIP_TRY(c, hipMemcpyAsync(params, c->gt.master, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
     if (m) HIP_TRY(c, hipMemcpyAsync(m, c->gt.m, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
     if (v) HIP_TRY(c, hipMemcpyAsync(v, c->gt.v, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
@@ -2048,7 +2025,6 @@ int qpt_guide_get_weights(qpt_ctx *c, float *params, uint32_t *steps)
     if (!c) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     if (params) HIP_TRY(c, hipMemcpyAsync(params, c->gt.master, kGuideParams * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (steps) *steps = c->guide_steps;
@@ -2061,7 +2037,6 @@ int qpt_guide_debug_forward(qpt_ctx *c, const float *x, uint32_t n, float *out)
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     Frame f = c->frame;
     HIP_TRY(c, launch_guide_debug_forward(f, x, n, out, c->stream));
     return QPT_OK;
@@ -2073,7 +2048,6 @@ int qpt_guide_debug_eval(qpt_ctx *c, const float *x, const float *wo, uint32_t n
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     if (!n) return QPT_OK;
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     // the renderer's copy of the newest weights (its output order, see k_guide_frag)
     Frame f = c->frame;
     f.guide.frag = c->pub_frag[c->last_buf];
@@ -2087,7 +2061,6 @@ int qpt_guide_debug_grad(qpt_ctx *c, const float *x, const float *dirs, const fl
     if (!c || !n || !x || !dirs || !w || !grad) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 0, 0u, 0.0f, c->stream, nullptr, nullptr,
                                        nullptr, nullptr));
     return QPT_OK;
@@ -2099,7 +2072,6 @@ int qpt_guide_debug_train(qpt_ctx *c, const float *x, const float *dirs, const f
     if (!c || !n || !x || !dirs || !w || !(lr > 0.0f)) return QPT_E_INVALID;
     if (!c->bound || !c->guide_weights) return fail(c, QPT_E_STATE, "no guide weights");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     ++c->guide_steps;
     HIP_TRY(c, launch_guide_debug_grad(c->frame, c->gt, x, dirs, w, n, grad, 1, c->guide_steps, lr, c->stream,
                                        c->pub_frag[0], c->pub_bias[0], c->pub_frag[1], c->pub_bias[1]));
@@ -2111,7 +2083,6 @@ int qpt_guide_loss(qpt_ctx *c, double *loss, double *weight_sum)
     if (!c) return QPT_E_INVALID;
     if (!c->bound) return fail(c, QPT_E_STATE, "no workspace bound");
     DeviceGuard g(c->device);
-    HIP_TRY(c, join_train(c));
     float sc[2];
     HIP_TRY(c, hipMemcpyAsync(sc, c->gt.scalars, sizeof sc, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));

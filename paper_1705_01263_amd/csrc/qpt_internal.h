@@ -18,6 +18,8 @@ constexpr uint32_t kMaxTreeDepth = 32;   // depth limit of the binary build tree
 constexpr uint32_t kTravBlocksPerCU = 16; // traversal grid: 16 blocks of 4 waves per CU, twice what is resident
 constexpr uint32_t kShadeGuidedBlock = 512;     // guided shading: 8 waves share the weights in LDS
 constexpr uint32_t kShadeGuidedBlocksPerCU = 2;  // 69 KB of LDS per block (weights, 512 mixtures)
+// waves per SIMD of two such blocks on a CU: the register budget the kernel is compiled for (128 VGPRs)
+constexpr uint32_t kShadeGuidedWavesPerSIMD = kShadeGuidedBlocksPerCU * kShadeGuidedBlock / 64 / 4;
 constexpr uint32_t kShadeGuidedGridPerCU = 8;    // its grid: blocks per CU
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
 constexpr uint32_t kNoHit = 0xffffffffu;

@@ -1389,7 +1389,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
 // mixtures, so after the weights are staged the waves synchronise with
 // themselves only. Blocks without rows leave before staging the weights
 // (uniform per block, so the one block barrier is reached by all).
-__global__ __launch_bounds__(kShadeGuidedBlock, kShadeGuidedBlocksPerCU) void k_shade_guided(Frame F, Pool P, uint32_t v)
+__global__ __launch_bounds__(kShadeGuidedBlock, kShadeGuidedWavesPerSIMD) void k_shade_guided(Frame F, Pool P, uint32_t v)
 {
     __shared__ uint2 sfrag[kGuideFrags * 64];
     __shared__ __align__(16) float sbias[256];

@@ -107,7 +107,7 @@ def lib():
             "qpt_build_bvh": ([P, C.POINTER(qpt_bvh_opts), C.POINTER(qpt_bvh_stats)], i32),
             "qpt_build_bvh_noalloc": ([P, C.POINTER(qpt_bvh_opts), C.POINTER(qpt_bvh_stats)], i32),
             "qpt_bvh_scratch_size": ([P, C.POINTER(C.c_size_t)], i32),
-            "qpt_set_streams": ([P, P, P], i32),
+            "qpt_set_streams": ([P, P], i32),
             "qpt_workspace_size": ([P, u32, C.POINTER(C.c_size_t)], i32),
             "qpt_bind_workspace": ([P, P, C.c_size_t, u32], i32),
             "qpt_render_pass": ([P, u64, u32, C.POINTER(qpt_render_opts)], i32),
@@ -241,9 +241,8 @@ class Context:
         self.check(self.L.qpt_bvh_scratch_size(self.h, C.byref(n)), "qpt_bvh_scratch_size")
         return n.value
 
-    def set_streams(self, lane_stream: int, train_stream: int) -> None:
-        self.check(self.L.qpt_set_streams(self.h, C.c_void_p(lane_stream), C.c_void_p(train_stream)),
-                   "qpt_set_streams")
+    def set_streams(self, lane_stream: int) -> None:
+        self.check(self.L.qpt_set_streams(self.h, C.c_void_p(lane_stream)), "qpt_set_streams")
 
     def workspace_size(self, pool_paths: int = 0) -> int:
         n = C.c_size_t()
@@ -434,7 +433,7 @@ class Renderer:
     """Scene + BVH + a torch-owned workspace on one GPU; renders 1-spp passes."""
 
     def __init__(self, sc, device: int = 0, pool_paths: int = 0, stream=None, bvh_builder: int = 0,
-                 node_format: int = 0):
+                 node_format: int = 0, lane_stream=None):
         import torch
 
         self.torch = torch
@@ -442,9 +441,13 @@ class Renderer:
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.ctx = Context(device, self.stream.cuda_stream)
-        # the second batch in flight and the guide's training run on torch streams (default priority)
-        self.aux_streams = (torch.cuda.Stream(self.device), torch.cuda.Stream(self.device))
-        self.ctx.set_streams(self.aux_streams[0].cuda_stream, self.aux_streams[1].cuda_stream)
+        # the second batch in flight: on the library's own stream unless one is
+        # given (torch's stream pool hands out streams round-robin over the
+        # device's few hardware queues, so a pool stream can share the
+        # caller's queue, and the two batches then run one after the other)
+        self.lane_stream = lane_stream
+        if lane_stream is not None:
+            self.ctx.set_streams(lane_stream.cuda_stream)
         self.ctx.ntri = sc.num_triangles
         self.ctx.build_scene(sc)
         if bvh_builder == 1:

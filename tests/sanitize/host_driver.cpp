@@ -156,7 +156,7 @@ static void run_scene(const char *path)
     qpt_render_opts ro{};
     ro.max_depth = 4;
     CHECK(qpt_render_pass(c, 0, 1, &ro) == QPT_E_STATE);
-    CHECK(qpt_set_streams(c, nullptr, nullptr) == QPT_E_INVALID);
+    CHECK(qpt_set_streams(c, nullptr) == QPT_E_INVALID);
     std::printf("%s: %u triangles, %u emitters, %u light-tree nodes: ok\n", path, nt, ne, nn);
     qpt_destroy(c);
 }
