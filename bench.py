@@ -47,7 +47,7 @@ WORKLOADS = {
                 "depth 12, "
                 "NEE+MIS, roulette"),
     "city": ("city_16m", "procedural city, 16.0M triangles, 5,000 emissive window cells (10k triangles, alias-table light "
-                "selection), 3840x2160, 1 spp per step (passes in nearly equal batches of at most eight frames, two "
+                "selection), 3840x2160, 1 spp per step (passes in nearly equal batches of at most sixteen frames, two "
                 "batches in flight), max depth 16, NEE+MIS, roulette"),
 }
 # the guided tracer's settings in the equal-time legs
@@ -685,8 +685,8 @@ def main():
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=24, help="timed passes (24 = three batches of eight frames at 4K)")
-    ap.add_argument("--warmup", type=int, default=8, help="untimed passes (8 = one batch at 4K)")
+    ap.add_argument("--steps", type=int, default=24, help="timed passes (24 = two batches of twelve at 4K)")
+    ap.add_argument("--warmup", type=int, default=8, help="untimed passes (8 = one batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
@@ -763,7 +763,7 @@ def main():
     bs = r.bvh_stats
     _say(f"bench: bvh nodes={bs.num_nodes} leaves={bs.num_leaves} depth={bs.max_depth} build={bs.build_ms:.0f} ms")
     # the passes go to the library as one range, which renders them in batches
-    # of as many whole passes as its path pool holds (eight frames' worth)
+    # of as many whole passes as its path pool holds (sixteen frames' worth)
     cs = args.compress_state
     td = args.tail_depth if args.tail_depth >= 0 else D // 2
     r.render(0, args.warmup, compress_state=cs, tail_depth=td)
@@ -887,7 +887,7 @@ def main():
         if args.workload == "city" and not args.no_et_city:
             _say("bench: equal time, guided vs plain, on the city")
             et.append(equal_time(sc, [("the workload's camera", None)], args.et_city_seconds, args.et_city_ref_passes,
-                                 16, oracle_scene=S, oracle_seconds=args.et_oracle_seconds, oracle_stride=(64, 64)))
+                                 32, oracle_scene=S, oracle_seconds=args.et_oracle_seconds, oracle_stride=(64, 64)))
             torch.cuda.empty_cache()
         S = None
         w, h = (int(v) for v in args.et_size.split("x"))

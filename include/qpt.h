@@ -257,7 +257,7 @@ int qpt_set_streams(qpt_ctx *ctx, void *lane_stream);
 
 /* Bytes of device workspace needed for `pool_paths` concurrent paths per
  * batch (0 = sixteen frames' worth: the smallest power of two >= 16 W H,
- * within [2^16, 2^26]). A range of passes is rendered in as few batches of whole
+ * within [2^16, 2^27]). A range of passes is rendered in as few batches of whole
  * passes as the pool allows, of nearly equal size (or in pixel chunks of one
  * pass when a frame exceeds the pool); larger batches keep the queues of deep
  * vertices full. The workspace holds two such

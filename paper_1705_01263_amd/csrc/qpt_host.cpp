@@ -900,13 +900,13 @@ void set_frame_constants(qpt_ctx *c)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // paths per batch when the caller leaves it to the library: sixteen frames'
-// worth (a power of two in [2^16, 2^26]; two such pools take 16 GB at 1080p
-// and 33 GB at 4K with the guide's buffers); batches of several one-sample
+// worth (a power of two in [2^16, 2^27]; two such pools take 16 GB at 1080p
+// and 40 GB at 4K with the guide's buffers); batches of several one-sample
 // passes keep the short queues of deep vertices full
 uint32_t default_pool(const qpt_ctx *c)
 {
     uint64_t want = 16ull * c->W * c->H, cap = 1u << 16;
-    while (cap < want && cap < (1u << 26)) cap <<= 1;
+    while (cap < want && cap < (1u << 27)) cap <<= 1;
     return (uint32_t)cap;
 }
 
