@@ -417,6 +417,13 @@ int qpt_profile_read(qpt_ctx *ctx, qpt_kernel_time *out);
 int qpt_debug_sample_bits(qpt_ctx *ctx, const uint64_t *idx, const uint32_t *dim, uint32_t n,
                           int scramble, uint32_t *out);
 
+/* out[w] = in[64 w] + ... + in[64 w + 63] modulo 2^32 for w < n / 64, by
+ * the wavefront reduction (DPP row moves, then the four row sums) that the
+ * traversal kernels use to add their lanes' node and triangle counts. n must
+ * be a multiple of 64 (QPT_E_INVALID otherwise). Needs a context on a
+ * device; no workspace. */
+int qpt_debug_wave_sum(qpt_ctx *ctx, const uint32_t *in, uint32_t n, uint32_t *out);
+
 /* out[y*width + x] = Halton index of pixel (x, y) in iteration `pass`. */
 int qpt_debug_pixel_index(qpt_ctx *ctx, uint64_t pass, uint64_t *out);
 
@@ -426,7 +433,7 @@ int qpt_debug_pixel_index(qpt_ctx *ctx, uint64_t pass, uint64_t *out);
  * b12[2n] barycentrics of vertices 1 and 2. any_hit = 1: tri[q] = 1 if
  * occluded, else 0 (t and b12 may be NULL). stack_max (may be NULL; BVH
  * mode only) receives each ray's deepest traversal stack: entries beyond
- * the 16 kept in LDS spill to the workspace's overflow area. */
+ * the 15 kept in LDS spill to the workspace's overflow area. */
 int qpt_debug_trace(qpt_ctx *ctx, const float *rays, uint32_t n, int any_hit, int brute_force,
                     float *t, uint32_t *tri, float *b12, uint32_t *stack_max);
 

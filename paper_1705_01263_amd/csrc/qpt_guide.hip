@@ -78,7 +78,7 @@ __device__ __forceinline__ void gather40(const v16f *acc, float *o)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         float mine = acc[0][v];
-        float other = __shfl_xor(mine, 32);
+        float other = guide::xor32(mine);
         int f = 8 * (v / 4) + (v % 4);
         o[f] = hi ? other : mine;       // features with 4(l/32) = 0
         o[f + 4] = hi ? mine : other;   // features with 4(l/32) = 4
@@ -86,7 +86,7 @@ __device__ __forceinline__ void gather40(const v16f *acc, float *o)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         float mine = acc[1][v];
-        float other = __shfl_xor(mine, 32);
+        float other = guide::xor32(mine);
         o[32 + v] = hi ? other : mine;
         o[36 + v] = hi ? mine : other;
     }
@@ -108,11 +108,11 @@ __device__ __forceinline__ void gather40(const v16f *acc, float *o)
 __device__ __forceinline__ void pair_loss_grad(const v16f *out, guide::V3 wd, float w, v16f *dz, float &loss)
 {
     float mx = fmaxf(fmaxf(out[0][0], out[0][1]), fmaxf(out[0][2], out[0][3]));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    mx = fmaxf(mx, guide::xor32(mx));
     float se = 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) se += __expf(out[0][j] - mx);
-    se += __shfl_xor(se, 32);
+    se += guide::xor32(se);
     const float lse = __logf(se);
     float lp[4], kap[4], inv_mn[4], cw[4], mu[4][3], em[4], lf[4];
     bool clamped[4];
@@ -133,14 +133,14 @@ __device__ __forceinline__ void pair_loss_grad(const v16f *out, guide::V3 wd, fl
         lf[j] = lp[j] + __logf(kap[j] / (2.0f * guide::kPiF * -em[j])) + kap[j] * (cw[j] - 1.0f);
         lmax = fmaxf(lmax, lf[j]);
     }
-    lmax = fmaxf(lmax, __shfl_xor(lmax, 32));
+    lmax = fmaxf(lmax, guide::xor32(lmax));
     float g[4], sg = 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         g[j] = __expf(lf[j] - lmax);
         sg += g[j];
     }
-    sg += __shfl_xor(sg, 32);
+    sg += guide::xor32(sg);
     loss = -w * (lmax + __logf(sg));
     const float inv = 1.0f / sg;
 #pragma unroll

@@ -27,6 +27,19 @@ __device__ constexpr float kOct[4] = {1.0f, 2.0f, 4.0f, 8.0f};
 struct V3 {
     float x, y, z;
 };
+
+// the value of lane l ^ 32 (the other half of the wave), by gfx950's
+// v_permlane32_swap, which exchanges one register's upper half with another
+// register's lower half: given the value twice, one of the two results
+// holds the partner's value on each lane and the other the lane's own, so
+// XOR-ing both with the own value leaves the partner's bits whichever of
+// the two results it is in (no LDS crossbar round trip as with a shuffle)
+__device__ __forceinline__ uint32_t xor32_u32(uint32_t v)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return r[0] ^ r[1] ^ v;
+}
+__device__ __forceinline__ float xor32(float v) { return __uint_as_float(xor32_u32(__float_as_uint(v))); }
 __device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
 // sin and cos of 2 pi r for an angle r given in revolutions (hardware

@@ -197,12 +197,12 @@ __device__ __forceinline__ void infer_pair(const uint2 *sfrag, const float *sbia
     // logit out[0][j], mean direction out[0][4 + j], out[0][8 + j],
     // out[0][12 + j], concentration out[1][j]
     float mx = fmaxf(fmaxf(out[0][0], out[0][1]), fmaxf(out[0][2], out[0][3]));
-    mx = fmaxf(mx, __shfl_xor(mx, 32));
+    mx = fmaxf(mx, guide::xor32(mx));
     float e[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) e[j] = __expf(out[0][j] - mx);
     float se = (e[0] + e[1]) + (e[2] + e[3]);
-    se += __shfl_xor(se, 32);
+    se += guide::xor32(se);
     if (!valid) return;
     const float inv = 1.0f / se;
     uint32_t q[8];
@@ -228,9 +228,9 @@ __device__ __forceinline__ void infer_wave64(const uint2 *sfrag, const float *sb
                                              bool valid, const float *bmin, const float *binv, uint4 *rows)
 {
     const uint32_t lane = lane_id(), h = lane >> 5;
-    const guide::V3 xp = {__shfl_xor(x.x, 32), __shfl_xor(x.y, 32), __shfl_xor(x.z, 32)};
-    const guide::V3 wp = {__shfl_xor(wo.x, 32), __shfl_xor(wo.y, 32), __shfl_xor(wo.z, 32)};
-    const bool vp = __shfl_xor((int)valid, 32) != 0;
+    const guide::V3 xp = {guide::xor32(x.x), guide::xor32(x.y), guide::xor32(x.z)};
+    const guide::V3 wp = {guide::xor32(wo.x), guide::xor32(wo.y), guide::xor32(wo.z)};
+    const bool vp = guide::xor32_u32(valid ? 1u : 0u) != 0u;
     infer_pair(sfrag, sbias, h ? xp : x, h ? wp : wo, bmin, binv, h ? vp : valid, rows + (lane & 31u) * guide::kMixU4);
     // the second pass reads the weights from LDS again: shared between the
     // passes, the 56 fragments would stay live in registers

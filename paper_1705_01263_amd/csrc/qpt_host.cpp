@@ -1938,6 +1938,16 @@ int qpt_debug_sample_bits(qpt_ctx *c, const uint64_t *idx, const uint32_t *dim, 
     return QPT_OK;
 }
 
+int qpt_debug_wave_sum(qpt_ctx *c, const uint32_t *in, uint32_t n, uint32_t *out)
+{
+    if (!c || (n && (!in || !out)) || (n & 63u)) return QPT_E_INVALID;
+    if (c->device < 0) return fail(c, QPT_E_STATE, "context has no device");
+    if (!n) return QPT_OK;
+    DeviceGuard g(c->device);
+    HIP_TRY(c, launch_debug_wave_sum(in, n, out, c->stream));
+    return QPT_OK;
+}
+
 int qpt_debug_pixel_index(qpt_ctx *c, uint64_t pass, uint64_t *out)
 {
     if (!c || !out) return QPT_E_INVALID;

@@ -295,6 +295,7 @@ hipError_t launch_guide_debug_grad(const Frame &f, const GuideTrain &T, const fl
 hipError_t launch_guide_debug_mixture(const float *out40, const float *dirs, const float *u, uint32_t n,
                                       float *pdf, float *sample, hipStream_t s);
 
+hipError_t launch_debug_wave_sum(const uint32_t *in, uint32_t n, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_sample_bits(const Frame &f, const uint64_t *idx, const uint32_t *dim,
                                     uint32_t n, int scramble, uint32_t *out, hipStream_t s);
 hipError_t launch_debug_pixel_index(const Frame &f, uint64_t pass, uint64_t *out, hipStream_t s);

@@ -288,10 +288,25 @@ struct HitRec {
     uint32_t depth;         // deepest traversal stack (DEPTH = true only)
 };
 
+// sum of a per-lane count over the wave (every lane active): within each
+// row of 16 lanes by DPP moves (pairs and quads by quad permutes, then the
+// half-row and row mirrors, each lane adding its image), then the four row
+// sums read by the scalar unit -- no LDS round trips
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1, 0, 3, 2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2, 3, 0, 1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
 // sum a per-lane count over the wave and add it to a 64-bit counter once
+// (called with every lane of the wave active)
 __device__ __forceinline__ void wave_count(unsigned long long *ctr, uint32_t v)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    v = wave_sum_u32(v);
     if (__lane_id() == 0 && v) atomicAdd(ctr, (unsigned long long)v);
 }
 
@@ -1652,6 +1667,16 @@ __global__ __launch_bounds__(kBlock) void k_accumulate(Frame F, Pool P, uint32_t
     P.fb_count[p] += npass;
 }
 
+// per-wave sums of in[0 .. n) (n a multiple of 64, so a wave is either
+// wholly in range, every lane active, or wholly out)
+__global__ __launch_bounds__(kBlock) void k_debug_wave_sum(const uint32_t *in, uint32_t n, uint32_t *out)
+{
+    const size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t s = wave_sum_u32(in[q]);
+    if (__lane_id() == 0) out[q / 64] = s;
+}
+
 __global__ void k_debug_sample_bits(Frame F, const uint64_t *idx, const uint32_t *dim, uint32_t n, int scramble,
                                     uint32_t *out)
 {
@@ -1901,6 +1926,12 @@ hipError_t launch_debug_records(const Frame &F, const Pool &P, uint32_t pix0, ui
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_debug_records, dim3((n + 255) / 256), dim3(256), 0, s, F, P, pix0, npix, pass0, npass, n,
                        ident, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_wave_sum(const uint32_t *in, uint32_t n, uint32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_wave_sum, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, in, n, out);
     return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ EXPORTS = [
     "qpt_create", "qpt_destroy", "qpt_last_error", "qpt_build_scene", "qpt_build_bvh", "qpt_build_bvh_noalloc",
     "qpt_bvh_scratch_size", "qpt_set_streams", "qpt_workspace_size",
     "qpt_bind_workspace", "qpt_render_pass", "qpt_readback", "qpt_reset_accum", "qpt_get_stats",
-    "qpt_debug_sample_bits", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
+    "qpt_debug_sample_bits", "qpt_debug_wave_sum", "qpt_debug_pixel_index", "qpt_debug_trace", "qpt_debug_light_tables",
     "qpt_abort", "qpt_load_accum", "qpt_guide_get_state", "qpt_guide_set_state",
     "qpt_debug_light_tree", "qpt_debug_light_sample", "qpt_debug_env_pyramid", "qpt_debug_env_sample",
     "qpt_debug_env_tables", "qpt_debug_bvh_nodes", "qpt_profile", "qpt_profile_read", "qpt_guide_config",
@@ -115,6 +115,7 @@ def lib():
             "qpt_reset_accum": ([P], i32),
             "qpt_get_stats": ([P, C.POINTER(qpt_stats)], i32),
             "qpt_debug_sample_bits": ([P, P, P, u32, i32, P], i32),
+            "qpt_debug_wave_sum": ([P, P, u32, P], i32),
             "qpt_debug_pixel_index": ([P, u64, P], i32),
             "qpt_debug_trace": ([P, P, u32, i32, i32, P, P, P, P], i32),
             "qpt_debug_light_tables": ([P, P, P, P, P, P], i32),
@@ -351,6 +352,9 @@ class Context:
     def debug_sample_bits(self, idx, dim, n, scramble, out) -> None:
         self.check(self.L.qpt_debug_sample_bits(self.h, _p(idx), _p(dim), n, int(scramble), _p(out)),
                    "qpt_debug_sample_bits")
+
+    def debug_wave_sum(self, inp, n: int, out) -> None:
+        self.check(self.L.qpt_debug_wave_sum(self.h, _p(inp), n, _p(out)), "qpt_debug_wave_sum")
 
     def debug_pixel_index(self, pass_: int, out) -> None:
         self.check(self.L.qpt_debug_pixel_index(self.h, pass_, _p(out)), "qpt_debug_pixel_index")

@@ -408,6 +408,48 @@ def test_two_lanes_bit_identical(Renderer, pool):
     assert t1 == t2
 
 
+def test_wave_sum_dpp(Renderer):
+    """The wavefront reduction the traversal kernels add their lanes' node
+    and triangle counts with (DPP row moves, then the four row sums) equals
+    numpy's sums modulo 2^32: random counts, sums that wrap, one lane set,
+    all lanes at the maximum."""
+    from paper_1705_01263_amd import qpt
+    rng = np.random.default_rng(11)
+    waves = 4096
+    a = rng.integers(0, 1 << 20, size=(waves, 64), dtype=np.uint64)
+    a[1] = rng.integers(0, 1 << 32, size=64, dtype=np.uint64)   # wraps modulo 2^32
+    a[2] = 0
+    a[2, 37] = 12345                                            # one lane
+    a[3] = (1 << 32) - 1                                        # every lane at the maximum
+    a[4] = np.arange(64, dtype=np.uint64) << np.uint64(20)      # lane-dependent, no two equal
+    want = (a.sum(axis=1) % (1 << 32)).astype(np.uint32)
+    inp = torch.from_numpy(a.astype(np.uint32).reshape(-1).view(np.int32)).cuda()
+    out = torch.zeros(waves, dtype=torch.int32, device="cuda")
+    ctx = qpt.Context(0, torch.cuda.current_stream(0).cuda_stream)
+    ctx.debug_wave_sum(inp, waves * 64, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), want)
+    with pytest.raises(qpt.QptError):
+        ctx.debug_wave_sum(inp, 100, out)   # not whole waves
+
+
+def test_caller_lane_stream_bit_identical(Renderer):
+    """The second batch in flight on a stream the caller provides
+    (qpt_set_streams) renders the same sums and counts as on the library's
+    own; the context's own stream is refused for it."""
+    from paper_1705_01263_amd import qpt
+    sc = g.cornell(width=64, height=48)
+    base, cb, _ = _render(Renderer, sc, 40)
+    lane = torch.cuda.Stream(0)
+    r = Renderer(sc, lane_stream=lane)
+    r.render(0, 40)
+    s, c = r.readback()
+    assert np.array_equal(c, cb) and np.array_equal(s, base)
+    ctx = qpt.Context(0, torch.cuda.current_stream(0).cuda_stream)
+    with pytest.raises(qpt.QptError):
+        ctx.set_streams(torch.cuda.current_stream(0).cuda_stream)
+
+
 def test_counts_and_stats(Renderer):
     sc = g.cornell(width=32, height=32)
     _, c, r = _render(Renderer, sc, 5)
