@@ -68,6 +68,51 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred)
     return base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
 }
 
+// Appends of a whole block to three counters with one atomic per counter
+// and block (a device-wide atomic on one address is served one at a time, so
+// every wave of a large launch taking its own slots serialised on it): each
+// wave ballots its lanes, the waves' counts meet in LDS, three lanes turn them
+// into offsets and reserve the block's totals, and every lane finds its place
+// from its wave's offset and mbcnt. Every thread of the block calls it, with
+// no lane of a wave inactive (two block barriers); s holds 3 x (waves + 1)
+// words of LDS. A wave writes only its own counts and reads only its own
+// offsets and the totals, which change only after the next call's first
+// barrier, so calls in a loop need no further barrier.
+constexpr uint32_t kAppendWaves = 8;  // the most waves per block that append
+static_assert(kBlock / 64 <= kAppendWaves && kShadeGuidedBlock / 64 <= kAppendWaves, "appending blocks fit the LDS counts");
+__device__ __forceinline__ void block_append3(uint32_t *c0, bool p0, uint32_t *c1, bool p1, uint32_t *c2, bool p2,
+                                              uint32_t *s, uint32_t &o0, uint32_t &o1, uint32_t &o2)
+{
+    constexpr uint32_t S = kAppendWaves + 1;
+    const unsigned long long m[3] = {__ballot(p0), __ballot(p1), __ballot(p2)};
+    const uint32_t waves = blockDim.x >> 6, w = threadIdx.x >> 6, lane = __lane_id();
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s[j * S + w] = (uint32_t)__popcll(m[j]);
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        uint32_t *a = s + threadIdx.x * S;
+        uint32_t *ctr = threadIdx.x == 0 ? c0 : (threadIdx.x == 1 ? c1 : c2);
+        uint32_t tot = 0;
+        for (uint32_t k = 0; k < waves; ++k) {
+            const uint32_t c = a[k];
+            a[k] = tot;
+            tot += c;
+        }
+        a[kAppendWaves] = tot ? atomicAdd(ctr, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t r[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const uint32_t lo = (uint32_t)m[j], hi = (uint32_t)(m[j] >> 32);
+        r[j] = s[j * S + kAppendWaves] + s[j * S + w] + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+    }
+    o0 = r[0];
+    o1 = r[1];
+    o2 = r[2];
+}
+
 // ----------------------------------------------------------------- Halton
 
 __device__ __forceinline__ uint32_t div_b(uint32_t n, uint32_t m, uint32_t sh)
@@ -1341,12 +1386,15 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
 // a shaded vertex's outputs: its training record, its shadow ray and its
 // place in the next depth's queue (wave-aggregated appends)
 __device__ __forceinline__ void shade_emit(const Frame &F, const Pool &P, uint32_t v, uint32_t slot, ShadeOut &o,
-                                           uint32_t *qn)
+                                           uint32_t *qn, uint32_t *s_app)
 {
     uint32_t rec_idx = kNoHit;
+    const bool rec = F.guide.record && o.record;
+    uint32_t pr, ps, pe;
+    block_append3(&P.counters[127], rec, &P.counters[64 + v], o.shadow, &P.counters[v + 1], o.alive, s_app, pr, ps,
+                  pe);
     if (F.guide.record) {
-        uint32_t pr = wave_append(&P.counters[127], o.record);
-        if (o.record && pr < F.guide.rec_cap) {
+        if (rec && pr < F.guide.rec_cap) {
             float4 *r = F.guide.rec + (size_t)pr * kRecF4;
             r[0] = o.rec[0];
             r[1] = o.rec[1];
@@ -1357,14 +1405,12 @@ __device__ __forceinline__ void shade_emit(const Frame &F, const Pool &P, uint32
             rec_idx = pr;
         }
     }
-    uint32_t ps = wave_append(&P.counters[64 + v], o.shadow);
     if (o.shadow) {
         o.sh_c.w = ubits(rec_idx);
         P.sh_o[ps] = o.sh_o;
         P.sh_d[ps] = o.sh_d;
         P.sh_c[ps] = o.sh_c;
     }
-    uint32_t pe = wave_append(&P.counters[v + 1], o.alive);
     if (o.alive) qn[pe] = slot;
 }
 
@@ -1378,6 +1424,7 @@ __device__ __forceinline__ void shade_out_init(ShadeOut &o)
 
 __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v)
 {
+    __shared__ uint32_t s_app[3 * (kAppendWaves + 1)];
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];
     uint32_t *qn = P.q_ext[(v + 1) & 1];
@@ -1390,7 +1437,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v
             slot = q[i];
             shade_slot(F, P, v, slot, slot, o);
         }
-        shade_emit(F, P, v, slot, o, qn);
+        shade_emit(F, P, v, slot, o, qn, s_app);
     }
 }
 
@@ -1409,6 +1456,7 @@ __global__ __launch_bounds__(kShadeGuidedBlock, kShadeGuidedWavesPerSIMD) void k
     __shared__ uint2 sfrag[kGuideFrags * 64];
     __shared__ __align__(16) float sbias[256];
     __shared__ uint4 smix[kShadeGuidedBlock * guide::kMixU4];
+    __shared__ uint32_t s_app[3 * (kAppendWaves + 1)];
     const uint32_t n = P.counters[v];
     if ((size_t)blockIdx.x * kShadeGuidedBlock >= n) return;
     mlp::load_weights(F.guide.frag, F.guide.bias, sfrag, sbias);
@@ -1449,7 +1497,7 @@ __global__ __launch_bounds__(kShadeGuidedBlock, kShadeGuidedWavesPerSIMD) void k
         ShadeOut o;
         shade_out_init(o);
         if (i < n) shade_slot(F, P, v, slot, slot, o, smix + threadIdx.x * guide::kMixU4);
-        shade_emit(F, P, v, slot, o, qn);
+        shade_emit(F, P, v, slot, o, qn, s_app);
     }
 }
 
@@ -1489,6 +1537,7 @@ __global__ __launch_bounds__(kBlock) void k_regen_init(Frame F, Pool P, uint32_t
 // rendering: no guide, no training records)
 __global__ __launch_bounds__(kBlock, 4) void k_shade_regen(Frame F, Pool P, uint32_t t)
 {
+    __shared__ uint32_t s_app[3 * (kAppendWaves + 1)];
     const uint32_t n = P.counters[rg_queue_count(t)];
     const uint32_t *q = P.q_ext[t & 1];
     uint32_t *qn = P.q_ext[(t + 1) & 1];
@@ -1507,17 +1556,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_shade_regen(Frame F, Pool P, uint
             shade_slot(F, P, pv.y, slot, pv.x, o);
             if (o.alive) P.pv[slot] = make_uint2(pv.x, pv.y + 1u);
         }
-        const uint32_t ps = wave_append(&P.counters[kRgSh], o.shadow);
+        const bool dead = active && !o.alive;
+        uint32_t ps, pe, pd;
+        block_append3(&P.counters[kRgSh], o.shadow, cn, o.alive, &P.counters[kRgDead], dead, s_app, ps, pe, pd);
         if (o.shadow) {
             o.sh_c.w = ubits(kNoHit);
             P.sh_o[ps] = o.sh_o;
             P.sh_d[ps] = o.sh_d;
             P.sh_c[ps] = o.sh_c;
         }
-        const uint32_t pe = wave_append(cn, o.alive);
         if (o.alive) qn[pe] = slot;
-        const bool dead = active && !o.alive;
-        const uint32_t pd = wave_append(&P.counters[kRgDead], dead);
         if (dead) P.q_dead[pd] = slot;
     }
 }
