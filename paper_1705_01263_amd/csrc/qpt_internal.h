@@ -22,6 +22,7 @@ constexpr uint32_t kShadeGuidedBlocksPerCU = 2;  // 69 KB of LDS per block (weig
 constexpr uint32_t kShadeGuidedWavesPerSIMD = kShadeGuidedBlocksPerCU * kShadeGuidedBlock / 64 / 4;
 constexpr uint32_t kShadeGuidedGridPerCU = 8;    // its grid: blocks per CU
 constexpr uint32_t kBlock = 256;         // threads per block for the path kernels
+constexpr uint32_t kShadeBlock = 256;    // threads per block of the shading kernel (its queue appends are per block)
 constexpr uint32_t kNoHit = 0xffffffffu;
 // per-lane counter words beyond the queue counts: the abort decision latched
 // by a pass's first batch, and whether the current batch renders nothing

@@ -79,7 +79,8 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool pred)
 // offsets and the totals, which change only after the next call's first
 // barrier, so calls in a loop need no further barrier.
 constexpr uint32_t kAppendWaves = 8;  // the most waves per block that append
-static_assert(kBlock / 64 <= kAppendWaves && kShadeGuidedBlock / 64 <= kAppendWaves, "appending blocks fit the LDS counts");
+static_assert(kShadeBlock / 64 <= kAppendWaves && kBlock / 64 <= kAppendWaves && kShadeGuidedBlock / 64 <= kAppendWaves,
+              "appending blocks fit the LDS counts");
 __device__ __forceinline__ void block_append3(uint32_t *c0, bool p0, uint32_t *c1, bool p1, uint32_t *c2, bool p2,
                                               uint32_t *s, uint32_t &o0, uint32_t &o1, uint32_t &o2)
 {
@@ -1422,13 +1423,13 @@ __device__ __forceinline__ void shade_out_init(ShadeOut &o)
     for (int k = 0; k < 5; ++k) o.rec[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-__global__ __launch_bounds__(kBlock, 4) void k_shade(Frame F, Pool P, uint32_t v)
+__global__ __launch_bounds__(kShadeBlock, 4) void k_shade(Frame F, Pool P, uint32_t v)
 {
     __shared__ uint32_t s_app[3 * (kAppendWaves + 1)];
     const uint32_t n = P.counters[v];
     const uint32_t *q = P.q_ext[v & 1];
     uint32_t *qn = P.q_ext[(v + 1) & 1];
-    for (uint32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
+    for (uint32_t base = blockIdx.x * kShadeBlock; base < n; base += gridDim.x * kShadeBlock) {
         uint32_t i = base + threadIdx.x;
         uint32_t slot = 0;
         ShadeOut o;
@@ -1827,6 +1828,7 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
         hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
     });
     uint32_t g = blocks_for(n, 8192);
+    const uint32_t gs = (uint32_t)std::max<size_t>(1, (size_t)g * kBlock / kShadeBlock);  // k_shade: the same threads
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
     // guided shading: four times the blocks resident at once, each staging
     // the weights once (a grid of only the resident blocks balances badly
@@ -1855,7 +1857,7 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
         if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex)
             timed(K_SHADE_GUIDED, [&] { hipLaunchKernelGGL(k_shade_guided, dim3(gg), dim3(kShadeGuidedBlock), 0, s, F, P, v); });
         else
-            timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(g), dim3(kBlock), 0, s, F, P, v); });
+            timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, F, P, v); });
         timed(K_SHADOW, [&] {
             if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
             else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
