@@ -195,11 +195,21 @@ __device__ inline void decode(const float *o, Mix &m)
     }
 }
 
-// vMF density on the unit sphere
+// 1 - e^-x for x >= 0: a Taylor polynomial below 0.1, where the subtraction
+// would cancel (truncation below 2e-7 relative), else the hardware exponential
+__device__ __forceinline__ float one_minus_exp_neg(float x)
+{
+    const float p = x * (1.0f - x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f)))));
+    return x < 0.1f ? p : 1.0f - __expf(-x);
+}
+
+// vMF density on the unit sphere, kappa / (2 pi (1 - e^-2 kappa)) e^(kappa (mu.w - 1)),
+// with the hardware's exponential and reciprocal (evaluated at every lobe
+// for each density the guided shading needs, twice per vertex)
 __device__ __forceinline__ float vmf_pdf(float4 l, V3 w)
 {
     float c = l.x * w.x + l.y * w.y + l.z * w.z;
-    return l.w / (2.0f * kPiF * -expm1f(-2.0f * l.w)) * expf(l.w * (c - 1.0f));
+    return l.w * __builtin_amdgcn_rcpf(2.0f * kPiF * one_minus_exp_neg(2.0f * l.w)) * __expf(l.w * (c - 1.0f));
 }
 
 template <class M>
