@@ -408,7 +408,8 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
     bounded pixel sample (every `oracle_stride` pixels, also from an
     independent pass range), whose own error against the GPU reference is
     reported beside it. `per_call` passes go to the library per call (two
-    batches in flight); both tracers (and the references) render with the
+    batches in flight), with the next call enqueued before the host waits
+    for the previous one; both tracers (and the references) render with the
     megakernel tail from `tail_depth` (default: half the maximum depth,
     past the guided vertices), as the throughput leg does.
     """
@@ -444,10 +445,29 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             n = 0
-            while (passes is not None and n < passes) or (budget is not None and time.perf_counter() - t0 < budget):
+            # one call stays in flight while the host waits for the one before
+            # it, so the GPU renders without a gap between calls (as a
+            # progressive renderer would). With a time budget, another call is
+            # started only if it is expected to end within half a call of the
+            # budget (one call is still in flight; a call's duration is the
+            # mean so far), so a run ends near the budget however long its
+            # calls are; the wall time includes the last call
+            prev, done, d = None, 0, 0.0
+            while True:
+                if passes is not None and n >= passes:
+                    break
+                if budget is not None and done and time.perf_counter() - t0 + 1.5 * d > budget:
+                    break
                 r.render(n, per_call, tail_depth=td)
                 n += per_call
-                torch.cuda.synchronize()
+                ev = torch.cuda.Event()
+                ev.record()
+                if prev is not None:
+                    prev.synchronize()
+                    done += 1
+                    d = (time.perf_counter() - t0) / done
+                prev = ev
+            torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s, c = r.readback()
             steps = r.ctx.guide_get_weights()[1] if guided else 0
@@ -488,7 +508,10 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
                 "guided": {"passes": n_g, "seconds": round(t_g, 3), "adam_steps": int(steps),
                            "rmse_vs_gpu_reference": rmse(guided, ref), "rmse": rmse_c(guided),
                            "final_loss": round(r.ctx.guide_loss()[0], 4)},
-                "guided_over_plain_rmse": round(rmse_c(guided) / max(rmse_c(plain), 1e-30), 4)})
+                "guided_over_plain_rmse": round(rmse_c(guided) / max(rmse_c(plain), 1e-30), 4),
+                # the same ratio with each error scaled to the plain run's exact wall time
+                # (an error falls as one over the square root of the time spent)
+                "time_adjusted": round(rmse_c(guided) / max(rmse_c(plain), 1e-30) * (t_g / t_p) ** 0.5, 4)})
             _say(f"bench: equal time [{sc.name}, {vname}, {label}] plain {n_p} passes, guided {n_g} passes, "
                  f"ratio {view['budgets'][-1]['guided_over_plain_rmse']}")
         del r

@@ -580,47 +580,49 @@ __global__ __launch_bounds__(256) void k_guide_reduce(GuideTrain T, uint32_t blo
     __shared__ float part[4][kReduceParams];
     const uint32_t lane = threadIdx.x & 63u, grp = threadIdx.x >> 6;
     const uint32_t p = blockIdx.x * kReduceParams + lane;
+    // the weight and loss sums over the training blocks: each thread loads
+    // those of the blocks t, t + 256, ... (every load at once), then a fixed
+    // pairwise tree in LDS (every block forms the same sums)
+    __shared__ float swl[2][256];
+    {
+        float w = 0.0f, l = 0.0f;
+        for (uint32_t b = threadIdx.x; b < blocks; b += 256) {
+            w += T.scalars[2 + 2 * b];
+            l += T.scalars[3 + 2 * b];
+        }
+        swl[0][threadIdx.x] = w;
+        swl[1][threadIdx.x] = l;
+    }
     // every fourth partial from grp on, into four running sums (partial
-    // grp + 4 i goes to sum i mod 4), sixteen loads in flight per lane (the
-    // partials come from L2 or HBM: a chain of dependent loads would pay
+    // grp + 4 i goes to sum i mod 4), thirty-two loads in flight per lane
+    // (the partials come from L2 or HBM: a chain of dependent loads would pay
     // their latency once per partial); a fixed order, so the step stays a
     // deterministic function of its rows
     float g4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     if (p < kGuideParams) {
         uint32_t b = grp;
-        for (; b + 60 < blocks; b += 64) {
-            float t[16];
+        for (; b + 124 < blocks; b += 128) {
+            float t[32];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) t[j] = T.partial[(size_t)(b + 4 * j) * kGuideParams + p];
+            for (int j = 0; j < 32; ++j) t[j] = T.partial[(size_t)(b + 4 * j) * kGuideParams + p];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) g4[j & 3] += t[j];
+            for (int j = 0; j < 32; ++j) g4[j & 3] += t[j];
         }
         for (int j = 0; b < blocks; b += 4, ++j) g4[j & 3] += T.partial[(size_t)b * kGuideParams + p];
     }
     float g = (g4[0] + g4[1]) + (g4[2] + g4[3]);
     part[grp][lane] = g;
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        __syncthreads();
+        if (threadIdx.x < h) {
+            swl[0][threadIdx.x] += swl[0][threadIdx.x + h];
+            swl[1][threadIdx.x] += swl[1][threadIdx.x + h];
+        }
+    }
     __syncthreads();
     if (grp != 0 || p >= kGuideParams) return;
     g = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-    // the weight and loss sums over the training blocks, eight running sums
-    // each (block b into sum b mod 8) combined in a fixed order (every thread
-    // forms the same sums); one thread keeps them for readers
-    float w8[8] = {}, l8[8] = {};
-    {
-        uint32_t b = 0;
-        for (; b + 8 <= blocks; b += 8)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                w8[j] += T.scalars[2 + 2 * (b + j)];
-                l8[j] += T.scalars[3 + 2 * (b + j)];
-            }
-        for (int j = 0; b < blocks; ++b, ++j) {
-            w8[j] += T.scalars[2 + 2 * b];
-            l8[j] += T.scalars[3 + 2 * b];
-        }
-    }
-    const float ws = ((w8[0] + w8[1]) + (w8[2] + w8[3])) + ((w8[4] + w8[5]) + (w8[6] + w8[7]));
-    const float ls = ((l8[0] + l8[1]) + (l8[2] + l8[3])) + ((l8[4] + l8[5]) + (l8[6] + l8[7]));
+    const float ws = swl[0][0], ls = swl[1][0];
     if (blockIdx.x == 0 && lane == 0) {
         T.scalars[0] = ws;
         T.scalars[1] = ls;
