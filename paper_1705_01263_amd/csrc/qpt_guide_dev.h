@@ -212,12 +212,42 @@ __device__ __forceinline__ float vmf_pdf(float4 l, V3 w)
     return l.w * __builtin_amdgcn_rcpf(2.0f * kPiF * one_minus_exp_neg(2.0f * l.w)) * __expf(l.w * (c - 1.0f));
 }
 
+// the eight lobes' weights times their vMF normalisers, formed once per
+// mixture for the densities evaluated at several directions
+struct MixCoef {
+    float c[kLobes];
+};
+
+template <class M>
+__device__ __forceinline__ MixCoef mixture_coef(const M &m)
+{
+    MixCoef mc;
+#pragma unroll
+    for (int k = 0; k < kLobes; ++k) {
+        const float kap = lobe(m, k).w;
+        mc.c[k] = weight(m, k) * (kap * __builtin_amdgcn_rcpf(2.0f * kPiF * one_minus_exp_neg(2.0f * kap)));
+    }
+    return mc;
+}
+
+// the mixture's density at w, sum_k c_k e^(kappa_k (mu_k.w - 1)) (the same
+// value as the sum of weight times vmf_pdf, up to the order of the products)
+template <class M>
+__device__ __forceinline__ float mixture_pdf(const M &m, const MixCoef &mc, V3 w)
+{
+    float q = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kLobes; ++k) {
+        const float4 l = lobe(m, k);
+        q += mc.c[k] * __expf(l.w * ((l.x * w.x + l.y * w.y + l.z * w.z) - 1.0f));
+    }
+    return q;
+}
+
 template <class M>
 __device__ __forceinline__ float mixture_pdf(const M &m, V3 w)
 {
-    float q = 0.0f;
-    for (int k = 0; k < kLobes; ++k) q += weight(m, k) * vmf_pdf(lobe(m, k), w);
-    return q;
+    return mixture_pdf(m, mixture_coef(m), w);
 }
 
 // lobe: first k with u < cumulative weight; direction by stable vMF sampling

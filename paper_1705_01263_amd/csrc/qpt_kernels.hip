@@ -1202,7 +1202,11 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
             // vertices, and only with alpha > 0)
             const bool guided = mix_row != nullptr;
             guide::MixRef mix{nullptr, 0.0f};
-            if (guided) mix = guide::mix_ref(mix_row);
+            guide::MixCoef mc{};
+            if (guided) {
+                mix = guide::mix_ref(mix_row);
+                mc = guide::mixture_coef(mix);
+            }
             const float alpha = F.guide.alpha;
             // next-event estimation
             if (F.mode != 1 && (F.num_emit || F.env_w)) {
@@ -1295,7 +1299,7 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
                         f3 fb;
                         float pb;
                         bsdf_eval(m, nn, wo, wi, fb, pb);
-                        if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
+                        if (guided) pb = alpha * guide::mixture_pdf(mix, mc, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
                         float w = F.mode == 2 ? 1.0f : mis2(pl, pb);
                         f3 contrib = T * fb * Le * (ci * w / pl);
                         if (maxc(contrib) > 0.0f) {
@@ -1340,7 +1344,7 @@ __device__ __forceinline__ void shade_slot(const Frame &F, const Pool &P, uint32
                 f3 fb;
                 float pb;
                 bsdf_eval(m, nn, wo, wi, fb, pb);
-                if (guided) pb = alpha * guide::mixture_pdf(mix, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
+                if (guided) pb = alpha * guide::mixture_pdf(mix, mc, {wi.x, wi.y, wi.z}) + (1.0f - alpha) * pb;
                 if (pb > 0.0f) {
                     f3 Tb = T;  // throughput before this vertex's scattering
                     T = T * fb * (dot(nn, wi) / pb);
