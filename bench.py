@@ -789,7 +789,7 @@ def main():
     # of as many whole passes as its path pool holds (sixteen frames' worth)
     cs = args.compress_state
     td = args.tail_depth if args.tail_depth >= 0 else D // 2
-    r.render(0, args.warmup, compress_state=cs, tail_depth=td)
+    r.render(0, args.warmup, single_stream=args.single_stream, compress_state=cs, tail_depth=td)
     torch.cuda.synchronize()
     _say(f"bench: warmup {args.warmup} passes done")
     st0 = r.stats()

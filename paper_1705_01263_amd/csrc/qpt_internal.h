@@ -228,8 +228,11 @@ enum KernelKind { K_CLEAR = 0, K_GENERATE, K_TRACE, K_SHADE, K_SHADOW, K_ACCUMUL
 
 // brackets every kernel launch of a batch with stream events when set
 struct Profiler {
+    // a span of work on s: events recorded before and after it
     virtual void begin(int kind, hipStream_t s) = 0;
     virtual void end(int kind, hipStream_t s) = 0;
+    // one kernel: the two events its launch records at the dispatch's start and end
+    virtual void kernel_events(int kind, hipEvent_t *start, hipEvent_t *stop) = 0;
     virtual ~Profiler() {}
 };
 

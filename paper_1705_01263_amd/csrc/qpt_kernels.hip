@@ -9,6 +9,7 @@
 // stays in place as structures of arrays (Sec. 3.1.1). A final kernel adds
 // the batch into the FP64 framebuffer in pass order and bumps the per-pixel
 // sample counts (Appendix A.4).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1816,21 +1817,25 @@ hipError_t launch_fill_f64(double *p, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// one kernel launch; when profiling, the dispatch itself records the start
+// and stop events (the kernel's own execution time, as a kernel trace
+// measures it, without the event packets' overhead around it)
+template <typename Kern, typename... Args>
+static inline void launch_timed(Profiler *prof, int kind, Kern kernel, dim3 grid, dim3 block, hipStream_t s,
+                                Args... args)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof) prof->kernel_events(kind, &a, &b);
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+}
+
 hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint64_t pass0,
                                uint32_t npass, hipStream_t s, Profiler *prof)
 {
     uint32_t n = npix * npass;
-    auto timed = [&](int kind, auto &&launch) {
-        if (prof) prof->begin(kind, s);
-        launch();
-        if (prof) prof->end(kind, s);
-    };
-    timed(K_CLEAR, [&] {
-        hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(kCounters), 0, s, P, F.abort_word, pix0 == 0 ? 1u : 0u);
-    });
-    timed(K_GENERATE, [&] {
-        hipLaunchKernelGGL(k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, pass0, n);
-    });
+    launch_timed(prof, K_CLEAR, k_batch_begin, dim3(1), dim3(kCounters), s, P, F.abort_word, pix0 == 0 ? 1u : 0u);
+    launch_timed(prof, K_GENERATE, k_generate, dim3(blocks_for(n, 1u << 30)), dim3(kBlock), s, F, P, pix0, npix, pass0,
+                 n);
     uint32_t g = blocks_for(n, 8192);
     const uint32_t gs = (uint32_t)std::max<size_t>(1, (size_t)g * kBlock / kShadeBlock);  // k_shade: the same threads
     uint32_t gt = blocks_for(n, P.trav_threads / kBlock);
@@ -1848,24 +1853,22 @@ hipError_t launch_render_paths(const Frame &F, const Pool &P, uint32_t pix0, uin
     for (uint32_t v = 1; v <= F.max_depth; ++v) {
         if (tail_ok && v == F.tail_depth) {
             // the rest of the batch's paths in one launch (traversal grid, four blocks per CU resident)
-            timed(K_TAIL, [&] {
-                if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_tail<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
-                else hipLaunchKernelGGL(k_tail<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v);
-            });
+            if (F.node_format == kNodeQuant) launch_timed(prof, K_TAIL, k_tail<true>, dim3(gt), dim3(kBlock), s, F, P, v);
+            else launch_timed(prof, K_TAIL, k_tail<false>, dim3(gt), dim3(kBlock), s, F, P, v);
             break;
         }
-        timed(K_TRACE, [&] {
-            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_trace<true>, dim3(gt), dim3(kBlock), 0, s, F, P, v, v & 1);
-            else hipLaunchKernelGGL(k_trace<false>, dim3(gt), dim3(kBlock), 0, s, F, P, v, v & 1);
-        });
-        if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex)
-            timed(K_SHADE_GUIDED, [&] { hipLaunchKernelGGL(k_shade_guided, dim3(gg), dim3(kShadeGuidedBlock), 0, s, F, P, v); });
+        if (F.node_format == kNodeQuant)
+            launch_timed(prof, K_TRACE, k_trace<true>, dim3(gt), dim3(kBlock), s, F, P, v, v & 1u);
         else
-            timed(K_SHADE, [&] { hipLaunchKernelGGL(k_shade, dim3(gs), dim3(kShadeBlock), 0, s, F, P, v); });
-        timed(K_SHADOW, [&] {
-            if (F.node_format == kNodeQuant) hipLaunchKernelGGL(k_shadow<true>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
-            else hipLaunchKernelGGL(k_shadow<false>, dim3(gt), dim3(kBlock), 0, s, F, P, 64 + v);
-        });
+            launch_timed(prof, K_TRACE, k_trace<false>, dim3(gt), dim3(kBlock), s, F, P, v, v & 1u);
+        if (F.guide.alpha_thr && v < F.max_depth && v <= F.guide.max_vertex)
+            launch_timed(prof, K_SHADE_GUIDED, k_shade_guided, dim3(gg), dim3(kShadeGuidedBlock), s, F, P, v);
+        else
+            launch_timed(prof, K_SHADE, k_shade, dim3(gs), dim3(kShadeBlock), s, F, P, v);
+        if (F.node_format == kNodeQuant)
+            launch_timed(prof, K_SHADOW, k_shadow<true>, dim3(gt), dim3(kBlock), s, F, P, 64u + v);
+        else
+            launch_timed(prof, K_SHADOW, k_shadow<false>, dim3(gt), dim3(kBlock), s, F, P, 64u + v);
     }
     return hipGetLastError();
 }
@@ -1929,9 +1932,8 @@ hipError_t launch_render_regen(const Frame &F, const Pool &P, uint32_t npix, uin
 hipError_t launch_accumulate(const Frame &F, const Pool &P, uint32_t pix0, uint32_t npix, uint32_t npass,
                              hipStream_t s, Profiler *prof)
 {
-    if (prof) prof->begin(K_ACCUMULATE, s);
-    hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), 0, s, F, P, pix0, npix, npass);
-    if (prof) prof->end(K_ACCUMULATE, s);
+    launch_timed(prof, K_ACCUMULATE, k_accumulate, dim3(blocks_for(npix, 1u << 30)), dim3(kBlock), s, F, P, pix0, npix,
+                 npass);
     return hipGetLastError();
 }
 
