@@ -409,9 +409,15 @@ def equal_time(sc, views, seconds: float, ref_passes: int, per_call: int, oracle
     independent pass range), whose own error against the GPU reference is
     reported beside it. `per_call` passes go to the library per call (two
     batches in flight), with the next call enqueued before the host waits
-    for the previous one; both tracers (and the references) render with the
-    megakernel tail from `tail_depth` (default: half the maximum depth,
-    past the guided vertices), as the throughput leg does.
+    for the previous one. A timed run starts another call only while the
+    mean call time so far says it would end within half a call of the
+    budget, so both runs overshoot it by about the same fraction; the
+    ratio is also reported scaled by sqrt(guided time / plain time)
+    (`time_adjusted`), which removes what difference in wall time is left,
+    since RMSE falls as one over the square root of the passes. Both
+    tracers (and the references) render with the megakernel tail from
+    `tail_depth` (default: half the maximum depth, past the guided
+    vertices), as the throughput leg does.
     """
     import numpy as np
     import torch
