@@ -51,7 +51,7 @@ WORKLOADS = {
                 "batches in flight), max depth 16, NEE+MIS, roulette"),
 }
 # the guided tracer's settings in the equal-time legs
-GUIDE = {"alpha": 0.7, "warmup": 16, "max_vertex": 2, "lr": 1e-3, "batch": 1 << 18}
+GUIDE = {"alpha": 0.7, "warmup": 16, "max_vertex": 2, "lr": 2e-3, "batch": 1 << 17}
 
 # algorithmic bytes per unit of work
 TRI_BYTES = 48   # triangle (three float4 corners); a 4-wide node is 64 bytes quantised, 128 in full (bvh stats)
